@@ -1,0 +1,73 @@
+"""FP64 reference gradients of a loss on the JKO flow output.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).  This is the reduced
+scaling iteration of ``jko_oracle.jko_step`` (Proposition 3.3 with the u, v
+corrections dropped) written with torch float64 CPU tensors, unrolled at fixed
+iteration counts, and differentiated by torch autograd.  The JKO flow
+(eq. smooth-jko) chains the steps with q = p_t, cold-starting each one
+(Listing 1, step 2).
+
+Energies: ``zero``, ``congestion`` (Proposition 4.1; the clamp takes the
+capped branch on ties) and ``entropy`` (Proposition 4.2, m = 1).
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+
+def _centres(n):
+    return (torch.arange(n, dtype=torch.float64) + 0.5) / n
+
+
+def _factor(n, gamma):
+    x = _centres(n)
+    return torch.exp(-(x[:, None] - x[None, :]) ** 2 / gamma)
+
+
+def _apply(x, factors):
+    y = x
+    for ax, K in enumerate(factors):
+        y = torch.movedim(torch.tensordot(K, torch.movedim(y, ax, 0), dims=([1], [0])), 0, ax)
+    return y
+
+
+def flow_torch(p0, w, kappa, gamma, tau, iters_per_step, kind="congestion", coef=None):
+    """Differentiable flow output p_T (torch tensors in, torch tensor out)."""
+    shape = tuple(p0.shape)
+    factors = [_factor(n, gamma) for n in shape]
+    sigma = tau / gamma
+    q = p0
+    for K in iters_per_step:
+        a = torch.ones(shape, dtype=torch.float64)
+        p = None
+        for _ in range(K):
+            t = _apply(a, factors)
+            b = q / t
+            s = _apply(b, factors)
+            if kind == "congestion":
+                sg = s * torch.exp(-sigma * w)
+                p = torch.where(sg < kappa, sg, kappa)
+            elif kind == "entropy":
+                p = s ** (1.0 / (1.0 + sigma * coef))
+            elif kind == "zero":
+                p = s
+            else:
+                raise ValueError(kind)
+            a = p / s
+        q = p
+    return q
+
+
+def loss_and_grads(p0, w, kappa, gamma, tau, iters_per_step, target, kind="congestion",
+                   coef=None):
+    """loss = ||p_T - target||^2 and its gradients with respect to w and p0,
+    all as float64 numpy arrays."""
+    tp0 = torch.tensor(np.asarray(p0, np.float64), requires_grad=True)
+    tw = torch.tensor(np.asarray(w, np.float64), requires_grad=True)
+    tk = torch.tensor(np.broadcast_to(np.asarray(kappa, np.float64), p0.shape).copy())
+    tc = None if coef is None else torch.tensor(np.asarray(coef, np.float64))
+    pT = flow_torch(tp0, tw, tk, gamma, tau, iters_per_step, kind, tc)
+    loss = ((pT - torch.tensor(np.asarray(target, np.float64))) ** 2).sum()
+    loss.backward()
+    return float(loss.detach()), tw.grad.numpy().copy(), tp0.grad.numpy().copy(), pT.detach().numpy()

@@ -1,0 +1,269 @@
+"""Seeded synthetic inputs for the entropic JKO flows.
+
+This module only *draws* inputs: densities, obstacle masks, potentials,
+capacity fields and coefficient fields, all in float64 numpy arrays.  It holds
+none of the method's arithmetic (no Gibbs kernel, no proximal map, no scaling
+update), so both the FP64 oracle and the HIP path can take their inputs from
+here without sharing any computation.
+
+Every generator takes an explicit ``seed`` and uses ``numpy.random.default_rng``
+(PCG64).  Grids are cell-centred on the unit cube: along an axis of length n the
+cell centres are ``(i + 0.5) / n``.  Array index ``(i0, i1[, i2])`` is the point
+``(x1, x2[, x3])``; the last axis is contiguous in memory.
+
+Workloads (synthetic stand-ins for the paper's figures, which print no data):
+
+* ``crowd32``   -- 2D crowd motion with congestion (Section 4.2) on 32x32:
+                   3 Gaussian bumps, scalar capacity, potential |x - exit|^2.
+* ``crowd256``  -- 2D crowd motion on 256x256 with 6 rectangular obstacles
+                   (capacity 0 inside), 8 bumps.
+* ``porous512`` -- 2D nonlinear diffusion on 512x512 with
+                   f(p) = sum c(x) p^m / (m - 1), m = 2 (Section 4.4), smoothed
+                   uniform noise as initial density.
+* ``crowd128c`` -- 3D crowd motion on 128^3 with 10 box obstacles, 16 bumps.
+
+The ``projected`` flag replaces p0 by min(c * p0, kappa) with the scalar c found
+by bisection so that the total mass is one: the paper requires the capacity to
+dominate the initial density (Section 4.2), which the raw bump mixtures do not.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+__all__ = [
+    "Workload", "cell_centres", "gaussian_bumps", "box_obstacles",
+    "project_capacity", "make_workload", "WORKLOADS", "small_case",
+]
+
+
+def cell_centres(n: int) -> np.ndarray:
+    """Cell centres (i + 0.5) / n of a uniform grid on [0, 1]."""
+    return (np.arange(n, dtype=np.float64) + 0.5) / n
+
+
+def _mesh(shape):
+    return np.meshgrid(*[cell_centres(n) for n in shape], indexing="ij")
+
+
+def gaussian_bumps(shape, centres, sigma, weights) -> np.ndarray:
+    """Sum of isotropic Gaussian bumps sampled at the cell centres, mass 1."""
+    X = _mesh(shape)
+    out = np.zeros(shape, dtype=np.float64)
+    for c, wt in zip(centres, weights):
+        r2 = sum((X[k] - c[k]) ** 2 for k in range(len(shape)))
+        out += wt * np.exp(-r2 / (2.0 * sigma * sigma))
+    return out / out.sum()
+
+
+def box_obstacles(shape, corners, sides) -> np.ndarray:
+    """Boolean mask of the cells whose centre lies in one of the boxes
+    [corner, corner + side) (one box per row of ``corners``/``sides``)."""
+    X = _mesh(shape)
+    mask = np.zeros(shape, dtype=bool)
+    for c, s in zip(corners, sides):
+        inside = np.ones(shape, dtype=bool)
+        for k in range(len(shape)):
+            inside &= (X[k] >= c[k]) & (X[k] < c[k] + s[k])
+        mask |= inside
+    return mask
+
+
+def squared_distance(shape, point) -> np.ndarray:
+    X = _mesh(shape)
+    return sum((X[k] - point[k]) ** 2 for k in range(len(shape)))
+
+
+def project_capacity(p: np.ndarray, kappa: np.ndarray, iters: int = 90) -> np.ndarray:
+    """Return min(c * p, kappa) with c > 0 chosen by bisection so the sum is 1.
+
+    Requires sum(kappa) > 1 over the support of p.
+    """
+    kappa = np.broadcast_to(kappa, p.shape)
+    lo, hi = 0.0, 1.0
+    while np.minimum(hi * p, kappa).sum() < 1.0:
+        hi *= 2.0
+        if hi > 1e30:
+            raise ValueError("capacity too small to hold unit mass")
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        if np.minimum(mid * p, kappa).sum() < 1.0:
+            lo = mid
+        else:
+            hi = mid
+    out = np.minimum(hi * p, kappa)
+    return out / out.sum()
+
+
+@dataclass
+class Workload:
+    """One synthetic flow: grid, energy fields, solver parameters, p0."""
+    name: str
+    shape: tuple
+    gamma: float
+    tau: float
+    kind: str                    # "congestion" | "porous" | "entropy" | "zero"
+    p0: np.ndarray
+    w: Optional[np.ndarray] = None         # congestion potential (None = 0)
+    kappa: Optional[np.ndarray] = None     # capacity field (None = kappa_scalar)
+    kappa_scalar: float = math.inf
+    coef: Optional[np.ndarray] = None      # porous / entropy coefficient c(x)
+    coef_scalar: float = 1.0
+    m: float = 2.0
+    density_scale: float = 1.0
+    n_steps: int = 1
+    max_iters: int = 300
+    tol: float = 0.0                       # 0 = fixed iteration count
+    check_every: int = 10
+    extras: dict = field(default_factory=dict)
+
+    @property
+    def N(self) -> int:
+        return int(np.prod(self.shape))
+
+    def kappa_field(self) -> np.ndarray:
+        if self.kappa is not None:
+            return self.kappa
+        return np.full(self.shape, self.kappa_scalar, dtype=np.float64)
+
+
+def _crowd(name, shape, gamma, tau, n_bumps, n_boxes, centre_box, exit_pt,
+           cap_factor, seed, projected, n_steps, max_iters, tol):
+    rng = np.random.default_rng(seed)
+    d = len(shape)
+    N = int(np.prod(shape))
+    X = _mesh(shape)
+    exit_cell = tuple(min(int(exit_pt[k] * shape[k]), shape[k] - 1) for k in range(d))
+    # obstacles: all sides, then all corners; redraw until feasible
+    if n_boxes > 0:
+        while True:
+            sides = rng.uniform(0.05, 0.2, size=(n_boxes, d))
+            corners = rng.uniform(0.0, 1.0 - sides)
+            mask = box_obstacles(shape, corners, sides)
+            free = 1.0 - mask.mean()
+            if cap_factor * free >= 1.05 and not mask[exit_cell]:
+                break
+    else:
+        sides = np.zeros((0, d))
+        corners = np.zeros((0, d))
+        mask = np.zeros(shape, dtype=bool)
+    # bump centres by rejection outside the obstacles
+    lo, hi = centre_box
+    centres = []
+    while len(centres) < n_bumps:
+        c = rng.uniform(lo, hi)
+        cell = tuple(min(int(c[k] * shape[k]), shape[k] - 1) for k in range(d))
+        if not mask[cell]:
+            centres.append(c)
+    weights = rng.dirichlet(np.ones(n_bumps))
+    p0 = gaussian_bumps(shape, centres, 0.05, weights)
+    p0[mask] = 0.0
+    p0 /= p0.sum()
+    w = squared_distance(shape, exit_pt)
+    if n_boxes > 0:
+        kappa = np.where(mask, 0.0, cap_factor / N)
+        kappa_scalar = math.inf
+    else:
+        kappa = None
+        kappa_scalar = cap_factor / N
+    if projected:
+        p0 = project_capacity(p0, kappa if kappa is not None else kappa_scalar)
+    return Workload(
+        name=name, shape=tuple(shape), gamma=gamma, tau=tau, kind="congestion",
+        p0=p0, w=w, kappa=kappa, kappa_scalar=kappa_scalar, n_steps=n_steps,
+        max_iters=max_iters, tol=tol,
+        extras=dict(mask=mask, corners=corners, sides=sides, centres=np.array(centres),
+                    weights=weights, exit=np.array(exit_pt)),
+    )
+
+
+def _porous(name, shape, gamma, tau, m, seed, density_scaled, n_steps, max_iters, tol):
+    rng = np.random.default_rng(seed)
+    N = int(np.prod(shape))
+    noise = rng.uniform(0.5, 1.5, size=shape)
+    # normalised separable Gaussian smoothing, std 0.02
+    sm = noise
+    for ax, n in enumerate(shape):
+        x = cell_centres(n)
+        G = np.exp(-((x[:, None] - x[None, :]) ** 2) / (2.0 * 0.02 ** 2))
+        G /= G.sum(axis=1, keepdims=True)
+        sm = np.moveaxis(np.tensordot(G, np.moveaxis(sm, ax, 0), axes=(1, 0)), 0, ax)
+    p0 = sm / sm.sum()
+    X = _mesh(shape)
+    coef = 1.0 + 0.9 * np.sin(6 * np.pi * X[0]) * np.sin(6 * np.pi * X[1])
+    return Workload(
+        name=name, shape=tuple(shape), gamma=gamma, tau=tau, kind="porous", p0=p0,
+        coef=coef, m=m, density_scale=float(N) if density_scaled else 1.0,
+        n_steps=n_steps, max_iters=max_iters, tol=tol,
+    )
+
+
+def make_workload(name: str, seed: int = 0, projected: bool = True, **over) -> Workload:
+    """Build a named workload.  ``over`` overrides scalar solver parameters
+    (n_steps, max_iters, tol, check_every)."""
+    if name == "crowd32":
+        wl = _crowd(name, (32, 32), 2e-3, 5e-3, 3, 0, ([0.1, 0.1], [0.5, 0.9]),
+                    (0.9, 0.5), 1.5, seed, projected, 10, 300, 0.0)
+    elif name == "crowd256":
+        wl = _crowd(name, (256, 256), 2e-4, 2e-3, 8, 6, ([0.1, 0.1], [0.9, 0.9]),
+                    (0.9, 0.5), 1.2, seed, projected, 50, 2000, 1e-6)
+    elif name == "crowd256_fixed":
+        wl = _crowd(name, (256, 256), 2e-4, 2e-3, 8, 6, ([0.1, 0.1], [0.9, 0.9]),
+                    (0.9, 0.5), 1.2, seed, projected, 20, 300, 0.0)
+    elif name == "porous512":
+        wl = _porous(name, (512, 512), 1e-4, 1e-3, 2.0, seed, False, 40, 300, 1e-6)
+    elif name == "porous512_scaled":
+        wl = _porous(name, (512, 512), 1e-4, 1e-3, 2.0, seed, True, 40, 300, 1e-6)
+    elif name == "crowd128c":
+        wl = _crowd(name, (128, 128, 128), 5e-4, 2e-3, 16, 10,
+                    ([0.1, 0.1, 0.1], [0.9, 0.9, 0.9]), (0.9, 0.5, 0.5), 1.2, seed,
+                    projected, 20, 300, 0.0)
+    else:
+        raise KeyError(name)
+    for k, v in over.items():
+        if not hasattr(wl, k):
+            raise KeyError(k)
+        setattr(wl, k, v)
+    return wl
+
+
+WORKLOADS = ("crowd32", "crowd256", "crowd256_fixed", "porous512", "porous512_scaled",
+             "crowd128c")
+
+
+def small_case(shape, kind="congestion", seed=0, gamma=None, tau=None, n_boxes=None,
+               n_bumps=3, cap_factor=1.5, projected=True, **over) -> Workload:
+    """A workload of arbitrary (possibly ragged) shape for parity tests.
+
+    Same recipe as the named workloads; gamma defaults to a kernel width of a
+    few cells, tau to 2.5 gamma.
+    """
+    d = len(shape)
+    h = 1.0 / max(shape)
+    if gamma is None:
+        gamma = 2.0 * (2.0 * h) ** 2 * 2.0
+    if tau is None:
+        tau = 2.5 * gamma
+    if kind == "congestion":
+        nb = (0 if d == 1 else 2) if n_boxes is None else n_boxes
+        lo = [0.15] * d
+        hi = [0.85] * d
+        wl = _crowd("small", tuple(shape), gamma, tau, n_bumps, nb, (lo, hi),
+                    tuple([0.9] + [0.5] * (d - 1)), cap_factor, seed, projected, 2, 50, 0.0)
+    elif kind in ("porous", "entropy", "zero"):
+        rng = np.random.default_rng(seed)
+        centres = rng.uniform(0.25, 0.75, size=(n_bumps, d))
+        weights = rng.dirichlet(np.ones(n_bumps))
+        p0 = gaussian_bumps(shape, centres, 0.08, weights)
+        coef = 1.0 + 0.5 * rng.uniform(size=shape)
+        wl = Workload(name="small", shape=tuple(shape), gamma=gamma, tau=tau, kind=kind,
+                      p0=p0, coef=coef if kind != "zero" else None, m=2.0,
+                      n_steps=2, max_iters=50)
+    else:
+        raise KeyError(kind)
+    for k, v in over.items():
+        setattr(wl, k, v)
+    return wl
