@@ -1,0 +1,209 @@
+#!/usr/bin/env python3
+"""Throughput of the entropic JKO hot path on one MI355X.
+
+Workload (the 256x256 crowd-motion flow): 2D congestion energy
+f = iota_[0,kappa] + <w, p> with 6 rectangular obstacles (kappa = 0 inside,
+1.2/N outside), w = squared distance to the exit (0.9, 0.5), 8 Gaussian bumps
+projected onto the capacity, gamma = 2e-4, tau = 2e-3; each JKO step iterates
+until the marginal violation ||b * xi^T a - q||_1 <= 1e-6 (checked every 10
+iterations, cap 2000).  A timed "step" is one JKO step of the flow; the flow
+state carries over from step to step.
+
+Prints ONE JSON line.  `value` is Sinkhorn iterations per second (iterations
+whose result the step returns), with every input resident in HBM.  Extras:
+JKO steps/s, the split-BF16 run, the 128^3 3D flow, adjoint/forward time, and
+the roofline of the dominant contraction kernel from HIP-event timings of its
+launches on the library's stream.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_BF16_MFMA_TFLOPS = 2500.0
+PEAK_HBM_GBPS = 8000.0
+
+
+def _args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "split_bf16"])
+    ap.add_argument("--no-extra", action="store_true", help="skip the 3D, split and adjoint extras")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def _dev(a):
+    import torch
+    return None if a is None else torch.from_numpy(np.ascontiguousarray(np.asarray(a, np.float32))).cuda()
+
+
+def _energy(wl):
+    import paper_1502_06216_amd as jk
+    return jk.EnergySpec(kind=wl.kind, w=_dev(wl.w), kappa=_dev(wl.kappa), kappa_scalar=wl.kappa_scalar,
+                         coef=_dev(wl.coef), coef_scalar=wl.coef_scalar, m=wl.m,
+                         density_scale=wl.density_scale)
+
+
+def run_flow(wl, precision, steps, warmup, tol=None, max_iters=None):
+    """Run warmup + timed JKO steps of a workload; returns (iters, seconds, stats)."""
+    import torch
+    import paper_1502_06216_amd as jk
+    en = _energy(wl)
+    tol = wl.tol if tol is None else tol
+    max_iters = wl.max_iters if max_iters is None else max_iters
+    q = _dev(wl.p0)
+    for _ in range(warmup):
+        q, _ = jk.step(q, en, wl.gamma, wl.tau, max_iters=max_iters, tol=tol, check_every=wl.check_every,
+                       precision=precision)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = 0
+    stats = []
+    for _ in range(steps):
+        q, st = jk.step(q, en, wl.gamma, wl.tau, max_iters=max_iters, tol=tol, check_every=wl.check_every,
+                        precision=precision)
+        iters += st["iters"]
+        stats.append(st)
+    torch.cuda.synchronize()
+    return iters, time.perf_counter() - t0, stats, q
+
+
+def roofline(wl, precision, q):
+    """Per-launch durations of the 2d contraction launches of one iteration
+    (HIP events on the library's stream) and the roofline of the slowest."""
+    import paper_1502_06216_amd as jk
+    en = _energy(wl)
+    ms = jk.time_iteration(q, en, wl.gamma, wl.tau, precision=precision, reps=200)
+    d = len(wl.shape)
+    N = int(np.prod(wl.shape))
+    # algorithmic flops of one pass along axis k: 2 n_k N (multiply-add per kernel entry)
+    order = list(range(d - 1, -1, -1)) * 2
+    flops = [2.0 * wl.shape[ax] * N for ax in order]
+    k = int(np.argmax(ms))
+    achieved = flops[k] / (ms[k] * 1e-3) / 1e12
+    peak = PEAK_FP32_MFMA_TFLOPS if precision == "fp32" else PEAK_BF16_MFMA_TFLOPS
+    return {
+        "bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+        "frac": round(achieved / peak, 4), "traffic": None,
+        "kernel": f"contraction pass {k} of {2 * d} (axis {order[k]}, "
+                  f"{'b-update' if k == d - 1 else 'prox' if k == 2 * d - 1 else 'store'} epilogue)",
+        "flops_per_launch": flops[k], "ms_per_launch": round(ms[k], 5),
+        "ms_per_launch_all": [round(x, 5) for x in ms],
+    }
+
+
+def cpu_baseline(wl, seconds):
+    """The FP64 oracle (numpy/BLAS, separable kernel) on the same workload:
+    first JKO step, a fixed number of iterations sized to ~`seconds`."""
+    import oracle as O
+    en = O.Energy(kind=wl.kind, w=wl.w, kappa=wl.kappa, kappa_scalar=wl.kappa_scalar,
+                  coef=wl.coef, coef_scalar=wl.coef_scalar, m=wl.m, density_scale=wl.density_scale)
+    t0 = time.perf_counter()
+    O.jko_step(wl.p0, en, wl.gamma, wl.tau, 10)
+    per_it = (time.perf_counter() - t0) / 10
+    n_it = int(max(10, min(20000, seconds / per_it)))
+    t0 = time.perf_counter()
+    O.jko_step(wl.p0, en, wl.gamma, wl.tau, n_it)
+    el = time.perf_counter() - t0
+    cores = len(os.sched_getaffinity(0))
+    return {
+        "value": round(n_it / el, 3), "unit": "Sinkhorn iters/s", "cores": cores, "kind": "oracle",
+        "sample": f"FP64 oracle jko_step on {wl.name} {wl.shape} (separable numpy/BLAS kernel), "
+                  f"first JKO step, {n_it} fixed iterations, {el:.1f} s; cpu={platform.processor() or 'x86_64'}",
+    }
+
+
+def adjoint_ratio(precision="fp32"):
+    """Forward flow (20 steps x 300 iterations, checkpoints kept) vs backward
+    (recompute + reverse sweep) on the 256x256 crowd workload."""
+    import torch
+    import paper_1502_06216_amd as jk
+    from workloads import make_workload
+    wl = make_workload("crowd256_fixed")
+    en = _energy(wl)
+    p0 = _dev(wl.p0)
+    jk.flow(p0, en, wl.gamma, wl.tau, 1, max_iters=10, checkpoints=True, with_stats=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pT, _, ck = jk.flow(p0, en, wl.gamma, wl.tau, wl.n_steps, max_iters=wl.max_iters, checkpoints=True,
+                        with_stats=False, precision=precision)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    g = torch.ones_like(pT)
+    t0 = time.perf_counter()
+    jk.backward(ck, [wl.max_iters] * wl.n_steps, g, en, wl.gamma, wl.tau, precision=precision)
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    return {"forward_s": round(t_fwd, 4), "backward_s": round(t_bwd, 4), "ratio": round(t_bwd / t_fwd, 3),
+            "workload": "crowd256_fixed 20 steps x 300 iterations"}
+
+
+def main():
+    args = _args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "a flow would shard by slabs along axis 0, which is not built", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1502_06216_amd as jk
+    from workloads import make_workload
+    jk.load()
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+
+    wl = make_workload("crowd256")
+    iters, el, stats, q = run_flow(wl, args.precision, args.steps, args.warmup)
+    value = iters / el
+    line = {
+        "metric": "Sinkhorn iters/s + JKO steps/s at 256^2 and 128^3, FP32 vs split-BF16; adjoint time",
+        "value": round(value, 2),
+        "unit": "Sinkhorn iters/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * el / args.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "bf16x3",
+        "data": "synthetic",
+        "config": {
+            "workload": "crowd256: 2D crowd motion 256x256, 6 obstacles, 8 bumps (projected onto kappa), "
+                        "gamma=2e-4, tau=2e-3, tol 1e-6 L1 (check every 10, cap 2000)",
+            "grid": list(wl.shape), "gamma": wl.gamma, "tau": wl.tau, "tol": wl.tol,
+            "cap": wl.max_iters, "check_every": wl.check_every, "precision": args.precision,
+        },
+        "jko_steps_per_s": round(args.steps / el, 3),
+        "iters_per_step": [s["iters"] for s in stats],
+        "marginal_l1": [s["marginal_l1"] for s in stats],
+    }
+    line["roofline"] = roofline(wl, args.precision, q)
+    extra = {}
+    if not args.no_extra:
+        other = "split_bf16" if args.precision == "fp32" else "fp32"
+        it2, el2, st2, _ = run_flow(wl, other, args.steps, args.warmup)
+        extra[f"crowd256_{other}"] = {"iters_per_s": round(it2 / el2, 2), "jko_steps_per_s": round(args.steps / el2, 3),
+                                      "iters_per_step": [s["iters"] for s in st2]}
+        wl3 = make_workload("crowd128c")
+        for prec in ("fp32", "split_bf16"):
+            it3, el3, st3, q3 = run_flow(wl3, prec, 2, 1, tol=0.0, max_iters=300)
+            extra[f"crowd128c_{prec}"] = {"iters_per_s": round(it3 / el3, 2), "jko_steps_per_s": round(2 / el3, 3),
+                                         "iters_per_step": 300, "roofline": roofline(wl3, prec, q3)}
+        extra["adjoint_fp32"] = adjoint_ratio("fp32")
+    line["extra"] = extra
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(make_workload("crowd256"), args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

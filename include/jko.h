@@ -1,0 +1,194 @@
+/*
+ * jko.h -- C ABI of the MI355X (gfx950) entropic JKO library (libjko.so).
+ *
+ * The library computes entropic Wasserstein gradient-flow (JKO) steps
+ *     p_{t+1} = argmin_{p in simplex} W_gamma(p, p_t) + tau f(p)
+ * (Peyre 2015, Section 2.2, eq. def-jko-operator and eq. smooth-jko) on a
+ * uniform cell-centred grid of [0,1]^d, d in {1,2,3}, with squared Euclidean
+ * ground cost c_ij = |x_i - x_j|^2 (Section 2.1, alpha = 2).  Cell centres
+ * along an axis of length n are (i + 1/2)/n.
+ *
+ * Each step is solved by KL Dykstra in diagonal-scaling form (Section 3.4,
+ * Proposition 3.3, Listing 1): pi = diag(a) xi diag(b) with the Gibbs kernel
+ * xi = exp(-c/gamma) (Section 3.1).  The correction factors u, v of
+ * Proposition 3.3 are identically 1 (u = 1/a after even half-steps), so one
+ * iteration is
+ *     b = q / (xi^T a);  s = xi b;  p = Prox^KL_{(tau/gamma) f}(s);  a = p / s
+ * with q = p_t, a cold-started at 1 at every step (Listing 1, step 2), and the
+ * stopping test of Listing 1 on || b * xi^T a - q ||_1 after an even
+ * half-step.  xi is applied as per-axis dense contractions with the factor
+ * K1[i][j] = exp(-(x_i - x_j)^2 / gamma) (the separable Gaussian kernel of
+ * Section 4.1), exactly (no truncation, no boundary condition).
+ *
+ * Conventions shared by every entry point:
+ *  - Fields are contiguous float32 arrays in row-major order
+ *    n[0] x ... x n[ndim-1] (last axis fastest), N = prod n[k] cells.
+ *  - Every float / double pointer argument named as a field, and the
+ *    workspace, is a DEVICE pointer on the current HIP device; pointers to
+ *    jko_grid / jko_energy / jko_params / jko_stats structs, and the
+ *    iters_per_step array of jko_backward, are HOST pointers.
+ *  - The caller owns every buffer.  The library never allocates device
+ *    memory: all scratch lives in the caller's workspace, whose size is given
+ *    by jko_workspace_bytes().  It keeps one small pinned host buffer and one
+ *    event per process for its stop-test read-back.
+ *  - All work is ordered on `stream` (a hipStream_t; NULL = default stream).
+ *    A call returns before its kernels finish unless it must read a device
+ *    result: a tolerance-mode step (it polls the stop test every
+ *    check_every iterations) or a call with a non-NULL stats pointer.
+ *  - Arguments are validated before any launch; on error nothing is launched
+ *    and a status < 0 is returned.  jko_last_error() describes the last
+ *    failure of the calling thread.
+ *  - Calls that share a workspace must not overlap in time.
+ */
+#ifndef JKO_H
+#define JKO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    JKO_OK = 0,
+    JKO_ERR_INVALID = -1,     /* bad argument (sizes, parameters, null pointer) */
+    JKO_ERR_WORKSPACE = -2,   /* workspace missing or smaller than required */
+    JKO_ERR_HIP = -3,         /* a HIP runtime call failed (see jko_last_error) */
+    JKO_ERR_NONFINITE = -4,   /* NaN/inf met by the FP64 monitor; outputs are still written */
+    JKO_ERR_INFEASIBLE = -5   /* congestion capacity sum(kappa) < sum(p_t) */
+} jko_status;
+
+/* Arithmetic of the Gibbs contractions.  Accumulation is float32 in both;
+ * JKO_SPLIT_BF16 splits each operand x = hi + lo (bfloat16, round to nearest
+ * even) and sums the three MFMA products hi*hi + hi*lo + lo*hi. */
+typedef enum { JKO_FP32 = 0, JKO_SPLIT_BF16 = 1 } jko_precision;
+
+/* Energy f (Section 4).  sigma = tau / gamma below.
+ *  JKO_F_ZERO        f = 0; prox is the identity.
+ *  JKO_F_CONGESTION  f = iota_{[0,kappa]}(p) + <w, p>; prox min(s e^{-sigma w}, kappa)
+ *                    (Section 4.2, Proposition 4.1; kappa may vary in space,
+ *                    kappa = +inf means no cap).
+ *  JKO_F_POROUS      f = sum_i c_i (D p_i)^m / ((m - 1) D), m > 1, density scale D;
+ *                    prox psi solves log psi + k psi^{m-1} = log s with
+ *                    k = sigma c m D^{m-1} / (m - 1) (first-order condition as in
+ *                    Section 4.4, Proposition 4.2), by Newton steps on log psi.
+ *  JKO_F_ENTROPY     f = sum_i c_i p_i (log p_i - 1); prox s^{1/(1 + sigma c)}
+ *                    (Section 4.4, Proposition 4.2 with m = 1). */
+typedef enum { JKO_F_ZERO = 0, JKO_F_CONGESTION = 1, JKO_F_POROUS = 2, JKO_F_ENTROPY = 3 } jko_energy_kind;
+
+typedef struct {
+    int32_t ndim;        /* 1, 2 or 3 */
+    int32_t n[3];        /* axis lengths, 1 <= n[k] <= 1024; unused entries ignored */
+} jko_grid;
+
+typedef struct {
+    int32_t kind;            /* jko_energy_kind */
+    const float* w;          /* congestion potential, N cells, device; NULL = 0 */
+    const float* kappa;      /* congestion capacity, N cells, device; NULL = kappa_scalar */
+    float kappa_scalar;      /* used when kappa == NULL; may be +inf */
+    const float* coef;       /* porous / entropy weight c, N cells, device; NULL = coef_scalar */
+    float coef_scalar;
+    float m;                 /* porous exponent, > 1 */
+    float density_scale;     /* porous D, > 0 (1 = per-cell mass) */
+    int32_t newton_steps;    /* porous Newton steps per cell, 1..32 (0 = default 8) */
+} jko_energy;
+
+typedef struct {
+    double gamma;            /* entropic regularisation, > 0 */
+    double tau;              /* JKO time step, > 0 */
+    double tol_l1;           /* stop when ||b * xi^T a - q||_1 <= tol_l1; <= 0: run max_iters */
+    int32_t max_iters;       /* iteration cap per step, >= 1 */
+    int32_t check_every;     /* stop-test cadence in iterations, >= 1 */
+    int32_t precision;       /* jko_precision */
+    int32_t reserved;
+    double absorb_threshold; /* log-domain absorption when max|log a|,|log b| exceeds it
+                                (checked every check_every iterations); <= 0 or +inf: never */
+} jko_params;
+
+typedef enum { JKO_STOP_TOL = 0, JKO_STOP_CAP = 1 } jko_stop_reason;
+
+typedef struct {
+    int32_t iters;           /* iterations whose p was returned */
+    int32_t absorptions;     /* number of log-domain absorptions performed */
+    int32_t stop_reason;     /* jko_stop_reason */
+    int32_t status;          /* jko_status of this step */
+    double marginal_l1;      /* ||b * xi^T a - q||_1 of the returned iterate (FP64 sum) */
+    double mass;             /* sum of the returned p (FP64 sum) */
+    double max_abs_log_a;    /* max |log a| over cells with a > 0, last check */
+    double max_abs_log_b;    /* max |log b| over cells with b > 0, last check */
+} jko_stats;
+
+/* Operation codes for jko_workspace_bytes. */
+typedef enum { JKO_OP_GIBBS = 0, JKO_OP_STEP = 1, JKO_OP_FLOW = 2, JKO_OP_BACKWARD = 3 } jko_op;
+
+/* Bytes of device workspace `op` needs for this grid and these parameters
+ * (for JKO_OP_BACKWARD, n_steps is the largest iteration count of one step).
+ * Returns 0 when the grid is invalid. */
+size_t jko_workspace_bytes(const jko_grid* grid, const jko_params* params, int32_t op,
+                           int32_t n_steps);
+
+/* y = xi x: the Gibbs kernel of Section 3.1 applied to one field (the
+ * operation Section 3.4 notes the whole method reduces to).  xi is symmetric
+ * on this grid, so this is also xi^T x.  x and y are N-cell device fields
+ * and may not alias.  precision: jko_precision. */
+jko_status jko_gibbs_apply(const jko_grid* grid, double gamma, int32_t precision,
+                           const float* x, float* y, void* workspace, size_t workspace_bytes,
+                           void* stream);
+
+/* One JKO step p_out = Prox^{W_gamma}_{tau f}(p_in) (eq. def-jko-operator) by
+ * the iteration of Listing 1.  p_in >= 0 (any mass); p_out may not alias
+ * p_in.  stats (host, nullable) receives the step's statistics and makes the
+ * call synchronous.  Returns JKO_ERR_INFEASIBLE before launching the
+ * iteration when a congestion capacity cannot hold the mass of p_in. */
+jko_status jko_step(const jko_grid* grid, const jko_energy* energy, const jko_params* params,
+                    const float* p_in, float* p_out, jko_stats* stats,
+                    void* workspace, size_t workspace_bytes, void* stream);
+
+/* n_steps JKO steps from p0 (eq. smooth-jko with fixed gamma, tau).
+ * pT (device, N cells) receives p_{n_steps}.  checkpoints (device, nullable,
+ * n_steps * N floats) receives p_0 ... p_{n_steps-1}, the inputs of each step,
+ * for jko_backward.  stats (host, nullable) is an array of n_steps records. */
+jko_status jko_flow(const jko_grid* grid, const jko_energy* energy, const jko_params* params,
+                    int32_t n_steps, const float* p0, float* pT, float* checkpoints,
+                    jko_stats* stats, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Reverse-mode derivative of L(p_T) through the unrolled flow: given the
+ * checkpoints p_0..p_{n_steps-1} written by jko_flow and the iteration count
+ * of every step (host array, stats[t].iters of the forward), and dL/dp_T,
+ * writes dL/dw (nullable; congestion only) and dL/dp0 (nullable).  Each
+ * step's iterations are recomputed from its checkpoint, their intermediate
+ * Gibbs products are kept in the workspace, then swept in reverse.  The
+ * derivative is that of the map at the given iteration counts (tol_l1 is
+ * ignored).  Energies: ZERO, CONGESTION, ENTROPY, POROUS (dL/dp0 only for
+ * the last two). */
+jko_status jko_backward(const jko_grid* grid, const jko_energy* energy, const jko_params* params,
+                        int32_t n_steps, const int32_t* iters_per_step, const float* checkpoints,
+                        const float* dL_dpT, float* dL_dw, float* dL_dp0,
+                        void* workspace, size_t workspace_bytes, void* stream);
+
+/* Measurement aid (not part of the method): sets up one step of p_in as
+ * jko_step does, then times each of the 2*ndim contraction launches of one
+ * iteration -- the ndim passes of t = xi^T a ending in the b-update epilogue,
+ * then the ndim passes of s = xi b ending in the proximal epilogue -- `reps`
+ * times back to back between two HIP events on `stream`.  ms_per_launch (host,
+ * 2*ndim doubles) receives the mean duration of one launch of each.  The
+ * scalings are set to 1 first; p_in is not modified.  Synchronous. */
+jko_status jko_time_iteration(const jko_grid* grid, const jko_energy* energy, const jko_params* params,
+                              const float* p_in, int32_t reps, double* ms_per_launch,
+                              void* workspace, size_t workspace_bytes, void* stream);
+
+/* Static description of a status code. */
+const char* jko_status_string(int32_t status);
+
+/* Message of the last failure in the calling thread ("" if none). */
+const char* jko_last_error(void);
+
+/* Library version, for the binding's compatibility check. */
+int32_t jko_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JKO_H */

@@ -5,7 +5,7 @@ may import this package.  The HIP library and its Python binding never do: the
 product path has no CPU fallback.
 """
 from .jko_oracle import (  # noqa: F401
-    Energy, grid_points, all_points, gibbs_dense, gibbs_factor, gibbs_apply,
+    Energy, grid_points, all_points, gibbs_dense, gibbs_rows, gibbs_factor, gibbs_apply,
     log_gibbs_apply, prox, log_prox, prox_congestion, prox_entropy, prox_porous,
     lambertw_of_log, dykstra_coupling, dykstra_scaling, jko_step, jko_step_log, jko_flow,
 )

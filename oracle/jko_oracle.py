@@ -84,6 +84,19 @@ def gibbs_dense(shape, gamma: float) -> np.ndarray:
     return np.exp(-cdist(P, P, "sqeuclidean") / gamma)
 
 
+def gibbs_rows(shape, gamma: float, flat_index: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """(xi x)[I] for selected flat cell indices I, each as the plain sum
+    sum_J exp(-|x_I - x_J|^2 / gamma) x_J over all N cells (Section 3.1);
+    for spot checks of large grids."""
+    P = all_points(shape)
+    xv = x.ravel()
+    out = np.empty(len(flat_index))
+    for r, I in enumerate(np.asarray(flat_index)):
+        d2 = ((P - P[I]) ** 2).sum(axis=1)
+        out[r] = np.dot(np.exp(-d2 / gamma), xv)
+    return out
+
+
 def gibbs_factor(n: int, gamma: float) -> np.ndarray:
     """One-axis factor K1_ij = exp(-(x_i - x_j)^2 / gamma).  On a uniform grid
     with squared Euclidean cost, xi is the Kronecker product of these factors

@@ -1,0 +1,18 @@
+"""MI355X-native entropic Wasserstein gradient flows (JKO) -- HIP for gfx950.
+
+The compute path is libjko.so (hand-written HIP kernels behind a C ABI,
+``include/jko.h``); this package is its thin Python binding.  See
+``paper_1502_06216_amd._native`` for the calls:
+
+* ``gibbs_apply(x, gamma, precision)``   y = xi x
+* ``step(p, energy, gamma, tau, ...)``    one JKO step (Listing 1 of the paper)
+* ``flow(p0, energy, gamma, tau, n_steps, ...)``
+* ``backward(checkpoints, iters, dL_dpT, energy, gamma, tau)``
+* ``JKOFlowFn`` -- torch.autograd.Function over flow/backward
+"""
+from ._native import (  # noqa: F401
+    EnergySpec, JKOError, JKOFlowFn, backward, time_iteration, flow, gibbs_apply, load, step, workspace_bytes,
+    make_grid, make_params, Grid, EnergyC, Params, Stats, LIB_PATH,
+    JKO_OK, JKO_ERR_INVALID, JKO_ERR_WORKSPACE, JKO_ERR_HIP, JKO_ERR_NONFINITE, JKO_ERR_INFEASIBLE,
+    OP_GIBBS, OP_STEP, OP_FLOW, OP_BACKWARD,
+)

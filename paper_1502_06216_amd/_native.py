@@ -1,0 +1,313 @@
+"""ctypes binding of libjko.so (argument marshalling only).
+
+Every computation happens in the HIP library; this module checks dtypes,
+devices and contiguity, allocates the caller-owned workspace with torch, and
+passes raw device pointers and the current HIP stream.  There is no CPU
+fallback: if the library is not built, or no GPU is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libjko.so")
+
+# status codes (include/jko.h)
+JKO_OK = 0
+JKO_ERR_INVALID = -1
+JKO_ERR_WORKSPACE = -2
+JKO_ERR_HIP = -3
+JKO_ERR_NONFINITE = -4
+JKO_ERR_INFEASIBLE = -5
+
+PRECISIONS = {"fp32": 0, "split_bf16": 1}
+ENERGY_KINDS = {"zero": 0, "congestion": 1, "porous": 2, "entropy": 3}
+OP_GIBBS, OP_STEP, OP_FLOW, OP_BACKWARD = 0, 1, 2, 3
+
+
+class JKOError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"jko status {status}: {message}")
+        self.status = status
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("n", ctypes.c_int32 * 3)]
+
+
+class EnergyC(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("w", ctypes.c_void_p), ("kappa", ctypes.c_void_p),
+                ("kappa_scalar", ctypes.c_float), ("coef", ctypes.c_void_p),
+                ("coef_scalar", ctypes.c_float), ("m", ctypes.c_float),
+                ("density_scale", ctypes.c_float), ("newton_steps", ctypes.c_int32)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("tau", ctypes.c_double), ("tol_l1", ctypes.c_double),
+                ("max_iters", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("absorb_threshold", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("absorptions", ctypes.c_int32),
+                ("stop_reason", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("marginal_l1", ctypes.c_double), ("mass", ctypes.c_double),
+                ("max_abs_log_a", ctypes.c_double), ("max_abs_log_b", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return dict(iters=self.iters, absorptions=self.absorptions,
+                    stop="tol" if self.stop_reason == 0 else "cap", status=self.status,
+                    marginal_l1=self.marginal_l1, mass=self.mass,
+                    max_abs_log_a=self.max_abs_log_a, max_abs_log_b=self.max_abs_log_b)
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libjko.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1502_06216_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, sz, i32, f64 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_double
+    G, E, P, S = ctypes.POINTER(Grid), ctypes.POINTER(EnergyC), ctypes.POINTER(Params), ctypes.POINTER(Stats)
+    lib.jko_workspace_bytes.argtypes = [G, P, i32, i32]
+    lib.jko_workspace_bytes.restype = sz
+    lib.jko_gibbs_apply.argtypes = [G, f64, i32, vp, vp, vp, sz, vp]
+    lib.jko_gibbs_apply.restype = i32
+    lib.jko_step.argtypes = [G, E, P, vp, vp, S, vp, sz, vp]
+    lib.jko_step.restype = i32
+    lib.jko_flow.argtypes = [G, E, P, i32, vp, vp, vp, S, vp, sz, vp]
+    lib.jko_flow.restype = i32
+    lib.jko_backward.argtypes = [G, E, P, i32, ctypes.POINTER(i32), vp, vp, vp, vp, vp, sz, vp]
+    lib.jko_backward.restype = i32
+    lib.jko_time_iteration.argtypes = [G, E, P, vp, i32, ctypes.POINTER(f64), vp, sz, vp]
+    lib.jko_time_iteration.restype = i32
+    lib.jko_status_string.argtypes = [i32]
+    lib.jko_status_string.restype = ctypes.c_char_p
+    lib.jko_last_error.argtypes = []
+    lib.jko_last_error.restype = ctypes.c_char_p
+    lib.jko_version.argtypes = []
+    lib.jko_version.restype = i32
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != JKO_OK:
+        lib = load()
+        msg = lib.jko_last_error().decode() or lib.jko_status_string(status).decode()
+        raise JKOError(status, msg)
+
+
+def make_grid(shape: Sequence[int]) -> Grid:
+    g = Grid()
+    g.ndim = len(shape)
+    for k in range(3):
+        g.n[k] = int(shape[k]) if k < len(shape) else 1
+    return g
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _field(t: Optional[torch.Tensor], shape, name: str) -> Optional[torch.Tensor]:
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float32 or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+        raise TypeError(f"{name} must be a contiguous float32 tensor of shape {tuple(shape)}")
+    return t
+
+
+def _stream(device: torch.device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+@dataclass
+class EnergySpec:
+    """Energy f of the JKO step (Section 4 of the paper); fields are device
+    float32 tensors of the grid's shape or None for the scalar defaults."""
+    kind: str = "zero"
+    w: Optional[torch.Tensor] = None
+    kappa: Optional[torch.Tensor] = None
+    kappa_scalar: float = math.inf
+    coef: Optional[torch.Tensor] = None
+    coef_scalar: float = 1.0
+    m: float = 2.0
+    density_scale: float = 1.0
+    newton_steps: int = 8
+
+    def to_c(self, shape) -> EnergyC:
+        e = EnergyC()
+        e.kind = ENERGY_KINDS[self.kind]
+        e.w = _ptr(_field(self.w, shape, "w"))
+        e.kappa = _ptr(_field(self.kappa, shape, "kappa"))
+        e.kappa_scalar = float(self.kappa_scalar)
+        e.coef = _ptr(_field(self.coef, shape, "coef"))
+        e.coef_scalar = float(self.coef_scalar)
+        e.m = float(self.m)
+        e.density_scale = float(self.density_scale)
+        e.newton_steps = int(self.newton_steps)
+        return e
+
+
+def make_params(gamma, tau, max_iters=300, tol=0.0, check_every=10, precision="fp32",
+                absorb_threshold=math.inf) -> Params:
+    p = Params()
+    p.gamma = float(gamma)
+    p.tau = float(tau)
+    p.tol_l1 = float(tol)
+    p.max_iters = int(max_iters)
+    p.check_every = int(check_every)
+    p.precision = PRECISIONS[precision]
+    p.reserved = 0
+    p.absorb_threshold = float(absorb_threshold)
+    return p
+
+
+def workspace_bytes(shape, op: int, n: int = 0, params: Optional[Params] = None) -> int:
+    lib = load()
+    g = make_grid(shape)
+    return int(lib.jko_workspace_bytes(ctypes.byref(g), ctypes.byref(params) if params else None, op, n))
+
+
+def gibbs_apply(x: torch.Tensor, gamma: float, precision: str = "fp32",
+                out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """y = xi x for a float32 field on the GPU (xi = exp(-|x_i - x_j|^2/gamma))."""
+    lib = load()
+    shape = tuple(x.shape)
+    _field(x, shape, "x")
+    y = torch.empty_like(x) if out is None else _field(out, shape, "out")
+    g = make_grid(shape)
+    nb = lib.jko_workspace_bytes(ctypes.byref(g), None, OP_GIBBS, 0)
+    ws = _workspace(nb, x.device)
+    _check(lib.jko_gibbs_apply(ctypes.byref(g), float(gamma), PRECISIONS[precision], _ptr(x), _ptr(y),
+                               _ptr(ws), ws.numel(), _stream(x.device)))
+    return y
+
+
+def step(p: torch.Tensor, energy: EnergySpec, gamma: float, tau: float, max_iters: int = 300,
+         tol: float = 0.0, check_every: int = 10, precision: str = "fp32",
+         absorb_threshold: float = math.inf, out: Optional[torch.Tensor] = None,
+         with_stats: bool = True):
+    """One JKO step p -> argmin_p' W_gamma(p', p) + tau f(p').  Returns
+    (p_next, stats dict or None)."""
+    lib = load()
+    shape = tuple(p.shape)
+    _field(p, shape, "p")
+    pout = torch.empty_like(p) if out is None else _field(out, shape, "out")
+    g = make_grid(shape)
+    prm = make_params(gamma, tau, max_iters, tol, check_every, precision, absorb_threshold)
+    e = energy.to_c(shape)
+    nb = lib.jko_workspace_bytes(ctypes.byref(g), ctypes.byref(prm), OP_STEP, 0)
+    ws = _workspace(nb, p.device)
+    st = Stats()
+    _check(lib.jko_step(ctypes.byref(g), ctypes.byref(e), ctypes.byref(prm), _ptr(p), _ptr(pout),
+                        ctypes.byref(st) if with_stats else None, _ptr(ws), ws.numel(), _stream(p.device)))
+    return pout, (st.as_dict() if with_stats else None)
+
+
+def flow(p0: torch.Tensor, energy: EnergySpec, gamma: float, tau: float, n_steps: int,
+         max_iters: int = 300, tol: float = 0.0, check_every: int = 10, precision: str = "fp32",
+         absorb_threshold: float = math.inf, checkpoints: bool = False, with_stats: bool = True,
+         out: Optional[torch.Tensor] = None):
+    """n_steps JKO steps from p0.  Returns (p_T, stats list or None,
+    checkpoints tensor (n_steps, *shape) or None)."""
+    lib = load()
+    shape = tuple(p0.shape)
+    _field(p0, shape, "p0")
+    pT = torch.empty_like(p0) if out is None else _field(out, shape, "out")
+    ck = torch.empty((n_steps,) + shape, dtype=torch.float32, device=p0.device) if checkpoints else None
+    g = make_grid(shape)
+    prm = make_params(gamma, tau, max_iters, tol, check_every, precision, absorb_threshold)
+    e = energy.to_c(shape)
+    nb = lib.jko_workspace_bytes(ctypes.byref(g), ctypes.byref(prm), OP_FLOW, n_steps)
+    ws = _workspace(nb, p0.device)
+    sts = (Stats * n_steps)() if with_stats else None
+    _check(lib.jko_flow(ctypes.byref(g), ctypes.byref(e), ctypes.byref(prm), int(n_steps), _ptr(p0), _ptr(pT),
+                        _ptr(ck), sts, _ptr(ws), ws.numel(), _stream(p0.device)))
+    return pT, ([s.as_dict() for s in sts] if with_stats else None), ck
+
+
+def backward(checkpoints: torch.Tensor, iters_per_step: Sequence[int], dL_dpT: torch.Tensor,
+             energy: EnergySpec, gamma: float, tau: float, precision: str = "fp32",
+             want_w: bool = True, want_p0: bool = True):
+    """Gradients (dL/dw or None, dL/dp0 or None) of L(p_T) through the flow
+    recorded in `checkpoints` at the given iteration counts."""
+    lib = load()
+    n_steps = int(checkpoints.shape[0])
+    shape = tuple(checkpoints.shape[1:])
+    if not checkpoints.is_contiguous() or checkpoints.dtype != torch.float32:
+        raise TypeError("checkpoints must be contiguous float32")
+    _field(dL_dpT, shape, "dL_dpT")
+    iters = (ctypes.c_int32 * n_steps)(*[int(k) for k in iters_per_step])
+    g = make_grid(shape)
+    prm = make_params(gamma, tau, max(iters_per_step), 0.0, 1, precision)
+    e = energy.to_c(shape)
+    nb = lib.jko_workspace_bytes(ctypes.byref(g), ctypes.byref(prm), OP_BACKWARD, max(iters_per_step))
+    ws = _workspace(nb, dL_dpT.device)
+    gw = torch.empty_like(dL_dpT) if want_w else None
+    gp = torch.empty_like(dL_dpT) if want_p0 else None
+    _check(lib.jko_backward(ctypes.byref(g), ctypes.byref(e), ctypes.byref(prm), n_steps, iters,
+                            _ptr(checkpoints), _ptr(dL_dpT), _ptr(gw), _ptr(gp), _ptr(ws), ws.numel(),
+                            _stream(dL_dpT.device)))
+    return gw, gp
+
+
+def time_iteration(p: torch.Tensor, energy: EnergySpec, gamma: float, tau: float,
+                   precision: str = "fp32", reps: int = 50):
+    """Mean duration (ms) of each contraction launch of one iteration, timed
+    with HIP events on the current stream (measurement aid)."""
+    lib = load()
+    shape = tuple(p.shape)
+    _field(p, shape, "p")
+    g = make_grid(shape)
+    prm = make_params(gamma, tau, 1, 0.0, 1, precision)
+    e = energy.to_c(shape)
+    nb = lib.jko_workspace_bytes(ctypes.byref(g), ctypes.byref(prm), OP_STEP, 0)
+    ws = _workspace(nb, p.device)
+    out = (ctypes.c_double * (2 * len(shape)))()
+    _check(lib.jko_time_iteration(ctypes.byref(g), ctypes.byref(e), ctypes.byref(prm), _ptr(p), int(reps), out,
+                                  _ptr(ws), ws.numel(), _stream(p.device)))
+    return list(out)
+
+
+class JKOFlowFn(torch.autograd.Function):
+    """p_T = JKO flow of p0 for the congestion energy with potential w, at
+    fixed iteration counts; backward calls the library's adjoint, which
+    recomputes each step from its checkpoint."""
+
+    @staticmethod
+    def forward(ctx, p0, w, kappa, gamma, tau, n_steps, iters, precision):
+        en = EnergySpec(kind="congestion", w=w.detach(), kappa=kappa)
+        pT, stats, ck = flow(p0.detach(), en, gamma, tau, n_steps, max_iters=iters, tol=0.0,
+                             precision=precision, checkpoints=True, with_stats=False)
+        ctx.save_for_backward(ck, w.detach(), kappa)
+        ctx.cfg = (gamma, tau, n_steps, iters, precision)
+        return pT
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        ck, w, kappa = ctx.saved_tensors
+        gamma, tau, n_steps, iters, precision = ctx.cfg
+        en = EnergySpec(kind="congestion", w=w, kappa=kappa)
+        gw, gp = backward(ck, [iters] * n_steps, grad_out.contiguous(), en, gamma, tau, precision,
+                          want_w=ctx.needs_input_grad[1], want_p0=ctx.needs_input_grad[0])
+        return gp, gw, None, None, None, None, None, None

@@ -1,0 +1,728 @@
+// Host driver and C ABI of libjko (see include/jko.h).
+//
+// One JKO step runs Listing 1 of the paper in the reduced scaling form of
+// Proposition 3.3:  per iteration  t = xi^T a -> b = q / t  and
+// s = xi b -> p = Prox(s), a = p / s, each Gibbs application being d per-axis
+// contraction passes whose last pass carries the pointwise update.  The stop
+// test of Listing 1 (|| b * xi^T a - q ||_1 <= tol after an even half-step) is
+// computed on the device every `check_every` iterations from the t of the next
+// iteration; the host queues iterations one check interval ahead of the test
+// it has read back, and every kernel returns at once when the device control
+// block says the step is done, so the GPU never idles on the read-back.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "jko_internal.h"
+
+using namespace jko;
+
+namespace {
+
+thread_local std::string g_err;
+
+jko_status fail(jko_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIP_TRY(x)                                                                  \
+    do {                                                                            \
+        hipError_t e_ = (x);                                                        \
+        if (e_ != hipSuccess)                                                       \
+            return fail(JKO_ERR_HIP, "%s failed: %s", #x, hipGetErrorString(e_));   \
+    } while (0)
+
+constexpr int kMaxN = 1024;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Geo {
+    int d = 0;
+    int n[3] = {1, 1, 1};
+    int64_t N = 0;
+};
+
+bool geo_of(const jko_grid* g, Geo* out) {
+    if (!g || g->ndim < 1 || g->ndim > 3) return false;
+    Geo r;
+    r.d = g->ndim;
+    r.N = 1;
+    for (int k = 0; k < r.d; ++k) {
+        if (g->n[k] < 1 || g->n[k] > kMaxN) return false;
+        r.n[k] = g->n[k];
+        r.N *= g->n[k];
+    }
+    *out = r;
+    return true;
+}
+
+// The passes of one application of xi, in order: axis d-1 (contiguous, LAST
+// form) first, then axes d-2 .. 0 (OUTER form).  in/out buffers are chosen by
+// the caller; the last pass writes through the epilogue.
+struct PassShape {
+    Form form;
+    int64_t R, B, M;
+    int n;
+    int axis;
+};
+
+std::vector<PassShape> passes_of(const Geo& g) {
+    std::vector<PassShape> v;
+    const int d = g.d;
+    int64_t outer = 1;
+    for (int k = 0; k < d - 1; ++k) outer *= g.n[k];
+    v.push_back(PassShape{Form::LAST, outer, 1, 1, g.n[d - 1], d - 1});
+    int64_t inner = g.n[d - 1];
+    for (int k = d - 2; k >= 0; --k) {
+        int64_t B = 1;
+        for (int j = 0; j < k; ++j) B *= g.n[j];
+        v.push_back(PassShape{Form::OUTER, 1, B, inner, g.n[k], k});
+        inner *= g.n[k];
+    }
+    return v;
+}
+
+Pass make_pass(const PassShape& ps) {
+    Pass p{};
+    p.form = ps.form;
+    p.R = ps.R;
+    p.B = ps.B;
+    p.M = ps.M;
+    p.n = ps.n;
+    return p;
+}
+
+// ---------------------------------------------------------------- workspace
+
+enum : int { OP_GIBBS = 0, OP_STEP = 1, OP_FLOW = 2, OP_BACKWARD = 3 };
+
+struct Layout {
+    size_t ctl = 0, hostout = 0, part = 0, factors = 0, fields = 0, hist = 0, stats = 0, total = 0;
+    int part_cap = 0;
+    size_t factor_off[3] = {0, 0, 0};
+    int nfields = 0;
+    int64_t hist_fields = 0;
+};
+
+int part_cap_of(const Geo& g) {
+    int64_t cap = 768;   // input check uses 3 x 256
+    for (const PassShape& ps : passes_of(g)) {
+        const int64_t b = contract_max_blocks(make_pass(ps), 0);
+        if (b > cap) cap = b;
+    }
+    return (int)cap;
+}
+
+Layout layout_of(const Geo& g, int op, int64_t iters_or_steps) {
+    Layout L;
+    size_t off = 0;
+    L.ctl = off;
+    off += align_up(sizeof(Ctl));
+    L.hostout = off;
+    off += align_up(8 * sizeof(double));
+    L.part_cap = part_cap_of(g);
+    L.part = off;
+    off += align_up(4 * (size_t)L.part_cap * sizeof(double));
+    L.factors = off;
+    for (int k = 0; k < g.d; ++k) {
+        int same = -1;
+        for (int j = 0; j < k; ++j)
+            if (g.n[j] == g.n[k]) same = j;
+        if (same >= 0) {
+            L.factor_off[k] = L.factor_off[same];
+            continue;
+        }
+        const size_t nn = (size_t)g.n[k] * g.n[k];
+        L.factor_off[k] = off;
+        off += align_up(nn * sizeof(float)) + 2 * align_up(nn * sizeof(uint16_t));
+    }
+    // fields: z1, z2 (all ops); a, b, g, kf (step+); p ping-pong x2 (flow+);
+    // backward: q, abar, sbar, bbar, tbar, qbar, pbar, wacc, tmp
+    int nf = 2;
+    if (op >= OP_STEP) nf += 4;
+    if (op >= OP_FLOW) nf += 2;
+    if (op == OP_BACKWARD) nf += 9;
+    L.nfields = nf;
+    L.fields = off;
+    off += (size_t)nf * align_up((size_t)g.N * sizeof(float));
+    if (op == OP_BACKWARD) {
+        L.hist_fields = 2 * std::max<int64_t>(iters_or_steps, 1);
+        L.hist = off;
+        off += (size_t)L.hist_fields * align_up((size_t)g.N * sizeof(float));
+    }
+    if (op == OP_FLOW) {
+        L.stats = off;
+        off += align_up((size_t)std::max<int64_t>(iters_or_steps, 1) * 8 * sizeof(double));
+    }
+    L.total = off;
+    return L;
+}
+
+struct Plan {
+    Geo g;
+    Layout L;
+    char* base = nullptr;
+    Ctl* ctl = nullptr;
+    double* hostout = nullptr;
+    Partials part{};
+    const float* K1[3] = {};
+    const uint16_t* K1hi[3] = {};
+    const uint16_t* K1lo[3] = {};
+    float* field[24] = {};
+    hipStream_t st = nullptr;
+    int prec = 0;
+
+    float* F(int i) const { return field[i]; }
+    float* hist(int64_t i) const {
+        return reinterpret_cast<float*>(base + L.hist + (size_t)i * align_up((size_t)g.N * sizeof(float)));
+    }
+};
+
+enum : int { F_Z1 = 0, F_Z2, F_A, F_B, F_G, F_KF, F_P0, F_P1, F_Q, F_ABAR, F_SBAR, F_BBAR, F_TBAR, F_QBAR,
+             F_PBAR, F_WACC, F_TMP };
+
+jko_status carve(Plan* P, const Geo& g, int op, int64_t extra, void* ws, size_t ws_bytes, int prec,
+                 hipStream_t st) {
+    P->g = g;
+    P->L = layout_of(g, op, extra);
+    if (!ws) return fail(JKO_ERR_WORKSPACE, "workspace is NULL (%zu bytes needed)", P->L.total);
+    if (ws_bytes < P->L.total)
+        return fail(JKO_ERR_WORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, P->L.total);
+    if (((uintptr_t)ws) % 16 != 0) return fail(JKO_ERR_WORKSPACE, "workspace must be 16-byte aligned");
+    P->base = static_cast<char*>(ws);
+    P->ctl = reinterpret_cast<Ctl*>(P->base + P->L.ctl);
+    P->hostout = reinterpret_cast<double*>(P->base + P->L.hostout);
+    double* pd = reinterpret_cast<double*>(P->base + P->L.part);
+    const int cap = P->L.part_cap;
+    P->part = Partials{pd, pd + cap, pd + 2 * cap, pd + 3 * cap, cap};
+    for (int k = 0; k < g.d; ++k) {
+        const size_t nn = (size_t)g.n[k] * g.n[k];
+        char* f = P->base + P->L.factor_off[k];
+        P->K1[k] = reinterpret_cast<const float*>(f);
+        P->K1hi[k] = reinterpret_cast<const uint16_t*>(f + align_up(nn * sizeof(float)));
+        P->K1lo[k] = reinterpret_cast<const uint16_t*>(f + align_up(nn * sizeof(float)) +
+                                                       align_up(nn * sizeof(uint16_t)));
+    }
+    for (int i = 0; i < P->L.nfields; ++i)
+        P->field[i] = reinterpret_cast<float*>(P->base + P->L.fields +
+                                               (size_t)i * align_up((size_t)g.N * sizeof(float)));
+    P->st = st;
+    P->prec = prec;
+    return JKO_OK;
+}
+
+jko_status build_factors(const Plan& P, double gamma) {
+    for (int k = 0; k < P.g.d; ++k) {
+        bool done = false;
+        for (int j = 0; j < k; ++j)
+            if (P.g.n[j] == P.g.n[k]) done = true;
+        if (done) continue;
+        HIP_TRY(launch_build_factor(const_cast<float*>(P.K1[k]), const_cast<uint16_t*>(P.K1hi[k]),
+                                    const_cast<uint16_t*>(P.K1lo[k]), P.g.n[k], gamma, P.st));
+    }
+    return JKO_OK;
+}
+
+// y = xi x with the last pass's result handed to `epi`.  Uses z1, z2 as
+// intermediates; x must not alias them.  *nblocks = blocks of the last pass.
+jko_status apply_xi(const Plan& P, const float* x, EpiArgs epi, int* nblocks) {
+    const std::vector<PassShape> ps = passes_of(P.g);
+    const float* in = x;
+    for (size_t i = 0; i < ps.size(); ++i) {
+        Pass pass = make_pass(ps[i]);
+        pass.K1 = P.K1[ps[i].axis];
+        pass.K1hi = P.K1hi[ps[i].axis];
+        pass.K1lo = P.K1lo[ps[i].axis];
+        pass.X = in;
+        const bool last = (i + 1 == ps.size());
+        EpiArgs e;
+        int nb = 0;
+        if (last) {
+            e = epi;
+        } else {
+            e = EpiArgs{};
+            e.kind = EpiKind::STORE;
+            e.y = P.F((i % 2 == 0) ? F_Z1 : F_Z2);
+            e.ctl = epi.ctl;
+            e.part = epi.part;
+        }
+        HIP_TRY(launch_contract(pass, P.prec, e, &nb, P.st));
+        if (last && nblocks) *nblocks = nb;
+        if (!last) in = e.y;
+    }
+    return JKO_OK;
+}
+
+// Pinned host mirror of the control block (one per process) and its event.
+struct Readback {
+    Ctl* host = nullptr;
+    hipEvent_t ev = nullptr;
+    int device = -1;
+};
+thread_local Readback g_rb;
+
+jko_status readback_init() {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (g_rb.host && g_rb.device == dev) return JKO_OK;
+    if (!g_rb.host) HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&g_rb.host), 4 * sizeof(Ctl), hipHostMallocDefault));
+    if (g_rb.ev && g_rb.device != dev) {
+        (void)hipEventDestroy(g_rb.ev);
+        g_rb.ev = nullptr;
+    }
+    if (!g_rb.ev) HIP_TRY(hipEventCreateWithFlags(&g_rb.ev, hipEventDisableTiming));
+    g_rb.device = dev;
+    return JKO_OK;
+}
+
+jko_status read_ctl(const Plan& P, Ctl* out) {
+    HIP_TRY(hipMemcpyAsync(g_rb.host, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, P.st));
+    HIP_TRY(hipStreamSynchronize(P.st));
+    *out = *g_rb.host;
+    return JKO_OK;
+}
+
+// ---------------------------------------------------------------- validation
+
+jko_status check_params(const jko_params* pr) {
+    if (!pr) return fail(JKO_ERR_INVALID, "params is NULL");
+    if (!(pr->gamma > 0.0) || !isfinite(pr->gamma)) return fail(JKO_ERR_INVALID, "gamma must be finite and > 0");
+    if (!(pr->tau > 0.0) || !isfinite(pr->tau)) return fail(JKO_ERR_INVALID, "tau must be finite and > 0");
+    if (pr->max_iters < 1) return fail(JKO_ERR_INVALID, "max_iters must be >= 1");
+    if (pr->check_every < 1) return fail(JKO_ERR_INVALID, "check_every must be >= 1");
+    if (pr->precision != JKO_FP32 && pr->precision != JKO_SPLIT_BF16)
+        return fail(JKO_ERR_INVALID, "unknown precision %d", pr->precision);
+    if (isnan(pr->tol_l1)) return fail(JKO_ERR_INVALID, "tol_l1 is NaN");
+    return JKO_OK;
+}
+
+jko_status check_energy(const jko_energy* en) {
+    if (!en) return fail(JKO_ERR_INVALID, "energy is NULL");
+    switch (en->kind) {
+        case JKO_F_ZERO:
+            return JKO_OK;
+        case JKO_F_CONGESTION:
+            if (!en->kappa && (isnan(en->kappa_scalar) || en->kappa_scalar < 0.f))
+                return fail(JKO_ERR_INVALID, "kappa_scalar must be >= 0 (or +inf)");
+            return JKO_OK;
+        case JKO_F_ENTROPY:
+            if (!en->coef && !(en->coef_scalar >= 0.f)) return fail(JKO_ERR_INVALID, "coef_scalar must be >= 0");
+            return JKO_OK;
+        case JKO_F_POROUS:
+            if (!(en->m > 1.f) || !isfinite(en->m)) return fail(JKO_ERR_INVALID, "porous exponent m must be > 1");
+            if (!(en->density_scale > 0.f)) return fail(JKO_ERR_INVALID, "density_scale must be > 0");
+            if (!en->coef && !(en->coef_scalar >= 0.f)) return fail(JKO_ERR_INVALID, "coef_scalar must be >= 0");
+            if (en->newton_steps < 0 || en->newton_steps > 32)
+                return fail(JKO_ERR_INVALID, "newton_steps must be in 0..32");
+            return JKO_OK;
+        default:
+            return fail(JKO_ERR_INVALID, "unknown energy kind %d", en->kind);
+    }
+}
+
+ProxArgs prox_args(const Plan& P, const jko_energy* en, double sigma) {
+    ProxArgs px{};
+    px.kind = en->kind;
+    px.m = en->m;
+    px.newton = en->newton_steps > 0 ? en->newton_steps : 8;
+    if (en->kind == JKO_F_CONGESTION) {
+        px.g = en->w ? P.F(F_G) : nullptr;
+        px.kappa = en->kappa;
+        px.kappa_s = en->kappa_scalar;
+    } else if (en->kind == JKO_F_ENTROPY) {
+        if (en->coef) px.kf = P.F(F_KF);
+        else px.kf_s = (float)(1.0 / (1.0 + sigma * (double)en->coef_scalar));
+    } else if (en->kind == JKO_F_POROUS) {
+        if (en->coef) px.kf = P.F(F_KF);
+        else {
+            const double m = en->m;
+            px.kf_s = (float)log(sigma * (double)en->coef_scalar * m * pow((double)en->density_scale, m - 1.0));
+        }
+    }
+    return px;
+}
+
+jko_status prepare_energy(const Plan& P, const jko_energy* en, double sigma) {
+    const bool need = (en->kind == JKO_F_CONGESTION && en->w) ||
+                      ((en->kind == JKO_F_ENTROPY || en->kind == JKO_F_POROUS) && en->coef);
+    if (!need) return JKO_OK;
+    HIP_TRY(launch_prepare_energy(en, sigma, P.g.N, P.F(F_G), P.F(F_KF), P.st));
+    return JKO_OK;
+}
+
+// Capacity / finiteness check of a density (synchronous).
+jko_status input_check(const Plan& P, const jko_energy* en, const float* p) {
+    HIP_TRY(launch_input_check(p, en->kappa, en->kappa_scalar, P.g.N, en->kind == JKO_F_CONGESTION,
+                               P.part.err, 3 * 256, P.hostout, P.st));
+    double h[3];
+    HIP_TRY(hipMemcpyAsync(g_rb.host, P.hostout, 3 * sizeof(double), hipMemcpyDeviceToHost, P.st));
+    HIP_TRY(hipStreamSynchronize(P.st));
+    memcpy(h, g_rb.host, sizeof h);
+    if (h[2] > 0.0) return fail(JKO_ERR_NONFINITE, "input density or capacity has %g negative/non-finite cells", h[2]);
+    if (en->kind == JKO_F_CONGESTION && h[1] < h[0] * (1.0 - 1e-6))
+        return fail(JKO_ERR_INFEASIBLE, "capacity sum %.9g < mass %.9g", h[1], h[0]);
+    return JKO_OK;
+}
+
+// ----------------------------------------------------------------- one step
+
+struct StepOut {
+    jko_stats st{};
+};
+
+// Runs the iteration of one step with q (device) -> p_out (device).  When
+// `t_hist`/`s_hist` are set, iteration k stores t_k and s_k into
+// P.hist(2(k-1)) and P.hist(2(k-1)+1) (adjoint recomputation, fixed count).
+jko_status run_step(const Plan& P, const jko_params* pr, const ProxArgs& px, const float* q, float* p_out,
+                    bool want_stats, bool record_hist, jko_stats* st_out) {
+    const int K = pr->max_iters;
+    const int ce = pr->check_every;
+    const bool tolmode = pr->tol_l1 > 0.0;
+    float* a = P.F(F_A);
+    float* b = P.F(F_B);
+
+    HIP_TRY(launch_fill(a, 1.f, P.g.N, P.st));
+    HIP_TRY(launch_ctl_reset(P.ctl, P.st));
+
+    EpiArgs eb{};
+    eb.kind = EpiKind::BUPDATE;
+    eb.q = q;
+    eb.b = b;
+    eb.part = P.part;
+    eb.ctl = P.ctl;
+    EpiArgs ep{};
+    ep.kind = EpiKind::PROX;
+    ep.a = a;
+    ep.p_out = p_out;
+    ep.prox = px;
+    ep.part = P.part;
+    ep.ctl = P.ctl;
+
+    bool pending = false;   // a read-back of the control block is in flight
+    bool stopped = false;
+    int nb = 0;
+    for (int k = 1; k <= K; ++k) {
+        eb.check = (tolmode && k > 1 && (k - 1) % ce == 0) ? 1 : 0;
+        eb.t_out = record_hist ? P.hist(2 * (int64_t)(k - 1)) : nullptr;
+        jko_status s = apply_xi(P, a, eb, &nb);
+        if (s) return s;
+        if (eb.check) {
+            HIP_TRY(launch_ctl_check(P.ctl, P.part, nb, k, pr->tol_l1, 1, P.st));
+            // Look at the previous stop test while this interval is queued,
+            // then queue the read-back of this one.
+            if (pending) {
+                HIP_TRY(hipEventSynchronize(g_rb.ev));
+                if (g_rb.host->done) stopped = true;
+            }
+            if (stopped) break;
+            HIP_TRY(hipMemcpyAsync(g_rb.host, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, P.st));
+            HIP_TRY(hipEventRecord(g_rb.ev, P.st));
+            pending = true;
+        }
+        const bool cand = (tolmode && k % ce == 0) || k == K;
+        ep.check = cand ? 1 : 0;
+        ep.write_p = cand ? 1 : 0;
+        ep.s_out = record_hist ? P.hist(2 * (int64_t)(k - 1) + 1) : nullptr;
+        s = apply_xi(P, b, ep, &nb);
+        if (s) return s;
+    }
+    Ctl c{};
+    if (tolmode || want_stats) {
+        HIP_TRY(hipStreamSynchronize(P.st));
+        jko_status s = read_ctl(P, &c);
+        if (s) return s;
+        if (!c.done && want_stats) {
+            // Cap reached: violation of the returned iterate, one more t = xi^T a.
+            EpiArgs em{};
+            em.kind = EpiKind::MONITOR;
+            em.q = q;
+            em.b = b;
+            em.part = P.part;
+            em.ctl = P.ctl;
+            s = apply_xi(P, a, em, &nb);
+            if (s) return s;
+            HIP_TRY(launch_ctl_check(P.ctl, P.part, nb, K + 1, -1.0, 1, P.st));
+            s = read_ctl(P, &c);
+            if (s) return s;
+            c.done = 0;
+        }
+    }
+    if (st_out) {
+        jko_stats& o = *st_out;
+        const bool bytol = tolmode && c.done && !c.nonfinite;
+        o.iters = bytol ? c.stop_iter : K;
+        o.absorptions = c.absorptions;
+        o.stop_reason = bytol ? JKO_STOP_TOL : JKO_STOP_CAP;
+        o.status = c.nonfinite ? JKO_ERR_NONFINITE : JKO_OK;
+        o.marginal_l1 = c.err;
+        o.mass = c.mass;
+        o.max_abs_log_a = c.maxloga;
+        o.max_abs_log_b = c.maxlogb;
+    }
+    if (c.nonfinite) return fail(JKO_ERR_NONFINITE, "non-finite value in the marginal monitor");
+    return JKO_OK;
+}
+
+jko_status common_checks(const jko_grid* grid, Geo* g) {
+    if (!geo_of(grid, g)) return fail(JKO_ERR_INVALID, "grid: ndim must be 1..3 and 1 <= n[k] <= %d", kMaxN);
+    return JKO_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+
+extern "C" {
+
+int32_t jko_version(void) { return 1; }
+
+const char* jko_last_error(void) { return g_err.c_str(); }
+
+const char* jko_status_string(int32_t s) {
+    switch (s) {
+        case JKO_OK: return "ok";
+        case JKO_ERR_INVALID: return "invalid argument";
+        case JKO_ERR_WORKSPACE: return "workspace missing or too small";
+        case JKO_ERR_HIP: return "HIP runtime error";
+        case JKO_ERR_NONFINITE: return "non-finite value";
+        case JKO_ERR_INFEASIBLE: return "capacity cannot hold the mass";
+        default: return "unknown status";
+    }
+}
+
+size_t jko_workspace_bytes(const jko_grid* grid, const jko_params* params, int32_t op, int32_t n) {
+    Geo g;
+    if (!geo_of(grid, &g)) return 0;
+    if (op < OP_GIBBS || op > OP_BACKWARD) return 0;
+    int64_t extra = n;
+    if (op == OP_BACKWARD && params && n <= 0) extra = params->max_iters;
+    return layout_of(g, op, extra).total;
+}
+
+jko_status jko_gibbs_apply(const jko_grid* grid, double gamma, int32_t precision, const float* x, float* y,
+                           void* ws, size_t ws_bytes, void* stream) {
+    g_err.clear();
+    Geo g;
+    jko_status s = common_checks(grid, &g);
+    if (s) return s;
+    if (!(gamma > 0.0) || !isfinite(gamma)) return fail(JKO_ERR_INVALID, "gamma must be finite and > 0");
+    if (precision != JKO_FP32 && precision != JKO_SPLIT_BF16) return fail(JKO_ERR_INVALID, "unknown precision");
+    if (!x || !y) return fail(JKO_ERR_INVALID, "x and y must be non-NULL");
+    if (x == y) return fail(JKO_ERR_INVALID, "x and y may not alias");
+    Plan P;
+    s = carve(&P, g, OP_GIBBS, 0, ws, ws_bytes, precision, static_cast<hipStream_t>(stream));
+    if (s) return s;
+    s = build_factors(P, gamma);
+    if (s) return s;
+    EpiArgs e{};
+    e.kind = EpiKind::STORE;
+    e.y = y;
+    return apply_xi(P, x, e, nullptr);
+}
+
+jko_status jko_step(const jko_grid* grid, const jko_energy* energy, const jko_params* params, const float* p_in,
+                    float* p_out, jko_stats* stats, void* ws, size_t ws_bytes, void* stream) {
+    g_err.clear();
+    Geo g;
+    jko_status s = common_checks(grid, &g);
+    if (s) return s;
+    if ((s = check_params(params)) || (s = check_energy(energy))) return s;
+    if (!p_in || !p_out) return fail(JKO_ERR_INVALID, "p_in and p_out must be non-NULL");
+    if (p_in == p_out) return fail(JKO_ERR_INVALID, "p_in and p_out may not alias");
+    Plan P;
+    s = carve(&P, g, OP_STEP, 0, ws, ws_bytes, params->precision, static_cast<hipStream_t>(stream));
+    if (s) return s;
+    if ((s = readback_init())) return s;
+    const double sigma = params->tau / params->gamma;
+    if ((s = build_factors(P, params->gamma))) return s;
+    if ((s = prepare_energy(P, energy, sigma))) return s;
+    if ((s = input_check(P, energy, p_in))) return s;
+    const ProxArgs px = prox_args(P, energy, sigma);
+    return run_step(P, params, px, p_in, p_out, stats != nullptr, false, stats);
+}
+
+jko_status jko_flow(const jko_grid* grid, const jko_energy* energy, const jko_params* params, int32_t n_steps,
+                    const float* p0, float* pT, float* checkpoints, jko_stats* stats, void* ws, size_t ws_bytes,
+                    void* stream) {
+    g_err.clear();
+    Geo g;
+    jko_status s = common_checks(grid, &g);
+    if (s) return s;
+    if ((s = check_params(params)) || (s = check_energy(energy))) return s;
+    if (n_steps < 1) return fail(JKO_ERR_INVALID, "n_steps must be >= 1");
+    if (!p0 || !pT) return fail(JKO_ERR_INVALID, "p0 and pT must be non-NULL");
+    if (p0 == pT) return fail(JKO_ERR_INVALID, "p0 and pT may not alias");
+    Plan P;
+    s = carve(&P, g, OP_FLOW, n_steps, ws, ws_bytes, params->precision, static_cast<hipStream_t>(stream));
+    if (s) return s;
+    if ((s = readback_init())) return s;
+    const double sigma = params->tau / params->gamma;
+    if ((s = build_factors(P, params->gamma))) return s;
+    if ((s = prepare_energy(P, energy, sigma))) return s;
+    if ((s = input_check(P, energy, p0))) return s;
+    const ProxArgs px = prox_args(P, energy, sigma);
+    const float* q = p0;
+    jko_status worst = JKO_OK;
+    for (int t = 0; t < n_steps; ++t) {
+        if (checkpoints) HIP_TRY(launch_copy(checkpoints + (int64_t)t * g.N, q, g.N, P.st));
+        float* out = (t == n_steps - 1) ? pT : P.F((t % 2 == 0) ? F_P0 : F_P1);
+        s = run_step(P, params, px, q, out, stats != nullptr, false, stats ? &stats[t] : nullptr);
+        if (s == JKO_ERR_NONFINITE) {
+            worst = s;
+        } else if (s) {
+            return s;
+        }
+        q = out;
+    }
+    if (worst) return fail(worst, "non-finite value in the marginal monitor");
+    return JKO_OK;
+}
+
+jko_status jko_time_iteration(const jko_grid* grid, const jko_energy* energy, const jko_params* params,
+                              const float* p_in, int32_t reps, double* ms_per_launch, void* ws,
+                              size_t ws_bytes, void* stream) {
+    g_err.clear();
+    Geo g;
+    jko_status s = common_checks(grid, &g);
+    if (s) return s;
+    if ((s = check_params(params)) || (s = check_energy(energy))) return s;
+    if (!p_in || !ms_per_launch || reps < 1) return fail(JKO_ERR_INVALID, "bad timing arguments");
+    Plan P;
+    s = carve(&P, g, OP_STEP, 0, ws, ws_bytes, params->precision, static_cast<hipStream_t>(stream));
+    if (s) return s;
+    const double sigma = params->tau / params->gamma;
+    if ((s = build_factors(P, params->gamma))) return s;
+    if ((s = prepare_energy(P, energy, sigma))) return s;
+    const ProxArgs px = prox_args(P, energy, sigma);
+    HIP_TRY(launch_fill(P.F(F_A), 1.f, g.N, P.st));
+    HIP_TRY(launch_fill(P.F(F_B), 1.f, g.N, P.st));
+    HIP_TRY(launch_ctl_reset(P.ctl, P.st));
+    // scratch copy of p: the prox epilogue writes a and p_out
+    float* pscratch = P.F(F_Z2);
+    const std::vector<PassShape> ps = passes_of(g);
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    int slot = 0;
+    for (int app = 0; app < 2; ++app) {
+        for (size_t i = 0; i < ps.size(); ++i, ++slot) {
+            Pass pass = make_pass(ps[i]);
+            pass.K1 = P.K1[ps[i].axis];
+            pass.K1hi = P.K1hi[ps[i].axis];
+            pass.K1lo = P.K1lo[ps[i].axis];
+            const bool last = (i + 1 == ps.size());
+            EpiArgs e{};
+            e.ctl = P.ctl;
+            e.part = P.part;
+            // inputs: a (or b) for the first pass, z1 for later ones; outputs to z1/z2
+            pass.X = (i == 0) ? P.F(app == 0 ? F_A : F_B) : P.F((i % 2 == 1) ? F_Z1 : F_Z2);
+            if (!last) {
+                e.kind = EpiKind::STORE;
+                e.y = P.F(i % 2 == 0 ? F_Z1 : F_Z2);
+            } else if (app == 0) {
+                e.kind = EpiKind::BUPDATE;
+                e.q = p_in;
+                e.b = P.F(F_B);
+            } else {
+                e.kind = EpiKind::PROX;
+                e.a = P.F(F_A);
+                e.p_out = pscratch;
+                e.prox = px;
+            }
+            int nb = 0;
+            HIP_TRY(launch_contract(pass, P.prec, e, &nb, P.st));   // warm-up
+            HIP_TRY(hipEventRecord(e0, P.st));
+            for (int r = 0; r < reps; ++r) HIP_TRY(launch_contract(pass, P.prec, e, &nb, P.st));
+            HIP_TRY(hipEventRecord(e1, P.st));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            ms_per_launch[slot] = (double)ms / reps;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return JKO_OK;
+}
+
+jko_status jko_backward(const jko_grid* grid, const jko_energy* energy, const jko_params* params,
+                        int32_t n_steps, const int32_t* iters_per_step, const float* checkpoints,
+                        const float* dL_dpT, float* dL_dw, float* dL_dp0, void* ws, size_t ws_bytes,
+                        void* stream) {
+    g_err.clear();
+    Geo g;
+    jko_status s = common_checks(grid, &g);
+    if (s) return s;
+    if ((s = check_params(params)) || (s = check_energy(energy))) return s;
+    if (n_steps < 1) return fail(JKO_ERR_INVALID, "n_steps must be >= 1");
+    if (!iters_per_step || !checkpoints || !dL_dpT) return fail(JKO_ERR_INVALID, "missing input");
+    if (dL_dw && energy->kind != JKO_F_CONGESTION)
+        return fail(JKO_ERR_INVALID, "dL/dw exists only for the congestion energy");
+    if (dL_dw && !energy->w) return fail(JKO_ERR_INVALID, "dL/dw needs the potential w");
+    int kmax = 0;
+    for (int t = 0; t < n_steps; ++t) {
+        if (iters_per_step[t] < 1) return fail(JKO_ERR_INVALID, "iters_per_step[%d] < 1", t);
+        kmax = std::max(kmax, iters_per_step[t]);
+    }
+    Plan P;
+    s = carve(&P, g, OP_BACKWARD, kmax, ws, ws_bytes, params->precision, static_cast<hipStream_t>(stream));
+    if (s) return s;
+    if ((s = readback_init())) return s;
+    const double sigma = params->tau / params->gamma;
+    if ((s = build_factors(P, params->gamma))) return s;
+    if ((s = prepare_energy(P, energy, sigma))) return s;
+    const ProxArgs px = prox_args(P, energy, sigma);
+    const int64_t N = g.N;
+    float* pbar = P.F(F_PBAR);    // adjoint of the current step's output
+    float* qbar = P.F(F_QBAR);    // adjoint of the current step's input
+    float* wacc = P.F(F_WACC);
+    HIP_TRY(launch_copy(pbar, dL_dpT, N, P.st));
+    if (dL_dw) HIP_TRY(launch_fill(wacc, 0.f, N, P.st));
+    jko_params fixed = *params;
+    fixed.tol_l1 = 0.0;
+    for (int t = n_steps - 1; t >= 0; --t) {
+        const float* q = checkpoints + (int64_t)t * N;
+        const int K = iters_per_step[t];
+        fixed.max_iters = K;
+        // Recompute the step, keeping t_k and s_k.
+        s = run_step(P, &fixed, px, q, P.F(F_TMP), false, true, nullptr);
+        if (s) return s;
+        HIP_TRY(launch_fill(qbar, 0.f, N, P.st));
+        float* abar = P.F(F_ABAR);
+        float* sbar = P.F(F_SBAR);
+        float* bbar = P.F(F_BBAR);
+        float* tbar = P.F(F_TBAR);
+        for (int k = K; k >= 1; --k) {
+            const float* tk = P.hist(2 * (int64_t)(k - 1));
+            const float* sk = P.hist(2 * (int64_t)(k - 1) + 1);
+            HIP_TRY(launch_adj_prox(sk, (k == K) ? pbar : nullptr, (k == K) ? nullptr : abar, sbar,
+                                    dL_dw ? wacc : nullptr, px, sigma, N, P.st));
+            EpiArgs e{};
+            e.kind = EpiKind::STORE;
+            e.y = bbar;
+            if ((s = apply_xi(P, sbar, e, nullptr))) return s;
+            HIP_TRY(launch_adj_b(tk, q, bbar, tbar, qbar, N, P.st));
+            if (k > 1) {
+                e.y = abar;
+                if ((s = apply_xi(P, tbar, e, nullptr))) return s;
+            }
+        }
+        HIP_TRY(launch_copy(pbar, qbar, N, P.st));
+    }
+    if (dL_dp0) HIP_TRY(launch_copy(dL_dp0, pbar, N, P.st));
+    if (dL_dw) HIP_TRY(launch_copy(dL_dw, wacc, N, P.st));
+    return JKO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,129 @@
+// Internal declarations of libjko: device control block, epilogue records and
+// the host-side launchers of the kernels (each defined in the translation unit
+// that holds its kernels, so no relocatable device code is needed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "jko.h"
+
+namespace jko {
+
+// ---------------------------------------------------------------------------
+// Device control block, one per workspace.  Written only by the single-block
+// control kernels; every iteration kernel reads `done` first and returns when
+// it is set, so that the host can queue iterations ahead of the stop test.
+// ---------------------------------------------------------------------------
+struct Ctl {
+    int32_t done;          // 1 once the stop test passed or a non-finite value was met
+    int32_t stop_iter;     // iterations whose p is returned (valid when done by tolerance)
+    int32_t nonfinite;     // 1 if the monitor saw NaN/inf
+    int32_t absorptions;
+    int32_t absorb_pending;  // 1 when the last check asked for an absorption
+    int32_t pad[3];
+    double err;            // last ||b * xi^T a - q||_1
+    double mass;           // last sum p
+    double maxloga;        // last max |log a| over a > 0
+    double maxlogb;        // last max |log b| over b > 0
+    double aux[4];
+};
+
+// Per-block partial results of the fused epilogues (FP64, one slot per block).
+struct Partials {
+    double* err;
+    double* mass;
+    double* maxloga;
+    double* maxlogb;
+    int32_t cap;           // slots per array
+};
+
+// Energy parameters as the kernels see them (fields precomputed per call).
+struct ProxArgs {
+    int32_t kind;          // jko_energy_kind
+    const float* g;        // congestion: exp(-sigma w) per cell, or NULL for 1
+    const float* kappa;    // congestion capacity field or NULL
+    float kappa_s;         // scalar capacity when kappa == NULL
+    const float* kf;       // porous: log((m-1) k) per cell; entropy: 1/(1 + sigma c) per cell
+    float kf_s;            // scalar value when kf == NULL
+    float m;               // porous exponent
+    int32_t newton;        // porous Newton steps
+};
+
+// ---------------------------------------------------------------------------
+// Contraction problems.  One pass contracts one grid axis with the factor K1
+// (n x n, symmetric):
+//   LAST  axis (contiguous):   Y[r][i]    = sum_k X[r][k]    K1[k][i],  r < R
+//   OUTER axis (strided):      Y[b][i][m] = sum_k K1[i][k] X[b][k][m],  b < B, m < M
+// The result goes to one of the epilogues below.
+// ---------------------------------------------------------------------------
+enum class Form : int { LAST = 0, OUTER = 1 };
+
+struct Pass {
+    Form form;
+    int64_t R;             // LAST: rows
+    int64_t B, M;          // OUTER: batches and inner length
+    int32_t n;             // contracted length (= output length along the axis)
+    const float* K1;       // n x n float32 factor
+    const uint16_t* K1hi;  // bfloat16 split of K1 (split precision only)
+    const uint16_t* K1lo;
+    const float* X;        // input field
+};
+
+enum class EpiKind : int {
+    STORE = 0,      // y = v
+    BUPDATE = 1,    // t = v; [err += |b t - q|]; b = q / t
+    PROX = 2,       // s = v; p = prox(s); a = p / s; [p_out = p]
+    MONITOR = 3,    // t = v; err += |b t - q| (no write)
+};
+
+struct EpiArgs {
+    EpiKind kind;
+    float* y;              // STORE destination
+    const float* q;        // BUPDATE/MONITOR: old density q
+    float* b;              // BUPDATE: scaling b, updated in place; MONITOR: read
+    float* a;              // PROX: scaling a, written
+    float* p_out;          // PROX: density written when write_p
+    float* s_out;          // PROX: optional copy of s (adjoint recomputation)
+    float* t_out;          // BUPDATE: optional copy of t (adjoint recomputation)
+    int32_t check;         // BUPDATE: accumulate err with the old b; PROX: mass + max|log a|
+    int32_t write_p;
+    ProxArgs prox;
+    Partials part;
+    const Ctl* ctl;        // kernels return early when ctl->done
+};
+
+// Launch one contraction pass; returns the number of blocks (partials slots
+// used by the epilogue) through *nblocks.
+hipError_t launch_contract(const Pass& pass, int32_t precision, const EpiArgs& epi,
+                           int* nblocks, hipStream_t stream);
+
+// Upper bound of the blocks launch_contract may use for a pass of this shape.
+int64_t contract_max_blocks(const Pass& pass, int32_t precision);
+
+// ----------------------------------------------------------------- pointwise
+hipError_t launch_build_factor(float* K1, uint16_t* hi, uint16_t* lo, int n, double gamma,
+                               hipStream_t s);
+hipError_t launch_fill(float* x, float v, int64_t n, hipStream_t s);
+hipError_t launch_copy(float* dst, const float* src, int64_t n, hipStream_t s);
+hipError_t launch_prepare_energy(const jko_energy* en, double sigma, int64_t N, float* g,
+                                 float* kf, hipStream_t s);
+hipError_t launch_ctl_reset(Ctl* ctl, hipStream_t s);
+// Sum of the per-block err partials -> ctl->err; stop / non-finite decision.
+hipError_t launch_ctl_check(Ctl* ctl, Partials part, int nparts, int iter, double tol,
+                            int check_mass, hipStream_t s);
+// FP64 sums of p_in, of kappa (or kappa_s * N) and non-finite / negative
+// detection of p_in; results to out[0..3] (device doubles).
+hipError_t launch_input_check(const float* p_in, const float* kappa, float kappa_s, int64_t N,
+                              int congestion, double* part, int part_cap, double* out,
+                              hipStream_t s);
+
+// ------------------------------------------------------------------ adjoint
+hipError_t launch_adj_prox(const float* s, const float* pbar_ext, const float* abar,
+                           float* sbar, float* wbar, const ProxArgs& px, double sigma,
+                           int64_t N, hipStream_t st);
+hipError_t launch_adj_b(const float* t, const float* q, const float* bbar, float* tbar,
+                        float* qbar, int64_t N, hipStream_t st);
+hipError_t launch_axpy_inplace(float* y, const float* x, int64_t N, hipStream_t st);
+
+}  // namespace jko

@@ -1,0 +1,136 @@
+"""C ABI checks that need no GPU: the library loads, exports every function the
+header declares, sizes workspaces, and rejects bad arguments before it makes
+any HIP call."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+import paper_1502_06216_amd as jk
+from paper_1502_06216_amd import _native as nat
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "jko.h")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*(jko_[a-z_]+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return jk.load()
+
+
+def test_header_declares_the_four_calls():
+    names = _declared_functions()
+    for n in ("jko_gibbs_apply", "jko_step", "jko_flow", "jko_backward", "jko_workspace_bytes"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_struct_layouts_match_header():
+    # sizes implied by include/jko.h on x86-64
+    assert ctypes.sizeof(nat.Grid) == 16
+    assert ctypes.sizeof(nat.EnergyC) == 56
+    assert ctypes.sizeof(nat.Params) == 48
+    assert ctypes.sizeof(nat.Stats) == 48
+
+
+def test_version_and_status_strings(lib):
+    assert lib.jko_version() >= 1
+    assert lib.jko_status_string(0) == b"ok"
+    assert b"capacity" in lib.jko_status_string(-5)
+    assert lib.jko_status_string(123) == b"unknown status"
+
+
+def test_workspace_bytes(lib):
+    p = nat.make_params(1e-3, 1e-3, 300)
+    small = jk.workspace_bytes((32, 32), jk.OP_STEP, 0, p)
+    big = jk.workspace_bytes((256, 256), jk.OP_STEP, 0, p)
+    assert 0 < small < big
+    assert big >= 6 * 256 * 256 * 4
+    flow = jk.workspace_bytes((256, 256), jk.OP_FLOW, 20, p)
+    assert flow > big
+    bwd = jk.workspace_bytes((64, 64), jk.OP_BACKWARD, 300, p)
+    assert bwd >= 2 * 300 * 64 * 64 * 4
+    assert jk.workspace_bytes((2000,), jk.OP_STEP, 0, p) == 0       # n > 1024
+    assert jk.workspace_bytes((4, 4, 4, 4)[:3], 7, 0, p) == 0       # bad op
+
+
+def _call_step(lib, grid, energy, params, p_in=1, p_out=2, ws=16, nbytes=1 << 30):
+    return lib.jko_step(ctypes.byref(grid), ctypes.byref(energy) if energy else None,
+                        ctypes.byref(params) if params else None, ctypes.c_void_p(p_in),
+                        ctypes.c_void_p(p_out), None, ctypes.c_void_p(ws), nbytes, None)
+
+
+def test_argument_errors_before_any_launch(lib):
+    """Validation happens on the host before any HIP call, so these run without
+    a GPU (the pointers are never dereferenced)."""
+    en = jk.EnergySpec(kind="congestion", kappa_scalar=1.0).to_c((8, 8))
+    prm = nat.make_params(1e-3, 1e-3, 10)
+    g = nat.make_grid((8, 8))
+    bad = nat.make_grid((8, 8))
+    bad.ndim = 4
+    assert _call_step(lib, bad, en, prm) == jk.JKO_ERR_INVALID
+    assert b"ndim" in lib.jko_last_error()
+    big = nat.make_grid((2048, 8))
+    assert _call_step(lib, big, en, prm) == jk.JKO_ERR_INVALID
+    for field, val in (("gamma", 0.0), ("gamma", math.nan), ("tau", -1.0), ("max_iters", 0),
+                       ("check_every", 0), ("precision", 7)):
+        p2 = nat.make_params(1e-3, 1e-3, 10)
+        setattr(p2, field, val)
+        assert _call_step(lib, g, en, p2) == jk.JKO_ERR_INVALID, field
+    assert _call_step(lib, g, None, prm) == jk.JKO_ERR_INVALID
+    assert _call_step(lib, g, en, None) == jk.JKO_ERR_INVALID
+    assert _call_step(lib, g, en, prm, p_in=0) == jk.JKO_ERR_INVALID
+    assert _call_step(lib, g, en, prm, p_in=5, p_out=5) == jk.JKO_ERR_INVALID
+    e2 = jk.EnergySpec(kind="porous", m=1.0).to_c((8, 8))
+    assert _call_step(lib, g, e2, prm) == jk.JKO_ERR_INVALID
+    e3 = jk.EnergySpec(kind="congestion", kappa_scalar=-1.0).to_c((8, 8))
+    assert _call_step(lib, g, e3, prm) == jk.JKO_ERR_INVALID
+    e4 = nat.EnergyC()
+    e4.kind = 9
+    assert _call_step(lib, g, e4, prm) == jk.JKO_ERR_INVALID
+    # workspace too small / missing
+    assert _call_step(lib, g, en, prm, ws=0) == jk.JKO_ERR_WORKSPACE
+    assert _call_step(lib, g, en, prm, nbytes=100) == jk.JKO_ERR_WORKSPACE
+    assert b"needed" in lib.jko_last_error()
+
+
+def test_gibbs_and_flow_and_backward_argument_errors(lib):
+    g = nat.make_grid((8, 8))
+    assert lib.jko_gibbs_apply(ctypes.byref(g), -1.0, 0, ctypes.c_void_p(1), ctypes.c_void_p(2),
+                               ctypes.c_void_p(16), 1 << 20, None) == jk.JKO_ERR_INVALID
+    assert lib.jko_gibbs_apply(ctypes.byref(g), 1e-3, 0, ctypes.c_void_p(1), ctypes.c_void_p(1),
+                               ctypes.c_void_p(16), 1 << 20, None) == jk.JKO_ERR_INVALID
+    en = jk.EnergySpec(kind="congestion", kappa_scalar=1.0).to_c((8, 8))
+    prm = nat.make_params(1e-3, 1e-3, 10)
+    assert lib.jko_flow(ctypes.byref(g), ctypes.byref(en), ctypes.byref(prm), 0, ctypes.c_void_p(1),
+                        ctypes.c_void_p(2), None, None, ctypes.c_void_p(16), 1 << 30, None) == jk.JKO_ERR_INVALID
+    iters = (ctypes.c_int32 * 2)(10, 0)
+    assert lib.jko_backward(ctypes.byref(g), ctypes.byref(en), ctypes.byref(prm), 2, iters, ctypes.c_void_p(1),
+                            ctypes.c_void_p(2), None, ctypes.c_void_p(3), ctypes.c_void_p(16), 1 << 30,
+                            None) == jk.JKO_ERR_INVALID
+    ent = jk.EnergySpec(kind="entropy").to_c((8, 8))
+    iters = (ctypes.c_int32 * 1)(10)
+    # dL/dw only for congestion
+    assert lib.jko_backward(ctypes.byref(g), ctypes.byref(ent), ctypes.byref(prm), 1, iters, ctypes.c_void_p(1),
+                            ctypes.c_void_p(2), ctypes.c_void_p(4), None, ctypes.c_void_p(16), 1 << 30,
+                            None) == jk.JKO_ERR_INVALID
+
+
+def test_binding_refuses_cpu_tensors():
+    import torch
+    x = torch.zeros(8, 8)
+    with pytest.raises(TypeError):
+        jk.gibbs_apply(x, 1e-3)

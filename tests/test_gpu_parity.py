@@ -1,0 +1,250 @@
+"""HIP path vs the FP64 oracle, element by element, through the C ABI.
+
+Tolerances (relative L1 on densities): 1e-5 for FP32 contractions, 1e-4 for
+split-BF16; Gibbs products alone: 1e-6 / 2e-5 (rel-L1).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_1502_06216_amd as jk
+from workloads import make_workload, small_case, gaussian_bumps
+
+from _util import banner, dev, energies, f32, host64, rel_l1
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-5, "split_bf16": 1e-4}
+GIBBS_TOL = {"fp32": 1e-6, "split_bf16": 2e-5}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    jk.load()
+
+
+# ------------------------------------------------------------- Gibbs products
+
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("shape,gamma", [((37,), 4e-3), ((50, 70), 2e-3), ((64, 64), 1e-3),
+                                         ((20, 24, 36), 5e-3), ((33, 17, 40), 1e-2), ((256, 256), 2e-4),
+                                         ((130, 6), 3e-2), ((1, 96), 1e-3), ((96, 1), 1e-3)])
+def test_gibbs_apply_matches_oracle(shape, gamma, precision):
+    banner(f"gibbs {shape} gamma={gamma} {precision}")
+    rng = np.random.default_rng(11)
+    x = rng.uniform(0.0, 1.0, size=shape) * np.exp(rng.normal(0, 2, size=shape))
+    y = jk.gibbs_apply(dev(x), gamma, precision)
+    ref = O.gibbs_apply(f32(x).astype(np.float64), gamma)
+    assert rel_l1(host64(y), ref) <= GIBBS_TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+def test_gibbs_apply_structured_inputs(precision):
+    """Bumps with exact zeros and tiny tails."""
+    shape = (96, 80)
+    x = gaussian_bumps(shape, [(0.3, 0.4), (0.7, 0.6)], 0.05, [0.5, 0.5])
+    x[x < 1e-30] = 0.0
+    x[10:20, :] = 0.0
+    y = jk.gibbs_apply(dev(x), 1e-3, precision)
+    ref = O.gibbs_apply(f32(x).astype(np.float64), 1e-3)
+    assert rel_l1(host64(y), ref) <= GIBBS_TOL[precision]
+    assert (host64(y) >= 0).all()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+def test_gibbs_apply_128cube_sampled(precision):
+    """Full-size 3D grid: sampled outputs against the plain sum over all cells."""
+    shape = (128, 128, 128)
+    gamma = 5e-4
+    banner(f"gibbs 128^3 sampled {precision}")
+    rng = np.random.default_rng(3)
+    x = rng.uniform(0.0, 1.0, size=shape).astype(np.float32).astype(np.float64)
+    y = host64(jk.gibbs_apply(dev(x), gamma, precision)).ravel()
+    idx = rng.choice(x.size, size=48, replace=False)
+    ref = O.gibbs_rows(shape, gamma, idx, x)
+    assert rel_l1(y[idx], ref) <= GIBBS_TOL[precision]
+
+
+def test_gibbs_apply_deterministic():
+    x = dev(np.random.default_rng(0).uniform(size=(130, 70)))
+    y1 = jk.gibbs_apply(x, 2e-3)
+    y2 = jk.gibbs_apply(x, 2e-3)
+    assert torch.equal(y1, y2)
+
+
+# ------------------------------------------------------------- whole flows
+
+def _flow_parity(wl, precision, n_steps, iters, tol=None):
+    g_en, o_en = energies(wl)
+    p0 = f32(wl.p0).astype(np.float64)
+    pT, stats, ck = jk.flow(dev(wl.p0), g_en, wl.gamma, wl.tau, n_steps, max_iters=iters,
+                            precision=precision, checkpoints=True)
+    ck = host64(ck)
+    q = p0
+    errs = []
+    for t in range(n_steps):
+        # the device checkpoints are the inputs of each step
+        if t > 0:
+            errs.append(rel_l1(ck[t], q))
+        q, st = O.jko_step(q, o_en, wl.gamma, wl.tau, iters)
+        assert stats[t]["iters"] == iters
+        assert stats[t]["marginal_l1"] == pytest.approx(st["marginal_l1"], rel=0.05, abs=1e-7)
+    errs.append(rel_l1(host64(pT), q))
+    return errs, stats, host64(pT), q
+
+
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("projected", [True, False])
+def test_crowd32_flow_matches_oracle(precision, projected):
+    """32x32 crowd motion, 10 JKO steps x 300 iterations (paper Listing 1)."""
+    banner(f"crowd32 projected={projected} {precision}")
+    wl = make_workload("crowd32", projected=projected)
+    errs, stats, p, ref = _flow_parity(wl, precision, wl.n_steps, wl.max_iters)
+    assert max(errs) <= TOL[precision], errs
+    assert (p <= np.float32(wl.kappa_scalar)).all()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("shape", [(45, 70), (20, 24, 36), (100,)])
+def test_ragged_congestion_matches_oracle(shape, precision):
+    banner(f"ragged congestion {shape} {precision}")
+    wl = small_case(shape, "congestion", seed=2)
+    errs, stats, p, ref = _flow_parity(wl, precision, 2, 60)
+    assert max(errs) <= TOL[precision], errs
+    assert (p <= f32(wl.kappa_field()) + 0).all()
+
+
+@pytest.mark.parametrize("kind", ["entropy", "porous", "zero"])
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+def test_other_energies_match_oracle(kind, precision):
+    banner(f"energy {kind} {precision}")
+    wl = small_case((48, 40), kind, seed=4)
+    if kind == "porous":
+        wl.density_scale = float(np.prod(wl.shape))   # Newton regime k s^{m-1} >> 1
+    errs, stats, p, ref = _flow_parity(wl, precision, 2, 40)
+    assert max(errs) <= TOL[precision], errs
+
+
+def test_porous512_literal_and_scaled_one_step():
+    for name in ("porous512", "porous512_scaled"):
+        banner(name)
+        wl = make_workload(name)
+        g_en, o_en = energies(wl)
+        p, st = jk.step(dev(wl.p0), g_en, wl.gamma, wl.tau, max_iters=20)
+        ref, ost = O.jko_step(f32(wl.p0).astype(np.float64), o_en, wl.gamma, wl.tau, 20)
+        assert rel_l1(host64(p), ref) <= TOL["fp32"]
+
+
+def test_tolerance_mode_stops_like_the_oracle():
+    wl = make_workload("crowd32", projected=True)
+    g_en, o_en = energies(wl)
+    tol, ce = 1e-6, 10
+    p, st = jk.step(dev(wl.p0), g_en, wl.gamma, wl.tau, max_iters=3000, tol=tol, check_every=ce)
+    ref, ost = O.jko_step(f32(wl.p0).astype(np.float64), o_en, wl.gamma, wl.tau, 3000, tol=tol,
+                          check_every=ce)
+    assert st["stop"] == "tol" and ost["stop"] == "tol"
+    assert st["iters"] % ce == 0
+    assert abs(st["iters"] - ost["iters"]) <= ce
+    assert st["marginal_l1"] <= tol
+    ref_same, _ = O.jko_step(f32(wl.p0).astype(np.float64), o_en, wl.gamma, wl.tau, st["iters"])
+    assert rel_l1(host64(p), ref_same) <= TOL["fp32"]
+
+
+def test_mass_and_capacity_invariants():
+    wl = make_workload("crowd32", projected=False)
+    g_en, _ = energies(wl)
+    q = dev(wl.p0)
+    for _ in range(3):
+        p, st = jk.step(q, g_en, wl.gamma, wl.tau, max_iters=300)
+        ph = host64(p)
+        assert ph.min() >= 0.0
+        assert (ph <= np.float32(wl.kappa_scalar)).all()
+        assert abs(ph.sum() - host64(q).sum()) <= st["marginal_l1"] + 1e-6
+        assert st["mass"] == pytest.approx(ph.sum(), rel=1e-6)
+        q = p
+
+
+def test_errors_are_reported():
+    wl = make_workload("crowd32", projected=True)
+    g_en, _ = energies(wl)
+    g_en.kappa_scalar = 0.5 / 1024          # capacity holds half the mass
+    with pytest.raises(jk.JKOError) as e:
+        jk.step(dev(wl.p0), g_en, wl.gamma, wl.tau, max_iters=10)
+    assert e.value.status == jk.JKO_ERR_INFEASIBLE
+    g_en, _ = energies(wl)
+    p = dev(wl.p0)
+    p[3, 4] = float("nan")
+    with pytest.raises(jk.JKOError) as e:
+        jk.step(p, g_en, wl.gamma, wl.tau, max_iters=10)
+    assert e.value.status == jk.JKO_ERR_NONFINITE
+
+
+# ------------------------------------------------------------- closed forms
+
+def _moments(p, x):
+    m = (p * x).sum() / p.sum()
+    return m, (p * (x - m) ** 2).sum() / p.sum()
+
+
+def test_heat_flow_gaussian_on_gpu():
+    """Entropy energy on a 256x256 product Gaussian: each axis follows the
+    closed-form variance recursion of the heat flow."""
+    n, gamma, tau, S0 = 256, 5e-4, 2e-3, 2e-3
+    x = (np.arange(n) + 0.5) / n
+    g1 = np.exp(-(x - 0.5) ** 2 / (2 * S0))
+    p = np.outer(g1, g1)
+    p /= p.sum()
+    S = _moments(f32(p).astype(np.float64).sum(1), x)[1]
+    q = dev(p)
+    en = jk.EnergySpec(kind="entropy")
+    for _ in range(3):
+        q, st = jk.step(q, en, gamma, tau, max_iters=3000, tol=1e-7, check_every=20)
+        u = ((gamma + 2 * S) + math.sqrt((gamma + 2 * S) ** 2 + 8 * tau * S)) / 2
+        S = (u + tau) / 2
+        ph = host64(q)
+        assert _moments(ph.sum(1), x)[1] == pytest.approx(S, rel=2e-4)
+        assert _moments(ph.sum(0), x)[1] == pytest.approx(S, rel=2e-4)
+
+
+def test_ornstein_uhlenbeck_on_gpu():
+    n, gamma, tau, lam, c = 512, 2e-4, 2e-3, 1.0, 0.7
+    x = (np.arange(n) + 0.5) / n
+    p = np.exp(-(x - 0.4) ** 2 / (2 * 2e-3))
+    p /= p.sum()
+    mu, S = _moments(f32(p).astype(np.float64), x)
+    en = jk.EnergySpec(kind="congestion", w=dev(lam * (x - c) ** 2))
+    q = dev(p)
+    for _ in range(4):
+        q, st = jk.step(q, en, gamma, tau, max_iters=3)
+        mu = (mu + tau * lam * c) / (1 + tau * lam)
+        S = S / (1 + tau * lam) ** 2 + gamma / (2 * (1 + tau * lam))
+        m_, v_ = _moments(host64(q), x)
+        assert m_ == pytest.approx(mu, rel=1e-5)
+        assert v_ == pytest.approx(S, rel=1e-4)
+
+
+# ------------------------------------------------------------- full sizes
+
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+def test_crowd256_one_step_full_size(precision):
+    """The 256x256 crowd workload at its full size, one step of 300 iterations."""
+    banner(f"crowd256 full {precision}")
+    wl = make_workload("crowd256_fixed")
+    g_en, o_en = energies(wl)
+    p, st = jk.step(dev(wl.p0), g_en, wl.gamma, wl.tau, max_iters=300, precision=precision)
+    ref, ost = O.jko_step(f32(wl.p0).astype(np.float64), o_en, wl.gamma, wl.tau, 300)
+    assert rel_l1(host64(p), ref) <= TOL[precision]
+    assert st["marginal_l1"] == pytest.approx(ost["marginal_l1"], rel=0.05)
+
+
+def test_crowd128c_few_iterations_full_size():
+    banner("crowd128c full, 8 iterations")
+    wl = make_workload("crowd128c")
+    g_en, o_en = energies(wl)
+    p, st = jk.step(dev(wl.p0), g_en, wl.gamma, wl.tau, max_iters=8)
+    ref, _ = O.jko_step(f32(wl.p0).astype(np.float64), o_en, wl.gamma, wl.tau, 8)
+    assert rel_l1(host64(p), ref) <= TOL["fp32"]
