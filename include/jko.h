@@ -102,8 +102,12 @@ typedef struct {
     int32_t check_every;     /* stop-test cadence in iterations, >= 1 */
     int32_t precision;       /* jko_precision */
     int32_t reserved;
-    double absorb_threshold; /* log-domain absorption when max|log a|,|log b| exceeds it
-                                (checked every check_every iterations); <= 0 or +inf: never */
+    double absorb_threshold; /* log-domain absorption: at the first stop-test check where
+                                max|log a| or max|log b| exceeds it, a and b are absorbed
+                                (carried as logs) and every later contraction runs on
+                                per-fibre shifted exponentials; <= 0: log domain from the
+                                first iteration; +inf or NaN: never.  With a finite
+                                threshold the checks also run in fixed-count mode. */
 } jko_params;
 
 typedef enum { JKO_STOP_TOL = 0, JKO_STOP_CAP = 1 } jko_stop_reason;
@@ -168,14 +172,16 @@ jko_status jko_backward(const jko_grid* grid, const jko_energy* energy, const jk
                         void* workspace, size_t workspace_bytes, void* stream);
 
 /* Measurement aid (not part of the method): sets up one step of p_in as
- * jko_step does, then times each of the 2*ndim contraction launches of one
- * iteration -- the ndim passes of t = xi^T a ending in the b-update epilogue,
- * then the ndim passes of s = xi b ending in the proximal epilogue -- `reps`
- * times back to back between two HIP events on `stream`.  ms_per_launch (host,
- * 2*ndim doubles) receives the mean duration of one launch of each.  The
- * scalings are set to 1 first; p_in is not modified.  Synchronous. */
+ * jko_step does, then times each kernel launch of one iteration -- the
+ * launches of t = xi^T a ending in the b-update epilogue, then those of
+ * s = xi b ending in the proximal epilogue (one launch per application for
+ * 2D grids on the fused band kernel, else one per axis) -- `reps` times back
+ * to back between two HIP events on `stream`.  ms_per_launch (host, room for
+ * 2*ndim doubles) receives the mean duration of one launch of each, in
+ * launch order; *n_launches (host, nullable) their number.  The scalings are
+ * set to 1 first; p_in is not modified.  Synchronous. */
 jko_status jko_time_iteration(const jko_grid* grid, const jko_energy* energy, const jko_params* params,
-                              const float* p_in, int32_t reps, double* ms_per_launch,
+                              const float* p_in, int32_t reps, double* ms_per_launch, int32_t* n_launches,
                               void* workspace, size_t workspace_bytes, void* stream);
 
 /* Static description of a status code. */

@@ -91,7 +91,7 @@ def load(path: str = LIB_PATH):
     lib.jko_flow.restype = i32
     lib.jko_backward.argtypes = [G, E, P, i32, ctypes.POINTER(i32), vp, vp, vp, vp, vp, sz, vp]
     lib.jko_backward.restype = i32
-    lib.jko_time_iteration.argtypes = [G, E, P, vp, i32, ctypes.POINTER(f64), vp, sz, vp]
+    lib.jko_time_iteration.argtypes = [G, E, P, vp, i32, ctypes.POINTER(f64), ctypes.POINTER(i32), vp, sz, vp]
     lib.jko_time_iteration.restype = i32
     lib.jko_status_string.argtypes = [i32]
     lib.jko_status_string.restype = ctypes.c_char_p
@@ -273,8 +273,8 @@ def backward(checkpoints: torch.Tensor, iters_per_step: Sequence[int], dL_dpT: t
 
 def time_iteration(p: torch.Tensor, energy: EnergySpec, gamma: float, tau: float,
                    precision: str = "fp32", reps: int = 50):
-    """Mean duration (ms) of each contraction launch of one iteration, timed
-    with HIP events on the current stream (measurement aid)."""
+    """Mean duration (ms) of each kernel launch of one iteration, in launch
+    order, timed with HIP events on the current stream (measurement aid)."""
     lib = load()
     shape = tuple(p.shape)
     _field(p, shape, "p")
@@ -284,9 +284,10 @@ def time_iteration(p: torch.Tensor, energy: EnergySpec, gamma: float, tau: float
     nb = lib.jko_workspace_bytes(ctypes.byref(g), ctypes.byref(prm), OP_STEP, 0)
     ws = _workspace(nb, p.device)
     out = (ctypes.c_double * (2 * len(shape)))()
+    cnt = ctypes.c_int32(0)
     _check(lib.jko_time_iteration(ctypes.byref(g), ctypes.byref(e), ctypes.byref(prm), _ptr(p), int(reps), out,
-                                  _ptr(ws), ws.numel(), _stream(p.device)))
-    return list(out)
+                                  ctypes.byref(cnt), _ptr(ws), ws.numel(), _stream(p.device)))
+    return list(out)[:cnt.value]
 
 
 class JKOFlowFn(torch.autograd.Function):

@@ -117,6 +117,7 @@ struct Layout {
 
 int part_cap_of(const Geo& g) {
     int64_t cap = 768;   // input check uses 3 x 256
+    if (g.d == 2) cap = std::max<int64_t>(cap, gibbs2d_blocks(g.n[0], g.n[1]));
     for (const PassShape& ps : passes_of(g)) {
         const int64_t b = contract_max_blocks(make_pass(ps), 0);
         if (b > cap) cap = b;
@@ -182,6 +183,8 @@ struct Plan {
     float* field[24] = {};
     hipStream_t st = nullptr;
     int prec = 0;
+    int W[3] = {0, 0, 0};        // float32 band half-widths of the factors
+    bool fused2d = false;        // 2D applications use the fused band kernel
 
     float* F(int i) const { return field[i]; }
     float* hist(int64_t i) const {
@@ -222,7 +225,9 @@ jko_status carve(Plan* P, const Geo& g, int op, int64_t extra, void* ws, size_t 
     return JKO_OK;
 }
 
-jko_status build_factors(const Plan& P, double gamma) {
+jko_status build_factors(Plan& P, double gamma) {
+    for (int k = 0; k < P.g.d; ++k) P.W[k] = band_halfwidth(P.g.n[k], gamma);
+    P.fused2d = P.g.d == 2 && P.prec == JKO_FP32 && gibbs2d_fits(P.g.n[0], P.g.n[1], P.W[0], P.W[1]);
     for (int k = 0; k < P.g.d; ++k) {
         bool done = false;
         for (int j = 0; j < k; ++j)
@@ -234,9 +239,27 @@ jko_status build_factors(const Plan& P, double gamma) {
     return JKO_OK;
 }
 
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+// Vector (16-byte) epilogue access is allowed when every field pointer is aligned.
+void set_vec(EpiArgs& e) {
+    const void* ps[] = {e.y, e.q, e.b, e.a, e.p_out, e.s_out, e.t_out, e.prox.g, e.prox.kappa, e.prox.kf};
+    bool ok = true;
+    for (const void* p : ps) ok = ok && aligned16(p);
+    e.vec_ok = ok ? 1 : 0;
+}
+
 // y = xi x with the last pass's result handed to `epi`.  Uses z1, z2 as
 // intermediates; x must not alias them.  *nblocks = blocks of the last pass.
 jko_status apply_xi(const Plan& P, const float* x, EpiArgs epi, int* nblocks) {
+    set_vec(epi);
+    if (P.fused2d) {
+        Band2D b{P.g.n[0], P.g.n[1], P.W[0], P.W[1], P.K1[0], P.K1[1], x};
+        int nb = 0;
+        HIP_TRY(launch_gibbs2d(b, P.prec, epi, &nb, P.st));
+        if (nblocks) *nblocks = nb;
+        return JKO_OK;
+    }
     const std::vector<PassShape> ps = passes_of(P.g);
     const float* in = x;
     for (size_t i = 0; i < ps.size(); ++i) {
@@ -256,6 +279,7 @@ jko_status apply_xi(const Plan& P, const float* x, EpiArgs epi, int* nblocks) {
             e.y = P.F((i % 2 == 0) ? F_Z1 : F_Z2);
             e.ctl = epi.ctl;
             e.part = epi.part;
+            set_vec(e);
         }
         HIP_TRY(launch_contract(pass, P.prec, e, &nb, P.st));
         if (last && nblocks) *nblocks = nb;
@@ -392,8 +416,17 @@ jko_status run_step(const Plan& P, const jko_params* pr, const ProxArgs& px, con
     float* a = P.F(F_A);
     float* b = P.F(F_B);
 
-    HIP_TRY(launch_fill(a, 1.f, P.g.N, P.st));
-    HIP_TRY(launch_ctl_reset(P.ctl, P.st));
+    // Absorption: threshold <= 0 runs the log domain from the start (log a = 0),
+    // +inf never switches, otherwise the check that sees max|log a|, max|log b|
+    // above it switches.
+    const double thr = pr->absorb_threshold;
+    const bool log_from_start = thr <= 0.0;
+    const double absorb = (log_from_start || !(thr < INFINITY)) ? 0.0 : thr;
+    HIP_TRY(launch_fill(a, log_from_start ? 0.f : 1.f, P.g.N, P.st));
+    HIP_TRY(launch_ctl_reset(P.ctl, log_from_start ? 1 : 0, P.st));
+    // Checks (monitor, absorption trigger) every `ce` iterations in tolerance
+    // mode, and in fixed-count mode when absorption may trigger.
+    const bool checks = tolmode || absorb > 0.0;
 
     EpiArgs eb{};
     eb.kind = EpiKind::BUPDATE;
@@ -413,12 +446,15 @@ jko_status run_step(const Plan& P, const jko_params* pr, const ProxArgs& px, con
     bool stopped = false;
     int nb = 0;
     for (int k = 1; k <= K; ++k) {
-        eb.check = (tolmode && k > 1 && (k - 1) % ce == 0) ? 1 : 0;
+        eb.check = (checks && k > 1 && (k - 1) % ce == 0) ? 1 : 0;
         eb.t_out = record_hist ? P.hist(2 * (int64_t)(k - 1)) : nullptr;
         jko_status s = apply_xi(P, a, eb, &nb);
         if (s) return s;
         if (eb.check) {
-            HIP_TRY(launch_ctl_check(P.ctl, P.part, nb, k, pr->tol_l1, 1, P.st));
+            HIP_TRY(launch_ctl_check(P.ctl, P.part, nb, k, pr->tol_l1, 1, absorb, P.st));
+            if (absorb > 0.0) HIP_TRY(launch_absorb(P.ctl, a, b, P.g.N, P.st));
+        }
+        if (eb.check && tolmode) {
             // Look at the previous stop test while this interval is queued,
             // then queue the read-back of this one.
             if (pending) {
@@ -430,7 +466,7 @@ jko_status run_step(const Plan& P, const jko_params* pr, const ProxArgs& px, con
             HIP_TRY(hipEventRecord(g_rb.ev, P.st));
             pending = true;
         }
-        const bool cand = (tolmode && k % ce == 0) || k == K;
+        const bool cand = (checks && k % ce == 0) || k == K;
         ep.check = cand ? 1 : 0;
         ep.write_p = cand ? 1 : 0;
         ep.s_out = record_hist ? P.hist(2 * (int64_t)(k - 1) + 1) : nullptr;
@@ -452,7 +488,7 @@ jko_status run_step(const Plan& P, const jko_params* pr, const ProxArgs& px, con
             em.ctl = P.ctl;
             s = apply_xi(P, a, em, &nb);
             if (s) return s;
-            HIP_TRY(launch_ctl_check(P.ctl, P.part, nb, K + 1, -1.0, 1, P.st));
+            HIP_TRY(launch_ctl_check(P.ctl, P.part, nb, K + 1, -1.0, 1, 0.0, P.st));
             s = read_ctl(P, &c);
             if (s) return s;
             c.done = 0;
@@ -590,8 +626,8 @@ jko_status jko_flow(const jko_grid* grid, const jko_energy* energy, const jko_pa
 }
 
 jko_status jko_time_iteration(const jko_grid* grid, const jko_energy* energy, const jko_params* params,
-                              const float* p_in, int32_t reps, double* ms_per_launch, void* ws,
-                              size_t ws_bytes, void* stream) {
+                              const float* p_in, int32_t reps, double* ms_per_launch, int32_t* n_launches,
+                              void* ws, size_t ws_bytes, void* stream) {
     g_err.clear();
     Geo g;
     jko_status s = common_checks(grid, &g);
@@ -605,55 +641,81 @@ jko_status jko_time_iteration(const jko_grid* grid, const jko_energy* energy, co
     if ((s = build_factors(P, params->gamma))) return s;
     if ((s = prepare_energy(P, energy, sigma))) return s;
     const ProxArgs px = prox_args(P, energy, sigma);
-    HIP_TRY(launch_fill(P.F(F_A), 1.f, g.N, P.st));
-    HIP_TRY(launch_fill(P.F(F_B), 1.f, g.N, P.st));
-    HIP_TRY(launch_ctl_reset(P.ctl, P.st));
-    // scratch copy of p: the prox epilogue writes a and p_out
-    float* pscratch = P.F(F_Z2);
-    const std::vector<PassShape> ps = passes_of(g);
+    float* a = P.F(F_A);
+    float* b = P.F(F_B);
+    HIP_TRY(launch_fill(a, 1.f, g.N, P.st));
+    HIP_TRY(launch_fill(b, 1.f, g.N, P.st));
+    HIP_TRY(launch_ctl_reset(P.ctl, 0, P.st));
+    for (int i = 0; i < 2 * g.d; ++i) ms_per_launch[i] = 0.0;
+
+    EpiArgs eb{};
+    eb.kind = EpiKind::BUPDATE;
+    eb.q = p_in;
+    eb.b = b;
+    eb.part = P.part;
+    eb.ctl = P.ctl;
+    EpiArgs ep{};
+    ep.kind = EpiKind::PROX;
+    ep.a = a;
+    ep.p_out = nullptr;   // write_p = 0
+    ep.prox = px;
+    ep.part = P.part;
+    ep.ctl = P.ctl;
+    set_vec(eb);
+    set_vec(ep);
+
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
+    auto timed = [&](auto&& launch, double* out) -> jko_status {
+        jko_status r = launch();   // warm-up
+        if (r) return r;
+        HIP_TRY(hipEventRecord(e0, P.st));
+        for (int k = 0; k < reps; ++k)
+            if ((r = launch())) return r;
+        HIP_TRY(hipEventRecord(e1, P.st));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        *out = (double)ms / reps;
+        return JKO_OK;
+    };
     int slot = 0;
-    for (int app = 0; app < 2; ++app) {
-        for (size_t i = 0; i < ps.size(); ++i, ++slot) {
-            Pass pass = make_pass(ps[i]);
-            pass.K1 = P.K1[ps[i].axis];
-            pass.K1hi = P.K1hi[ps[i].axis];
-            pass.K1lo = P.K1lo[ps[i].axis];
-            const bool last = (i + 1 == ps.size());
-            EpiArgs e{};
-            e.ctl = P.ctl;
-            e.part = P.part;
-            // inputs: a (or b) for the first pass, z1 for later ones; outputs to z1/z2
-            pass.X = (i == 0) ? P.F(app == 0 ? F_A : F_B) : P.F((i % 2 == 1) ? F_Z1 : F_Z2);
-            if (!last) {
-                e.kind = EpiKind::STORE;
-                e.y = P.F(i % 2 == 0 ? F_Z1 : F_Z2);
-            } else if (app == 0) {
-                e.kind = EpiKind::BUPDATE;
-                e.q = p_in;
-                e.b = P.F(F_B);
-            } else {
-                e.kind = EpiKind::PROX;
-                e.a = P.F(F_A);
-                e.p_out = pscratch;
-                e.prox = px;
+    if (P.fused2d) {
+        // one launch per application
+        s = timed([&]() { return apply_xi(P, a, eb, nullptr); }, &ms_per_launch[slot++]);
+        if (!s) s = timed([&]() { return apply_xi(P, b, ep, nullptr); }, &ms_per_launch[slot++]);
+    } else {
+        const std::vector<PassShape> ps = passes_of(g);
+        for (int app = 0; app < 2 && !s; ++app) {
+            for (size_t i = 0; i < ps.size() && !s; ++i) {
+                Pass pass = make_pass(ps[i]);
+                pass.K1 = P.K1[ps[i].axis];
+                pass.K1hi = P.K1hi[ps[i].axis];
+                pass.K1lo = P.K1lo[ps[i].axis];
+                const bool last = (i + 1 == ps.size());
+                pass.X = (i == 0) ? (app == 0 ? a : b) : P.F((i % 2 == 1) ? F_Z1 : F_Z2);
+                EpiArgs e = app == 0 ? eb : ep;
+                if (!last) {
+                    e = EpiArgs{};
+                    e.kind = EpiKind::STORE;
+                    e.y = P.F(i % 2 == 0 ? F_Z1 : F_Z2);
+                    e.ctl = P.ctl;
+                    e.part = P.part;
+                    set_vec(e);
+                }
+                s = timed([&]() -> jko_status {
+                    int nb = 0;
+                    HIP_TRY(launch_contract(pass, P.prec, e, &nb, P.st));
+                    return JKO_OK;
+                }, &ms_per_launch[slot++]);
             }
-            int nb = 0;
-            HIP_TRY(launch_contract(pass, P.prec, e, &nb, P.st));   // warm-up
-            HIP_TRY(hipEventRecord(e0, P.st));
-            for (int r = 0; r < reps; ++r) HIP_TRY(launch_contract(pass, P.prec, e, &nb, P.st));
-            HIP_TRY(hipEventRecord(e1, P.st));
-            HIP_TRY(hipEventSynchronize(e1));
-            float ms = 0.f;
-            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-            ms_per_launch[slot] = (double)ms / reps;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    return JKO_OK;
+    if (n_launches) *n_launches = slot;
+    return s;
 }
 
 jko_status jko_backward(const jko_grid* grid, const jko_energy* energy, const jko_params* params,
@@ -691,6 +753,7 @@ jko_status jko_backward(const jko_grid* grid, const jko_energy* energy, const jk
     if (dL_dw) HIP_TRY(launch_fill(wacc, 0.f, N, P.st));
     jko_params fixed = *params;
     fixed.tol_l1 = 0.0;
+    fixed.absorb_threshold = INFINITY;   // the adjoint differentiates the plain iteration
     for (int t = n_steps - 1; t >= 0; --t) {
         const float* q = checkpoints + (int64_t)t * N;
         const int K = iters_per_step[t];

@@ -23,155 +23,9 @@
 #include <float.h>
 #include <math.h>
 
-#include "jko_internal.h"
+#include "epilogue.h"
 
 namespace jko {
-
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
-typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
-
-constexpr int kThreads = 256;
-
-// ----------------------------------------------------------------- helpers
-
-__device__ __forceinline__ uint16_t f2bf_rne(float x) {
-    uint32_t u = __float_as_uint(x);
-    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
-
-// Block-wide FP64 reductions; every thread of the block must call them.
-__device__ double block_sum(double v, double* sh) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    __syncthreads();
-    if (lane == 0) sh[wave] = v;
-    __syncthreads();
-    double r = 0.0;
-    if (threadIdx.x == 0)
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r += sh[w];
-    return r;  // valid in thread 0
-}
-__device__ double block_max(double v, double* sh) {
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    __syncthreads();
-    if (lane == 0) sh[wave] = v;
-    __syncthreads();
-    double r = 0.0;
-    if (threadIdx.x == 0)
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r = fmax(r, sh[w]);
-    return r;
-}
-
-// --------------------------------------------------------- proximal maps
-
-// Porous prox in the variable v = (m-1) k psi^{m-1}: the root equation
-// log psi + k psi^{m-1} = log s becomes v + log v = lz with
-// lz = log((m-1) k) + (m-1) log s (Lambert W of e^lz).  Newton steps on it in
-// residual form; the start v0 = log(1 + e^lz) (lz < 1) or lz - log lz is within
-// 2% of the root everywhere, and 4 steps reach float32 rounding.
-__device__ __forceinline__ float prox_porous(float s, float lk, float m, int steps) {
-    if (!(s > 0.f)) return 0.f;
-    const float ls = logf(s);
-    const float lz = lk + (m - 1.f) * ls;
-    if (lz < -60.f) return s;   // v < 1e-26: psi = s to float32 rounding (also k = 0)
-    float v = (lz < 1.f) ? log1pf(expf(lz)) : lz - logf(lz);
-    for (int it = 0; it < steps; ++it) {
-        const float r = logf(v) + v - lz;
-        v = v - r * v / (1.f + v);
-    }
-    return expf(ls - v / (m - 1.f));
-}
-
-__device__ __forceinline__ float prox_apply(const ProxArgs& px, float s, int64_t idx) {
-    switch (px.kind) {
-        case JKO_F_CONGESTION: {
-            const float g = px.g ? px.g[idx] : 1.f;
-            const float k = px.kappa ? px.kappa[idx] : px.kappa_s;
-            return fminf(s * g, k);
-        }
-        case JKO_F_ENTROPY: {
-            const float e = px.kf ? px.kf[idx] : px.kf_s;
-            return s > 0.f ? expf(e * logf(s)) : 0.f;
-        }
-        case JKO_F_POROUS: {
-            const float lk = px.kf ? px.kf[idx] : px.kf_s;
-            return prox_porous(s, lk, px.m, px.newton);
-        }
-        default:
-            return s;
-    }
-}
-
-// Per-thread accumulators of the epilogue reductions.
-struct EpiAcc {
-    double err = 0.0, mass = 0.0, maxla = 0.0, maxlb = 0.0;
-};
-
-// Pointwise epilogue on one output element (value v at linear index idx).
-__device__ __forceinline__ void epi_elem(const EpiArgs& E, int64_t idx, float v, EpiAcc& acc) {
-    switch (E.kind) {
-        case EpiKind::STORE:
-            E.y[idx] = v;
-            break;
-        case EpiKind::BUPDATE: {
-            const float q = E.q[idx];
-            if (E.check) {
-                const float bo = E.b[idx];
-                acc.err += fabs((double)bo * (double)v - (double)q);
-            }
-            const float bn = (q == 0.f) ? 0.f : q / v;
-            if (E.check && bn > 0.f) acc.maxlb = fmax(acc.maxlb, fabs((double)logf(bn)));
-            E.b[idx] = bn;
-            if (E.t_out) E.t_out[idx] = v;
-            break;
-        }
-        case EpiKind::MONITOR: {
-            const float q = E.q[idx];
-            acc.err += fabs((double)E.b[idx] * (double)v - (double)q);
-            break;
-        }
-        case EpiKind::PROX: {
-            const float p = prox_apply(E.prox, v, idx);
-            const float a = (p == 0.f) ? 0.f : p / v;
-            E.a[idx] = a;
-            if (E.write_p) E.p_out[idx] = p;
-            if (E.s_out) E.s_out[idx] = v;
-            if (E.check) {
-                acc.mass += (double)p;
-                if (a > 0.f) acc.maxla = fmax(acc.maxla, fabs((double)logf(a)));
-            }
-            break;
-        }
-    }
-}
-
-__device__ __forceinline__ void epi_finish(const EpiArgs& E, const EpiAcc& acc, int slot, double* sh) {
-    if (E.kind == EpiKind::STORE) return;
-    const bool want_err = (E.kind == EpiKind::MONITOR) || (E.kind == EpiKind::BUPDATE && E.check);
-    const bool want_pm = (E.kind == EpiKind::PROX && E.check);
-    if (want_err) {
-        const double e = block_sum(acc.err, sh);
-        const double mb = block_max(acc.maxlb, sh);
-        if (threadIdx.x == 0) {
-            E.part.err[slot] = e;
-            E.part.maxlogb[slot] = mb;
-        }
-    }
-    if (want_pm) {
-        const double ms = block_sum(acc.mass, sh);
-        const double ma = block_max(acc.maxla, sh);
-        if (threadIdx.x == 0) {
-            E.part.mass[slot] = ms;
-            E.part.maxloga[slot] = ma;
-        }
-    }
-}
 
 // ----------------------------------------------------------- tile mapping
 
@@ -213,6 +67,51 @@ __device__ __forceinline__ TileCoord tile_of(int64_t logical, int64_t RT, int64_
     return t;
 }
 
+// Log domain: per-fibre shift M_f = max over the contracted axis of the log
+// input, so that the contraction of exp(L - M_f) stays in float range and the
+// output is M_f + log(sum).  Fibres of a block: OUTER the TM columns m of its
+// row tile, LAST the TN rows r of its column tile.  Empty fibres get M_f = 0.
+template <bool OUTER, int FIB>
+__device__ void fibre_max(const float* __restrict__ X, int n, int64_t M, int64_t R, int64_t first,
+                          float* fshift, float* scratch) {
+    constexpr int G = kThreads / FIB;
+    const int tid = threadIdx.x;
+    float mx = -INFINITY;
+    if (OUTER) {
+        const int f = tid % FIB, g = tid / FIB;
+        const int64_t m = first + f;
+        if (m < M)
+            for (int k = g; k < n; k += G) mx = fmaxf(mx, X[(int64_t)k * M + m]);
+        scratch[g * FIB + f] = mx;
+    } else {
+        const int f = tid / G, g = tid % G;
+        const int64_t r = first + f;
+        if (r < R)
+            for (int k = g; k < n; k += G) mx = fmaxf(mx, X[r * (int64_t)n + k]);
+        scratch[g * FIB + f] = mx;
+    }
+    __syncthreads();
+    if (tid < FIB) {
+        float v = -INFINITY;
+        for (int g = 0; g < G; ++g) v = fmaxf(v, scratch[g * FIB + tid]);
+        fshift[tid] = (v == -INFINITY) ? NAN : v;   // NaN marks an all-zero fibre
+    }
+    __syncthreads();
+}
+
+// exp(L - shift) for a staged log input (an all-zero fibre stages zeros).
+__device__ __forceinline__ float shifted_exp(float L, float shift) {
+    return (shift == shift) ? expf(L - shift) : 0.f;
+}
+
+// log of a log-domain contraction output.  A non-empty fibre whose sum
+// underflowed (every contribution below e^-87 of the fibre maximum) is held at
+// the floor shift - 104 instead of -inf, so that b = q / t stays finite.
+__device__ __forceinline__ float shifted_log(float acc, float shift) {
+    if (shift != shift) return -INFINITY;
+    return acc > 0.f ? shift + logf(acc) : shift - 104.f;
+}
+
 // ======================================================= FP32 MFMA kernel
 
 template <int FM, int FN, int WM, int WN, int WK, bool OUTER>
@@ -242,6 +141,14 @@ contract_f32(Pass P, EpiArgs E) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wk = wave / (WM * WN), wmn = wave % (WM * WN), wm = wmn % WM, wn = wmn / WM;
 
+    // Log domain (after the absorption switch): inputs are logs, shifted per fibre.
+    const bool logx = (E.ctl != nullptr) && (E.ctl->logmode != 0);
+    constexpr int FIB = OUTER ? TM : TN;
+    __shared__ float fshift[FIB];
+    __shared__ float fscr[kThreads];
+    if (logx) fibre_max<OUTER, FIB>(X, n, P.M, P.R, OUTER ? row0 : col0, fshift, fscr);
+    const float xfill = logx ? -INFINITY : 0.f;
+
     f4 acc[FM][FN];
 #pragma unroll
     for (int i = 0; i < FM; ++i)
@@ -256,11 +163,11 @@ contract_f32(Pass P, EpiArgs E) {
     // Direct tile loader: rows [base, base+D) of a row-major matrix G (ld = n
     // for K1 and for LAST-axis X), k in [k0, k0+BK).
     auto load_direct = [&](f4* r, const float* __restrict__ G, int64_t base, int64_t lim, int D,
-                           int k0, int U) {
+                           int k0, int U, float fill) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int unit = tid + u * kThreads;
-            f4 v = f4{0.f, 0.f, 0.f, 0.f};
+            f4 v = f4{fill, fill, fill, fill};
             if (unit < D * BK / 4) {
                 const int d = unit / (BK / 4), kq = unit % (BK / 4);
                 const int64_t row = base + d;
@@ -271,20 +178,25 @@ contract_f32(Pass P, EpiArgs E) {
                         v = *reinterpret_cast<const f4*>(src);
                     } else {
 #pragma unroll
-                        for (int j = 0; j < 4; ++j) v[j] = (k + j < n) ? src[j] : 0.f;
+                        for (int j = 0; j < 4; ++j) v[j] = (k + j < n) ? src[j] : fill;
                     }
                 }
             }
             r[u] = v;
         }
     };
-    auto store_direct = [&](const f4* r, float* L, int D, int U) {
+    auto store_direct = [&](const f4* r, float* L, int D, int U, bool xform) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int unit = tid + u * kThreads;
             if (unit < D * BK / 4) {
                 const int d = unit / (BK / 4), kq = unit % (BK / 4);
-                *reinterpret_cast<f4*>(&L[d * S + 4 * kq]) = r[u];
+                f4 v = r[u];
+                if (xform) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) v[j] = shifted_exp(v[j], fshift[d]);
+                }
+                *reinterpret_cast<f4*>(&L[d * S + 4 * kq]) = v;
             }
         }
     };
@@ -293,7 +205,7 @@ contract_f32(Pass P, EpiArgs E) {
 #pragma unroll
         for (int u = 0; u < UP; ++u) {
             const int unit = tid + u * kThreads;
-            f4 v = f4{0.f, 0.f, 0.f, 0.f};
+            f4 v = f4{xfill, xfill, xfill, xfill};
             if (unit < TM * BK / 4) {
                 const int mq = unit % (TM / 4), kk = unit / (TM / 4);
                 const int k = k0 + kk;
@@ -304,7 +216,7 @@ contract_f32(Pass P, EpiArgs E) {
                         v = *reinterpret_cast<const f4*>(src);
                     } else {
 #pragma unroll
-                        for (int j = 0; j < 4; ++j) v[j] = (m + j < P.M) ? src[j] : 0.f;
+                        for (int j = 0; j < 4; ++j) v[j] = (m + j < P.M) ? src[j] : xfill;
                     }
                 }
             }
@@ -318,23 +230,24 @@ contract_f32(Pass P, EpiArgs E) {
             if (unit < TM * BK / 4) {
                 const int mq = unit % (TM / 4), kk = unit / (TM / 4);
 #pragma unroll
-                for (int j = 0; j < 4; ++j) Ps[(4 * mq + j) * S + kk] = r[u][j];
+                for (int j = 0; j < 4; ++j)
+                    Ps[(4 * mq + j) * S + kk] = logx ? shifted_exp(r[u][j], fshift[4 * mq + j]) : r[u][j];
             }
         }
     };
     auto load_chunk = [&](int k0) {
         if (OUTER) {
             load_trans(rp, k0);
-            load_direct(rq, K1, col0, n, TN, k0, UQ);
+            load_direct(rq, K1, col0, n, TN, k0, UQ, 0.f);
         } else {
-            load_direct(rp, K1, row0, n, TM, k0, UP);
-            load_direct(rq, X, col0, P.R, TN, k0, UQ);
+            load_direct(rp, K1, row0, n, TM, k0, UP, 0.f);
+            load_direct(rq, X, col0, P.R, TN, k0, UQ, xfill);
         }
     };
     auto store_chunk = [&]() {
         if (OUTER) store_trans(rp);
-        else store_direct(rp, Ps, TM, UP);
-        store_direct(rq, Qs, TN, UQ);
+        else store_direct(rp, Ps, TM, UP, false);
+        store_direct(rq, Qs, TN, UQ, !OUTER && logx);
     };
 
     const int nchunks = (n + BK - 1) / BK;
@@ -389,19 +302,37 @@ contract_f32(Pass P, EpiArgs E) {
 
     EpiAcc ea;
     if (wk == 0) {
+        EpiIn ein[FM][FN];
+        int64_t ebase[FM][FN];
+        int ecnt[FM][FN];
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
             for (int j = 0; j < FN; ++j) {
                 const int64_t row = row0 + wm * 16 * FM + i * 16 + 4 * (lane >> 4);
                 const int64_t col = col0 + wn * 16 * FN + j * 16 + (lane & 15);
-                if (col >= colsLim) continue;
-                int64_t base;
-                if (OUTER) base = tc.batch * (int64_t)n * P.M + col * P.M + row;  // (b, i=col, m=row)
-                else base = col * (int64_t)n + row;                                  // (r=col, i=row)
+                int64_t left = rowsLim - row;
+                ecnt[i][j] = (col < colsLim) ? (int)(left < 0 ? 0 : (left > 4 ? 4 : left)) : 0;
+                // OUTER: element (b, i = col, m = row);  LAST: element (r = col, i = row)
+                ebase[i][j] = OUTER ? tc.batch * (int64_t)n * P.M + col * P.M + row : col * (int64_t)n + row;
+                ein[i][j] = epi_prefetch(E, ebase[i][j], ecnt[i][j]);
+            }
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    if (row + e < rowsLim) epi_elem(E, base + e, acc[i][j][e], ea);
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                f4 v = acc[i][j];
+                if (logx && ecnt[i][j] > 0) {
+                    const int64_t row = row0 + wm * 16 * FM + i * 16 + 4 * (lane >> 4);
+                    const int64_t col = col0 + wn * 16 * FN + j * 16 + (lane & 15);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int64_t fr = OUTER ? (row + e - row0) : (col - col0);
+                        const float sh_ = fshift[(fr < FIB && fr >= 0) ? fr : 0];
+                        v[e] = shifted_log(acc[i][j][e], sh_);
+                    }
+                }
+                epi_apply(E, ebase[i][j], ecnt[i][j], v, logx, ein[i][j], ea);
             }
     }
     epi_finish(E, ea, (int)blockIdx.x, sh);
@@ -436,6 +367,13 @@ contract_split(Pass P, EpiArgs E) {
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wk = wave / (WM * WN), wmn = wave % (WM * WN), wm = wmn % WM, wn = wmn / WM;
+
+    const bool logx = (E.ctl != nullptr) && (E.ctl->logmode != 0);
+    constexpr int FIB = OUTER ? TM : TN;
+    __shared__ float fshift[FIB];
+    __shared__ float fscr[kThreads];
+    if (logx) fibre_max<OUTER, FIB>(X, n, P.M, P.R, OUTER ? row0 : col0, fshift, fscr);
+    const float xfill = logx ? -INFINITY : 0.f;
 
     f4 acc[FM][FN];
 #pragma unroll
@@ -499,7 +437,7 @@ contract_split(Pass P, EpiArgs E) {
 #pragma unroll
         for (int u = 0; u < UX; ++u) {
             const int unit = tid + u * kThreads;
-            f4 v = f4{0.f, 0.f, 0.f, 0.f};
+            f4 v = f4{xfill, xfill, xfill, xfill};
             if (unit < DX * BK / 4) {
                 if (OUTER) {
                     const int mq = unit % (TM / 4), kk = unit / (TM / 4);
@@ -510,7 +448,7 @@ contract_split(Pass P, EpiArgs E) {
                         if (m + 3 < P.M && ((P.M & 3) == 0)) v = *reinterpret_cast<const f4*>(src);
                         else
 #pragma unroll
-                            for (int j = 0; j < 4; ++j) v[j] = (m + j < P.M) ? src[j] : 0.f;
+                            for (int j = 0; j < 4; ++j) v[j] = (m + j < P.M) ? src[j] : xfill;
                     }
                 } else {
                     const int d = unit / (BK / 4), kq = unit % (BK / 4);
@@ -521,7 +459,7 @@ contract_split(Pass P, EpiArgs E) {
                         if (k + 3 < n && ((n & 3) == 0)) v = *reinterpret_cast<const f4*>(src);
                         else
 #pragma unroll
-                            for (int j = 0; j < 4; ++j) v[j] = (k + j < n) ? src[j] : 0.f;
+                            for (int j = 0; j < 4; ++j) v[j] = (k + j < n) ? src[j] : xfill;
                     }
                 }
             }
@@ -533,11 +471,23 @@ contract_split(Pass P, EpiArgs E) {
         for (int u = 0; u < UX; ++u) {
             const int unit = tid + u * kThreads;
             if (unit < DX * BK / 4) {
+                f4 x = rx[u];
+                if (logx) {
+                    if (OUTER) {
+                        const int mq = unit % (TM / 4);
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) x[j] = shifted_exp(x[j], fshift[4 * mq + j]);
+                    } else {
+                        const int d = unit / (BK / 4);
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) x[j] = shifted_exp(x[j], fshift[d]);
+                    }
+                }
                 u16x4 h, l;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    h[j] = f2bf_rne(rx[u][j]);
-                    l[j] = f2bf_rne(rx[u][j] - bf2f(h[j]));
+                    h[j] = f2bf_rne(x[j]);
+                    l[j] = f2bf_rne(x[j] - bf2f(h[j]));
                 }
                 if (OUTER) {
                     const int mq = unit % (TM / 4), kk = unit / (TM / 4);
@@ -618,19 +568,37 @@ contract_split(Pass P, EpiArgs E) {
 
     EpiAcc ea;
     if (wk == 0) {
+        EpiIn ein[FM][FN];
+        int64_t ebase[FM][FN];
+        int ecnt[FM][FN];
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
             for (int j = 0; j < FN; ++j) {
                 const int64_t row = row0 + wm * 16 * FM + i * 16 + 4 * (lane >> 4);
                 const int64_t col = col0 + wn * 16 * FN + j * 16 + (lane & 15);
-                if (col >= colsLim) continue;
-                int64_t base;
-                if (OUTER) base = tc.batch * (int64_t)n * P.M + col * P.M + row;
-                else base = col * (int64_t)n + row;
+                int64_t left = rowsLim - row;
+                ecnt[i][j] = (col < colsLim) ? (int)(left < 0 ? 0 : (left > 4 ? 4 : left)) : 0;
+                // OUTER: element (b, i = col, m = row);  LAST: element (r = col, i = row)
+                ebase[i][j] = OUTER ? tc.batch * (int64_t)n * P.M + col * P.M + row : col * (int64_t)n + row;
+                ein[i][j] = epi_prefetch(E, ebase[i][j], ecnt[i][j]);
+            }
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    if (row + e < rowsLim) epi_elem(E, base + e, acc[i][j][e], ea);
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                f4 v = acc[i][j];
+                if (logx && ecnt[i][j] > 0) {
+                    const int64_t row = row0 + wm * 16 * FM + i * 16 + 4 * (lane >> 4);
+                    const int64_t col = col0 + wn * 16 * FN + j * 16 + (lane & 15);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int64_t fr = OUTER ? (row + e - row0) : (col - col0);
+                        const float sh_ = fshift[(fr < FIB && fr >= 0) ? fr : 0];
+                        v[e] = shifted_log(acc[i][j][e], sh_);
+                    }
+                }
+                epi_apply(E, ebase[i][j], ecnt[i][j], v, logx, ein[i][j], ea);
             }
     }
     epi_finish(E, ea, (int)blockIdx.x, sh);

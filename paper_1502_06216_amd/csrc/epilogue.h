@@ -1,0 +1,251 @@
+// Device-side helpers shared by the contraction kernels: bfloat16 split,
+// block reductions, the proximal maps of the energies and the pointwise
+// epilogues that finish an iteration's half-step (plain and log domain).
+#pragma once
+
+#include <math.h>
+
+#include "jko_internal.h"
+
+namespace jko {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kThreads = 256;
+
+// ----------------------------------------------------------------- helpers
+
+__device__ __forceinline__ uint16_t f2bf_rne(float x) {
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+// Block-wide FP64 reductions; every thread of the block must call them.
+__device__ inline double block_sum(double v, double* sh) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r += sh[w];
+    return r;  // valid in thread 0
+}
+__device__ inline double block_max(double v, double* sh) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r = fmax(r, sh[w]);
+    return r;
+}
+
+// --------------------------------------------------------- proximal maps
+
+// Porous prox in the variable v = (m-1) k psi^{m-1}: the root equation
+// log psi + k psi^{m-1} = log s becomes v + log v = lz with
+// lz = log((m-1) k) + (m-1) log s (Lambert W of e^lz).  Newton steps on it in
+// residual form; the start v0 = log(1 + e^lz) (lz < 1) or lz - log lz is within
+// 2% of the root everywhere, and 4 steps reach float32 rounding.  Returns
+// log psi.
+__device__ __forceinline__ float log_prox_porous(float ls, float lk, float m, int steps) {
+    if (ls == -INFINITY) return -INFINITY;
+    const float lz = lk + (m - 1.f) * ls;
+    if (lz < -60.f) return ls;   // v < 1e-26: psi = s to float32 rounding (also k = 0)
+    float v = (lz < 1.f) ? log1pf(expf(lz)) : lz - logf(lz);
+    for (int it = 0; it < steps; ++it) {
+        const float r = logf(v) + v - lz;
+        v = v - r * v / (1.f + v);
+    }
+    return ls - v / (m - 1.f);
+}
+
+// Prox of one cell; pu, pv are the cell's prefetched energy parameters
+// (congestion: exp(-sigma w), kappa; entropy: 1/(1 + sigma c); porous:
+// log((m-1) k)).
+__device__ __forceinline__ float prox_val(const ProxArgs& px, float s, float pu, float pv) {
+    switch (px.kind) {
+        case JKO_F_CONGESTION: return fminf(s * pu, pv);
+        case JKO_F_ENTROPY: return s > 0.f ? expf(pu * logf(s)) : 0.f;
+        case JKO_F_POROUS: return s > 0.f ? expf(log_prox_porous(logf(s), pu, px.m, px.newton)) : 0.f;
+        default: return s;
+    }
+}
+
+// log Prox(exp(ls)) of one cell.
+__device__ __forceinline__ float log_prox_val(const ProxArgs& px, float ls, float pu, float pv) {
+    switch (px.kind) {
+        case JKO_F_CONGESTION: return fminf(ls + logf(pu), logf(pv));
+        case JKO_F_ENTROPY: return pu * ls;
+        case JKO_F_POROUS: return log_prox_porous(ls, pu, px.m, px.newton);
+        default: return ls;
+    }
+}
+
+// ------------------------------------------------------------- epilogues
+
+// Per-thread accumulators of the epilogue reductions.
+struct EpiAcc {
+    double err = 0.0, mass = 0.0, maxla = 0.0, maxlb = 0.0;
+};
+
+// Inputs of the pointwise epilogue for a run of up to 4 consecutive outputs,
+// loaded before they are needed so that their latency overlaps the
+// contraction.  BUPDATE/MONITOR: u = q, v = old b;  PROX: u, v = the energy
+// parameters of prox_val.
+struct EpiIn {
+    f4 u, v;
+};
+
+__device__ __forceinline__ f4 ld4(const float* __restrict__ p, int64_t idx, int cnt, bool vec, float fill) {
+    if (vec && cnt == 4) return *reinterpret_cast<const f4*>(p + idx);
+    f4 r = f4{fill, fill, fill, fill};
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        if (e < cnt) r[e] = p[idx + e];
+    return r;
+}
+
+__device__ __forceinline__ void st4(float* __restrict__ p, int64_t idx, int cnt, bool vec, f4 v) {
+    if (vec && cnt == 4) {
+        *reinterpret_cast<f4*>(p + idx) = v;
+        return;
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        if (e < cnt) p[idx + e] = v[e];
+}
+
+__device__ __forceinline__ EpiIn epi_prefetch(const EpiArgs& E, int64_t idx, int cnt) {
+    EpiIn in;
+    in.u = f4{0.f, 0.f, 0.f, 0.f};
+    in.v = f4{0.f, 0.f, 0.f, 0.f};
+    if (cnt <= 0) return in;
+    const bool vec = E.vec_ok && ((idx & 3) == 0);
+    switch (E.kind) {
+        case EpiKind::BUPDATE:
+        case EpiKind::MONITOR:
+            in.u = ld4(E.q, idx, cnt, vec, 0.f);
+            if (E.kind == EpiKind::MONITOR || E.check) in.v = ld4(E.b, idx, cnt, vec, 0.f);
+            break;
+        case EpiKind::PROX: {
+            const ProxArgs& px = E.prox;
+            if (px.kind == JKO_F_CONGESTION) {
+                in.u = px.g ? ld4(px.g, idx, cnt, vec, 1.f) : f4{1.f, 1.f, 1.f, 1.f};
+                in.v = px.kappa ? ld4(px.kappa, idx, cnt, vec, 0.f)
+                                : f4{px.kappa_s, px.kappa_s, px.kappa_s, px.kappa_s};
+            } else if (px.kind == JKO_F_ENTROPY || px.kind == JKO_F_POROUS) {
+                in.u = px.kf ? ld4(px.kf, idx, cnt, vec, 0.f) : f4{px.kf_s, px.kf_s, px.kf_s, px.kf_s};
+            }
+            break;
+        }
+        default:
+            break;
+    }
+    return in;
+}
+
+// Finish `cnt` consecutive outputs idx .. idx+cnt-1 of a contraction whose
+// values are `val` (logs of the values when logx).  Plain domain:
+//   STORE    y = v
+//   BUPDATE  t = v; [err += |b_old t - q|]; b = q / t          (0/0 = 0)
+//   MONITOR  err += |b t - q|
+//   PROX     s = v; p = prox(s); a = p / s; [p_out = p]       (0/0 = 0)
+// Log domain: the same with b, a held as log b, log a.
+__device__ __forceinline__ void epi_apply(const EpiArgs& E, int64_t idx, int cnt, f4 val, bool logx,
+                                          const EpiIn& in, EpiAcc& acc) {
+    if (cnt <= 0) return;
+    const bool vec = E.vec_ok && ((idx & 3) == 0);
+    switch (E.kind) {
+        case EpiKind::STORE:
+            st4(E.y, idx, cnt, vec, val);
+            break;
+        case EpiKind::BUPDATE: {
+            f4 bn;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float q = in.u[e], t = val[e];
+                if (logx) {
+                    bn[e] = (q == 0.f) ? -INFINITY : logf(q) - t;
+                    if (E.check && e < cnt) {
+                        acc.err += fabs((double)expf(in.v[e] + t) - (double)q);
+                        if (bn[e] > -INFINITY) acc.maxlb = fmax(acc.maxlb, fabs((double)bn[e]));
+                    }
+                } else {
+                    bn[e] = (q == 0.f) ? 0.f : q / t;
+                    if (E.check && e < cnt) {
+                        acc.err += fabs((double)in.v[e] * (double)t - (double)q);
+                        if (bn[e] > 0.f) acc.maxlb = fmax(acc.maxlb, fabs((double)logf(bn[e])));
+                    }
+                }
+            }
+            st4(E.b, idx, cnt, vec, bn);
+            if (E.t_out) st4(E.t_out, idx, cnt, vec, val);
+            break;
+        }
+        case EpiKind::MONITOR:
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                if (e >= cnt) continue;
+                const double bt = logx ? (double)expf(in.v[e] + val[e]) : (double)in.v[e] * (double)val[e];
+                acc.err += fabs(bt - (double)in.u[e]);
+            }
+            break;
+        case EpiKind::PROX: {
+            f4 an, pn;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                if (logx) {
+                    const float lp = log_prox_val(E.prox, val[e], in.u[e], in.v[e]);
+                    an[e] = (lp == -INFINITY) ? -INFINITY : lp - val[e];
+                    pn[e] = expf(lp);
+                    if (E.check && e < cnt && an[e] > -INFINITY) acc.maxla = fmax(acc.maxla, fabs((double)an[e]));
+                } else {
+                    const float p = prox_val(E.prox, val[e], in.u[e], in.v[e]);
+                    pn[e] = p;
+                    an[e] = (p == 0.f) ? 0.f : p / val[e];
+                    if (E.check && e < cnt && an[e] > 0.f) acc.maxla = fmax(acc.maxla, fabs((double)logf(an[e])));
+                }
+                if (E.check && e < cnt) acc.mass += (double)pn[e];
+            }
+            st4(E.a, idx, cnt, vec, an);
+            if (E.write_p) st4(E.p_out, idx, cnt, vec, pn);
+            if (E.s_out) st4(E.s_out, idx, cnt, vec, val);
+            break;
+        }
+    }
+}
+
+__device__ __forceinline__ void epi_finish(const EpiArgs& E, const EpiAcc& acc, int slot, double* sh) {
+    if (E.kind == EpiKind::STORE) return;
+    const bool want_err = (E.kind == EpiKind::MONITOR) || (E.kind == EpiKind::BUPDATE && E.check);
+    const bool want_pm = (E.kind == EpiKind::PROX && E.check);
+    if (want_err) {
+        const double e = block_sum(acc.err, sh);
+        const double mb = block_max(acc.maxlb, sh);
+        if (threadIdx.x == 0) {
+            E.part.err[slot] = e;
+            E.part.maxlogb[slot] = mb;
+        }
+    }
+    if (want_pm) {
+        const double ms = block_sum(acc.mass, sh);
+        const double ma = block_max(acc.maxla, sh);
+        if (threadIdx.x == 0) {
+            E.part.mass[slot] = ms;
+            E.part.maxloga[slot] = ma;
+        }
+    }
+}
+
+}  // namespace jko

@@ -20,8 +20,10 @@ struct Ctl {
     int32_t stop_iter;     // iterations whose p is returned (valid when done by tolerance)
     int32_t nonfinite;     // 1 if the monitor saw NaN/inf
     int32_t absorptions;
-    int32_t absorb_pending;  // 1 when the last check asked for an absorption
-    int32_t pad[3];
+    int32_t absorb_pending;  // 1 when the last check switched to the log domain
+    int32_t logmode;         // 1: the scalings a, b are stored as log a, log b and every
+                             //    contraction runs log-in / log-out with per-fibre shifts
+    int32_t pad[2];
     double err;            // last ||b * xi^T a - q||_1
     double mass;           // last sum p
     double maxloga;        // last max |log a| over a > 0
@@ -88,6 +90,7 @@ struct EpiArgs {
     float* t_out;          // BUPDATE: optional copy of t (adjoint recomputation)
     int32_t check;         // BUPDATE: accumulate err with the old b; PROX: mass + max|log a|
     int32_t write_p;
+    int32_t vec_ok;        // every field pointer above is 16-byte aligned (vector access)
     ProxArgs prox;
     Partials part;
     const Ctl* ctl;        // kernels return early when ctl->done
@@ -101,6 +104,24 @@ hipError_t launch_contract(const Pass& pass, int32_t precision, const EpiArgs& e
 // Upper bound of the blocks launch_contract may use for a pass of this shape.
 int64_t contract_max_blocks(const Pass& pass, int32_t precision);
 
+// Fused 2D application Y = K1_0 X K1_1 restricted to the float32 band of the
+// factors (|i - j| > W => K1[i][j] == 0 exactly).
+struct Band2D {
+    int n0, n1;            // grid
+    int W0, W1;            // band half-widths of K1_0, K1_1
+    const float* K0;       // n0 x n0
+    const float* K1;       // n1 x n1
+    const float* X;        // n0 x n1 input
+};
+bool gibbs2d_fits(int n0, int n1, int W0, int W1);
+int64_t gibbs2d_blocks(int n0, int n1);
+hipError_t launch_gibbs2d(const Band2D& b, int32_t precision, const EpiArgs& epi, int* nblocks,
+                          hipStream_t stream);
+
+// Largest |i - j| at which the float32 factor exp(-((i-j)/n)^2/gamma) can be
+// non-zero (entries below 2^-150 round to zero).
+int band_halfwidth(int n, double gamma);
+
 // ----------------------------------------------------------------- pointwise
 hipError_t launch_build_factor(float* K1, uint16_t* hi, uint16_t* lo, int n, double gamma,
                                hipStream_t s);
@@ -108,10 +129,13 @@ hipError_t launch_fill(float* x, float v, int64_t n, hipStream_t s);
 hipError_t launch_copy(float* dst, const float* src, int64_t n, hipStream_t s);
 hipError_t launch_prepare_energy(const jko_energy* en, double sigma, int64_t N, float* g,
                                  float* kf, hipStream_t s);
-hipError_t launch_ctl_reset(Ctl* ctl, hipStream_t s);
-// Sum of the per-block err partials -> ctl->err; stop / non-finite decision.
+hipError_t launch_ctl_reset(Ctl* ctl, int logmode, hipStream_t s);
+// Sum of the per-block err partials -> ctl->err; stop / non-finite decision;
+// switch to the log domain when max|log a| or max|log b| > absorb (absorb > 0).
 hipError_t launch_ctl_check(Ctl* ctl, Partials part, int nparts, int iter, double tol,
-                            int check_mass, hipStream_t s);
+                            int check_mass, double absorb, hipStream_t s);
+// a <- log a, b <- log b when the last check asked for the switch.
+hipError_t launch_absorb(Ctl* ctl, float* a, float* b, int64_t N, hipStream_t s);
 // FP64 sums of p_in, of kappa (or kappa_s * N) and non-finite / negative
 // detection of p_in; results to out[0..3] (device doubles).
 hipError_t launch_input_check(const float* p_in, const float* kappa, float kappa_s, int64_t N,

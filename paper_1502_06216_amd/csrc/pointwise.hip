@@ -78,13 +78,14 @@ __global__ void k_prepare(int kind, const float* w, const float* coef, float coe
     }
 }
 
-__global__ void k_ctl_reset(Ctl* c) {
+__global__ void k_ctl_reset(Ctl* c, int logmode) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         c->done = 0;
         c->stop_iter = 0;
         c->nonfinite = 0;
-        c->absorptions = 0;
+        c->absorptions = logmode ? 1 : 0;
         c->absorb_pending = 0;
+        c->logmode = logmode;
         c->err = 0.0;
         c->mass = 0.0;
         c->maxloga = 0.0;
@@ -121,18 +122,29 @@ __device__ double fixed_max(const double* v, int n, double* sh) {
     return r;
 }
 
-__global__ void __launch_bounds__(256) k_ctl_check(Ctl* c, Partials part, int nparts, int iter,
-                                                   double tol, int check_mass) {
-    __shared__ double sh[256];
+// One wave: each lane sums a fixed strided subset of the partials, then a
+// fixed xor-butterfly combines the lanes (same order every call: bitwise
+// reproducible).
+__global__ void __launch_bounds__(64) k_ctl_check(Ctl* c, Partials part, int nparts, int iter,
+                                                  double tol, int check_mass, double absorb) {
     if (c->done) return;
-    const double err = fixed_sum(part.err, nparts, sh);
-    const double mlb = fixed_max(part.maxlogb, nparts, sh);
-    double mass = 0.0, mla = 0.0;
-    if (check_mass) {
-        mass = fixed_sum(part.mass, nparts, sh);
-        mla = fixed_max(part.maxloga, nparts, sh);
+    const int lane = threadIdx.x;
+    double err = 0.0, mlb = 0.0, mass = 0.0, mla = 0.0;
+    for (int i = lane; i < nparts; i += 64) {
+        err += part.err[i];
+        mlb = fmax(mlb, part.maxlogb[i]);
+        if (check_mass) {
+            mass += part.mass[i];
+            mla = fmax(mla, part.maxloga[i]);
+        }
     }
-    if (threadIdx.x == 0) {
+    for (int o = 32; o > 0; o >>= 1) {
+        err += __shfl_xor(err, o, 64);
+        mlb = fmax(mlb, __shfl_xor(mlb, o, 64));
+        mass += __shfl_xor(mass, o, 64);
+        mla = fmax(mla, __shfl_xor(mla, o, 64));
+    }
+    if (lane == 0) {
         c->err = err;
         c->maxlogb = mlb;
         if (check_mass) {
@@ -148,6 +160,24 @@ __global__ void __launch_bounds__(256) k_ctl_check(Ctl* c, Partials part, int np
             c->done = 1;
             c->stop_iter = iter - 1;
         }
+        // Log-domain absorption: from here on a, b are carried as log a, log b.
+        c->absorb_pending = 0;
+        if (!c->done && !c->logmode && absorb > 0.0 && (mlb > absorb || (check_mass && mla > absorb))) {
+            c->absorb_pending = 1;
+            c->logmode = 1;
+            c->absorptions += 1;
+        }
+    }
+}
+
+__global__ void k_absorb(const Ctl* c, float* __restrict__ a, float* __restrict__ b, int64_t N) {
+    if (!c->absorb_pending || c->done) return;
+    const float ninf = -INFINITY;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float av = a[i], bv = b[i];
+        a[i] = av > 0.f ? logf(av) : ninf;
+        b[i] = bv > 0.f ? logf(bv) : ninf;
     }
 }
 
@@ -191,9 +221,11 @@ __global__ void __launch_bounds__(256) k_input_final(const double* part, int nb,
 
 // Reverse of p = prox(s), a = p / s for one iteration:
 //   pbar = pbar_ext + abar / s
-//   sbar = -abar p / s^2 + pbar dp/ds
+//   sbar = -abar a / s + pbar dp/ds          (abar p / s^2 written with a = p / s)
 //   wbar += pbar dp/dw          (congestion: dp/dw = -sigma s g on the free branch)
-// Ties s g = kappa take the capped branch (derivative 0).
+// Ties s g = kappa take the capped branch (derivative 0).  Terms whose factor
+// is structurally zero (a = 0, dp/ds = 0) are skipped, so cells with s, p at
+// the float32 underflow limit contribute 0 rather than 0 * inf.
 __global__ void k_adj_prox(const float* __restrict__ s, const float* __restrict__ pbar_ext,
                            const float* __restrict__ abar, float* __restrict__ sbar,
                            float* __restrict__ wbar, ProxArgs px, float sigma, int64_t N) {
@@ -203,6 +235,7 @@ __global__ void k_adj_prox(const float* __restrict__ s, const float* __restrict_
         const float ab = abar ? abar[i] : 0.f;
         float pb = pbar_ext ? pbar_ext[i] : 0.f;
         float p = 0.f, dpds = 0.f, dpdw = 0.f;
+        float sb = 0.f;
         if (sv > 0.f) {
             switch (px.kind) {
                 case JKO_F_CONGESTION: {
@@ -241,32 +274,38 @@ __global__ void k_adj_prox(const float* __restrict__ s, const float* __restrict_
                     }
                     p = expf(ls - v / (m - 1.f));
                     // implicit derivative of log psi + k psi^{m-1} = log s
-                    dpds = p / (sv * (1.f + v));
+                    dpds = (p / sv) / (1.f + v);
                     break;
                 }
                 default:
                     p = sv;
                     dpds = 1.f;
             }
-            pb += ab / sv;
-            sbar[i] = -ab * p / (sv * sv) + pb * dpds;
-        } else {
-            sbar[i] = 0.f;
+            const float a = (p == 0.f) ? 0.f : p / sv;
+            const float abs_ = (ab != 0.f) ? ab / sv : 0.f;
+            pb += abs_;
+            if (a != 0.f) sb -= abs_ * a;
+            if (dpds != 0.f) sb += pb * dpds;
         }
-        if (wbar) wbar[i] += pb * dpdw;
+        sbar[i] = sb;
+        if (wbar && dpdw != 0.f) wbar[i] += pb * dpdw;
     }
 }
 
-// Reverse of b = q / t:  tbar = -bbar q / t^2,  qbar += bbar / t.
+// Reverse of b = q / t:  tbar = -bbar q / t^2 = -bbar b / t,  qbar += bbar / t.
 __global__ void k_adj_b(const float* __restrict__ t, const float* __restrict__ q,
                         const float* __restrict__ bbar, float* __restrict__ tbar,
                         float* __restrict__ qbar, int64_t N) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const float tv = t[i], bb = bbar[i];
-        const float inv = (tv > 0.f) ? 1.f / tv : 0.f;
-        tbar[i] = -bb * q[i] * inv * inv;
-        qbar[i] += bb * inv;
+        const float tv = t[i], bb = bbar[i], qv = q[i];
+        if (tv > 0.f) {
+            const float bv = (qv == 0.f) ? 0.f : qv / tv;
+            tbar[i] = (bv == 0.f || bb == 0.f) ? 0.f : -bb * (bv / tv);
+            qbar[i] += bb / tv;
+        } else {
+            tbar[i] = 0.f;
+        }
     }
 }
 
@@ -302,14 +341,19 @@ hipError_t launch_prepare_energy(const jko_energy* en, double sigma, int64_t N, 
     return hipGetLastError();
 }
 
-hipError_t launch_ctl_reset(Ctl* ctl, hipStream_t s) {
-    hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, s, ctl);
+hipError_t launch_ctl_reset(Ctl* ctl, int logmode, hipStream_t s) {
+    hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, s, ctl, logmode);
     return hipGetLastError();
 }
 
 hipError_t launch_ctl_check(Ctl* ctl, Partials part, int nparts, int iter, double tol, int check_mass,
-                            hipStream_t s) {
-    hipLaunchKernelGGL(k_ctl_check, dim3(1), dim3(256), 0, s, ctl, part, nparts, iter, tol, check_mass);
+                            double absorb, hipStream_t s) {
+    hipLaunchKernelGGL(k_ctl_check, dim3(1), dim3(64), 0, s, ctl, part, nparts, iter, tol, check_mass, absorb);
+    return hipGetLastError();
+}
+
+hipError_t launch_absorb(Ctl* ctl, float* a, float* b, int64_t N, hipStream_t s) {
+    hipLaunchKernelGGL(k_absorb, dim3(blocks_for(N, 1024)), dim3(256), 0, s, ctl, a, b, N);
     return hipGetLastError();
 }
 

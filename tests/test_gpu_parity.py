@@ -18,6 +18,8 @@ from _util import banner, dev, energies, f32, host64, rel_l1
 pytestmark = pytest.mark.gpu
 
 TOL = {"fp32": 1e-5, "split_bf16": 1e-4}
+# absolute slack on the reported marginal violation near its rounding floor
+MONITOR_ABS = {"fp32": 2e-7, "split_bf16": 3e-6}
 GIBBS_TOL = {"fp32": 1e-6, "split_bf16": 2e-5}
 
 
@@ -92,7 +94,7 @@ def _flow_parity(wl, precision, n_steps, iters, tol=None):
             errs.append(rel_l1(ck[t], q))
         q, st = O.jko_step(q, o_en, wl.gamma, wl.tau, iters)
         assert stats[t]["iters"] == iters
-        assert stats[t]["marginal_l1"] == pytest.approx(st["marginal_l1"], rel=0.05, abs=1e-7)
+        assert stats[t]["marginal_l1"] == pytest.approx(st["marginal_l1"], rel=0.05, abs=MONITOR_ABS[precision])
     errs.append(rel_l1(host64(pT), q))
     return errs, stats, host64(pT), q
 
@@ -190,24 +192,31 @@ def _moments(p, x):
     return m, (p * (x - m) ** 2).sum() / p.sum()
 
 
-def test_heat_flow_gaussian_on_gpu():
-    """Entropy energy on a 256x256 product Gaussian: each axis follows the
-    closed-form variance recursion of the heat flow."""
-    n, gamma, tau, S0 = 256, 5e-4, 2e-3, 2e-3
+@pytest.mark.parametrize("absorb", [math.inf, 0.0])
+def test_heat_flow_gaussian_on_gpu(absorb):
+    """Entropy energy on a 256x256 product Gaussian (plain scalings, and the log
+    domain from the first iteration): parity with the FP64 oracle at the same
+    iteration count, and each axis's variance against the closed-form heat-flow
+    recursion (within the truncation of the bounded domain, 1e-3)."""
+    n, gamma, tau, S0 = 256, 1e-3, 2e-3, 1e-2
     x = (np.arange(n) + 0.5) / n
     g1 = np.exp(-(x - 0.5) ** 2 / (2 * S0))
     p = np.outer(g1, g1)
     p /= p.sum()
-    S = _moments(f32(p).astype(np.float64).sum(1), x)[1]
+    ref = f32(p).astype(np.float64)
+    S = _moments(ref.sum(1), x)[1]
     q = dev(p)
     en = jk.EnergySpec(kind="entropy")
-    for _ in range(3):
-        q, st = jk.step(q, en, gamma, tau, max_iters=3000, tol=1e-7, check_every=20)
+    oen = O.Energy(kind="entropy")
+    for _ in range(2):
+        q, st = jk.step(q, en, gamma, tau, max_iters=600, absorb_threshold=absorb)
+        ref, _ = O.jko_step(ref, oen, gamma, tau, 600)
         u = ((gamma + 2 * S) + math.sqrt((gamma + 2 * S) ** 2 + 8 * tau * S)) / 2
         S = (u + tau) / 2
         ph = host64(q)
-        assert _moments(ph.sum(1), x)[1] == pytest.approx(S, rel=2e-4)
-        assert _moments(ph.sum(0), x)[1] == pytest.approx(S, rel=2e-4)
+        assert rel_l1(ph, ref) <= TOL["fp32"]
+        assert _moments(ph.sum(1), x)[1] == pytest.approx(S, rel=1e-3)
+        assert _moments(ph.sum(0), x)[1] == pytest.approx(S, rel=1e-3)
 
 
 def test_ornstein_uhlenbeck_on_gpu():
@@ -248,3 +257,118 @@ def test_crowd128c_few_iterations_full_size():
     p, st = jk.step(dev(wl.p0), g_en, wl.gamma, wl.tau, max_iters=8)
     ref, _ = O.jko_step(f32(wl.p0).astype(np.float64), o_en, wl.gamma, wl.tau, 8)
     assert rel_l1(host64(p), ref) <= TOL["fp32"]
+
+
+# ------------------------------------------------------------- log domain
+
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("threshold", [0.0, 50.0])
+def test_log_domain_matches_plain_oracle(threshold, precision):
+    """Absorbing the scalings (from the start, or at the first check above 50)
+    gives the plain iteration's result where that one stays finite."""
+    banner(f"log domain thr={threshold} {precision}")
+    wl = make_workload("crowd32", projected=False)
+    g_en, o_en = energies(wl)
+    p, st = jk.step(dev(wl.p0), g_en, wl.gamma, wl.tau, max_iters=300, check_every=10,
+                    absorb_threshold=threshold, precision=precision)
+    ref, _ = O.jko_step(f32(wl.p0).astype(np.float64), o_en, wl.gamma, wl.tau, 300)
+    assert st["absorptions"] == 1
+    assert rel_l1(host64(p), ref) <= TOL[precision]
+    ph = host64(p)
+    assert (ph <= np.float32(wl.kappa_scalar)).all() and ph.min() >= 0
+
+
+def test_log_domain_survives_where_plain_fp32_overflows():
+    """Small gamma, literal bump mixture far above the capacity: the plain FP32
+    scalings overflow.  The absorbed iteration stays finite and keeps the
+    invariants; its distance to the exact log-sum-exp oracle is printed (the
+    per-fibre shift drops contributions more than e^-87 below a fibre's
+    maximum, so this case carries no tight parity claim)."""
+    banner("log domain stress")
+    wl = small_case((64, 64), "congestion", seed=1, gamma=2e-4, tau=2e-3, n_boxes=3, projected=False,
+                    cap_factor=1.2)
+    g_en, o_en = energies(wl)
+    iters = 60
+    with pytest.raises(jk.JKOError):
+        jk.step(dev(wl.p0), g_en, wl.gamma, wl.tau, max_iters=iters)   # NONFINITE in plain FP32
+    p, st = jk.step(dev(wl.p0), g_en, wl.gamma, wl.tau, max_iters=iters, check_every=5, absorb_threshold=0.0)
+    ph = host64(p)
+    assert np.isfinite(ph).all() and np.isfinite(st["marginal_l1"])
+    assert ph.min() >= 0 and (ph <= f32(wl.kappa_field())).all()
+    ref, ost = O.jko_step_log(f32(wl.p0).astype(np.float64), o_en, wl.gamma, wl.tau, iters)
+    err = rel_l1(ph, ref)
+    print(f"[gpu-test] log-domain stress: rel-L1 vs exact LSE oracle {err:.3e}, "
+          f"marginal {st['marginal_l1']:.3e} (oracle {ost['marginal_l1']:.3e})", flush=True)
+
+
+# ------------------------------------------------------------- adjoint
+
+def _adjoint_case(shape_name, n_steps, iters):
+    if shape_name == "crowd32":
+        wl = make_workload("crowd32", projected=True)
+    else:
+        wl = make_workload("crowd256_fixed")
+    rng = np.random.default_rng(7)
+    N = wl.N
+    ex = wl.extras["exit"]
+    from workloads import gaussian_bumps as gb
+    target = gb(wl.shape, [ex - np.array([0.1, 0.0])], 0.05, [1.0])
+    mask = wl.extras["mask"]
+    target[mask] = 0.0
+    target /= target.sum()
+    return wl, target
+
+
+@pytest.mark.parametrize("name,n_steps,iters", [("crowd32", 3, 50), ("crowd256", 2, 60)])
+def test_adjoint_matches_fp64_autograd(name, n_steps, iters):
+    """dL/dw and dL/dp0 of L = ||p_T - target||^2 from the hand-written adjoint
+    (recompute from per-step checkpoints, reverse sweep) against torch float64
+    autograd through the oracle's unrolled iteration."""
+    from oracle.grad import loss_and_grads
+    banner(f"adjoint {name} {n_steps}x{iters}")
+    wl, target = _adjoint_case(name, n_steps, iters)
+    g_en, o_en = energies(wl)
+    p0 = dev(wl.p0)
+    pT, _, ck = jk.flow(p0, g_en, wl.gamma, wl.tau, n_steps, max_iters=iters, checkpoints=True)
+    dL = 2.0 * (pT - dev(target))
+    gw, gp = jk.backward(ck, [iters] * n_steps, dL.contiguous(), g_en, wl.gamma, wl.tau)
+    kap = wl.kappa_field()
+    loss, rw, rp, _ = loss_and_grads(f32(wl.p0).astype(np.float64), f32(wl.w).astype(np.float64),
+                                     f32(kap).astype(np.float64), wl.gamma, wl.tau, [iters] * n_steps, target)
+    ew = np.linalg.norm(host64(gw) - rw) / np.linalg.norm(rw)
+    ep = np.linalg.norm(host64(gp) - rp) / np.linalg.norm(rp)
+    print(f"[gpu-test] adjoint {name}: rel err dL/dw {ew:.2e}, dL/dp0 {ep:.2e}", flush=True)
+    assert ew <= 1e-3 and ep <= 1e-3
+
+
+def test_autograd_function_and_directional_derivative():
+    """JKOFlowFn.backward equals the library gradient, and <grad, d> matches a
+    central difference of the GPU forward along a random direction d (no
+    capacity, so the flow is smooth in w)."""
+    banner("autograd fn")
+    wl, target = _adjoint_case("crowd32", 2, 40)
+    g_en, _ = energies(wl)
+    g_en.kappa_scalar = math.inf
+    w = dev(wl.w).requires_grad_(True)
+    p0 = dev(wl.p0).requires_grad_(True)
+    kap = torch.full(wl.shape, math.inf, dtype=torch.float32, device="cuda")
+    tgt = dev(target)
+    pT = jk.JKOFlowFn.apply(p0, w, kap, wl.gamma, wl.tau, 2, 40, "fp32")
+    loss = ((pT - tgt) ** 2).sum()
+    loss.backward()
+    d = torch.from_numpy(np.random.default_rng(3).standard_normal(wl.shape).astype(np.float32)).cuda()
+    h = 2e-3
+
+    def L(wv):
+        with torch.no_grad():
+            out = jk.JKOFlowFn.apply(p0.detach(), wv, kap, wl.gamma, wl.tau, 2, 40, "fp32")
+            return float(((out.double() - tgt.double()) ** 2).sum())
+
+    fd = (L(w.detach() + h * d) - L(w.detach() - h * d)) / (2 * h)
+    an = float((w.grad.double() * d.double()).sum())
+    assert an == pytest.approx(fd, rel=1e-2)
+    # the autograd path returns the library's gradient
+    ck = jk.flow(p0.detach(), g_en, wl.gamma, wl.tau, 2, max_iters=40, checkpoints=True)[2]
+    gw, gp = jk.backward(ck, [40, 40], (2.0 * (pT.detach() - tgt)).contiguous(), g_en, wl.gamma, wl.tau)
+    assert torch.allclose(w.grad, gw, rtol=1e-5, atol=1e-12)
+    assert torch.allclose(p0.grad, gp, rtol=1e-5, atol=1e-12)
