@@ -67,38 +67,25 @@ bool geo_of(const jko_grid* g, Geo* out) {
     return true;
 }
 
-// The passes of one application of xi, in order: axis d-1 (contiguous, LAST
-// form) first, then axes d-2 .. 0 (OUTER form).  in/out buffers are chosen by
-// the caller; the last pass writes through the epilogue.
+// The passes of one application of xi, in order: axis d-1 (contiguous) first,
+// then d-2, ..., 0.  Each pass moves its axis to the front of the memory
+// order, so pass p contracts the contiguous axis of pass p-1's output, and
+// after all d passes the field is back in row-major order.
 struct PassShape {
-    Form form;
-    int64_t R, B, M;
+    int64_t R;
     int n;
     int axis;
 };
 
 std::vector<PassShape> passes_of(const Geo& g) {
     std::vector<PassShape> v;
-    const int d = g.d;
-    int64_t outer = 1;
-    for (int k = 0; k < d - 1; ++k) outer *= g.n[k];
-    v.push_back(PassShape{Form::LAST, outer, 1, 1, g.n[d - 1], d - 1});
-    int64_t inner = g.n[d - 1];
-    for (int k = d - 2; k >= 0; --k) {
-        int64_t B = 1;
-        for (int j = 0; j < k; ++j) B *= g.n[j];
-        v.push_back(PassShape{Form::OUTER, 1, B, inner, g.n[k], k});
-        inner *= g.n[k];
-    }
+    for (int k = g.d - 1; k >= 0; --k) v.push_back(PassShape{g.N / g.n[k], g.n[k], k});
     return v;
 }
 
 Pass make_pass(const PassShape& ps) {
     Pass p{};
-    p.form = ps.form;
     p.R = ps.R;
-    p.B = ps.B;
-    p.M = ps.M;
     p.n = ps.n;
     return p;
 }
@@ -267,6 +254,7 @@ jko_status apply_xi(const Plan& P, const float* x, EpiArgs epi, int* nblocks) {
         pass.K1 = P.K1[ps[i].axis];
         pass.K1hi = P.K1hi[ps[i].axis];
         pass.K1lo = P.K1lo[ps[i].axis];
+        pass.W = P.W[ps[i].axis];
         pass.X = in;
         const bool last = (i + 1 == ps.size());
         EpiArgs e;
@@ -693,6 +681,7 @@ jko_status jko_time_iteration(const jko_grid* grid, const jko_energy* energy, co
                 pass.K1 = P.K1[ps[i].axis];
                 pass.K1hi = P.K1hi[ps[i].axis];
                 pass.K1lo = P.K1lo[ps[i].axis];
+                pass.W = P.W[ps[i].axis];
                 const bool last = (i + 1 == ps.size());
                 pass.X = (i == 0) ? (app == 0 ? a : b) : P.F((i % 2 == 1) ? F_Z1 : F_Z2);
                 EpiArgs e = app == 0 ? eb : ep;

@@ -33,19 +33,26 @@ __device__ __forceinline__ int64_t xcd_block() {
     return (bid % 8) * (nb / 8) + bid / 8;
 }
 
-__global__ void __launch_bounds__(kThreads)
+constexpr int kThr = 512;   // 8 waves per block
+
+__global__ void __launch_bounds__(kThr)
 gibbs2d_f32(Band2D B, EpiArgs E) {
     __shared__ __attribute__((aligned(16))) float Xs[kHalo * kS];   // [ib][jb]
     __shared__ __attribute__((aligned(16))) float Kj[kT * kS];      // [j][jb]  = K1_1[j0+j][jb0+jb]
     __shared__ __attribute__((aligned(16))) float Ki[kT * kS];      // [i][ib]  = K1_0[i0+i][ib0+ib]
     __shared__ __attribute__((aligned(16))) float Zs[kT * kS];      // [j][ib]
-    __shared__ float red[3 * 64 * 4];
+    __shared__ float red[7 * 64 * 4];
     __shared__ float sh1[kHalo];     // log domain: row shifts of the halo
     __shared__ float sh2[kT];        // log domain: column shifts of Z
     __shared__ double shd[8];
 
-    if (E.ctl && E.ctl->done) return;
-    const bool logx = (E.ctl != nullptr) && (E.ctl->logmode != 0);
+    // The control flags are read here but acted on only after the halo loads
+    // are in flight, so their latencies overlap.
+    int done = 0, lmode = 0;
+    if (E.ctl) {
+        done = E.ctl->done;
+        lmode = E.ctl->logmode;
+    }
 
     const int n0 = B.n0, n1 = B.n1;
     const int tiles_j = (n1 + kT - 1) / kT;
@@ -62,7 +69,7 @@ gibbs2d_f32(Band2D B, EpiArgs E) {
     const int LIp = (LI + 15) & ~15, LJp = (LJ + 15) & ~15;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const float fill = logx ? -INFINITY : 0.f;
+    const bool vec1 = (n1 & 3) == 0, vec0 = (n0 & 3) == 0;
 
     // Wave 0 finishes the tile: lane (i = lane & 15, j = 4 (lane >> 4) + e).
     // Its epilogue inputs are fetched now, ahead of the contraction.
@@ -72,56 +79,95 @@ gibbs2d_f32(Band2D B, EpiArgs E) {
     const int ocnt = (oi < n0) ? max(0, min(4, n1 - (j0 + koff))) : 0;
     EpiIn ein;
     if (wave == 0) ein = epi_prefetch(E, obase, ocnt);
-    const bool vec1 = (n1 & 3) == 0, vec0 = (n0 & 3) == 0;
 
-    // ---- stage the halo of X and the two factor bands
-    for (int u = tid; u < LIp * (LJp / 4); u += kThreads) {
-        const int r = u / (LJp / 4), c = 4 * (u % (LJp / 4));
-        f4 v = f4{fill, fill, fill, fill};
-        if (r < LI) {
-            const float* src = B.X + (int64_t)(ib0 + r) * n1 + jb0 + c;
-            if (vec1 && c + 3 < LJ) v = *reinterpret_cast<const f4*>(src);
-            else
+    // ---- stage the halo of X and the two factor bands: every load is issued
+    // before the first LDS store
+    constexpr int UXM = kHalo * (kHalo / 4) / kThr;     // max halo units per thread
+    constexpr int UKM = kT * (kHalo / 4) / kThr;        // max factor units per thread
+    const int nux = LIp * (LJp / 4), nkj = kT * (LJp / 4), nki = kT * (LIp / 4);
+    f4 bx[UXM], bj[UKM], bi[UKM];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) v[e] = (c + e < LJ) ? src[e] : fill;
-        }
-        *reinterpret_cast<f4*>(&Xs[r * kS + c]) = v;
-    }
-    for (int u = tid; u < kT * (LJp / 4); u += kThreads) {
-        const int j = u / (LJp / 4), c = 4 * (u % (LJp / 4));
+    for (int u = 0; u < UXM; ++u) {
+        const int unit = tid + u * kThr;
         f4 v = f4{0.f, 0.f, 0.f, 0.f};
-        if (j0 + j < n1) {
-            const float* src = B.K1 + (int64_t)(j0 + j) * n1 + jb0 + c;
-            if (vec1 && c + 3 < LJ) v = *reinterpret_cast<const f4*>(src);
-            else
+        if (unit < nux) {
+            const int r = unit / (LJp / 4), c = 4 * (unit % (LJp / 4));
+            if (r < LI) {
+                const float* src = B.X + (int64_t)(ib0 + r) * n1 + jb0 + c;
+                if (vec1 && c + 3 < LJ) v = *reinterpret_cast<const f4*>(src);
+                else
 #pragma unroll
-                for (int e = 0; e < 4; ++e) v[e] = (c + e < LJ) ? src[e] : 0.f;
+                    for (int e = 0; e < 4; ++e) v[e] = (c + e < LJ) ? src[e] : 0.f;
+            }
         }
-        *reinterpret_cast<f4*>(&Kj[j * kS + c]) = v;
+        bx[u] = v;
     }
-    for (int u = tid; u < kT * (LIp / 4); u += kThreads) {
-        const int i = u / (LIp / 4), c = 4 * (u % (LIp / 4));
+#pragma unroll
+    for (int u = 0; u < UKM; ++u) {
+        const int unit = tid + u * kThr;
         f4 v = f4{0.f, 0.f, 0.f, 0.f};
-        if (i0 + i < n0) {
-            const float* src = B.K0 + (int64_t)(i0 + i) * n0 + ib0 + c;
-            if (vec0 && c + 3 < LI) v = *reinterpret_cast<const f4*>(src);
-            else
+        if (unit < nkj) {
+            const int j = unit / (LJp / 4), c = 4 * (unit % (LJp / 4));
+            if (j0 + j < n1) {
+                const float* src = B.K1 + (int64_t)(j0 + j) * n1 + jb0 + c;
+                if (vec1 && c + 3 < LJ) v = *reinterpret_cast<const f4*>(src);
+                else
 #pragma unroll
-                for (int e = 0; e < 4; ++e) v[e] = (c + e < LI) ? src[e] : 0.f;
+                    for (int e = 0; e < 4; ++e) v[e] = (c + e < LJ) ? src[e] : 0.f;
+            }
         }
-        *reinterpret_cast<f4*>(&Ki[i * kS + c]) = v;
+        bj[u] = v;
+        f4 w = f4{0.f, 0.f, 0.f, 0.f};
+        if (unit < nki) {
+            const int i = unit / (LIp / 4), c = 4 * (unit % (LIp / 4));
+            if (i0 + i < n0) {
+                const float* src = B.K0 + (int64_t)(i0 + i) * n0 + ib0 + c;
+                if (vec0 && c + 3 < LI) w = *reinterpret_cast<const f4*>(src);
+                else
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) w[e] = (c + e < LI) ? src[e] : 0.f;
+            }
+        }
+        bi[u] = w;
     }
+    const bool logx = lmode != 0;
+#pragma unroll
+    for (int u = 0; u < UXM; ++u) {
+        const int unit = tid + u * kThr;
+        if (unit < nux) {
+            const int r = unit / (LJp / 4), c = 4 * (unit % (LJp / 4));
+            f4 v = bx[u];
+            if (logx)   // staged logs: cells outside the halo are exact zeros
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (r >= LI || c + e >= LJ) v[e] = -INFINITY;
+            *reinterpret_cast<f4*>(&Xs[r * kS + c]) = v;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < UKM; ++u) {
+        const int unit = tid + u * kThr;
+        if (unit < nkj) {
+            const int j = unit / (LJp / 4), c = 4 * (unit % (LJp / 4));
+            *reinterpret_cast<f4*>(&Kj[j * kS + c]) = bj[u];
+        }
+        if (unit < nki) {
+            const int i = unit / (LIp / 4), c = 4 * (unit % (LIp / 4));
+            *reinterpret_cast<f4*>(&Ki[i * kS + c]) = bi[u];
+        }
+    }
+    if (done) return;   // the step has stopped: nothing to compute (uniform)
     __syncthreads();
 
     if (logx) {
         // row shifts over the halo, then exponentiate the staged logs
-        for (int r = tid; r < LIp; r += kThreads) {
+        for (int r = tid; r < LIp; r += kThr) {
             float m = -INFINITY;
             for (int c = 0; c < LJ; ++c) m = fmaxf(m, Xs[r * kS + c]);
             sh1[r] = (m == -INFINITY) ? NAN : m;
         }
         __syncthreads();
-        for (int u = tid; u < LIp * LJp; u += kThreads) {
+        for (int u = tid; u < LIp * LJp; u += kThr) {
             const int r = u / LJp, c = u % LJp;
             const float m = sh1[r];
             Xs[r * kS + c] = (m == m) ? expf(Xs[r * kS + c] - m) : 0.f;
@@ -129,16 +175,33 @@ gibbs2d_f32(Band2D B, EpiArgs E) {
         __syncthreads();
     }
 
-    // ---- Z = X K1_1^T over the halo rows: 16-row fragments round-robin over waves
+    // ---- Z = X K1_1^T over the halo rows: wave f owns the 16-row fragment f;
+    // even and odd k-chunks go to two accumulators (independent MFMA chains)
     const int F = LIp / 16;
-    for (int f = wave; f < F; f += 4) {
-        f4 acc = f4{0.f, 0.f, 0.f, 0.f};
-        for (int c0 = 0; c0 < LJp; c0 += 16) {
-            const f4 a = *reinterpret_cast<const f4*>(&Xs[(16 * f + (lane & 15)) * kS + c0 + koff]);
-            const f4 b = *reinterpret_cast<const f4*>(&Kj[(lane & 15) * kS + c0 + koff]);
+    if (wave < F) {
+        const int f = wave;
+        f4 acc0 = f4{0.f, 0.f, 0.f, 0.f}, acc1 = f4{0.f, 0.f, 0.f, 0.f};
+        const float* xr = &Xs[(16 * f + (lane & 15)) * kS + koff];
+        const float* kr = &Kj[(lane & 15) * kS + koff];
+        int c0 = 0;
+        for (; c0 + 16 < LJp; c0 += 32) {
+            const f4 a0 = *reinterpret_cast<const f4*>(xr + c0);
+            const f4 b0 = *reinterpret_cast<const f4*>(kr + c0);
+            const f4 a1 = *reinterpret_cast<const f4*>(xr + c0 + 16);
+            const f4 b1 = *reinterpret_cast<const f4*>(kr + c0 + 16);
 #pragma unroll
-            for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b[s], acc, 0, 0, 0);
+            for (int s = 0; s < 4; ++s) {
+                acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[s], b0[s], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[s], b1[s], acc1, 0, 0, 0);
+            }
         }
+        if (c0 < LJp) {
+            const f4 a0 = *reinterpret_cast<const f4*>(xr + c0);
+            const f4 b0 = *reinterpret_cast<const f4*>(kr + c0);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[s], b0[s], acc0, 0, 0, 0);
+        }
+        f4 acc = acc0 + acc1;
         // acc holds Z[ib = 16f + koff + e][j = lane & 15]
         if (logx) {
 #pragma unroll
@@ -159,7 +222,7 @@ gibbs2d_f32(Band2D B, EpiArgs E) {
             sh2[tid] = (m == -INFINITY) ? NAN : m;
         }
         __syncthreads();
-        for (int u = tid; u < kT * LIp; u += kThreads) {
+        for (int u = tid; u < kT * LIp; u += kThr) {
             const int j = u / LIp, r = u % LIp;
             const float m = sh2[j];
             Zs[j * kS + r] = (m == m && r < LI) ? expf(Zs[j * kS + r] - m) : 0.f;
@@ -167,25 +230,22 @@ gibbs2d_f32(Band2D B, EpiArgs E) {
         __syncthreads();
     }
 
-    // ---- Y^T = Z^T K1_0^T: one 16 x 16 fragment, K split over the waves
+    // ---- Y^T = Z^T K1_0^T: one 16 x 16 fragment, its 16-wide k-chunks spread
+    // over the waves (at most 8 chunks), partial sums combined in a fixed order
     f4 acc = f4{0.f, 0.f, 0.f, 0.f};
-    for (int c0 = 16 * wave; c0 < LIp; c0 += 64) {
+    if (16 * wave < LIp) {
+        const int c0 = 16 * wave;
         const f4 a = *reinterpret_cast<const f4*>(&Zs[(lane & 15) * kS + c0 + koff]);
         const f4 b = *reinterpret_cast<const f4*>(&Ki[(lane & 15) * kS + c0 + koff]);
 #pragma unroll
         for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b[s], acc, 0, 0, 0);
     }
-    if (wave > 0) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) red[((wave - 1) * 64 + lane) * 4 + e] = acc[e];
-    }
+    if (wave > 0) *reinterpret_cast<f4*>(&red[((wave - 1) * 64 + lane) * 4]) = acc;
     __syncthreads();
     EpiAcc ea;
     if (wave == 0) {
 #pragma unroll
-        for (int w = 0; w < 3; ++w)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) acc[e] += red[(w * 64 + lane) * 4 + e];
+        for (int w = 0; w < 7; ++w) acc += *reinterpret_cast<const f4*>(&red[(w * 64 + lane) * 4]);
         // acc holds Y[i = i0 + (lane & 15)][j = j0 + koff + e]
         if (logx) {
 #pragma unroll
@@ -224,7 +284,7 @@ hipError_t launch_gibbs2d(const Band2D& b, int32_t precision, const EpiArgs& epi
     (void)precision;
     const int64_t nb = gibbs2d_blocks(b.n0, b.n1);
     if (nblocks) *nblocks = (int)nb;
-    hipLaunchKernelGGL(gibbs2d_f32, dim3((unsigned)nb), dim3(kThreads), 0, stream, b, epi);
+    hipLaunchKernelGGL(gibbs2d_f32, dim3((unsigned)nb), dim3(kThr), 0, stream, b, epi);
     return hipGetLastError();
 }
 

@@ -53,19 +53,16 @@ struct ProxArgs {
 };
 
 // ---------------------------------------------------------------------------
-// Contraction problems.  One pass contracts one grid axis with the factor K1
-// (n x n, symmetric):
-//   LAST  axis (contiguous):   Y[r][i]    = sum_k X[r][k]    K1[k][i],  r < R
-//   OUTER axis (strided):      Y[b][i][m] = sum_k K1[i][k] X[b][k][m],  b < B, m < M
-// The result goes to one of the epilogues below.
+// Contraction pass: contract the contiguous axis of X (R rows of length n)
+// with the factor K1 (n x n, symmetric) and write the result with that axis
+// first:   Y[i][r] = sum_k K1[i][k] X[r][k].
+// K1[i][k] == 0 exactly for |i - k| > W, so each output tile only runs over
+// its band of k.  The result goes to one of the epilogues below.
 // ---------------------------------------------------------------------------
-enum class Form : int { LAST = 0, OUTER = 1 };
-
 struct Pass {
-    Form form;
-    int64_t R;             // LAST: rows
-    int64_t B, M;          // OUTER: batches and inner length
+    int64_t R;             // rows of X (product of the other axes)
     int32_t n;             // contracted length (= output length along the axis)
+    int32_t W;             // band half-width of K1
     const float* K1;       // n x n float32 factor
     const uint16_t* K1hi;  // bfloat16 split of K1 (split precision only)
     const uint16_t* K1lo;
