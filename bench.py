@@ -41,6 +41,9 @@ def _args():
     ap.add_argument("--no-extra", action="store_true", help="skip the 3D, split and adjoint extras")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--pmc-probe", choices=["crowd256", "crowd128c"], default=None,
+                    help="profiling probe: 50 fixed iterations of one step of the workload, "
+                         "then a 64 MiB device copy of known size (counter calibration)")
     return ap.parse_args()
 
 
@@ -180,8 +183,31 @@ def adjoint_ratio(precision="fp32"):
             "workload": "crowd256_fixed 20 steps x 300 iterations"}
 
 
+def pmc_probe(name, precision):
+    """A short fixed-count step of `name` followed by a plain 64 MiB device
+    copy, for hardware-counter passes (FETCH_SIZE / WRITE_SIZE per dispatch)."""
+    import torch
+    import paper_1502_06216_amd as jk
+    from workloads import make_workload
+    wl = make_workload(name)
+    en = _energy(wl)
+    q = _dev(wl.p0)
+    p, st = jk.step(q, en, wl.gamma, wl.tau, max_iters=50, tol=0.0, precision=precision)
+    torch.cuda.synchronize()
+    src = torch.ones(16 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": name, "iterations": 50, "precision": precision,
+                      "copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4}), flush=True)
+
+
 def main():
     args = _args()
+    if args.pmc_probe:
+        pmc_probe(args.pmc_probe, args.precision)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "a flow would shard by slabs along axis 0, which is not built", file=sys.stderr)

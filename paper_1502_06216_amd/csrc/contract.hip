@@ -27,6 +27,8 @@
 // output is shift + log(sum).
 #include <math.h>
 
+#include <algorithm>
+
 #include "epilogue.h"
 
 namespace jko {
@@ -35,8 +37,8 @@ namespace {
 
 // The hardware hands consecutive blocks to the 8 XCDs in turn; give each XCD
 // a contiguous range of tiles so that tiles sharing an X row strip share an L2.
-__device__ __forceinline__ int64_t xcd_logical_block() {
-    const int64_t nb = gridDim.x, bid = blockIdx.x;
+__device__ __forceinline__ int xcd_logical_block() {
+    const int nb = gridDim.x, bid = blockIdx.x;
     if (nb % 8 != 0) return bid;
     return (bid % 8) * (nb / 8) + bid / 8;
 }
@@ -54,21 +56,23 @@ __device__ __forceinline__ float shifted_log(float acc, float shift) {
     return acc > 0.f ? shift + logf(acc) : shift - 104.f;
 }
 
-template <int TR, int TI, int WR, int WI, bool SPLIT>
+// BK: k per chunk.  STAGES = 2: double-buffered chunks; STAGES = 1: the whole
+// band of a tile fits in one chunk (loaded once, then multiplied).
+template <int TR, int TI, int WR, int WI, bool SPLIT, int BK, int STAGES, int EK>
 __global__ void __launch_bounds__(kThreads)
 contract_rot(Pass P, EpiArgs E) {
     static_assert(WR * WI == 4, "four waves per block");
     constexpr int FM = TR / WR / 16;           // 16-row fragments per wave along r
     constexpr int FN = TI / WI / 16;           // 16-col fragments per wave along i
     static_assert(FM >= 1 && FN >= 1, "tile too small for the wave grid");
-    constexpr int BK = SPLIT ? 64 : 32;        // k per chunk
+    static_assert(BK % (SPLIT ? 32 : 16) == 0, "chunk must hold whole MFMA k-steps");
     constexpr int SF = BK + 4;                 // FP32 LDS row (floats)
     constexpr int SB = BK + 8;                 // split LDS row (bf16)
-    constexpr int NF = SPLIT ? 1 : 2 * (TR + TI) * SF;
-    constexpr int NB = SPLIT ? 2 * (TR + TI) * SB : 1;
-    __shared__ __attribute__((aligned(16))) float ldsf[NF];        // [buf][TR+TI][SF]
-    __shared__ __attribute__((aligned(16))) uint16_t ldsh[NB];     // [buf][TR+TI][SB] hi
-    __shared__ __attribute__((aligned(16))) uint16_t ldsl[NB];     //                  lo
+    constexpr int NF = SPLIT ? 1 : STAGES * (TR + TI) * SF;
+    constexpr int NB = SPLIT ? STAGES * (TR + TI) * SB : 1;
+    __shared__ __attribute__((aligned(16))) float ldsf[NF];        // [stage][TR+TI][SF]
+    __shared__ __attribute__((aligned(16))) uint16_t ldsh[NB];     // [stage][TR+TI][SB] hi
+    __shared__ __attribute__((aligned(16))) uint16_t ldsl[NB];     //                    lo
     __shared__ float fshift[TR];
     __shared__ float fscr[kThreads];
     __shared__ double shd[8];
@@ -81,12 +85,13 @@ contract_rot(Pass P, EpiArgs E) {
         lmode = E.ctl->logmode;
     }
 
+    // Every field has at most 2^30 cells, so 32-bit element offsets suffice.
     const int n = P.n;
-    const int64_t R = P.R;
+    const int R = (int)P.R;
     const int IT = (n + TI - 1) / TI;
-    const int64_t logical = xcd_logical_block();
-    const int64_t r0 = (logical / IT) * TR;
-    const int i0 = (int)(logical % IT) * TI;
+    const int logical = xcd_logical_block();
+    const int r0 = (logical / IT) * TR;
+    const int i0 = (logical % IT) * TI;
     // band of the output tile, start aligned down to 4 (the extra columns meet exact zeros)
     const int kb0 = max(0, i0 - P.W) & ~3;
     const int kb1 = min(n, i0 + TI + P.W);
@@ -99,9 +104,11 @@ contract_rot(Pass P, EpiArgs E) {
     // Staging: one unit = 4 consecutive k of one row.
     constexpr int UX = (TR * BK / 4 + kThreads - 1) / kThreads;
     constexpr int UK = (TI * BK / 4 + kThreads - 1) / kThreads;
-    f4 rx[UX];
-    f4 rk[SPLIT ? 1 : UK];
-    u16x4 rkh[SPLIT ? UK : 1], rkl[SPLIT ? UK : 1];
+    struct Regs {   // one chunk of X and K1 on its way from HBM to LDS
+        f4 x[UX];
+        f4 k[SPLIT ? 1 : UK];
+        u16x4 kh[SPLIT ? UK : 1], kl[SPLIT ? UK : 1];
+    };
     bool logx = false;
 
     // per-row maximum of the log input over the band (log domain only)
@@ -110,7 +117,7 @@ contract_rot(Pass P, EpiArgs E) {
         const int f = tid / G, g = tid % G;
         float mx = -INFINITY;
         if (f < TR && r0 + f < R)
-            for (int k = kb0 + g; k < kb1; k += G) mx = fmaxf(mx, P.X[(r0 + f) * (int64_t)n + k]);
+            for (int k = kb0 + g; k < kb1; k += G) mx = fmaxf(mx, P.X[(r0 + f) * n + k]);
         if (f < TR) fscr[g * TR + f] = mx;
         __syncthreads();
         if (tid < TR) {
@@ -121,7 +128,7 @@ contract_rot(Pass P, EpiArgs E) {
         __syncthreads();
     };
 
-    auto load = [&](int c, float fill) {
+    auto load = [&](int c, float fill, Regs& g) {
         const int kc = kb0 + c * BK;
 #pragma unroll
         for (int u = 0; u < UX; ++u) {
@@ -129,23 +136,23 @@ contract_rot(Pass P, EpiArgs E) {
             f4 v = f4{fill, fill, fill, fill};
             if (unit < TR * BK / 4) {
                 const int d = unit / (BK / 4), k = kc + 4 * (unit % (BK / 4));
-                const int64_t row = r0 + d;
+                const int row = r0 + d;
                 if (row < R) {
-                    const float* src = P.X + row * (int64_t)n + k;
+                    const float* src = P.X + (row * n + k);
                     if (vec && k + 3 < kb1) v = *reinterpret_cast<const f4*>(src);
                     else
 #pragma unroll
                         for (int e = 0; e < 4; ++e) v[e] = (k + e < kb1) ? src[e] : fill;
                 }
             }
-            rx[u] = v;
+            g.x[u] = v;
         }
 #pragma unroll
         for (int u = 0; u < UK; ++u) {
             const int unit = tid + u * kThreads;
             const int d = unit / (BK / 4), k = kc + 4 * (unit % (BK / 4));
             const bool ok = unit < TI * BK / 4 && i0 + d < n;
-            const int64_t off = (int64_t)(i0 + d) * n + k;
+            const int off = (i0 + d) * n + k;
             if (SPLIT) {
                 u16x4 h = u16x4{0, 0, 0, 0}, l = u16x4{0, 0, 0, 0};
                 if (ok) {
@@ -160,8 +167,8 @@ contract_rot(Pass P, EpiArgs E) {
                         }
                     }
                 }
-                rkh[u] = h;
-                rkl[u] = l;
+                g.kh[u] = h;
+                g.kl[u] = l;
             } else {
                 f4 v = f4{0.f, 0.f, 0.f, 0.f};
                 if (ok) {
@@ -170,18 +177,18 @@ contract_rot(Pass P, EpiArgs E) {
 #pragma unroll
                         for (int e = 0; e < 4; ++e) v[e] = (k + e < kb1) ? P.K1[off + e] : 0.f;
                 }
-                rk[u] = v;
+                g.k[u] = v;
             }
         }
     };
 
-    auto store = [&](int buf) {
+    auto store = [&](int buf, const Regs& g) {
 #pragma unroll
         for (int u = 0; u < UX; ++u) {
             const int unit = tid + u * kThreads;
             if (unit >= TR * BK / 4) continue;
             const int d = unit / (BK / 4), kq = unit % (BK / 4);
-            f4 v = rx[u];
+            f4 v = g.x[u];
             if (logx) {
                 const float m = fshift[d];
 #pragma unroll
@@ -208,10 +215,10 @@ contract_rot(Pass P, EpiArgs E) {
             const int d = unit / (BK / 4), kq = unit % (BK / 4);
             if (SPLIT) {
                 const int o = (buf * (TR + TI) + TR + d) * SB + 4 * kq;
-                *reinterpret_cast<u16x4*>(&ldsh[o]) = rkh[u];
-                *reinterpret_cast<u16x4*>(&ldsl[o]) = rkl[u];
+                *reinterpret_cast<u16x4*>(&ldsh[o]) = g.kh[u];
+                *reinterpret_cast<u16x4*>(&ldsl[o]) = g.kl[u];
             } else {
-                *reinterpret_cast<f4*>(&ldsf[(buf * (TR + TI) + TR + d) * SF + 4 * kq]) = rk[u];
+                *reinterpret_cast<f4*>(&ldsf[(buf * (TR + TI) + TR + d) * SF + 4 * kq]) = g.k[u];
             }
         }
     };
@@ -273,54 +280,91 @@ contract_rot(Pass P, EpiArgs E) {
         }
     };
 
-    // Epilogue inputs: fetched before the K loop so that their latency overlaps it.
-    EpiIn ein[FM][FN];
-    int64_t ebase[FM][FN];
-    int ecnt[FM][FN];
+    // Epilogue: the accumulator tile goes through LDS as [i][r] rows, and each
+    // thread finishes UE runs of 4 consecutive r of one output row i (row i of
+    // the output tile is TR contiguous floats: coalesced loads and stores).
+    // Their inputs are fetched now, before the K loop.
+    constexpr int UE = (TI * TR / 4 + kThreads - 1) / kThreads;
+    constexpr int TS = TR + 4;   // LDS row of the staged tile
+    static_assert(TI * TS * 4 <= (SPLIT ? NB * 2 : NF * 4), "staged tile must fit in the staging LDS");
+    EpiIn ein[UE];
+    int eidx[UE], ecnt[UE];
 #pragma unroll
-    for (int a = 0; a < FM; ++a)
-#pragma unroll
-        for (int b = 0; b < FN; ++b) {
-            const int64_t r = r0 + wr * 16 * FM + a * 16 + 4 * (lane >> 4);
-            const int i = i0 + wi * 16 * FN + b * 16 + (lane & 15);
-            const int64_t left = R - r;
-            ecnt[a][b] = (i < n) ? (int)(left < 0 ? 0 : (left > 4 ? 4 : left)) : 0;
-            ebase[a][b] = (int64_t)i * R + r;
-            ein[a][b] = epi_prefetch(E, ebase[a][b], ecnt[a][b]);
-        }
+    for (int u = 0; u < UE; ++u) {
+        const int unit = tid + u * kThreads;
+        const int il = unit / (TR / 4), rl = 4 * (unit % (TR / 4));
+        const int i = i0 + il, r = r0 + rl;
+        ecnt[u] = (unit < TI * TR / 4 && i < n) ? max(0, min(4, R - r)) : 0;
+        eidx[u] = i * R + r;
+        ein[u] = epi_prefetch<EK>(E, eidx[u], ecnt[u]);
+    }
 
-    // first chunk in flight before the control flags are looked at
-    load(0, 0.f);
+    // The first chunks are in flight before the control flags are looked at.
+    // Pipelined form: two register sets keep the loads of chunk c+2 in flight
+    // while chunk c is multiplied and chunk c+1 is written to LDS.
+    Regs ra, rb;
+    load(0, 0.f, ra);
+    if (STAGES == 2 && nch > 1) load(1, 0.f, rb);
     logx = lmode != 0;
     if (logx) {
         row_shifts();
-        load(0, -INFINITY);   // staged logs: cells outside the band are exact zeros
+        load(0, -INFINITY, ra);   // staged logs: cells outside the band are exact zeros
+        if (STAGES == 2 && nch > 1) load(1, -INFINITY, rb);
     }
-    store(0);
+    store(0, ra);
     if (done) return;   // the step has stopped: nothing to compute (uniform)
     __syncthreads();
     const float fill = logx ? -INFINITY : 0.f;
-    for (int c = 0; c < nch; ++c) {
-        const int cur = c & 1;
-        if (c + 1 < nch) load(c + 1, fill);
-        compute(cur);
-        if (c + 1 < nch) store(cur ^ 1);
-        __syncthreads();
+    if (STAGES == 2) {
+        for (int c = 0; c < nch; c += 2) {
+            // chunk c in stage 0, rb holds chunk c+1, ra is free
+            if (c + 2 < nch) load(c + 2, fill, ra);
+            compute(0);
+            if (c + 1 < nch) store(1, rb);
+            __syncthreads();
+            if (c + 1 >= nch) break;
+            // chunk c+1 in stage 1, ra holds chunk c+2, rb is free
+            if (c + 3 < nch) load(c + 3, fill, rb);
+            compute(1);
+            if (c + 2 < nch) store(0, ra);
+            __syncthreads();
+        }
+    } else {
+        for (int c = 0; c < nch; ++c) {
+            if (c > 0) {
+                load(c, fill, ra);
+                __syncthreads();
+                store(0, ra);
+                __syncthreads();
+            }
+            compute(0);
+        }
     }
 
-    EpiAcc ea;
+    // (the K loop ended on a barrier: the staging LDS is free)
+    float* tile = SPLIT ? reinterpret_cast<float*>(ldsh) : ldsf;
 #pragma unroll
     for (int a = 0; a < FM; ++a)
 #pragma unroll
         for (int b = 0; b < FN; ++b) {
-            f4 v = acc[a][b];
-            if (logx && ecnt[a][b] > 0) {
-                const int rl = wr * 16 * FM + a * 16 + 4 * (lane >> 4);
-#pragma unroll
-                for (int e = 0; e < 4; ++e) v[e] = shifted_log(v[e], fshift[(rl + e < TR) ? rl + e : 0]);
-            }
-            epi_apply(E, ebase[a][b], ecnt[a][b], v, logx, ein[a][b], ea);
+            const int rl = wr * 16 * FM + a * 16 + 4 * (lane >> 4);
+            const int il = wi * 16 * FN + b * 16 + (lane & 15);
+            *reinterpret_cast<f4*>(&tile[il * TS + rl]) = acc[a][b];
         }
+    __syncthreads();
+    EpiAcc ea;
+#pragma unroll
+    for (int u = 0; u < UE; ++u) {
+        const int unit = tid + u * kThreads;
+        const int il = unit / (TR / 4), rl = 4 * (unit % (TR / 4));
+        if (ecnt[u] == 0) continue;
+        f4 v = *reinterpret_cast<const f4*>(&tile[il * TS + rl]);
+        if (logx) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] = shifted_log(v[e], fshift[rl + e]);
+        }
+        epi_apply<EK>(E, eidx[u], ecnt[u], v, logx, ein[u], ea);
+    }
     epi_finish(E, ea, (int)blockIdx.x, shd);
 }
 
@@ -329,6 +373,7 @@ contract_rot(Pass P, EpiArgs E) {
 //  1: 32 x 32, 2 x 2 waves of one fragment
 //  2: 16 x 64, 1 x 4 waves (few rows: 1D grids)
 //  3: 64 x 16, 4 x 1 waves (short axes)
+// K runs in 32-wide (FP32) or 64-wide (split) chunks through two LDS stages.
 constexpr int kCfgTR[4] = {64, 32, 16, 64};
 constexpr int kCfgTI[4] = {64, 32, 64, 16};
 
@@ -343,16 +388,29 @@ int pick_cfg(const Pass& p) {
     return 1;
 }
 
-template <bool SPLIT>
+template <bool SPLIT, int BK, int EK>
 hipError_t launch_cfg(int cfg, int64_t nb, const Pass& p, const EpiArgs& e, hipStream_t st) {
     const dim3 grid((unsigned)nb), block(kThreads);
     switch (cfg) {
-        case 0: hipLaunchKernelGGL((contract_rot<64, 64, 2, 2, SPLIT>), grid, block, 0, st, p, e); break;
-        case 1: hipLaunchKernelGGL((contract_rot<32, 32, 2, 2, SPLIT>), grid, block, 0, st, p, e); break;
-        case 2: hipLaunchKernelGGL((contract_rot<16, 64, 1, 4, SPLIT>), grid, block, 0, st, p, e); break;
-        default: hipLaunchKernelGGL((contract_rot<64, 16, 4, 1, SPLIT>), grid, block, 0, st, p, e); break;
+        case 0: hipLaunchKernelGGL((contract_rot<64, 64, 2, 2, SPLIT, BK, 2, EK>), grid, block, 0, st, p, e); break;
+        case 1: hipLaunchKernelGGL((contract_rot<32, 32, 2, 2, SPLIT, BK, 2, EK>), grid, block, 0, st, p, e); break;
+        case 2: hipLaunchKernelGGL((contract_rot<16, 64, 1, 4, SPLIT, BK, 2, EK>), grid, block, 0, st, p, e); break;
+        default: hipLaunchKernelGGL((contract_rot<64, 16, 4, 1, SPLIT, BK, 2, EK>), grid, block, 0, st, p, e); break;
     }
     return hipGetLastError();
+}
+
+template <bool SPLIT, int BK>
+hipError_t launch_ek(int ek, int cfg, int64_t nb, const Pass& p, const EpiArgs& e, hipStream_t st) {
+    switch (ek) {
+        case EK_STORE: return launch_cfg<SPLIT, BK, EK_STORE>(cfg, nb, p, e, st);
+        case EK_BUPDATE: return launch_cfg<SPLIT, BK, EK_BUPDATE>(cfg, nb, p, e, st);
+        case EK_MONITOR: return launch_cfg<SPLIT, BK, EK_MONITOR>(cfg, nb, p, e, st);
+        case EK_PROX + JKO_F_ZERO: return launch_cfg<SPLIT, BK, EK_PROX + JKO_F_ZERO>(cfg, nb, p, e, st);
+        case EK_PROX + JKO_F_CONGESTION: return launch_cfg<SPLIT, BK, EK_PROX + JKO_F_CONGESTION>(cfg, nb, p, e, st);
+        case EK_PROX + JKO_F_POROUS: return launch_cfg<SPLIT, BK, EK_PROX + JKO_F_POROUS>(cfg, nb, p, e, st);
+        default: return launch_cfg<SPLIT, BK, EK_PROX + JKO_F_ENTROPY>(cfg, nb, p, e, st);
+    }
 }
 
 }  // namespace
@@ -365,8 +423,9 @@ hipError_t launch_contract(const Pass& pass, int32_t precision, const EpiArgs& e
     const int64_t nb = tiles_of(pass, c);
     if (nblocks) *nblocks = (int)nb;
     if (nb <= 0) return hipSuccess;
-    if (precision == JKO_SPLIT_BF16) return launch_cfg<true>(c, nb, pass, epi, stream);
-    return launch_cfg<false>(c, nb, pass, epi, stream);
+    const int ek = ek_of(epi);
+    if (precision == JKO_SPLIT_BF16) return launch_ek<true, 64>(ek, c, nb, pass, epi, stream);
+    return launch_ek<false, 32>(ek, c, nb, pass, epi, stream);
 }
 
 }  // namespace jko

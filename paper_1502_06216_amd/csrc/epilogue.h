@@ -70,26 +70,43 @@ __device__ __forceinline__ float log_prox_porous(float ls, float lk, float m, in
     return ls - v / (m - 1.f);
 }
 
-// Prox of one cell; pu, pv are the cell's prefetched energy parameters
-// (congestion: exp(-sigma w), kappa; entropy: 1/(1 + sigma c); porous:
-// log((m-1) k)).
-__device__ __forceinline__ float prox_val(const ProxArgs& px, float s, float pu, float pv) {
-    switch (px.kind) {
-        case JKO_F_CONGESTION: return fminf(s * pu, pv);
-        case JKO_F_ENTROPY: return s > 0.f ? expf(pu * logf(s)) : 0.f;
-        case JKO_F_POROUS: return s > 0.f ? expf(log_prox_porous(logf(s), pu, px.m, px.newton)) : 0.f;
-        default: return s;
+// Epilogue codes: the epilogue kind and, for the proximal epilogue, the
+// energy, fixed at compile time so that each kernel carries only its own code.
+enum : int { EK_STORE = 0, EK_BUPDATE = 1, EK_MONITOR = 2, EK_PROX = 3 };   // EK_PROX + energy kind
+constexpr int ek_count = EK_PROX + 4;
+
+__host__ __device__ constexpr EpiKind ek_kind(int ek) {
+    return ek == EK_STORE ? EpiKind::STORE : ek == EK_BUPDATE ? EpiKind::BUPDATE
+         : ek == EK_MONITOR ? EpiKind::MONITOR : EpiKind::PROX;
+}
+
+inline int ek_of(const EpiArgs& e) {
+    switch (e.kind) {
+        case EpiKind::STORE: return EK_STORE;
+        case EpiKind::BUPDATE: return EK_BUPDATE;
+        case EpiKind::MONITOR: return EK_MONITOR;
+        default: return EK_PROX + e.prox.kind;
     }
 }
 
+// Prox of one cell; pu, pv are the cell's prefetched energy parameters
+// (congestion: exp(-sigma w), kappa; entropy: 1/(1 + sigma c); porous:
+// log((m-1) k)).
+template <int KIND>
+__device__ __forceinline__ float prox_val(const ProxArgs& px, float s, float pu, float pv) {
+    if (KIND == JKO_F_CONGESTION) return fminf(s * pu, pv);
+    if (KIND == JKO_F_ENTROPY) return s > 0.f ? expf(pu * logf(s)) : 0.f;
+    if (KIND == JKO_F_POROUS) return s > 0.f ? expf(log_prox_porous(logf(s), pu, px.m, px.newton)) : 0.f;
+    return s;
+}
+
 // log Prox(exp(ls)) of one cell.
+template <int KIND>
 __device__ __forceinline__ float log_prox_val(const ProxArgs& px, float ls, float pu, float pv) {
-    switch (px.kind) {
-        case JKO_F_CONGESTION: return fminf(ls + logf(pu), logf(pv));
-        case JKO_F_ENTROPY: return pu * ls;
-        case JKO_F_POROUS: return log_prox_porous(ls, pu, px.m, px.newton);
-        default: return ls;
-    }
+    if (KIND == JKO_F_CONGESTION) return fminf(ls + logf(pu), logf(pv));
+    if (KIND == JKO_F_ENTROPY) return pu * ls;
+    if (KIND == JKO_F_POROUS) return log_prox_porous(ls, pu, px.m, px.newton);
+    return ls;
 }
 
 // ------------------------------------------------------------- epilogues
@@ -107,7 +124,7 @@ struct EpiIn {
     f4 u, v;
 };
 
-__device__ __forceinline__ f4 ld4(const float* __restrict__ p, int64_t idx, int cnt, bool vec, float fill) {
+__device__ __forceinline__ f4 ld4(const float* __restrict__ p, int idx, int cnt, bool vec, float fill) {
     if (vec && cnt == 4) return *reinterpret_cast<const f4*>(p + idx);
     f4 r = f4{fill, fill, fill, fill};
 #pragma unroll
@@ -116,7 +133,7 @@ __device__ __forceinline__ f4 ld4(const float* __restrict__ p, int64_t idx, int 
     return r;
 }
 
-__device__ __forceinline__ void st4(float* __restrict__ p, int64_t idx, int cnt, bool vec, f4 v) {
+__device__ __forceinline__ void st4(float* __restrict__ p, int idx, int cnt, bool vec, f4 v) {
     if (vec && cnt == 4) {
         *reinterpret_cast<f4*>(p + idx) = v;
         return;
@@ -126,31 +143,25 @@ __device__ __forceinline__ void st4(float* __restrict__ p, int64_t idx, int cnt,
         if (e < cnt) p[idx + e] = v[e];
 }
 
-__device__ __forceinline__ EpiIn epi_prefetch(const EpiArgs& E, int64_t idx, int cnt) {
+template <int EK>
+__device__ __forceinline__ EpiIn epi_prefetch(const EpiArgs& E, int idx, int cnt) {
     EpiIn in;
     in.u = f4{0.f, 0.f, 0.f, 0.f};
     in.v = f4{0.f, 0.f, 0.f, 0.f};
     if (cnt <= 0) return in;
     const bool vec = E.vec_ok && ((idx & 3) == 0);
-    switch (E.kind) {
-        case EpiKind::BUPDATE:
-        case EpiKind::MONITOR:
-            in.u = ld4(E.q, idx, cnt, vec, 0.f);
-            if (E.kind == EpiKind::MONITOR || E.check) in.v = ld4(E.b, idx, cnt, vec, 0.f);
-            break;
-        case EpiKind::PROX: {
-            const ProxArgs& px = E.prox;
-            if (px.kind == JKO_F_CONGESTION) {
-                in.u = px.g ? ld4(px.g, idx, cnt, vec, 1.f) : f4{1.f, 1.f, 1.f, 1.f};
-                in.v = px.kappa ? ld4(px.kappa, idx, cnt, vec, 0.f)
-                                : f4{px.kappa_s, px.kappa_s, px.kappa_s, px.kappa_s};
-            } else if (px.kind == JKO_F_ENTROPY || px.kind == JKO_F_POROUS) {
-                in.u = px.kf ? ld4(px.kf, idx, cnt, vec, 0.f) : f4{px.kf_s, px.kf_s, px.kf_s, px.kf_s};
-            }
-            break;
+    if (EK == EK_BUPDATE || EK == EK_MONITOR) {
+        in.u = ld4(E.q, idx, cnt, vec, 0.f);
+        if (EK == EK_MONITOR || E.check) in.v = ld4(E.b, idx, cnt, vec, 0.f);
+    } else if (EK >= EK_PROX) {
+        const ProxArgs& px = E.prox;
+        if (EK - EK_PROX == JKO_F_CONGESTION) {
+            in.u = px.g ? ld4(px.g, idx, cnt, vec, 1.f) : f4{1.f, 1.f, 1.f, 1.f};
+            in.v = px.kappa ? ld4(px.kappa, idx, cnt, vec, 0.f)
+                            : f4{px.kappa_s, px.kappa_s, px.kappa_s, px.kappa_s};
+        } else if (EK - EK_PROX == JKO_F_ENTROPY || EK - EK_PROX == JKO_F_POROUS) {
+            in.u = px.kf ? ld4(px.kf, idx, cnt, vec, 0.f) : f4{px.kf_s, px.kf_s, px.kf_s, px.kf_s};
         }
-        default:
-            break;
     }
     return in;
 }
@@ -162,67 +173,62 @@ __device__ __forceinline__ EpiIn epi_prefetch(const EpiArgs& E, int64_t idx, int
 //   MONITOR  err += |b t - q|
 //   PROX     s = v; p = prox(s); a = p / s; [p_out = p]       (0/0 = 0)
 // Log domain: the same with b, a held as log b, log a.
-__device__ __forceinline__ void epi_apply(const EpiArgs& E, int64_t idx, int cnt, f4 val, bool logx,
+template <int EK>
+__device__ __forceinline__ void epi_apply(const EpiArgs& E, int idx, int cnt, f4 val, bool logx,
                                           const EpiIn& in, EpiAcc& acc) {
     if (cnt <= 0) return;
     const bool vec = E.vec_ok && ((idx & 3) == 0);
-    switch (E.kind) {
-        case EpiKind::STORE:
-            st4(E.y, idx, cnt, vec, val);
-            break;
-        case EpiKind::BUPDATE: {
-            f4 bn;
+    if (EK == EK_STORE) {
+        st4(E.y, idx, cnt, vec, val);
+    } else if (EK == EK_BUPDATE) {
+        f4 bn;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const float q = in.u[e], t = val[e];
-                if (logx) {
-                    bn[e] = (q == 0.f) ? -INFINITY : logf(q) - t;
-                    if (E.check && e < cnt) {
-                        acc.err += fabs((double)expf(in.v[e] + t) - (double)q);
-                        if (bn[e] > -INFINITY) acc.maxlb = fmax(acc.maxlb, fabs((double)bn[e]));
-                    }
-                } else {
-                    bn[e] = (q == 0.f) ? 0.f : q / t;
-                    if (E.check && e < cnt) {
-                        acc.err += fabs((double)in.v[e] * (double)t - (double)q);
-                        if (bn[e] > 0.f) acc.maxlb = fmax(acc.maxlb, fabs((double)logf(bn[e])));
-                    }
+        for (int e = 0; e < 4; ++e) {
+            const float q = in.u[e], t = val[e];
+            if (logx) {
+                bn[e] = (q == 0.f) ? -INFINITY : logf(q) - t;
+                if (E.check && e < cnt) {
+                    acc.err += fabs((double)expf(in.v[e] + t) - (double)q);
+                    if (bn[e] > -INFINITY) acc.maxlb = fmax(acc.maxlb, fabs((double)bn[e]));
+                }
+            } else {
+                bn[e] = (q == 0.f) ? 0.f : q / t;
+                if (E.check && e < cnt) {
+                    acc.err += fabs((double)in.v[e] * (double)t - (double)q);
+                    if (bn[e] > 0.f) acc.maxlb = fmax(acc.maxlb, fabs((double)logf(bn[e])));
                 }
             }
-            st4(E.b, idx, cnt, vec, bn);
-            if (E.t_out) st4(E.t_out, idx, cnt, vec, val);
-            break;
         }
-        case EpiKind::MONITOR:
+        st4(E.b, idx, cnt, vec, bn);
+        if (E.t_out) st4(E.t_out, idx, cnt, vec, val);
+    } else if (EK == EK_MONITOR) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                if (e >= cnt) continue;
-                const double bt = logx ? (double)expf(in.v[e] + val[e]) : (double)in.v[e] * (double)val[e];
-                acc.err += fabs(bt - (double)in.u[e]);
-            }
-            break;
-        case EpiKind::PROX: {
-            f4 an, pn;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                if (logx) {
-                    const float lp = log_prox_val(E.prox, val[e], in.u[e], in.v[e]);
-                    an[e] = (lp == -INFINITY) ? -INFINITY : lp - val[e];
-                    pn[e] = expf(lp);
-                    if (E.check && e < cnt && an[e] > -INFINITY) acc.maxla = fmax(acc.maxla, fabs((double)an[e]));
-                } else {
-                    const float p = prox_val(E.prox, val[e], in.u[e], in.v[e]);
-                    pn[e] = p;
-                    an[e] = (p == 0.f) ? 0.f : p / val[e];
-                    if (E.check && e < cnt && an[e] > 0.f) acc.maxla = fmax(acc.maxla, fabs((double)logf(an[e])));
-                }
-                if (E.check && e < cnt) acc.mass += (double)pn[e];
-            }
-            st4(E.a, idx, cnt, vec, an);
-            if (E.write_p) st4(E.p_out, idx, cnt, vec, pn);
-            if (E.s_out) st4(E.s_out, idx, cnt, vec, val);
-            break;
+        for (int e = 0; e < 4; ++e) {
+            if (e >= cnt) continue;
+            const double bt = logx ? (double)expf(in.v[e] + val[e]) : (double)in.v[e] * (double)val[e];
+            acc.err += fabs(bt - (double)in.u[e]);
         }
+    } else {
+        constexpr int KIND = EK - EK_PROX;
+        f4 an, pn;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            if (logx) {
+                const float lp = log_prox_val<KIND>(E.prox, val[e], in.u[e], in.v[e]);
+                an[e] = (lp == -INFINITY) ? -INFINITY : lp - val[e];
+                pn[e] = expf(lp);
+                if (E.check && e < cnt && an[e] > -INFINITY) acc.maxla = fmax(acc.maxla, fabs((double)an[e]));
+            } else {
+                const float p = prox_val<KIND>(E.prox, val[e], in.u[e], in.v[e]);
+                pn[e] = p;
+                an[e] = (p == 0.f) ? 0.f : p / val[e];
+                if (E.check && e < cnt && an[e] > 0.f) acc.maxla = fmax(acc.maxla, fabs((double)logf(an[e])));
+            }
+            if (E.check && e < cnt) acc.mass += (double)pn[e];
+        }
+        st4(E.a, idx, cnt, vec, an);
+        if (E.write_p) st4(E.p_out, idx, cnt, vec, pn);
+        if (E.s_out) st4(E.s_out, idx, cnt, vec, val);
     }
 }
 

@@ -35,6 +35,7 @@ __device__ __forceinline__ int64_t xcd_block() {
 
 constexpr int kThr = 512;   // 8 waves per block
 
+template <int EK>
 __global__ void __launch_bounds__(kThr)
 gibbs2d_f32(Band2D B, EpiArgs E) {
     __shared__ __attribute__((aligned(16))) float Xs[kHalo * kS];   // [ib][jb]
@@ -75,10 +76,10 @@ gibbs2d_f32(Band2D B, EpiArgs E) {
     // Its epilogue inputs are fetched now, ahead of the contraction.
     const int koff = 4 * (lane >> 4);
     const int oi = i0 + (lane & 15);
-    const int64_t obase = (int64_t)oi * n1 + j0 + koff;
+    const int obase = oi * n1 + j0 + koff;
     const int ocnt = (oi < n0) ? max(0, min(4, n1 - (j0 + koff))) : 0;
     EpiIn ein;
-    if (wave == 0) ein = epi_prefetch(E, obase, ocnt);
+    if (wave == 0) ein = epi_prefetch<EK>(E, obase, ocnt);
 
     // ---- stage the halo of X and the two factor bands: every load is issued
     // before the first LDS store
@@ -254,7 +255,7 @@ gibbs2d_f32(Band2D B, EpiArgs E) {
                 acc[e] = (m != m) ? -INFINITY : (acc[e] > 0.f ? m + logf(acc[e]) : m - 104.f);
             }
         }
-        epi_apply(E, obase, ocnt, acc, logx, ein, ea);
+        epi_apply<EK>(E, obase, ocnt, acc, logx, ein, ea);
     }
     epi_finish(E, ea, (int)blockIdx.x, shd);
 }
@@ -284,7 +285,19 @@ hipError_t launch_gibbs2d(const Band2D& b, int32_t precision, const EpiArgs& epi
     (void)precision;
     const int64_t nb = gibbs2d_blocks(b.n0, b.n1);
     if (nblocks) *nblocks = (int)nb;
-    hipLaunchKernelGGL(gibbs2d_f32, dim3((unsigned)nb), dim3(kThr), 0, stream, b, epi);
+    const dim3 grid((unsigned)nb), block(kThr);
+    switch (ek_of(epi)) {
+        case EK_STORE: hipLaunchKernelGGL(gibbs2d_f32<EK_STORE>, grid, block, 0, stream, b, epi); break;
+        case EK_BUPDATE: hipLaunchKernelGGL(gibbs2d_f32<EK_BUPDATE>, grid, block, 0, stream, b, epi); break;
+        case EK_MONITOR: hipLaunchKernelGGL(gibbs2d_f32<EK_MONITOR>, grid, block, 0, stream, b, epi); break;
+        case EK_PROX + JKO_F_ZERO:
+            hipLaunchKernelGGL(gibbs2d_f32<EK_PROX + JKO_F_ZERO>, grid, block, 0, stream, b, epi); break;
+        case EK_PROX + JKO_F_CONGESTION:
+            hipLaunchKernelGGL(gibbs2d_f32<EK_PROX + JKO_F_CONGESTION>, grid, block, 0, stream, b, epi); break;
+        case EK_PROX + JKO_F_POROUS:
+            hipLaunchKernelGGL(gibbs2d_f32<EK_PROX + JKO_F_POROUS>, grid, block, 0, stream, b, epi); break;
+        default: hipLaunchKernelGGL(gibbs2d_f32<EK_PROX + JKO_F_ENTROPY>, grid, block, 0, stream, b, epi); break;
+    }
     return hipGetLastError();
 }
 
