@@ -102,38 +102,108 @@ def fused2d_executed_flops(n0, n1, W0, W1):
     return tot
 
 
-def roofline(wl, precision, q):
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1502_06216_amd", "csrc")
+PROFILES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
+# counter summaries of the dominant launch per (workload, precision)
+TRAFFIC_PROFILES = {("crowd256", "fp32"): "gibbs2d_prox_congestion_crowd256_traffic.md",
+                    ("crowd128c", "fp32"): "pass_prox_congestion_crowd128c_traffic.md"}
+
+
+def kernel_source_hash(kernel_file):
+    """sha256 of the sources one kernel is compiled from (its file plus the
+    shared device headers); a stored counter reading is valid only for the
+    sources it was taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("jko_internal.h", "epilogue.h", kernel_file):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic(profile_name, kernel_file, launch):
+    """Calibrated HBM bytes per dispatch from a committed counter summary
+    (FETCH_SIZE and WRITE_SIZE passes), or None when the summary is missing,
+    covers another launch, or the kernel's sources changed since it was
+    taken."""
+    import re
+    path = os.path.join(PROFILES, profile_name)
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m_h = re.search(r"^source_sha256:\s*([0-9a-f]{64})", txt, re.M)
+    m_b = re.search(r"^traffic_bytes_per_dispatch:\s*([0-9.eE+]+)", txt, re.M)
+    m_l = re.search(r"^launch:\s*(.+?)\s*$", txt, re.M)
+    if not m_h or not m_b or not m_l or m_l.group(1) != launch:
+        return None
+    if m_h.group(1) != kernel_source_hash(kernel_file):
+        return None
+    return float(m_b.group(1))
+
+
+def _field_bytes(wl):
+    """Bytes per cell the prox epilogue reads for the energy's fields."""
+    fields = 0
+    if wl.kind == "congestion":
+        fields += (wl.w is not None) + (wl.kappa is not None)
+    elif wl.kind in ("entropy", "porous"):
+        fields += wl.coef is not None
+    return 4 * fields
+
+
+def roofline(wl, precision, q, traffic_profile=None):
     """Per-launch durations of the kernel launches of one iteration (HIP
-    events on the library's stream) and the roofline of the slowest.
-    Algorithmic flops: the dense separable contraction, 2 n_k N per axis."""
+    events on the library's stream) and the roofline of the slowest launch.
+
+    Algorithmic work per launch:
+      flops  the dense separable contraction, 2 n_k N per axis pass
+             (2 (n0 + n1) N for a fused 2D application);
+      bytes  each field read or written once: a pass without epilogue reads
+             X and writes Y (8 B/cell); the b-update epilogue reads t's input,
+             q and writes b (12 B/cell); the prox epilogue reads s's input and
+             the energy's fields and writes a (8 B/cell + 4 per field).
+    The bound is the roof with the larger lower-bound time."""
     import paper_1502_06216_amd as jk
     en = _energy(wl)
     ms = jk.time_iteration(q, en, wl.gamma, wl.tau, precision=precision, reps=200)
     d = len(wl.shape)
     N = int(np.prod(wl.shape))
+    fb = _field_bytes(wl)
     if len(ms) == 2 and d == 2:
         flops = [2.0 * (wl.shape[0] + wl.shape[1]) * N] * 2
+        nbytes = [12.0 * N, (8.0 + fb) * N]
         names = ["fused 2D application, b-update epilogue", "fused 2D application, prox epilogue"]
+        kfile = "gibbs2d.hip"
         W = [band_halfwidth(n, wl.gamma) for n in wl.shape]
         executed = fused2d_executed_flops(wl.shape[0], wl.shape[1], W[0], W[1])
     else:
         order = list(range(d - 1, -1, -1)) * 2
         flops = [2.0 * wl.shape[ax] * N for ax in order]
+        nbytes = [12.0 * N if i == d - 1 else (8.0 + fb) * N if i == 2 * d - 1 else 8.0 * N
+                  for i in range(2 * d)]
         names = [f"axis-{ax} pass" + (", b-update epilogue" if i == d - 1 else ", prox epilogue" if i == 2 * d - 1 else "")
                  for i, ax in enumerate(order)]
+        kfile = "contract.hip"
         executed = None
     k = int(np.argmax(ms))
-    achieved = flops[k] / (ms[k] * 1e-3) / 1e12
-    peak = PEAK_FP32_MFMA_TFLOPS if precision == "fp32" else PEAK_BF16_MFMA_TFLOPS
-    out = {
-        "bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-        "frac": round(achieved / peak, 4), "traffic": None, "kernel": names[k],
-        "flops_per_launch": flops[k], "ms_per_launch": round(ms[k], 5),
-        "ms_per_launch_all": [round(x, 5) for x in ms],
-    }
+    sec = ms[k] * 1e-3
+    peak_f = PEAK_FP32_MFMA_TFLOPS if precision == "fp32" else PEAK_BF16_MFMA_TFLOPS
+    t_mfma = flops[k] / (peak_f * 1e12)
+    t_hbm = nbytes[k] / (PEAK_HBM_GBPS * 1e9)
+    mfma = {"achieved": round(flops[k] / sec / 1e12, 3), "peak": peak_f, "unit": "TFLOP/s",
+            "frac": round(flops[k] / sec / 1e12 / peak_f, 4)}
+    hbm = {"achieved": round(nbytes[k] / sec / 1e9, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+           "frac": round(nbytes[k] / sec / 1e9 / PEAK_HBM_GBPS, 4)}
+    bound = "mfma" if t_mfma >= t_hbm else "hbm"
+    main = mfma if bound == "mfma" else hbm
+    traffic = stored_traffic(traffic_profile, kfile, names[k]) if traffic_profile else None
+    out = {"bound": bound, **main, "traffic": traffic, "kernel": names[k],
+           "flops_per_launch": flops[k], "algorithmic_bytes_per_launch": nbytes[k],
+           "ms_per_launch": round(ms[k], 5), "ms_per_launch_all": [round(x, 5) for x in ms],
+           "other_roof": hbm if bound == "mfma" else mfma}
     if executed is not None:
         out["executed_mfma_flops_per_launch"] = executed
-        out["executed_frac"] = round(executed / (ms[k] * 1e-3) / 1e12 / peak, 4)
+        out["executed_mfma_frac"] = round(executed / sec / 1e12 / peak_f, 4)
     return out
 
 
@@ -185,7 +255,10 @@ def adjoint_ratio(precision="fp32"):
 
 def pmc_probe(name, precision):
     """A short fixed-count step of `name` followed by a plain 64 MiB device
-    copy, for hardware-counter passes (FETCH_SIZE / WRITE_SIZE per dispatch)."""
+    copy, for hardware-counter passes (FETCH_SIZE / WRITE_SIZE per dispatch).
+    The copy's source is evicted from the caches first (a 512 MiB fill runs
+    between writing it and copying it), so its counters read the copy's
+    known byte counts and calibrate the ones of the step's kernels."""
     import torch
     import paper_1502_06216_amd as jk
     from workloads import make_workload
@@ -196,6 +269,8 @@ def pmc_probe(name, precision):
     torch.cuda.synchronize()
     src = torch.ones(16 * 1024 * 1024, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
+    evict = torch.empty(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    evict.fill_(2.0)
     torch.cuda.synchronize()
     dst.copy_(src)
     torch.cuda.synchronize()
@@ -242,7 +317,7 @@ def main():
         "iters_per_step": [s["iters"] for s in stats],
         "marginal_l1": [s["marginal_l1"] for s in stats],
     }
-    line["roofline"] = roofline(wl, args.precision, q)
+    line["roofline"] = roofline(wl, args.precision, q, TRAFFIC_PROFILES.get(("crowd256", args.precision)))
     extra = {}
     if not args.no_extra:
         other = "split_bf16" if args.precision == "fp32" else "fp32"
@@ -253,7 +328,8 @@ def main():
         for prec in ("fp32", "split_bf16"):
             it3, el3, st3, q3 = run_flow(wl3, prec, 2, 1, tol=0.0, max_iters=300)
             extra[f"crowd128c_{prec}"] = {"iters_per_s": round(it3 / el3, 2), "jko_steps_per_s": round(2 / el3, 3),
-                                         "iters_per_step": 300, "roofline": roofline(wl3, prec, q3)}
+                                         "iters_per_step": 300,
+                                         "roofline": roofline(wl3, prec, q3, TRAFFIC_PROFILES.get(("crowd128c", prec)))}
         extra["adjoint_fp32"] = adjoint_ratio("fp32")
     line["extra"] = extra
     if not args.no_cpu_baseline:

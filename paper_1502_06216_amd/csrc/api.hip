@@ -214,7 +214,10 @@ jko_status carve(Plan* P, const Geo& g, int op, int64_t extra, void* ws, size_t 
 
 jko_status build_factors(Plan& P, double gamma) {
     for (int k = 0; k < P.g.d; ++k) P.W[k] = band_halfwidth(P.g.n[k], gamma);
-    P.fused2d = P.g.d == 2 && P.prec == JKO_FP32 && gibbs2d_fits(P.g.n[0], P.g.n[1], P.W[0], P.W[1]);
+    // The fused kernel trades redundant halo work for one launch per
+    // application: it wins while its grid is at most one block per CU.
+    P.fused2d = P.g.d == 2 && P.prec == JKO_FP32 && gibbs2d_fits(P.g.n[0], P.g.n[1], P.W[0], P.W[1]) &&
+                gibbs2d_blocks(P.g.n[0], P.g.n[1]) <= kFusedMaxBlocks;
     for (int k = 0; k < P.g.d; ++k) {
         bool done = false;
         for (int j = 0; j < k; ++j)

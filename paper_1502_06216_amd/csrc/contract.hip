@@ -369,32 +369,30 @@ contract_rot(Pass P, EpiArgs E) {
 }
 
 // Tile configurations (TR, TI, WR, WI):
-//  0: 64 x 64, 2 x 2 waves of 2 x 2 fragments
-//  1: 32 x 32, 2 x 2 waves of one fragment
-//  2: 16 x 64, 1 x 4 waves (few rows: 1D grids)
-//  3: 64 x 16, 4 x 1 waves (short axes)
-// K runs in 32-wide (FP32) or 64-wide (split) chunks through two LDS stages.
-constexpr int kCfgTR[4] = {64, 32, 16, 64};
-constexpr int kCfgTI[4] = {64, 32, 64, 16};
+//  0: 32 x 32, 2 x 2 waves of one fragment
+//  1: 16 x 64, 1 x 4 waves (few rows: 1D grids)
+//  2: 64 x 16, 4 x 1 waves (short axes)
+// K runs in 32-wide chunks through two LDS stages.  Larger tiles (64 x 64)
+// re-read less but leave too few blocks to hide latency at these sizes.
+constexpr int kCfgTR[3] = {32, 16, 64};
+constexpr int kCfgTI[3] = {32, 64, 16};
 
 int64_t tiles_of(const Pass& p, int c) {
     return ((p.R + kCfgTR[c] - 1) / kCfgTR[c]) * (int64_t)((p.n + kCfgTI[c] - 1) / kCfgTI[c]);
 }
 
 int pick_cfg(const Pass& p) {
-    if (p.n <= 16) return 3;
-    if (p.R <= 16) return 2;
-    if (tiles_of(p, 0) >= 256) return 0;
-    return 1;
+    if (p.n <= 16) return 2;
+    if (p.R <= 16) return 1;
+    return 0;
 }
 
 template <bool SPLIT, int BK, int EK>
 hipError_t launch_cfg(int cfg, int64_t nb, const Pass& p, const EpiArgs& e, hipStream_t st) {
     const dim3 grid((unsigned)nb), block(kThreads);
     switch (cfg) {
-        case 0: hipLaunchKernelGGL((contract_rot<64, 64, 2, 2, SPLIT, BK, 2, EK>), grid, block, 0, st, p, e); break;
-        case 1: hipLaunchKernelGGL((contract_rot<32, 32, 2, 2, SPLIT, BK, 2, EK>), grid, block, 0, st, p, e); break;
-        case 2: hipLaunchKernelGGL((contract_rot<16, 64, 1, 4, SPLIT, BK, 2, EK>), grid, block, 0, st, p, e); break;
+        case 0: hipLaunchKernelGGL((contract_rot<32, 32, 2, 2, SPLIT, BK, 2, EK>), grid, block, 0, st, p, e); break;
+        case 1: hipLaunchKernelGGL((contract_rot<16, 64, 1, 4, SPLIT, BK, 2, EK>), grid, block, 0, st, p, e); break;
         default: hipLaunchKernelGGL((contract_rot<64, 16, 4, 1, SPLIT, BK, 2, EK>), grid, block, 0, st, p, e); break;
     }
     return hipGetLastError();
@@ -424,7 +422,7 @@ hipError_t launch_contract(const Pass& pass, int32_t precision, const EpiArgs& e
     if (nblocks) *nblocks = (int)nb;
     if (nb <= 0) return hipSuccess;
     const int ek = ek_of(epi);
-    if (precision == JKO_SPLIT_BF16) return launch_ek<true, 64>(ek, c, nb, pass, epi, stream);
+    if (precision == JKO_SPLIT_BF16) return launch_ek<true, 32>(ek, c, nb, pass, epi, stream);
     return launch_ek<false, 32>(ek, c, nb, pass, epi, stream);
 }
 

@@ -112,6 +112,7 @@ struct Band2D {
 };
 bool gibbs2d_fits(int n0, int n1, int W0, int W1);
 int64_t gibbs2d_blocks(int n0, int n1);
+constexpr int64_t kFusedMaxBlocks = 256;   // one block per CU of the chip
 hipError_t launch_gibbs2d(const Band2D& b, int32_t precision, const EpiArgs& epi, int* nblocks,
                           hipStream_t stream);
 
