@@ -59,7 +59,7 @@ def _energy(wl):
                          density_scale=wl.density_scale)
 
 
-def run_flow(wl, precision, steps, warmup, tol=None, max_iters=None):
+def run_flow(wl, precision, steps, warmup, tol=None, max_iters=None, resident=True):
     """Run warmup + timed JKO steps of a workload; returns (iters, seconds, stats)."""
     import torch
     import paper_1502_06216_amd as jk
@@ -69,14 +69,14 @@ def run_flow(wl, precision, steps, warmup, tol=None, max_iters=None):
     q = _dev(wl.p0)
     for _ in range(warmup):
         q, _ = jk.step(q, en, wl.gamma, wl.tau, max_iters=max_iters, tol=tol, check_every=wl.check_every,
-                       precision=precision)
+                       precision=precision, resident=resident)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     iters = 0
     stats = []
     for _ in range(steps):
         q, st = jk.step(q, en, wl.gamma, wl.tau, max_iters=max_iters, tol=tol, check_every=wl.check_every,
-                        precision=precision)
+                        precision=precision, resident=resident)
         iters += st["iters"]
         stats.append(st)
     torch.cuda.synchronize()
@@ -105,7 +105,7 @@ def fused2d_executed_flops(n0, n1, W0, W1):
 CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1502_06216_amd", "csrc")
 PROFILES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
 # counter summaries of the dominant launch per (workload, precision)
-TRAFFIC_PROFILES = {("crowd256", "fp32"): "gibbs2d_prox_congestion_crowd256_traffic.md",
+TRAFFIC_PROFILES = {("crowd256", "fp32"): "resident2d_congestion_crowd256_traffic.md",
                     ("crowd128c", "fp32"): "pass_prox_congestion_crowd128c_traffic.md"}
 
 
@@ -115,7 +115,7 @@ def kernel_source_hash(kernel_file):
     sources it was taken on."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("jko_internal.h", "epilogue.h", kernel_file):
+    for f in ("jko_internal.h", "control.h", "epilogue.h", kernel_file):
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -151,7 +151,7 @@ def _field_bytes(wl):
     return 4 * fields
 
 
-def roofline(wl, precision, q, traffic_profile=None):
+def roofline(wl, precision, q, traffic_profile=None, resident=True):
     """Per-launch durations of the kernel launches of one iteration (HIP
     events on the library's stream) and the roofline of the slowest launch.
 
@@ -162,14 +162,29 @@ def roofline(wl, precision, q, traffic_profile=None):
              X and writes Y (8 B/cell); the b-update epilogue reads t's input,
              q and writes b (12 B/cell); the prox epilogue reads s's input and
              the energy's fields and writes a (8 B/cell + 4 per field).
+    A resident 2D launch runs `wl.max_iters` iterations: twice the fused
+    application's work per iteration, plus the b-update and prox bytes.
     The bound is the roof with the larger lower-bound time."""
     import paper_1502_06216_amd as jk
     en = _energy(wl)
-    ms = jk.time_iteration(q, en, wl.gamma, wl.tau, precision=precision, reps=200)
     d = len(wl.shape)
     N = int(np.prod(wl.shape))
     fb = _field_bytes(wl)
-    if len(ms) == 2 and d == 2:
+    ms = jk.time_iteration(q, en, wl.gamma, wl.tau, precision=precision, reps=200, resident=False)
+    if d == 2 and resident:
+        msr = jk.time_iteration(q, en, wl.gamma, wl.tau, precision=precision, reps=5, iters=wl.max_iters)
+        if len(msr) == 1:
+            per_launch = ms
+            ms = msr
+    if len(ms) == 1:
+        K = wl.max_iters
+        flops = [K * 2 * 2.0 * (wl.shape[0] + wl.shape[1]) * N]
+        nbytes = [K * (12.0 + 8.0 + fb) * N]
+        names = [f"resident 2D kernel, {K} iterations"]
+        kfile = "gibbs2d.hip"
+        W = [band_halfwidth(n, wl.gamma) for n in wl.shape]
+        executed = K * 2 * fused2d_executed_flops(wl.shape[0], wl.shape[1], W[0], W[1])
+    elif len(ms) == 2 and d == 2:
         flops = [2.0 * (wl.shape[0] + wl.shape[1]) * N] * 2
         nbytes = [12.0 * N, (8.0 + fb) * N]
         names = ["fused 2D application, b-update epilogue", "fused 2D application, prox epilogue"]
@@ -204,6 +219,9 @@ def roofline(wl, precision, q, traffic_profile=None):
     if executed is not None:
         out["executed_mfma_flops_per_launch"] = executed
         out["executed_mfma_frac"] = round(executed / sec / 1e12 / peak_f, 4)
+    if len(ms) == 1:
+        out["us_per_iteration"] = round(1e3 * ms[0] / wl.max_iters, 3)
+        out["launch_per_application_ms"] = [round(x, 5) for x in per_launch]
     return out
 
 
@@ -254,7 +272,8 @@ def adjoint_ratio(precision="fp32"):
 
 
 def pmc_probe(name, precision):
-    """A short fixed-count step of `name` followed by a plain 64 MiB device
+    """A fixed-count step of `name` (the workload's cap in 2D, where it is one
+    resident launch; 50 iterations in 3D) followed by a plain 64 MiB device
     copy, for hardware-counter passes (FETCH_SIZE / WRITE_SIZE per dispatch).
     The copy's source is evicted from the caches first (a 512 MiB fill runs
     between writing it and copying it), so its counters read the copy's
@@ -265,7 +284,8 @@ def pmc_probe(name, precision):
     wl = make_workload(name)
     en = _energy(wl)
     q = _dev(wl.p0)
-    p, st = jk.step(q, en, wl.gamma, wl.tau, max_iters=50, tol=0.0, precision=precision)
+    iters = wl.max_iters if len(wl.shape) == 2 else 50
+    p, st = jk.step(q, en, wl.gamma, wl.tau, max_iters=iters, tol=0.0, precision=precision)
     torch.cuda.synchronize()
     src = torch.ones(16 * 1024 * 1024, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
@@ -274,7 +294,7 @@ def pmc_probe(name, precision):
     torch.cuda.synchronize()
     dst.copy_(src)
     torch.cuda.synchronize()
-    print(json.dumps({"probe": name, "iterations": 50, "precision": precision,
+    print(json.dumps({"probe": name, "iterations": iters, "precision": precision,
                       "copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4}), flush=True)
 
 
@@ -324,6 +344,11 @@ def main():
         it2, el2, st2, _ = run_flow(wl, other, args.steps, args.warmup)
         extra[f"crowd256_{other}"] = {"iters_per_s": round(it2 / el2, 2), "jko_steps_per_s": round(args.steps / el2, 3),
                                       "iters_per_step": [s["iters"] for s in st2]}
+        if args.precision == "fp32":
+            it4, el4, st4, _ = run_flow(wl, "fp32", args.steps, args.warmup, resident=False)
+            extra["crowd256_fp32_launch_per_application"] = {
+                "iters_per_s": round(it4 / el4, 2), "jko_steps_per_s": round(args.steps / el4, 3),
+                "iters_per_step": [s["iters"] for s in st4]}
         wl3 = make_workload("crowd128c")
         for prec in ("fp32", "split_bf16"):
             it3, el3, st3, q3 = run_flow(wl3, prec, 2, 1, tol=0.0, max_iters=300)

@@ -101,7 +101,7 @@ typedef struct {
     int32_t max_iters;       /* iteration cap per step, >= 1 */
     int32_t check_every;     /* stop-test cadence in iterations, >= 1 */
     int32_t precision;       /* jko_precision */
-    int32_t reserved;
+    int32_t flags;           /* jko_flags bits (0 = defaults) */
     double absorb_threshold; /* log-domain absorption: at the first stop-test check where
                                 max|log a| or max|log b| exceeds it, a and b are absorbed
                                 (carried as logs) and every later contraction runs on
@@ -109,6 +109,13 @@ typedef struct {
                                 first iteration; +inf or NaN: never.  With a finite
                                 threshold the checks also run in fixed-count mode. */
 } jko_params;
+
+/* Execution flags of jko_params.flags.
+ * JKO_FLAG_NO_RESIDENT: on 2D grids whose fused kernel fits the chip in one
+ *   wave of blocks, a step's whole iteration normally runs in one cooperative
+ *   launch (the resident kernel); this flag keeps one launch per Gibbs
+ *   application instead.  Both paths give the same bits. */
+typedef enum { JKO_FLAG_NO_RESIDENT = 1 } jko_flags;
 
 typedef enum { JKO_STOP_TOL = 0, JKO_STOP_CAP = 1 } jko_stop_reason;
 
@@ -172,14 +179,17 @@ jko_status jko_backward(const jko_grid* grid, const jko_energy* energy, const jk
                         void* workspace, size_t workspace_bytes, void* stream);
 
 /* Measurement aid (not part of the method): sets up one step of p_in as
- * jko_step does, then times each kernel launch of one iteration -- the
- * launches of t = xi^T a ending in the b-update epilogue, then those of
- * s = xi b ending in the proximal epilogue (one launch per application for
- * 2D grids on the fused band kernel, else one per axis) -- `reps` times back
- * to back between two HIP events on `stream`.  ms_per_launch (host, room for
- * 2*ndim doubles) receives the mean duration of one launch of each, in
- * launch order; *n_launches (host, nullable) their number.  The scalings are
- * set to 1 first; p_in is not modified.  Synchronous. */
+ * jko_step does, then times its kernel launches `reps` times on `stream` with
+ * HIP events.  Where a step runs on the resident 2D kernel (see
+ * JKO_FLAG_NO_RESIDENT), that is one launch running params->max_iters
+ * iterations with no stop test.  Otherwise it is each launch of one
+ * iteration -- those of t = xi^T a ending in the b-update epilogue, then those
+ * of s = xi b ending in the proximal epilogue (one launch per application for
+ * 2D grids on the fused band kernel, else one per axis) -- back to back.
+ * ms_per_launch (host, room for 2*ndim doubles) receives the mean duration of
+ * one launch of each, in launch order; *n_launches (host, nullable) their
+ * number.  The scalings are set to 1 first; p_in is not modified.
+ * Synchronous. */
 jko_status jko_time_iteration(const jko_grid* grid, const jko_energy* energy, const jko_params* params,
                               const float* p_in, int32_t reps, double* ms_per_launch, int32_t* n_launches,
                               void* workspace, size_t workspace_bytes, void* stream);

@@ -29,6 +29,7 @@ JKO_ERR_INFEASIBLE = -5
 PRECISIONS = {"fp32": 0, "split_bf16": 1}
 ENERGY_KINDS = {"zero": 0, "congestion": 1, "porous": 2, "entropy": 3}
 OP_GIBBS, OP_STEP, OP_FLOW, OP_BACKWARD = 0, 1, 2, 3
+FLAG_NO_RESIDENT = 1   # jko_flags: keep one launch per Gibbs application
 
 
 class JKOError(RuntimeError):
@@ -51,7 +52,7 @@ class EnergyC(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("tau", ctypes.c_double), ("tol_l1", ctypes.c_double),
                 ("max_iters", ctypes.c_int32), ("check_every", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("absorb_threshold", ctypes.c_double)]
 
 
@@ -169,7 +170,7 @@ class EnergySpec:
 
 
 def make_params(gamma, tau, max_iters=300, tol=0.0, check_every=10, precision="fp32",
-                absorb_threshold=math.inf) -> Params:
+                absorb_threshold=math.inf, resident=True) -> Params:
     p = Params()
     p.gamma = float(gamma)
     p.tau = float(tau)
@@ -177,7 +178,7 @@ def make_params(gamma, tau, max_iters=300, tol=0.0, check_every=10, precision="f
     p.max_iters = int(max_iters)
     p.check_every = int(check_every)
     p.precision = PRECISIONS[precision]
-    p.reserved = 0
+    p.flags = 0 if resident else FLAG_NO_RESIDENT
     p.absorb_threshold = float(absorb_threshold)
     return p
 
@@ -206,15 +207,16 @@ def gibbs_apply(x: torch.Tensor, gamma: float, precision: str = "fp32",
 def step(p: torch.Tensor, energy: EnergySpec, gamma: float, tau: float, max_iters: int = 300,
          tol: float = 0.0, check_every: int = 10, precision: str = "fp32",
          absorb_threshold: float = math.inf, out: Optional[torch.Tensor] = None,
-         with_stats: bool = True):
+         with_stats: bool = True, resident: bool = True):
     """One JKO step p -> argmin_p' W_gamma(p', p) + tau f(p').  Returns
-    (p_next, stats dict or None)."""
+    (p_next, stats dict or None).  resident=False keeps one launch per Gibbs
+    application where the resident 2D kernel would run the step."""
     lib = load()
     shape = tuple(p.shape)
     _field(p, shape, "p")
     pout = torch.empty_like(p) if out is None else _field(out, shape, "out")
     g = make_grid(shape)
-    prm = make_params(gamma, tau, max_iters, tol, check_every, precision, absorb_threshold)
+    prm = make_params(gamma, tau, max_iters, tol, check_every, precision, absorb_threshold, resident)
     e = energy.to_c(shape)
     nb = lib.jko_workspace_bytes(ctypes.byref(g), ctypes.byref(prm), OP_STEP, 0)
     ws = _workspace(nb, p.device)
@@ -227,7 +229,7 @@ def step(p: torch.Tensor, energy: EnergySpec, gamma: float, tau: float, max_iter
 def flow(p0: torch.Tensor, energy: EnergySpec, gamma: float, tau: float, n_steps: int,
          max_iters: int = 300, tol: float = 0.0, check_every: int = 10, precision: str = "fp32",
          absorb_threshold: float = math.inf, checkpoints: bool = False, with_stats: bool = True,
-         out: Optional[torch.Tensor] = None):
+         out: Optional[torch.Tensor] = None, resident: bool = True):
     """n_steps JKO steps from p0.  Returns (p_T, stats list or None,
     checkpoints tensor (n_steps, *shape) or None)."""
     lib = load()
@@ -236,7 +238,7 @@ def flow(p0: torch.Tensor, energy: EnergySpec, gamma: float, tau: float, n_steps
     pT = torch.empty_like(p0) if out is None else _field(out, shape, "out")
     ck = torch.empty((n_steps,) + shape, dtype=torch.float32, device=p0.device) if checkpoints else None
     g = make_grid(shape)
-    prm = make_params(gamma, tau, max_iters, tol, check_every, precision, absorb_threshold)
+    prm = make_params(gamma, tau, max_iters, tol, check_every, precision, absorb_threshold, resident)
     e = energy.to_c(shape)
     nb = lib.jko_workspace_bytes(ctypes.byref(g), ctypes.byref(prm), OP_FLOW, n_steps)
     ws = _workspace(nb, p0.device)
@@ -248,7 +250,7 @@ def flow(p0: torch.Tensor, energy: EnergySpec, gamma: float, tau: float, n_steps
 
 def backward(checkpoints: torch.Tensor, iters_per_step: Sequence[int], dL_dpT: torch.Tensor,
              energy: EnergySpec, gamma: float, tau: float, precision: str = "fp32",
-             want_w: bool = True, want_p0: bool = True):
+             want_w: bool = True, want_p0: bool = True, resident: bool = True):
     """Gradients (dL/dw or None, dL/dp0 or None) of L(p_T) through the flow
     recorded in `checkpoints` at the given iteration counts."""
     lib = load()
@@ -259,7 +261,7 @@ def backward(checkpoints: torch.Tensor, iters_per_step: Sequence[int], dL_dpT: t
     _field(dL_dpT, shape, "dL_dpT")
     iters = (ctypes.c_int32 * n_steps)(*[int(k) for k in iters_per_step])
     g = make_grid(shape)
-    prm = make_params(gamma, tau, max(iters_per_step), 0.0, 1, precision)
+    prm = make_params(gamma, tau, max(iters_per_step), 0.0, 1, precision, resident=resident)
     e = energy.to_c(shape)
     nb = lib.jko_workspace_bytes(ctypes.byref(g), ctypes.byref(prm), OP_BACKWARD, max(iters_per_step))
     ws = _workspace(nb, dL_dpT.device)
@@ -272,14 +274,15 @@ def backward(checkpoints: torch.Tensor, iters_per_step: Sequence[int], dL_dpT: t
 
 
 def time_iteration(p: torch.Tensor, energy: EnergySpec, gamma: float, tau: float,
-                   precision: str = "fp32", reps: int = 50):
-    """Mean duration (ms) of each kernel launch of one iteration, in launch
-    order, timed with HIP events on the current stream (measurement aid)."""
+                   precision: str = "fp32", reps: int = 50, iters: int = 1, resident: bool = True):
+    """Mean duration (ms) of each kernel launch, in launch order, timed with
+    HIP events on the current stream (measurement aid): the launches of one
+    iteration, or the one resident launch running `iters` iterations."""
     lib = load()
     shape = tuple(p.shape)
     _field(p, shape, "p")
     g = make_grid(shape)
-    prm = make_params(gamma, tau, 1, 0.0, 1, precision)
+    prm = make_params(gamma, tau, iters, 0.0, 1, precision, resident=resident)
     e = energy.to_c(shape)
     nb = lib.jko_workspace_bytes(ctypes.byref(g), ctypes.byref(prm), OP_STEP, 0)
     ws = _workspace(nb, p.device)

@@ -44,6 +44,9 @@ jko_status fail(jko_status st, const char* fmt, ...) {
 
 constexpr int kMaxN = 1024;
 constexpr size_t kAlign = 256;
+// Polls of one grid-barrier wait of the resident kernel before it gives up
+// (each poll sleeps ~64 cycles: far beyond any legitimate wait).
+constexpr int kBarrierSpinLimit = 1 << 22;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -95,7 +98,7 @@ Pass make_pass(const PassShape& ps) {
 enum : int { OP_GIBBS = 0, OP_STEP = 1, OP_FLOW = 2, OP_BACKWARD = 3 };
 
 struct Layout {
-    size_t ctl = 0, hostout = 0, part = 0, factors = 0, fields = 0, hist = 0, stats = 0, total = 0;
+    size_t ctl = 0, sync = 0, hostout = 0, part = 0, factors = 0, fields = 0, hist = 0, stats = 0, total = 0;
     int part_cap = 0;
     size_t factor_off[3] = {0, 0, 0};
     int nfields = 0;
@@ -117,6 +120,8 @@ Layout layout_of(const Geo& g, int op, int64_t iters_or_steps) {
     size_t off = 0;
     L.ctl = off;
     off += align_up(sizeof(Ctl));
+    L.sync = off;
+    off += align_up(4 * (size_t)resident_sync_words(kFusedMaxBlocks));
     L.hostout = off;
     off += align_up(8 * sizeof(double));
     L.part_cap = part_cap_of(g);
@@ -162,6 +167,7 @@ struct Plan {
     Layout L;
     char* base = nullptr;
     Ctl* ctl = nullptr;
+    uint32_t* sync = nullptr;
     double* hostout = nullptr;
     Partials part{};
     const float* K1[3] = {};
@@ -172,6 +178,7 @@ struct Plan {
     int prec = 0;
     int W[3] = {0, 0, 0};        // float32 band half-widths of the factors
     bool fused2d = false;        // 2D applications use the fused band kernel
+    bool resident = false;       // ... and a step may run in one resident launch
 
     float* F(int i) const { return field[i]; }
     float* hist(int64_t i) const {
@@ -192,6 +199,7 @@ jko_status carve(Plan* P, const Geo& g, int op, int64_t extra, void* ws, size_t 
     if (((uintptr_t)ws) % 16 != 0) return fail(JKO_ERR_WORKSPACE, "workspace must be 16-byte aligned");
     P->base = static_cast<char*>(ws);
     P->ctl = reinterpret_cast<Ctl*>(P->base + P->L.ctl);
+    P->sync = reinterpret_cast<uint32_t*>(P->base + P->L.sync);
     P->hostout = reinterpret_cast<double*>(P->base + P->L.hostout);
     double* pd = reinterpret_cast<double*>(P->base + P->L.part);
     const int cap = P->L.part_cap;
@@ -218,6 +226,7 @@ jko_status build_factors(Plan& P, double gamma) {
     // application: it wins while its grid is at most one block per CU.
     P.fused2d = P.g.d == 2 && P.prec == JKO_FP32 && gibbs2d_fits(P.g.n[0], P.g.n[1], P.W[0], P.W[1]) &&
                 gibbs2d_blocks(P.g.n[0], P.g.n[1]) <= kFusedMaxBlocks;
+    P.resident = P.fused2d;
     for (int k = 0; k < P.g.d; ++k) {
         bool done = false;
         for (int j = 0; j < k; ++j)
@@ -319,6 +328,7 @@ jko_status check_params(const jko_params* pr) {
     if (pr->precision != JKO_FP32 && pr->precision != JKO_SPLIT_BF16)
         return fail(JKO_ERR_INVALID, "unknown precision %d", pr->precision);
     if (isnan(pr->tol_l1)) return fail(JKO_ERR_INVALID, "tol_l1 is NaN");
+    if (pr->flags & ~JKO_FLAG_NO_RESIDENT) return fail(JKO_ERR_INVALID, "unknown flags 0x%x", pr->flags);
     return JKO_OK;
 }
 
@@ -390,6 +400,59 @@ jko_status input_check(const Plan& P, const jko_energy* en, const float* p) {
     return JKO_OK;
 }
 
+// ----------------------------------------------------------------- resident
+
+bool use_resident(const Plan& P, const jko_params* pr, const ProxArgs& px) {
+    return P.resident && !(pr->flags & JKO_FLAG_NO_RESIDENT) && resident2d_fits(P.g.n[0], P.g.n[1], P.W[0], P.W[1], px.kind);
+}
+
+// Queue the resident kernel for K iterations of a step (scalings and control
+// block already initialised).
+jko_status launch_resident(const Plan& P, const float* q, float* p_out, const ProxArgs& px, int K, int ce,
+                           bool checks, double tol, double absorb, bool record_hist) {
+    Resident2D r{};
+    r.B = Band2D{P.g.n[0], P.g.n[1], P.W[0], P.W[1], P.K1[0], P.K1[1], nullptr};
+    r.q = q;
+    r.a = P.F(F_A);
+    r.b = P.F(F_B);
+    r.p_out = p_out;
+    r.hist = record_hist ? P.hist(0) : nullptr;
+    r.hist_stride = record_hist ? (int64_t)(P.hist(1) - P.hist(0)) : 0;
+    r.prox = px;
+    r.part = P.part;
+    r.ctl = P.ctl;
+    r.sync = P.sync;
+    r.K = K;
+    r.ce = ce;
+    r.checks = checks ? 1 : 0;
+    r.tol = tol;
+    r.absorb = absorb;
+    r.spin_limit = kBarrierSpinLimit;
+    EpiArgs al{};
+    al.q = q;
+    al.b = r.b;
+    al.a = r.a;
+    al.p_out = p_out;
+    al.prox = px;
+    al.t_out = r.hist;
+    set_vec(al);
+    r.vec_ok = al.vec_ok && (r.hist_stride % 4 == 0);
+    HIP_TRY(launch_fill(reinterpret_cast<float*>(P.sync), 0.f,
+                        resident_sync_words(gibbs2d_blocks(P.g.n[0], P.g.n[1])), P.st));
+    HIP_TRY(launch_resident2d(r, P.st));
+    return JKO_OK;
+}
+
+// Synchronous: fails if a wait of the last resident launch ran out.
+jko_status resident_check(const Plan& P) {
+    uint32_t w = 0;
+    HIP_TRY(hipMemcpyAsync(g_rb.host, P.sync, sizeof w, hipMemcpyDeviceToHost, P.st));
+    HIP_TRY(hipStreamSynchronize(P.st));
+    memcpy(&w, g_rb.host, sizeof w);
+    if (w) return fail(JKO_ERR_HIP, "resident kernel: a wait for another block timed out");
+    return JKO_OK;
+}
+
 // ----------------------------------------------------------------- one step
 
 struct StepOut {
@@ -433,10 +496,17 @@ jko_status run_step(const Plan& P, const jko_params* pr, const ProxArgs& px, con
     ep.part = P.part;
     ep.ctl = P.ctl;
 
+    const bool resident = use_resident(P, pr, px);
+    if (resident) {
+        jko_status s = launch_resident(P, q, p_out, px, K, ce, checks, pr->tol_l1, absorb, record_hist);
+        if (s) return s;
+        if ((s = resident_check(P))) return s;
+    }
+
     bool pending = false;   // a read-back of the control block is in flight
     bool stopped = false;
     int nb = 0;
-    for (int k = 1; k <= K; ++k) {
+    for (int k = 1; k <= (resident ? 0 : K); ++k) {
         eb.check = (checks && k > 1 && (k - 1) % ce == 0) ? 1 : 0;
         eb.t_out = record_hist ? P.hist(2 * (int64_t)(k - 1)) : nullptr;
         jko_status s = apply_xi(P, a, eb, &nb);
@@ -672,7 +742,24 @@ jko_status jko_time_iteration(const jko_grid* grid, const jko_energy* energy, co
         return JKO_OK;
     };
     int slot = 0;
-    if (P.fused2d) {
+    if (use_resident(P, params, px)) {
+        // one launch of the resident kernel running max_iters iterations
+        if ((s = readback_init())) return s;
+        double tot = 0.0;
+        for (int k = 0; k <= reps && !s; ++k) {   // k = 0: warm-up
+            HIP_TRY(launch_fill(a, 1.f, g.N, P.st));
+            HIP_TRY(launch_ctl_reset(P.ctl, 0, P.st));
+            HIP_TRY(hipEventRecord(e0, P.st));
+            s = launch_resident(P, p_in, P.F(F_Z1), px, params->max_iters, 1, false, 0.0, 0.0, false);
+            if (s) break;
+            HIP_TRY(hipEventRecord(e1, P.st));
+            if ((s = resident_check(P))) break;
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            if (k > 0) tot += ms;
+        }
+        ms_per_launch[slot++] = tot / reps;
+    } else if (P.fused2d) {
         // one launch per application
         s = timed([&]() { return apply_xi(P, a, eb, nullptr); }, &ms_per_launch[slot++]);
         if (!s) s = timed([&]() { return apply_xi(P, b, ep, nullptr); }, &ms_per_launch[slot++]);

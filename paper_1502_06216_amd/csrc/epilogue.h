@@ -143,6 +143,22 @@ __device__ __forceinline__ void st4(float* __restrict__ p, int idx, int cnt, boo
         if (e < cnt) p[idx + e] = v[e];
 }
 
+
+// Device-scope (coherent across XCDs) element stores and loads, for data one
+// block of the resident kernel writes and another reads within the launch.
+__device__ __forceinline__ void st4_coh(float* p, int idx, int cnt, f4 v) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        if (e < cnt) __hip_atomic_store(p + idx + e, v[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ f4 ld4_coh(const float* p, int idx, int cnt, float fill) {
+    f4 r;
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        r[e] = (e < cnt) ? __hip_atomic_load(p + idx + e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : fill;
+    return r;
+}
+
 template <int EK>
 __device__ __forceinline__ EpiIn epi_prefetch(const EpiArgs& E, int idx, int cnt) {
     EpiIn in;
@@ -173,7 +189,8 @@ __device__ __forceinline__ EpiIn epi_prefetch(const EpiArgs& E, int idx, int cnt
 //   MONITOR  err += |b t - q|
 //   PROX     s = v; p = prox(s); a = p / s; [p_out = p]       (0/0 = 0)
 // Log domain: the same with b, a held as log b, log a.
-template <int EK>
+// COH: b (b-update) and a (prox) are stored with device-scope stores.
+template <int EK, bool COH = false>
 __device__ __forceinline__ void epi_apply(const EpiArgs& E, int idx, int cnt, f4 val, bool logx,
                                           const EpiIn& in, EpiAcc& acc) {
     if (cnt <= 0) return;
@@ -199,7 +216,8 @@ __device__ __forceinline__ void epi_apply(const EpiArgs& E, int idx, int cnt, f4
                 }
             }
         }
-        st4(E.b, idx, cnt, vec, bn);
+        if (COH) st4_coh(E.b, idx, cnt, bn);
+        else st4(E.b, idx, cnt, vec, bn);
         if (E.t_out) st4(E.t_out, idx, cnt, vec, val);
     } else if (EK == EK_MONITOR) {
 #pragma unroll
@@ -226,12 +244,15 @@ __device__ __forceinline__ void epi_apply(const EpiArgs& E, int idx, int cnt, f4
             }
             if (E.check && e < cnt) acc.mass += (double)pn[e];
         }
-        st4(E.a, idx, cnt, vec, an);
+        if (COH) st4_coh(E.a, idx, cnt, an);
+        else st4(E.a, idx, cnt, vec, an);
         if (E.write_p) st4(E.p_out, idx, cnt, vec, pn);
         if (E.s_out) st4(E.s_out, idx, cnt, vec, val);
     }
 }
 
+// COH: the partials are stored with device-scope stores.
+template <bool COH = false>
 __device__ __forceinline__ void epi_finish(const EpiArgs& E, const EpiAcc& acc, int slot, double* sh) {
     if (E.kind == EpiKind::STORE) return;
     const bool want_err = (E.kind == EpiKind::MONITOR) || (E.kind == EpiKind::BUPDATE && E.check);
@@ -240,16 +261,26 @@ __device__ __forceinline__ void epi_finish(const EpiArgs& E, const EpiAcc& acc, 
         const double e = block_sum(acc.err, sh);
         const double mb = block_max(acc.maxlb, sh);
         if (threadIdx.x == 0) {
-            E.part.err[slot] = e;
-            E.part.maxlogb[slot] = mb;
+            if (COH) {
+                __hip_atomic_store(E.part.err + slot, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(E.part.maxlogb + slot, mb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                E.part.err[slot] = e;
+                E.part.maxlogb[slot] = mb;
+            }
         }
     }
     if (want_pm) {
         const double ms = block_sum(acc.mass, sh);
         const double ma = block_max(acc.maxla, sh);
         if (threadIdx.x == 0) {
-            E.part.mass[slot] = ms;
-            E.part.maxloga[slot] = ma;
+            if (COH) {
+                __hip_atomic_store(E.part.mass + slot, ms, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(E.part.maxloga + slot, ma, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                E.part.mass[slot] = ms;
+                E.part.maxloga[slot] = ma;
+            }
         }
     }
 }

@@ -1,4 +1,5 @@
-// Fused 2D Gibbs application  Y = K1_0 X K1_1  on MFMA (gfx950), one launch.
+// Fused 2D Gibbs application  Y = K1_0 X K1_1  on MFMA (gfx950), and the
+// resident 2D kernel that runs a whole step's iteration in one launch.
 //
 // On a uniform 2D grid xi = K1_0 (x) K1_1 (separable Gaussian, Section 4.1 of
 // the paper).  In float32 the factor K1[i][j] = exp(-(x_i - x_j)^2/gamma) is
@@ -15,8 +16,18 @@
 // are shifted by their maximum over the halo before the first contraction, Z
 // is carried to the second in log form and re-shifted per output column, so
 // each shift is local to the band around the outputs it serves.
+//
+// Resident kernel: when every tile's block fits on the chip at once, the
+// iteration of a step (3.2: t = xi^T a, b = q / t, s = xi b, a = prox(s) / s,
+// the stop test and the absorption switch) runs in one cooperative launch.
+// Each block keeps its factor bands and its tile's epilogue inputs on chip
+// and, between applications, waits only for the blocks whose tiles its halo
+// reaches; the stop test is evaluated by every block from the same partials
+// in the same order, so all blocks take the same decision.  Results are
+// bit-identical to the launch-per-application path.
 #include <algorithm>
 
+#include "control.h"
 #include "epilogue.h"
 
 namespace jko {
@@ -26,152 +37,190 @@ namespace {
 constexpr int kT = 16;          // output tile edge
 constexpr int kHalo = 128;      // largest halo edge held in LDS
 constexpr int kS = kHalo + 4;   // padded LDS row (floats)
+constexpr int kThr = 512;       // 8 waves per block
+constexpr int kMaxNeighbours = 9 * 9;   // halo reach of at most 4 tiles per side
 
-__device__ __forceinline__ int64_t xcd_block() {
-    const int64_t nb = gridDim.x, bid = blockIdx.x;
+struct Smem {
+    float Xs[kHalo * kS];   // [ib][jb]
+    float Kj[kT * kS];      // [j][jb]  = K1_1[j0+j][jb0+jb]
+    float Ki[kT * kS];      // [i][ib]  = K1_0[i0+i][ib0+ib]
+    float Zs[kT * kS];      // [j][ib]
+    float red[7 * 64 * 4];
+    float sh1[kHalo];       // log domain: row shifts of the halo
+    float sh2[kT];          // log domain: column shifts of Z
+    double shd[8];
+};
+
+__device__ __forceinline__ int xcd_block() {
+    const int nb = gridDim.x, bid = blockIdx.x;
     if (nb % 8 != 0) return bid;
     return (bid % 8) * (nb / 8) + bid / 8;
 }
 
-constexpr int kThr = 512;   // 8 waves per block
+// Geometry of one block's tile.  The halo start is aligned down to a
+// multiple of 4 (the extra entries meet exact zeros of the band).
+struct Tile {
+    int i0, j0, ib0, jb0, LI, LJ, LIp, LJp;
+    int obase, ocnt;   // wave 0: this lane's run of outputs (i = lane & 15, j = 4 (lane >> 4) + e)
+};
 
-template <int EK>
-__global__ void __launch_bounds__(kThr)
-gibbs2d_f32(Band2D B, EpiArgs E) {
-    __shared__ __attribute__((aligned(16))) float Xs[kHalo * kS];   // [ib][jb]
-    __shared__ __attribute__((aligned(16))) float Kj[kT * kS];      // [j][jb]  = K1_1[j0+j][jb0+jb]
-    __shared__ __attribute__((aligned(16))) float Ki[kT * kS];      // [i][ib]  = K1_0[i0+i][ib0+ib]
-    __shared__ __attribute__((aligned(16))) float Zs[kT * kS];      // [j][ib]
-    __shared__ float red[7 * 64 * 4];
-    __shared__ float sh1[kHalo];     // log domain: row shifts of the halo
-    __shared__ float sh2[kT];        // log domain: column shifts of Z
-    __shared__ double shd[8];
-
-    // The control flags are read here but acted on only after the halo loads
-    // are in flight, so their latencies overlap.
-    int done = 0, lmode = 0;
-    if (E.ctl) {
-        done = E.ctl->done;
-        lmode = E.ctl->logmode;
-    }
-
-    const int n0 = B.n0, n1 = B.n1;
-    const int tiles_j = (n1 + kT - 1) / kT;
-    const int64_t logical = xcd_block();
-    const int i0 = (int)(logical / tiles_j) * kT;
-    const int j0 = (int)(logical % tiles_j) * kT;
-    // halo, start aligned down to a multiple of 4 (the extra entries meet
-    // exact zeros of the band)
-    const int ib0 = max(0, i0 - B.W0) & ~3;
-    const int ib1 = min(n0, i0 + kT + B.W0);
-    const int jb0 = max(0, j0 - B.W1) & ~3;
-    const int jb1 = min(n1, j0 + kT + B.W1);
-    const int LI = ib1 - ib0, LJ = jb1 - jb0;
-    const int LIp = (LI + 15) & ~15, LJp = (LJ + 15) & ~15;
-
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const bool vec1 = (n1 & 3) == 0, vec0 = (n0 & 3) == 0;
-
-    // Wave 0 finishes the tile: lane (i = lane & 15, j = 4 (lane >> 4) + e).
-    // Its epilogue inputs are fetched now, ahead of the contraction.
+__device__ __forceinline__ Tile tile_of(const Band2D& B, int logical, int lane) {
+    Tile T;
+    const int tiles_j = (B.n1 + kT - 1) / kT;
+    T.i0 = (logical / tiles_j) * kT;
+    T.j0 = (logical % tiles_j) * kT;
+    T.ib0 = max(0, T.i0 - B.W0) & ~3;
+    T.jb0 = max(0, T.j0 - B.W1) & ~3;
+    T.LI = min(B.n0, T.i0 + kT + B.W0) - T.ib0;
+    T.LJ = min(B.n1, T.j0 + kT + B.W1) - T.jb0;
+    T.LIp = (T.LI + 15) & ~15;
+    T.LJp = (T.LJ + 15) & ~15;
     const int koff = 4 * (lane >> 4);
-    const int oi = i0 + (lane & 15);
-    const int obase = oi * n1 + j0 + koff;
-    const int ocnt = (oi < n0) ? max(0, min(4, n1 - (j0 + koff))) : 0;
-    EpiIn ein;
-    if (wave == 0) ein = epi_prefetch<EK>(E, obase, ocnt);
+    const int oi = T.i0 + (lane & 15);
+    T.obase = oi * B.n1 + T.j0 + koff;
+    T.ocnt = (oi < B.n0) ? max(0, min(4, B.n1 - (T.j0 + koff))) : 0;
+    return T;
+}
 
-    // ---- stage the halo of X and the two factor bands: every load is issued
-    // before the first LDS store
-    constexpr int UXM = kHalo * (kHalo / 4) / kThr;     // max halo units per thread
-    constexpr int UKM = kT * (kHalo / 4) / kThr;        // max factor units per thread
-    const int nux = LIp * (LJp / 4), nkj = kT * (LJp / 4), nki = kT * (LIp / 4);
-    f4 bx[UXM], bj[UKM], bi[UKM];
+constexpr int UXM = kHalo * (kHalo / 4) / kThr;   // max halo units per thread
+constexpr int UKM = kT * (kHalo / 4) / kThr;      // max factor units per thread
+
+// Issue the loads of the X halo (zero outside the grid).  COH: device-scope
+// loads (buffer loads with scope bit SC1, range-checked by the descriptor) of
+// a field other blocks of the same launch wrote.
+constexpr int kCpolDevice = 16;   // SC1: device scope
+
+template <bool COH = false>
+__device__ __forceinline__ void load_halo(const Band2D& B, const Tile& T, f4 (&bx)[UXM]) {
+    const int tid = threadIdx.x;
+    const int nux = T.LIp * (T.LJp / 4);
+    const bool vec1 = (B.n1 & 3) == 0;
+    __amdgpu_buffer_rsrc_t rs;
+    if (COH)
+        rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(B.X), (short)0, B.n0 * B.n1 * 4, 0x00020000);
 #pragma unroll
     for (int u = 0; u < UXM; ++u) {
         const int unit = tid + u * kThr;
         f4 v = f4{0.f, 0.f, 0.f, 0.f};
         if (unit < nux) {
-            const int r = unit / (LJp / 4), c = 4 * (unit % (LJp / 4));
-            if (r < LI) {
-                const float* src = B.X + (int64_t)(ib0 + r) * n1 + jb0 + c;
-                if (vec1 && c + 3 < LJ) v = *reinterpret_cast<const f4*>(src);
-                else
+            const int r = unit / (T.LJp / 4), c = 4 * (unit % (T.LJp / 4));
+            if (r < T.LI) {
+                const int off = (T.ib0 + r) * B.n1 + T.jb0 + c;
+                if (COH) {
+                    if (vec1 && c + 3 < T.LJ)
+                        v = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(rs, 4 * off, 0, kCpolDevice));
+                    else
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) v[e] = (c + e < LJ) ? src[e] : 0.f;
+                        for (int e = 0; e < 4; ++e)
+                            v[e] = (c + e < T.LJ) ? __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                                                                  rs, 4 * (off + e), 0, kCpolDevice))
+                                                  : 0.f;
+                } else {
+                    const float* src = B.X + off;
+                    if (vec1 && c + 3 < T.LJ) v = *reinterpret_cast<const f4*>(src);
+                    else
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) v[e] = (c + e < T.LJ) ? src[e] : 0.f;
+                }
             }
         }
         bx[u] = v;
     }
+}
+
+__device__ __forceinline__ void store_halo(Smem& S, const Tile& T, const f4 (&bx)[UXM], bool logx) {
+    const int tid = threadIdx.x;
+    const int nux = T.LIp * (T.LJp / 4);
+#pragma unroll
+    for (int u = 0; u < UXM; ++u) {
+        const int unit = tid + u * kThr;
+        if (unit < nux) {
+            const int r = unit / (T.LJp / 4), c = 4 * (unit % (T.LJp / 4));
+            f4 v = bx[u];
+            if (logx)   // staged logs: cells outside the halo are exact zeros
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (r >= T.LI || c + e >= T.LJ) v[e] = -INFINITY;
+            *reinterpret_cast<f4*>(&S.Xs[r * kS + c]) = v;
+        }
+    }
+}
+
+// Issue the loads of the two factor bands of the tile.
+__device__ __forceinline__ void load_bands(const Band2D& B, const Tile& T, f4 (&bj)[UKM], f4 (&bi)[UKM]) {
+    const int tid = threadIdx.x;
+    const int nkj = kT * (T.LJp / 4), nki = kT * (T.LIp / 4);
+    const bool vec1 = (B.n1 & 3) == 0, vec0 = (B.n0 & 3) == 0;
 #pragma unroll
     for (int u = 0; u < UKM; ++u) {
         const int unit = tid + u * kThr;
         f4 v = f4{0.f, 0.f, 0.f, 0.f};
         if (unit < nkj) {
-            const int j = unit / (LJp / 4), c = 4 * (unit % (LJp / 4));
-            if (j0 + j < n1) {
-                const float* src = B.K1 + (int64_t)(j0 + j) * n1 + jb0 + c;
-                if (vec1 && c + 3 < LJ) v = *reinterpret_cast<const f4*>(src);
+            const int j = unit / (T.LJp / 4), c = 4 * (unit % (T.LJp / 4));
+            if (T.j0 + j < B.n1) {
+                const float* src = B.K1 + (int64_t)(T.j0 + j) * B.n1 + T.jb0 + c;
+                if (vec1 && c + 3 < T.LJ) v = *reinterpret_cast<const f4*>(src);
                 else
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) v[e] = (c + e < LJ) ? src[e] : 0.f;
+                    for (int e = 0; e < 4; ++e) v[e] = (c + e < T.LJ) ? src[e] : 0.f;
             }
         }
         bj[u] = v;
         f4 w = f4{0.f, 0.f, 0.f, 0.f};
         if (unit < nki) {
-            const int i = unit / (LIp / 4), c = 4 * (unit % (LIp / 4));
-            if (i0 + i < n0) {
-                const float* src = B.K0 + (int64_t)(i0 + i) * n0 + ib0 + c;
-                if (vec0 && c + 3 < LI) w = *reinterpret_cast<const f4*>(src);
+            const int i = unit / (T.LIp / 4), c = 4 * (unit % (T.LIp / 4));
+            if (T.i0 + i < B.n0) {
+                const float* src = B.K0 + (int64_t)(T.i0 + i) * B.n0 + T.ib0 + c;
+                if (vec0 && c + 3 < T.LI) w = *reinterpret_cast<const f4*>(src);
                 else
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) w[e] = (c + e < LI) ? src[e] : 0.f;
+                    for (int e = 0; e < 4; ++e) w[e] = (c + e < T.LI) ? src[e] : 0.f;
             }
         }
         bi[u] = w;
     }
-    const bool logx = lmode != 0;
-#pragma unroll
-    for (int u = 0; u < UXM; ++u) {
-        const int unit = tid + u * kThr;
-        if (unit < nux) {
-            const int r = unit / (LJp / 4), c = 4 * (unit % (LJp / 4));
-            f4 v = bx[u];
-            if (logx)   // staged logs: cells outside the halo are exact zeros
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    if (r >= LI || c + e >= LJ) v[e] = -INFINITY;
-            *reinterpret_cast<f4*>(&Xs[r * kS + c]) = v;
-        }
-    }
+}
+
+__device__ __forceinline__ void store_bands(Smem& S, const Tile& T, const f4 (&bj)[UKM], const f4 (&bi)[UKM]) {
+    const int tid = threadIdx.x;
+    const int nkj = kT * (T.LJp / 4), nki = kT * (T.LIp / 4);
 #pragma unroll
     for (int u = 0; u < UKM; ++u) {
         const int unit = tid + u * kThr;
         if (unit < nkj) {
-            const int j = unit / (LJp / 4), c = 4 * (unit % (LJp / 4));
-            *reinterpret_cast<f4*>(&Kj[j * kS + c]) = bj[u];
+            const int j = unit / (T.LJp / 4), c = 4 * (unit % (T.LJp / 4));
+            *reinterpret_cast<f4*>(&S.Kj[j * kS + c]) = bj[u];
         }
         if (unit < nki) {
-            const int i = unit / (LIp / 4), c = 4 * (unit % (LIp / 4));
-            *reinterpret_cast<f4*>(&Ki[i * kS + c]) = bi[u];
+            const int i = unit / (T.LIp / 4), c = 4 * (unit % (T.LIp / 4));
+            *reinterpret_cast<f4*>(&S.Ki[i * kS + c]) = bi[u];
         }
     }
-    if (done) return;   // the step has stopped: nothing to compute (uniform)
+}
+
+// Both contractions of the staged tile and its epilogue (wave 0), then the
+// block's partials into slot `slot`.  Xs, Kj, Ki are staged, not yet synced.
+// COH: the scalings and partials the epilogue writes use device-scope stores.
+template <int EK, bool COH = false>
+__device__ __forceinline__ void contract_tile(const EpiArgs& E, const Tile& T, const EpiIn& ein, bool logx,
+                                              Smem& S, int slot) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int koff = 4 * (lane >> 4);
+    const int LI = T.LI, LJ = T.LJ, LIp = T.LIp, LJp = T.LJp;
     __syncthreads();
 
     if (logx) {
         // row shifts over the halo, then exponentiate the staged logs
         for (int r = tid; r < LIp; r += kThr) {
             float m = -INFINITY;
-            for (int c = 0; c < LJ; ++c) m = fmaxf(m, Xs[r * kS + c]);
-            sh1[r] = (m == -INFINITY) ? NAN : m;
+            for (int c = 0; c < LJ; ++c) m = fmaxf(m, S.Xs[r * kS + c]);
+            S.sh1[r] = (m == -INFINITY) ? NAN : m;
         }
         __syncthreads();
         for (int u = tid; u < LIp * LJp; u += kThr) {
             const int r = u / LJp, c = u % LJp;
-            const float m = sh1[r];
-            Xs[r * kS + c] = (m == m) ? expf(Xs[r * kS + c] - m) : 0.f;
+            const float m = S.sh1[r];
+            S.Xs[r * kS + c] = (m == m) ? expf(S.Xs[r * kS + c] - m) : 0.f;
         }
         __syncthreads();
     }
@@ -182,8 +231,8 @@ gibbs2d_f32(Band2D B, EpiArgs E) {
     if (wave < F) {
         const int f = wave;
         f4 acc0 = f4{0.f, 0.f, 0.f, 0.f}, acc1 = f4{0.f, 0.f, 0.f, 0.f};
-        const float* xr = &Xs[(16 * f + (lane & 15)) * kS + koff];
-        const float* kr = &Kj[(lane & 15) * kS + koff];
+        const float* xr = &S.Xs[(16 * f + (lane & 15)) * kS + koff];
+        const float* kr = &S.Kj[(lane & 15) * kS + koff];
         int c0 = 0;
         for (; c0 + 16 < LJp; c0 += 32) {
             const f4 a0 = *reinterpret_cast<const f4*>(xr + c0);
@@ -207,11 +256,11 @@ gibbs2d_f32(Band2D B, EpiArgs E) {
         if (logx) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const float m = sh1[16 * f + koff + e];
+                const float m = S.sh1[16 * f + koff + e];
                 acc[e] = (m != m) ? -INFINITY : (acc[e] > 0.f ? m + logf(acc[e]) : m - 104.f);
             }
         }
-        *reinterpret_cast<f4*>(&Zs[(lane & 15) * kS + 16 * f + koff]) = acc;
+        *reinterpret_cast<f4*>(&S.Zs[(lane & 15) * kS + 16 * f + koff]) = acc;
     }
     __syncthreads();
 
@@ -219,14 +268,14 @@ gibbs2d_f32(Band2D B, EpiArgs E) {
         // column shifts of Z over the valid halo rows, then exponentiate
         if (tid < kT) {
             float m = -INFINITY;
-            for (int r = 0; r < LI; ++r) m = fmaxf(m, Zs[tid * kS + r]);
-            sh2[tid] = (m == -INFINITY) ? NAN : m;
+            for (int r = 0; r < LI; ++r) m = fmaxf(m, S.Zs[tid * kS + r]);
+            S.sh2[tid] = (m == -INFINITY) ? NAN : m;
         }
         __syncthreads();
         for (int u = tid; u < kT * LIp; u += kThr) {
             const int j = u / LIp, r = u % LIp;
-            const float m = sh2[j];
-            Zs[j * kS + r] = (m == m && r < LI) ? expf(Zs[j * kS + r] - m) : 0.f;
+            const float m = S.sh2[j];
+            S.Zs[j * kS + r] = (m == m && r < LI) ? expf(S.Zs[j * kS + r] - m) : 0.f;
         }
         __syncthreads();
     }
@@ -236,28 +285,265 @@ gibbs2d_f32(Band2D B, EpiArgs E) {
     f4 acc = f4{0.f, 0.f, 0.f, 0.f};
     if (16 * wave < LIp) {
         const int c0 = 16 * wave;
-        const f4 a = *reinterpret_cast<const f4*>(&Zs[(lane & 15) * kS + c0 + koff]);
-        const f4 b = *reinterpret_cast<const f4*>(&Ki[(lane & 15) * kS + c0 + koff]);
+        const f4 a = *reinterpret_cast<const f4*>(&S.Zs[(lane & 15) * kS + c0 + koff]);
+        const f4 b = *reinterpret_cast<const f4*>(&S.Ki[(lane & 15) * kS + c0 + koff]);
 #pragma unroll
         for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b[s], acc, 0, 0, 0);
     }
-    if (wave > 0) *reinterpret_cast<f4*>(&red[((wave - 1) * 64 + lane) * 4]) = acc;
+    if (wave > 0) *reinterpret_cast<f4*>(&S.red[((wave - 1) * 64 + lane) * 4]) = acc;
     __syncthreads();
     EpiAcc ea;
     if (wave == 0) {
 #pragma unroll
-        for (int w = 0; w < 7; ++w) acc += *reinterpret_cast<const f4*>(&red[(w * 64 + lane) * 4]);
+        for (int w = 0; w < 7; ++w) acc += *reinterpret_cast<const f4*>(&S.red[(w * 64 + lane) * 4]);
         // acc holds Y[i = i0 + (lane & 15)][j = j0 + koff + e]
         if (logx) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const float m = sh2[koff + e];
+                const float m = S.sh2[koff + e];
                 acc[e] = (m != m) ? -INFINITY : (acc[e] > 0.f ? m + logf(acc[e]) : m - 104.f);
             }
         }
-        epi_apply<EK>(E, obase, ocnt, acc, logx, ein, ea);
+        epi_apply<EK, COH>(E, T.obase, T.ocnt, acc, logx, ein, ea);
     }
-    epi_finish(E, ea, (int)blockIdx.x, shd);
+    epi_finish<COH>(E, ea, slot, S.shd);
+}
+
+template <int EK>
+__global__ void __launch_bounds__(kThr)
+gibbs2d_f32(Band2D B, EpiArgs E) {
+    __shared__ __attribute__((aligned(16))) Smem S;
+
+    // The control flags are read here but acted on only after the halo loads
+    // are in flight, so their latencies overlap.
+    int done = 0, lmode = 0;
+    if (E.ctl) {
+        done = E.ctl->done;
+        lmode = E.ctl->logmode;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const Tile T = tile_of(B, xcd_block(), lane);
+
+    // Wave 0 finishes the tile; its epilogue inputs are fetched now, ahead of
+    // the contraction.
+    EpiIn ein;
+    if (wave == 0) ein = epi_prefetch<EK>(E, T.obase, T.ocnt);
+
+    // every staging load is issued before the first LDS store
+    f4 bx[UXM], bj[UKM], bi[UKM];
+    load_halo(B, T, bx);
+    load_bands(B, T, bj, bi);
+    store_halo(S, T, bx, lmode != 0);
+    store_bands(S, T, bj, bi);
+    if (done) return;   // the step has stopped: nothing to compute (uniform)
+    contract_tile<EK>(E, T, ein, lmode != 0, S, (int)blockIdx.x);
+}
+
+// ------------------------------------------------------------ resident kernel
+//
+// Synchronisation without atomics read-modify-write and without cache-wide
+// fences: every value one block writes for another (a, b, the partials) is
+// stored and loaded at device scope, which is coherent across the XCDs'
+// separate L2s.  After a phase's stores have completed (s_waitcnt), block t
+// publishes its phase count in flags[t]; before a phase that reads other
+// blocks' values, a block waits until each block it reads from has published
+// at least its own count.  Tiles only read the tiles within their halo, so
+// most phases wait on those neighbours only (the relation is symmetric, which
+// also keeps a block from overwriting values a neighbour is still reading);
+// a stop-test check waits on every block, twice (partials written; partials
+// read).  Each wait polls a bounded number of times; one that runs out raises
+// the abort word, which every waiting block also polls, so every wave ends.
+
+// Sync region layout (uint32 words): [0] abort, flags[t] at kFlag0 + kFlagStride * t.
+constexpr int kFlag0 = 64;
+constexpr int kFlagStride = 16;   // one 64-byte line per block
+
+__device__ __forceinline__ uint32_t* flag_of(uint32_t* sync, int t) { return sync + kFlag0 + kFlagStride * t; }
+
+// All stores of this block completed, then publish `count` for it.
+__device__ __forceinline__ void publish(uint32_t* sync, int slot, uint32_t count) {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(flag_of(sync, slot), count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until blocks list[0 .. n) (one per thread) have published >= count.
+// Returns false (in every thread) if the wait ran out or another block aborted.
+__device__ __forceinline__ bool wait_for(uint32_t* sync, int n, const int* list, uint32_t count, int spin_limit) {
+    int ok = 1;
+    const int t = threadIdx.x;
+    if (t < n) {
+        const uint32_t* f = flag_of(sync, list[t]);
+        for (int spins = 0; __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < count; ++spins) {
+            if ((spins & 31) == 31 &&
+                __hip_atomic_load(sync, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                ok = 0;
+                break;
+            }
+            if (spins >= spin_limit) {
+                __hip_atomic_store(sync, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    return __syncthreads_and(ok) != 0;
+}
+
+template <int PK>
+__global__ void __launch_bounds__(kThr)
+resident2d(Resident2D R) {
+    __shared__ __attribute__((aligned(16))) Smem S;
+    __shared__ Ctl C;                // this block's copy of the control state
+    __shared__ int nbr[kMaxNeighbours];
+    __shared__ int all[kFusedMaxBlocks];
+    __shared__ int n_nbr;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nb = (int)gridDim.x;
+    const int slot = (int)blockIdx.x;
+    Band2D B = R.B;
+    const int logical = xcd_block();
+    const Tile T = tile_of(B, logical, lane);
+
+    // the blocks whose tiles lie within this tile's halo reach (and itself)
+    if (tid == 0) {
+        const int tiles_i = (B.n0 + kT - 1) / kT, tiles_j = (B.n1 + kT - 1) / kT;
+        const int ri = (B.W0 + 3 + kT - 1) / kT, rj = (B.W1 + 3 + kT - 1) / kT;
+        const int ti = logical / tiles_j, tj = logical % tiles_j;
+        int m = 0;
+        for (int a = max(0, ti - ri); a <= min(tiles_i - 1, ti + ri); ++a)
+            for (int b = max(0, tj - rj); b <= min(tiles_j - 1, tj + rj); ++b) {
+                const int lg = a * tiles_j + b;   // logical tile -> block index (inverse of xcd_block)
+                nbr[m++] = (nb % 8 != 0) ? lg : (lg % (nb / 8)) * 8 + lg / (nb / 8);
+            }
+        n_nbr = m;
+        C = *R.ctl;
+    }
+    for (int t = tid; t < nb; t += kThr) all[t] = t;
+
+    EpiArgs eb{};
+    eb.kind = EpiKind::BUPDATE;
+    eb.q = R.q;
+    eb.b = R.b;
+    eb.vec_ok = R.vec_ok;
+    eb.part = R.part;
+    EpiArgs ep{};
+    ep.kind = EpiKind::PROX;
+    ep.a = R.a;
+    ep.p_out = R.p_out;
+    ep.prox = R.prox;
+    ep.vec_ok = R.vec_ok;
+    ep.part = R.part;
+
+    // factor bands: staged once for the whole launch
+    {
+        f4 bj[UKM], bi[UKM];
+        load_bands(B, T, bj, bi);
+        store_bands(S, T, bj, bi);
+    }
+    // epilogue inputs that do not change over the iteration (q; the energy's fields)
+    EpiIn inq, inp;
+    if (wave == 0) {
+        inq = epi_prefetch<EK_BUPDATE>(eb, T.obase, T.ocnt);
+        inp = epi_prefetch<PK>(ep, T.obase, T.ocnt);
+    }
+    __syncthreads();
+    const int nn = n_nbr;
+    int lmode = C.logmode;
+    uint32_t count = 0;   // phases this block has published
+
+    for (int k = 1; k <= R.K; ++k) {
+        // ---- t = xi^T a, b = q / t (and the violation of the previous iterate at checks)
+        const bool chk = R.checks && k > 1 && (k - 1) % R.ce == 0;
+        eb.check = chk ? 1 : 0;
+        eb.t_out = R.hist ? R.hist + (2 * (int64_t)(k - 1)) * R.hist_stride : nullptr;
+        EpiIn ia = inq;
+        if (chk && wave == 0) ia.v = ld4_coh(R.b, T.obase, T.ocnt, 0.f);
+        if (!wait_for(R.sync, nn, nbr, count, R.spin_limit)) return;
+        {
+            B.X = R.a;
+            f4 bx[UXM];
+            load_halo<true>(B, T, bx);
+            store_halo(S, T, bx, lmode != 0);
+        }
+        contract_tile<EK_BUPDATE, true>(eb, T, ia, lmode != 0, S, slot);
+        publish(R.sync, slot, ++count);
+
+        if (chk) {
+            // every block's partials are in: the same decision everywhere
+            if (!wait_for(R.sync, nb, all, count, R.spin_limit)) return;
+            if (wave == 0) ctl_update<true>(&C, R.part, nb, k, R.tol, 1, R.absorb);
+            __syncthreads();
+            if (slot == 0 && tid == 0) {
+                Ctl* g = R.ctl;
+                g->done = C.done;
+                g->stop_iter = C.stop_iter;
+                g->nonfinite = C.nonfinite;
+                g->absorptions = C.absorptions;
+                g->absorb_pending = C.absorb_pending;
+                g->logmode = C.logmode;
+                g->err = C.err;
+                g->mass = C.mass;
+                g->maxloga = C.maxloga;
+                g->maxlogb = C.maxlogb;
+            }
+            if (C.done) return;
+            // every block has read the partials before any block rewrites them
+            publish(R.sync, slot, ++count);
+            if (!wait_for(R.sync, nb, all, count, R.spin_limit)) return;
+            if (C.absorb_pending) {
+                // a <- log a, b <- log b on this block's own tile
+                if (tid < kT * kT) {
+                    const int i = T.i0 + tid / kT, j = T.j0 + tid % kT;
+                    if (i < B.n0 && j < B.n1) {
+                        float* pa = R.a + (int64_t)i * B.n1 + j;
+                        float* pb = R.b + (int64_t)i * B.n1 + j;
+                        const float av = __hip_atomic_load(pa, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        const float bv = __hip_atomic_load(pb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(pa, av > 0.f ? logf(av) : -INFINITY, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(pb, bv > 0.f ? logf(bv) : -INFINITY, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                }
+                lmode = 1;
+                publish(R.sync, slot, ++count);
+            }
+        }
+
+        // ---- s = xi b, p = prox(s), a = p / s (p kept at candidate iterations)
+        const bool cand = (R.checks && k % R.ce == 0) || k == R.K;
+        ep.check = cand ? 1 : 0;
+        ep.write_p = cand ? 1 : 0;
+        ep.s_out = R.hist ? R.hist + (2 * (int64_t)(k - 1) + 1) * R.hist_stride : nullptr;
+        if (!wait_for(R.sync, nn, nbr, count, R.spin_limit)) return;
+        {
+            B.X = R.b;
+            f4 bx[UXM];
+            load_halo<true>(B, T, bx);
+            store_halo(S, T, bx, lmode != 0);
+        }
+        contract_tile<PK, true>(ep, T, inp, lmode != 0, S, slot);
+        publish(R.sync, slot, ++count);
+    }
+}
+
+template <int PK>
+const void* resident_fn() {
+    return reinterpret_cast<const void*>(&resident2d<PK>);
+}
+
+const void* resident_kernel(int prox_kind) {
+    switch (prox_kind) {
+        case JKO_F_ZERO: return resident_fn<EK_PROX + JKO_F_ZERO>();
+        case JKO_F_CONGESTION: return resident_fn<EK_PROX + JKO_F_CONGESTION>();
+        case JKO_F_POROUS: return resident_fn<EK_PROX + JKO_F_POROUS>();
+        default: return resident_fn<EK_PROX + JKO_F_ENTROPY>();
+    }
 }
 
 }  // namespace
@@ -299,6 +585,28 @@ hipError_t launch_gibbs2d(const Band2D& b, int32_t precision, const EpiArgs& epi
         default: hipLaunchKernelGGL(gibbs2d_f32<EK_PROX + JKO_F_ENTROPY>, grid, block, 0, stream, b, epi); break;
     }
     return hipGetLastError();
+}
+
+bool resident2d_fits(int n0, int n1, int W0, int W1, int prox_kind) {
+    const int ti = (n0 + kT - 1) / kT, tj = (n1 + kT - 1) / kT;
+    const int ri = (W0 + 3 + kT - 1) / kT, rj = (W1 + 3 + kT - 1) / kT;
+    if ((int64_t)std::min(ti, 2 * ri + 1) * std::min(tj, 2 * rj + 1) > kMaxNeighbours) return false;
+    if (gibbs2d_blocks(n0, n1) > kFusedMaxBlocks) return false;
+    int dev = 0, coop = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return false;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return false;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, resident_kernel(prox_kind), kThr, 0) != hipSuccess)
+        return false;
+    return (int64_t)per_cu * cus >= gibbs2d_blocks(n0, n1);
+}
+
+hipError_t launch_resident2d(const Resident2D& r, hipStream_t stream) {
+    const int64_t nb = gibbs2d_blocks(r.B.n0, r.B.n1);
+    Resident2D arg = r;
+    void* args[] = {&arg};
+    return hipLaunchCooperativeKernel(resident_kernel(r.prox.kind), dim3((unsigned)nb), dim3(kThr), args, 0,
+                                      stream);
 }
 
 }  // namespace jko

@@ -11,9 +11,10 @@
 namespace jko {
 
 // ---------------------------------------------------------------------------
-// Device control block, one per workspace.  Written only by the single-block
-// control kernels; every iteration kernel reads `done` first and returns when
-// it is set, so that the host can queue iterations ahead of the stop test.
+// Device control block, one per workspace.  Written by the single-block
+// control kernels (or by block 0 of the resident 2D kernel); every iteration
+// kernel reads `done` first and returns when it is set, so that the host can
+// queue iterations ahead of the stop test.
 // ---------------------------------------------------------------------------
 struct Ctl {
     int32_t done;          // 1 once the stop test passed or a non-finite value was met
@@ -115,6 +116,38 @@ int64_t gibbs2d_blocks(int n0, int n1);
 constexpr int64_t kFusedMaxBlocks = 256;   // one block per CU of the chip
 hipError_t launch_gibbs2d(const Band2D& b, int32_t precision, const EpiArgs& epi, int* nblocks,
                           hipStream_t stream);
+
+// Synchronisation words of the resident kernel (uint32): an abort word, then
+// one 64-byte line per block holding the count of phases it has published.
+constexpr int64_t resident_sync_words(int64_t nblocks) { return 64 + 16 * nblocks; }
+
+// One JKO step's iteration on a 2D grid in one cooperative launch (one block
+// per 16 x 16 output tile, all resident).  Same arithmetic, order of
+// operations, partials and control decisions as the launch-per-application
+// path with the fused 2D kernel.
+struct Resident2D {
+    Band2D B;              // geometry and factors (B.X unused)
+    const float* q;        // old density
+    float* a;              // scalings, in/out (a starts at 1, or 0 = log 1)
+    float* b;
+    float* p_out;          // density written at candidate iterations
+    float* hist;           // adjoint recomputation: t_k, s_k at hist + (2(k-1)) stride, +stride; or NULL
+    int64_t hist_stride;   // floats
+    ProxArgs prox;
+    Partials part;
+    Ctl* ctl;
+    uint32_t* sync;        // resident_sync_words(blocks), zeroed before the launch
+    int32_t K;             // iterations
+    int32_t ce;            // check cadence
+    int32_t checks;        // stop test / absorption checks on
+    int32_t vec_ok;        // all field pointers 16-byte aligned
+    int32_t spin_limit;    // polls before a barrier wait gives up
+    double tol;
+    double absorb;
+};
+// True when all blocks of the resident kernel fit on the device at once.
+bool resident2d_fits(int n0, int n1, int W0, int W1, int prox_kind);
+hipError_t launch_resident2d(const Resident2D& r, hipStream_t stream);
 
 // Largest |i - j| at which the float32 factor exp(-((i-j)/n)^2/gamma) can be
 // non-zero (entries below 2^-150 round to zero).

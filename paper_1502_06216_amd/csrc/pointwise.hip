@@ -14,6 +14,7 @@
 //  * the pointwise parts of the adjoint sweep.
 #include <math.h>
 
+#include "control.h"
 #include "jko_internal.h"
 
 namespace jko {
@@ -122,52 +123,10 @@ __device__ double fixed_max(const double* v, int n, double* sh) {
     return r;
 }
 
-// One wave: each lane sums a fixed strided subset of the partials, then a
-// fixed xor-butterfly combines the lanes (same order every call: bitwise
-// reproducible).
 __global__ void __launch_bounds__(64) k_ctl_check(Ctl* c, Partials part, int nparts, int iter,
                                                   double tol, int check_mass, double absorb) {
     if (c->done) return;
-    const int lane = threadIdx.x;
-    double err = 0.0, mlb = 0.0, mass = 0.0, mla = 0.0;
-    for (int i = lane; i < nparts; i += 64) {
-        err += part.err[i];
-        mlb = fmax(mlb, part.maxlogb[i]);
-        if (check_mass) {
-            mass += part.mass[i];
-            mla = fmax(mla, part.maxloga[i]);
-        }
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-        err += __shfl_xor(err, o, 64);
-        mlb = fmax(mlb, __shfl_xor(mlb, o, 64));
-        mass += __shfl_xor(mass, o, 64);
-        mla = fmax(mla, __shfl_xor(mla, o, 64));
-    }
-    if (lane == 0) {
-        c->err = err;
-        c->maxlogb = mlb;
-        if (check_mass) {
-            c->mass = mass;
-            c->maxloga = mla;
-        }
-        const bool finite = isfinite(err) && (!check_mass || isfinite(mass));
-        if (!finite) {
-            c->nonfinite = 1;
-            c->done = 1;
-            c->stop_iter = iter - 1;
-        } else if (tol > 0.0 && err <= tol) {
-            c->done = 1;
-            c->stop_iter = iter - 1;
-        }
-        // Log-domain absorption: from here on a, b are carried as log a, log b.
-        c->absorb_pending = 0;
-        if (!c->done && !c->logmode && absorb > 0.0 && (mlb > absorb || (check_mass && mla > absorb))) {
-            c->absorb_pending = 1;
-            c->logmode = 1;
-            c->absorptions += 1;
-        }
-    }
+    ctl_update(c, part, nparts, iter, tol, check_mass, absorb);
 }
 
 __global__ void k_absorb(const Ctl* c, float* __restrict__ a, float* __restrict__ b, int64_t N) {
