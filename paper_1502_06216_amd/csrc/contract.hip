@@ -368,46 +368,281 @@ contract_rot(Pass P, EpiArgs E) {
     epi_finish(E, ea, (int)blockIdx.x, shd);
 }
 
+// Panel form, for axes whose length is a multiple of 32.  The tile's band of
+// k, [kb0, kb1) aligned to 32, is staged in LDS as panels of 32 k:
+//   X            [panel][TR rows][32 floats]   (128-byte rows)
+//   K1 (FP32)    [panel][TI rows][32 floats]
+//   K1 (split)   hi and lo, [panel][TI rows][32 bf16]   (64-byte rows)
+// by buffer loads that write LDS directly (16 bytes per lane, no registers on
+// the way, rows past R read as zeros by the range check), all issued at once:
+// one memory round trip per block, and every index a shift or mask.  Within a
+// row the 16-byte chunks are XOR-swizzled so the operand reads of 16
+// consecutive rows fall in distinct banks:
+//   128-byte rows: chunk c of row r is stored at c ^ ((r >> 1) & 7)
+//    64-byte rows: chunk c of row r is stored at c ^ ((r >> 2) & 3)
+// Split path: X is staged in FP32 and split into bfloat16 hi + lo (hardware
+// round-to-nearest-even) as each wave reads its operand.
+constexpr int kPanelMax = 5;      // panels per tile band (160 k)
+constexpr int kBufRsrcWord3 = 0x00020000;
+
+__device__ __forceinline__ void lds_copy16(__amdgpu_buffer_rsrc_t rs, void* lds, int voff) {
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)lds, 16, voff, 0, 0, 0);
+}
+
+template <int TR, int TI, int WR, int WI, bool SPLIT, int EK>
+__global__ void __launch_bounds__(kThreads)
+contract_panel(Pass P, EpiArgs E) {
+    static_assert(WR * WI == 4, "four waves per block");
+    constexpr int FM = TR / WR / 16;
+    constexpr int FN = TI / WI / 16;
+    static_assert(FM >= 1 && FN >= 1 && TR % 16 == 0 && TI % 16 == 0, "tile shape");
+    extern __shared__ __attribute__((aligned(16))) float dyn[];
+    __shared__ float fshift[TR];
+    __shared__ double shd[8];
+
+    int done = 0, lmode = 0;
+    if (E.ctl) {
+        done = E.ctl->done;
+        lmode = E.ctl->logmode;
+    }
+    const int n = P.n;
+    const int R = (int)P.R;
+    const int IT = n / TI;
+    const int logical = xcd_logical_block();
+    const int r0 = (logical / IT) * TR;
+    const int i0 = (logical % IT) * TI;
+    const int kb0 = max(0, i0 - P.W) & ~31;
+    const int kb1 = min(n, (i0 + TI + P.W + 31) & ~31);
+    const int NP = (kb1 - kb0) >> 5;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave % WR, wi = wave / WR;
+    float* Xs = dyn;                                               // NP * TR * 32 floats
+    float* Kf = dyn + NP * TR * 32;                                // NP * TI * 32 floats
+    uint16_t* Kh = reinterpret_cast<uint16_t*>(dyn + NP * TR * 32);   // NP * TI * 32 bf16
+    uint16_t* Kl = Kh + NP * TI * 32;
+
+    // epilogue inputs first, then the staging copies; one wait covers both
+    constexpr int UE = (TI * TR / 4 + kThreads - 1) / kThreads;
+    EpiIn ein[UE];
+    int eidx[UE], ecnt[UE];
+#pragma unroll
+    for (int u = 0; u < UE; ++u) {
+        const int unit = tid + u * kThreads;
+        const int il = unit / (TR / 4), rl = 4 * (unit % (TR / 4));
+        const int i = i0 + il, r = r0 + rl;
+        ecnt[u] = (unit < TI * TR / 4 && i < n) ? max(0, min(4, R - r)) : 0;
+        eidx[u] = i * R + r;
+        ein[u] = epi_prefetch<EK>(E, eidx[u], ecnt[u]);
+    }
+    {
+        const __amdgpu_buffer_rsrc_t rx =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(P.X), (short)0, R * n * 4, kBufRsrcWord3);
+        // X: 8 rows of one panel per wave-wide copy
+        constexpr int XPP = TR / 8;
+        const int nX = NP * XPP;
+        const int xrow = lane >> 3, xch = lane & 7;
+        for (int j = wave; j < nX; j += kThreads / 64) {
+            const int pnl = j / XPP, row = (j % XPP) * 8 + xrow;
+            const int col = kb0 + 32 * pnl + 4 * (xch ^ ((row >> 1) & 7));
+            lds_copy16(rx, Xs + j * 256, 4 * ((r0 + row) * n + col));
+        }
+        if (SPLIT) {
+            const __amdgpu_buffer_rsrc_t rh = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<uint16_t*>(P.K1hi), (short)0, n * n * 2, kBufRsrcWord3);
+            const __amdgpu_buffer_rsrc_t rl = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<uint16_t*>(P.K1lo), (short)0, n * n * 2, kBufRsrcWord3);
+            // 16 rows of one bf16 panel per wave-wide copy
+            constexpr int KPP = TI / 16;
+            const int nK = NP * KPP;
+            const int krow = lane >> 2, kch = lane & 3;
+            for (int j = wave; j < 2 * nK; j += kThreads / 64) {
+                const int jj = j < nK ? j : j - nK;
+                const int pnl = jj / KPP, row = (jj % KPP) * 16 + krow;
+                const int col = kb0 + 32 * pnl + 8 * (kch ^ ((row >> 2) & 3));
+                const int voff = 2 * ((i0 + row) * n + col);
+                if (j < nK) lds_copy16(rh, Kh + jj * 512, voff);
+                else lds_copy16(rl, Kl + jj * 512, voff);
+            }
+        } else {
+            const __amdgpu_buffer_rsrc_t rk = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<float*>(P.K1), (short)0, n * n * 4, kBufRsrcWord3);
+            constexpr int KPP = TI / 8;
+            const int nK = NP * KPP;
+            for (int j = wave; j < nK; j += kThreads / 64) {
+                const int pnl = j / KPP, row = (j % KPP) * 8 + xrow;
+                const int col = kb0 + 32 * pnl + 4 * (xch ^ ((row >> 1) & 7));
+                lds_copy16(rk, Kf + j * 256, 4 * ((i0 + row) * n + col));
+            }
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    if (done) return;   // the step has stopped: nothing to compute (uniform)
+    __syncthreads();
+    const bool logx = lmode != 0;
+    if (logx) {
+        // per-row maximum of the staged logs over the band, then exponentiate
+        if (tid < TR) {
+            float m = -INFINITY;
+            for (int pnl = 0; pnl < NP; ++pnl)
+                for (int q = 0; q < 32; ++q) m = fmaxf(m, Xs[(pnl * TR + tid) * 32 + q]);
+            fshift[tid] = (m == -INFINITY) ? NAN : m;
+        }
+        __syncthreads();
+        for (int u = tid; u < NP * TR * 32; u += kThreads) Xs[u] = shifted_exp(Xs[u], fshift[(u >> 5) % TR]);
+        __syncthreads();
+    }
+
+    f4 acc[FM][FN];
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+    const int s8 = (lane >> 1) & 7;   // 128-byte row swizzle of every row this lane reads
+    const int g = lane >> 4;
+    for (int pnl = 0; pnl < NP; ++pnl) {
+        const float* xp = Xs + (pnl * TR + wr * 16 * FM + (lane & 15)) * 32;
+        if (SPLIT) {
+            const int s4 = (lane >> 2) & 3;
+            bf8 ah[FM], al[FM], bh[FN], bl[FN];
+#pragma unroll
+            for (int a = 0; a < FM; ++a) {
+                const float* xr = xp + a * 16 * 32;
+                const f4 v0 = *reinterpret_cast<const f4*>(xr + 4 * ((2 * g) ^ s8));
+                const f4 v1 = *reinterpret_cast<const f4*>(xr + 4 * ((2 * g + 1) ^ s8));
+                split_bf16(v0, v1, ah[a], al[a]);
+            }
+#pragma unroll
+            for (int b = 0; b < FN; ++b) {
+                const int o = (pnl * TI + wi * 16 * FN + b * 16 + (lane & 15)) * 32 + 8 * (g ^ s4);
+                bh[b] = __builtin_bit_cast(bf8, *reinterpret_cast<const u16x8*>(Kh + o));
+                bl[b] = __builtin_bit_cast(bf8, *reinterpret_cast<const u16x8*>(Kl + o));
+            }
+#pragma unroll
+            for (int a = 0; a < FM; ++a)
+#pragma unroll
+                for (int b = 0; b < FN; ++b) {
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+                }
+        } else {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int ch = 4 * ((4 * h + g) ^ s8);
+                f4 av[FM], bv[FN];
+#pragma unroll
+                for (int a = 0; a < FM; ++a) av[a] = *reinterpret_cast<const f4*>(xp + a * 16 * 32 + ch);
+#pragma unroll
+                for (int b = 0; b < FN; ++b)
+                    bv[b] = *reinterpret_cast<const f4*>(
+                        Kf + (pnl * TI + wi * 16 * FN + b * 16 + (lane & 15)) * 32 + ch);
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+#pragma unroll
+                    for (int a = 0; a < FM; ++a)
+#pragma unroll
+                        for (int b = 0; b < FN; ++b)
+                            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a][s], bv[b][s], acc[a][b], 0, 0, 0);
+            }
+        }
+    }
+    __syncthreads();
+
+    // epilogue through LDS as in contract_rot
+    constexpr int TS = TR + 4;
+    float* tile = dyn;
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) {
+            const int rl = wr * 16 * FM + a * 16 + 4 * (lane >> 4);
+            const int il = wi * 16 * FN + b * 16 + (lane & 15);
+            *reinterpret_cast<f4*>(&tile[il * TS + rl]) = acc[a][b];
+        }
+    __syncthreads();
+    EpiAcc ea;
+#pragma unroll
+    for (int u = 0; u < UE; ++u) {
+        const int unit = tid + u * kThreads;
+        const int il = unit / (TR / 4), rl = 4 * (unit % (TR / 4));
+        if (ecnt[u] == 0) continue;
+        f4 v = *reinterpret_cast<const f4*>(&tile[il * TS + rl]);
+        if (logx) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] = shifted_log(v[e], fshift[rl + e]);
+        }
+        epi_apply<EK>(E, eidx[u], ecnt[u], v, logx, ein[u], ea);
+    }
+    epi_finish(E, ea, (int)blockIdx.x, shd);
+}
+
+// Dynamic LDS bytes of the panel form for a tile of TR + TI rows and NP panels
+// (the staged epilogue tile reuses it).
+constexpr int panel_lds_bytes(int TR, int TI, int NP) { return NP * (TR + TI) * 128; }
+
 // Tile configurations (TR, TI, WR, WI):
-//  0: 32 x 32, 2 x 2 waves of one fragment
+//  0: 32 x 32, 2 x 2 waves of one fragment, chunked K loop
 //  1: 16 x 64, 1 x 4 waves (few rows: 1D grids)
 //  2: 64 x 16, 4 x 1 waves (short axes)
-// K runs in 32-wide chunks through two LDS stages.  Larger tiles (64 x 64)
-// re-read less but leave too few blocks to hide latency at these sizes.
-constexpr int kCfgTR[3] = {32, 16, 64};
-constexpr int kCfgTI[3] = {32, 64, 16};
+//  3: 32 x 32 panel form (axes of a multiple of 32, band of at most 160 k)
+//  4: 64 x 32 panel form, when it still leaves 4 blocks per CU
+// The chunked forms run K in 32-wide chunks through two LDS stages.
+constexpr int kCfgTR[5] = {32, 16, 64, 32, 64};
+constexpr int kCfgTI[5] = {32, 64, 16, 32, 32};
+constexpr int64_t kPanelWideBlocks = 1024;
 
 int64_t tiles_of(const Pass& p, int c) {
     return ((p.R + kCfgTR[c] - 1) / kCfgTR[c]) * (int64_t)((p.n + kCfgTI[c] - 1) / kCfgTI[c]);
 }
 
+// Panels of the widest tile band of the pass (0 if the panel form does not apply).
+int panel_count(const Pass& p) {
+    if (p.n % 32 != 0 || p.R * (int64_t)p.n * 4 >= ((int64_t)1 << 31)) return 0;
+    int np = 0;
+    for (int i0 = 0; i0 < p.n; i0 += 32) {
+        const int kb0 = std::max(0, i0 - p.W) & ~31;
+        const int kb1 = std::min(p.n, (i0 + 32 + p.W + 31) & ~31);
+        np = std::max(np, (kb1 - kb0) >> 5);
+    }
+    return np <= kPanelMax ? np : 0;
+}
+
 int pick_cfg(const Pass& p) {
     if (p.n <= 16) return 2;
     if (p.R <= 16) return 1;
+    if (panel_count(p) > 0) return tiles_of(p, 4) >= kPanelWideBlocks ? 4 : 3;
     return 0;
 }
 
-template <bool SPLIT, int BK, int EK>
+template <bool SPLIT, int EK>
 hipError_t launch_cfg(int cfg, int64_t nb, const Pass& p, const EpiArgs& e, hipStream_t st) {
     const dim3 grid((unsigned)nb), block(kThreads);
     switch (cfg) {
-        case 0: hipLaunchKernelGGL((contract_rot<32, 32, 2, 2, SPLIT, BK, 2, EK>), grid, block, 0, st, p, e); break;
-        case 1: hipLaunchKernelGGL((contract_rot<16, 64, 1, 4, SPLIT, BK, 2, EK>), grid, block, 0, st, p, e); break;
-        default: hipLaunchKernelGGL((contract_rot<64, 16, 4, 1, SPLIT, BK, 2, EK>), grid, block, 0, st, p, e); break;
+        case 0: hipLaunchKernelGGL((contract_rot<32, 32, 2, 2, SPLIT, 32, 2, EK>), grid, block, 0, st, p, e); break;
+        case 1: hipLaunchKernelGGL((contract_rot<16, 64, 1, 4, SPLIT, 32, 2, EK>), grid, block, 0, st, p, e); break;
+        case 2: hipLaunchKernelGGL((contract_rot<64, 16, 4, 1, SPLIT, 32, 2, EK>), grid, block, 0, st, p, e); break;
+        case 3:
+            hipLaunchKernelGGL((contract_panel<32, 32, 2, 2, SPLIT, EK>), grid, block,
+                               panel_lds_bytes(32, 32, panel_count(p)), st, p, e);
+            break;
+        default:
+            hipLaunchKernelGGL((contract_panel<64, 32, 2, 2, SPLIT, EK>), grid, block,
+                               panel_lds_bytes(64, 32, panel_count(p)), st, p, e);
+            break;
     }
     return hipGetLastError();
 }
 
-template <bool SPLIT, int BK>
+template <bool SPLIT>
 hipError_t launch_ek(int ek, int cfg, int64_t nb, const Pass& p, const EpiArgs& e, hipStream_t st) {
     switch (ek) {
-        case EK_STORE: return launch_cfg<SPLIT, BK, EK_STORE>(cfg, nb, p, e, st);
-        case EK_BUPDATE: return launch_cfg<SPLIT, BK, EK_BUPDATE>(cfg, nb, p, e, st);
-        case EK_MONITOR: return launch_cfg<SPLIT, BK, EK_MONITOR>(cfg, nb, p, e, st);
-        case EK_PROX + JKO_F_ZERO: return launch_cfg<SPLIT, BK, EK_PROX + JKO_F_ZERO>(cfg, nb, p, e, st);
-        case EK_PROX + JKO_F_CONGESTION: return launch_cfg<SPLIT, BK, EK_PROX + JKO_F_CONGESTION>(cfg, nb, p, e, st);
-        case EK_PROX + JKO_F_POROUS: return launch_cfg<SPLIT, BK, EK_PROX + JKO_F_POROUS>(cfg, nb, p, e, st);
-        default: return launch_cfg<SPLIT, BK, EK_PROX + JKO_F_ENTROPY>(cfg, nb, p, e, st);
+        case EK_STORE: return launch_cfg<SPLIT, EK_STORE>(cfg, nb, p, e, st);
+        case EK_BUPDATE: return launch_cfg<SPLIT, EK_BUPDATE>(cfg, nb, p, e, st);
+        case EK_MONITOR: return launch_cfg<SPLIT, EK_MONITOR>(cfg, nb, p, e, st);
+        case EK_PROX + JKO_F_ZERO: return launch_cfg<SPLIT, EK_PROX + JKO_F_ZERO>(cfg, nb, p, e, st);
+        case EK_PROX + JKO_F_CONGESTION: return launch_cfg<SPLIT, EK_PROX + JKO_F_CONGESTION>(cfg, nb, p, e, st);
+        case EK_PROX + JKO_F_POROUS: return launch_cfg<SPLIT, EK_PROX + JKO_F_POROUS>(cfg, nb, p, e, st);
+        default: return launch_cfg<SPLIT, EK_PROX + JKO_F_ENTROPY>(cfg, nb, p, e, st);
     }
 }
 
@@ -422,8 +657,8 @@ hipError_t launch_contract(const Pass& pass, int32_t precision, const EpiArgs& e
     if (nblocks) *nblocks = (int)nb;
     if (nb <= 0) return hipSuccess;
     const int ek = ek_of(epi);
-    if (precision == JKO_SPLIT_BF16) return launch_ek<true, 32>(ek, c, nb, pass, epi, stream);
-    return launch_ek<false, 32>(ek, c, nb, pass, epi, stream);
+    if (precision == JKO_SPLIT_BF16) return launch_ek<true>(ek, c, nb, pass, epi, stream);
+    return launch_ek<false>(ek, c, nb, pass, epi, stream);
 }
 
 }  // namespace jko

@@ -144,6 +144,23 @@ __device__ __forceinline__ void st4(float* __restrict__ p, int idx, int cnt, boo
 }
 
 
+// Split 8 consecutive floats into bfloat16 hi + lo, x = hi + lo + O(2^-16 x),
+// with the hardware's round-to-nearest-even conversion.
+__device__ __forceinline__ void split_bf16(f4 v0, f4 v1, bf8& hi, bf8& lo) {
+    typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+    typedef float fl2 __attribute__((ext_vector_type(2)));
+    const fl2 x[4] = {fl2{v0[0], v0[1]}, fl2{v0[2], v0[3]}, fl2{v1[0], v1[1]}, fl2{v1[2], v1[3]}};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const b2 h = __builtin_convertvector(x[q], b2);
+        const b2 l = __builtin_convertvector(x[q] - __builtin_convertvector(h, fl2), b2);
+        hi[2 * q] = h[0];
+        hi[2 * q + 1] = h[1];
+        lo[2 * q] = l[0];
+        lo[2 * q + 1] = l[1];
+    }
+}
+
 // Device-scope (coherent across XCDs) element stores and loads, for data one
 // block of the resident kernel writes and another reads within the launch.
 __device__ __forceinline__ void st4_coh(float* p, int idx, int cnt, f4 v) {
