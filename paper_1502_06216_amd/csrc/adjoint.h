@@ -1,0 +1,80 @@
+// Per-cell reverse steps of the iteration (3.2), shared by the pointwise
+// adjoint kernels and the contraction epilogues that fuse them.
+#pragma once
+
+#include <math.h>
+
+#include "jko_internal.h"
+
+namespace jko {
+
+// Reverse of p = prox(s), a = p / s at one cell:
+//   pbar = pbar_ext + abar / s
+//   sbar = -abar a / s + pbar dp/ds          (abar p / s^2 written with a = p / s)
+//   wbar += pbar dp/dw          (congestion: dp/dw = -sigma s g on the free branch)
+// Ties s g = kappa take the capped branch (derivative 0).  Terms whose factor
+// is structurally zero (a = 0, dp/ds = 0) are skipped, so cells with s, p at
+// the float32 underflow limit contribute 0 rather than 0 * inf.
+// fu, fv: the cell's energy fields (congestion: g, kappa; entropy: 1/(1 + sigma c);
+// porous: log((m-1) k)).  Returns sbar; *dw receives the wbar increment.
+template <int KIND>
+__device__ __forceinline__ float adj_prox_cell(const ProxArgs& px, float sigma, float sv, float pb, float ab,
+                                               float fu, float fv, float* dw) {
+    float p = 0.f, dpds = 0.f, dpdw = 0.f, sb = 0.f;
+    *dw = 0.f;
+    if (!(sv > 0.f)) return 0.f;
+    if (KIND == JKO_F_CONGESTION) {
+        const float sg = sv * fu;
+        if (sg < fv) {
+            p = sg;
+            dpds = fu;
+            dpdw = -sigma * sg;
+        } else {
+            p = fv;
+        }
+    } else if (KIND == JKO_F_ENTROPY) {
+        p = expf(fu * logf(sv));
+        dpds = fu * p / sv;
+    } else if (KIND == JKO_F_POROUS) {
+        const float m = px.m;
+        const float ls = logf(sv);
+        const float lz = fu + (m - 1.f) * ls;
+        if (lz < -60.f) {   // k psi^{m-1} negligible: psi = s
+            p = sv;
+            dpds = 1.f;
+        } else {
+            float v = (lz < 1.f) ? log1pf(expf(lz)) : lz - logf(lz);
+            for (int it = 0; it < px.newton; ++it) {
+                const float r = logf(v) + v - lz;
+                v = v - r * v / (1.f + v);
+            }
+            p = expf(ls - v / (m - 1.f));
+            // implicit derivative of log psi + k psi^{m-1} = log s
+            dpds = (p / sv) / (1.f + v);
+        }
+    } else {
+        p = sv;
+        dpds = 1.f;
+    }
+    const float a = (p == 0.f) ? 0.f : p / sv;
+    const float abs_ = (ab != 0.f) ? ab / sv : 0.f;
+    pb += abs_;
+    if (a != 0.f) sb -= abs_ * a;
+    if (dpds != 0.f) sb += pb * dpds;
+    if (dpdw != 0.f) *dw = pb * dpdw;
+    return sb;
+}
+
+// Reverse of b = q / t at one cell: tbar = -bbar q / t^2 = -bbar b / t and the
+// qbar increment bbar / t (zero where t = 0).
+__device__ __forceinline__ float adj_b_cell(float tv, float qv, float bb, float* dq) {
+    if (!(tv > 0.f)) {
+        *dq = 0.f;
+        return 0.f;
+    }
+    const float bv = (qv == 0.f) ? 0.f : qv / tv;
+    *dq = bb / tv;
+    return (bv == 0.f || bb == 0.f) ? 0.f : -bb * (bv / tv);
+}
+
+}  // namespace jko

@@ -242,7 +242,8 @@ bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
 // Vector (16-byte) epilogue access is allowed when every field pointer is aligned.
 void set_vec(EpiArgs& e) {
-    const void* ps[] = {e.y, e.q, e.b, e.a, e.p_out, e.s_out, e.t_out, e.prox.g, e.prox.kappa, e.prox.kf};
+    const void* ps[] = {e.y, e.q, e.b, e.a, e.p_out, e.s_out, e.t_out, e.hin, e.acc,
+                        e.prox.g, e.prox.kappa, e.prox.kf};
     bool ok = true;
     for (const void* p : ps) ok = ok && aligned16(p);
     e.vec_ok = ok ? 1 : 0;
@@ -841,23 +842,31 @@ jko_status jko_backward(const jko_grid* grid, const jko_energy* energy, const jk
         s = run_step(P, &fixed, px, q, P.F(F_TMP), false, true, nullptr);
         if (s) return s;
         HIP_TRY(launch_fill(qbar, 0.f, N, P.st));
-        float* abar = P.F(F_ABAR);
         float* sbar = P.F(F_SBAR);
-        float* bbar = P.F(F_BBAR);
         float* tbar = P.F(F_TBAR);
+        // k = K: the external pbar enters; afterwards each reverse step is two
+        // Gibbs applications whose epilogues carry the pointwise reverse steps:
+        //   bbar = xi sbar_k  -> tbar_k, qbar += ...          (reverse of b = q / t)
+        //   abar = xi tbar_k  -> sbar_{k-1}, wbar += ...      (reverse of the prox at k - 1)
+        HIP_TRY(launch_adj_prox(P.hist(2 * (int64_t)(K - 1) + 1), pbar, nullptr, sbar, dL_dw ? wacc : nullptr, px,
+                                sigma, N, P.st));
         for (int k = K; k >= 1; --k) {
-            const float* tk = P.hist(2 * (int64_t)(k - 1));
-            const float* sk = P.hist(2 * (int64_t)(k - 1) + 1);
-            HIP_TRY(launch_adj_prox(sk, (k == K) ? pbar : nullptr, (k == K) ? nullptr : abar, sbar,
-                                    dL_dw ? wacc : nullptr, px, sigma, N, P.st));
-            EpiArgs e{};
-            e.kind = EpiKind::STORE;
-            e.y = bbar;
-            if ((s = apply_xi(P, sbar, e, nullptr))) return s;
-            HIP_TRY(launch_adj_b(tk, q, bbar, tbar, qbar, N, P.st));
+            EpiArgs eb{};
+            eb.kind = EpiKind::ADJ_B;
+            eb.hin = P.hist(2 * (int64_t)(k - 1));
+            eb.q = q;
+            eb.y = tbar;
+            eb.acc = qbar;
+            if ((s = apply_xi(P, sbar, eb, nullptr))) return s;
             if (k > 1) {
-                e.y = abar;
-                if ((s = apply_xi(P, tbar, e, nullptr))) return s;
+                EpiArgs ea{};
+                ea.kind = EpiKind::ADJ_PROX;
+                ea.hin = P.hist(2 * (int64_t)(k - 2) + 1);
+                ea.y = sbar;
+                ea.acc = dL_dw ? wacc : nullptr;
+                ea.prox = px;
+                ea.sigma = (float)sigma;
+                if ((s = apply_xi(P, tbar, ea, nullptr))) return s;
             }
         }
         HIP_TRY(launch_copy(pbar, qbar, N, P.st));

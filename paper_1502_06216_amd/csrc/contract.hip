@@ -642,7 +642,13 @@ hipError_t launch_ek(int ek, int cfg, int64_t nb, const Pass& p, const EpiArgs& 
         case EK_PROX + JKO_F_ZERO: return launch_cfg<SPLIT, EK_PROX + JKO_F_ZERO>(cfg, nb, p, e, st);
         case EK_PROX + JKO_F_CONGESTION: return launch_cfg<SPLIT, EK_PROX + JKO_F_CONGESTION>(cfg, nb, p, e, st);
         case EK_PROX + JKO_F_POROUS: return launch_cfg<SPLIT, EK_PROX + JKO_F_POROUS>(cfg, nb, p, e, st);
-        default: return launch_cfg<SPLIT, EK_PROX + JKO_F_ENTROPY>(cfg, nb, p, e, st);
+        case EK_PROX + JKO_F_ENTROPY: return launch_cfg<SPLIT, EK_PROX + JKO_F_ENTROPY>(cfg, nb, p, e, st);
+        case EK_ADJ_B: return launch_cfg<SPLIT, EK_ADJ_B>(cfg, nb, p, e, st);
+        case EK_ADJ_PROX + JKO_F_ZERO: return launch_cfg<SPLIT, EK_ADJ_PROX + JKO_F_ZERO>(cfg, nb, p, e, st);
+        case EK_ADJ_PROX + JKO_F_CONGESTION:
+            return launch_cfg<SPLIT, EK_ADJ_PROX + JKO_F_CONGESTION>(cfg, nb, p, e, st);
+        case EK_ADJ_PROX + JKO_F_POROUS: return launch_cfg<SPLIT, EK_ADJ_PROX + JKO_F_POROUS>(cfg, nb, p, e, st);
+        default: return launch_cfg<SPLIT, EK_ADJ_PROX + JKO_F_ENTROPY>(cfg, nb, p, e, st);
     }
 }
 

@@ -5,6 +5,7 @@
 
 #include <math.h>
 
+#include "adjoint.h"
 #include "jko_internal.h"
 
 namespace jko {
@@ -72,12 +73,14 @@ __device__ __forceinline__ float log_prox_porous(float ls, float lk, float m, in
 
 // Epilogue codes: the epilogue kind and, for the proximal epilogue, the
 // energy, fixed at compile time so that each kernel carries only its own code.
-enum : int { EK_STORE = 0, EK_BUPDATE = 1, EK_MONITOR = 2, EK_PROX = 3 };   // EK_PROX + energy kind
-constexpr int ek_count = EK_PROX + 4;
+// EK_PROX + energy kind, EK_ADJ_B, EK_ADJ_PROX + energy kind
+enum : int { EK_STORE = 0, EK_BUPDATE = 1, EK_MONITOR = 2, EK_PROX = 3, EK_ADJ_B = 7, EK_ADJ_PROX = 8 };
+constexpr int ek_count = EK_ADJ_PROX + 4;
 
 __host__ __device__ constexpr EpiKind ek_kind(int ek) {
     return ek == EK_STORE ? EpiKind::STORE : ek == EK_BUPDATE ? EpiKind::BUPDATE
-         : ek == EK_MONITOR ? EpiKind::MONITOR : EpiKind::PROX;
+         : ek == EK_MONITOR ? EpiKind::MONITOR : ek == EK_ADJ_B ? EpiKind::ADJ_B
+         : ek >= EK_ADJ_PROX ? EpiKind::ADJ_PROX : EpiKind::PROX;
 }
 
 inline int ek_of(const EpiArgs& e) {
@@ -85,6 +88,8 @@ inline int ek_of(const EpiArgs& e) {
         case EpiKind::STORE: return EK_STORE;
         case EpiKind::BUPDATE: return EK_BUPDATE;
         case EpiKind::MONITOR: return EK_MONITOR;
+        case EpiKind::ADJ_B: return EK_ADJ_B;
+        case EpiKind::ADJ_PROX: return EK_ADJ_PROX + e.prox.kind;
         default: return EK_PROX + e.prox.kind;
     }
 }
@@ -121,7 +126,7 @@ struct EpiAcc {
 // contraction.  BUPDATE/MONITOR: u = q, v = old b;  PROX: u, v = the energy
 // parameters of prox_val.
 struct EpiIn {
-    f4 u, v;
+    f4 u, v, w;
 };
 
 __device__ __forceinline__ f4 ld4(const float* __restrict__ p, int idx, int cnt, bool vec, float fill) {
@@ -181,11 +186,26 @@ __device__ __forceinline__ EpiIn epi_prefetch(const EpiArgs& E, int idx, int cnt
     EpiIn in;
     in.u = f4{0.f, 0.f, 0.f, 0.f};
     in.v = f4{0.f, 0.f, 0.f, 0.f};
+    in.w = f4{0.f, 0.f, 0.f, 0.f};
     if (cnt <= 0) return in;
     const bool vec = E.vec_ok && ((idx & 3) == 0);
     if (EK == EK_BUPDATE || EK == EK_MONITOR) {
         in.u = ld4(E.q, idx, cnt, vec, 0.f);
         if (EK == EK_MONITOR || E.check) in.v = ld4(E.b, idx, cnt, vec, 0.f);
+    } else if (EK == EK_ADJ_B) {
+        in.u = ld4(E.hin, idx, cnt, vec, 0.f);
+        in.v = ld4(E.q, idx, cnt, vec, 0.f);
+        in.w = ld4(E.acc, idx, cnt, vec, 0.f);
+    } else if (EK >= EK_ADJ_PROX) {
+        const ProxArgs& px = E.prox;
+        in.u = ld4(E.hin, idx, cnt, vec, 0.f);
+        if (EK - EK_ADJ_PROX == JKO_F_CONGESTION) {
+            in.v = px.g ? ld4(px.g, idx, cnt, vec, 1.f) : f4{1.f, 1.f, 1.f, 1.f};
+            in.w = px.kappa ? ld4(px.kappa, idx, cnt, vec, 0.f)
+                            : f4{px.kappa_s, px.kappa_s, px.kappa_s, px.kappa_s};
+        } else if (EK - EK_ADJ_PROX == JKO_F_ENTROPY || EK - EK_ADJ_PROX == JKO_F_POROUS) {
+            in.v = px.kf ? ld4(px.kf, idx, cnt, vec, 0.f) : f4{px.kf_s, px.kf_s, px.kf_s, px.kf_s};
+        }
     } else if (EK >= EK_PROX) {
         const ProxArgs& px = E.prox;
         if (EK - EK_PROX == JKO_F_CONGESTION) {
@@ -236,6 +256,33 @@ __device__ __forceinline__ void epi_apply(const EpiArgs& E, int idx, int cnt, f4
         if (COH) st4_coh(E.b, idx, cnt, bn);
         else st4(E.b, idx, cnt, vec, bn);
         if (E.t_out) st4(E.t_out, idx, cnt, vec, val);
+    } else if (EK == EK_ADJ_B) {
+        f4 tb, qb;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            float dq;
+            tb[e] = adj_b_cell(in.u[e], in.v[e], val[e], &dq);
+            qb[e] = (dq != 0.f) ? in.w[e] + dq : in.w[e];
+        }
+        st4(E.y, idx, cnt, vec, tb);
+        st4(E.acc, idx, cnt, vec, qb);
+    } else if (EK >= EK_ADJ_PROX) {
+        constexpr int KIND = EK - EK_ADJ_PROX;
+        f4 sb, dw;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            float d;
+            sb[e] = adj_prox_cell<KIND>(E.prox, E.sigma, in.u[e], 0.f, val[e], in.v[e], in.w[e], &d);
+            dw[e] = d;
+        }
+        st4(E.y, idx, cnt, vec, sb);
+        if (KIND == JKO_F_CONGESTION && E.acc) {
+            f4 wb = ld4(E.acc, idx, cnt, vec, 0.f);
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (dw[e] != 0.f) wb[e] += dw[e];
+            st4(E.acc, idx, cnt, vec, wb);
+        }
     } else if (EK == EK_MONITOR) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {

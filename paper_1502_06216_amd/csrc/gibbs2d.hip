@@ -582,7 +582,17 @@ hipError_t launch_gibbs2d(const Band2D& b, int32_t precision, const EpiArgs& epi
             hipLaunchKernelGGL(gibbs2d_f32<EK_PROX + JKO_F_CONGESTION>, grid, block, 0, stream, b, epi); break;
         case EK_PROX + JKO_F_POROUS:
             hipLaunchKernelGGL(gibbs2d_f32<EK_PROX + JKO_F_POROUS>, grid, block, 0, stream, b, epi); break;
-        default: hipLaunchKernelGGL(gibbs2d_f32<EK_PROX + JKO_F_ENTROPY>, grid, block, 0, stream, b, epi); break;
+        case EK_PROX + JKO_F_ENTROPY:
+            hipLaunchKernelGGL(gibbs2d_f32<EK_PROX + JKO_F_ENTROPY>, grid, block, 0, stream, b, epi); break;
+        case EK_ADJ_B: hipLaunchKernelGGL(gibbs2d_f32<EK_ADJ_B>, grid, block, 0, stream, b, epi); break;
+        case EK_ADJ_PROX + JKO_F_ZERO:
+            hipLaunchKernelGGL(gibbs2d_f32<EK_ADJ_PROX + JKO_F_ZERO>, grid, block, 0, stream, b, epi); break;
+        case EK_ADJ_PROX + JKO_F_CONGESTION:
+            hipLaunchKernelGGL(gibbs2d_f32<EK_ADJ_PROX + JKO_F_CONGESTION>, grid, block, 0, stream, b, epi); break;
+        case EK_ADJ_PROX + JKO_F_POROUS:
+            hipLaunchKernelGGL(gibbs2d_f32<EK_ADJ_PROX + JKO_F_POROUS>, grid, block, 0, stream, b, epi); break;
+        default:
+            hipLaunchKernelGGL(gibbs2d_f32<EK_ADJ_PROX + JKO_F_ENTROPY>, grid, block, 0, stream, b, epi); break;
     }
     return hipGetLastError();
 }

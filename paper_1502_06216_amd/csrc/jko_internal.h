@@ -75,6 +75,8 @@ enum class EpiKind : int {
     BUPDATE = 1,    // t = v; [err += |b t - q|]; b = q / t
     PROX = 2,       // s = v; p = prox(s); a = p / s; [p_out = p]
     MONITOR = 3,    // t = v; err += |b t - q| (no write)
+    ADJ_B = 4,      // bbar = v; y = tbar; acc (qbar) += bbar / t         (reverse of b = q / t)
+    ADJ_PROX = 5,   // abar = v; y = sbar; acc (wbar) += ...               (reverse of p = prox(s), a = p / s)
 };
 
 struct EpiArgs {
@@ -86,6 +88,9 @@ struct EpiArgs {
     float* p_out;          // PROX: density written when write_p
     float* s_out;          // PROX: optional copy of s (adjoint recomputation)
     float* t_out;          // BUPDATE: optional copy of t (adjoint recomputation)
+    const float* hin;      // ADJ_B: t of the iteration; ADJ_PROX: s of the iteration
+    float* acc;            // ADJ_B: qbar (accumulated); ADJ_PROX: wbar (accumulated) or NULL
+    float sigma;           // ADJ_PROX: tau / gamma
     int32_t check;         // BUPDATE: accumulate err with the old b; PROX: mass + max|log a|
     int32_t write_p;
     int32_t vec_ok;        // every field pointer above is 16-byte aligned (vector access)

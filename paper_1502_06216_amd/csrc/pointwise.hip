@@ -14,6 +14,7 @@
 //  * the pointwise parts of the adjoint sweep.
 #include <math.h>
 
+#include "adjoint.h"
 #include "control.h"
 #include "jko_internal.h"
 
@@ -178,93 +179,36 @@ __global__ void __launch_bounds__(256) k_input_final(const double* part, int nb,
 
 // ---------------------------------------------------------------- adjoint
 
-// Reverse of p = prox(s), a = p / s for one iteration:
-//   pbar = pbar_ext + abar / s
-//   sbar = -abar a / s + pbar dp/ds          (abar p / s^2 written with a = p / s)
-//   wbar += pbar dp/dw          (congestion: dp/dw = -sigma s g on the free branch)
-// Ties s g = kappa take the capped branch (derivative 0).  Terms whose factor
-// is structurally zero (a = 0, dp/ds = 0) are skipped, so cells with s, p at
-// the float32 underflow limit contribute 0 rather than 0 * inf.
+// Reverse of p = prox(s), a = p / s over the field (adj_prox_cell per cell).
+template <int KIND>
 __global__ void k_adj_prox(const float* __restrict__ s, const float* __restrict__ pbar_ext,
                            const float* __restrict__ abar, float* __restrict__ sbar,
                            float* __restrict__ wbar, ProxArgs px, float sigma, int64_t N) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const float sv = s[i];
-        const float ab = abar ? abar[i] : 0.f;
-        float pb = pbar_ext ? pbar_ext[i] : 0.f;
-        float p = 0.f, dpds = 0.f, dpdw = 0.f;
-        float sb = 0.f;
-        if (sv > 0.f) {
-            switch (px.kind) {
-                case JKO_F_CONGESTION: {
-                    const float g = px.g ? px.g[i] : 1.f;
-                    const float k = px.kappa ? px.kappa[i] : px.kappa_s;
-                    const float sg = sv * g;
-                    if (sg < k) {
-                        p = sg;
-                        dpds = g;
-                        dpdw = -sigma * sg;
-                    } else {
-                        p = k;
-                    }
-                    break;
-                }
-                case JKO_F_ENTROPY: {
-                    const float e = px.kf ? px.kf[i] : px.kf_s;
-                    p = expf(e * logf(sv));
-                    dpds = e * p / sv;
-                    break;
-                }
-                case JKO_F_POROUS: {
-                    const float lk = px.kf ? px.kf[i] : px.kf_s;
-                    const float m = px.m;
-                    const float ls = logf(sv);
-                    const float lz = lk + (m - 1.f) * ls;
-                    if (lz < -60.f) {   // k psi^{m-1} negligible: psi = s
-                        p = sv;
-                        dpds = 1.f;
-                        break;
-                    }
-                    float v = (lz < 1.f) ? log1pf(expf(lz)) : lz - logf(lz);
-                    for (int it = 0; it < px.newton; ++it) {
-                        const float r = logf(v) + v - lz;
-                        v = v - r * v / (1.f + v);
-                    }
-                    p = expf(ls - v / (m - 1.f));
-                    // implicit derivative of log psi + k psi^{m-1} = log s
-                    dpds = (p / sv) / (1.f + v);
-                    break;
-                }
-                default:
-                    p = sv;
-                    dpds = 1.f;
-            }
-            const float a = (p == 0.f) ? 0.f : p / sv;
-            const float abs_ = (ab != 0.f) ? ab / sv : 0.f;
-            pb += abs_;
-            if (a != 0.f) sb -= abs_ * a;
-            if (dpds != 0.f) sb += pb * dpds;
+        float fu = 0.f, fv = 0.f;
+        if (KIND == JKO_F_CONGESTION) {
+            fu = px.g ? px.g[i] : 1.f;
+            fv = px.kappa ? px.kappa[i] : px.kappa_s;
+        } else if (KIND == JKO_F_ENTROPY || KIND == JKO_F_POROUS) {
+            fu = px.kf ? px.kf[i] : px.kf_s;
         }
-        sbar[i] = sb;
-        if (wbar && dpdw != 0.f) wbar[i] += pb * dpdw;
+        float dw;
+        sbar[i] = adj_prox_cell<KIND>(px, sigma, s[i], pbar_ext ? pbar_ext[i] : 0.f, abar ? abar[i] : 0.f, fu,
+                                      fv, &dw);
+        if (wbar && dw != 0.f) wbar[i] += dw;
     }
 }
 
-// Reverse of b = q / t:  tbar = -bbar q / t^2 = -bbar b / t,  qbar += bbar / t.
+// Reverse of b = q / t over the field (adj_b_cell per cell).
 __global__ void k_adj_b(const float* __restrict__ t, const float* __restrict__ q,
                         const float* __restrict__ bbar, float* __restrict__ tbar,
                         float* __restrict__ qbar, int64_t N) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const float tv = t[i], bb = bbar[i], qv = q[i];
-        if (tv > 0.f) {
-            const float bv = (qv == 0.f) ? 0.f : qv / tv;
-            tbar[i] = (bv == 0.f || bb == 0.f) ? 0.f : -bb * (bv / tv);
-            qbar[i] += bb / tv;
-        } else {
-            tbar[i] = 0.f;
-        }
+        float dq;
+        tbar[i] = adj_b_cell(t[i], q[i], bbar[i], &dq);
+        if (dq != 0.f) qbar[i] += dq;
     }
 }
 
@@ -330,8 +274,24 @@ hipError_t launch_input_check(const float* p_in, const float* kappa, float kappa
 
 hipError_t launch_adj_prox(const float* s, const float* pbar_ext, const float* abar, float* sbar,
                            float* wbar, const ProxArgs& px, double sigma, int64_t N, hipStream_t st) {
-    hipLaunchKernelGGL(k_adj_prox, dim3(blocks_for(N, 1024)), dim3(256), 0, st, s, pbar_ext, abar, sbar,
-                       wbar, px, (float)sigma, N);
+    const dim3 grid(blocks_for(N, 1024)), block(256);
+    switch (px.kind) {
+        case JKO_F_CONGESTION:
+            hipLaunchKernelGGL(k_adj_prox<JKO_F_CONGESTION>, grid, block, 0, st, s, pbar_ext, abar, sbar, wbar, px,
+                               (float)sigma, N);
+            break;
+        case JKO_F_ENTROPY:
+            hipLaunchKernelGGL(k_adj_prox<JKO_F_ENTROPY>, grid, block, 0, st, s, pbar_ext, abar, sbar, wbar, px,
+                               (float)sigma, N);
+            break;
+        case JKO_F_POROUS:
+            hipLaunchKernelGGL(k_adj_prox<JKO_F_POROUS>, grid, block, 0, st, s, pbar_ext, abar, sbar, wbar, px,
+                               (float)sigma, N);
+            break;
+        default:
+            hipLaunchKernelGGL(k_adj_prox<JKO_F_ZERO>, grid, block, 0, st, s, pbar_ext, abar, sbar, wbar, px,
+                               (float)sigma, N);
+    }
     return hipGetLastError();
 }
 
