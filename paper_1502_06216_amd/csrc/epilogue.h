@@ -12,6 +12,7 @@ namespace jko {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 
@@ -138,14 +139,16 @@ __device__ __forceinline__ f4 ld4(const float* __restrict__ p, int idx, int cnt,
     return r;
 }
 
+// Epilogue results are written with the non-temporal (streaming) hint: each
+// is read once, by the next kernel or pass, usually from another XCD.
 __device__ __forceinline__ void st4(float* __restrict__ p, int idx, int cnt, bool vec, f4 v) {
     if (vec && cnt == 4) {
-        *reinterpret_cast<f4*>(p + idx) = v;
+        __builtin_nontemporal_store(v, reinterpret_cast<f4*>(p + idx));
         return;
     }
 #pragma unroll
     for (int e = 0; e < 4; ++e)
-        if (e < cnt) p[idx + e] = v[e];
+        if (e < cnt) __builtin_nontemporal_store(v[e], p + idx + e);
 }
 
 
@@ -168,7 +171,14 @@ __device__ __forceinline__ void split_bf16(f4 v0, f4 v1, bf8& hi, bf8& lo) {
 
 // Device-scope (coherent across XCDs) element stores and loads, for data one
 // block of the resident kernel writes and another reads within the launch.
-__device__ __forceinline__ void st4_coh(float* p, int idx, int cnt, f4 v) {
+// A whole aligned run goes out as one 16-byte buffer store with the device
+// scope bit (SC1); the descriptor spans the 2^31 bytes a 32-bit offset reaches.
+__device__ __forceinline__ void st4_coh(float* p, int idx, int cnt, bool vec, f4 v) {
+    if (vec && cnt == 4) {
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(p, (short)0, 0x7fffffff, 0x00020000);
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), rs, 4 * idx, 0, 16);
+        return;
+    }
 #pragma unroll
     for (int e = 0; e < 4; ++e)
         if (e < cnt) __hip_atomic_store(p + idx + e, v[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -253,7 +263,7 @@ __device__ __forceinline__ void epi_apply(const EpiArgs& E, int idx, int cnt, f4
                 }
             }
         }
-        if (COH) st4_coh(E.b, idx, cnt, bn);
+        if (COH) st4_coh(E.b, idx, cnt, vec, bn);
         else st4(E.b, idx, cnt, vec, bn);
         if (E.t_out) st4(E.t_out, idx, cnt, vec, val);
     } else if (EK == EK_ADJ_B) {
@@ -308,7 +318,7 @@ __device__ __forceinline__ void epi_apply(const EpiArgs& E, int idx, int cnt, f4
             }
             if (E.check && e < cnt) acc.mass += (double)pn[e];
         }
-        if (COH) st4_coh(E.a, idx, cnt, an);
+        if (COH) st4_coh(E.a, idx, cnt, vec, an);
         else st4(E.a, idx, cnt, vec, an);
         if (E.write_p) st4(E.p_out, idx, cnt, vec, pn);
         if (E.s_out) st4(E.s_out, idx, cnt, vec, val);
