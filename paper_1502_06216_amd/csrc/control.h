@@ -16,7 +16,7 @@ namespace jko {
 //             returns the p of iteration iter - 1;
 //   logmode   switched on when max |log a| or max |log b| exceeds absorb.
 // COH: the partials are read with device-scope loads (written by other
-// blocks of the same launch).
+// blocks of the same launch); at most 256 of them (one per resident block).
 template <bool COH = false>
 __device__ __forceinline__ double part_ld(const double* p) {
     return COH ? __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : *p;
@@ -27,12 +27,37 @@ __device__ __forceinline__ void ctl_update(Ctl* c, const Partials& part, int npa
                                            int check_mass, double absorb) {
     const int lane = threadIdx.x & 63;
     double err = 0.0, mlb = 0.0, mass = 0.0, mla = 0.0;
-    for (int i = lane; i < nparts; i += 64) {
-        err += part_ld<COH>(part.err + i);
-        mlb = fmax(mlb, part_ld<COH>(part.maxlogb + i));
-        if (check_mass) {
-            mass += part_ld<COH>(part.mass + i);
-            mla = fmax(mla, part_ld<COH>(part.maxloga + i));
+    if (COH) {
+        // at most 4 partials per lane (256 blocks): all loads in flight at
+        // once, then the same sums in the same order as the loop below
+        double ve[4], vb[4], vm[4], va[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int i = lane + 64 * j;
+            const bool in = i < nparts;
+            ve[j] = in ? part_ld<COH>(part.err + i) : 0.0;
+            vb[j] = in ? part_ld<COH>(part.maxlogb + i) : 0.0;
+            vm[j] = (in && check_mass) ? part_ld<COH>(part.mass + i) : 0.0;
+            va[j] = (in && check_mass) ? part_ld<COH>(part.maxloga + i) : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (lane + 64 * j >= nparts) break;
+            err += ve[j];
+            mlb = fmax(mlb, vb[j]);
+            if (check_mass) {
+                mass += vm[j];
+                mla = fmax(mla, va[j]);
+            }
+        }
+    } else {
+        for (int i = lane; i < nparts; i += 64) {
+            err += part_ld<COH>(part.err + i);
+            mlb = fmax(mlb, part_ld<COH>(part.maxlogb + i));
+            if (check_mass) {
+                mass += part_ld<COH>(part.mass + i);
+                mla = fmax(mla, part_ld<COH>(part.maxloga + i));
+            }
         }
     }
     for (int o = 32; o > 0; o >>= 1) {

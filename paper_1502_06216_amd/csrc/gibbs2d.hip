@@ -350,11 +350,16 @@ gibbs2d_f32(Band2D B, EpiArgs E) {
 // at least its own count.  Tiles only read the tiles within their halo, so
 // most phases wait on those neighbours only (the relation is symmetric, which
 // also keeps a block from overwriting values a neighbour is still reading);
-// a stop-test check waits on every block, twice (partials written; partials
-// read).  Each wait polls a bounded number of times; one that runs out raises
-// the abort word, which every waiting block also polls, so every wave ends.
+// at a stop-test check, block 0 waits on every block, evaluates the test
+// from all partials and publishes the decision, which the others wait for.
+// Each wait polls a bounded number of times; one that runs out raises the
+// abort word, which every waiting block also polls, so every wave ends.
 
-// Sync region layout (uint32 words): [0] abort, flags[t] at kFlag0 + kFlagStride * t.
+// Sync region layout (uint32 words): [0] abort, [16] decision bits of the
+// last check (1 done, 2 absorb), [32] the phase count that decision belongs
+// to, flags[t] at kFlag0 + kFlagStride * t.
+constexpr int kDecision = 16;
+constexpr int kDecisionSeq = 32;
 constexpr int kFlag0 = 64;
 constexpr int kFlagStride = 16;   // one 64-byte line per block
 
@@ -393,6 +398,39 @@ __device__ __forceinline__ bool wait_for(uint32_t* sync, int n, const int* list,
     return __syncthreads_and(ok) != 0;
 }
 
+// All stores of this block completed, then store `value` to `word`.
+__device__ __forceinline__ void publish_word(uint32_t* word, uint32_t value) {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(word, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Thread 0 waits until `word` >= value (bounded, watching the abort word);
+// false in every thread if the wait ran out or another block aborted.
+__device__ __forceinline__ bool wait_word(const uint32_t* word, uint32_t value, uint32_t* sync, int spin_limit,
+                                          uint32_t* shared_ok) {
+    if (threadIdx.x == 0) {
+        uint32_t ok = 1;
+        for (int spins = 0; __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < value; ++spins) {
+            if ((spins & 31) == 31 && __hip_atomic_load(sync, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                ok = 0;
+                break;
+            }
+            if (spins >= spin_limit) {
+                __hip_atomic_store(sync, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        *shared_ok = ok;
+    }
+    __syncthreads();
+    return *shared_ok != 0;
+}
+
 template <int PK>
 __global__ void __launch_bounds__(kThr)
 resident2d(Resident2D R) {
@@ -401,6 +439,7 @@ resident2d(Resident2D R) {
     __shared__ int nbr[kMaxNeighbours];
     __shared__ int all[kFusedMaxBlocks];
     __shared__ int n_nbr;
+    __shared__ uint32_t okw, word;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nb = (int)gridDim.x;
@@ -474,28 +513,38 @@ resident2d(Resident2D R) {
         publish(R.sync, slot, ++count);
 
         if (chk) {
-            // every block's partials are in: the same decision everywhere
-            if (!wait_for(R.sync, nb, all, count, R.spin_limit)) return;
-            if (wave == 0) ctl_update<true>(&C, R.part, nb, k, R.tol, 1, R.absorb);
-            __syncthreads();
-            if (slot == 0 && tid == 0) {
-                Ctl* g = R.ctl;
-                g->done = C.done;
-                g->stop_iter = C.stop_iter;
-                g->nonfinite = C.nonfinite;
-                g->absorptions = C.absorptions;
-                g->absorb_pending = C.absorb_pending;
-                g->logmode = C.logmode;
-                g->err = C.err;
-                g->mass = C.mass;
-                g->maxloga = C.maxloga;
-                g->maxlogb = C.maxlogb;
+            // Block 0 waits for every block's partials, takes the decision and
+            // publishes it; the others wait for the decision.  No block writes
+            // partials again before it has seen the decision, so block 0 has
+            // read them all by then.
+            if (slot == 0) {
+                if (!wait_for(R.sync, nb, all, count, R.spin_limit)) return;
+                if (wave == 0) ctl_update<true>(&C, R.part, nb, k, R.tol, 1, R.absorb);
+                __syncthreads();
+                if (tid == 0) {
+                    Ctl* g = R.ctl;
+                    g->done = C.done;
+                    g->stop_iter = C.stop_iter;
+                    g->nonfinite = C.nonfinite;
+                    g->absorptions = C.absorptions;
+                    g->absorb_pending = C.absorb_pending;
+                    g->logmode = C.logmode;
+                    g->err = C.err;
+                    g->mass = C.mass;
+                    g->maxloga = C.maxloga;
+                    g->maxlogb = C.maxlogb;
+                    __hip_atomic_store(R.sync + kDecision, (uint32_t)(C.done | (C.absorb_pending << 1)),
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                publish_word(R.sync + kDecisionSeq, count);
             }
-            if (C.done) return;
-            // every block has read the partials before any block rewrites them
-            publish(R.sync, slot, ++count);
-            if (!wait_for(R.sync, nb, all, count, R.spin_limit)) return;
-            if (C.absorb_pending) {
+            if (!wait_word(R.sync + kDecisionSeq, count, R.sync, R.spin_limit, &okw)) return;
+            if (tid == 0)
+                word = __hip_atomic_load(R.sync + kDecision, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __syncthreads();
+            const uint32_t decision = word;
+            if (decision & 1u) return;   // same decision in every block
+            if (decision & 2u) {
                 // a <- log a, b <- log b on this block's own tile
                 if (tid < kT * kT) {
                     const int i = T.i0 + tid / kT, j = T.j0 + tid % kT;
