@@ -26,6 +26,7 @@
 // in the same order, so all blocks take the same decision.  Results are
 // bit-identical to the launch-per-application path.
 #include <algorithm>
+#include <type_traits>
 
 #include "control.h"
 #include "epilogue.h"
@@ -495,21 +496,41 @@ resident2d(Resident2D R) {
     int lmode = C.logmode;
     uint32_t count = 0;   // phases this block has published
 
+    // One phase: stage the halo of X, contract, epilogue.  Specialised at
+    // compile time on the domain (plain / log) and on whether the epilogue
+    // accumulates the stop-test partials, so the common iteration runs
+    // straight-line code.
+    using yes = std::true_type;
+    using no = std::false_type;
+    auto phase = [&](auto ek, auto logc, auto chkc, EpiArgs& E, const EpiIn& in, const float* X) {
+        constexpr int EKv = decltype(ek)::value;
+        constexpr bool LOG = decltype(logc)::value;
+        constexpr bool CHK = decltype(chkc)::value;
+        E.check = CHK ? 1 : 0;
+        if (EKv >= EK_PROX) E.write_p = CHK ? 1 : 0;
+        B.X = X;
+        f4 bx[UXM];
+        load_halo<true>(B, T, bx);
+        store_halo(S, T, bx, LOG);
+        contract_tile<EKv, true>(E, T, in, LOG, S, slot);
+    };
+    const std::integral_constant<int, EK_BUPDATE> ekb;
+    const std::integral_constant<int, PK> ekp;
+
     for (int k = 1; k <= R.K; ++k) {
         // ---- t = xi^T a, b = q / t (and the violation of the previous iterate at checks)
         const bool chk = R.checks && k > 1 && (k - 1) % R.ce == 0;
-        eb.check = chk ? 1 : 0;
         eb.t_out = R.hist ? R.hist + (2 * (int64_t)(k - 1)) * R.hist_stride : nullptr;
         EpiIn ia = inq;
         if (chk && wave == 0) ia.v = ld4_coh(R.b, T.obase, T.ocnt, 0.f);
         if (!wait_for(R.sync, nn, nbr, count, R.spin_limit)) return;
-        {
-            B.X = R.a;
-            f4 bx[UXM];
-            load_halo<true>(B, T, bx);
-            store_halo(S, T, bx, lmode != 0);
+        if (lmode) {
+            if (chk) phase(ekb, yes(), yes(), eb, ia, R.a);
+            else phase(ekb, yes(), no(), eb, ia, R.a);
+        } else {
+            if (chk) phase(ekb, no(), yes(), eb, ia, R.a);
+            else phase(ekb, no(), no(), eb, ia, R.a);
         }
-        contract_tile<EK_BUPDATE, true>(eb, T, ia, lmode != 0, S, slot);
         publish(R.sync, slot, ++count);
 
         if (chk) {
@@ -566,17 +587,15 @@ resident2d(Resident2D R) {
 
         // ---- s = xi b, p = prox(s), a = p / s (p kept at candidate iterations)
         const bool cand = (R.checks && k % R.ce == 0) || k == R.K;
-        ep.check = cand ? 1 : 0;
-        ep.write_p = cand ? 1 : 0;
         ep.s_out = R.hist ? R.hist + (2 * (int64_t)(k - 1) + 1) * R.hist_stride : nullptr;
         if (!wait_for(R.sync, nn, nbr, count, R.spin_limit)) return;
-        {
-            B.X = R.b;
-            f4 bx[UXM];
-            load_halo<true>(B, T, bx);
-            store_halo(S, T, bx, lmode != 0);
+        if (lmode) {
+            if (cand) phase(ekp, yes(), yes(), ep, inp, R.b);
+            else phase(ekp, yes(), no(), ep, inp, R.b);
+        } else {
+            if (cand) phase(ekp, no(), yes(), ep, inp, R.b);
+            else phase(ekp, no(), no(), ep, inp, R.b);
         }
-        contract_tile<PK, true>(ep, T, inp, lmode != 0, S, slot);
         publish(R.sync, slot, ++count);
     }
 }
