@@ -231,14 +231,22 @@ def cpu_baseline(wl, seconds):
     import oracle as O
     en = O.Energy(kind=wl.kind, w=wl.w, kappa=wl.kappa, kappa_scalar=wl.kappa_scalar,
                   coef=wl.coef, coef_scalar=wl.coef_scalar, m=wl.m, density_scale=wl.density_scale)
+    O.jko_step(wl.p0, en, wl.gamma, wl.tau, 5)   # warm-up (first-call costs)
     t0 = time.perf_counter()
-    O.jko_step(wl.p0, en, wl.gamma, wl.tau, 10)
-    per_it = (time.perf_counter() - t0) / 10
-    n_it = int(max(10, min(20000, seconds / per_it)))
+    O.jko_step(wl.p0, en, wl.gamma, wl.tau, 30)
+    per_it = (time.perf_counter() - t0) / 30
+    n_it = int(max(10, min(50000, seconds / per_it)))
     t0 = time.perf_counter()
     O.jko_step(wl.p0, en, wl.gamma, wl.tau, n_it)
     el = time.perf_counter() - t0
     cores = len(os.sched_getaffinity(0))
+    try:   # threads the BLAS behind numpy actually runs
+        from threadpoolctl import threadpool_info
+        blas = [t["num_threads"] for t in threadpool_info() if t.get("user_api") == "blas"]
+        if blas:
+            cores = min(cores, max(blas))
+    except Exception:
+        pass
     return {
         "value": round(n_it / el, 3), "unit": "Sinkhorn iters/s", "cores": cores, "kind": "oracle",
         "sample": f"FP64 oracle jko_step on {wl.name} {wl.shape} (separable numpy/BLAS kernel), "
