@@ -224,7 +224,7 @@ jko_status build_factors(Plan& P, double gamma) {
     for (int k = 0; k < P.g.d; ++k) P.W[k] = band_halfwidth(P.g.n[k], gamma);
     // The fused kernel trades redundant halo work for one launch per
     // application: it wins while its grid is at most one block per CU.
-    P.fused2d = P.g.d == 2 && P.prec == JKO_FP32 && gibbs2d_fits(P.g.n[0], P.g.n[1], P.W[0], P.W[1]) &&
+    P.fused2d = P.g.d == 2 && gibbs2d_fits(P.g.n[0], P.g.n[1], P.W[0], P.W[1], P.prec) &&
                 gibbs2d_blocks(P.g.n[0], P.g.n[1]) <= kFusedMaxBlocks;
     P.resident = P.fused2d;
     for (int k = 0; k < P.g.d; ++k) {
@@ -254,7 +254,7 @@ void set_vec(EpiArgs& e) {
 jko_status apply_xi(const Plan& P, const float* x, EpiArgs epi, int* nblocks) {
     set_vec(epi);
     if (P.fused2d) {
-        Band2D b{P.g.n[0], P.g.n[1], P.W[0], P.W[1], P.K1[0], P.K1[1], x};
+        Band2D b{P.g.n[0], P.g.n[1], P.W[0], P.W[1], P.K1[0], P.K1[1], x, P.K1hi[0], P.K1lo[0], P.K1hi[1], P.K1lo[1]};
         int nb = 0;
         HIP_TRY(launch_gibbs2d(b, P.prec, epi, &nb, P.st));
         if (nblocks) *nblocks = nb;
@@ -404,7 +404,7 @@ jko_status input_check(const Plan& P, const jko_energy* en, const float* p) {
 // ----------------------------------------------------------------- resident
 
 bool use_resident(const Plan& P, const jko_params* pr, const ProxArgs& px) {
-    return P.resident && !(pr->flags & JKO_FLAG_NO_RESIDENT) && resident2d_fits(P.g.n[0], P.g.n[1], P.W[0], P.W[1], px.kind);
+    return P.resident && !(pr->flags & JKO_FLAG_NO_RESIDENT) && resident2d_fits(P.g.n[0], P.g.n[1], P.W[0], P.W[1], px.kind, P.prec);
 }
 
 // Queue the resident kernel for K iterations of a step (scalings and control
@@ -412,7 +412,9 @@ bool use_resident(const Plan& P, const jko_params* pr, const ProxArgs& px) {
 jko_status launch_resident(const Plan& P, const float* q, float* p_out, const ProxArgs& px, int K, int ce,
                            bool checks, double tol, double absorb, bool record_hist) {
     Resident2D r{};
-    r.B = Band2D{P.g.n[0], P.g.n[1], P.W[0], P.W[1], P.K1[0], P.K1[1], nullptr};
+    r.B = Band2D{P.g.n[0], P.g.n[1], P.W[0], P.W[1], P.K1[0], P.K1[1], nullptr,
+                 P.K1hi[0], P.K1lo[0], P.K1hi[1], P.K1lo[1]};
+    r.split = P.prec == JKO_SPLIT_BF16 ? 1 : 0;
     r.q = q;
     r.a = P.F(F_A);
     r.b = P.F(F_B);

@@ -41,10 +41,14 @@ constexpr int kS = kHalo + 4;   // padded LDS row (floats)
 constexpr int kThr = 512;       // 8 waves per block
 constexpr int kMaxNeighbours = 9 * 9;   // halo reach of at most 4 tiles per side
 
+constexpr int kS2 = kHalo + 8;   // padded LDS row of a bfloat16 band (16-byte aligned)
+
 struct Smem {
     float Xs[kHalo * kS];   // [ib][jb]
     float Kj[kT * kS];      // [j][jb]  = K1_1[j0+j][jb0+jb]
     float Ki[kT * kS];      // [i][ib]  = K1_0[i0+i][ib0+ib]
+    uint16_t Kjh[kT * kS2], Kjl[kT * kS2];   // split path: bfloat16 hi / lo of the bands
+    uint16_t Kih[kT * kS2], Kil[kT * kS2];
     float Zs[kT * kS];      // [j][ib]
     float red[7 * 64 * 4];
     float sh1[kHalo];       // log domain: row shifts of the halo
@@ -65,7 +69,10 @@ struct Tile {
     int obase, ocnt;   // wave 0: this lane's run of outputs (i = lane & 15, j = 4 (lane >> 4) + e)
 };
 
+// Halo extents are padded to whole MFMA k-steps: 16 (FP32) or 32 (split).
+template <bool SPLIT = false>
 __device__ __forceinline__ Tile tile_of(const Band2D& B, int logical, int lane) {
+    constexpr int RND = SPLIT ? 32 : 16;
     Tile T;
     const int tiles_j = (B.n1 + kT - 1) / kT;
     T.i0 = (logical / tiles_j) * kT;
@@ -74,8 +81,8 @@ __device__ __forceinline__ Tile tile_of(const Band2D& B, int logical, int lane) 
     T.jb0 = max(0, T.j0 - B.W1) & ~3;
     T.LI = min(B.n0, T.i0 + kT + B.W0) - T.ib0;
     T.LJ = min(B.n1, T.j0 + kT + B.W1) - T.jb0;
-    T.LIp = (T.LI + 15) & ~15;
-    T.LJp = (T.LJ + 15) & ~15;
+    T.LIp = (T.LI + RND - 1) & ~(RND - 1);
+    T.LJp = (T.LJ + RND - 1) & ~(RND - 1);
     const int koff = 4 * (lane >> 4);
     const int oi = T.i0 + (lane & 15);
     T.obase = oi * B.n1 + T.j0 + koff;
@@ -199,10 +206,64 @@ __device__ __forceinline__ void store_bands(Smem& S, const Tile& T, const f4 (&b
     }
 }
 
+// Split path: stage the bfloat16 hi / lo factor bands (built from the exact
+// factor in double precision), zero outside the band.
+constexpr int UKS = kT * (kHalo / 4) / kThr;   // 4-element units per thread, per array
+
+__device__ __forceinline__ void stage_bands_split(const Band2D& B, const Tile& T, Smem& S) {
+    const int tid = threadIdx.x;
+    const int nkj = kT * (T.LJp / 4), nki = kT * (T.LIp / 4);
+    u16x4 jh[UKS], jl[UKS], ih[UKS], il[UKS];
+#pragma unroll
+    for (int u = 0; u < UKS; ++u) {
+        const int unit = tid + u * kThr;
+        jh[u] = jl[u] = ih[u] = il[u] = u16x4{0, 0, 0, 0};
+        if (unit < nkj) {
+            const int j = unit / (T.LJp / 4), c = 4 * (unit % (T.LJp / 4));
+            if (T.j0 + j < B.n1) {
+                const int64_t off = (int64_t)(T.j0 + j) * B.n1 + T.jb0 + c;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    jh[u][e] = (c + e < T.LJ) ? B.K1hi[off + e] : (uint16_t)0;
+                    jl[u][e] = (c + e < T.LJ) ? B.K1lo[off + e] : (uint16_t)0;
+                }
+            }
+        }
+        if (unit < nki) {
+            const int i = unit / (T.LIp / 4), c = 4 * (unit % (T.LIp / 4));
+            if (T.i0 + i < B.n0) {
+                const int64_t off = (int64_t)(T.i0 + i) * B.n0 + T.ib0 + c;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    ih[u][e] = (c + e < T.LI) ? B.K0hi[off + e] : (uint16_t)0;
+                    il[u][e] = (c + e < T.LI) ? B.K0lo[off + e] : (uint16_t)0;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < UKS; ++u) {
+        const int unit = tid + u * kThr;
+        if (unit < nkj) {
+            const int j = unit / (T.LJp / 4), c = 4 * (unit % (T.LJp / 4));
+            *reinterpret_cast<u16x4*>(&S.Kjh[j * kS2 + c]) = jh[u];
+            *reinterpret_cast<u16x4*>(&S.Kjl[j * kS2 + c]) = jl[u];
+        }
+        if (unit < nki) {
+            const int i = unit / (T.LIp / 4), c = 4 * (unit % (T.LIp / 4));
+            *reinterpret_cast<u16x4*>(&S.Kih[i * kS2 + c]) = ih[u];
+            *reinterpret_cast<u16x4*>(&S.Kil[i * kS2 + c]) = il[u];
+        }
+    }
+}
+
 // Both contractions of the staged tile and its epilogue (wave 0), then the
 // block's partials into slot `slot`.  Xs, Kj, Ki are staged, not yet synced.
 // COH: the scalings and partials the epilogue writes use device-scope stores.
-template <int EK, bool COH = false>
+// SPLIT: each FP32 operand (X, then Z) is split into bfloat16 hi + lo as it is
+// read and multiplied with the factor bands' hi / lo, three products
+// (hi*hi + hi*lo + lo*hi) on v_mfma_f32_16x16x32_bf16, FP32 accumulation.
+template <int EK, bool COH = false, bool SPLIT = false>
 __device__ __forceinline__ void contract_tile(const EpiArgs& E, const Tile& T, const EpiIn& ein, bool logx,
                                               Smem& S, int slot) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -229,7 +290,31 @@ __device__ __forceinline__ void contract_tile(const EpiArgs& E, const Tile& T, c
     // ---- Z = X K1_1^T over the halo rows: wave f owns the 16-row fragment f;
     // even and odd k-chunks go to two accumulators (independent MFMA chains)
     const int F = LIp / 16;
-    if (wave < F) {
+    if (SPLIT && wave < F) {
+        const int f = wave;
+        const int k8 = 8 * (lane >> 4);
+        f4 acc = f4{0.f, 0.f, 0.f, 0.f};
+        const float* xr = &S.Xs[(16 * f + (lane & 15)) * kS + k8];
+        const uint16_t* khr = &S.Kjh[(lane & 15) * kS2 + k8];
+        const uint16_t* klr = &S.Kjl[(lane & 15) * kS2 + k8];
+        for (int c0 = 0; c0 < LJp; c0 += 32) {
+            bf8 ah, al;
+            split_bf16(*reinterpret_cast<const f4*>(xr + c0), *reinterpret_cast<const f4*>(xr + c0 + 4), ah, al);
+            const bf8 bh = __builtin_bit_cast(bf8, *reinterpret_cast<const u16x8*>(khr + c0));
+            const bf8 bl = __builtin_bit_cast(bf8, *reinterpret_cast<const u16x8*>(klr + c0));
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
+        }
+        if (logx) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float m = S.sh1[16 * f + koff + e];
+                acc[e] = (m != m) ? -INFINITY : (acc[e] > 0.f ? m + logf(acc[e]) : m - 104.f);
+            }
+        }
+        *reinterpret_cast<f4*>(&S.Zs[(lane & 15) * kS + 16 * f + koff]) = acc;
+    } else if (!SPLIT && wave < F) {
         const int f = wave;
         f4 acc0 = f4{0.f, 0.f, 0.f, 0.f}, acc1 = f4{0.f, 0.f, 0.f, 0.f};
         const float* xr = &S.Xs[(16 * f + (lane & 15)) * kS + koff];
@@ -284,7 +369,19 @@ __device__ __forceinline__ void contract_tile(const EpiArgs& E, const Tile& T, c
     // ---- Y^T = Z^T K1_0^T: one 16 x 16 fragment, its 16-wide k-chunks spread
     // over the waves (at most 8 chunks), partial sums combined in a fixed order
     f4 acc = f4{0.f, 0.f, 0.f, 0.f};
-    if (16 * wave < LIp) {
+    if (SPLIT) {
+        if (32 * wave < LIp) {   // 32-wide k-chunks over the waves
+            const int c0 = 32 * wave + 8 * (lane >> 4);
+            bf8 ah, al;
+            const float* zr = &S.Zs[(lane & 15) * kS + c0];
+            split_bf16(*reinterpret_cast<const f4*>(zr), *reinterpret_cast<const f4*>(zr + 4), ah, al);
+            const bf8 bh = __builtin_bit_cast(bf8, *reinterpret_cast<const u16x8*>(&S.Kih[(lane & 15) * kS2 + c0]));
+            const bf8 bl = __builtin_bit_cast(bf8, *reinterpret_cast<const u16x8*>(&S.Kil[(lane & 15) * kS2 + c0]));
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
+        }
+    } else if (16 * wave < LIp) {
         const int c0 = 16 * wave;
         const f4 a = *reinterpret_cast<const f4*>(&S.Zs[(lane & 15) * kS + c0 + koff]);
         const f4 b = *reinterpret_cast<const f4*>(&S.Ki[(lane & 15) * kS + c0 + koff]);
@@ -310,9 +407,9 @@ __device__ __forceinline__ void contract_tile(const EpiArgs& E, const Tile& T, c
     epi_finish<COH>(E, ea, slot, S.shd);
 }
 
-template <int EK>
+template <int EK, bool SPLIT>
 __global__ void __launch_bounds__(kThr)
-gibbs2d_f32(Band2D B, EpiArgs E) {
+gibbs2d_kernel(Band2D B, EpiArgs E) {
     __shared__ __attribute__((aligned(16))) Smem S;
 
     // The control flags are read here but acted on only after the halo loads
@@ -323,21 +420,26 @@ gibbs2d_f32(Band2D B, EpiArgs E) {
         lmode = E.ctl->logmode;
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const Tile T = tile_of(B, xcd_block(), lane);
+    const Tile T = tile_of<SPLIT>(B, xcd_block(), lane);
 
     // Wave 0 finishes the tile; its epilogue inputs are fetched now, ahead of
     // the contraction.
     EpiIn ein;
     if (wave == 0) ein = epi_prefetch<EK>(E, T.obase, T.ocnt);
 
-    // every staging load is issued before the first LDS store
-    f4 bx[UXM], bj[UKM], bi[UKM];
+    // the staging loads are issued before the LDS stores
+    f4 bx[UXM];
     load_halo(B, T, bx);
-    load_bands(B, T, bj, bi);
+    if (SPLIT) {
+        stage_bands_split(B, T, S);
+    } else {
+        f4 bj[UKM], bi[UKM];
+        load_bands(B, T, bj, bi);
+        store_bands(S, T, bj, bi);
+    }
     store_halo(S, T, bx, lmode != 0);
-    store_bands(S, T, bj, bi);
     if (done) return;   // the step has stopped: nothing to compute (uniform)
-    contract_tile<EK>(E, T, ein, lmode != 0, S, (int)blockIdx.x);
+    contract_tile<EK, false, SPLIT>(E, T, ein, lmode != 0, S, (int)blockIdx.x);
 }
 
 // ------------------------------------------------------------ resident kernel
@@ -432,7 +534,7 @@ __device__ __forceinline__ bool wait_word(const uint32_t* word, uint32_t value, 
     return *shared_ok != 0;
 }
 
-template <int PK>
+template <int PK, bool SPLIT>
 __global__ void __launch_bounds__(kThr)
 resident2d(Resident2D R) {
     __shared__ __attribute__((aligned(16))) Smem S;
@@ -447,7 +549,7 @@ resident2d(Resident2D R) {
     const int slot = (int)blockIdx.x;
     Band2D B = R.B;
     const int logical = xcd_block();
-    const Tile T = tile_of(B, logical, lane);
+    const Tile T = tile_of<SPLIT>(B, logical, lane);
 
     // the blocks whose tiles lie within this tile's halo reach (and itself)
     if (tid == 0) {
@@ -480,7 +582,9 @@ resident2d(Resident2D R) {
     ep.part = R.part;
 
     // factor bands: staged once for the whole launch
-    {
+    if (SPLIT) {
+        stage_bands_split(B, T, S);
+    } else {
         f4 bj[UKM], bi[UKM];
         load_bands(B, T, bj, bi);
         store_bands(S, T, bj, bi);
@@ -512,7 +616,7 @@ resident2d(Resident2D R) {
         f4 bx[UXM];
         load_halo<true>(B, T, bx);
         store_halo(S, T, bx, LOG);
-        contract_tile<EKv, true>(E, T, in, LOG, S, slot);
+        contract_tile<EKv, true, SPLIT>(E, T, in, LOG, S, slot);
     };
     const std::integral_constant<int, EK_BUPDATE> ekb;
     const std::integral_constant<int, PK> ekp;
@@ -600,17 +704,49 @@ resident2d(Resident2D R) {
     }
 }
 
-template <int PK>
-const void* resident_fn() {
-    return reinterpret_cast<const void*>(&resident2d<PK>);
+template <bool SPLIT>
+const void* resident_kernel_of(int prox_kind) {
+    switch (prox_kind) {
+        case JKO_F_ZERO: return reinterpret_cast<const void*>(&resident2d<EK_PROX + JKO_F_ZERO, SPLIT>);
+        case JKO_F_CONGESTION: return reinterpret_cast<const void*>(&resident2d<EK_PROX + JKO_F_CONGESTION, SPLIT>);
+        case JKO_F_POROUS: return reinterpret_cast<const void*>(&resident2d<EK_PROX + JKO_F_POROUS, SPLIT>);
+        default: return reinterpret_cast<const void*>(&resident2d<EK_PROX + JKO_F_ENTROPY, SPLIT>);
+    }
 }
 
-const void* resident_kernel(int prox_kind) {
-    switch (prox_kind) {
-        case JKO_F_ZERO: return resident_fn<EK_PROX + JKO_F_ZERO>();
-        case JKO_F_CONGESTION: return resident_fn<EK_PROX + JKO_F_CONGESTION>();
-        case JKO_F_POROUS: return resident_fn<EK_PROX + JKO_F_POROUS>();
-        default: return resident_fn<EK_PROX + JKO_F_ENTROPY>();
+const void* resident_kernel(int prox_kind, bool split) {
+    return split ? resident_kernel_of<true>(prox_kind) : resident_kernel_of<false>(prox_kind);
+}
+
+template <bool SPLIT>
+void launch_g2(int ek, dim3 grid, dim3 block, const Band2D& b, const EpiArgs& epi, hipStream_t stream) {
+    switch (ek) {
+        case EK_STORE: hipLaunchKernelGGL((gibbs2d_kernel<EK_STORE, SPLIT>), grid, block, 0, stream, b, epi); break;
+        case EK_BUPDATE: hipLaunchKernelGGL((gibbs2d_kernel<EK_BUPDATE, SPLIT>), grid, block, 0, stream, b, epi); break;
+        case EK_MONITOR: hipLaunchKernelGGL((gibbs2d_kernel<EK_MONITOR, SPLIT>), grid, block, 0, stream, b, epi); break;
+        case EK_PROX + JKO_F_ZERO:
+            hipLaunchKernelGGL((gibbs2d_kernel<EK_PROX + JKO_F_ZERO, SPLIT>), grid, block, 0, stream, b, epi); break;
+        case EK_PROX + JKO_F_CONGESTION:
+            hipLaunchKernelGGL((gibbs2d_kernel<EK_PROX + JKO_F_CONGESTION, SPLIT>), grid, block, 0, stream, b, epi);
+            break;
+        case EK_PROX + JKO_F_POROUS:
+            hipLaunchKernelGGL((gibbs2d_kernel<EK_PROX + JKO_F_POROUS, SPLIT>), grid, block, 0, stream, b, epi); break;
+        case EK_PROX + JKO_F_ENTROPY:
+            hipLaunchKernelGGL((gibbs2d_kernel<EK_PROX + JKO_F_ENTROPY, SPLIT>), grid, block, 0, stream, b, epi); break;
+        case EK_ADJ_B: hipLaunchKernelGGL((gibbs2d_kernel<EK_ADJ_B, SPLIT>), grid, block, 0, stream, b, epi); break;
+        case EK_ADJ_PROX + JKO_F_ZERO:
+            hipLaunchKernelGGL((gibbs2d_kernel<EK_ADJ_PROX + JKO_F_ZERO, SPLIT>), grid, block, 0, stream, b, epi);
+            break;
+        case EK_ADJ_PROX + JKO_F_CONGESTION:
+            hipLaunchKernelGGL((gibbs2d_kernel<EK_ADJ_PROX + JKO_F_CONGESTION, SPLIT>), grid, block, 0, stream, b,
+                               epi);
+            break;
+        case EK_ADJ_PROX + JKO_F_POROUS:
+            hipLaunchKernelGGL((gibbs2d_kernel<EK_ADJ_PROX + JKO_F_POROUS, SPLIT>), grid, block, 0, stream, b, epi);
+            break;
+        default:
+            hipLaunchKernelGGL((gibbs2d_kernel<EK_ADJ_PROX + JKO_F_ENTROPY, SPLIT>), grid, block, 0, stream, b, epi);
+            break;
     }
 }
 
@@ -627,45 +763,25 @@ int64_t gibbs2d_blocks(int n0, int n1) {
     return (int64_t)((n0 + kT - 1) / kT) * ((n1 + kT - 1) / kT);
 }
 
-bool gibbs2d_fits(int n0, int n1, int W0, int W1) {
-    // halo = tile + 2 W + 3 (alignment), rounded up to 16
-    const int h0 = ((std::min(n0, kT + 2 * W0 + 3)) + 15) & ~15;
-    const int h1 = ((std::min(n1, kT + 2 * W1 + 3)) + 15) & ~15;
+bool gibbs2d_fits(int n0, int n1, int W0, int W1, int32_t precision) {
+    // halo = tile + 2 W + 3 (alignment), rounded up to 16 (32 for split)
+    const int rnd = precision == JKO_SPLIT_BF16 ? 31 : 15;
+    const int h0 = ((std::min(n0, kT + 2 * W0 + 3)) + rnd) & ~rnd;
+    const int h1 = ((std::min(n1, kT + 2 * W1 + 3)) + rnd) & ~rnd;
     return h0 <= kHalo && h1 <= kHalo;
 }
 
 hipError_t launch_gibbs2d(const Band2D& b, int32_t precision, const EpiArgs& epi, int* nblocks,
                           hipStream_t stream) {
-    (void)precision;
     const int64_t nb = gibbs2d_blocks(b.n0, b.n1);
     if (nblocks) *nblocks = (int)nb;
     const dim3 grid((unsigned)nb), block(kThr);
-    switch (ek_of(epi)) {
-        case EK_STORE: hipLaunchKernelGGL(gibbs2d_f32<EK_STORE>, grid, block, 0, stream, b, epi); break;
-        case EK_BUPDATE: hipLaunchKernelGGL(gibbs2d_f32<EK_BUPDATE>, grid, block, 0, stream, b, epi); break;
-        case EK_MONITOR: hipLaunchKernelGGL(gibbs2d_f32<EK_MONITOR>, grid, block, 0, stream, b, epi); break;
-        case EK_PROX + JKO_F_ZERO:
-            hipLaunchKernelGGL(gibbs2d_f32<EK_PROX + JKO_F_ZERO>, grid, block, 0, stream, b, epi); break;
-        case EK_PROX + JKO_F_CONGESTION:
-            hipLaunchKernelGGL(gibbs2d_f32<EK_PROX + JKO_F_CONGESTION>, grid, block, 0, stream, b, epi); break;
-        case EK_PROX + JKO_F_POROUS:
-            hipLaunchKernelGGL(gibbs2d_f32<EK_PROX + JKO_F_POROUS>, grid, block, 0, stream, b, epi); break;
-        case EK_PROX + JKO_F_ENTROPY:
-            hipLaunchKernelGGL(gibbs2d_f32<EK_PROX + JKO_F_ENTROPY>, grid, block, 0, stream, b, epi); break;
-        case EK_ADJ_B: hipLaunchKernelGGL(gibbs2d_f32<EK_ADJ_B>, grid, block, 0, stream, b, epi); break;
-        case EK_ADJ_PROX + JKO_F_ZERO:
-            hipLaunchKernelGGL(gibbs2d_f32<EK_ADJ_PROX + JKO_F_ZERO>, grid, block, 0, stream, b, epi); break;
-        case EK_ADJ_PROX + JKO_F_CONGESTION:
-            hipLaunchKernelGGL(gibbs2d_f32<EK_ADJ_PROX + JKO_F_CONGESTION>, grid, block, 0, stream, b, epi); break;
-        case EK_ADJ_PROX + JKO_F_POROUS:
-            hipLaunchKernelGGL(gibbs2d_f32<EK_ADJ_PROX + JKO_F_POROUS>, grid, block, 0, stream, b, epi); break;
-        default:
-            hipLaunchKernelGGL(gibbs2d_f32<EK_ADJ_PROX + JKO_F_ENTROPY>, grid, block, 0, stream, b, epi); break;
-    }
+    if (precision == JKO_SPLIT_BF16) launch_g2<true>(ek_of(epi), grid, block, b, epi, stream);
+    else launch_g2<false>(ek_of(epi), grid, block, b, epi, stream);
     return hipGetLastError();
 }
 
-bool resident2d_fits(int n0, int n1, int W0, int W1, int prox_kind) {
+bool resident2d_fits(int n0, int n1, int W0, int W1, int prox_kind, int32_t precision) {
     const int ti = (n0 + kT - 1) / kT, tj = (n1 + kT - 1) / kT;
     const int ri = (W0 + 3 + kT - 1) / kT, rj = (W1 + 3 + kT - 1) / kT;
     if ((int64_t)std::min(ti, 2 * ri + 1) * std::min(tj, 2 * rj + 1) > kMaxNeighbours) return false;
@@ -674,7 +790,8 @@ bool resident2d_fits(int n0, int n1, int W0, int W1, int prox_kind) {
     if (hipGetDevice(&dev) != hipSuccess) return false;
     if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return false;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return false;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, resident_kernel(prox_kind), kThr, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, resident_kernel(prox_kind, precision == JKO_SPLIT_BF16),
+                                                     kThr, 0) != hipSuccess)
         return false;
     return (int64_t)per_cu * cus >= gibbs2d_blocks(n0, n1);
 }
@@ -683,7 +800,7 @@ hipError_t launch_resident2d(const Resident2D& r, hipStream_t stream) {
     const int64_t nb = gibbs2d_blocks(r.B.n0, r.B.n1);
     Resident2D arg = r;
     void* args[] = {&arg};
-    return hipLaunchCooperativeKernel(resident_kernel(r.prox.kind), dim3((unsigned)nb), dim3(kThr), args, 0,
+    return hipLaunchCooperativeKernel(resident_kernel(r.prox.kind, r.split != 0), dim3((unsigned)nb), dim3(kThr), args, 0,
                                       stream);
 }
 

@@ -115,8 +115,12 @@ struct Band2D {
     const float* K0;       // n0 x n0
     const float* K1;       // n1 x n1
     const float* X;        // n0 x n1 input
+    const uint16_t* K0hi;  // split precision: bfloat16 hi / lo of the factors
+    const uint16_t* K0lo;
+    const uint16_t* K1hi;
+    const uint16_t* K1lo;
 };
-bool gibbs2d_fits(int n0, int n1, int W0, int W1);
+bool gibbs2d_fits(int n0, int n1, int W0, int W1, int32_t precision);
 int64_t gibbs2d_blocks(int n0, int n1);
 constexpr int64_t kFusedMaxBlocks = 256;   // one block per CU of the chip
 hipError_t launch_gibbs2d(const Band2D& b, int32_t precision, const EpiArgs& epi, int* nblocks,
@@ -146,12 +150,13 @@ struct Resident2D {
     int32_t ce;            // check cadence
     int32_t checks;        // stop test / absorption checks on
     int32_t vec_ok;        // all field pointers 16-byte aligned
-    int32_t spin_limit;    // polls before a barrier wait gives up
+    int32_t spin_limit;    // polls before a wait gives up
+    int32_t split;         // split-BF16 contractions
     double tol;
     double absorb;
 };
 // True when all blocks of the resident kernel fit on the device at once.
-bool resident2d_fits(int n0, int n1, int W0, int W1, int prox_kind);
+bool resident2d_fits(int n0, int n1, int W0, int W1, int prox_kind, int32_t precision);
 hipError_t launch_resident2d(const Resident2D& r, hipStream_t stream);
 
 // Largest |i - j| at which the float32 factor exp(-((i-j)/n)^2/gamma) can be

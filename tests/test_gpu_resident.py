@@ -50,32 +50,35 @@ def test_crowd32_same_bits(tol):
         assert res[1]["stop"] == "tol"
 
 
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
 @pytest.mark.parametrize("tol,cap", [(0.0, 300), (1e-6, 2000)])
-def test_crowd256_same_bits(tol, cap):
+def test_crowd256_same_bits(tol, cap, precision):
     """The 256x256 crowd workload at full size (256 resident blocks)."""
-    banner(f"resident crowd256 tol={tol} cap={cap}")
+    banner(f"resident crowd256 tol={tol} cap={cap} {precision}")
     wl = make_workload("crowd256")
-    res, ref = _both(wl, max_iters=cap, tol=tol, check_every=10)
+    res, ref = _both(wl, max_iters=cap, tol=tol, check_every=10, precision=precision)
     _same(res, ref)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
 @pytest.mark.parametrize("shape,kind", [((45, 70), "congestion"), ((48, 40), "entropy"), ((48, 40), "porous"),
                                         ((48, 40), "zero"), ((17, 130), "congestion")])
-def test_ragged_and_other_energies_same_bits(shape, kind):
-    banner(f"resident {shape} {kind}")
+def test_ragged_and_other_energies_same_bits(shape, kind, precision):
+    banner(f"resident {shape} {kind} {precision}")
     wl = small_case(shape, kind, seed=4)
     if kind == "porous":
         wl.density_scale = float(np.prod(wl.shape))
-    _same(*_both(wl, max_iters=60, tol=1e-7, check_every=7))
+    _same(*_both(wl, max_iters=60, tol=1e-7, check_every=7, precision=precision))
 
 
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
 @pytest.mark.parametrize("threshold", [0.0, 50.0])
-def test_log_domain_same_bits(threshold):
+def test_log_domain_same_bits(threshold, precision):
     """Absorption inside the resident launch (from the start, or switched at a
     check) matches the launch path's separate absorb kernel."""
-    banner(f"resident log domain thr={threshold}")
+    banner(f"resident log domain thr={threshold} {precision}")
     wl = make_workload("crowd32", projected=False)
-    res, ref = _both(wl, max_iters=300, check_every=10, absorb_threshold=threshold)
+    res, ref = _both(wl, max_iters=300, check_every=10, absorb_threshold=threshold, precision=precision)
     _same(res, ref)
     assert res[1]["absorptions"] == 1
 
