@@ -11,7 +11,8 @@ state carries over from step to step.
 
 Prints ONE JSON line.  `value` is Sinkhorn iterations per second (iterations
 whose result the step returns), with every input resident in HBM.  Extras:
-JKO steps/s, the split-BF16 run, the 128^3 3D flow, adjoint/forward time, and
+JKO steps/s, the split-BF16 run, the 128^3 3D flow, the 512^2 porous-medium
+flow (density-scaled), adjoint/forward time, and
 the roofline of the dominant contraction kernel from HIP-event timings of its
 launches on the library's stream.
 """
@@ -363,6 +364,12 @@ def main():
             extra[f"crowd128c_{prec}"] = {"iters_per_s": round(it3 / el3, 2), "jko_steps_per_s": round(2 / el3, 3),
                                          "iters_per_step": 300,
                                          "roofline": roofline(wl3, prec, q3, TRAFFIC_PROFILES.get(("crowd128c", prec)))}
+        wl5 = make_workload("porous512_scaled")
+        for prec in ("fp32", "split_bf16"):
+            it5, el5, st5, _ = run_flow(wl5, prec, 3, 1)
+            extra[f"porous512_scaled_{prec}"] = {"iters_per_s": round(it5 / el5, 2),
+                                                 "jko_steps_per_s": round(3 / el5, 3),
+                                                 "iters_per_step": [s["iters"] for s in st5]}
         extra["adjoint_fp32"] = adjoint_ratio("fp32")
     line["extra"] = extra
     if not args.no_cpu_baseline:

@@ -408,9 +408,13 @@ bool use_resident(const Plan& P, const jko_params* pr, const ProxArgs& px) {
 }
 
 // Queue the resident kernel for K iterations of a step (scalings and control
-// block already initialised).
+// block already initialised).  *launched is false (and nothing is queued but
+// the sync-word reset) when the runtime refuses the cooperative grid, e.g.
+// because part of the device is unavailable: the caller then runs the launch
+// path instead.
 jko_status launch_resident(const Plan& P, const float* q, float* p_out, const ProxArgs& px, int K, int ce,
-                           bool checks, double tol, double absorb, bool record_hist) {
+                           bool checks, double tol, double absorb, bool record_hist, bool* launched) {
+    *launched = false;
     Resident2D r{};
     r.B = Band2D{P.g.n[0], P.g.n[1], P.W[0], P.W[1], P.K1[0], P.K1[1], nullptr,
                  P.K1hi[0], P.K1lo[0], P.K1hi[1], P.K1lo[1]};
@@ -442,7 +446,13 @@ jko_status launch_resident(const Plan& P, const float* q, float* p_out, const Pr
     r.vec_ok = al.vec_ok && (r.hist_stride % 4 == 0);
     HIP_TRY(launch_fill(reinterpret_cast<float*>(P.sync), 0.f,
                         resident_sync_words(gibbs2d_blocks(P.g.n[0], P.g.n[1])), P.st));
-    HIP_TRY(launch_resident2d(r, P.st));
+    const hipError_t e = launch_resident2d(r, P.st);
+    if (e == hipErrorCooperativeLaunchTooLarge) {
+        (void)hipGetLastError();
+        return JKO_OK;
+    }
+    HIP_TRY(e);
+    *launched = true;
     return JKO_OK;
 }
 
@@ -499,11 +509,11 @@ jko_status run_step(const Plan& P, const jko_params* pr, const ProxArgs& px, con
     ep.part = P.part;
     ep.ctl = P.ctl;
 
-    const bool resident = use_resident(P, pr, px);
-    if (resident) {
-        jko_status s = launch_resident(P, q, p_out, px, K, ce, checks, pr->tol_l1, absorb, record_hist);
+    bool resident = false;
+    if (use_resident(P, pr, px)) {
+        jko_status s = launch_resident(P, q, p_out, px, K, ce, checks, pr->tol_l1, absorb, record_hist, &resident);
         if (s) return s;
-        if ((s = resident_check(P))) return s;
+        if (resident && (s = resident_check(P))) return s;
     }
 
     bool pending = false;   // a read-back of the control block is in flight
@@ -753,8 +763,13 @@ jko_status jko_time_iteration(const jko_grid* grid, const jko_energy* energy, co
             HIP_TRY(launch_fill(a, 1.f, g.N, P.st));
             HIP_TRY(launch_ctl_reset(P.ctl, 0, P.st));
             HIP_TRY(hipEventRecord(e0, P.st));
-            s = launch_resident(P, p_in, P.F(F_Z1), px, params->max_iters, 1, false, 0.0, 0.0, false);
+            bool launched = false;
+            s = launch_resident(P, p_in, P.F(F_Z1), px, params->max_iters, 1, false, 0.0, 0.0, false, &launched);
             if (s) break;
+            if (!launched) {
+                s = fail(JKO_ERR_HIP, "the cooperative grid of the resident kernel was refused");
+                break;
+            }
             HIP_TRY(hipEventRecord(e1, P.st));
             if ((s = resident_check(P))) break;
             float ms = 0.f;

@@ -86,7 +86,7 @@ def test_argument_errors_before_any_launch(lib):
     big = nat.make_grid((2048, 8))
     assert _call_step(lib, big, en, prm) == jk.JKO_ERR_INVALID
     for field, val in (("gamma", 0.0), ("gamma", math.nan), ("tau", -1.0), ("max_iters", 0),
-                       ("check_every", 0), ("precision", 7)):
+                       ("check_every", 0), ("precision", 7), ("flags", 2), ("flags", -1)):
         p2 = nat.make_params(1e-3, 1e-3, 10)
         setattr(p2, field, val)
         assert _call_step(lib, g, en, p2) == jk.JKO_ERR_INVALID, field
@@ -127,6 +127,15 @@ def test_gibbs_and_flow_and_backward_argument_errors(lib):
     assert lib.jko_backward(ctypes.byref(g), ctypes.byref(ent), ctypes.byref(prm), 1, iters, ctypes.c_void_p(1),
                             ctypes.c_void_p(2), ctypes.c_void_p(4), None, ctypes.c_void_p(16), 1 << 30,
                             None) == jk.JKO_ERR_INVALID
+
+
+def test_flags_field_and_binding():
+    """jko_params.flags: the resident path is the default, JKO_FLAG_NO_RESIDENT
+    keeps one launch per application (the header names the bit)."""
+    assert nat.make_params(1e-3, 1e-3).flags == 0
+    assert nat.make_params(1e-3, 1e-3, resident=False).flags == nat.FLAG_NO_RESIDENT == 1
+    hdr = open(os.path.join(ROOT, "include", "jko.h")).read()
+    assert "JKO_FLAG_NO_RESIDENT = 1" in hdr
 
 
 def test_binding_refuses_cpu_tensors():
