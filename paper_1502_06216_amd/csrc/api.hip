@@ -865,9 +865,49 @@ jko_status jko_backward(const jko_grid* grid, const jko_energy* energy, const jk
         // Gibbs applications whose epilogues carry the pointwise reverse steps:
         //   bbar = xi sbar_k  -> tbar_k, qbar += ...          (reverse of b = q / t)
         //   abar = xi tbar_k  -> sbar_{k-1}, wbar += ...      (reverse of the prox at k - 1)
+        // in one resident launch where the 2D tiles fit the chip, else one
+        // launch per application.
         HIP_TRY(launch_adj_prox(P.hist(2 * (int64_t)(K - 1) + 1), pbar, nullptr, sbar, dL_dw ? wacc : nullptr, px,
                                 sigma, N, P.st));
-        for (int k = K; k >= 1; --k) {
+        bool resident = false;
+        if (P.resident && !(params->flags & JKO_FLAG_NO_RESIDENT) &&
+            resident_adj_fits(g.n[0], g.n[1], P.W[0], P.W[1], px.kind, P.prec)) {
+            ResidentAdj r{};
+            r.B = Band2D{g.n[0], g.n[1], P.W[0], P.W[1], P.K1[0], P.K1[1], nullptr,
+                         P.K1hi[0], P.K1lo[0], P.K1hi[1], P.K1lo[1]};
+            r.q = q;
+            r.hist = P.hist(0);
+            r.hist_stride = (int64_t)(P.hist(1) - P.hist(0));
+            r.sbar = sbar;
+            r.tbar = tbar;
+            r.qbar = qbar;
+            r.wbar = dL_dw ? wacc : nullptr;
+            r.prox = px;
+            r.sigma = (float)sigma;
+            r.sync = P.sync;
+            r.K = K;
+            r.spin_limit = kBarrierSpinLimit;
+            r.split = P.prec == JKO_SPLIT_BF16 ? 1 : 0;
+            EpiArgs al{};
+            al.q = q;
+            al.y = tbar;
+            al.acc = qbar;
+            al.hin = r.hist;
+            al.prox = px;
+            set_vec(al);
+            r.vec_ok = al.vec_ok && aligned16(sbar) && aligned16(wacc) && (r.hist_stride % 4 == 0);
+            HIP_TRY(launch_fill(reinterpret_cast<float*>(P.sync), 0.f, resident_sync_words(gibbs2d_blocks(g.n[0], g.n[1])),
+                                P.st));
+            const hipError_t e = launch_resident_adj(r, P.st);
+            if (e == hipErrorCooperativeLaunchTooLarge) {
+                (void)hipGetLastError();
+            } else {
+                HIP_TRY(e);
+                resident = true;
+                if ((s = resident_check(P))) return s;
+            }
+        }
+        for (int k = K; k >= 1 && !resident; --k) {
             EpiArgs eb{};
             eb.kind = EpiKind::ADJ_B;
             eb.hin = P.hist(2 * (int64_t)(k - 1));

@@ -191,7 +191,9 @@ __device__ __forceinline__ f4 ld4_coh(const float* p, int idx, int cnt, float fi
     return r;
 }
 
-template <int EK>
+// COH: accumulators of the adjoint epilogues are read with device-scope loads
+// (the resident reverse sweep writes them with device-scope stores).
+template <int EK, bool COH = false>
 __device__ __forceinline__ EpiIn epi_prefetch(const EpiArgs& E, int idx, int cnt) {
     EpiIn in;
     in.u = f4{0.f, 0.f, 0.f, 0.f};
@@ -205,7 +207,7 @@ __device__ __forceinline__ EpiIn epi_prefetch(const EpiArgs& E, int idx, int cnt
     } else if (EK == EK_ADJ_B) {
         in.u = ld4(E.hin, idx, cnt, vec, 0.f);
         in.v = ld4(E.q, idx, cnt, vec, 0.f);
-        in.w = ld4(E.acc, idx, cnt, vec, 0.f);
+        in.w = COH ? ld4_coh(E.acc, idx, cnt, 0.f) : ld4(E.acc, idx, cnt, vec, 0.f);
     } else if (EK >= EK_ADJ_PROX) {
         const ProxArgs& px = E.prox;
         in.u = ld4(E.hin, idx, cnt, vec, 0.f);
@@ -274,8 +276,13 @@ __device__ __forceinline__ void epi_apply(const EpiArgs& E, int idx, int cnt, f4
             tb[e] = adj_b_cell(in.u[e], in.v[e], val[e], &dq);
             qb[e] = (dq != 0.f) ? in.w[e] + dq : in.w[e];
         }
-        st4(E.y, idx, cnt, vec, tb);
-        st4(E.acc, idx, cnt, vec, qb);
+        if (COH) {
+            st4_coh(E.y, idx, cnt, vec, tb);
+            st4_coh(E.acc, idx, cnt, vec, qb);
+        } else {
+            st4(E.y, idx, cnt, vec, tb);
+            st4(E.acc, idx, cnt, vec, qb);
+        }
     } else if (EK >= EK_ADJ_PROX) {
         constexpr int KIND = EK - EK_ADJ_PROX;
         f4 sb, dw;
@@ -285,13 +292,15 @@ __device__ __forceinline__ void epi_apply(const EpiArgs& E, int idx, int cnt, f4
             sb[e] = adj_prox_cell<KIND>(E.prox, E.sigma, in.u[e], 0.f, val[e], in.v[e], in.w[e], &d);
             dw[e] = d;
         }
-        st4(E.y, idx, cnt, vec, sb);
+        if (COH) st4_coh(E.y, idx, cnt, vec, sb);
+        else st4(E.y, idx, cnt, vec, sb);
         if (KIND == JKO_F_CONGESTION && E.acc) {
-            f4 wb = ld4(E.acc, idx, cnt, vec, 0.f);
+            f4 wb = COH ? ld4_coh(E.acc, idx, cnt, 0.f) : ld4(E.acc, idx, cnt, vec, 0.f);
 #pragma unroll
             for (int e = 0; e < 4; ++e)
                 if (dw[e] != 0.f) wb[e] += dw[e];
-            st4(E.acc, idx, cnt, vec, wb);
+            if (COH) st4_coh(E.acc, idx, cnt, vec, wb);
+            else st4(E.acc, idx, cnt, vec, wb);
         }
     } else if (EK == EK_MONITOR) {
 #pragma unroll

@@ -534,6 +534,21 @@ __device__ __forceinline__ bool wait_word(const uint32_t* word, uint32_t value, 
     return *shared_ok != 0;
 }
 
+// The blocks whose tiles lie within a tile's halo reach (and itself); returns
+// their number (at most kMaxNeighbours).
+__device__ __forceinline__ int neighbours_of(const Band2D& B, int logical, int nb, int* nbr) {
+    const int tiles_i = (B.n0 + kT - 1) / kT, tiles_j = (B.n1 + kT - 1) / kT;
+    const int ri = (B.W0 + 3 + kT - 1) / kT, rj = (B.W1 + 3 + kT - 1) / kT;
+    const int ti = logical / tiles_j, tj = logical % tiles_j;
+    int m = 0;
+    for (int a = max(0, ti - ri); a <= min(tiles_i - 1, ti + ri); ++a)
+        for (int b = max(0, tj - rj); b <= min(tiles_j - 1, tj + rj); ++b) {
+            const int lg = a * tiles_j + b;   // logical tile -> block index (inverse of xcd_block)
+            nbr[m++] = (nb % 8 != 0) ? lg : (lg % (nb / 8)) * 8 + lg / (nb / 8);
+        }
+    return m;
+}
+
 template <int PK, bool SPLIT>
 __global__ void __launch_bounds__(kThr)
 resident2d(Resident2D R) {
@@ -551,18 +566,8 @@ resident2d(Resident2D R) {
     const int logical = xcd_block();
     const Tile T = tile_of<SPLIT>(B, logical, lane);
 
-    // the blocks whose tiles lie within this tile's halo reach (and itself)
     if (tid == 0) {
-        const int tiles_i = (B.n0 + kT - 1) / kT, tiles_j = (B.n1 + kT - 1) / kT;
-        const int ri = (B.W0 + 3 + kT - 1) / kT, rj = (B.W1 + 3 + kT - 1) / kT;
-        const int ti = logical / tiles_j, tj = logical % tiles_j;
-        int m = 0;
-        for (int a = max(0, ti - ri); a <= min(tiles_i - 1, ti + ri); ++a)
-            for (int b = max(0, tj - rj); b <= min(tiles_j - 1, tj + rj); ++b) {
-                const int lg = a * tiles_j + b;   // logical tile -> block index (inverse of xcd_block)
-                nbr[m++] = (nb % 8 != 0) ? lg : (lg % (nb / 8)) * 8 + lg / (nb / 8);
-            }
-        n_nbr = m;
+        n_nbr = neighbours_of(B, logical, nb, nbr);
         C = *R.ctl;
     }
     for (int t = tid; t < nb; t += kThr) all[t] = t;
@@ -704,6 +709,89 @@ resident2d(Resident2D R) {
     }
 }
 
+// Reverse sweep of one step in one cooperative launch (same tiles, halo
+// waits and device-scope exchange as resident2d): for k = K .. 1,
+//   bbar = xi sbar_k  -> tbar_k = -bbar b / t,  qbar += bbar / t        (ADJ_B)
+//   abar = xi tbar_k  -> sbar_{k-1}, wbar += ...                         (ADJ_PROX, k > 1)
+// with t_k, s_k read from the recomputation's history.  Same tile code and
+// order as the launch path: bit-identical results.
+template <int AK, bool SPLIT>
+__global__ void __launch_bounds__(kThr)
+resident_adj(ResidentAdj R) {
+    __shared__ __attribute__((aligned(16))) Smem S;
+    __shared__ int nbr[kMaxNeighbours];
+    __shared__ int n_nbr;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nb = (int)gridDim.x;
+    const int slot = (int)blockIdx.x;
+    Band2D B = R.B;
+    const int logical = xcd_block();
+    const Tile T = tile_of<SPLIT>(B, logical, lane);
+    if (tid == 0) n_nbr = neighbours_of(B, logical, nb, nbr);
+    if (SPLIT) {
+        stage_bands_split(B, T, S);
+    } else {
+        f4 bj[UKM], bi[UKM];
+        load_bands(B, T, bj, bi);
+        store_bands(S, T, bj, bi);
+    }
+    EpiArgs eb{};
+    eb.kind = EpiKind::ADJ_B;
+    eb.q = R.q;
+    eb.y = R.tbar;
+    eb.acc = R.qbar;
+    eb.vec_ok = R.vec_ok;
+    EpiArgs ep{};
+    ep.kind = EpiKind::ADJ_PROX;
+    ep.y = R.sbar;
+    ep.acc = R.wbar;
+    ep.prox = R.prox;
+    ep.sigma = R.sigma;
+    ep.vec_ok = R.vec_ok;
+    __syncthreads();
+    const int nn = n_nbr;
+    uint32_t count = 0;
+    for (int k = R.K; k >= 1; --k) {
+        eb.hin = R.hist + (2 * (int64_t)(k - 1)) * R.hist_stride;
+        EpiIn ia;
+        if (wave == 0) ia = epi_prefetch<EK_ADJ_B, true>(eb, T.obase, T.ocnt);
+        if (!wait_for(R.sync, nn, nbr, count, R.spin_limit)) return;
+        {
+            B.X = R.sbar;
+            f4 bx[UXM];
+            load_halo<true>(B, T, bx);
+            store_halo(S, T, bx, false);
+        }
+        contract_tile<EK_ADJ_B, true, SPLIT>(eb, T, ia, false, S, slot);
+        publish(R.sync, slot, ++count);
+        if (k == 1) break;
+        ep.hin = R.hist + (2 * (int64_t)(k - 2) + 1) * R.hist_stride;
+        EpiIn ip;
+        if (wave == 0) ip = epi_prefetch<AK, true>(ep, T.obase, T.ocnt);
+        if (!wait_for(R.sync, nn, nbr, count, R.spin_limit)) return;
+        {
+            B.X = R.tbar;
+            f4 bx[UXM];
+            load_halo<true>(B, T, bx);
+            store_halo(S, T, bx, false);
+        }
+        contract_tile<AK, true, SPLIT>(ep, T, ip, false, S, slot);
+        publish(R.sync, slot, ++count);
+    }
+}
+
+template <bool SPLIT>
+const void* adjoint_kernel_of(int prox_kind) {
+    switch (prox_kind) {
+        case JKO_F_ZERO: return reinterpret_cast<const void*>(&resident_adj<EK_ADJ_PROX + JKO_F_ZERO, SPLIT>);
+        case JKO_F_CONGESTION:
+            return reinterpret_cast<const void*>(&resident_adj<EK_ADJ_PROX + JKO_F_CONGESTION, SPLIT>);
+        case JKO_F_POROUS: return reinterpret_cast<const void*>(&resident_adj<EK_ADJ_PROX + JKO_F_POROUS, SPLIT>);
+        default: return reinterpret_cast<const void*>(&resident_adj<EK_ADJ_PROX + JKO_F_ENTROPY, SPLIT>);
+    }
+}
+
 template <bool SPLIT>
 const void* resident_kernel_of(int prox_kind) {
     switch (prox_kind) {
@@ -779,6 +867,33 @@ hipError_t launch_gibbs2d(const Band2D& b, int32_t precision, const EpiArgs& epi
     if (precision == JKO_SPLIT_BF16) launch_g2<true>(ek_of(epi), grid, block, b, epi, stream);
     else launch_g2<false>(ek_of(epi), grid, block, b, epi, stream);
     return hipGetLastError();
+}
+
+// Every block of `fn` co-resident on the device (cooperative launch possible).
+bool grid_fits(const void* fn, int64_t blocks) {
+    int dev = 0, coop = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return false;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return false;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThr, 0) != hipSuccess) return false;
+    return (int64_t)per_cu * cus >= blocks;
+}
+
+bool resident_adj_fits(int n0, int n1, int W0, int W1, int prox_kind, int32_t precision) {
+    const int ti = (n0 + kT - 1) / kT, tj = (n1 + kT - 1) / kT;
+    const int ri = (W0 + 3 + kT - 1) / kT, rj = (W1 + 3 + kT - 1) / kT;
+    if ((int64_t)std::min(ti, 2 * ri + 1) * std::min(tj, 2 * rj + 1) > kMaxNeighbours) return false;
+    if (gibbs2d_blocks(n0, n1) > kFusedMaxBlocks) return false;
+    const void* fn = precision == JKO_SPLIT_BF16 ? adjoint_kernel_of<true>(prox_kind) : adjoint_kernel_of<false>(prox_kind);
+    return grid_fits(fn, gibbs2d_blocks(n0, n1));
+}
+
+hipError_t launch_resident_adj(const ResidentAdj& r, hipStream_t stream) {
+    const int64_t nb = gibbs2d_blocks(r.B.n0, r.B.n1);
+    ResidentAdj arg = r;
+    void* args[] = {&arg};
+    const void* fn = r.split ? adjoint_kernel_of<true>(r.prox.kind) : adjoint_kernel_of<false>(r.prox.kind);
+    return hipLaunchCooperativeKernel(fn, dim3((unsigned)nb), dim3(kThr), args, 0, stream);
 }
 
 bool resident2d_fits(int n0, int n1, int W0, int W1, int prox_kind, int32_t precision) {

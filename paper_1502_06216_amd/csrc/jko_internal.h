@@ -155,6 +155,28 @@ struct Resident2D {
     double tol;
     double absorb;
 };
+// The reverse sweep of one step in one cooperative launch (the adjoint of
+// the above, on the same tiles).
+struct ResidentAdj {
+    Band2D B;              // geometry and factors (B.X unused)
+    const float* q;        // the step's input density
+    const float* hist;     // t_k at hist + (2(k-1)) stride, s_k at + stride
+    int64_t hist_stride;   // floats
+    float* sbar;           // in: sbar_K; exchanged between blocks
+    float* tbar;           // exchanged between blocks
+    float* qbar;           // accumulated (zeroed before the launch)
+    float* wbar;           // accumulated, or NULL
+    ProxArgs prox;
+    float sigma;
+    uint32_t* sync;        // resident_sync_words(blocks), zeroed before the launch
+    int32_t K;
+    int32_t vec_ok;
+    int32_t spin_limit;
+    int32_t split;
+};
+bool resident_adj_fits(int n0, int n1, int W0, int W1, int prox_kind, int32_t precision);
+hipError_t launch_resident_adj(const ResidentAdj& r, hipStream_t stream);
+
 // True when all blocks of the resident kernel fit on the device at once.
 bool resident2d_fits(int n0, int n1, int W0, int W1, int prox_kind, int32_t precision);
 hipError_t launch_resident2d(const Resident2D& r, hipStream_t stream);

@@ -94,18 +94,20 @@ def test_nonfinite_is_reported_the_same():
         assert e.value.status == jk.JKO_ERR_NONFINITE
 
 
-def test_flow_and_adjoint_same_bits():
-    """Checkpointed flow and the adjoint's recomputation (t_k, s_k recorded by
-    the resident kernel) against the launch path."""
-    banner("resident flow + adjoint")
-    wl = make_workload("crowd32", projected=True)
+@pytest.mark.parametrize("name,steps,iters", [("crowd32", 3, 50), ("crowd256_fixed", 2, 60)])
+def test_flow_and_adjoint_same_bits(name, steps, iters):
+    """Checkpointed flow, the adjoint's recomputation (t_k, s_k recorded by
+    the resident kernel) and the resident reverse sweep against the launch
+    path."""
+    banner(f"resident flow + adjoint {name}")
+    wl = make_workload(name, projected=True) if name == "crowd32" else make_workload(name)
     g_en, _ = energies(wl)
     outs = []
     for resident in (True, False):
-        pT, st, ck = jk.flow(dev(wl.p0), g_en, wl.gamma, wl.tau, 3, max_iters=50, checkpoints=True,
+        pT, st, ck = jk.flow(dev(wl.p0), g_en, wl.gamma, wl.tau, steps, max_iters=iters, checkpoints=True,
                              resident=resident)
         dL = (2.0 * pT).contiguous()
-        gw, gp = jk.backward(ck, [50] * 3, dL, g_en, wl.gamma, wl.tau, resident=resident)
+        gw, gp = jk.backward(ck, [iters] * steps, dL, g_en, wl.gamma, wl.tau, resident=resident)
         outs.append((pT, ck, gw, gp, st))
     for a, b in zip(outs[0][:4], outs[1][:4]):
         assert torch.equal(a, b)
