@@ -524,10 +524,7 @@ jko_status run_step(const Plan& P, const jko_params* pr, const ProxArgs& px, con
         eb.t_out = record_hist ? P.hist(2 * (int64_t)(k - 1)) : nullptr;
         jko_status s = apply_xi(P, a, eb, &nb);
         if (s) return s;
-        if (eb.check) {
-            HIP_TRY(launch_ctl_check(P.ctl, P.part, nb, k, pr->tol_l1, 1, absorb, P.st));
-            if (absorb > 0.0) HIP_TRY(launch_absorb(P.ctl, a, b, P.g.N, P.st));
-        }
+        if (eb.check) HIP_TRY(launch_ctl_check(P.ctl, P.part, nb, k, pr->tol_l1, 1, absorb, P.st));
         if (eb.check && tolmode) {
             // Look at the previous stop test while this interval is queued,
             // then queue the read-back of this one.
@@ -546,6 +543,11 @@ jko_status run_step(const Plan& P, const jko_params* pr, const ProxArgs& px, con
         ep.s_out = record_hist ? P.hist(2 * (int64_t)(k - 1) + 1) : nullptr;
         s = apply_xi(P, b, ep, &nb);
         if (s) return s;
+        if (eb.check && absorb > 0.0) {
+            // a switch decided at this iteration's check takes effect now
+            HIP_TRY(launch_absorb(P.ctl, a, b, P.g.N, P.st));
+            HIP_TRY(launch_ctl_commit(P.ctl, P.st));
+        }
     }
     Ctl c{};
     if (tolmode || want_stats) {

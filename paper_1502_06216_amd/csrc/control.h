@@ -14,7 +14,8 @@ namespace jko {
 // every call (the resident kernel's blocks rely on this to agree).
 //   done      when the violation is <= tol (tol > 0) or not finite; the step
 //             returns the p of iteration iter - 1;
-//   logmode   switched on when max |log a| or max |log b| exceeds absorb.
+//   absorb_pending  set when max |log a| or max |log b| exceeds absorb: the
+//             scalings are carried as logs from the end of this iteration on.
 // COH: the partials are read with device-scope loads (written by other
 // blocks of the same launch); at most 256 of them (one per resident block).
 template <bool COH = false>
@@ -82,10 +83,11 @@ __device__ __forceinline__ void ctl_update(Ctl* c, const Partials& part, int npa
             c->done = 1;
             c->stop_iter = iter - 1;
         }
+        // the switch itself happens after this iteration's proximal
+        // half-step (the scalings are converted, then logmode is set)
         c->absorb_pending = 0;
         if (!c->done && !c->logmode && absorb > 0.0 && (mlb > absorb || (check_mass && mla > absorb))) {
             c->absorb_pending = 1;
-            c->logmode = 1;
             c->absorptions += 1;
         }
     }

@@ -642,11 +642,17 @@ resident2d(Resident2D R) {
         }
         publish(R.sync, slot, ++count);
 
+        // Stop test: block 0 waits for every block's partials, takes the
+        // decision and publishes it.  No block writes partials again before
+        // it has seen the decision, so block 0 has read them all by then.
+        // With check_every >= 2 and k < K the proximal half-step of this
+        // iteration writes no partials and no p, so the other blocks run it
+        // while block 0 decides and read the decision afterwards; a stop
+        // then discards only scalings.  Otherwise they wait for it first.
+        const bool spec = chk && R.ce >= 2 && k < R.K;
+        const uint32_t chk_count = count;
+        uint32_t decision = 0;
         if (chk) {
-            // Block 0 waits for every block's partials, takes the decision and
-            // publishes it; the others wait for the decision.  No block writes
-            // partials again before it has seen the decision, so block 0 has
-            // read them all by then.
             if (slot == 0) {
                 if (!wait_for(R.sync, nb, all, count, R.spin_limit)) return;
                 if (wave == 0) ctl_update<true>(&C, R.part, nb, k, R.tol, 1, R.absorb);
@@ -666,31 +672,15 @@ resident2d(Resident2D R) {
                     __hip_atomic_store(R.sync + kDecision, (uint32_t)(C.done | (C.absorb_pending << 1)),
                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
-                publish_word(R.sync + kDecisionSeq, count);
+                publish_word(R.sync + kDecisionSeq, chk_count);
             }
-            if (!wait_word(R.sync + kDecisionSeq, count, R.sync, R.spin_limit, &okw)) return;
-            if (tid == 0)
-                word = __hip_atomic_load(R.sync + kDecision, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __syncthreads();
-            const uint32_t decision = word;
-            if (decision & 1u) return;   // same decision in every block
-            if (decision & 2u) {
-                // a <- log a, b <- log b on this block's own tile
-                if (tid < kT * kT) {
-                    const int i = T.i0 + tid / kT, j = T.j0 + tid % kT;
-                    if (i < B.n0 && j < B.n1) {
-                        float* pa = R.a + (int64_t)i * B.n1 + j;
-                        float* pb = R.b + (int64_t)i * B.n1 + j;
-                        const float av = __hip_atomic_load(pa, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        const float bv = __hip_atomic_load(pb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        __hip_atomic_store(pa, av > 0.f ? logf(av) : -INFINITY, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                        __hip_atomic_store(pb, bv > 0.f ? logf(bv) : -INFINITY, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                    }
-                }
-                lmode = 1;
-                publish(R.sync, slot, ++count);
+            if (!spec) {
+                if (!wait_word(R.sync + kDecisionSeq, chk_count, R.sync, R.spin_limit, &okw)) return;
+                if (tid == 0)
+                    word = __hip_atomic_load(R.sync + kDecision, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __syncthreads();
+                decision = word;
+                if (decision & 1u) return;   // same decision in every block
             }
         }
 
@@ -706,6 +696,42 @@ resident2d(Resident2D R) {
             else phase(ekp, no(), no(), ep, inp, R.b);
         }
         publish(R.sync, slot, ++count);
+
+        if (chk) {
+            if (spec) {
+                if (!wait_word(R.sync + kDecisionSeq, chk_count, R.sync, R.spin_limit, &okw)) return;
+                if (tid == 0)
+                    word = __hip_atomic_load(R.sync + kDecision, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __syncthreads();
+                decision = word;
+                if (decision & 1u) return;   // same decision in every block
+            }
+            if (decision & 2u) {
+                // the switch takes effect after this proximal half-step:
+                // a <- log a, b <- log b on this block's own tile
+                if (tid < kT * kT) {
+                    const int i = T.i0 + tid / kT, j = T.j0 + tid % kT;
+                    if (i < B.n0 && j < B.n1) {
+                        float* pa = R.a + (int64_t)i * B.n1 + j;
+                        float* pb = R.b + (int64_t)i * B.n1 + j;
+                        const float av = __hip_atomic_load(pa, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        const float bv = __hip_atomic_load(pb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(pa, av > 0.f ? logf(av) : -INFINITY, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(pb, bv > 0.f ? logf(bv) : -INFINITY, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                }
+                lmode = 1;
+                if (slot == 0 && tid == 0) {
+                    C.logmode = 1;
+                    C.absorb_pending = 0;
+                    R.ctl->logmode = 1;
+                    R.ctl->absorb_pending = 0;
+                }
+                publish(R.sync, slot, ++count);
+            }
+        }
     }
 }
 

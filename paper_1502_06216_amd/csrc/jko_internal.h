@@ -21,7 +21,8 @@ struct Ctl {
     int32_t stop_iter;     // iterations whose p is returned (valid when done by tolerance)
     int32_t nonfinite;     // 1 if the monitor saw NaN/inf
     int32_t absorptions;
-    int32_t absorb_pending;  // 1 when the last check switched to the log domain
+    int32_t absorb_pending;  // 1 when the last check asked for the log domain: a, b are
+                             //    converted after that iteration's proximal half-step
     int32_t logmode;         // 1: the scalings a, b are stored as log a, log b and every
                              //    contraction runs log-in / log-out with per-fibre shifts
     int32_t pad[2];
@@ -199,6 +200,8 @@ hipError_t launch_ctl_check(Ctl* ctl, Partials part, int nparts, int iter, doubl
                             int check_mass, double absorb, hipStream_t s);
 // a <- log a, b <- log b when the last check asked for the switch.
 hipError_t launch_absorb(Ctl* ctl, float* a, float* b, int64_t N, hipStream_t s);
+// After launch_absorb: logmode <- 1 if the switch was pending; pending <- 0.
+hipError_t launch_ctl_commit(Ctl* ctl, hipStream_t s);
 // FP64 sums of p_in, of kappa (or kappa_s * N) and non-finite / negative
 // detection of p_in; results to out[0..3] (device doubles).
 hipError_t launch_input_check(const float* p_in, const float* kappa, float kappa_s, int64_t N,

@@ -141,6 +141,13 @@ __global__ void k_absorb(const Ctl* c, float* __restrict__ a, float* __restrict_
     }
 }
 
+__global__ void k_ctl_commit(Ctl* c) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        if (c->absorb_pending && !c->done) c->logmode = 1;
+        c->absorb_pending = 0;
+    }
+}
+
 __global__ void __launch_bounds__(256) k_input_partial(const float* p, const float* kappa, float kappa_s,
                                                        int64_t N, int congestion, double* part) {
     __shared__ double sh[256];
@@ -257,6 +264,11 @@ hipError_t launch_ctl_check(Ctl* ctl, Partials part, int nparts, int iter, doubl
 
 hipError_t launch_absorb(Ctl* ctl, float* a, float* b, int64_t N, hipStream_t s) {
     hipLaunchKernelGGL(k_absorb, dim3(blocks_for(N, 1024)), dim3(256), 0, s, ctl, a, b, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_ctl_commit(Ctl* ctl, hipStream_t s) {
+    hipLaunchKernelGGL(k_ctl_commit, dim3(1), dim3(64), 0, s, ctl);
     return hipGetLastError();
 }
 
