@@ -154,3 +154,16 @@ def test_crowd256_flow_many_steps_same_bits():
     for s1, s2 in zip(outs[0][2], outs[1][2]):
         for k in STAT_KEYS:
             assert s1[k] == s2[k]
+
+
+@pytest.mark.parametrize("ce,tol,thr", [(1, 1e-6, float("inf")), (2, 1e-6, float("inf")), (3, 0.0, 50.0),
+                                        (1, 0.0, 50.0), (7, 1e-7, 50.0)])
+def test_check_cadences_same_bits(ce, tol, thr):
+    """Every check cadence: checks every iteration (the decision is awaited
+    before the proximal half-step), and cadences >= 2 (the half-step overlaps
+    the decision), with and without an absorption switch, stopping early or
+    at the cap."""
+    banner(f"resident cadence ce={ce} tol={tol} thr={thr}")
+    wl = make_workload("crowd32", projected=False)
+    res, ref = _both(wl, max_iters=400, tol=tol, check_every=ce, absorb_threshold=thr)
+    _same(res, ref)
