@@ -158,7 +158,8 @@ def roofline(wl, precision, q, traffic_profile=None, resident=True):
 
     Algorithmic work per launch:
       flops  the dense separable contraction, 2 n_k N per axis pass
-             (2 (n0 + n1) N for a fused 2D application);
+             (2 (n0 + n1) N for a fused 2D application, 2 (n1 + n2) N for
+             a 3D plane pass);
       bytes  each field read or written once: a pass without epilogue reads
              X and writes Y (8 B/cell); the b-update epilogue reads t's input,
              q and writes b (12 B/cell); the prox epilogue reads s's input and
@@ -192,6 +193,15 @@ def roofline(wl, precision, q, traffic_profile=None, resident=True):
         kfile = "gibbs2d.hip"
         W = [band_halfwidth(n, wl.gamma) for n in wl.shape]
         executed = fused2d_executed_flops(wl.shape[0], wl.shape[1], W[0], W[1])
+    elif len(ms) == 4 and d == 3:
+        # plane pass (axes 1 and 2, intermediate on chip), then the axis-0 pass with the epilogue
+        fp, fs = 2.0 * (wl.shape[1] + wl.shape[2]) * N, 2.0 * wl.shape[0] * N
+        flops = [fp, fs, fp, fs]
+        nbytes = [8.0 * N, 12.0 * N, 8.0 * N, (8.0 + fb) * N]
+        names = ["plane pass (axes 1, 2)", "axis-0 pass, b-update epilogue",
+                 "plane pass (axes 1, 2)", "axis-0 pass, prox epilogue"]
+        kfile = "contract.hip"
+        executed = None
     else:
         order = list(range(d - 1, -1, -1)) * 2
         flops = [2.0 * wl.shape[ax] * N for ax in order]

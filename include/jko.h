@@ -114,8 +114,12 @@ typedef struct {
  * JKO_FLAG_NO_RESIDENT: on 2D grids whose fused kernel fits the chip in one
  *   wave of blocks, a step's whole iteration normally runs in one cooperative
  *   launch (the resident kernel); this flag keeps one launch per Gibbs
- *   application instead.  Both paths give the same bits. */
-typedef enum { JKO_FLAG_NO_RESIDENT = 1 } jko_flags;
+ *   application instead.  Both paths give the same bits.
+ * JKO_FLAG_AXIS_PASSES: on 3D grids whose axes are multiples of 32 (the
+ *   second at most 128), an application of xi normally runs as a plane pass
+ *   (axes 1 and 2 of each plane, the intermediate kept on chip) and an axis-0
+ *   pass; this flag runs three axis passes instead.  Both give the same bits. */
+typedef enum { JKO_FLAG_NO_RESIDENT = 1, JKO_FLAG_AXIS_PASSES = 2 } jko_flags;
 
 typedef enum { JKO_STOP_TOL = 0, JKO_STOP_CAP = 1 } jko_stop_reason;
 

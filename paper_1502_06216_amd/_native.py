@@ -30,6 +30,7 @@ PRECISIONS = {"fp32": 0, "split_bf16": 1}
 ENERGY_KINDS = {"zero": 0, "congestion": 1, "porous": 2, "entropy": 3}
 OP_GIBBS, OP_STEP, OP_FLOW, OP_BACKWARD = 0, 1, 2, 3
 FLAG_NO_RESIDENT = 1   # jko_flags: keep one launch per Gibbs application
+FLAG_AXIS_PASSES = 2   # jko_flags: 3D applications as three axis passes
 
 
 class JKOError(RuntimeError):
@@ -170,7 +171,7 @@ class EnergySpec:
 
 
 def make_params(gamma, tau, max_iters=300, tol=0.0, check_every=10, precision="fp32",
-                absorb_threshold=math.inf, resident=True) -> Params:
+                absorb_threshold=math.inf, resident=True, planes=True) -> Params:
     p = Params()
     p.gamma = float(gamma)
     p.tau = float(tau)
@@ -178,7 +179,7 @@ def make_params(gamma, tau, max_iters=300, tol=0.0, check_every=10, precision="f
     p.max_iters = int(max_iters)
     p.check_every = int(check_every)
     p.precision = PRECISIONS[precision]
-    p.flags = 0 if resident else FLAG_NO_RESIDENT
+    p.flags = (0 if resident else FLAG_NO_RESIDENT) | (0 if planes else FLAG_AXIS_PASSES)
     p.absorb_threshold = float(absorb_threshold)
     return p
 
@@ -207,16 +208,18 @@ def gibbs_apply(x: torch.Tensor, gamma: float, precision: str = "fp32",
 def step(p: torch.Tensor, energy: EnergySpec, gamma: float, tau: float, max_iters: int = 300,
          tol: float = 0.0, check_every: int = 10, precision: str = "fp32",
          absorb_threshold: float = math.inf, out: Optional[torch.Tensor] = None,
-         with_stats: bool = True, resident: bool = True):
+         with_stats: bool = True, resident: bool = True, planes: bool = True):
     """One JKO step p -> argmin_p' W_gamma(p', p) + tau f(p').  Returns
     (p_next, stats dict or None).  resident=False keeps one launch per Gibbs
-    application where the resident 2D kernel would run the step."""
+    application where the resident 2D kernel would run the step; planes=False
+    runs 3D applications as three axis passes instead of a plane pass and an
+    axis-0 pass."""
     lib = load()
     shape = tuple(p.shape)
     _field(p, shape, "p")
     pout = torch.empty_like(p) if out is None else _field(out, shape, "out")
     g = make_grid(shape)
-    prm = make_params(gamma, tau, max_iters, tol, check_every, precision, absorb_threshold, resident)
+    prm = make_params(gamma, tau, max_iters, tol, check_every, precision, absorb_threshold, resident, planes)
     e = energy.to_c(shape)
     nb = lib.jko_workspace_bytes(ctypes.byref(g), ctypes.byref(prm), OP_STEP, 0)
     ws = _workspace(nb, p.device)
@@ -229,7 +232,7 @@ def step(p: torch.Tensor, energy: EnergySpec, gamma: float, tau: float, max_iter
 def flow(p0: torch.Tensor, energy: EnergySpec, gamma: float, tau: float, n_steps: int,
          max_iters: int = 300, tol: float = 0.0, check_every: int = 10, precision: str = "fp32",
          absorb_threshold: float = math.inf, checkpoints: bool = False, with_stats: bool = True,
-         out: Optional[torch.Tensor] = None, resident: bool = True):
+         out: Optional[torch.Tensor] = None, resident: bool = True, planes: bool = True):
     """n_steps JKO steps from p0.  Returns (p_T, stats list or None,
     checkpoints tensor (n_steps, *shape) or None)."""
     lib = load()
@@ -238,7 +241,7 @@ def flow(p0: torch.Tensor, energy: EnergySpec, gamma: float, tau: float, n_steps
     pT = torch.empty_like(p0) if out is None else _field(out, shape, "out")
     ck = torch.empty((n_steps,) + shape, dtype=torch.float32, device=p0.device) if checkpoints else None
     g = make_grid(shape)
-    prm = make_params(gamma, tau, max_iters, tol, check_every, precision, absorb_threshold, resident)
+    prm = make_params(gamma, tau, max_iters, tol, check_every, precision, absorb_threshold, resident, planes)
     e = energy.to_c(shape)
     nb = lib.jko_workspace_bytes(ctypes.byref(g), ctypes.byref(prm), OP_FLOW, n_steps)
     ws = _workspace(nb, p0.device)
@@ -250,7 +253,7 @@ def flow(p0: torch.Tensor, energy: EnergySpec, gamma: float, tau: float, n_steps
 
 def backward(checkpoints: torch.Tensor, iters_per_step: Sequence[int], dL_dpT: torch.Tensor,
              energy: EnergySpec, gamma: float, tau: float, precision: str = "fp32",
-             want_w: bool = True, want_p0: bool = True, resident: bool = True):
+             want_w: bool = True, want_p0: bool = True, resident: bool = True, planes: bool = True):
     """Gradients (dL/dw or None, dL/dp0 or None) of L(p_T) through the flow
     recorded in `checkpoints` at the given iteration counts."""
     lib = load()
@@ -261,7 +264,7 @@ def backward(checkpoints: torch.Tensor, iters_per_step: Sequence[int], dL_dpT: t
     _field(dL_dpT, shape, "dL_dpT")
     iters = (ctypes.c_int32 * n_steps)(*[int(k) for k in iters_per_step])
     g = make_grid(shape)
-    prm = make_params(gamma, tau, max(iters_per_step), 0.0, 1, precision, resident=resident)
+    prm = make_params(gamma, tau, max(iters_per_step), 0.0, 1, precision, resident=resident, planes=planes)
     e = energy.to_c(shape)
     nb = lib.jko_workspace_bytes(ctypes.byref(g), ctypes.byref(prm), OP_BACKWARD, max(iters_per_step))
     ws = _workspace(nb, dL_dpT.device)
@@ -274,7 +277,8 @@ def backward(checkpoints: torch.Tensor, iters_per_step: Sequence[int], dL_dpT: t
 
 
 def time_iteration(p: torch.Tensor, energy: EnergySpec, gamma: float, tau: float,
-                   precision: str = "fp32", reps: int = 50, iters: int = 1, resident: bool = True):
+                   precision: str = "fp32", reps: int = 50, iters: int = 1, resident: bool = True,
+                   planes: bool = True):
     """Mean duration (ms) of each kernel launch, in launch order, timed with
     HIP events on the current stream (measurement aid): the launches of one
     iteration, or the one resident launch running `iters` iterations."""
@@ -282,7 +286,7 @@ def time_iteration(p: torch.Tensor, energy: EnergySpec, gamma: float, tau: float
     shape = tuple(p.shape)
     _field(p, shape, "p")
     g = make_grid(shape)
-    prm = make_params(gamma, tau, iters, 0.0, 1, precision, resident=resident)
+    prm = make_params(gamma, tau, iters, 0.0, 1, precision, resident=resident, planes=planes)
     e = energy.to_c(shape)
     nb = lib.jko_workspace_bytes(ctypes.byref(g), ctypes.byref(prm), OP_STEP, 0)
     ws = _workspace(nb, p.device)

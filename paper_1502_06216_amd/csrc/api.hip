@@ -112,6 +112,12 @@ int part_cap_of(const Geo& g) {
         const int64_t b = contract_max_blocks(make_pass(ps), 0);
         if (b > cap) cap = b;
     }
+    if (g.d == 3) {
+        Pass s{};
+        s.R = (int64_t)g.n[1] * g.n[2];
+        s.n = g.n[0];
+        cap = std::max<int64_t>(cap, contract_slow_blocks(s));
+    }
     return (int)cap;
 }
 
@@ -179,6 +185,7 @@ struct Plan {
     int W[3] = {0, 0, 0};        // float32 band half-widths of the factors
     bool fused2d = false;        // 2D applications use the fused band kernel
     bool resident = false;       // ... and a step may run in one resident launch
+    bool plane3d = false;        // 3D applications run as a plane pass and a slow-axis pass
 
     float* F(int i) const { return field[i]; }
     float* hist(int64_t i) const {
@@ -220,8 +227,10 @@ jko_status carve(Plan* P, const Geo& g, int op, int64_t extra, void* ws, size_t 
     return JKO_OK;
 }
 
-jko_status build_factors(Plan& P, double gamma) {
+jko_status build_factors(Plan& P, double gamma, int32_t flags = 0) {
     for (int k = 0; k < P.g.d; ++k) P.W[k] = band_halfwidth(P.g.n[k], gamma);
+    P.plane3d = P.g.d == 3 && !(flags & JKO_FLAG_AXIS_PASSES) &&
+                plane3d_fits(P.g.n[0], P.g.n[1], P.g.n[2], P.W[0], P.W[1], P.W[2]);
     // The fused kernel trades redundant halo work for one launch per
     // application: it wins while its grid is at most one block per CU.
     P.fused2d = P.g.d == 2 && gibbs2d_fits(P.g.n[0], P.g.n[1], P.W[0], P.W[1], P.prec) &&
@@ -249,6 +258,23 @@ void set_vec(EpiArgs& e) {
     e.vec_ok = ok ? 1 : 0;
 }
 
+// The plane pass of a 3D application (x -> z1) and its slow-axis pass (z1 -> epilogue).
+Plane3D plane_of(const Plan& P, const float* x, const Ctl* ctl) {
+    return Plane3D{P.g.n[0], P.g.n[1], P.g.n[2], P.W[1], P.W[2], P.K1[1], P.K1hi[1], P.K1lo[1],
+                   P.K1[2], P.K1hi[2], P.K1lo[2], x, P.F(F_Z1), ctl};
+}
+Pass slow_of(const Plan& P) {
+    Pass s{};
+    s.R = (int64_t)P.g.n[1] * P.g.n[2];
+    s.n = P.g.n[0];
+    s.W = P.W[0];
+    s.K1 = P.K1[0];
+    s.K1hi = P.K1hi[0];
+    s.K1lo = P.K1lo[0];
+    s.X = P.F(F_Z1);
+    return s;
+}
+
 // y = xi x with the last pass's result handed to `epi`.  Uses z1, z2 as
 // intermediates; x must not alias them.  *nblocks = blocks of the last pass.
 jko_status apply_xi(const Plan& P, const float* x, EpiArgs epi, int* nblocks) {
@@ -257,6 +283,13 @@ jko_status apply_xi(const Plan& P, const float* x, EpiArgs epi, int* nblocks) {
         Band2D b{P.g.n[0], P.g.n[1], P.W[0], P.W[1], P.K1[0], P.K1[1], x, P.K1hi[0], P.K1lo[0], P.K1hi[1], P.K1lo[1]};
         int nb = 0;
         HIP_TRY(launch_gibbs2d(b, P.prec, epi, &nb, P.st));
+        if (nblocks) *nblocks = nb;
+        return JKO_OK;
+    }
+    if (P.plane3d) {
+        HIP_TRY(launch_plane3d(plane_of(P, x, epi.ctl), P.prec, nullptr, P.st));
+        int nb = 0;
+        HIP_TRY(launch_contract_slow(slow_of(P), P.prec, epi, &nb, P.st));
         if (nblocks) *nblocks = nb;
         return JKO_OK;
     }
@@ -329,7 +362,8 @@ jko_status check_params(const jko_params* pr) {
     if (pr->precision != JKO_FP32 && pr->precision != JKO_SPLIT_BF16)
         return fail(JKO_ERR_INVALID, "unknown precision %d", pr->precision);
     if (isnan(pr->tol_l1)) return fail(JKO_ERR_INVALID, "tol_l1 is NaN");
-    if (pr->flags & ~JKO_FLAG_NO_RESIDENT) return fail(JKO_ERR_INVALID, "unknown flags 0x%x", pr->flags);
+    if (pr->flags & ~(JKO_FLAG_NO_RESIDENT | JKO_FLAG_AXIS_PASSES))
+        return fail(JKO_ERR_INVALID, "unknown flags 0x%x", pr->flags);
     return JKO_OK;
 }
 
@@ -657,7 +691,7 @@ jko_status jko_step(const jko_grid* grid, const jko_energy* energy, const jko_pa
     if (s) return s;
     if ((s = readback_init())) return s;
     const double sigma = params->tau / params->gamma;
-    if ((s = build_factors(P, params->gamma))) return s;
+    if ((s = build_factors(P, params->gamma, params->flags))) return s;
     if ((s = prepare_energy(P, energy, sigma))) return s;
     if ((s = input_check(P, energy, p_in))) return s;
     const ProxArgs px = prox_args(P, energy, sigma);
@@ -680,7 +714,7 @@ jko_status jko_flow(const jko_grid* grid, const jko_energy* energy, const jko_pa
     if (s) return s;
     if ((s = readback_init())) return s;
     const double sigma = params->tau / params->gamma;
-    if ((s = build_factors(P, params->gamma))) return s;
+    if ((s = build_factors(P, params->gamma, params->flags))) return s;
     if ((s = prepare_energy(P, energy, sigma))) return s;
     if ((s = input_check(P, energy, p0))) return s;
     const ProxArgs px = prox_args(P, energy, sigma);
@@ -714,7 +748,7 @@ jko_status jko_time_iteration(const jko_grid* grid, const jko_energy* energy, co
     s = carve(&P, g, OP_STEP, 0, ws, ws_bytes, params->precision, static_cast<hipStream_t>(stream));
     if (s) return s;
     const double sigma = params->tau / params->gamma;
-    if ((s = build_factors(P, params->gamma))) return s;
+    if ((s = build_factors(P, params->gamma, params->flags))) return s;
     if ((s = prepare_energy(P, energy, sigma))) return s;
     const ProxArgs px = prox_args(P, energy, sigma);
     float* a = P.F(F_A);
@@ -783,6 +817,22 @@ jko_status jko_time_iteration(const jko_grid* grid, const jko_energy* energy, co
         // one launch per application
         s = timed([&]() { return apply_xi(P, a, eb, nullptr); }, &ms_per_launch[slot++]);
         if (!s) s = timed([&]() { return apply_xi(P, b, ep, nullptr); }, &ms_per_launch[slot++]);
+    } else if (P.plane3d) {
+        // per application: the plane pass, then the axis-0 pass with the epilogue
+        for (int app = 0; app < 2 && !s; ++app) {
+            const float* x = app == 0 ? a : b;
+            s = timed([&]() -> jko_status {
+                HIP_TRY(launch_plane3d(plane_of(P, x, P.ctl), P.prec, nullptr, P.st));
+                return JKO_OK;
+            }, &ms_per_launch[slot++]);
+            if (s) break;
+            const EpiArgs e = app == 0 ? eb : ep;
+            s = timed([&]() -> jko_status {
+                int nb = 0;
+                HIP_TRY(launch_contract_slow(slow_of(P), P.prec, e, &nb, P.st));
+                return JKO_OK;
+            }, &ms_per_launch[slot++]);
+        }
     } else {
         const std::vector<PassShape> ps = passes_of(g);
         for (int app = 0; app < 2 && !s; ++app) {
@@ -841,7 +891,7 @@ jko_status jko_backward(const jko_grid* grid, const jko_energy* energy, const jk
     if (s) return s;
     if ((s = readback_init())) return s;
     const double sigma = params->tau / params->gamma;
-    if ((s = build_factors(P, params->gamma))) return s;
+    if ((s = build_factors(P, params->gamma, params->flags))) return s;
     if ((s = prepare_energy(P, energy, sigma))) return s;
     const ProxArgs px = prox_args(P, energy, sigma);
     const int64_t N = g.N;

@@ -385,6 +385,33 @@ contract_rot(Pass P, EpiArgs E) {
 constexpr int kPanelMax = 5;      // panels per tile band (160 k)
 constexpr int kBufRsrcWord3 = 0x00020000;
 
+// Wait until at most `n` (0 .. 15) of this wave's vector memory operations are
+// outstanding; they complete in issue order.
+template <int N>
+__device__ __forceinline__ void wait_vm_n() {
+    __builtin_amdgcn_s_waitcnt(N | (0x7 << 4) | (0xF << 8));   // expcnt, lgkmcnt: no wait
+}
+__device__ __forceinline__ void wait_vm(int n) {
+    switch (n) {
+        case 0: wait_vm_n<0>(); break;
+        case 1: wait_vm_n<1>(); break;
+        case 2: wait_vm_n<2>(); break;
+        case 3: wait_vm_n<3>(); break;
+        case 4: wait_vm_n<4>(); break;
+        case 5: wait_vm_n<5>(); break;
+        case 6: wait_vm_n<6>(); break;
+        case 7: wait_vm_n<7>(); break;
+        case 8: wait_vm_n<8>(); break;
+        case 9: wait_vm_n<9>(); break;
+        case 10: wait_vm_n<10>(); break;
+        case 11: wait_vm_n<11>(); break;
+        case 12: wait_vm_n<12>(); break;
+        case 13: wait_vm_n<13>(); break;
+        case 14: wait_vm_n<14>(); break;
+        default: wait_vm_n<15>(); break;
+    }
+}
+
 __device__ __forceinline__ void lds_copy16(__amdgpu_buffer_rsrc_t rs, void* lds, int voff) {
     __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)lds, 16, voff, 0, 0, 0);
 }
@@ -434,53 +461,63 @@ contract_panel(Pass P, EpiArgs E) {
         eidx[u] = i * R + r;
         ein[u] = epi_prefetch<EK>(E, eidx[u], ecnt[u]);
     }
+    // Staging copies panel by panel (this wave's X rows of the panel, then its
+    // K rows), CPP copies per wave and panel, so that panel p has landed once
+    // at most (NP - 1 - p) * CPP of this wave's copies are outstanding.
+    constexpr int XPP = TR / 8;                     // 8-row X copies per panel
+    constexpr int KQ = SPLIT ? 2 * (TI / 16) : TI / 8;   // K copies per panel (hi and lo rows)
+    static_assert(XPP % 4 == 0 && KQ % 4 == 0, "copies spread evenly over the four waves");
+    constexpr int CPP = XPP / 4 + KQ / 4;
+    static_assert((kPanelMax - 1) * CPP <= 15, "per-panel wait counts fit wait_vm");
     {
         const __amdgpu_buffer_rsrc_t rx =
             __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(P.X), (short)0, R * n * 4, kBufRsrcWord3);
-        // X: 8 rows of one panel per wave-wide copy
-        constexpr int XPP = TR / 8;
-        const int nX = NP * XPP;
+        const __amdgpu_buffer_rsrc_t rk = __builtin_amdgcn_make_buffer_rsrc(
+            SPLIT ? (void*)const_cast<uint16_t*>(P.K1hi) : (void*)const_cast<float*>(P.K1), (short)0,
+            SPLIT ? n * n * 2 : n * n * 4, kBufRsrcWord3);
+        const __amdgpu_buffer_rsrc_t rkl = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<uint16_t*>(SPLIT ? P.K1lo : P.K1hi), (short)0, n * n * 2, kBufRsrcWord3);
         const int xrow = lane >> 3, xch = lane & 7;
-        for (int j = wave; j < nX; j += kThreads / 64) {
-            const int pnl = j / XPP, row = (j % XPP) * 8 + xrow;
-            const int col = kb0 + 32 * pnl + 4 * (xch ^ ((row >> 1) & 7));
-            lds_copy16(rx, Xs + j * 256, 4 * ((r0 + row) * n + col));
-        }
-        if (SPLIT) {
-            const __amdgpu_buffer_rsrc_t rh = __builtin_amdgcn_make_buffer_rsrc(
-                const_cast<uint16_t*>(P.K1hi), (short)0, n * n * 2, kBufRsrcWord3);
-            const __amdgpu_buffer_rsrc_t rl = __builtin_amdgcn_make_buffer_rsrc(
-                const_cast<uint16_t*>(P.K1lo), (short)0, n * n * 2, kBufRsrcWord3);
-            // 16 rows of one bf16 panel per wave-wide copy
-            constexpr int KPP = TI / 16;
-            const int nK = NP * KPP;
-            const int krow = lane >> 2, kch = lane & 3;
-            for (int j = wave; j < 2 * nK; j += kThreads / 64) {
-                const int jj = j < nK ? j : j - nK;
-                const int pnl = jj / KPP, row = (jj % KPP) * 16 + krow;
-                const int col = kb0 + 32 * pnl + 8 * (kch ^ ((row >> 2) & 3));
-                const int voff = 2 * ((i0 + row) * n + col);
-                if (j < nK) lds_copy16(rh, Kh + jj * 512, voff);
-                else lds_copy16(rl, Kl + jj * 512, voff);
-            }
-        } else {
-            const __amdgpu_buffer_rsrc_t rk = __builtin_amdgcn_make_buffer_rsrc(
-                const_cast<float*>(P.K1), (short)0, n * n * 4, kBufRsrcWord3);
-            constexpr int KPP = TI / 8;
-            const int nK = NP * KPP;
-            for (int j = wave; j < nK; j += kThreads / 64) {
-                const int pnl = j / KPP, row = (j % KPP) * 8 + xrow;
+        const int krow = lane >> 2, kch = lane & 3;
+        for (int pnl = 0; pnl < NP; ++pnl) {
+            // X: 8 rows of the panel per wave-wide copy
+#pragma unroll
+            for (int q = wave; q < XPP; q += kThreads / 64) {
+                const int j = pnl * XPP + q, row = q * 8 + xrow;
                 const int col = kb0 + 32 * pnl + 4 * (xch ^ ((row >> 1) & 7));
-                lds_copy16(rk, Kf + j * 256, 4 * ((i0 + row) * n + col));
+                lds_copy16(rx, Xs + j * 256, 4 * ((r0 + row) * n + col));
+            }
+            if (SPLIT) {
+                // 16 rows of one bf16 panel (hi, then lo) per wave-wide copy
+                constexpr int KPP = TI / 16;
+#pragma unroll
+                for (int q = wave; q < KQ; q += kThreads / 64) {
+                    const int qq = q < KPP ? q : q - KPP;
+                    const int jj = pnl * KPP + qq, row = qq * 16 + krow;
+                    const int col = kb0 + 32 * pnl + 8 * (kch ^ ((row >> 2) & 3));
+                    const int voff = 2 * ((i0 + row) * n + col);
+                    if (q < KPP) lds_copy16(rk, Kh + jj * 512, voff);
+                    else lds_copy16(rkl, Kl + jj * 512, voff);
+                }
+            } else {
+#pragma unroll
+                for (int q = wave; q < KQ; q += kThreads / 64) {
+                    const int j = pnl * KQ + q, row = q * 8 + xrow;
+                    const int col = kb0 + 32 * pnl + 4 * (xch ^ ((row >> 1) & 7));
+                    lds_copy16(rk, Kf + j * 256, 4 * ((i0 + row) * n + col));
+                }
             }
         }
     }
-    __builtin_amdgcn_s_waitcnt(0);
-    if (done) return;   // the step has stopped: nothing to compute (uniform)
-    __syncthreads();
+    if (done) {   // the step has stopped: nothing to compute (uniform)
+        __builtin_amdgcn_s_waitcnt(0);
+        return;
+    }
     const bool logx = lmode != 0;
     if (logx) {
         // per-row maximum of the staged logs over the band, then exponentiate
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
         if (tid < TR) {
             float m = -INFINITY;
             for (int pnl = 0; pnl < NP; ++pnl)
@@ -500,6 +537,13 @@ contract_panel(Pass P, EpiArgs E) {
     const int s8 = (lane >> 1) & 7;   // 128-byte row swizzle of every row this lane reads
     const int g = lane >> 4;
     for (int pnl = 0; pnl < NP; ++pnl) {
+        if (!logx) {   // this panel's copies of every wave have landed
+            // (a bare barrier: __syncthreads would first wait for every copy)
+            wait_vm((NP - 1 - pnl) * CPP);
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            __builtin_amdgcn_s_barrier();
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        }
         const float* xp = Xs + (pnl * TR + wr * 16 * FM + (lane & 15)) * 32;
         if (SPLIT) {
             const int s4 = (lane >> 2) & 3;
@@ -652,9 +696,566 @@ hipError_t launch_ek(int ek, int cfg, int64_t nb, const Pass& p, const EpiArgs& 
     }
 }
 
+// ---------------------------------------------------------------- 3D planes
+//
+// A 3D application of xi as a plane pass (axes 2 and 1 of each plane a, the
+// intermediate kept in LDS) and a slow-axis pass (axis 0, with the epilogue),
+// both keeping the layout [a][b][c].  The arithmetic is that of the three
+// axis passes, in the same order: the plane pass's first stage is the axis-2
+// pass (rows b, outputs c' in 32-wide chunks over their 32-aligned bands), its
+// second stage the axis-1 pass on the staged intermediate (outputs b' in
+// 32-wide chunks, one per wave, each over its own band, with the same
+// log-domain shifts), and the slow-axis pass is the axis-0 pass with X staged
+// transposed.  Two launches per application instead of three, and one trip
+// of the field through memory fewer.
+
+constexpr int kPlaneMaxN1 = 128;             // one 32-row chunk of b' per wave in the second stage
+constexpr int kPlaneQ = kPlaneMaxN1 / 32;    // band panels of a b' chunk
+
+__host__ __device__ inline int band_lo32(int i0, int W) { return (i0 - W > 0 ? i0 - W : 0) & ~31; }
+__host__ __device__ inline int band_hi32(int i0, int W, int n) {
+    const int h = (i0 + 32 + W + 31) & ~31;
+    return h < n ? h : n;
+}
+
+// Dynamic LDS of the plane pass: the X and K2 panels of the block's band (the
+// split K2 hi + lo take the bytes of the FP32 panels), later the intermediate.
+int plane_lds_bytes(int n1, int NP) { return std::max(NP * (n1 + 32) * 128, 32 * (n1 + 4) * 4); }
+
+template <bool SPLIT>
+__global__ void __launch_bounds__(kThreads)
+plane_pass(Plane3D P) {
+    extern __shared__ __attribute__((aligned(16))) float dyn[];
+    __shared__ float fshift[kPlaneMaxN1];   // first stage: row shifts (log domain)
+    __shared__ float cshift[4][32];         // second stage: column shifts of each wave's chunk
+
+    int done = 0, lmode = 0;
+    if (P.ctl) {
+        done = P.ctl->done;
+        lmode = P.ctl->logmode;
+    }
+    const int n1 = P.n1, n2 = P.n2;
+    const int chunks = n2 >> 5;
+    const int logical = xcd_logical_block();
+    const int a = logical / chunks, c0 = (logical % chunks) * 32;
+    const int kb0 = band_lo32(c0, P.W2), kb1 = band_hi32(c0, P.W2, n2);
+    const int NP = (kb1 - kb0) >> 5;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4;
+    float* Xs = dyn;                                                   // [NP][n1][32]
+    float* K2f = dyn + NP * n1 * 32;                                   // [NP][32][32]
+    uint16_t* K2h = reinterpret_cast<uint16_t*>(dyn + NP * n1 * 32);   // [NP][32][32] bf16
+    uint16_t* K2l = K2h + NP * 32 * 32;
+    const int ZS = n1 + 4;
+    float* Zt = dyn;                                                   // [32][ZS] after the first stage
+
+    // Second-stage factor operands of this wave (rows b' of its chunk over
+    // their band), fetched from global memory ahead of everything else.
+    const int bq0 = 32 * wave;
+    const bool s2 = bq0 < n1;
+    const int qb0 = s2 ? band_lo32(bq0, P.W1) : 0;
+    const int NQ = s2 ? (band_hi32(bq0, P.W1, n1) - qb0) >> 5 : 0;
+    f4 kq[kPlaneQ][2][2];
+    bf8 kqh[kPlaneQ][2], kql[kPlaneQ][2];
+#pragma unroll
+    for (int q = 0; q < kPlaneQ; ++q)
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+            if (q >= NQ) continue;
+            const int row = bq0 + f * 16 + (lane & 15);
+            const int kb = qb0 + 32 * q;
+            if (SPLIT) {
+                kqh[q][f] = __builtin_bit_cast(bf8, *reinterpret_cast<const u16x8*>(P.K1hi + row * n1 + kb + 8 * g));
+                kql[q][f] = __builtin_bit_cast(bf8, *reinterpret_cast<const u16x8*>(P.K1lo + row * n1 + kb + 8 * g));
+            } else {
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+                    kq[q][f][h] = *reinterpret_cast<const f4*>(P.K1 + row * n1 + kb + 4 * (4 * h + g));
+            }
+        }
+
+    // First-stage staging: the plane's rows over the band, and the K2 rows of
+    // the chunk (layout and swizzle of the panel form).
+    {
+        const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<float*>(P.X), (short)0, P.n0 * n1 * n2 * 4, kBufRsrcWord3);
+        const int xrow = lane >> 3, xch = lane & 7;
+        const int XC = n1 / 8;
+        for (int j = wave; j < NP * XC; j += kThreads / 64) {
+            const int pnl = j / XC, row = (j % XC) * 8 + xrow;
+            const int col = kb0 + 32 * pnl + 4 * (xch ^ ((row >> 1) & 7));
+            lds_copy16(rx, Xs + j * 256, 4 * ((a * n1 + row) * n2 + col));
+        }
+        if (SPLIT) {
+            const __amdgpu_buffer_rsrc_t rh = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<uint16_t*>(P.K2hi), (short)0, n2 * n2 * 2, kBufRsrcWord3);
+            const __amdgpu_buffer_rsrc_t rl = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<uint16_t*>(P.K2lo), (short)0, n2 * n2 * 2, kBufRsrcWord3);
+            const int krow = lane >> 2, kch = lane & 3;
+            const int nK = NP * 2;
+            for (int j = wave; j < 2 * nK; j += kThreads / 64) {
+                const int jj = j < nK ? j : j - nK;
+                const int pnl = jj / 2, row = (jj % 2) * 16 + krow;
+                const int col = kb0 + 32 * pnl + 8 * (kch ^ ((row >> 2) & 3));
+                const int voff = 2 * ((c0 + row) * n2 + col);
+                if (j < nK) lds_copy16(rh, K2h + jj * 512, voff);
+                else lds_copy16(rl, K2l + jj * 512, voff);
+            }
+        } else {
+            const __amdgpu_buffer_rsrc_t rk = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<float*>(P.K2), (short)0, n2 * n2 * 4, kBufRsrcWord3);
+            for (int j = wave; j < NP * 4; j += kThreads / 64) {
+                const int pnl = j / 4, row = (j % 4) * 8 + xrow;
+                const int col = kb0 + 32 * pnl + 4 * (xch ^ ((row >> 1) & 7));
+                lds_copy16(rk, K2f + j * 256, 4 * ((c0 + row) * n2 + col));
+            }
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    if (done) return;   // the step has stopped: nothing to compute (uniform)
+    __syncthreads();
+    const bool logx = lmode != 0;
+    if (logx) {
+        if (tid < n1) {
+            float m = -INFINITY;
+            for (int pnl = 0; pnl < NP; ++pnl)
+                for (int q = 0; q < 32; ++q) m = fmaxf(m, Xs[(pnl * n1 + tid) * 32 + q]);
+            fshift[tid] = (m == -INFINITY) ? NAN : m;
+        }
+        __syncthreads();
+        for (int u = tid; u < NP * n1 * 32; u += kThreads) Xs[u] = shifted_exp(Xs[u], fshift[(u >> 5) % n1]);
+        __syncthreads();
+    }
+
+    // ---- first stage: Z[b][c'] = sum_c X[b][c] K2[c'][c]; wave w owns the
+    // 16-row fragments w and w + 4 of b, both 16-column fragments of c'
+    const int nfb = n1 >> 4;
+    const int s8 = (lane >> 1) & 7;
+    f4 acc[2][2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int f = 0; f < 2; ++f) acc[t][f] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int pnl = 0; pnl < NP; ++pnl) {
+        if (SPLIT) {
+            const int s4 = (lane >> 2) & 3;
+            bf8 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const int fb = wave + 4 * t;
+                if (fb >= nfb) continue;
+                const float* xr = Xs + (pnl * n1 + fb * 16 + (lane & 15)) * 32;
+                const f4 v0 = *reinterpret_cast<const f4*>(xr + 4 * ((2 * g) ^ s8));
+                const f4 v1 = *reinterpret_cast<const f4*>(xr + 4 * ((2 * g + 1) ^ s8));
+                split_bf16(v0, v1, ah[t], al[t]);
+            }
+#pragma unroll
+            for (int f = 0; f < 2; ++f) {
+                const int o = (pnl * 32 + f * 16 + (lane & 15)) * 32 + 8 * (g ^ s4);
+                bh[f] = __builtin_bit_cast(bf8, *reinterpret_cast<const u16x8*>(K2h + o));
+                bl[f] = __builtin_bit_cast(bf8, *reinterpret_cast<const u16x8*>(K2l + o));
+            }
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                if (wave + 4 * t >= nfb) continue;
+#pragma unroll
+                for (int f = 0; f < 2; ++f) {
+                    acc[t][f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[t], bh[f], acc[t][f], 0, 0, 0);
+                    acc[t][f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[t], bl[f], acc[t][f], 0, 0, 0);
+                    acc[t][f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[t], bh[f], acc[t][f], 0, 0, 0);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int ch = 4 * ((4 * h + g) ^ s8);
+                f4 av[2], bv[2];
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    const int fb = wave + 4 * t;
+                    av[t] = fb < nfb ? *reinterpret_cast<const f4*>(Xs + (pnl * n1 + fb * 16 + (lane & 15)) * 32 + ch)
+                                     : f4{0.f, 0.f, 0.f, 0.f};
+                }
+#pragma unroll
+                for (int f = 0; f < 2; ++f)
+                    bv[f] = *reinterpret_cast<const f4*>(K2f + (pnl * 32 + f * 16 + (lane & 15)) * 32 + ch);
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+#pragma unroll
+                    for (int t = 0; t < 2; ++t) {
+                        if (wave + 4 * t >= nfb) continue;
+#pragma unroll
+                        for (int f = 0; f < 2; ++f)
+                            acc[t][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t][s], bv[f][s], acc[t][f], 0, 0, 0);
+                    }
+            }
+        }
+    }
+    __syncthreads();   // every wave is done with the staged panels: the intermediate replaces them
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int fb = wave + 4 * t;
+        if (fb >= nfb) continue;
+        const int b = fb * 16 + 4 * g;
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+            f4 v = acc[t][f];
+            if (logx)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[e] = shifted_log(v[e], fshift[b + e]);
+            *reinterpret_cast<f4*>(&Zt[(f * 16 + (lane & 15)) * ZS + b]) = v;
+        }
+    }
+    __syncthreads();
+
+    // ---- second stage: Y[b'][c'] = sum_b K1[b'][b] Z[b][c'] over the band of
+    // this wave's chunk of b' (rows of the MFMA: c'; columns: b')
+    if (!s2) return;
+    float csh[2] = {0.f, 0.f};
+    if (logx) {
+        const int qb1 = qb0 + 32 * NQ;
+        const int cc = lane & 31;
+        float m = -INFINITY;
+        for (int b = qb0 + (lane >> 5); b < qb1; b += 2) m = fmaxf(m, Zt[cc * ZS + b]);
+        m = fmaxf(m, __shfl_xor(m, 32, 64));
+        if (lane < 32) cshift[wave][cc] = (m == -INFINITY) ? NAN : m;
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int f = 0; f < 2; ++f) csh[f] = cshift[wave][f * 16 + (lane & 15)];
+    }
+    f4 acc2[2][2];
+#pragma unroll
+    for (int f = 0; f < 2; ++f)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) acc2[f][t] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < kPlaneQ; ++q) {
+        if (q >= NQ) continue;
+        const int kb = qb0 + 32 * q;
+        if (SPLIT) {
+            bf8 ah[2], al[2];
+#pragma unroll
+            for (int f = 0; f < 2; ++f) {
+                const float* zr = Zt + (f * 16 + (lane & 15)) * ZS + kb + 8 * g;
+                f4 v0 = *reinterpret_cast<const f4*>(zr);
+                f4 v1 = *reinterpret_cast<const f4*>(zr + 4);
+                if (logx)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        v0[e] = shifted_exp(v0[e], csh[f]);
+                        v1[e] = shifted_exp(v1[e], csh[f]);
+                    }
+                split_bf16(v0, v1, ah[f], al[f]);
+            }
+#pragma unroll
+            for (int f = 0; f < 2; ++f)
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    acc2[f][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[f], kqh[q][t], acc2[f][t], 0, 0, 0);
+                    acc2[f][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[f], kql[q][t], acc2[f][t], 0, 0, 0);
+                    acc2[f][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[f], kqh[q][t], acc2[f][t], 0, 0, 0);
+                }
+        } else {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                f4 av[2];
+#pragma unroll
+                for (int f = 0; f < 2; ++f) {
+                    av[f] = *reinterpret_cast<const f4*>(Zt + (f * 16 + (lane & 15)) * ZS + kb + 4 * (4 * h + g));
+                    if (logx)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) av[f][e] = shifted_exp(av[f][e], csh[f]);
+                }
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+#pragma unroll
+                    for (int f = 0; f < 2; ++f)
+#pragma unroll
+                        for (int t = 0; t < 2; ++t)
+                            acc2[f][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[f][s], kq[q][t][h][s], acc2[f][t], 0, 0, 0);
+            }
+        }
+    }
+    // lane: c' = 16 f + 4 g + e, b' = bq0 + 16 t + (lane & 15)
+#pragma unroll
+    for (int f = 0; f < 2; ++f)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int cl = f * 16 + 4 * g;
+            f4 v = acc2[f][t];
+            if (logx)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[e] = shifted_log(v[e], cshift[wave][cl + e]);
+            const int bp = bq0 + t * 16 + (lane & 15);
+            __builtin_nontemporal_store(v, reinterpret_cast<f4*>(P.Y + ((int64_t)a * n1 + bp) * n2 + c0 + cl));
+        }
+}
+
+// Slow-axis pass: Y[i][r] = sum_k K1[i][k] X[k][r] (X: n x R, rows contiguous
+// in r), tiles of TR = 64 r x TI = 32 i, the MFMA rows r as in the panel form.
+// The band's X rows are staged as [panel][32 k][64 r]; within a row the
+// 16-byte chunk c of r is stored at c ^ (4 ((k >> 2) & 3)), so the operand
+// reads of four k at once fall in distinct banks.
+__device__ __forceinline__ int slow_pos(int k, int r) { return (((r >> 2) ^ (4 * ((k >> 2) & 3))) << 2) | (r & 3); }
+
+template <bool SPLIT, int EK>
+__global__ void __launch_bounds__(kThreads)
+contract_slow(Pass P, EpiArgs E) {
+    constexpr int TR = 64, TI = 32, WR = 2, WI = 2;
+    constexpr int FM = TR / WR / 16;
+    constexpr int FN = TI / WI / 16;
+    extern __shared__ __attribute__((aligned(16))) float dyn[];
+    __shared__ float fshift[TR];
+    __shared__ double shd[8];
+
+    int done = 0, lmode = 0;
+    if (E.ctl) {
+        done = E.ctl->done;
+        lmode = E.ctl->logmode;
+    }
+    const int n = P.n;
+    const int R = (int)P.R;
+    const int IT = n / TI;
+    const int logical = xcd_logical_block();
+    const int r0 = (logical / IT) * TR;
+    const int i0 = (logical % IT) * TI;
+    const int kb0 = band_lo32(i0, P.W), kb1 = band_hi32(i0, P.W, n);
+    const int NP = (kb1 - kb0) >> 5;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave % WR, wi = wave / WR;
+    float* Xs = dyn;                                                   // NP * 32 * TR floats
+    float* Kf = dyn + NP * TR * 32;                                    // NP * TI * 32 floats
+    uint16_t* Kh = reinterpret_cast<uint16_t*>(dyn + NP * TR * 32);    // NP * TI * 32 bf16
+    uint16_t* Kl = Kh + NP * TI * 32;
+
+    constexpr int UE = (TI * TR / 4 + kThreads - 1) / kThreads;
+    EpiIn ein[UE];
+    int eidx[UE], ecnt[UE];
+#pragma unroll
+    for (int u = 0; u < UE; ++u) {
+        const int unit = tid + u * kThreads;
+        const int il = unit / (TR / 4), rl = 4 * (unit % (TR / 4));
+        const int i = i0 + il, r = r0 + rl;
+        ecnt[u] = (unit < TI * TR / 4 && i < n) ? max(0, min(4, R - r)) : 0;
+        eidx[u] = i * R + r;
+        ein[u] = epi_prefetch<EK>(E, eidx[u], ecnt[u]);
+    }
+    {
+        const __amdgpu_buffer_rsrc_t rx =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(P.X), (short)0, R * n * 4, kBufRsrcWord3);
+        // X: 4 rows of 64 r per wave-wide copy; lane L fills position L & 15 of
+        // row 4 j + (L >> 4) with the chunk that the swizzle puts there
+        const int krow = lane >> 4, pos = lane & 15;
+        for (int j = wave; j < NP * 8; j += kThreads / 64) {
+            const int pnl = j / 8, k = (j % 8) * 4 + krow;
+            const int c = pos ^ (4 * ((k >> 2) & 3));
+            lds_copy16(rx, Xs + j * 256, 4 * ((kb0 + 32 * pnl + k) * R + r0 + 4 * c));
+        }
+        const int xrow = lane >> 3, xch = lane & 7;
+        if (SPLIT) {
+            const __amdgpu_buffer_rsrc_t rh = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<uint16_t*>(P.K1hi), (short)0, n * n * 2, kBufRsrcWord3);
+            const __amdgpu_buffer_rsrc_t rl = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<uint16_t*>(P.K1lo), (short)0, n * n * 2, kBufRsrcWord3);
+            constexpr int KPP = TI / 16;
+            const int nK = NP * KPP;
+            const int kr = lane >> 2, kch = lane & 3;
+            for (int j = wave; j < 2 * nK; j += kThreads / 64) {
+                const int jj = j < nK ? j : j - nK;
+                const int pnl = jj / KPP, row = (jj % KPP) * 16 + kr;
+                const int col = kb0 + 32 * pnl + 8 * (kch ^ ((row >> 2) & 3));
+                const int voff = 2 * ((i0 + row) * n + col);
+                if (j < nK) lds_copy16(rh, Kh + jj * 512, voff);
+                else lds_copy16(rl, Kl + jj * 512, voff);
+            }
+        } else {
+            const __amdgpu_buffer_rsrc_t rk = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<float*>(P.K1), (short)0, n * n * 4, kBufRsrcWord3);
+            constexpr int KPP = TI / 8;
+            for (int j = wave; j < NP * KPP; j += kThreads / 64) {
+                const int pnl = j / KPP, row = (j % KPP) * 8 + xrow;
+                const int col = kb0 + 32 * pnl + 4 * (xch ^ ((row >> 1) & 7));
+                lds_copy16(rk, Kf + j * 256, 4 * ((i0 + row) * n + col));
+            }
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    if (done) return;   // the step has stopped: nothing to compute (uniform)
+    __syncthreads();
+    const bool logx = lmode != 0;
+    if (logx) {
+        // per-column (r) maximum of the staged logs over the band, then exponentiate
+        if (tid < TR) {
+            float m = -INFINITY;
+            for (int k = 0; k < NP * 32; ++k) m = fmaxf(m, Xs[k * TR + slow_pos(k, tid)]);
+            fshift[tid] = (m == -INFINITY) ? NAN : m;
+        }
+        __syncthreads();
+        for (int u = tid; u < NP * 32 * TR; u += kThreads) {
+            const int k = u / TR, p = u % TR;
+            const int r = (((p >> 2) ^ (4 * ((k >> 2) & 3))) << 2) | (p & 3);
+            Xs[u] = shifted_exp(Xs[u], fshift[r]);
+        }
+        __syncthreads();
+    }
+
+    f4 acc[FM][FN];
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+    const int s8 = (lane >> 1) & 7;
+    const int g = lane >> 4;
+    for (int pnl = 0; pnl < NP; ++pnl) {
+        const float* xp = Xs + pnl * 32 * TR;
+        if (SPLIT) {
+            const int s4 = (lane >> 2) & 3;
+            bf8 ah[FM], al[FM], bh[FN], bl[FN];
+#pragma unroll
+            for (int a = 0; a < FM; ++a) {
+                const int r = wr * 16 * FM + a * 16 + (lane & 15);
+                f4 v0, v1;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    v0[e] = xp[(8 * g + e) * TR + slow_pos(8 * g + e, r)];
+                    v1[e] = xp[(8 * g + 4 + e) * TR + slow_pos(8 * g + 4 + e, r)];
+                }
+                split_bf16(v0, v1, ah[a], al[a]);
+            }
+#pragma unroll
+            for (int b = 0; b < FN; ++b) {
+                const int o = (pnl * TI + wi * 16 * FN + b * 16 + (lane & 15)) * 32 + 8 * (g ^ s4);
+                bh[b] = __builtin_bit_cast(bf8, *reinterpret_cast<const u16x8*>(Kh + o));
+                bl[b] = __builtin_bit_cast(bf8, *reinterpret_cast<const u16x8*>(Kl + o));
+            }
+#pragma unroll
+            for (int a = 0; a < FM; ++a)
+#pragma unroll
+                for (int b = 0; b < FN; ++b) {
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+                }
+        } else {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int kk = 4 * (4 * h + g);
+                const int ch = 4 * ((4 * h + g) ^ s8);
+                f4 av[FM], bv[FN];
+#pragma unroll
+                for (int a = 0; a < FM; ++a) {
+                    const int r = wr * 16 * FM + a * 16 + (lane & 15);
+                    const int pr = slow_pos(kk, r);   // the same position in the four rows kk .. kk + 3
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) av[a][s] = xp[(kk + s) * TR + pr];
+                }
+#pragma unroll
+                for (int b = 0; b < FN; ++b)
+                    bv[b] = *reinterpret_cast<const f4*>(
+                        Kf + (pnl * TI + wi * 16 * FN + b * 16 + (lane & 15)) * 32 + ch);
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+#pragma unroll
+                    for (int a = 0; a < FM; ++a)
+#pragma unroll
+                        for (int b = 0; b < FN; ++b)
+                            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a][s], bv[b][s], acc[a][b], 0, 0, 0);
+            }
+        }
+    }
+    __syncthreads();
+
+    // epilogue through LDS as in the panel form
+    constexpr int TS = TR + 4;
+    float* tile = dyn;
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) {
+            const int rl = wr * 16 * FM + a * 16 + 4 * (lane >> 4);
+            const int il = wi * 16 * FN + b * 16 + (lane & 15);
+            *reinterpret_cast<f4*>(&tile[il * TS + rl]) = acc[a][b];
+        }
+    __syncthreads();
+    EpiAcc ea;
+#pragma unroll
+    for (int u = 0; u < UE; ++u) {
+        const int unit = tid + u * kThreads;
+        const int il = unit / (TR / 4), rl = 4 * (unit % (TR / 4));
+        if (ecnt[u] == 0) continue;
+        f4 v = *reinterpret_cast<const f4*>(&tile[il * TS + rl]);
+        if (logx) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] = shifted_log(v[e], fshift[rl + e]);
+        }
+        epi_apply<EK>(E, eidx[u], ecnt[u], v, logx, ein[u], ea);
+    }
+    epi_finish(E, ea, (int)blockIdx.x, shd);
+}
+
+template <bool SPLIT>
+hipError_t launch_slow_ek(int ek, int64_t nb, const Pass& p, const EpiArgs& e, int lds, hipStream_t st) {
+    const dim3 grid((unsigned)nb), block(kThreads);
+#define JKO_SLOW(EKV) hipLaunchKernelGGL((contract_slow<SPLIT, EKV>), grid, block, lds, st, p, e); break
+    switch (ek) {
+        case EK_STORE: JKO_SLOW(EK_STORE);
+        case EK_BUPDATE: JKO_SLOW(EK_BUPDATE);
+        case EK_MONITOR: JKO_SLOW(EK_MONITOR);
+        case EK_PROX + JKO_F_ZERO: JKO_SLOW(EK_PROX + JKO_F_ZERO);
+        case EK_PROX + JKO_F_CONGESTION: JKO_SLOW(EK_PROX + JKO_F_CONGESTION);
+        case EK_PROX + JKO_F_POROUS: JKO_SLOW(EK_PROX + JKO_F_POROUS);
+        case EK_PROX + JKO_F_ENTROPY: JKO_SLOW(EK_PROX + JKO_F_ENTROPY);
+        case EK_ADJ_B: JKO_SLOW(EK_ADJ_B);
+        case EK_ADJ_PROX + JKO_F_ZERO: JKO_SLOW(EK_ADJ_PROX + JKO_F_ZERO);
+        case EK_ADJ_PROX + JKO_F_CONGESTION: JKO_SLOW(EK_ADJ_PROX + JKO_F_CONGESTION);
+        case EK_ADJ_PROX + JKO_F_POROUS: JKO_SLOW(EK_ADJ_PROX + JKO_F_POROUS);
+        default: JKO_SLOW(EK_ADJ_PROX + JKO_F_ENTROPY);
+    }
+#undef JKO_SLOW
+    return hipGetLastError();
+}
+
+// Widest band (in 32-panels) of the 32-chunks of an axis of length n.
+int band_panels(int n, int W) {
+    int np = 0;
+    for (int i0 = 0; i0 < n; i0 += 32) np = std::max(np, (band_hi32(i0, W, n) - band_lo32(i0, W)) >> 5);
+    return np;
+}
+
 }  // namespace
 
 int64_t contract_max_blocks(const Pass& pass, int32_t /*precision*/) { return tiles_of(pass, pick_cfg(pass)); }
+
+bool plane3d_fits(int n0, int n1, int n2, int W0, int W1, int W2) {
+    if (n0 % 32 != 0 || n1 % 32 != 0 || n2 % 32 != 0 || n1 > kPlaneMaxN1) return false;
+    if ((int64_t)n0 * n1 * n2 * 4 >= ((int64_t)1 << 31)) return false;
+    const int np2 = band_panels(n2, W2), np0 = band_panels(n0, W0);
+    if (np2 > kPanelMax || np0 > kPanelMax || band_panels(n1, W1) > kPlaneQ) return false;
+    // dynamic LDS within 64 KiB with the static arrays beside it
+    return plane_lds_bytes(n1, np2) <= 65536 - 2048 && panel_lds_bytes(64, 32, np0) <= 65536 - 2048;
+}
+
+hipError_t launch_plane3d(const Plane3D& p, int32_t precision, int* nblocks, hipStream_t stream) {
+    const int64_t nb = (int64_t)p.n0 * (p.n2 / 32);
+    if (nblocks) *nblocks = (int)nb;
+    const int lds = plane_lds_bytes(p.n1, band_panels(p.n2, p.W2));
+    if (precision == JKO_SPLIT_BF16)
+        hipLaunchKernelGGL(plane_pass<true>, dim3((unsigned)nb), dim3(kThreads), lds, stream, p);
+    else
+        hipLaunchKernelGGL(plane_pass<false>, dim3((unsigned)nb), dim3(kThreads), lds, stream, p);
+    return hipGetLastError();
+}
+
+int64_t contract_slow_blocks(const Pass& pass) { return (pass.R / 64) * (int64_t)(pass.n / 32); }
+
+hipError_t launch_contract_slow(const Pass& pass, int32_t precision, const EpiArgs& epi, int* nblocks,
+                                hipStream_t stream) {
+    const int64_t nb = contract_slow_blocks(pass);
+    if (nblocks) *nblocks = (int)nb;
+    if (nb <= 0) return hipSuccess;
+    const int lds = panel_lds_bytes(64, 32, band_panels(pass.n, pass.W));
+    if (precision == JKO_SPLIT_BF16) return launch_slow_ek<true>(ek_of(epi), nb, pass, epi, lds, stream);
+    return launch_slow_ek<false>(ek_of(epi), nb, pass, epi, lds, stream);
+}
 
 hipError_t launch_contract(const Pass& pass, int32_t precision, const EpiArgs& epi, int* nblocks,
                            hipStream_t stream) {

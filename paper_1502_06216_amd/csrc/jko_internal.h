@@ -108,6 +108,30 @@ hipError_t launch_contract(const Pass& pass, int32_t precision, const EpiArgs& e
 // Upper bound of the blocks launch_contract may use for a pass of this shape.
 int64_t contract_max_blocks(const Pass& pass, int32_t precision);
 
+// 3D application in two launches that keep the layout [a][b][c] (c contiguous):
+//   plane pass:  Y[a][b'][c'] = sum_b K1_1[b'][b] sum_c K1_2[c'][c] X[a][b][c]
+//   slow pass:   Y[a'][r] = sum_a K1_0[a'][a] X[a][r]   (r = b n2 + c), + epilogue
+// Same arithmetic, in the same order, as the three axis passes.
+struct Plane3D {
+    int n0, n1, n2;        // grid
+    int W1, W2;            // band half-widths of the axis-1 and axis-2 factors
+    const float* K1;       // n1 x n1 axis-1 factor (and its bfloat16 split)
+    const uint16_t* K1hi;
+    const uint16_t* K1lo;
+    const float* K2;       // n2 x n2 axis-2 factor
+    const uint16_t* K2hi;
+    const uint16_t* K2lo;
+    const float* X;        // input field
+    float* Y;              // output field (not X)
+    const Ctl* ctl;        // kernels return early when ctl->done
+};
+bool plane3d_fits(int n0, int n1, int n2, int W0, int W1, int W2);
+hipError_t launch_plane3d(const Plane3D& p, int32_t precision, int* nblocks, hipStream_t stream);
+// Slow-axis pass: Pass.R = n1 n2 columns, Pass.n = n0, X is n0 x R (rows contiguous in r).
+hipError_t launch_contract_slow(const Pass& pass, int32_t precision, const EpiArgs& epi, int* nblocks,
+                                hipStream_t stream);
+int64_t contract_slow_blocks(const Pass& pass);
+
 // Fused 2D application Y = K1_0 X K1_1 restricted to the float32 band of the
 // factors (|i - j| > W => K1[i][j] == 0 exactly).
 struct Band2D {

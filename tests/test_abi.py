@@ -86,7 +86,7 @@ def test_argument_errors_before_any_launch(lib):
     big = nat.make_grid((2048, 8))
     assert _call_step(lib, big, en, prm) == jk.JKO_ERR_INVALID
     for field, val in (("gamma", 0.0), ("gamma", math.nan), ("tau", -1.0), ("max_iters", 0),
-                       ("check_every", 0), ("precision", 7), ("flags", 2), ("flags", -1)):
+                       ("check_every", 0), ("precision", 7), ("flags", 4), ("flags", -1)):
         p2 = nat.make_params(1e-3, 1e-3, 10)
         setattr(p2, field, val)
         assert _call_step(lib, g, en, p2) == jk.JKO_ERR_INVALID, field
@@ -130,12 +130,15 @@ def test_gibbs_and_flow_and_backward_argument_errors(lib):
 
 
 def test_flags_field_and_binding():
-    """jko_params.flags: the resident path is the default, JKO_FLAG_NO_RESIDENT
-    keeps one launch per application (the header names the bit)."""
+    """jko_params.flags: the resident path and the 3D plane pass are the
+    defaults; JKO_FLAG_NO_RESIDENT keeps one launch per application and
+    JKO_FLAG_AXIS_PASSES three axis passes (the header names the bits)."""
     assert nat.make_params(1e-3, 1e-3).flags == 0
     assert nat.make_params(1e-3, 1e-3, resident=False).flags == nat.FLAG_NO_RESIDENT == 1
+    assert nat.make_params(1e-3, 1e-3, planes=False).flags == nat.FLAG_AXIS_PASSES == 2
+    assert nat.make_params(1e-3, 1e-3, resident=False, planes=False).flags == 3
     hdr = open(os.path.join(ROOT, "include", "jko.h")).read()
-    assert "JKO_FLAG_NO_RESIDENT = 1" in hdr
+    assert "JKO_FLAG_NO_RESIDENT = 1" in hdr and "JKO_FLAG_AXIS_PASSES = 2" in hdr
 
 
 def test_binding_refuses_cpu_tensors():
