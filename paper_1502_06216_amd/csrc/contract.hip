@@ -385,30 +385,22 @@ contract_rot(Pass P, EpiArgs E) {
 constexpr int kPanelMax = 5;      // panels per tile band (160 k)
 constexpr int kBufRsrcWord3 = 0x00020000;
 
-// Wait until at most `n` (0 .. 15) of this wave's vector memory operations are
-// outstanding; they complete in issue order.
+// Wait until at most `n` (0 .. 31) of this wave's vector memory operations are
+// outstanding; they complete in issue order.  The count is split over the
+// immediate's bits 3:0 and 15:14; expcnt and lgkmcnt are left unwaited.
 template <int N>
 __device__ __forceinline__ void wait_vm_n() {
-    __builtin_amdgcn_s_waitcnt(N | (0x7 << 4) | (0xF << 8));   // expcnt, lgkmcnt: no wait
+    __builtin_amdgcn_s_waitcnt((N & 0xF) | (((N >> 4) & 3) << 14) | (0x7 << 4) | (0xF << 8));
 }
 __device__ __forceinline__ void wait_vm(int n) {
     switch (n) {
-        case 0: wait_vm_n<0>(); break;
-        case 1: wait_vm_n<1>(); break;
-        case 2: wait_vm_n<2>(); break;
-        case 3: wait_vm_n<3>(); break;
-        case 4: wait_vm_n<4>(); break;
-        case 5: wait_vm_n<5>(); break;
-        case 6: wait_vm_n<6>(); break;
-        case 7: wait_vm_n<7>(); break;
-        case 8: wait_vm_n<8>(); break;
-        case 9: wait_vm_n<9>(); break;
-        case 10: wait_vm_n<10>(); break;
-        case 11: wait_vm_n<11>(); break;
-        case 12: wait_vm_n<12>(); break;
-        case 13: wait_vm_n<13>(); break;
-        case 14: wait_vm_n<14>(); break;
-        default: wait_vm_n<15>(); break;
+#define JKO_VM(N) case N: wait_vm_n<N>(); break;
+        JKO_VM(0) JKO_VM(1) JKO_VM(2) JKO_VM(3) JKO_VM(4) JKO_VM(5) JKO_VM(6) JKO_VM(7)
+        JKO_VM(8) JKO_VM(9) JKO_VM(10) JKO_VM(11) JKO_VM(12) JKO_VM(13) JKO_VM(14) JKO_VM(15)
+        JKO_VM(16) JKO_VM(17) JKO_VM(18) JKO_VM(19) JKO_VM(20) JKO_VM(21) JKO_VM(22) JKO_VM(23)
+        JKO_VM(24) JKO_VM(25) JKO_VM(26) JKO_VM(27) JKO_VM(28) JKO_VM(29) JKO_VM(30)
+#undef JKO_VM
+        default: wait_vm_n<31>(); break;
     }
 }
 
@@ -468,7 +460,7 @@ contract_panel(Pass P, EpiArgs E) {
     constexpr int KQ = SPLIT ? 2 * (TI / 16) : TI / 8;   // K copies per panel (hi and lo rows)
     static_assert(XPP % 4 == 0 && KQ % 4 == 0, "copies spread evenly over the four waves");
     constexpr int CPP = XPP / 4 + KQ / 4;
-    static_assert((kPanelMax - 1) * CPP <= 15, "per-panel wait counts fit wait_vm");
+    static_assert((kPanelMax - 1) * CPP <= 31, "per-panel wait counts fit wait_vm");
     {
         const __amdgpu_buffer_rsrc_t rx =
             __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(P.X), (short)0, R * n * 4, kBufRsrcWord3);
@@ -774,47 +766,49 @@ plane_pass(Plane3D P) {
         }
 
     // First-stage staging: the plane's rows over the band, and the K2 rows of
-    // the chunk (layout and swizzle of the panel form).
+    // the chunk (layout and swizzle of the panel form), panel by panel: each
+    // wave issues CPP copies per panel, so panel p has landed once at most
+    // (NP - 1 - p) CPP of its copies are outstanding.
+    const int XC = n1 / 8;         // 8-row X copies per panel (a multiple of 4)
+    const int CPP = XC / 4 + 1;    // per wave: X copies and one K2 copy (FP32 rows, or hi / lo)
     {
         const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
             const_cast<float*>(P.X), (short)0, P.n0 * n1 * n2 * 4, kBufRsrcWord3);
+        const __amdgpu_buffer_rsrc_t rk = __builtin_amdgcn_make_buffer_rsrc(
+            SPLIT ? (void*)const_cast<uint16_t*>(P.K2hi) : (void*)const_cast<float*>(P.K2), (short)0,
+            SPLIT ? n2 * n2 * 2 : n2 * n2 * 4, kBufRsrcWord3);
+        const __amdgpu_buffer_rsrc_t rkl = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<uint16_t*>(SPLIT ? P.K2lo : P.K2hi), (short)0, n2 * n2 * 2, kBufRsrcWord3);
         const int xrow = lane >> 3, xch = lane & 7;
-        const int XC = n1 / 8;
-        for (int j = wave; j < NP * XC; j += kThreads / 64) {
-            const int pnl = j / XC, row = (j % XC) * 8 + xrow;
-            const int col = kb0 + 32 * pnl + 4 * (xch ^ ((row >> 1) & 7));
-            lds_copy16(rx, Xs + j * 256, 4 * ((a * n1 + row) * n2 + col));
-        }
-        if (SPLIT) {
-            const __amdgpu_buffer_rsrc_t rh = __builtin_amdgcn_make_buffer_rsrc(
-                const_cast<uint16_t*>(P.K2hi), (short)0, n2 * n2 * 2, kBufRsrcWord3);
-            const __amdgpu_buffer_rsrc_t rl = __builtin_amdgcn_make_buffer_rsrc(
-                const_cast<uint16_t*>(P.K2lo), (short)0, n2 * n2 * 2, kBufRsrcWord3);
-            const int krow = lane >> 2, kch = lane & 3;
-            const int nK = NP * 2;
-            for (int j = wave; j < 2 * nK; j += kThreads / 64) {
-                const int jj = j < nK ? j : j - nK;
-                const int pnl = jj / 2, row = (jj % 2) * 16 + krow;
+        const int krow = lane >> 2, kch = lane & 3;
+        for (int pnl = 0; pnl < NP; ++pnl) {
+            for (int q = wave; q < XC; q += kThreads / 64) {
+                const int j = pnl * XC + q, row = q * 8 + xrow;
+                const int col = kb0 + 32 * pnl + 4 * (xch ^ ((row >> 1) & 7));
+                lds_copy16(rx, Xs + j * 256, 4 * ((a * n1 + row) * n2 + col));
+            }
+            if (SPLIT) {
+                // wave w: 16 rows of the hi (w < 2) or lo panel
+                const int qq = wave & 1, row = qq * 16 + krow;
                 const int col = kb0 + 32 * pnl + 8 * (kch ^ ((row >> 2) & 3));
                 const int voff = 2 * ((c0 + row) * n2 + col);
-                if (j < nK) lds_copy16(rh, K2h + jj * 512, voff);
-                else lds_copy16(rl, K2l + jj * 512, voff);
-            }
-        } else {
-            const __amdgpu_buffer_rsrc_t rk = __builtin_amdgcn_make_buffer_rsrc(
-                const_cast<float*>(P.K2), (short)0, n2 * n2 * 4, kBufRsrcWord3);
-            for (int j = wave; j < NP * 4; j += kThreads / 64) {
-                const int pnl = j / 4, row = (j % 4) * 8 + xrow;
+                if (wave < 2) lds_copy16(rk, K2h + (pnl * 2 + qq) * 512, voff);
+                else lds_copy16(rkl, K2l + (pnl * 2 + qq) * 512, voff);
+            } else {
+                const int row = wave * 8 + xrow;
                 const int col = kb0 + 32 * pnl + 4 * (xch ^ ((row >> 1) & 7));
-                lds_copy16(rk, K2f + j * 256, 4 * ((c0 + row) * n2 + col));
+                lds_copy16(rk, K2f + (pnl * 4 + wave) * 256, 4 * ((c0 + row) * n2 + col));
             }
         }
     }
-    __builtin_amdgcn_s_waitcnt(0);
-    if (done) return;   // the step has stopped: nothing to compute (uniform)
-    __syncthreads();
+    if (done) {   // the step has stopped: nothing to compute (uniform)
+        __builtin_amdgcn_s_waitcnt(0);
+        return;
+    }
     const bool logx = lmode != 0;
     if (logx) {
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
         if (tid < n1) {
             float m = -INFINITY;
             for (int pnl = 0; pnl < NP; ++pnl)
@@ -836,6 +830,12 @@ plane_pass(Plane3D P) {
 #pragma unroll
         for (int f = 0; f < 2; ++f) acc[t][f] = f4{0.f, 0.f, 0.f, 0.f};
     for (int pnl = 0; pnl < NP; ++pnl) {
+        if (!logx) {   // this panel's copies of every wave have landed (bare barrier: no full wait)
+            wait_vm((NP - 1 - pnl) * CPP);
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            __builtin_amdgcn_s_barrier();
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        }
         if (SPLIT) {
             const int s4 = (lane >> 2) & 3;
             bf8 ah[2], al[2], bh[2], bl[2];
