@@ -107,7 +107,7 @@ CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1502_0621
 PROFILES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
 # counter summaries of the dominant launch per (workload, precision)
 TRAFFIC_PROFILES = {("crowd256", "fp32"): "resident2d_congestion_crowd256_traffic.md",
-                    ("crowd128c", "fp32"): "pass_prox_congestion_crowd128c_traffic.md"}
+                    ("crowd128c", "fp32"): "plane_pass_crowd128c_traffic.md"}
 
 
 def kernel_source_hash(kernel_file):
