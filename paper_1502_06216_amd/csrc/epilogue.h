@@ -239,7 +239,8 @@ __device__ __forceinline__ EpiIn epi_prefetch(const EpiArgs& E, int idx, int cnt
 //   PROX     s = v; p = prox(s); a = p / s; [p_out = p]       (0/0 = 0)
 // Log domain: the same with b, a held as log b, log a.
 // COH: b (b-update) and a (prox) are stored with device-scope stores.
-template <int EK, bool COH = false>
+// NE: elements of `val` computed (cnt <= NE); 1 for one output per lane.
+template <int EK, bool COH = false, int NE = 4>
 __device__ __forceinline__ void epi_apply(const EpiArgs& E, int idx, int cnt, f4 val, bool logx,
                                           const EpiIn& in, EpiAcc& acc) {
     if (cnt <= 0) return;
@@ -249,7 +250,7 @@ __device__ __forceinline__ void epi_apply(const EpiArgs& E, int idx, int cnt, f4
     } else if (EK == EK_BUPDATE) {
         f4 bn;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < NE; ++e) {
             const float q = in.u[e], t = val[e];
             if (logx) {
                 bn[e] = (q == 0.f) ? -INFINITY : logf(q) - t;
@@ -271,7 +272,7 @@ __device__ __forceinline__ void epi_apply(const EpiArgs& E, int idx, int cnt, f4
     } else if (EK == EK_ADJ_B) {
         f4 tb, qb;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < NE; ++e) {
             float dq;
             tb[e] = adj_b_cell(in.u[e], in.v[e], val[e], &dq);
             qb[e] = (dq != 0.f) ? in.w[e] + dq : in.w[e];
@@ -287,7 +288,7 @@ __device__ __forceinline__ void epi_apply(const EpiArgs& E, int idx, int cnt, f4
         constexpr int KIND = EK - EK_ADJ_PROX;
         f4 sb, dw;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < NE; ++e) {
             float d;
             sb[e] = adj_prox_cell<KIND>(E.prox, E.sigma, in.u[e], 0.f, val[e], in.v[e], in.w[e], &d);
             dw[e] = d;
@@ -297,14 +298,14 @@ __device__ __forceinline__ void epi_apply(const EpiArgs& E, int idx, int cnt, f4
         if (KIND == JKO_F_CONGESTION && E.acc) {
             f4 wb = COH ? ld4_coh(E.acc, idx, cnt, 0.f) : ld4(E.acc, idx, cnt, vec, 0.f);
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
+            for (int e = 0; e < NE; ++e)
                 if (dw[e] != 0.f) wb[e] += dw[e];
             if (COH) st4_coh(E.acc, idx, cnt, vec, wb);
             else st4(E.acc, idx, cnt, vec, wb);
         }
     } else if (EK == EK_MONITOR) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < NE; ++e) {
             if (e >= cnt) continue;
             const double bt = logx ? (double)expf(in.v[e] + val[e]) : (double)in.v[e] * (double)val[e];
             acc.err += fabs(bt - (double)in.u[e]);
@@ -313,7 +314,7 @@ __device__ __forceinline__ void epi_apply(const EpiArgs& E, int idx, int cnt, f4
         constexpr int KIND = EK - EK_PROX;
         f4 an, pn;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < NE; ++e) {
             if (logx) {
                 const float lp = log_prox_val<KIND>(E.prox, val[e], in.u[e], in.v[e]);
                 an[e] = (lp == -INFINITY) ? -INFINITY : lp - val[e];

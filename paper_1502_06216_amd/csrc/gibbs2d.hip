@@ -50,7 +50,7 @@ struct Smem {
     uint16_t Kjh[kT * kS2], Kjl[kT * kS2];   // split path: bfloat16 hi / lo of the bands
     uint16_t Kih[kT * kS2], Kil[kT * kS2];
     float Zs[kT * kS];      // [j][ib]
-    float red[7 * 64 * 4];
+    float red[8 * 4 * 64];  // [wave][element][lane] partial sums of the second contraction
     float sh1[kHalo];       // log domain: row shifts of the halo
     float sh2[kT];          // log domain: column shifts of Z
     double shd[8];
@@ -66,7 +66,8 @@ __device__ __forceinline__ int xcd_block() {
 // multiple of 4 (the extra entries meet exact zeros of the band).
 struct Tile {
     int i0, j0, ib0, jb0, LI, LJ, LIp, LJp;
-    int obase, ocnt;   // wave 0: this lane's run of outputs (i = lane & 15, j = 4 (lane >> 4) + e)
+    int obase, ocnt;   // this lane's run of outputs (i = lane & 15, j = 4 (lane >> 4) + e, e < ocnt);
+                       // wave e < 4 finishes element e
 };
 
 // Halo extents are padded to whole MFMA k-steps: 16 (FP32) or 32 (split).
@@ -257,7 +258,7 @@ __device__ __forceinline__ void stage_bands_split(const Band2D& B, const Tile& T
     }
 }
 
-// Both contractions of the staged tile and its epilogue (wave 0), then the
+// Both contractions of the staged tile and its epilogue (waves 0-3), then the
 // block's partials into slot `slot`.  Xs, Kj, Ki are staged, not yet synced.
 // COH: the scalings and partials the epilogue writes use device-scope stores.
 // SPLIT: each FP32 operand (X, then Z) is split into bfloat16 hi + lo as it is
@@ -388,21 +389,23 @@ __device__ __forceinline__ void contract_tile(const EpiArgs& E, const Tile& T, c
 #pragma unroll
         for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b[s], acc, 0, 0, 0);
     }
-    if (wave > 0) *reinterpret_cast<f4*>(&S.red[((wave - 1) * 64 + lane) * 4]) = acc;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) S.red[(wave * 4 + e) * 64 + lane] = acc[e];
     __syncthreads();
     EpiAcc ea;
-    if (wave == 0) {
+    if (wave < 4) {
+        // Wave v finishes element v of every lane's run, one output per lane:
+        // Y[i = i0 + (lane & 15)][j = j0 + koff + v], its partial sums added
+        // in wave order.
+        const int v = wave;
+        float y = S.red[v * 64 + lane];
 #pragma unroll
-        for (int w = 0; w < 7; ++w) acc += *reinterpret_cast<const f4*>(&S.red[(w * 64 + lane) * 4]);
-        // acc holds Y[i = i0 + (lane & 15)][j = j0 + koff + e]
+        for (int w = 1; w < 8; ++w) y += S.red[(w * 4 + v) * 64 + lane];
         if (logx) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const float m = S.sh2[koff + e];
-                acc[e] = (m != m) ? -INFINITY : (acc[e] > 0.f ? m + logf(acc[e]) : m - 104.f);
-            }
+            const float m = S.sh2[koff + v];
+            y = (m != m) ? -INFINITY : (y > 0.f ? m + logf(y) : m - 104.f);
         }
-        epi_apply<EK, COH>(E, T.obase, T.ocnt, acc, logx, ein, ea);
+        epi_apply<EK, COH, 1>(E, T.obase + v, v < T.ocnt ? 1 : 0, f4{y, 0.f, 0.f, 0.f}, logx, ein, ea);
     }
     epi_finish<COH>(E, ea, slot, S.shd);
 }
@@ -422,10 +425,10 @@ gibbs2d_kernel(Band2D B, EpiArgs E) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const Tile T = tile_of<SPLIT>(B, xcd_block(), lane);
 
-    // Wave 0 finishes the tile; its epilogue inputs are fetched now, ahead of
-    // the contraction.
+    // Waves 0-3 finish the tile (one output per lane each); their epilogue
+    // inputs are fetched now, ahead of the contraction.
     EpiIn ein;
-    if (wave == 0) ein = epi_prefetch<EK>(E, T.obase, T.ocnt);
+    if (wave < 4) ein = epi_prefetch<EK>(E, T.obase + wave, wave < T.ocnt ? 1 : 0);
 
     // the staging loads are issued before the LDS stores
     f4 bx[UXM];
@@ -596,14 +599,15 @@ resident2d(Resident2D R) {
     }
     // epilogue inputs that do not change over the iteration (q; the energy's fields)
     EpiIn inq, inp;
-    if (wave == 0) {
-        inq = epi_prefetch<EK_BUPDATE>(eb, T.obase, T.ocnt);
-        inp = epi_prefetch<PK>(ep, T.obase, T.ocnt);
+    if (wave < 4) {
+        inq = epi_prefetch<EK_BUPDATE>(eb, T.obase + wave, wave < T.ocnt ? 1 : 0);
+        inp = epi_prefetch<PK>(ep, T.obase + wave, wave < T.ocnt ? 1 : 0);
     }
     __syncthreads();
     const int nn = n_nbr;
     int lmode = C.logmode;
     uint32_t count = 0;   // phases this block has published
+    bool b_plain = false;  // b still plain after an absorption switch
 
     // One phase: stage the halo of X, contract, epilogue.  Specialised at
     // compile time on the domain (plain / log) and on whether the epilogue
@@ -631,7 +635,10 @@ resident2d(Resident2D R) {
         const bool chk = R.checks && k > 1 && (k - 1) % R.ce == 0;
         eb.t_out = R.hist ? R.hist + (2 * (int64_t)(k - 1)) * R.hist_stride : nullptr;
         EpiIn ia = inq;
-        if (chk && wave == 0) ia.v = ld4_coh(R.b, T.obase, T.ocnt, 0.f);
+        if (chk && wave < 4) {
+            ia.v = ld4_coh(R.b, T.obase + wave, wave < T.ocnt ? 1 : 0, 0.f);
+            if (b_plain) ia.v[0] = ia.v[0] > 0.f ? logf(ia.v[0]) : -INFINITY;
+        }
         if (!wait_for(R.sync, nn, nbr, count, R.spin_limit)) return;
         if (lmode) {
             if (chk) phase(ekb, yes(), yes(), eb, ia, R.a);
@@ -641,6 +648,7 @@ resident2d(Resident2D R) {
             else phase(ekb, no(), no(), eb, ia, R.a);
         }
         publish(R.sync, slot, ++count);
+        b_plain = false;
 
         // Stop test: block 0 waits for every block's partials, takes the
         // decision and publishes it.  No block writes partials again before
@@ -707,21 +715,21 @@ resident2d(Resident2D R) {
                 if (decision & 1u) return;   // same decision in every block
             }
             if (decision & 2u) {
-                // the switch takes effect after this proximal half-step:
-                // a <- log a, b <- log b on this block's own tile
+                // The switch takes effect after this proximal half-step:
+                // a <- log a on this block's own tile.  Its b is still being
+                // read by neighbours in this half-step, so it stays plain: the
+                // next b-update overwrites it, and a check there takes the log
+                // of the old b as it reads it.
                 if (tid < kT * kT) {
                     const int i = T.i0 + tid / kT, j = T.j0 + tid % kT;
                     if (i < B.n0 && j < B.n1) {
                         float* pa = R.a + (int64_t)i * B.n1 + j;
-                        float* pb = R.b + (int64_t)i * B.n1 + j;
                         const float av = __hip_atomic_load(pa, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        const float bv = __hip_atomic_load(pb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         __hip_atomic_store(pa, av > 0.f ? logf(av) : -INFINITY, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                        __hip_atomic_store(pb, bv > 0.f ? logf(bv) : -INFINITY, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
                     }
                 }
+                b_plain = true;
                 lmode = 1;
                 if (slot == 0 && tid == 0) {
                     C.logmode = 1;
@@ -730,6 +738,21 @@ resident2d(Resident2D R) {
                     R.ctl->absorb_pending = 0;
                 }
                 publish(R.sync, slot, ++count);
+            }
+        }
+    }
+
+    // A switch after the last proximal half-step: once the neighbours have
+    // finished it (they published the switch), b <- log b on this tile, where
+    // the closing monitor of a capped step reads it.
+    if (b_plain) {
+        if (!wait_for(R.sync, nn, nbr, count, R.spin_limit)) return;
+        if (tid < kT * kT) {
+            const int i = T.i0 + tid / kT, j = T.j0 + tid % kT;
+            if (i < B.n0 && j < B.n1) {
+                float* pb = R.b + (int64_t)i * B.n1 + j;
+                const float bv = __hip_atomic_load(pb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(pb, bv > 0.f ? logf(bv) : -INFINITY, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
     }
@@ -781,7 +804,7 @@ resident_adj(ResidentAdj R) {
     for (int k = R.K; k >= 1; --k) {
         eb.hin = R.hist + (2 * (int64_t)(k - 1)) * R.hist_stride;
         EpiIn ia;
-        if (wave == 0) ia = epi_prefetch<EK_ADJ_B, true>(eb, T.obase, T.ocnt);
+        if (wave < 4) ia = epi_prefetch<EK_ADJ_B, true>(eb, T.obase + wave, wave < T.ocnt ? 1 : 0);
         if (!wait_for(R.sync, nn, nbr, count, R.spin_limit)) return;
         {
             B.X = R.sbar;
@@ -794,7 +817,7 @@ resident_adj(ResidentAdj R) {
         if (k == 1) break;
         ep.hin = R.hist + (2 * (int64_t)(k - 2) + 1) * R.hist_stride;
         EpiIn ip;
-        if (wave == 0) ip = epi_prefetch<AK, true>(ep, T.obase, T.ocnt);
+        if (wave < 4) ip = epi_prefetch<AK, true>(ep, T.obase + wave, wave < T.ocnt ? 1 : 0);
         if (!wait_for(R.sync, nn, nbr, count, R.spin_limit)) return;
         {
             B.X = R.tbar;
