@@ -167,3 +167,32 @@ def test_check_cadences_same_bits(ce, tol, thr):
     wl = make_workload("crowd32", projected=False)
     res, ref = _both(wl, max_iters=400, tol=tol, check_every=ce, absorb_threshold=thr)
     _same(res, ref)
+
+
+def test_switch_after_the_last_iteration_same_bits():
+    """An absorption switch decided at the check of the last iteration takes
+    effect after its proximal half-step, where the capped step's closing
+    monitor reads the log-domain scalings: the resident kernel converts b
+    there once its neighbours are done with it.  The cap is the first one at
+    which the switch happens (found by bisection on the launch path)."""
+    banner("resident switch after the last iteration")
+    wl = make_workload("crowd32", projected=False)
+    g_en, _ = energies(wl)
+    q = dev(wl.p0)
+
+    def switched(k):
+        _, st = jk.step(q, g_en, wl.gamma, wl.tau, max_iters=k, check_every=1, absorb_threshold=50.0,
+                        resident=False)
+        return st["absorptions"] == 1
+
+    lo, hi = 1, 300
+    assert switched(hi) and not switched(lo)
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        if switched(mid):
+            hi = mid
+        else:
+            lo = mid
+    res, ref = _both(wl, max_iters=hi, check_every=1, absorb_threshold=50.0)
+    _same(res, ref)
+    assert res[1]["absorptions"] == 1 and res[1]["stop"] == "cap"
