@@ -25,6 +25,11 @@
 // Log domain (after the absorption switch): X holds log values; each row is
 // shifted by its maximum over the block's band before exponentiation, and the
 // output is shift + log(sum).
+//
+// 3D grids whose axes are multiples of 32 use two other kernels defined here,
+// which keep the layout: a plane pass (axes 2 and 1 of each plane, the
+// intermediate in LDS) and a slow-axis pass (axis 0, X staged transposed),
+// with the same arithmetic in the same order as the three axis passes.
 #include <math.h>
 
 #include <algorithm>

@@ -42,6 +42,7 @@ constexpr int kThr = 512;       // 8 waves per block
 constexpr int kMaxNeighbours = 9 * 9;   // halo reach of at most 4 tiles per side
 
 constexpr int kS2 = kHalo + 8;   // padded LDS row of a bfloat16 band (16-byte aligned)
+constexpr int kRS = 68;          // padded row of the partial sums (64 lanes)
 
 struct Smem {
     float Xs[kHalo * kS];   // [ib][jb]
@@ -50,7 +51,7 @@ struct Smem {
     uint16_t Kjh[kT * kS2], Kjl[kT * kS2];   // split path: bfloat16 hi / lo of the bands
     uint16_t Kih[kT * kS2], Kil[kT * kS2];
     float Zs[kT * kS];      // [j][ib]
-    float red[8 * 4 * 64];  // [wave][element][lane] partial sums of the second contraction
+    float red[8 * 4 * kRS];  // [wave][element][lane] partial sums of the second contraction
     float sh1[kHalo];       // log domain: row shifts of the halo
     float sh2[kT];          // log domain: column shifts of Z
     double shd[8];
@@ -66,8 +67,7 @@ __device__ __forceinline__ int xcd_block() {
 // multiple of 4 (the extra entries meet exact zeros of the band).
 struct Tile {
     int i0, j0, ib0, jb0, LI, LJ, LIp, LJp;
-    int obase, ocnt;   // this lane's run of outputs (i = lane & 15, j = 4 (lane >> 4) + e, e < ocnt);
-                       // wave e < 4 finishes element e
+    int eidx, ecnt;    // the output this thread finishes (waves 0-3; ecnt = 0 elsewhere or outside the grid)
 };
 
 // Halo extents are padded to whole MFMA k-steps: 16 (FP32) or 32 (split).
@@ -84,10 +84,12 @@ __device__ __forceinline__ Tile tile_of(const Band2D& B, int logical, int lane) 
     T.LJ = min(B.n1, T.j0 + kT + B.W1) - T.jb0;
     T.LIp = (T.LI + RND - 1) & ~(RND - 1);
     T.LJp = (T.LJ + RND - 1) & ~(RND - 1);
-    const int koff = 4 * (lane >> 4);
-    const int oi = T.i0 + (lane & 15);
-    T.obase = oi * B.n1 + T.j0 + koff;
-    T.ocnt = (oi < B.n0) ? max(0, min(4, B.n1 - (T.j0 + koff))) : 0;
+    // wave v < 4, lane l finish row i0 + 4 v + (l >> 4), column j0 + (l & 15):
+    // each store instruction writes whole row segments
+    const int wave = threadIdx.x >> 6;
+    const int ei = T.i0 + 4 * wave + (lane >> 4), ej = T.j0 + (lane & 15);
+    T.eidx = ei * B.n1 + ej;
+    T.ecnt = (wave < 4 && ei < B.n0 && ej < B.n1) ? 1 : 0;
     return T;
 }
 
@@ -390,22 +392,23 @@ __device__ __forceinline__ void contract_tile(const EpiArgs& E, const Tile& T, c
         for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b[s], acc, 0, 0, 0);
     }
 #pragma unroll
-    for (int e = 0; e < 4; ++e) S.red[(wave * 4 + e) * 64 + lane] = acc[e];
+    for (int e = 0; e < 4; ++e) S.red[(wave * 4 + e) * kRS + lane] = acc[e];
     __syncthreads();
     EpiAcc ea;
     if (wave < 4) {
-        // Wave v finishes element v of every lane's run, one output per lane:
-        // Y[i = i0 + (lane & 15)][j = j0 + koff + v], its partial sums added
+        // One output per lane (Tile::eidx): Y[i][j] sits in element j & 3 of
+        // MFMA lane (i - i0) + 16 ((j - j0) >> 2); its partial sums are added
         // in wave order.
-        const int v = wave;
-        float y = S.red[v * 64 + lane];
+        const int il = 4 * wave + (lane >> 4), jl = lane & 15;
+        const int src = il + 16 * (jl >> 2), e = jl & 3;
+        float y = S.red[e * kRS + src];
 #pragma unroll
-        for (int w = 1; w < 8; ++w) y += S.red[(w * 4 + v) * 64 + lane];
+        for (int w = 1; w < 8; ++w) y += S.red[(w * 4 + e) * kRS + src];
         if (logx) {
-            const float m = S.sh2[koff + v];
+            const float m = S.sh2[jl];
             y = (m != m) ? -INFINITY : (y > 0.f ? m + logf(y) : m - 104.f);
         }
-        epi_apply<EK, COH, 1>(E, T.obase + v, v < T.ocnt ? 1 : 0, f4{y, 0.f, 0.f, 0.f}, logx, ein, ea);
+        epi_apply<EK, COH, 1>(E, T.eidx, T.ecnt, f4{y, 0.f, 0.f, 0.f}, logx, ein, ea);
     }
     epi_finish<COH>(E, ea, slot, S.shd);
 }
@@ -428,7 +431,7 @@ gibbs2d_kernel(Band2D B, EpiArgs E) {
     // Waves 0-3 finish the tile (one output per lane each); their epilogue
     // inputs are fetched now, ahead of the contraction.
     EpiIn ein;
-    if (wave < 4) ein = epi_prefetch<EK>(E, T.obase + wave, wave < T.ocnt ? 1 : 0);
+    if (wave < 4) ein = epi_prefetch<EK>(E, T.eidx, T.ecnt);
 
     // the staging loads are issued before the LDS stores
     f4 bx[UXM];
@@ -600,8 +603,8 @@ resident2d(Resident2D R) {
     // epilogue inputs that do not change over the iteration (q; the energy's fields)
     EpiIn inq, inp;
     if (wave < 4) {
-        inq = epi_prefetch<EK_BUPDATE>(eb, T.obase + wave, wave < T.ocnt ? 1 : 0);
-        inp = epi_prefetch<PK>(ep, T.obase + wave, wave < T.ocnt ? 1 : 0);
+        inq = epi_prefetch<EK_BUPDATE>(eb, T.eidx, T.ecnt);
+        inp = epi_prefetch<PK>(ep, T.eidx, T.ecnt);
     }
     __syncthreads();
     const int nn = n_nbr;
@@ -636,7 +639,7 @@ resident2d(Resident2D R) {
         eb.t_out = R.hist ? R.hist + (2 * (int64_t)(k - 1)) * R.hist_stride : nullptr;
         EpiIn ia = inq;
         if (chk && wave < 4) {
-            ia.v = ld4_coh(R.b, T.obase + wave, wave < T.ocnt ? 1 : 0, 0.f);
+            ia.v = ld4_coh(R.b, T.eidx, T.ecnt, 0.f);
             if (b_plain) ia.v[0] = ia.v[0] > 0.f ? logf(ia.v[0]) : -INFINITY;
         }
         if (!wait_for(R.sync, nn, nbr, count, R.spin_limit)) return;
@@ -804,7 +807,7 @@ resident_adj(ResidentAdj R) {
     for (int k = R.K; k >= 1; --k) {
         eb.hin = R.hist + (2 * (int64_t)(k - 1)) * R.hist_stride;
         EpiIn ia;
-        if (wave < 4) ia = epi_prefetch<EK_ADJ_B, true>(eb, T.obase + wave, wave < T.ocnt ? 1 : 0);
+        if (wave < 4) ia = epi_prefetch<EK_ADJ_B, true>(eb, T.eidx, T.ecnt);
         if (!wait_for(R.sync, nn, nbr, count, R.spin_limit)) return;
         {
             B.X = R.sbar;
@@ -817,7 +820,7 @@ resident_adj(ResidentAdj R) {
         if (k == 1) break;
         ep.hin = R.hist + (2 * (int64_t)(k - 2) + 1) * R.hist_stride;
         EpiIn ip;
-        if (wave < 4) ip = epi_prefetch<AK, true>(ep, T.obase + wave, wave < T.ocnt ? 1 : 0);
+        if (wave < 4) ip = epi_prefetch<AK, true>(ep, T.eidx, T.ecnt);
         if (!wait_for(R.sync, nn, nbr, count, R.spin_limit)) return;
         {
             B.X = R.tbar;
