@@ -96,7 +96,7 @@ __global__ void k_ctl_reset(Ctl* c, int logmode) {
     }
 }
 
-// Deterministic single-block sum / max of `n` partials.
+// Deterministic single-block sum of `n` partials.
 __device__ double fixed_sum(const double* v, int n, double* sh) {
     double s = 0.0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) s += v[i];
@@ -104,19 +104,6 @@ __device__ double fixed_sum(const double* v, int n, double* sh) {
     __syncthreads();
     for (int o = blockDim.x / 2; o > 0; o >>= 1) {
         if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-        __syncthreads();
-    }
-    const double r = sh[0];
-    __syncthreads();
-    return r;
-}
-__device__ double fixed_max(const double* v, int n, double* sh) {
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) s = fmax(s, v[i]);
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
         __syncthreads();
     }
     const double r = sh[0];
