@@ -85,6 +85,9 @@ def test_argument_errors_before_any_launch(lib):
     assert b"ndim" in lib.jko_last_error()
     big = nat.make_grid((2048, 8))
     assert _call_step(lib, big, en, prm) == jk.JKO_ERR_INVALID
+    empty = nat.make_grid((0, 8))   # an empty grid is refused, not silently skipped
+    assert _call_step(lib, empty, en, prm) == jk.JKO_ERR_INVALID
+    assert b"n[k]" in lib.jko_last_error()
     for field, val in (("gamma", 0.0), ("gamma", math.nan), ("tau", -1.0), ("max_iters", 0),
                        ("check_every", 0), ("precision", 7), ("flags", 4), ("flags", -1)):
         p2 = nat.make_params(1e-3, 1e-3, 10)

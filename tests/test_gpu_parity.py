@@ -71,6 +71,41 @@ def test_gibbs_apply_128cube_sampled(precision):
     assert rel_l1(y[idx], ref) <= GIBBS_TOL[precision]
 
 
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+def test_gibbs_apply_largest_axes(precision):
+    """The largest axis the boundary accepts (1024): a full 1D product, and
+    sampled outputs of a 1024 x 1024 grid against the plain sum."""
+    banner(f"gibbs largest axes {precision}")
+    rng = np.random.default_rng(21)
+    x1 = rng.uniform(0.0, 1.0, size=(1024,)) * np.exp(rng.normal(0, 2, size=(1024,)))
+    y1 = jk.gibbs_apply(dev(x1), 1e-4, precision)
+    assert rel_l1(host64(y1), O.gibbs_apply(f32(x1).astype(np.float64), 1e-4)) <= GIBBS_TOL[precision]
+    shape = (1024, 1024)
+    x = rng.uniform(0.0, 1.0, size=shape).astype(np.float32).astype(np.float64)
+    y = host64(jk.gibbs_apply(dev(x), 2e-5, precision)).ravel()
+    idx = np.concatenate([[0, 1023, 1024 * 1023, x.size - 1], rng.choice(x.size, size=28, replace=False)])
+    ref = O.gibbs_rows(shape, 2e-5, idx, x)
+    assert rel_l1(y[idx], ref) <= GIBBS_TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+def test_step_on_the_largest_2d_grid(precision):
+    """A few iterations of a congestion step on 1024 x 1024 against the oracle.
+    At this gamma the bumps' tails leave scalings in the float32 denormal
+    range, which the split-BF16 products do not keep (s rounds to 0, a to 0,
+    t to 0 and b = q / t overflows: reported as non-finite); the split run
+    therefore uses the log domain, whose result equals the plain iteration's."""
+    banner(f"step 1024^2 {precision}")
+    wl = small_case((1024, 1024), "congestion", seed=12)
+    g_en, o_en = energies(wl)
+    thr = 0.0 if precision == "split_bf16" else float("inf")
+    p, st = jk.step(dev(wl.p0), g_en, wl.gamma, wl.tau, max_iters=6, precision=precision, absorb_threshold=thr)
+    ref, _ = O.jko_step(f32(wl.p0).astype(np.float64), o_en, wl.gamma, wl.tau, 6)
+    err = rel_l1(host64(p), ref)
+    print(f"[gpu-test] accuracy 1024^2 6 it {precision}: rel-L1 vs FP64 oracle {err:.3e}", flush=True)
+    assert err <= TOL[precision]
+
+
 def test_gibbs_apply_deterministic():
     x = dev(np.random.default_rng(0).uniform(size=(130, 70)))
     y1 = jk.gibbs_apply(x, 2e-3)
