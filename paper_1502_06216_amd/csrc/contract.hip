@@ -706,7 +706,7 @@ hipError_t launch_ek(int ek, int cfg, int64_t nb, const Pass& p, const EpiArgs& 
 // transposed.  Two launches per application instead of three, and one trip
 // of the field through memory fewer.
 
-constexpr int kPlaneMaxN1 = 128;             // one 32-row chunk of b' per wave in the second stage
+constexpr int kPlaneMaxN1 = 128;             // one 16-row fragment of b per wave in the first stage
 constexpr int kPlaneQ = kPlaneMaxN1 / 32;    // band panels of a b' chunk
 
 __host__ __device__ inline int band_lo32(int i0, int W) { return (i0 - W > 0 ? i0 - W : 0) & ~31; }
@@ -719,12 +719,15 @@ __host__ __device__ inline int band_hi32(int i0, int W, int n) {
 // split K2 hi + lo take the bytes of the FP32 panels), later the intermediate.
 int plane_lds_bytes(int n1, int NP) { return std::max(NP * (n1 + 32) * 128, 32 * (n1 + 4) * 4); }
 
+constexpr int kPlaneWaves = 8;                 // 512 threads: two waves per SIMD per block
+constexpr int kPlaneThr = 64 * kPlaneWaves;
+
 template <bool SPLIT>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kPlaneThr)
 plane_pass(Plane3D P) {
     extern __shared__ __attribute__((aligned(16))) float dyn[];
-    __shared__ float fshift[kPlaneMaxN1];   // first stage: row shifts (log domain)
-    __shared__ float cshift[4][32];         // second stage: column shifts of each wave's chunk
+    __shared__ float fshift[kPlaneMaxN1];            // first stage: row shifts (log domain)
+    __shared__ float cshift[kPlaneWaves][32];        // second stage: column shifts of each wave's chunk
 
     int done = 0, lmode = 0;
     if (P.ctl) {
@@ -745,37 +748,33 @@ plane_pass(Plane3D P) {
     const int ZS = n1 + 4;
     float* Zt = dyn;                                                   // [32][ZS] after the first stage
 
-    // Second-stage factor operands of this wave (rows b' of its chunk over
-    // their band), fetched from global memory ahead of everything else.
-    const int bq0 = 32 * wave;
+    // Second stage: waves 2q and 2q + 1 share the 32-row chunk q of b', one
+    // 16-row fragment each.  Their factor rows over the chunk's band are
+    // fetched from global memory ahead of everything else.
+    const int bq0 = 32 * (wave >> 1);
+    const int bt = bq0 + 16 * (wave & 1);   // first b' of this wave's fragment
     const bool s2 = bq0 < n1;
     const int qb0 = s2 ? band_lo32(bq0, P.W1) : 0;
     const int NQ = s2 ? (band_hi32(bq0, P.W1, n1) - qb0) >> 5 : 0;
-    f4 kq[kPlaneQ][2][2];
-    bf8 kqh[kPlaneQ][2], kql[kPlaneQ][2];
+    f4 kq[kPlaneQ][2];
+    bf8 kqh[kPlaneQ], kql[kPlaneQ];
 #pragma unroll
-    for (int q = 0; q < kPlaneQ; ++q)
+    for (int q = 0; q < kPlaneQ; ++q) {
+        if (q >= NQ) continue;
+        const int row = bt + (lane & 15);
+        const int kb = qb0 + 32 * q;
+        if (SPLIT) {
+            kqh[q] = __builtin_bit_cast(bf8, *reinterpret_cast<const u16x8*>(P.K1hi + row * n1 + kb + 8 * g));
+            kql[q] = __builtin_bit_cast(bf8, *reinterpret_cast<const u16x8*>(P.K1lo + row * n1 + kb + 8 * g));
+        } else {
 #pragma unroll
-        for (int f = 0; f < 2; ++f) {
-            if (q >= NQ) continue;
-            const int row = bq0 + f * 16 + (lane & 15);
-            const int kb = qb0 + 32 * q;
-            if (SPLIT) {
-                kqh[q][f] = __builtin_bit_cast(bf8, *reinterpret_cast<const u16x8*>(P.K1hi + row * n1 + kb + 8 * g));
-                kql[q][f] = __builtin_bit_cast(bf8, *reinterpret_cast<const u16x8*>(P.K1lo + row * n1 + kb + 8 * g));
-            } else {
-#pragma unroll
-                for (int h = 0; h < 2; ++h)
-                    kq[q][f][h] = *reinterpret_cast<const f4*>(P.K1 + row * n1 + kb + 4 * (4 * h + g));
-            }
+            for (int h = 0; h < 2; ++h)
+                kq[q][h] = *reinterpret_cast<const f4*>(P.K1 + row * n1 + kb + 4 * (4 * h + g));
         }
+    }
 
     // First-stage staging: the plane's rows over the band, and the K2 rows of
-    // the chunk (layout and swizzle of the panel form), panel by panel: each
-    // wave issues CPP copies per panel, so panel p has landed once at most
-    // (NP - 1 - p) CPP of its copies are outstanding.
-    const int XC = n1 / 8;         // 8-row X copies per panel (a multiple of 4)
-    const int CPP = XC / 4 + 1;    // per wave: X copies and one K2 copy (FP32 rows, or hi / lo)
+    // the chunk (layout and swizzle of the panel form).
     {
         const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
             const_cast<float*>(P.X), (short)0, P.n0 * n1 * n2 * 4, kBufRsrcWord3);
@@ -786,34 +785,33 @@ plane_pass(Plane3D P) {
             const_cast<uint16_t*>(SPLIT ? P.K2lo : P.K2hi), (short)0, n2 * n2 * 2, kBufRsrcWord3);
         const int xrow = lane >> 3, xch = lane & 7;
         const int krow = lane >> 2, kch = lane & 3;
-        for (int pnl = 0; pnl < NP; ++pnl) {
-            for (int q = wave; q < XC; q += kThreads / 64) {
-                const int j = pnl * XC + q, row = q * 8 + xrow;
-                const int col = kb0 + 32 * pnl + 4 * (xch ^ ((row >> 1) & 7));
-                lds_copy16(rx, Xs + j * 256, 4 * ((a * n1 + row) * n2 + col));
-            }
+        const int XC = n1 / 8;   // 8-row X copies per panel
+        for (int j = wave; j < NP * XC; j += kPlaneWaves) {
+            const int pnl = j / XC, row = (j % XC) * 8 + xrow;
+            const int col = kb0 + 32 * pnl + 4 * (xch ^ ((row >> 1) & 7));
+            lds_copy16(rx, Xs + j * 256, 4 * ((a * n1 + row) * n2 + col));
+        }
+        // K2: four copies per panel (FP32: 8 rows each; split: 16 rows of hi, then lo)
+        for (int j = wave; j < NP * 4; j += kPlaneWaves) {
+            const int pnl = j >> 2, q = j & 3;
             if (SPLIT) {
-                // wave w: 16 rows of the hi (w < 2) or lo panel
-                const int qq = wave & 1, row = qq * 16 + krow;
+                const int qq = q & 1, row = qq * 16 + krow;
                 const int col = kb0 + 32 * pnl + 8 * (kch ^ ((row >> 2) & 3));
                 const int voff = 2 * ((c0 + row) * n2 + col);
-                if (wave < 2) lds_copy16(rk, K2h + (pnl * 2 + qq) * 512, voff);
+                if (q < 2) lds_copy16(rk, K2h + (pnl * 2 + qq) * 512, voff);
                 else lds_copy16(rkl, K2l + (pnl * 2 + qq) * 512, voff);
             } else {
-                const int row = wave * 8 + xrow;
+                const int row = q * 8 + xrow;
                 const int col = kb0 + 32 * pnl + 4 * (xch ^ ((row >> 1) & 7));
-                lds_copy16(rk, K2f + (pnl * 4 + wave) * 256, 4 * ((c0 + row) * n2 + col));
+                lds_copy16(rk, K2f + j * 256, 4 * ((c0 + row) * n2 + col));
             }
         }
     }
-    if (done) {   // the step has stopped: nothing to compute (uniform)
-        __builtin_amdgcn_s_waitcnt(0);
-        return;
-    }
+    __builtin_amdgcn_s_waitcnt(0);
+    if (done) return;   // the step has stopped: nothing to compute (uniform)
+    __syncthreads();
     const bool logx = lmode != 0;
     if (logx) {
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
         if (tid < n1) {
             float m = -INFINITY;
             for (int pnl = 0; pnl < NP; ++pnl)
@@ -821,89 +819,61 @@ plane_pass(Plane3D P) {
             fshift[tid] = (m == -INFINITY) ? NAN : m;
         }
         __syncthreads();
-        for (int u = tid; u < NP * n1 * 32; u += kThreads) Xs[u] = shifted_exp(Xs[u], fshift[(u >> 5) % n1]);
+        for (int u = tid; u < NP * n1 * 32; u += kPlaneThr) Xs[u] = shifted_exp(Xs[u], fshift[(u >> 5) % n1]);
         __syncthreads();
     }
 
     // ---- first stage: Z[b][c'] = sum_c X[b][c] K2[c'][c]; wave w owns the
-    // 16-row fragments w and w + 4 of b, both 16-column fragments of c'
-    const int nfb = n1 >> 4;
+    // 16-row fragment w of b and both 16-column fragments of c'
+    const int fb = wave;
+    const bool s1 = fb < (n1 >> 4);
     const int s8 = (lane >> 1) & 7;
-    f4 acc[2][2];
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-        for (int f = 0; f < 2; ++f) acc[t][f] = f4{0.f, 0.f, 0.f, 0.f};
-    for (int pnl = 0; pnl < NP; ++pnl) {
-        if (!logx) {   // this panel's copies of every wave have landed (bare barrier: no full wait)
-            wait_vm((NP - 1 - pnl) * CPP);
-            __atomic_signal_fence(__ATOMIC_SEQ_CST);
-            __builtin_amdgcn_s_barrier();
-            __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        }
-        if (SPLIT) {
-            const int s4 = (lane >> 2) & 3;
-            bf8 ah[2], al[2], bh[2], bl[2];
-#pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                const int fb = wave + 4 * t;
-                if (fb >= nfb) continue;
-                const float* xr = Xs + (pnl * n1 + fb * 16 + (lane & 15)) * 32;
+    f4 acc[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
+    if (s1) {
+        for (int pnl = 0; pnl < NP; ++pnl) {
+            const float* xr = Xs + (pnl * n1 + fb * 16 + (lane & 15)) * 32;
+            if (SPLIT) {
+                const int s4 = (lane >> 2) & 3;
+                bf8 ah, al, bh[2], bl[2];
                 const f4 v0 = *reinterpret_cast<const f4*>(xr + 4 * ((2 * g) ^ s8));
                 const f4 v1 = *reinterpret_cast<const f4*>(xr + 4 * ((2 * g + 1) ^ s8));
-                split_bf16(v0, v1, ah[t], al[t]);
-            }
-#pragma unroll
-            for (int f = 0; f < 2; ++f) {
-                const int o = (pnl * 32 + f * 16 + (lane & 15)) * 32 + 8 * (g ^ s4);
-                bh[f] = __builtin_bit_cast(bf8, *reinterpret_cast<const u16x8*>(K2h + o));
-                bl[f] = __builtin_bit_cast(bf8, *reinterpret_cast<const u16x8*>(K2l + o));
-            }
-#pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                if (wave + 4 * t >= nfb) continue;
+                split_bf16(v0, v1, ah, al);
 #pragma unroll
                 for (int f = 0; f < 2; ++f) {
-                    acc[t][f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[t], bh[f], acc[t][f], 0, 0, 0);
-                    acc[t][f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[t], bl[f], acc[t][f], 0, 0, 0);
-                    acc[t][f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[t], bh[f], acc[t][f], 0, 0, 0);
-                }
-            }
-        } else {
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int ch = 4 * ((4 * h + g) ^ s8);
-                f4 av[2], bv[2];
-#pragma unroll
-                for (int t = 0; t < 2; ++t) {
-                    const int fb = wave + 4 * t;
-                    av[t] = fb < nfb ? *reinterpret_cast<const f4*>(Xs + (pnl * n1 + fb * 16 + (lane & 15)) * 32 + ch)
-                                     : f4{0.f, 0.f, 0.f, 0.f};
+                    const int o = (pnl * 32 + f * 16 + (lane & 15)) * 32 + 8 * (g ^ s4);
+                    bh[f] = __builtin_bit_cast(bf8, *reinterpret_cast<const u16x8*>(K2h + o));
+                    bl[f] = __builtin_bit_cast(bf8, *reinterpret_cast<const u16x8*>(K2l + o));
                 }
 #pragma unroll
-                for (int f = 0; f < 2; ++f)
-                    bv[f] = *reinterpret_cast<const f4*>(K2f + (pnl * 32 + f * 16 + (lane & 15)) * 32 + ch);
+                for (int f = 0; f < 2; ++f) {
+                    acc[f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[f], acc[f], 0, 0, 0);
+                    acc[f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[f], acc[f], 0, 0, 0);
+                    acc[f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[f], acc[f], 0, 0, 0);
+                }
+            } else {
 #pragma unroll
-                for (int s = 0; s < 4; ++s)
+                for (int h = 0; h < 2; ++h) {
+                    const int ch = 4 * ((4 * h + g) ^ s8);
+                    const f4 av = *reinterpret_cast<const f4*>(xr + ch);
+                    f4 bv[2];
 #pragma unroll
-                    for (int t = 0; t < 2; ++t) {
-                        if (wave + 4 * t >= nfb) continue;
+                    for (int f = 0; f < 2; ++f)
+                        bv[f] = *reinterpret_cast<const f4*>(K2f + (pnl * 32 + f * 16 + (lane & 15)) * 32 + ch);
+#pragma unroll
+                    for (int s = 0; s < 4; ++s)
 #pragma unroll
                         for (int f = 0; f < 2; ++f)
-                            acc[t][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t][s], bv[f][s], acc[t][f], 0, 0, 0);
-                    }
+                            acc[f] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], bv[f][s], acc[f], 0, 0, 0);
+                }
             }
         }
     }
     __syncthreads();   // every wave is done with the staged panels: the intermediate replaces them
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        const int fb = wave + 4 * t;
-        if (fb >= nfb) continue;
+    if (s1) {
         const int b = fb * 16 + 4 * g;
 #pragma unroll
         for (int f = 0; f < 2; ++f) {
-            f4 v = acc[t][f];
+            f4 v = acc[f];
             if (logx)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) v[e] = shifted_log(v[e], fshift[b + e]);
@@ -927,11 +897,7 @@ plane_pass(Plane3D P) {
 #pragma unroll
         for (int f = 0; f < 2; ++f) csh[f] = cshift[wave][f * 16 + (lane & 15)];
     }
-    f4 acc2[2][2];
-#pragma unroll
-    for (int f = 0; f < 2; ++f)
-#pragma unroll
-        for (int t = 0; t < 2; ++t) acc2[f][t] = f4{0.f, 0.f, 0.f, 0.f};
+    f4 acc2[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
     for (int q = 0; q < kPlaneQ; ++q) {
         if (q >= NQ) continue;
@@ -952,13 +918,11 @@ plane_pass(Plane3D P) {
                 split_bf16(v0, v1, ah[f], al[f]);
             }
 #pragma unroll
-            for (int f = 0; f < 2; ++f)
-#pragma unroll
-                for (int t = 0; t < 2; ++t) {
-                    acc2[f][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[f], kqh[q][t], acc2[f][t], 0, 0, 0);
-                    acc2[f][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[f], kql[q][t], acc2[f][t], 0, 0, 0);
-                    acc2[f][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[f], kqh[q][t], acc2[f][t], 0, 0, 0);
-                }
+            for (int f = 0; f < 2; ++f) {
+                acc2[f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[f], kqh[q], acc2[f], 0, 0, 0);
+                acc2[f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[f], kql[q], acc2[f], 0, 0, 0);
+                acc2[f] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[f], kqh[q], acc2[f], 0, 0, 0);
+            }
         } else {
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
@@ -974,25 +938,21 @@ plane_pass(Plane3D P) {
                 for (int s = 0; s < 4; ++s)
 #pragma unroll
                     for (int f = 0; f < 2; ++f)
-#pragma unroll
-                        for (int t = 0; t < 2; ++t)
-                            acc2[f][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[f][s], kq[q][t][h][s], acc2[f][t], 0, 0, 0);
+                        acc2[f] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[f][s], kq[q][h][s], acc2[f], 0, 0, 0);
             }
         }
     }
-    // lane: c' = 16 f + 4 g + e, b' = bq0 + 16 t + (lane & 15)
+    // lane: c' = 16 f + 4 g + e, b' = bt + (lane & 15)
 #pragma unroll
-    for (int f = 0; f < 2; ++f)
+    for (int f = 0; f < 2; ++f) {
+        const int cl = f * 16 + 4 * g;
+        f4 v = acc2[f];
+        if (logx)
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
-            const int cl = f * 16 + 4 * g;
-            f4 v = acc2[f][t];
-            if (logx)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) v[e] = shifted_log(v[e], cshift[wave][cl + e]);
-            const int bp = bq0 + t * 16 + (lane & 15);
-            __builtin_nontemporal_store(v, reinterpret_cast<f4*>(P.Y + ((int64_t)a * n1 + bp) * n2 + c0 + cl));
-        }
+            for (int e = 0; e < 4; ++e) v[e] = shifted_log(v[e], cshift[wave][cl + e]);
+        const int bp = bt + (lane & 15);
+        __builtin_nontemporal_store(v, reinterpret_cast<f4*>(P.Y + ((int64_t)a * n1 + bp) * n2 + c0 + cl));
+    }
 }
 
 // Slow-axis pass: Y[i][r] = sum_k K1[i][k] X[k][r] (X: n x R, rows contiguous
@@ -1244,9 +1204,9 @@ hipError_t launch_plane3d(const Plane3D& p, int32_t precision, int* nblocks, hip
     if (nblocks) *nblocks = (int)nb;
     const int lds = plane_lds_bytes(p.n1, band_panels(p.n2, p.W2));
     if (precision == JKO_SPLIT_BF16)
-        hipLaunchKernelGGL(plane_pass<true>, dim3((unsigned)nb), dim3(kThreads), lds, stream, p);
+        hipLaunchKernelGGL(plane_pass<true>, dim3((unsigned)nb), dim3(kPlaneThr), lds, stream, p);
     else
-        hipLaunchKernelGGL(plane_pass<false>, dim3((unsigned)nb), dim3(kThreads), lds, stream, p);
+        hipLaunchKernelGGL(plane_pass<false>, dim3((unsigned)nb), dim3(kPlaneThr), lds, stream, p);
     return hipGetLastError();
 }
 
