@@ -398,7 +398,9 @@ __device__ __forceinline__ void wait_vm_n() {
     __builtin_amdgcn_s_waitcnt((N & 0xF) | (((N >> 4) & 3) << 14) | (0x7 << 4) | (0xF << 8));
 }
 __device__ __forceinline__ void wait_vm(int n) {
-    switch (n) {
+    // n is the same in every lane; read it as a scalar so the switch is a
+    // uniform branch (a wait in a case skipped under exec would still run)
+    switch (__builtin_amdgcn_readfirstlane(n)) {
 #define JKO_VM(N) case N: wait_vm_n<N>(); break;
         JKO_VM(0) JKO_VM(1) JKO_VM(2) JKO_VM(3) JKO_VM(4) JKO_VM(5) JKO_VM(6) JKO_VM(7)
         JKO_VM(8) JKO_VM(9) JKO_VM(10) JKO_VM(11) JKO_VM(12) JKO_VM(13) JKO_VM(14) JKO_VM(15)
@@ -411,6 +413,26 @@ __device__ __forceinline__ void wait_vm(int n) {
 
 __device__ __forceinline__ void lds_copy16(__amdgpu_buffer_rsrc_t rs, void* lds, int voff) {
     __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)lds, 16, voff, 0, 0, 0);
+}
+
+// The same copy as an instruction the compiler does not track.  The compiler
+// makes every LDS read wait for all the LDS copies it knows to be in flight
+// (it cannot tell which LDS they write), so with tracked copies a read of a
+// landed panel still waits for the whole band; issued this way, the caller
+// alone waits for them (vmcnt, then a barrier) before any access to their
+// destination.  The buffer descriptor is built by hand (base, no stride,
+// range in bytes); the s_nop covers the wait states between writing M0 or the
+// descriptor and the load that reads them.
+typedef int i4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ i4v buffer_desc(const void* base, int nbytes) {
+    const uint64_t a = reinterpret_cast<uint64_t>(base);
+    return i4v{(int)(uint32_t)a, (int)(uint32_t)((a >> 32) & 0xFFFF), nbytes, kBufRsrcWord3};
+}
+
+__device__ __forceinline__ void lds_copy16_untracked(i4v rs, void* lds, int voff) {
+    const uint32_t m0 = (uint32_t)reinterpret_cast<uintptr_t>((__attribute__((address_space(3))) void*)lds);
+    asm volatile("s_nop 4\n\tbuffer_load_dwordx4 %0, %1, 0 offen lds" ::"v"(voff), "s"(rs), "{m0}"(m0) : "memory");
 }
 
 template <int TR, int TI, int WR, int WI, bool SPLIT, int EK>
@@ -1002,25 +1024,15 @@ contract_slow(Pass P, EpiArgs E) {
         const int i = i0 + il, r = r0 + rl;
         ecnt[u] = (unit < TI * TR / 4 && i < n) ? max(0, min(4, R - r)) : 0;
         eidx[u] = i * R + r;
-        ein[u] = epi_prefetch<EK>(E, eidx[u], ecnt[u]);
+        ein[u] = epi_prefetch<EK, false, true>(E, eidx[u], ecnt[u]);   // whole tiles
     }
     {
-        const __amdgpu_buffer_rsrc_t rx =
-            __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(P.X), (short)0, R * n * 4, kBufRsrcWord3);
-        // X: 4 rows of 64 r per wave-wide copy; lane L fills position L & 15 of
-        // row 4 j + (L >> 4) with the chunk that the swizzle puts there
-        const int krow = lane >> 4, pos = lane & 15;
-        for (int j = wave; j < NP * 8; j += kThreads / 64) {
-            const int pnl = j / 8, k = (j % 8) * 4 + krow;
-            const int c = pos ^ (4 * ((k >> 2) & 3));
-            lds_copy16(rx, Xs + j * 256, 4 * ((kb0 + 32 * pnl + k) * R + r0 + 4 * c));
-        }
+        // copies issued untracked, K first, then X panel by panel: each
+        // wave issues two X copies per panel, so panel p has landed for this
+        // wave once at most 2 (NP - 1 - p) copies are outstanding
         const int xrow = lane >> 3, xch = lane & 7;
         if (SPLIT) {
-            const __amdgpu_buffer_rsrc_t rh = __builtin_amdgcn_make_buffer_rsrc(
-                const_cast<uint16_t*>(P.K1hi), (short)0, n * n * 2, kBufRsrcWord3);
-            const __amdgpu_buffer_rsrc_t rl = __builtin_amdgcn_make_buffer_rsrc(
-                const_cast<uint16_t*>(P.K1lo), (short)0, n * n * 2, kBufRsrcWord3);
+            const i4v rh = buffer_desc(P.K1hi, n * n * 2), rl = buffer_desc(P.K1lo, n * n * 2);
             constexpr int KPP = TI / 16;
             const int nK = NP * KPP;
             const int kr = lane >> 2, kch = lane & 3;
@@ -1029,25 +1041,33 @@ contract_slow(Pass P, EpiArgs E) {
                 const int pnl = jj / KPP, row = (jj % KPP) * 16 + kr;
                 const int col = kb0 + 32 * pnl + 8 * (kch ^ ((row >> 2) & 3));
                 const int voff = 2 * ((i0 + row) * n + col);
-                if (j < nK) lds_copy16(rh, Kh + jj * 512, voff);
-                else lds_copy16(rl, Kl + jj * 512, voff);
+                if (j < nK) lds_copy16_untracked(rh, Kh + jj * 512, voff);
+                else lds_copy16_untracked(rl, Kl + jj * 512, voff);
             }
         } else {
-            const __amdgpu_buffer_rsrc_t rk = __builtin_amdgcn_make_buffer_rsrc(
-                const_cast<float*>(P.K1), (short)0, n * n * 4, kBufRsrcWord3);
+            const i4v rk = buffer_desc(P.K1, n * n * 4);
             constexpr int KPP = TI / 8;
             for (int j = wave; j < NP * KPP; j += kThreads / 64) {
                 const int pnl = j / KPP, row = (j % KPP) * 8 + xrow;
                 const int col = kb0 + 32 * pnl + 4 * (xch ^ ((row >> 1) & 7));
-                lds_copy16(rk, Kf + j * 256, 4 * ((i0 + row) * n + col));
+                lds_copy16_untracked(rk, Kf + j * 256, 4 * ((i0 + row) * n + col));
             }
         }
+        // X: 4 rows of 64 r per wave-wide copy; lane L fills position L & 15 of
+        // row 4 j + (L >> 4) with the chunk that the swizzle puts there
+        const i4v rx = buffer_desc(P.X, R * n * 4);
+        const int krow = lane >> 4, pos = lane & 15;
+        for (int j = wave; j < NP * 8; j += kThreads / 64) {
+            const int pnl = j / 8, k = (j % 8) * 4 + krow;
+            const int c = pos ^ (4 * ((k >> 2) & 3));
+            lds_copy16_untracked(rx, Xs + j * 256, 4 * ((kb0 + 32 * pnl + k) * R + r0 + 4 * c));
+        }
     }
-    __builtin_amdgcn_s_waitcnt(0);
-    if (done) return;   // the step has stopped: nothing to compute (uniform)
-    __syncthreads();
     const bool logx = lmode != 0;
+    if (done || logx) __builtin_amdgcn_s_waitcnt(0);
+    if (done) return;   // the step has stopped: nothing to compute (uniform)
     if (logx) {
+        __syncthreads();
         // per-column (r) maximum of the staged logs over the band, then exponentiate
         if (tid < TR) {
             float m = -INFINITY;
@@ -1071,6 +1091,12 @@ contract_slow(Pass P, EpiArgs E) {
     const int s8 = (lane >> 1) & 7;
     const int g = lane >> 4;
     for (int pnl = 0; pnl < NP; ++pnl) {
+        if (!logx) {   // this panel's copies of every wave have landed
+            wait_vm(2 * (NP - 1 - pnl));
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            __builtin_amdgcn_s_barrier();
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        }
         const float* xp = Xs + pnl * 32 * TR;
         if (SPLIT) {
             const int s4 = (lane >> 2) & 3;
@@ -1141,6 +1167,9 @@ contract_slow(Pass P, EpiArgs E) {
             *reinterpret_cast<f4*>(&tile[il * TS + rl]) = acc[a][b];
         }
     __syncthreads();
+    // the prefetched inputs landed long ago; waiting for them here, before
+    // any store, keeps the compiler from placing that wait after a store
+    wait_vm_n<0>();
     EpiAcc ea;
 #pragma unroll
     for (int u = 0; u < UE; ++u) {
@@ -1214,6 +1243,8 @@ int64_t contract_slow_blocks(const Pass& pass) { return (pass.R / 64) * (int64_t
 
 hipError_t launch_contract_slow(const Pass& pass, int32_t precision, const EpiArgs& epi, int* nblocks,
                                 hipStream_t stream) {
+    // whole tiles only: every output group of four is complete
+    if (pass.R % 64 != 0 || pass.n % 32 != 0) return hipErrorInvalidValue;
     const int64_t nb = contract_slow_blocks(pass);
     if (nblocks) *nblocks = (int)nb;
     if (nb <= 0) return hipSuccess;

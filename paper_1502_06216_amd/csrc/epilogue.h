@@ -139,6 +139,13 @@ __device__ __forceinline__ f4 ld4(const float* __restrict__ p, int idx, int cnt,
     return r;
 }
 
+// Four consecutive values at any float index: the hardware needs only dword
+// alignment for a 16-byte load, so this is one load with no branch.
+typedef float f4_dw __attribute__((ext_vector_type(4), aligned(4)));
+__device__ __forceinline__ f4 ld4_full(const float* __restrict__ p, int idx) {
+    return *reinterpret_cast<const f4_dw*>(p + idx);
+}
+
 // Epilogue results are written with the non-temporal (streaming) hint: each
 // is read once, by the next kernel or pass, usually from another XCD.
 __device__ __forceinline__ void st4(float* __restrict__ p, int idx, int cnt, bool vec, f4 v) {
@@ -193,14 +200,20 @@ __device__ __forceinline__ f4 ld4_coh(const float* p, int idx, int cnt, float fi
 
 // COH: accumulators of the adjoint epilogues are read with device-scope loads
 // (the resident reverse sweep writes them with device-scope stores).
-template <int EK, bool COH = false>
+template <int EK, bool COH = false, bool FULL = false>
 __device__ __forceinline__ EpiIn epi_prefetch(const EpiArgs& E, int idx, int cnt) {
     EpiIn in;
     in.u = f4{0.f, 0.f, 0.f, 0.f};
     in.v = f4{0.f, 0.f, 0.f, 0.f};
     in.w = f4{0.f, 0.f, 0.f, 0.f};
-    if (cnt <= 0) return in;
+    if (!FULL && cnt <= 0) return in;
     const bool vec = E.vec_ok && ((idx & 3) == 0);
+    // FULL: every group of four is whole (cnt == 4): branch-free loads, so no
+    // register copy at a join waits for the load to land
+    auto ld4 = [&](const float* p, int i, int c, bool v, float fill) {
+        if constexpr (FULL) return ld4_full(p, i);
+        else return jko::ld4(p, i, c, v, fill);
+    };
     if (EK == EK_BUPDATE || EK == EK_MONITOR) {
         in.u = ld4(E.q, idx, cnt, vec, 0.f);
         if (EK == EK_MONITOR || E.check) in.v = ld4(E.b, idx, cnt, vec, 0.f);
