@@ -42,6 +42,11 @@ Energies (``Energy``):
 * ``zero``        f = 0, prox = identity;
 * ``congestion``  f = iota_[0,kappa](p) + <w, p>, prox min(s e^{-sigma w}, kappa)
                   (Proposition 4.1); kappa may be a field and may be +inf;
+* ``binary_congestion``  f = iota_{{0,kappa}^N}(p) + <w, p>, the non-convex
+                  functional of Section 4.5 (eq. dfn-congestion-noncvx).  Its
+                  KL prox is taken as its definition: per cell the argmin of
+                  KL(p|s) + sigma w p over the two candidates p in {0, kappa}
+                  (kappa finite), the tie going to kappa;
 * ``entropy``     f = sum c_i p_i (log p_i - 1), prox s^{1/(1 + sigma c)}
                   (Proposition 4.2, m = 1, weight c);
 * ``porous``      f = sum c_i (D p_i)^m / ((m-1) D) with density scale D
@@ -144,7 +149,7 @@ def log_gibbs_apply(L: np.ndarray, gamma: float) -> np.ndarray:
 
 @dataclass
 class Energy:
-    kind: str = "zero"                     # zero | congestion | entropy | porous
+    kind: str = "zero"                     # zero | congestion | binary_congestion | entropy | porous
     w: Optional[np.ndarray] = None         # congestion potential; None = 0
     kappa: Optional[np.ndarray] = None     # capacity; None = kappa_scalar
     kappa_scalar: float = math.inf
@@ -174,6 +179,33 @@ class Energy:
 def prox_congestion(s, sigma, w, kappa):
     """Proposition 4.1: Prox^KL_{sigma f}(s) = min(s e^{-sigma w}, kappa)."""
     return np.minimum(s * np.exp(-sigma * w), kappa)
+
+
+def kl_cell(p, s):
+    """KL(p|s) = p log(p/s) - p + s per cell, with 0 log 0 = 0 and +inf for
+    p > 0 = s (Section 3.1, eq. defn-KL-prbm, one term)."""
+    p = np.asarray(p, np.float64)
+    s = np.asarray(s, np.float64)
+    out = np.array(s, dtype=np.float64, copy=True)      # p = 0: the term is s
+    pos = p > 0
+    with np.errstate(divide="ignore"):
+        out[pos] = np.where(s[pos] > 0, p[pos] * np.log(p[pos] / np.where(s[pos] > 0, s[pos], 1.0)) - p[pos] + s[pos],
+                            np.inf)
+    return out
+
+
+def prox_binary_congestion(s, sigma, w, kappa):
+    """Section 4.5, eq. dfn-congestion-noncvx: KL prox of
+    sigma (iota_{{0,kappa}} + <w, .>), written as its definition: per cell
+    the candidate p in {0, kappa} of least KL(p|s) + sigma w p; at a tie kappa
+    is taken (the prox is two-valued there)."""
+    s = np.asarray(s, np.float64)
+    shape = s.shape
+    w = np.broadcast_to(np.asarray(w, np.float64), shape)
+    kappa = np.broadcast_to(np.asarray(kappa, np.float64), shape)
+    zero = kl_cell(np.zeros(shape), s)
+    full = kl_cell(kappa, s) + sigma * w * kappa
+    return np.where(full <= zero, kappa, 0.0)
 
 
 def prox_entropy(s, sigma, coef):
@@ -218,6 +250,8 @@ def prox(s: np.ndarray, sigma: float, en: Energy) -> np.ndarray:
         return s.copy()
     if en.kind == "congestion":
         return prox_congestion(s, sigma, en._w(shape), en._kappa(shape))
+    if en.kind == "binary_congestion":
+        return prox_binary_congestion(s, sigma, en._w(shape), en._kappa(shape))
     if en.kind == "entropy":
         return prox_entropy(s, sigma, en._coef(shape))
     if en.kind == "porous":
@@ -233,6 +267,15 @@ def log_prox(logs: np.ndarray, sigma: float, en: Energy) -> np.ndarray:
     if en.kind == "congestion":
         with np.errstate(divide="ignore"):
             return np.minimum(logs - sigma * en._w(shape), np.log(en._kappa(shape)))
+    if en.kind == "binary_congestion":
+        # the same two-candidate argmin with s = e^logs: kappa wins when
+        # kappa (log kappa - logs - 1 + sigma w) <= 0, so for kappa > 0 when
+        # log kappa - logs + sigma w <= 1 (logs = -inf: never)
+        kappa = en._kappa(shape)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            lk = np.log(kappa)
+            take = (kappa > 0) & np.isfinite(logs) & (lk - logs + sigma * en._w(shape) <= 1.0)
+        return np.where(take, lk, -np.inf)
     if en.kind == "entropy":
         return logs / (1.0 + sigma * en._coef(shape))
     if en.kind == "porous":

@@ -93,6 +93,62 @@ def test_prox_congestion_minimises(s, sigma):
         assert got == pytest.approx(ref, rel=2e-6, abs=1e-300)
 
 
+def test_prox_binary_congestion_follows_the_threshold_rule():
+    """Section 4.5: the KL prox of the binary constraint is 0 below kappa/e and
+    kappa above it.  With the potential, the argument is s e^{-sigma w} (the
+    linear term folded into the KL divergence, as for Proposition 4.1).  The
+    oracle's two-candidate argmin must reproduce that rule cell by cell."""
+    rng = np.random.default_rng(5)
+    n = 4000
+    s = rng.uniform(0, 2, n) * 10.0 ** rng.uniform(-6, 2, n)
+    w = rng.uniform(-1, 1, n)
+    kappa = rng.uniform(0, 3, n) * 10.0 ** rng.uniform(-6, 2, n)
+    for sigma in (0.3, 2.0, 9.0):
+        z = s * np.exp(-sigma * w)
+        got = O.prox_binary_congestion(s, sigma, w, kappa)
+        far = np.abs(z / (kappa / math.e) - 1.0) > 1e-9
+        rule = np.where(z > kappa / math.e, kappa, 0.0)
+        assert far.mean() > 0.99
+        np.testing.assert_array_equal(got[far], rule[far])
+        assert np.all((got == kappa) | (got == 0.0))
+
+
+def test_prox_binary_congestion_tie_and_degenerate_cells():
+    """At z = kappa/e exactly the prox is two-valued: kappa is taken.  Built
+    exactly in floating point with kappa = s and sigma w = 1; kappa = 0 and
+    s = 0 give 0; the log form takes the same decisions."""
+    s = np.array([0.3, 2.0, 1e-4])
+    assert np.array_equal(O.prox_binary_congestion(s, 1.0, 1.0, s), s)
+    en = O.Energy(kind="binary_congestion", w=np.ones(3), kappa=s)
+    np.testing.assert_allclose(np.exp(O.log_prox(np.log(s), 1.0, en)), s, rtol=1e-15)
+    assert O.prox_binary_congestion(np.array([0.5]), 1.0, 0.0, 0.0)[0] == 0.0
+    assert O.prox_binary_congestion(np.array([0.0]), 1.0, 0.0, 2.0)[0] == 0.0
+    rng = np.random.default_rng(6)
+    s = rng.uniform(1e-4, 3, 500)
+    en = O.Energy(kind="binary_congestion", w=rng.uniform(-1, 1, 500), kappa=rng.uniform(0, 2, 500))
+    lp, pp = np.exp(O.log_prox(np.log(s), 1.7, en)), O.prox(s, 1.7, en)
+    np.testing.assert_array_equal(lp > 0, pp > 0)
+    np.testing.assert_allclose(lp, pp, rtol=1e-15)
+
+
+def test_binary_congestion_step_is_binary_in_both_forms():
+    """A binary-congestion JKO step (the non-convex iteration of Section 4.5)
+    returns densities in {0, kappa}, and its plain and log forms agree."""
+    rng = np.random.default_rng(7)
+    shape = (12, 10)
+    N = int(np.prod(shape))
+    q = rng.uniform(0.2, 1.0, size=shape)
+    q /= q.sum()
+    en = O.Energy(kind="binary_congestion", w=rng.uniform(0, 1, size=shape), kappa_scalar=2.5 / N)
+    p1, st1 = O.jko_step(q, en, 0.01, 0.02, 40)
+    p2, st2 = O.jko_step_log(q, en, 0.01, 0.02, 40)
+    assert set(np.unique(p1)) <= {0.0, 2.5 / N}
+    assert (p1 > 0).any() and (p1 == 0).any()
+    # same decisions; the log form's exp(log kappa) may differ from kappa in the last bit
+    np.testing.assert_array_equal(p2 > 0, p1 > 0)
+    np.testing.assert_allclose(p2, p1, rtol=1e-15)
+
+
 @pytest.mark.parametrize("s", [1e-5, 0.02, 0.5, 1.0, 3.0])
 @pytest.mark.parametrize("sigma,c", [(0.5, 1.0), (2.5, 0.3), (10.0, 2.0)])
 def test_prox_entropy_minimises(s, sigma, c):
