@@ -56,7 +56,7 @@ typedef enum {
     JKO_ERR_WORKSPACE = -2,   /* workspace missing or smaller than required */
     JKO_ERR_HIP = -3,         /* a HIP runtime call failed (see jko_last_error) */
     JKO_ERR_NONFINITE = -4,   /* NaN/inf met by the FP64 monitor; outputs are still written */
-    JKO_ERR_INFEASIBLE = -5   /* congestion capacity sum(kappa) < sum(p_t) */
+    JKO_ERR_INFEASIBLE = -5   /* congestion (either kind) capacity sum(kappa) < sum(p_t) */
 } jko_status;
 
 /* Arithmetic of the Gibbs contractions.  Accumulation is float32 in both;
@@ -74,8 +74,24 @@ typedef enum { JKO_FP32 = 0, JKO_SPLIT_BF16 = 1 } jko_precision;
  *                    k = sigma c m D^{m-1} / (m - 1) (first-order condition as in
  *                    Section 4.4, Proposition 4.2), by Newton steps on log psi.
  *  JKO_F_ENTROPY     f = sum_i c_i p_i (log p_i - 1); prox s^{1/(1 + sigma c)}
- *                    (Section 4.4, Proposition 4.2 with m = 1). */
-typedef enum { JKO_F_ZERO = 0, JKO_F_CONGESTION = 1, JKO_F_POROUS = 2, JKO_F_ENTROPY = 3 } jko_energy_kind;
+ *                    (Section 4.4, Proposition 4.2 with m = 1).
+ *  JKO_F_CONGESTION_BINARY
+ *                    f = iota_{{0,kappa}^N}(p) + <w, p>, the non-convex functional
+ *                    of Section 4.5 (eq. dfn-congestion-noncvx); prox kappa where
+ *                    s e^{-sigma w} >= kappa / e (e = exp 1), else 0: the prox of the
+ *                    section with the linear term folded into the divergence.  At
+ *                    the tie the prox is two-valued and kappa is taken.  Same fields
+ *                    as JKO_F_CONGESTION, but kappa must be finite.  The iteration
+ *                    is the paper's non-convex Dykstra (no convergence guarantee);
+ *                    jko_backward refuses this energy (the prox is piecewise
+ *                    constant). */
+typedef enum {
+    JKO_F_ZERO = 0,
+    JKO_F_CONGESTION = 1,
+    JKO_F_POROUS = 2,
+    JKO_F_ENTROPY = 3,
+    JKO_F_CONGESTION_BINARY = 4
+} jko_energy_kind;
 
 typedef struct {
     int32_t ndim;        /* 1, 2 or 3 */

@@ -27,7 +27,7 @@ JKO_ERR_NONFINITE = -4
 JKO_ERR_INFEASIBLE = -5
 
 PRECISIONS = {"fp32": 0, "split_bf16": 1}
-ENERGY_KINDS = {"zero": 0, "congestion": 1, "porous": 2, "entropy": 3}
+ENERGY_KINDS = {"zero": 0, "congestion": 1, "porous": 2, "entropy": 3, "binary_congestion": 4}
 OP_GIBBS, OP_STEP, OP_FLOW, OP_BACKWARD = 0, 1, 2, 3
 FLAG_NO_RESIDENT = 1   # jko_flags: keep one launch per Gibbs application
 FLAG_AXIS_PASSES = 2   # jko_flags: 3D applications as three axis passes
@@ -145,7 +145,9 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
 @dataclass
 class EnergySpec:
     """Energy f of the JKO step (Section 4 of the paper); fields are device
-    float32 tensors of the grid's shape or None for the scalar defaults."""
+    float32 tensors of the grid's shape or None for the scalar defaults.
+    kind: "zero", "congestion", "binary_congestion" (the non-convex {0, kappa}
+    constraint of Section 4.5; finite kappa, no backward), "porous", "entropy"."""
     kind: str = "zero"
     w: Optional[torch.Tensor] = None
     kappa: Optional[torch.Tensor] = None

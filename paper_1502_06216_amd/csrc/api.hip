@@ -367,6 +367,12 @@ jko_status check_params(const jko_params* pr) {
     return JKO_OK;
 }
 
+// Both congestion kinds share the potential, capacity, preparation and
+// capacity check; they differ only in the prox.
+bool is_congestion(const jko_energy* en) {
+    return en->kind == JKO_F_CONGESTION || en->kind == JKO_F_CONGESTION_BINARY;
+}
+
 jko_status check_energy(const jko_energy* en) {
     if (!en) return fail(JKO_ERR_INVALID, "energy is NULL");
     switch (en->kind) {
@@ -375,6 +381,10 @@ jko_status check_energy(const jko_energy* en) {
         case JKO_F_CONGESTION:
             if (!en->kappa && (isnan(en->kappa_scalar) || en->kappa_scalar < 0.f))
                 return fail(JKO_ERR_INVALID, "kappa_scalar must be >= 0 (or +inf)");
+            return JKO_OK;
+        case JKO_F_CONGESTION_BINARY:
+            if (!en->kappa && !(en->kappa_scalar >= 0.f && isfinite(en->kappa_scalar)))
+                return fail(JKO_ERR_INVALID, "binary congestion: kappa_scalar must be finite and >= 0");
             return JKO_OK;
         case JKO_F_ENTROPY:
             if (!en->coef && !(en->coef_scalar >= 0.f)) return fail(JKO_ERR_INVALID, "coef_scalar must be >= 0");
@@ -396,7 +406,7 @@ ProxArgs prox_args(const Plan& P, const jko_energy* en, double sigma) {
     px.kind = en->kind;
     px.m = en->m;
     px.newton = en->newton_steps > 0 ? en->newton_steps : 8;
-    if (en->kind == JKO_F_CONGESTION) {
+    if (is_congestion(en)) {
         px.g = en->w ? P.F(F_G) : nullptr;
         px.kappa = en->kappa;
         px.kappa_s = en->kappa_scalar;
@@ -414,7 +424,7 @@ ProxArgs prox_args(const Plan& P, const jko_energy* en, double sigma) {
 }
 
 jko_status prepare_energy(const Plan& P, const jko_energy* en, double sigma) {
-    const bool need = (en->kind == JKO_F_CONGESTION && en->w) ||
+    const bool need = (is_congestion(en) && en->w) ||
                       ((en->kind == JKO_F_ENTROPY || en->kind == JKO_F_POROUS) && en->coef);
     if (!need) return JKO_OK;
     HIP_TRY(launch_prepare_energy(en, sigma, P.g.N, P.F(F_G), P.F(F_KF), P.st));
@@ -423,14 +433,14 @@ jko_status prepare_energy(const Plan& P, const jko_energy* en, double sigma) {
 
 // Capacity / finiteness check of a density (synchronous).
 jko_status input_check(const Plan& P, const jko_energy* en, const float* p) {
-    HIP_TRY(launch_input_check(p, en->kappa, en->kappa_scalar, P.g.N, en->kind == JKO_F_CONGESTION,
+    HIP_TRY(launch_input_check(p, en->kappa, en->kappa_scalar, P.g.N, is_congestion(en),
                                P.part.err, 3 * 256, P.hostout, P.st));
     double h[3];
     HIP_TRY(hipMemcpyAsync(g_rb.host, P.hostout, 3 * sizeof(double), hipMemcpyDeviceToHost, P.st));
     HIP_TRY(hipStreamSynchronize(P.st));
     memcpy(h, g_rb.host, sizeof h);
     if (h[2] > 0.0) return fail(JKO_ERR_NONFINITE, "input density or capacity has %g negative/non-finite cells", h[2]);
-    if (en->kind == JKO_F_CONGESTION && h[1] < h[0] * (1.0 - 1e-6))
+    if (is_congestion(en) && h[1] < h[0] * (1.0 - 1e-6))
         return fail(JKO_ERR_INFEASIBLE, "capacity sum %.9g < mass %.9g", h[1], h[0]);
     return JKO_OK;
 }
@@ -876,6 +886,8 @@ jko_status jko_backward(const jko_grid* grid, const jko_energy* energy, const jk
     jko_status s = common_checks(grid, &g);
     if (s) return s;
     if ((s = check_params(params)) || (s = check_energy(energy))) return s;
+    if (energy->kind == JKO_F_CONGESTION_BINARY)
+        return fail(JKO_ERR_INVALID, "binary congestion: the prox is piecewise constant, no gradient");
     if (n_steps < 1) return fail(JKO_ERR_INVALID, "n_steps must be >= 1");
     if (!iters_per_step || !checkpoints || !dL_dpT) return fail(JKO_ERR_INVALID, "missing input");
     if (dL_dw && energy->kind != JKO_F_CONGESTION)

@@ -75,8 +75,8 @@ __device__ __forceinline__ float log_prox_porous(float ls, float lk, float m, in
 // Epilogue codes: the epilogue kind and, for the proximal epilogue, the
 // energy, fixed at compile time so that each kernel carries only its own code.
 // EK_PROX + energy kind, EK_ADJ_B, EK_ADJ_PROX + energy kind
-enum : int { EK_STORE = 0, EK_BUPDATE = 1, EK_MONITOR = 2, EK_PROX = 3, EK_ADJ_B = 7, EK_ADJ_PROX = 8 };
-constexpr int ek_count = EK_ADJ_PROX + 4;
+// (the binary congestion prox, kind 4, has no adjoint epilogue)
+enum : int { EK_STORE = 0, EK_BUPDATE = 1, EK_MONITOR = 2, EK_PROX = 3, EK_ADJ_B = 8, EK_ADJ_PROX = 9 };
 
 __host__ __device__ constexpr EpiKind ek_kind(int ek) {
     return ek == EK_STORE ? EpiKind::STORE : ek == EK_BUPDATE ? EpiKind::BUPDATE
@@ -98,9 +98,14 @@ inline int ek_of(const EpiArgs& e) {
 // Prox of one cell; pu, pv are the cell's prefetched energy parameters
 // (congestion: exp(-sigma w), kappa; entropy: 1/(1 + sigma c); porous:
 // log((m-1) k)).
+// Binary congestion: kappa where z = s e^{-sigma w} reaches kappa/e, else 0
+// (the tie takes kappa).
+constexpr float kInvE = 0.36787944117144233f;   // 1 / e
+
 template <int KIND>
 __device__ __forceinline__ float prox_val(const ProxArgs& px, float s, float pu, float pv) {
     if (KIND == JKO_F_CONGESTION) return fminf(s * pu, pv);
+    if (KIND == JKO_F_CONGESTION_BINARY) return s * pu >= pv * kInvE ? pv : 0.f;
     if (KIND == JKO_F_ENTROPY) return s > 0.f ? expf(pu * logf(s)) : 0.f;
     if (KIND == JKO_F_POROUS) return s > 0.f ? expf(log_prox_porous(logf(s), pu, px.m, px.newton)) : 0.f;
     return s;
@@ -110,6 +115,10 @@ __device__ __forceinline__ float prox_val(const ProxArgs& px, float s, float pu,
 template <int KIND>
 __device__ __forceinline__ float log_prox_val(const ProxArgs& px, float ls, float pu, float pv) {
     if (KIND == JKO_F_CONGESTION) return fminf(ls + logf(pu), logf(pv));
+    if (KIND == JKO_F_CONGESTION_BINARY) {
+        const float lk = logf(pv);
+        return (pv > 0.f && ls + logf(pu) >= lk - 1.f) ? lk : -INFINITY;
+    }
     if (KIND == JKO_F_ENTROPY) return pu * ls;
     if (KIND == JKO_F_POROUS) return log_prox_porous(ls, pu, px.m, px.newton);
     return ls;
@@ -233,7 +242,7 @@ __device__ __forceinline__ EpiIn epi_prefetch(const EpiArgs& E, int idx, int cnt
         }
     } else if (EK >= EK_PROX) {
         const ProxArgs& px = E.prox;
-        if (EK - EK_PROX == JKO_F_CONGESTION) {
+        if (EK - EK_PROX == JKO_F_CONGESTION || EK - EK_PROX == JKO_F_CONGESTION_BINARY) {
             in.u = px.g ? ld4(px.g, idx, cnt, vec, 1.f) : f4{1.f, 1.f, 1.f, 1.f};
             in.v = px.kappa ? ld4(px.kappa, idx, cnt, vec, 0.f)
                             : f4{px.kappa_s, px.kappa_s, px.kappa_s, px.kappa_s};

@@ -849,6 +849,8 @@ const void* resident_kernel_of(int prox_kind) {
     switch (prox_kind) {
         case JKO_F_ZERO: return reinterpret_cast<const void*>(&resident2d<EK_PROX + JKO_F_ZERO, SPLIT>);
         case JKO_F_CONGESTION: return reinterpret_cast<const void*>(&resident2d<EK_PROX + JKO_F_CONGESTION, SPLIT>);
+        case JKO_F_CONGESTION_BINARY:
+            return reinterpret_cast<const void*>(&resident2d<EK_PROX + JKO_F_CONGESTION_BINARY, SPLIT>);
         case JKO_F_POROUS: return reinterpret_cast<const void*>(&resident2d<EK_PROX + JKO_F_POROUS, SPLIT>);
         default: return reinterpret_cast<const void*>(&resident2d<EK_PROX + JKO_F_ENTROPY, SPLIT>);
     }
@@ -868,6 +870,10 @@ void launch_g2(int ek, dim3 grid, dim3 block, const Band2D& b, const EpiArgs& ep
             hipLaunchKernelGGL((gibbs2d_kernel<EK_PROX + JKO_F_ZERO, SPLIT>), grid, block, 0, stream, b, epi); break;
         case EK_PROX + JKO_F_CONGESTION:
             hipLaunchKernelGGL((gibbs2d_kernel<EK_PROX + JKO_F_CONGESTION, SPLIT>), grid, block, 0, stream, b, epi);
+            break;
+        case EK_PROX + JKO_F_CONGESTION_BINARY:
+            hipLaunchKernelGGL((gibbs2d_kernel<EK_PROX + JKO_F_CONGESTION_BINARY, SPLIT>), grid, block, 0, stream, b,
+                               epi);
             break;
         case EK_PROX + JKO_F_POROUS:
             hipLaunchKernelGGL((gibbs2d_kernel<EK_PROX + JKO_F_POROUS, SPLIT>), grid, block, 0, stream, b, epi); break;

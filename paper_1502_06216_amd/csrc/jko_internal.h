@@ -45,7 +45,7 @@ struct Partials {
 // Energy parameters as the kernels see them (fields precomputed per call).
 struct ProxArgs {
     int32_t kind;          // jko_energy_kind
-    const float* g;        // congestion: exp(-sigma w) per cell, or NULL for 1
+    const float* g;        // congestion (both kinds): exp(-sigma w) per cell, or NULL for 1
     const float* kappa;    // congestion capacity field or NULL
     float kappa_s;         // scalar capacity when kappa == NULL
     const float* kf;       // porous: log((m-1) k) per cell; entropy: 1/(1 + sigma c) per cell

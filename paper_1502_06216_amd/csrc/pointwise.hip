@@ -233,7 +233,9 @@ hipError_t launch_copy(float* dst, const float* src, int64_t n, hipStream_t s) {
 
 hipError_t launch_prepare_energy(const jko_energy* en, double sigma, int64_t N, float* g, float* kf,
                                  hipStream_t s) {
-    hipLaunchKernelGGL(k_prepare, dim3(blocks_for(N, 1024)), dim3(256), 0, s, en->kind, en->w, en->coef,
+    // both congestion kinds prepare g = exp(-sigma w)
+    const int kind = en->kind == JKO_F_CONGESTION_BINARY ? JKO_F_CONGESTION : en->kind;
+    hipLaunchKernelGGL(k_prepare, dim3(blocks_for(N, 1024)), dim3(256), 0, s, kind, en->w, en->coef,
                        en->coef_scalar, en->m, en->density_scale, sigma, N, g, kf);
     return hipGetLastError();
 }

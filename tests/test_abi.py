@@ -104,6 +104,10 @@ def test_argument_errors_before_any_launch(lib):
     e4 = nat.EnergyC()
     e4.kind = 9
     assert _call_step(lib, g, e4, prm) == jk.JKO_ERR_INVALID
+    # binary congestion needs a finite capacity
+    e5 = jk.EnergySpec(kind="binary_congestion", kappa_scalar=math.inf).to_c((8, 8))
+    assert _call_step(lib, g, e5, prm) == jk.JKO_ERR_INVALID
+    assert b"finite" in lib.jko_last_error()
     # workspace too small / missing
     assert _call_step(lib, g, en, prm, ws=0) == jk.JKO_ERR_WORKSPACE
     assert _call_step(lib, g, en, prm, nbytes=100) == jk.JKO_ERR_WORKSPACE
@@ -124,6 +128,12 @@ def test_gibbs_and_flow_and_backward_argument_errors(lib):
     assert lib.jko_backward(ctypes.byref(g), ctypes.byref(en), ctypes.byref(prm), 2, iters, ctypes.c_void_p(1),
                             ctypes.c_void_p(2), None, ctypes.c_void_p(3), ctypes.c_void_p(16), 1 << 30,
                             None) == jk.JKO_ERR_INVALID
+    # no gradient through the binary (piecewise constant) prox
+    binc = jk.EnergySpec(kind="binary_congestion", kappa_scalar=1.0).to_c((8, 8))
+    assert lib.jko_backward(ctypes.byref(g), ctypes.byref(binc), ctypes.byref(prm), 2, iters, ctypes.c_void_p(1),
+                            ctypes.c_void_p(2), None, ctypes.c_void_p(3), ctypes.c_void_p(16), 1 << 30,
+                            None) == jk.JKO_ERR_INVALID
+    assert b"piecewise constant" in lib.jko_last_error()
     ent = jk.EnergySpec(kind="entropy").to_c((8, 8))
     iters = (ctypes.c_int32 * 1)(10)
     # dL/dw only for congestion
