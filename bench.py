@@ -376,12 +376,12 @@ def main():
                                          "roofline": roofline(wl3, prec, q3, TRAFFIC_PROFILES.get(("crowd128c", prec)))}
         # the non-convex binary constraint {0, kappa} on the same crowd
         # (300 iterations per step: the non-convex iteration has no tolerance to reach)
-        wlb = make_workload("crowd256")
-        wlb.kind = "binary_congestion"
+        wlb = make_workload("crowd256_binary")
         for prec in ("fp32", "split_bf16"):
-            itb, elb, stb, _ = run_flow(wlb, prec, 3, 1, tol=0.0, max_iters=300)
+            itb, elb, stb, _ = run_flow(wlb, prec, wlb.n_steps, 1)
             extra[f"crowd256_binary_{prec}"] = {"iters_per_s": round(itb / elb, 2),
-                                                "jko_steps_per_s": round(3 / elb, 3), "iters_per_step": 300}
+                                                "jko_steps_per_s": round(wlb.n_steps / elb, 3),
+                                                "iters_per_step": wlb.max_iters}
         wl5 = make_workload("porous512_scaled")
         for prec in ("fp32", "split_bf16"):
             it5, el5, st5, _ = run_flow(wl5, prec, 3, 1)

@@ -16,7 +16,7 @@ import torch
 
 import oracle as O
 import paper_1502_06216_amd as jk
-from workloads import small_case
+from workloads import make_workload, small_case
 
 from _util import banner, dev, energies, f32, host64
 
@@ -132,3 +132,40 @@ def test_log_domain_decides_like_the_plain_domain():
     differ = float(np.mean((outs[0] > 0) != (outs[1] > 0)))
     print(f"[gpu-test] binary log vs plain: {differ:.2e} of cells decided differently", flush=True)
     assert differ <= 0.005
+
+
+def test_collapsed_step_is_reported():
+    """Where sigma w > 1 over the whole support the prox empties every cell,
+    xi^T a vanishes under positive mass and the step is undefined (the
+    oracle's marginal is NaN there): the library reports JKO_ERR_NONFINITE."""
+    banner("binary collapse")
+    wl = _case((48, 40))
+    wl.w = wl.w * 0.0 + 2.0 * wl.gamma / wl.tau     # sigma w = 2 everywhere
+    g_en, o_en = energies(wl)
+    with np.errstate(all="ignore"):
+        _, st = O.jko_step(f32(wl.p0).astype(np.float64), o_en, wl.gamma, wl.tau, 3)
+    assert not np.isfinite(st["marginal_l1"])
+    with pytest.raises(jk.JKOError) as err:
+        jk.step(dev(wl.p0), g_en, wl.gamma, wl.tau, max_iters=3, tol=0.0)
+    assert err.value.status == jk.JKO_ERR_NONFINITE
+
+
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+def test_crowd256_binary_full_size(precision):
+    """The benchmarked configuration (256^2, 300 iterations) for one step:
+    binary values, the decisions of the FP64 oracle in all but a few cells,
+    and the reported marginal violation close to the oracle's."""
+    banner(f"crowd256_binary one step {precision}")
+    wl = make_workload("crowd256_binary")
+    g_en, o_en = energies(wl)
+    p, st = jk.step(dev(wl.p0), g_en, wl.gamma, wl.tau, max_iters=wl.max_iters, tol=0.0, precision=precision)
+    ref, rst = O.jko_step(f32(wl.p0).astype(np.float64), o_en, wl.gamma, wl.tau, wl.max_iters)
+    p = host64(p)
+    kappa = o_en._kappa(ref.shape)
+    assert _binary_values(p, kappa) and _binary_values(ref, kappa)
+    differ = float(np.mean((p > 0) != (ref > 0)))
+    print(f"[gpu-test] crowd256_binary {precision}: {differ:.2e} of cells decided differently, "
+          f"marginal {st['marginal_l1']:.4e} vs {rst['marginal_l1']:.4e}", flush=True)
+    assert differ <= 0.001
+    assert st["marginal_l1"] == pytest.approx(rst["marginal_l1"], rel=0.01)
+

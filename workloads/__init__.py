@@ -21,6 +21,11 @@ Workloads (synthetic stand-ins for the paper's figures, which print no data):
                    f(p) = sum c(x) p^m / (m - 1), m = 2 (Section 4.4), smoothed
                    uniform noise as initial density.
 * ``crowd128c`` -- 3D crowd motion on 128^3 with 10 box obstacles, 16 bumps.
+* ``crowd256_binary`` -- ``crowd256`` under the non-convex binary constraint
+                   {0, kappa} (Section 4.5): potential scaled to sigma w <= 1/2
+                   (above 1 the binary prox empties every cell), initial density
+                   binary (kappa where the projected p0 reaches kappa/2, else 0),
+                   3 steps of 300 iterations.
 
 The ``projected`` flag replaces p0 by min(c * p0, kappa) with the scalar c found
 by bisection so that the total mass is one: the paper requires the capacity to
@@ -221,6 +226,13 @@ def make_workload(name: str, seed: int = 0, projected: bool = True, **over) -> W
         wl = _crowd(name, (128, 128, 128), 5e-4, 2e-3, 16, 10,
                     ([0.1, 0.1, 0.1], [0.9, 0.9, 0.9]), (0.9, 0.5, 0.5), 1.2, seed,
                     projected, 20, 300, 0.0)
+    elif name == "crowd256_binary":
+        wl = _crowd(name, (256, 256), 2e-4, 2e-3, 8, 6, ([0.1, 0.1], [0.9, 0.9]),
+                    (0.9, 0.5), 1.2, seed, projected, 3, 300, 0.0)
+        wl.kind = "binary_congestion"
+        wl.w = wl.w * (0.5 / ((wl.tau / wl.gamma) * float(wl.w.max())))
+        kap = wl.kappa_field()
+        wl.p0 = np.where((kap > 0) & (wl.p0 >= 0.5 * kap), kap, 0.0)
     else:
         raise KeyError(name)
     for k, v in over.items():
@@ -230,7 +242,7 @@ def make_workload(name: str, seed: int = 0, projected: bool = True, **over) -> W
     return wl
 
 
-WORKLOADS = ("crowd32", "crowd256", "crowd256_fixed", "porous512", "porous512_scaled",
+WORKLOADS = ("crowd32", "crowd256", "crowd256_fixed", "crowd256_binary", "porous512", "porous512_scaled",
              "crowd128c")
 
 
