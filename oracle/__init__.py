@@ -7,6 +7,7 @@ product path has no CPU fallback.
 from .jko_oracle import (  # noqa: F401
     Energy, grid_points, all_points, gibbs_dense, gibbs_rows, gibbs_factor, gibbs_apply,
     log_gibbs_apply, prox, log_prox, prox_congestion, prox_binary_congestion, kl_cell, prox_entropy,
+    log_prox_gen_entropy,
     prox_porous,
     lambertw_of_log, dykstra_coupling, dykstra_scaling, jko_step, jko_step_log, jko_flow,
 )

@@ -47,6 +47,13 @@ Energies (``Energy``):
                   KL prox is taken as its definition: per cell the argmin of
                   KL(p|s) + sigma w p over the two candidates p in {0, kappa}
                   (kappa finite), the tie going to kappa;
+* ``gen_entropy`` f = sum_i b_i e_{m_i}(D p_i) / D, the generalised entropies
+                  of Section 4.4 (eq. defn-gen-entropies) with weights b_i and
+                  exponents m_i >= 1 per cell (D = 1: the paper's form).  Per
+                  Proposition 4.2 the prox of sigma b e_m is s^{1/(1+sigma b)}
+                  for m = 1 and otherwise the root psi of eq. prox-psi
+                  (sigma -> sigma b, applied to D s); the oracle takes that
+                  root exactly through Lambert W;
 * ``entropy``     f = sum c_i p_i (log p_i - 1), prox s^{1/(1 + sigma c)}
                   (Proposition 4.2, m = 1, weight c);
 * ``porous``      f = sum c_i (D p_i)^m / ((m-1) D) with density scale D
@@ -149,7 +156,7 @@ def log_gibbs_apply(L: np.ndarray, gamma: float) -> np.ndarray:
 
 @dataclass
 class Energy:
-    kind: str = "zero"                     # zero | congestion | binary_congestion | entropy | porous
+    kind: str = "zero"                     # zero | congestion | binary_congestion | entropy | porous | gen_entropy
     w: Optional[np.ndarray] = None         # congestion potential; None = 0
     kappa: Optional[np.ndarray] = None     # capacity; None = kappa_scalar
     kappa_scalar: float = math.inf
@@ -157,6 +164,7 @@ class Energy:
     coef_scalar: float = 1.0
     m: float = 2.0
     density_scale: float = 1.0
+    m_field: Optional[np.ndarray] = None   # gen_entropy exponents per cell; None = m
 
     def _w(self, shape):
         return np.zeros(shape) if self.w is None else np.asarray(self.w, np.float64)
@@ -170,6 +178,11 @@ class Energy:
         if self.coef is None:
             return np.full(shape, self.coef_scalar, dtype=np.float64)
         return np.asarray(self.coef, np.float64)
+
+    def _m(self, shape):
+        if self.m_field is None:
+            return np.full(shape, self.m, dtype=np.float64)
+        return np.asarray(self.m_field, np.float64)
 
     def porous_k(self, sigma: float, shape) -> np.ndarray:
         m = self.m
@@ -225,6 +238,31 @@ def prox_porous(s, k, m):
     return out
 
 
+def log_prox_gen_entropy(logs, sigma, b, m, D):
+    """Proposition 4.2 per cell for sigma b e_m applied to the density D p:
+    log psi, psi = D p, is Y = L / (1 + sigma b) for m = 1 (eq. prox-entropy)
+    and otherwise the root of eq. prox-psi with sigma -> sigma b:
+        Y + sigma b m (e^{(m-1) Y} - 1) / (m - 1) = L,   L = log(D s).
+    With c = sigma b m and u = (m-1) Y this is u + c e^u = (m-1) L + c, so
+    c e^u = W(c e^{(m-1) L + c}) (Lambert W, principal branch) and
+    Y = log(W / c) / (m - 1).  Returns log p = Y - log D (-inf where s = 0)."""
+    logs = np.asarray(logs, np.float64)
+    shape = logs.shape
+    b = np.broadcast_to(np.asarray(b, np.float64), shape)
+    m = np.broadcast_to(np.asarray(m, np.float64), shape)
+    L = logs + math.log(D)
+    out = np.full(shape, -np.inf)
+    fin = np.isfinite(logs)
+    one = fin & ((m == 1.0) | (b == 0.0))
+    out[one] = L[one] / (1.0 + sigma * b[one])          # b = 0: the identity
+    gen = fin & ~one
+    c = sigma * b[gen] * m[gen]
+    eps = m[gen] - 1.0
+    W = lambertw_of_log(np.log(c) + eps * L[gen] + c)
+    out[gen] = np.log(W / c) / eps
+    return out - math.log(D)
+
+
 def lambertw_of_log(logz: np.ndarray) -> np.ndarray:
     """Principal Lambert W at z = exp(logz), also where exp(logz) overflows:
     there W solves W + log W = logz (Newton from W = logz)."""
@@ -256,6 +294,9 @@ def prox(s: np.ndarray, sigma: float, en: Energy) -> np.ndarray:
         return prox_entropy(s, sigma, en._coef(shape))
     if en.kind == "porous":
         return prox_porous(s, en.porous_k(sigma, shape), en.m)
+    if en.kind == "gen_entropy":
+        with np.errstate(divide="ignore"):
+            return np.exp(log_prox_gen_entropy(np.log(s), sigma, en._coef(shape), en._m(shape), en.density_scale))
     raise ValueError(en.kind)
 
 
@@ -287,6 +328,8 @@ def log_prox(logs: np.ndarray, sigma: float, en: Energy) -> np.ndarray:
             logz = np.log((m - 1.0) * k) + (m - 1.0) * logs
         W = lambertw_of_log(logz)
         return np.where(np.isfinite(logs), logs - W / (m - 1.0), -np.inf)
+    if en.kind == "gen_entropy":
+        return log_prox_gen_entropy(logs, sigma, en._coef(shape), en._m(shape), en.density_scale)
     raise ValueError(en.kind)
 
 

@@ -174,6 +174,46 @@ def test_prox_porous_minimises(m, s, sigma, c, D):
     assert got_log == pytest.approx(got, rel=1e-12)
 
 
+def _e_m(x, m):
+    """Section 4.4, eq. defn-gen-entropies: e_1 = x (log x - 1),
+    e_m = x (x^{m-1} - m) / (m - 1), the latter evaluated as
+    x ((x^{m-1} - 1) / (m - 1) - 1) with expm1, free of cancellation near m = 1."""
+    if x == 0.0:
+        return 0.0
+    if m == 1.0:
+        return x * (math.log(x) - 1.0)
+    return x * (math.expm1((m - 1.0) * math.log(x)) / (m - 1.0) - 1.0)
+
+
+@pytest.mark.parametrize("m", [1.0, 1.0 + 1e-6, 1.05, 1.4, 2.0, 3.0])
+@pytest.mark.parametrize("s,sigma,b,D", [(0.3, 2.0, 1.0, 1.0), (2.5, 0.7, 4.0, 1.0), (1e-4, 5.0, 0.5, 1e3),
+                                         (0.02, 10.0, 20.0, 50.0), (3.0, 1.0, 0.0, 1.0)])
+def test_prox_gen_entropy_minimises(m, s, sigma, b, D):
+    """Proposition 4.2 with weight b and density scale D against a direct
+    minimisation of KL(p|s) + sigma b e_m(D p) / D written from the
+    definition of e_m."""
+    got = float(np.exp(O.log_prox_gen_entropy(np.log(s), sigma, b, m, D)))
+    ref = _log_golden_min(lambda p: _kl(p, s) + sigma * b * _e_m(D * p, m) / D, s * 1e-12, s * 1e6)
+    assert got == pytest.approx(ref, rel=2e-6)
+
+
+def test_prox_gen_entropy_is_continuous_at_m_one_and_matches_porous_shift():
+    """As m -> 1 the prox tends to the entropy prox (the -m s term of e_m
+    makes the family continuous), and for m > 1 it equals the porous prox
+    (no linear term) applied to s e^{sigma b m / (m - 1)}: the linear term
+    folded into the divergence."""
+    s = np.array([1e-3, 0.2, 1.0, 7.0])
+    for sigma, b in ((1.0, 1.0), (3.0, 0.4)):
+        at1 = O.log_prox_gen_entropy(np.log(s), sigma, b, 1.0, 1.0)
+        near = O.log_prox_gen_entropy(np.log(s), sigma, b, 1.0 + 1e-7, 1.0)
+        np.testing.assert_allclose(near, at1, rtol=0, atol=1e-5)
+        for m in (1.3, 2.0, 2.7):
+            got = np.exp(O.log_prox_gen_entropy(np.log(s), sigma, b, m, 1.0))
+            k = sigma * b * m / (m - 1.0)
+            ref = O.prox_porous(s * np.exp(k), k, m)
+            np.testing.assert_allclose(got, ref, rtol=1e-10)
+
+
 def test_lambertw_of_log_large_argument():
     for logz in (10.0, 300.0, 690.0):
         w = O.lambertw_of_log(np.array([logz]))[0]
@@ -193,7 +233,7 @@ def _tiny_congestion(shape, seed=0, kappa_factor=1.6):
     return q, O.Energy(kind="congestion", w=w, kappa_scalar=kappa_factor / N)
 
 
-@pytest.mark.parametrize("kind", ["congestion", "entropy", "porous"])
+@pytest.mark.parametrize("kind", ["congestion", "entropy", "porous", "gen_entropy"])
 def test_three_forms_of_dykstra_agree(kind):
     """Explicit-coupling KL Dykstra (Proposition 3.2 proxes) == Proposition 3.3
     scaling form == the reduced iteration, half-step by half-step."""
@@ -204,6 +244,9 @@ def test_three_forms_of_dykstra_agree(kind):
         en = O.Energy(kind="entropy", coef=np.linspace(0.5, 1.5, 20).reshape(shape))
     elif kind == "porous":
         en = O.Energy(kind="porous", coef_scalar=1.3, m=2.0, density_scale=20.0)
+    elif kind == "gen_entropy":
+        en = O.Energy(kind="gen_entropy", coef=np.linspace(1.0, 5.0, 20).reshape(shape),
+                      m_field=np.linspace(1.0, 2.0, 20).reshape(shape), density_scale=20.0)
     for L in (2, 4, 10, 30):
         p1 = O.dykstra_coupling(q, en, gamma, tau, L)
         p2, a, b, u, v = O.dykstra_scaling(q, en, gamma, tau, L)
@@ -406,6 +449,12 @@ def test_log_domain_matches_plain_where_both_finite():
     p3, _ = O.jko_step(wl.p0, en_p, wl.gamma, wl.tau, 20)
     p4, _ = O.jko_step_log(wl.p0, en_p, wl.gamma, wl.tau, 20)
     np.testing.assert_allclose(p4, p3, rtol=1e-10)
+    x = np.linspace(0, 1, 32)
+    en_g = O.Energy(kind="gen_entropy", coef=1.0 + 19.0 * np.outer(np.sin(np.pi * x), np.sin(np.pi * x)),
+                    m_field=1.0 + np.outer(np.sin(np.pi * x), np.sin(np.pi * x)), density_scale=1024.0)
+    p5, _ = O.jko_step(wl.p0, en_g, wl.gamma, wl.tau, 20)
+    p6, _ = O.jko_step_log(wl.p0, en_g, wl.gamma, wl.tau, 20)
+    np.testing.assert_allclose(p6, p5, rtol=1e-10)
 
 
 # ---------------------------------------------------------------- gradients
