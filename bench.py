@@ -57,7 +57,7 @@ def _energy(wl):
     import paper_1502_06216_amd as jk
     return jk.EnergySpec(kind=wl.kind, w=_dev(wl.w), kappa=_dev(wl.kappa), kappa_scalar=wl.kappa_scalar,
                          coef=_dev(wl.coef), coef_scalar=wl.coef_scalar, m=wl.m,
-                         density_scale=wl.density_scale)
+                         density_scale=wl.density_scale, m_field=_dev(wl.m_field))
 
 
 def run_flow(wl, precision, steps, warmup, tol=None, max_iters=None, resident=True):
@@ -382,6 +382,13 @@ def main():
             extra[f"crowd256_binary_{prec}"] = {"iters_per_s": round(itb / elb, 2),
                                                 "jko_steps_per_s": round(wlb.n_steps / elb, 3),
                                                 "iters_per_step": wlb.max_iters}
+        # generalised entropies with exponents varying from 1 to 2 over the grid
+        wlg = make_workload("gen512")
+        for prec in ("fp32", "split_bf16"):
+            itg, elg, stg, _ = run_flow(wlg, prec, wlg.n_steps, 1)
+            extra[f"gen512_{prec}"] = {"iters_per_s": round(itg / elg, 2),
+                                       "jko_steps_per_s": round(wlg.n_steps / elg, 3),
+                                       "iters_per_step": wlg.max_iters}
         wl5 = make_workload("porous512_scaled")
         for prec in ("fp32", "split_bf16"):
             it5, el5, st5, _ = run_flow(wl5, prec, 3, 1)

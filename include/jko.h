@@ -84,13 +84,24 @@ typedef enum { JKO_FP32 = 0, JKO_SPLIT_BF16 = 1 } jko_precision;
  *                    as JKO_F_CONGESTION, but kappa must be finite.  The iteration
  *                    is the paper's non-convex Dykstra (no convergence guarantee);
  *                    jko_backward refuses this energy (the prox is piecewise
- *                    constant). */
+ *                    constant).
+ *  JKO_F_GEN_ENTROPY f = sum_i b_i e_{m_i}(D p_i) / D, the generalised entropies of
+ *                    Section 4.4 (eq. defn-gen-entropies): e_1(x) = x (log x - 1),
+ *                    e_m(x) = x (x^{m-1} - m) / (m - 1); weights b_i = coef (or
+ *                    coef_scalar) >= 0, exponents m_i = m_field (or m) >= 1 per
+ *                    cell, density scale D = density_scale (1 = the paper's form).
+ *                    Prox (Proposition 4.2): psi = D p solves
+ *                    log psi + sigma b m (psi^{m-1} - 1) / (m - 1) = log(D s)
+ *                    (the m = 1 limit is psi = (D s)^{1/(1 + sigma b)}), by
+ *                    newton_steps Newton steps on log psi.  jko_backward refuses
+ *                    this energy (its adjoint is not built). */
 typedef enum {
     JKO_F_ZERO = 0,
     JKO_F_CONGESTION = 1,
     JKO_F_POROUS = 2,
     JKO_F_ENTROPY = 3,
-    JKO_F_CONGESTION_BINARY = 4
+    JKO_F_CONGESTION_BINARY = 4,
+    JKO_F_GEN_ENTROPY = 5
 } jko_energy_kind;
 
 typedef struct {
@@ -103,11 +114,12 @@ typedef struct {
     const float* w;          /* congestion potential, N cells, device; NULL = 0 */
     const float* kappa;      /* congestion capacity, N cells, device; NULL = kappa_scalar */
     float kappa_scalar;      /* used when kappa == NULL; may be +inf */
-    const float* coef;       /* porous / entropy weight c, N cells, device; NULL = coef_scalar */
+    const float* coef;       /* porous / entropy / gen. entropy weight, N cells, device; NULL = coef_scalar */
     float coef_scalar;
-    float m;                 /* porous exponent, > 1 */
-    float density_scale;     /* porous D, > 0 (1 = per-cell mass) */
-    int32_t newton_steps;    /* porous Newton steps per cell, 1..32 (0 = default 8) */
+    float m;                 /* porous exponent, > 1; gen. entropy exponent when m_field == NULL, >= 1 */
+    float density_scale;     /* porous / gen. entropy D, > 0 (1 = per-cell mass) */
+    int32_t newton_steps;    /* porous / gen. entropy Newton steps per cell, 1..32 (0 = default 8) */
+    const float* m_field;    /* gen. entropy exponents m_i >= 1, N cells, device; NULL = m */
 } jko_energy;
 
 typedef struct {

@@ -27,7 +27,7 @@ JKO_ERR_NONFINITE = -4
 JKO_ERR_INFEASIBLE = -5
 
 PRECISIONS = {"fp32": 0, "split_bf16": 1}
-ENERGY_KINDS = {"zero": 0, "congestion": 1, "porous": 2, "entropy": 3, "binary_congestion": 4}
+ENERGY_KINDS = {"zero": 0, "congestion": 1, "porous": 2, "entropy": 3, "binary_congestion": 4, "gen_entropy": 5}
 OP_GIBBS, OP_STEP, OP_FLOW, OP_BACKWARD = 0, 1, 2, 3
 FLAG_NO_RESIDENT = 1   # jko_flags: keep one launch per Gibbs application
 FLAG_AXIS_PASSES = 2   # jko_flags: 3D applications as three axis passes
@@ -47,7 +47,8 @@ class EnergyC(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("w", ctypes.c_void_p), ("kappa", ctypes.c_void_p),
                 ("kappa_scalar", ctypes.c_float), ("coef", ctypes.c_void_p),
                 ("coef_scalar", ctypes.c_float), ("m", ctypes.c_float),
-                ("density_scale", ctypes.c_float), ("newton_steps", ctypes.c_int32)]
+                ("density_scale", ctypes.c_float), ("newton_steps", ctypes.c_int32),
+                ("m_field", ctypes.c_void_p)]
 
 
 class Params(ctypes.Structure):
@@ -147,7 +148,9 @@ class EnergySpec:
     """Energy f of the JKO step (Section 4 of the paper); fields are device
     float32 tensors of the grid's shape or None for the scalar defaults.
     kind: "zero", "congestion", "binary_congestion" (the non-convex {0, kappa}
-    constraint of Section 4.5; finite kappa, no backward), "porous", "entropy"."""
+    constraint of Section 4.5; finite kappa, no backward), "porous", "entropy",
+    "gen_entropy" (the generalised entropies of Section 4.4 with per-cell
+    weights coef and exponents m_field >= 1; no backward)."""
     kind: str = "zero"
     w: Optional[torch.Tensor] = None
     kappa: Optional[torch.Tensor] = None
@@ -157,6 +160,7 @@ class EnergySpec:
     m: float = 2.0
     density_scale: float = 1.0
     newton_steps: int = 8
+    m_field: Optional[torch.Tensor] = None
 
     def to_c(self, shape) -> EnergyC:
         e = EnergyC()
@@ -169,6 +173,7 @@ class EnergySpec:
         e.m = float(self.m)
         e.density_scale = float(self.density_scale)
         e.newton_steps = int(self.newton_steps)
+        e.m_field = _ptr(_field(self.m_field, shape, "m_field"))
         return e
 
 

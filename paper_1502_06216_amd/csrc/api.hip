@@ -389,6 +389,15 @@ jko_status check_energy(const jko_energy* en) {
         case JKO_F_ENTROPY:
             if (!en->coef && !(en->coef_scalar >= 0.f)) return fail(JKO_ERR_INVALID, "coef_scalar must be >= 0");
             return JKO_OK;
+        case JKO_F_GEN_ENTROPY:
+            if (!en->m_field && (!(en->m >= 1.f) || !isfinite(en->m)))
+                return fail(JKO_ERR_INVALID, "generalised entropy exponent m must be >= 1");
+            if (!(en->density_scale > 0.f) || !isfinite(en->density_scale))
+                return fail(JKO_ERR_INVALID, "density_scale must be > 0");
+            if (!en->coef && !(en->coef_scalar >= 0.f)) return fail(JKO_ERR_INVALID, "coef_scalar must be >= 0");
+            if (en->newton_steps < 0 || en->newton_steps > 32)
+                return fail(JKO_ERR_INVALID, "newton_steps must be in 0..32");
+            return JKO_OK;
         case JKO_F_POROUS:
             if (!(en->m > 1.f) || !isfinite(en->m)) return fail(JKO_ERR_INVALID, "porous exponent m must be > 1");
             if (!(en->density_scale > 0.f)) return fail(JKO_ERR_INVALID, "density_scale must be > 0");
@@ -413,6 +422,16 @@ ProxArgs prox_args(const Plan& P, const jko_energy* en, double sigma) {
     } else if (en->kind == JKO_F_ENTROPY) {
         if (en->coef) px.kf = P.F(F_KF);
         else px.kf_s = (float)(1.0 / (1.0 + sigma * (double)en->coef_scalar));
+    } else if (en->kind == JKO_F_GEN_ENTROPY) {
+        // c = sigma b m and eps = m - 1 per cell when either b or m is a field
+        if (en->coef || en->m_field) {
+            px.kf = P.F(F_KF);
+            px.g = P.F(F_G);
+        } else {
+            px.kf_s = (float)(sigma * (double)en->coef_scalar * (double)en->m);
+            px.eps_s = en->m - 1.f;
+        }
+        px.lD = (float)log((double)en->density_scale);
     } else if (en->kind == JKO_F_POROUS) {
         if (en->coef) px.kf = P.F(F_KF);
         else {
@@ -425,7 +444,8 @@ ProxArgs prox_args(const Plan& P, const jko_energy* en, double sigma) {
 
 jko_status prepare_energy(const Plan& P, const jko_energy* en, double sigma) {
     const bool need = (is_congestion(en) && en->w) ||
-                      ((en->kind == JKO_F_ENTROPY || en->kind == JKO_F_POROUS) && en->coef);
+                      ((en->kind == JKO_F_ENTROPY || en->kind == JKO_F_POROUS) && en->coef) ||
+                      (en->kind == JKO_F_GEN_ENTROPY && (en->coef || en->m_field));
     if (!need) return JKO_OK;
     HIP_TRY(launch_prepare_energy(en, sigma, P.g.N, P.F(F_G), P.F(F_KF), P.st));
     return JKO_OK;
@@ -888,6 +908,8 @@ jko_status jko_backward(const jko_grid* grid, const jko_energy* energy, const jk
     if ((s = check_params(params)) || (s = check_energy(energy))) return s;
     if (energy->kind == JKO_F_CONGESTION_BINARY)
         return fail(JKO_ERR_INVALID, "binary congestion: the prox is piecewise constant, no gradient");
+    if (energy->kind == JKO_F_GEN_ENTROPY)
+        return fail(JKO_ERR_INVALID, "generalised entropy: no adjoint is built for this energy");
     if (n_steps < 1) return fail(JKO_ERR_INVALID, "n_steps must be >= 1");
     if (!iters_per_step || !checkpoints || !dL_dpT) return fail(JKO_ERR_INVALID, "missing input");
     if (dL_dw && energy->kind != JKO_F_CONGESTION)

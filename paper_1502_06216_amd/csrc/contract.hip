@@ -706,6 +706,7 @@ hipError_t launch_ek(int ek, int cfg, int64_t nb, const Pass& p, const EpiArgs& 
         case EK_PROX + JKO_F_CONGESTION: return launch_cfg<SPLIT, EK_PROX + JKO_F_CONGESTION>(cfg, nb, p, e, st);
         case EK_PROX + JKO_F_CONGESTION_BINARY:
             return launch_cfg<SPLIT, EK_PROX + JKO_F_CONGESTION_BINARY>(cfg, nb, p, e, st);
+        case EK_PROX + JKO_F_GEN_ENTROPY: return launch_cfg<SPLIT, EK_PROX + JKO_F_GEN_ENTROPY>(cfg, nb, p, e, st);
         case EK_PROX + JKO_F_POROUS: return launch_cfg<SPLIT, EK_PROX + JKO_F_POROUS>(cfg, nb, p, e, st);
         case EK_PROX + JKO_F_ENTROPY: return launch_cfg<SPLIT, EK_PROX + JKO_F_ENTROPY>(cfg, nb, p, e, st);
         case EK_ADJ_B: return launch_cfg<SPLIT, EK_ADJ_B>(cfg, nb, p, e, st);
@@ -1199,6 +1200,7 @@ hipError_t launch_slow_ek(int ek, int64_t nb, const Pass& p, const EpiArgs& e, i
         case EK_PROX + JKO_F_ZERO: JKO_SLOW(EK_PROX + JKO_F_ZERO);
         case EK_PROX + JKO_F_CONGESTION: JKO_SLOW(EK_PROX + JKO_F_CONGESTION);
         case EK_PROX + JKO_F_CONGESTION_BINARY: JKO_SLOW(EK_PROX + JKO_F_CONGESTION_BINARY);
+        case EK_PROX + JKO_F_GEN_ENTROPY: JKO_SLOW(EK_PROX + JKO_F_GEN_ENTROPY);
         case EK_PROX + JKO_F_POROUS: JKO_SLOW(EK_PROX + JKO_F_POROUS);
         case EK_PROX + JKO_F_ENTROPY: JKO_SLOW(EK_PROX + JKO_F_ENTROPY);
         case EK_ADJ_B: JKO_SLOW(EK_ADJ_B);

@@ -851,6 +851,7 @@ const void* resident_kernel_of(int prox_kind) {
         case JKO_F_CONGESTION: return reinterpret_cast<const void*>(&resident2d<EK_PROX + JKO_F_CONGESTION, SPLIT>);
         case JKO_F_CONGESTION_BINARY:
             return reinterpret_cast<const void*>(&resident2d<EK_PROX + JKO_F_CONGESTION_BINARY, SPLIT>);
+        case JKO_F_GEN_ENTROPY: return reinterpret_cast<const void*>(&resident2d<EK_PROX + JKO_F_GEN_ENTROPY, SPLIT>);
         case JKO_F_POROUS: return reinterpret_cast<const void*>(&resident2d<EK_PROX + JKO_F_POROUS, SPLIT>);
         default: return reinterpret_cast<const void*>(&resident2d<EK_PROX + JKO_F_ENTROPY, SPLIT>);
     }
@@ -874,6 +875,9 @@ void launch_g2(int ek, dim3 grid, dim3 block, const Band2D& b, const EpiArgs& ep
         case EK_PROX + JKO_F_CONGESTION_BINARY:
             hipLaunchKernelGGL((gibbs2d_kernel<EK_PROX + JKO_F_CONGESTION_BINARY, SPLIT>), grid, block, 0, stream, b,
                                epi);
+            break;
+        case EK_PROX + JKO_F_GEN_ENTROPY:
+            hipLaunchKernelGGL((gibbs2d_kernel<EK_PROX + JKO_F_GEN_ENTROPY, SPLIT>), grid, block, 0, stream, b, epi);
             break;
         case EK_PROX + JKO_F_POROUS:
             hipLaunchKernelGGL((gibbs2d_kernel<EK_PROX + JKO_F_POROUS, SPLIT>), grid, block, 0, stream, b, epi); break;

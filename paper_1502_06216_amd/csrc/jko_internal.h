@@ -48,8 +48,11 @@ struct ProxArgs {
     const float* g;        // congestion (both kinds): exp(-sigma w) per cell, or NULL for 1
     const float* kappa;    // congestion capacity field or NULL
     float kappa_s;         // scalar capacity when kappa == NULL
-    const float* kf;       // porous: log((m-1) k) per cell; entropy: 1/(1 + sigma c) per cell
+    const float* kf;       // porous: log((m-1) k) per cell; entropy: 1/(1 + sigma c) per cell;
+                           // gen. entropy: sigma b m per cell (g then holds m - 1)
     float kf_s;            // scalar value when kf == NULL
+    float eps_s;           // gen. entropy: m - 1 when g == NULL
+    float lD;              // gen. entropy: log of the density scale
     float m;               // porous exponent
     int32_t newton;        // porous Newton steps
 };

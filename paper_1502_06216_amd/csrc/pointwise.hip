@@ -63,7 +63,7 @@ __global__ void k_copy(float* __restrict__ d, const float* __restrict__ s, int64
         d[i] = s[i];
 }
 
-__global__ void k_prepare(int kind, const float* w, const float* coef, float coef_s, float m,
+__global__ void k_prepare(int kind, const float* w, const float* coef, float coef_s, float m, const float* mf,
                           float D, double sigma, int64_t N, float* g, float* kf) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -72,6 +72,12 @@ __global__ void k_prepare(int kind, const float* w, const float* coef, float coe
         } else if (kind == JKO_F_ENTROPY) {
             const double c = coef ? (double)coef[i] : (double)coef_s;
             kf[i] = (float)(1.0 / (1.0 + sigma * c));
+        } else if (kind == JKO_F_GEN_ENTROPY) {
+            // c = sigma b m and eps = m - 1 (exponents below 1 are taken as 1)
+            const double b = coef ? (double)coef[i] : (double)coef_s;
+            const double mi = fmax(mf ? (double)mf[i] : (double)m, 1.0);
+            kf[i] = (float)(sigma * b * mi);
+            g[i] = (float)(mi - 1.0);
         } else if (kind == JKO_F_POROUS) {
             const double c = coef ? (double)coef[i] : (double)coef_s;
             const double mm = (double)m;
@@ -236,7 +242,7 @@ hipError_t launch_prepare_energy(const jko_energy* en, double sigma, int64_t N, 
     // both congestion kinds prepare g = exp(-sigma w)
     const int kind = en->kind == JKO_F_CONGESTION_BINARY ? JKO_F_CONGESTION : en->kind;
     hipLaunchKernelGGL(k_prepare, dim3(blocks_for(N, 1024)), dim3(256), 0, s, kind, en->w, en->coef,
-                       en->coef_scalar, en->m, en->density_scale, sigma, N, g, kf);
+                       en->coef_scalar, en->m, en->m_field, en->density_scale, sigma, N, g, kf);
     return hipGetLastError();
 }
 

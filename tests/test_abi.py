@@ -41,7 +41,7 @@ def test_every_declared_symbol_is_exported(lib):
 def test_struct_layouts_match_header():
     # sizes implied by include/jko.h on x86-64
     assert ctypes.sizeof(nat.Grid) == 16
-    assert ctypes.sizeof(nat.EnergyC) == 56
+    assert ctypes.sizeof(nat.EnergyC) == 64
     assert ctypes.sizeof(nat.Params) == 48
     assert ctypes.sizeof(nat.Stats) == 48
 
@@ -108,6 +108,10 @@ def test_argument_errors_before_any_launch(lib):
     e5 = jk.EnergySpec(kind="binary_congestion", kappa_scalar=math.inf).to_c((8, 8))
     assert _call_step(lib, g, e5, prm) == jk.JKO_ERR_INVALID
     assert b"finite" in lib.jko_last_error()
+    # generalised entropy: exponent >= 1, positive density scale
+    for kw in ({"m": 0.5}, {"m": math.nan}, {"m": 1.5, "density_scale": 0.0}, {"m": 1.5, "coef_scalar": -1.0}):
+        e6 = jk.EnergySpec(kind="gen_entropy", **kw).to_c((8, 8))
+        assert _call_step(lib, g, e6, prm) == jk.JKO_ERR_INVALID, kw
     # workspace too small / missing
     assert _call_step(lib, g, en, prm, ws=0) == jk.JKO_ERR_WORKSPACE
     assert _call_step(lib, g, en, prm, nbytes=100) == jk.JKO_ERR_WORKSPACE
@@ -134,6 +138,10 @@ def test_gibbs_and_flow_and_backward_argument_errors(lib):
                             ctypes.c_void_p(2), None, ctypes.c_void_p(3), ctypes.c_void_p(16), 1 << 30,
                             None) == jk.JKO_ERR_INVALID
     assert b"piecewise constant" in lib.jko_last_error()
+    gen = jk.EnergySpec(kind="gen_entropy", m=1.5).to_c((8, 8))
+    assert lib.jko_backward(ctypes.byref(g), ctypes.byref(gen), ctypes.byref(prm), 2, iters, ctypes.c_void_p(1),
+                            ctypes.c_void_p(2), None, ctypes.c_void_p(3), ctypes.c_void_p(16), 1 << 30,
+                            None) == jk.JKO_ERR_INVALID
     ent = jk.EnergySpec(kind="entropy").to_c((8, 8))
     iters = (ctypes.c_int32 * 1)(10)
     # dL/dw only for congestion

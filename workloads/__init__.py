@@ -21,6 +21,12 @@ Workloads (synthetic stand-ins for the paper's figures, which print no data):
                    f(p) = sum c(x) p^m / (m - 1), m = 2 (Section 4.4), smoothed
                    uniform noise as initial density.
 * ``crowd128c`` -- 3D crowd motion on 128^3 with 10 box obstacles, 16 bumps.
+* ``gen512``    -- 2D nonlinear diffusion on 512x512 with the generalised
+                   entropies of Section 4.4: weights b = 1 and exponents
+                   m(x) = 1 + sin(pi x1) sin(pi x2) (1 at the boundary, 2 in the
+                   centre, as in the paper's second nonlinear-diffusion
+                   example), density units, the porous512 initial density,
+                   3 steps of 300 iterations.
 * ``crowd256_binary`` -- ``crowd256`` under the non-convex binary constraint
                    {0, kappa} (Section 4.5): potential scaled to sigma w <= 1/2
                    (above 1 the binary prox empties every cell), initial density
@@ -110,7 +116,7 @@ class Workload:
     shape: tuple
     gamma: float
     tau: float
-    kind: str                    # "congestion" | "porous" | "entropy" | "zero"
+    kind: str                    # "congestion" | "binary_congestion" | "porous" | "entropy" | "gen_entropy" | "zero"
     p0: np.ndarray
     w: Optional[np.ndarray] = None         # congestion potential (None = 0)
     kappa: Optional[np.ndarray] = None     # capacity field (None = kappa_scalar)
@@ -119,6 +125,7 @@ class Workload:
     coef_scalar: float = 1.0
     m: float = 2.0
     density_scale: float = 1.0
+    m_field: Optional[np.ndarray] = None   # gen_entropy exponents per cell (None = m)
     n_steps: int = 1
     max_iters: int = 300
     tol: float = 0.0                       # 0 = fixed iteration count
@@ -226,6 +233,13 @@ def make_workload(name: str, seed: int = 0, projected: bool = True, **over) -> W
         wl = _crowd(name, (128, 128, 128), 5e-4, 2e-3, 16, 10,
                     ([0.1, 0.1, 0.1], [0.9, 0.9, 0.9]), (0.9, 0.5, 0.5), 1.2, seed,
                     projected, 20, 300, 0.0)
+    elif name == "gen512":
+        wl = _porous(name, (512, 512), 1e-4, 1e-3, 2.0, seed, True, 3, 300, 0.0)
+        X = _mesh(wl.shape)
+        wl.kind = "gen_entropy"
+        wl.coef = None
+        wl.coef_scalar = 1.0
+        wl.m_field = 1.0 + np.sin(np.pi * X[0]) * np.sin(np.pi * X[1])
     elif name == "crowd256_binary":
         wl = _crowd(name, (256, 256), 2e-4, 2e-3, 8, 6, ([0.1, 0.1], [0.9, 0.9]),
                     (0.9, 0.5), 1.2, seed, projected, 3, 300, 0.0)
@@ -242,7 +256,7 @@ def make_workload(name: str, seed: int = 0, projected: bool = True, **over) -> W
     return wl
 
 
-WORKLOADS = ("crowd32", "crowd256", "crowd256_fixed", "crowd256_binary", "porous512", "porous512_scaled",
+WORKLOADS = ("crowd32", "crowd256", "crowd256_fixed", "crowd256_binary", "porous512", "porous512_scaled", "gen512",
              "crowd128c")
 
 
