@@ -93,8 +93,9 @@ typedef enum { JKO_FP32 = 0, JKO_SPLIT_BF16 = 1 } jko_precision;
  *                    Prox (Proposition 4.2): psi = D p solves
  *                    log psi + sigma b m (psi^{m-1} - 1) / (m - 1) = log(D s)
  *                    (the m = 1 limit is psi = (D s)^{1/(1 + sigma b)}), by
- *                    newton_steps Newton steps on log psi.  jko_backward refuses
- *                    this energy (its adjoint is not built). */
+ *                    newton_steps Newton steps on log psi; jko_backward
+ *                    differentiates it through the implicit derivative
+ *                    d log psi / d log s = 1 / (1 + sigma b m psi^{m-1}). */
 typedef enum {
     JKO_F_ZERO = 0,
     JKO_F_CONGESTION = 1,

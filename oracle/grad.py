@@ -8,12 +8,18 @@ iteration counts, and differentiated by torch autograd.  The JKO flow
 (Listing 1, step 2).
 
 Energies: ``zero``, ``congestion`` (Proposition 4.1; the clamp takes the
-capped branch on ties) and ``entropy`` (Proposition 4.2, m = 1).
+capped branch on ties), ``entropy`` (Proposition 4.2, m = 1) and
+``gen_entropy`` (Proposition 4.2 with per-cell weights and exponents): its
+prox is the oracle's exact Lambert-W root, differentiated through the
+implicit function theorem on eq. prox-psi,
+d log psi / d log s = 1 / (1 + sigma b m psi^{m-1}) (psi = D p).
 """
 from __future__ import annotations
 
 import numpy as np
 import torch
+
+from .jko_oracle import log_prox_gen_entropy
 
 
 def _centres(n):
@@ -32,7 +38,29 @@ def _apply(x, factors):
     return y
 
 
-def flow_torch(p0, w, kappa, gamma, tau, iters_per_step, kind="congestion", coef=None):
+class _GenEntropyProx(torch.autograd.Function):
+    """p = Prox^KL_{sigma f}(s) for the generalised entropies (values from the
+    exact root; derivative from the implicit function theorem)."""
+
+    @staticmethod
+    def forward(ctx, s, sigma, b, m, D):
+        with np.errstate(divide="ignore"):
+            lp = log_prox_gen_entropy(np.log(s.detach().numpy()), sigma, b.numpy(), m.numpy(), D)
+        p = torch.from_numpy(np.exp(lp))
+        ctx.save_for_backward(s, p, b, m)
+        ctx.sigma, ctx.D = sigma, D
+        return p
+
+    @staticmethod
+    def backward(ctx, gp):
+        s, p, b, m = ctx.saved_tensors
+        dlog = 1.0 / (1.0 + ctx.sigma * b * m * (ctx.D * p) ** (m - 1.0))
+        ds = torch.where(s > 0, gp * dlog * p / torch.where(s > 0, s, torch.ones_like(s)), torch.zeros_like(s))
+        return ds, None, None, None, None
+
+
+def flow_torch(p0, w, kappa, gamma, tau, iters_per_step, kind="congestion", coef=None, m=None,
+               density_scale=1.0):
     """Differentiable flow output p_T (torch tensors in, torch tensor out)."""
     shape = tuple(p0.shape)
     factors = [_factor(n, gamma) for n in shape]
@@ -50,6 +78,8 @@ def flow_torch(p0, w, kappa, gamma, tau, iters_per_step, kind="congestion", coef
                 p = torch.where(sg < kappa, sg, kappa)
             elif kind == "entropy":
                 p = s ** (1.0 / (1.0 + sigma * coef))
+            elif kind == "gen_entropy":
+                p = _GenEntropyProx.apply(s, sigma, coef, m, density_scale)
             elif kind == "zero":
                 p = s
             else:
@@ -60,14 +90,16 @@ def flow_torch(p0, w, kappa, gamma, tau, iters_per_step, kind="congestion", coef
 
 
 def loss_and_grads(p0, w, kappa, gamma, tau, iters_per_step, target, kind="congestion",
-                   coef=None):
+                   coef=None, m=None, density_scale=1.0):
     """loss = ||p_T - target||^2 and its gradients with respect to w and p0,
     all as float64 numpy arrays."""
     tp0 = torch.tensor(np.asarray(p0, np.float64), requires_grad=True)
     tw = torch.tensor(np.asarray(w, np.float64), requires_grad=True)
     tk = torch.tensor(np.broadcast_to(np.asarray(kappa, np.float64), p0.shape).copy())
-    tc = None if coef is None else torch.tensor(np.asarray(coef, np.float64))
-    pT = flow_torch(tp0, tw, tk, gamma, tau, iters_per_step, kind, tc)
+    tc = None if coef is None else torch.tensor(np.broadcast_to(np.asarray(coef, np.float64), p0.shape).copy())
+    tm = None if m is None else torch.tensor(np.broadcast_to(np.asarray(m, np.float64), p0.shape).copy())
+    pT = flow_torch(tp0, tw, tk, gamma, tau, iters_per_step, kind, tc, tm, density_scale)
     loss = ((pT - torch.tensor(np.asarray(target, np.float64))) ** 2).sum()
     loss.backward()
-    return float(loss.detach()), tw.grad.numpy().copy(), tp0.grad.numpy().copy(), pT.detach().numpy()
+    gw = None if tw.grad is None else tw.grad.numpy().copy()      # None: f does not involve w
+    return float(loss.detach()), gw, tp0.grad.numpy().copy(), pT.detach().numpy()

@@ -8,6 +8,27 @@
 
 namespace jko {
 
+// Generalised entropy (Proposition 4.2 with weight b, exponent m = 1 + eps and
+// density scale D): Y = log(D psi) is the root of
+//   F(Y) = Y + c (e^{eps Y} - 1) / eps - L = 0,   c = sigma b m,  L = log(D s),
+// continuous down to eps = 0 (where Y = L / (1 + c)).  F is increasing and
+// convex, and both L / (1 + c) and, for L > 0, log(1 + eps L / c) / eps lie at
+// or right of the root (e^x >= 1 + x), so Newton from their minimum descends
+// monotonically onto it.  (e^x - 1) / x is taken as 1 + x/2 for |x| < 1e-4.
+__device__ __forceinline__ float log_prox_gen(float L, float c, float eps, int steps) {
+    float y = L / (1.f + c);
+    if (eps > 0.f && c > 0.f) {
+        if (L > 0.f) y = fminf(y, log1pf(eps * L / c) / eps);
+        for (int it = 0; it < steps; ++it) {
+            const float x = eps * y;
+            const float phi = fabsf(x) < 1e-4f ? 1.f + 0.5f * x : expm1f(x) / x;
+            const float f = y + c * y * phi - L;
+            y -= f / (1.f + c * expf(x));
+        }
+    }
+    return y;
+}
+
 // Reverse of p = prox(s), a = p / s at one cell:
 //   pbar = pbar_ext + abar / s
 //   sbar = -abar a / s + pbar dp/ds          (abar p / s^2 written with a = p / s)
@@ -16,7 +37,8 @@ namespace jko {
 // is structurally zero (a = 0, dp/ds = 0) are skipped, so cells with s, p at
 // the float32 underflow limit contribute 0 rather than 0 * inf.
 // fu, fv: the cell's energy fields (congestion: g, kappa; entropy: 1/(1 + sigma c);
-// porous: log((m-1) k)).  Returns sbar; *dw receives the wbar increment.
+// porous: log((m-1) k); generalised entropy: c = sigma b m, eps = m - 1).
+// Returns sbar; *dw receives the wbar increment.
 template <int KIND>
 __device__ __forceinline__ float adj_prox_cell(const ProxArgs& px, float sigma, float sv, float pb, float ab,
                                                float fu, float fv, float* dw) {
@@ -52,6 +74,12 @@ __device__ __forceinline__ float adj_prox_cell(const ProxArgs& px, float sigma, 
             // implicit derivative of log psi + k psi^{m-1} = log s
             dpds = (p / sv) / (1.f + v);
         }
+    } else if (KIND == JKO_F_GEN_ENTROPY) {
+        // implicit derivative of Y + c (e^{eps Y} - 1) / eps = log(D s):
+        // dY / dlog s = 1 / (1 + c e^{eps Y})
+        const float y = log_prox_gen(logf(sv) + px.lD, fu, fv, px.newton);
+        p = expf(y - px.lD);
+        dpds = (p / sv) / (1.f + fu * expf(fv * y));
     } else {
         p = sv;
         dpds = 1.f;

@@ -908,8 +908,6 @@ jko_status jko_backward(const jko_grid* grid, const jko_energy* energy, const jk
     if ((s = check_params(params)) || (s = check_energy(energy))) return s;
     if (energy->kind == JKO_F_CONGESTION_BINARY)
         return fail(JKO_ERR_INVALID, "binary congestion: the prox is piecewise constant, no gradient");
-    if (energy->kind == JKO_F_GEN_ENTROPY)
-        return fail(JKO_ERR_INVALID, "generalised entropy: no adjoint is built for this energy");
     if (n_steps < 1) return fail(JKO_ERR_INVALID, "n_steps must be >= 1");
     if (!iters_per_step || !checkpoints || !dL_dpT) return fail(JKO_ERR_INVALID, "missing input");
     if (dL_dw && energy->kind != JKO_F_CONGESTION)

@@ -714,6 +714,8 @@ hipError_t launch_ek(int ek, int cfg, int64_t nb, const Pass& p, const EpiArgs& 
         case EK_ADJ_PROX + JKO_F_CONGESTION:
             return launch_cfg<SPLIT, EK_ADJ_PROX + JKO_F_CONGESTION>(cfg, nb, p, e, st);
         case EK_ADJ_PROX + JKO_F_POROUS: return launch_cfg<SPLIT, EK_ADJ_PROX + JKO_F_POROUS>(cfg, nb, p, e, st);
+        case EK_ADJ_PROX + JKO_F_GEN_ENTROPY:
+            return launch_cfg<SPLIT, EK_ADJ_PROX + JKO_F_GEN_ENTROPY>(cfg, nb, p, e, st);
         default: return launch_cfg<SPLIT, EK_ADJ_PROX + JKO_F_ENTROPY>(cfg, nb, p, e, st);
     }
 }
@@ -1207,6 +1209,7 @@ hipError_t launch_slow_ek(int ek, int64_t nb, const Pass& p, const EpiArgs& e, i
         case EK_ADJ_PROX + JKO_F_ZERO: JKO_SLOW(EK_ADJ_PROX + JKO_F_ZERO);
         case EK_ADJ_PROX + JKO_F_CONGESTION: JKO_SLOW(EK_ADJ_PROX + JKO_F_CONGESTION);
         case EK_ADJ_PROX + JKO_F_POROUS: JKO_SLOW(EK_ADJ_PROX + JKO_F_POROUS);
+        case EK_ADJ_PROX + JKO_F_GEN_ENTROPY: JKO_SLOW(EK_ADJ_PROX + JKO_F_GEN_ENTROPY);
         default: JKO_SLOW(EK_ADJ_PROX + JKO_F_ENTROPY);
     }
 #undef JKO_SLOW

@@ -72,32 +72,11 @@ __device__ __forceinline__ float log_prox_porous(float ls, float lk, float m, in
     return ls - v / (m - 1.f);
 }
 
-// Generalised entropy (Proposition 4.2 with weight b, exponent m = 1 + eps and
-// density scale D): Y = log(D psi) is the root of
-//   F(Y) = Y + c (e^{eps Y} - 1) / eps - L = 0,   c = sigma b m,  L = log(D s),
-// continuous down to eps = 0 (where Y = L / (1 + c)).  F is increasing and
-// convex, and both L / (1 + c) and, for L > 0, log(1 + eps L / c) / eps lie at
-// or right of the root (e^x >= 1 + x), so Newton from their minimum descends
-// monotonically onto it.  (e^x - 1) / x is taken as 1 + x/2 for |x| < 1e-4.
-__device__ __forceinline__ float log_prox_gen(float L, float c, float eps, int steps) {
-    float y = L / (1.f + c);
-    if (eps > 0.f && c > 0.f) {
-        if (L > 0.f) y = fminf(y, log1pf(eps * L / c) / eps);
-        for (int it = 0; it < steps; ++it) {
-            const float x = eps * y;
-            const float phi = fabsf(x) < 1e-4f ? 1.f + 0.5f * x : expm1f(x) / x;
-            const float f = y + c * y * phi - L;
-            y -= f / (1.f + c * expf(x));
-        }
-    }
-    return y;
-}
 
 // Epilogue codes: the epilogue kind and, for the proximal epilogue, the
 // energy, fixed at compile time so that each kernel carries only its own code.
 // EK_PROX + energy kind, EK_ADJ_B, EK_ADJ_PROX + energy kind
-// (the binary congestion and generalised entropy proxes, kinds 4 and 5, have
-// no adjoint epilogue)
+// (the binary congestion prox, kind 4, has no adjoint epilogue)
 enum : int { EK_STORE = 0, EK_BUPDATE = 1, EK_MONITOR = 2, EK_PROX = 3, EK_ADJ_B = 9, EK_ADJ_PROX = 10 };
 
 __host__ __device__ constexpr EpiKind ek_kind(int ek) {
@@ -265,6 +244,9 @@ __device__ __forceinline__ EpiIn epi_prefetch(const EpiArgs& E, int idx, int cnt
                             : f4{px.kappa_s, px.kappa_s, px.kappa_s, px.kappa_s};
         } else if (EK - EK_ADJ_PROX == JKO_F_ENTROPY || EK - EK_ADJ_PROX == JKO_F_POROUS) {
             in.v = px.kf ? ld4(px.kf, idx, cnt, vec, 0.f) : f4{px.kf_s, px.kf_s, px.kf_s, px.kf_s};
+        } else if (EK - EK_ADJ_PROX == JKO_F_GEN_ENTROPY) {
+            in.v = px.kf ? ld4(px.kf, idx, cnt, vec, 0.f) : f4{px.kf_s, px.kf_s, px.kf_s, px.kf_s};
+            in.w = px.g ? ld4(px.g, idx, cnt, vec, 0.f) : f4{px.eps_s, px.eps_s, px.eps_s, px.eps_s};
         }
     } else if (EK >= EK_PROX) {
         const ProxArgs& px = E.prox;

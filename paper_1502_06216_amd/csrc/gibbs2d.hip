@@ -840,6 +840,8 @@ const void* adjoint_kernel_of(int prox_kind) {
         case JKO_F_CONGESTION:
             return reinterpret_cast<const void*>(&resident_adj<EK_ADJ_PROX + JKO_F_CONGESTION, SPLIT>);
         case JKO_F_POROUS: return reinterpret_cast<const void*>(&resident_adj<EK_ADJ_PROX + JKO_F_POROUS, SPLIT>);
+        case JKO_F_GEN_ENTROPY:
+            return reinterpret_cast<const void*>(&resident_adj<EK_ADJ_PROX + JKO_F_GEN_ENTROPY, SPLIT>);
         default: return reinterpret_cast<const void*>(&resident_adj<EK_ADJ_PROX + JKO_F_ENTROPY, SPLIT>);
     }
 }
@@ -889,6 +891,10 @@ void launch_g2(int ek, dim3 grid, dim3 block, const Band2D& b, const EpiArgs& ep
             break;
         case EK_ADJ_PROX + JKO_F_CONGESTION:
             hipLaunchKernelGGL((gibbs2d_kernel<EK_ADJ_PROX + JKO_F_CONGESTION, SPLIT>), grid, block, 0, stream, b,
+                               epi);
+            break;
+        case EK_ADJ_PROX + JKO_F_GEN_ENTROPY:
+            hipLaunchKernelGGL((gibbs2d_kernel<EK_ADJ_PROX + JKO_F_GEN_ENTROPY, SPLIT>), grid, block, 0, stream, b,
                                epi);
             break;
         case EK_ADJ_PROX + JKO_F_POROUS:

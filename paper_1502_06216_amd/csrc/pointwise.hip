@@ -192,6 +192,9 @@ __global__ void k_adj_prox(const float* __restrict__ s, const float* __restrict_
             fv = px.kappa ? px.kappa[i] : px.kappa_s;
         } else if (KIND == JKO_F_ENTROPY || KIND == JKO_F_POROUS) {
             fu = px.kf ? px.kf[i] : px.kf_s;
+        } else if (KIND == JKO_F_GEN_ENTROPY) {
+            fu = px.kf ? px.kf[i] : px.kf_s;
+            fv = px.g ? px.g[i] : px.eps_s;
         }
         float dw;
         sbar[i] = adj_prox_cell<KIND>(px, sigma, s[i], pbar_ext ? pbar_ext[i] : 0.f, abar ? abar[i] : 0.f, fu,
@@ -293,6 +296,10 @@ hipError_t launch_adj_prox(const float* s, const float* pbar_ext, const float* a
             break;
         case JKO_F_POROUS:
             hipLaunchKernelGGL(k_adj_prox<JKO_F_POROUS>, grid, block, 0, st, s, pbar_ext, abar, sbar, wbar, px,
+                               (float)sigma, N);
+            break;
+        case JKO_F_GEN_ENTROPY:
+            hipLaunchKernelGGL(k_adj_prox<JKO_F_GEN_ENTROPY>, grid, block, 0, st, s, pbar_ext, abar, sbar, wbar, px,
                                (float)sigma, N);
             break;
         default:

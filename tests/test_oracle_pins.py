@@ -459,6 +459,41 @@ def test_log_domain_matches_plain_where_both_finite():
 
 # ---------------------------------------------------------------- gradients
 
+def test_reference_gradient_gen_entropy_matches_finite_differences():
+    """The generalised-entropy flow (per-cell weights and exponents from 1 to
+    2, density units): autograd through the implicit derivative of the prox
+    == central differences of the numpy oracle's forward map in p0."""
+    shape = (8, 8)
+    rng = np.random.default_rng(8)
+    gamma, tau = 2e-2, 5e-2
+    p0 = gaussian_bumps(shape, rng.uniform(0.3, 0.7, size=(2, 2)), 0.15, [0.5, 0.5])
+    b = rng.uniform(0.5, 3.0, size=shape)
+    m = 1.0 + rng.uniform(0.0, 1.0, size=shape)
+    m[0, :] = 1.0
+    D = 64.0
+    target = rng.uniform(size=shape)
+    target /= target.sum()
+    iters = [20, 20]
+    en = O.Energy(kind="gen_entropy", coef=b, m_field=m, density_scale=D)
+
+    def fwd(p0_):
+        q = p0_
+        for K in iters:
+            q, _ = O.jko_step(q, en, gamma, tau, K)
+        return float(((q - target) ** 2).sum())
+
+    loss, _, gp, _ = loss_and_grads(p0, np.zeros(shape), np.inf, gamma, tau, iters, target, kind="gen_entropy",
+                                    coef=b, m=m, density_scale=D)
+    assert loss == pytest.approx(fwd(p0), rel=1e-13)
+    for c in [(1, 1), (4, 5), (6, 2), (7, 7), (0, 5)]:
+        hp = 1e-5 * p0[c]
+        pp, pm = p0.copy(), p0.copy()
+        pp[c] += hp
+        pm[c] -= hp
+        fd = (fwd(pp) - fwd(pm)) / (2 * hp)
+        assert gp[c] == pytest.approx(fd, rel=1e-5, abs=1e-9 * abs(loss))
+
+
 def test_reference_gradient_matches_finite_differences():
     """torch float64 autograd through the unrolled flow == central finite
     differences of the numpy oracle's forward map."""
