@@ -200,12 +200,15 @@ jko_status jko_flow(const jko_grid* grid, const jko_energy* energy, const jko_pa
 /* Reverse-mode derivative of L(p_T) through the unrolled flow: given the
  * checkpoints p_0..p_{n_steps-1} written by jko_flow and the iteration count
  * of every step (host array, stats[t].iters of the forward), and dL/dp_T,
- * writes dL/dw (nullable; congestion only) and dL/dp0 (nullable).  Each
- * step's iterations are recomputed from its checkpoint, their intermediate
- * Gibbs products are kept in the workspace, then swept in reverse.  The
- * derivative is that of the map at the given iteration counts (tol_l1 is
- * ignored).  Energies: ZERO, CONGESTION, ENTROPY, POROUS (dL/dp0 only for
- * the last two). */
+ * writes dL/dw (nullable) and dL/dp0 (nullable).  dL/dw is the derivative
+ * with respect to the energy's per-cell field: the potential w for
+ * CONGESTION (w required), the weights coef for GEN_ENTROPY (coef required).
+ * Each step's iterations are recomputed from its checkpoint, their
+ * intermediate Gibbs products are kept in the workspace, then swept in
+ * reverse.  The derivative is that of the map at the given iteration counts
+ * (tol_l1 is ignored).  Energies: ZERO, CONGESTION, ENTROPY, POROUS,
+ * GEN_ENTROPY (dL/dp0 only for ENTROPY and POROUS); CONGESTION_BINARY is
+ * refused. */
 jko_status jko_backward(const jko_grid* grid, const jko_energy* energy, const jko_params* params,
                         int32_t n_steps, const int32_t* iters_per_step, const float* checkpoints,
                         const float* dL_dpT, float* dL_dw, float* dL_dp0,

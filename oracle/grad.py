@@ -40,7 +40,10 @@ def _apply(x, factors):
 
 class _GenEntropyProx(torch.autograd.Function):
     """p = Prox^KL_{sigma f}(s) for the generalised entropies (values from the
-    exact root; derivative from the implicit function theorem)."""
+    exact root; derivatives in s and in the weights b from the implicit
+    function theorem on Y + c (e^{eps Y} - 1)/eps = log(D s), c = sigma b m,
+    Y = log(D p): dY/dlog s = 1/(1 + c e^{eps Y}),
+    dY/db = -sigma m (e^{eps Y} - 1)/eps / (1 + c e^{eps Y}))."""
 
     @staticmethod
     def forward(ctx, s, sigma, b, m, D):
@@ -54,9 +57,14 @@ class _GenEntropyProx(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gp):
         s, p, b, m = ctx.saved_tensors
-        dlog = 1.0 / (1.0 + ctx.sigma * b * m * (ctx.D * p) ** (m - 1.0))
+        Y = torch.log(ctx.D * p)
+        eps = m - 1.0
+        ey = torch.exp(eps * Y)
+        dlog = 1.0 / (1.0 + ctx.sigma * b * m * ey)
         ds = torch.where(s > 0, gp * dlog * p / torch.where(s > 0, s, torch.ones_like(s)), torch.zeros_like(s))
-        return ds, None, None, None, None
+        phi = torch.where(eps > 0, torch.expm1(eps * Y) / torch.where(eps > 0, eps, torch.ones_like(eps)), Y)
+        db = torch.where(s > 0, -gp * p * ctx.sigma * m * phi * dlog, torch.zeros_like(s))
+        return ds, None, db, None, None
 
 
 def flow_torch(p0, w, kappa, gamma, tau, iters_per_step, kind="congestion", coef=None, m=None,
@@ -96,10 +104,13 @@ def loss_and_grads(p0, w, kappa, gamma, tau, iters_per_step, target, kind="conge
     tp0 = torch.tensor(np.asarray(p0, np.float64), requires_grad=True)
     tw = torch.tensor(np.asarray(w, np.float64), requires_grad=True)
     tk = torch.tensor(np.broadcast_to(np.asarray(kappa, np.float64), p0.shape).copy())
-    tc = None if coef is None else torch.tensor(np.broadcast_to(np.asarray(coef, np.float64), p0.shape).copy())
+    tc = None if coef is None else torch.tensor(np.broadcast_to(np.asarray(coef, np.float64), p0.shape).copy(),
+                                                requires_grad=(kind == "gen_entropy"))
     tm = None if m is None else torch.tensor(np.broadcast_to(np.asarray(m, np.float64), p0.shape).copy())
     pT = flow_torch(tp0, tw, tk, gamma, tau, iters_per_step, kind, tc, tm, density_scale)
     loss = ((pT - torch.tensor(np.asarray(target, np.float64))) ** 2).sum()
     loss.backward()
-    gw = None if tw.grad is None else tw.grad.numpy().copy()      # None: f does not involve w
+    # the gradient in the energy's per-cell field: w, or the weights b of the
+    # generalised entropies
+    gw = tc.grad.numpy().copy() if kind == "gen_entropy" else (None if tw.grad is None else tw.grad.numpy().copy())
     return float(loss.detach()), gw, tp0.grad.numpy().copy(), pT.detach().numpy()

@@ -32,7 +32,8 @@ __device__ __forceinline__ float log_prox_gen(float L, float c, float eps, int s
 // Reverse of p = prox(s), a = p / s at one cell:
 //   pbar = pbar_ext + abar / s
 //   sbar = -abar a / s + pbar dp/ds          (abar p / s^2 written with a = p / s)
-//   wbar += pbar dp/dw          (congestion: dp/dw = -sigma s g on the free branch)
+//   wbar += pbar dp/dw          (congestion: dp/dw = -sigma s g on the free branch;
+//                                generalised entropy: the weight b in place of w)
 // Ties s g = kappa take the capped branch (derivative 0).  Terms whose factor
 // is structurally zero (a = 0, dp/ds = 0) are skipped, so cells with s, p at
 // the float32 underflow limit contribute 0 rather than 0 * inf.
@@ -75,11 +76,16 @@ __device__ __forceinline__ float adj_prox_cell(const ProxArgs& px, float sigma, 
             dpds = (p / sv) / (1.f + v);
         }
     } else if (KIND == JKO_F_GEN_ENTROPY) {
-        // implicit derivative of Y + c (e^{eps Y} - 1) / eps = log(D s):
-        // dY / dlog s = 1 / (1 + c e^{eps Y})
+        // implicit derivatives of Y + c (e^{eps Y} - 1) / eps = log(D s),
+        // c = sigma b m: dY / dlog s = 1 / (1 + c e^{eps Y}) and
+        // dY / db = -sigma m (e^{eps Y} - 1) / eps / (1 + c e^{eps Y})
         const float y = log_prox_gen(logf(sv) + px.lD, fu, fv, px.newton);
+        const float x = fv * y;
+        const float inv = 1.f / (1.f + fu * expf(x));
+        const float phi = fabsf(x) < 1e-4f ? y * (1.f + 0.5f * x) : expm1f(x) / fv;
         p = expf(y - px.lD);
-        dpds = (p / sv) / (1.f + fu * expf(fv * y));
+        dpds = (p / sv) * inv;
+        dpdw = -p * sigma * (1.f + fv) * phi * inv;
     } else {
         p = sv;
         dpds = 1.f;

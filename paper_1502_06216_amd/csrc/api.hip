@@ -910,9 +910,12 @@ jko_status jko_backward(const jko_grid* grid, const jko_energy* energy, const jk
         return fail(JKO_ERR_INVALID, "binary congestion: the prox is piecewise constant, no gradient");
     if (n_steps < 1) return fail(JKO_ERR_INVALID, "n_steps must be >= 1");
     if (!iters_per_step || !checkpoints || !dL_dpT) return fail(JKO_ERR_INVALID, "missing input");
-    if (dL_dw && energy->kind != JKO_F_CONGESTION)
-        return fail(JKO_ERR_INVALID, "dL/dw exists only for the congestion energy");
-    if (dL_dw && !energy->w) return fail(JKO_ERR_INVALID, "dL/dw needs the potential w");
+    if (dL_dw && energy->kind != JKO_F_CONGESTION && energy->kind != JKO_F_GEN_ENTROPY)
+        return fail(JKO_ERR_INVALID, "dL/dw exists only for the congestion and generalised entropy energies");
+    if (dL_dw && energy->kind == JKO_F_CONGESTION && !energy->w)
+        return fail(JKO_ERR_INVALID, "dL/dw needs the potential w");
+    if (dL_dw && energy->kind == JKO_F_GEN_ENTROPY && !energy->coef)
+        return fail(JKO_ERR_INVALID, "dL/dcoef needs the weight field coef");
     int kmax = 0;
     for (int t = 0; t < n_steps; ++t) {
         if (iters_per_step[t] < 1) return fail(JKO_ERR_INVALID, "iters_per_step[%d] < 1", t);

@@ -328,7 +328,7 @@ __device__ __forceinline__ void epi_apply(const EpiArgs& E, int idx, int cnt, f4
         }
         if (COH) st4_coh(E.y, idx, cnt, vec, sb);
         else st4(E.y, idx, cnt, vec, sb);
-        if (KIND == JKO_F_CONGESTION && E.acc) {
+        if ((KIND == JKO_F_CONGESTION || KIND == JKO_F_GEN_ENTROPY) && E.acc) {
             f4 wb = COH ? ld4_coh(E.acc, idx, cnt, 0.f) : ld4(E.acc, idx, cnt, vec, 0.f);
 #pragma unroll
             for (int e = 0; e < NE; ++e)

@@ -138,6 +138,12 @@ def test_gibbs_and_flow_and_backward_argument_errors(lib):
                             ctypes.c_void_p(2), None, ctypes.c_void_p(3), ctypes.c_void_p(16), 1 << 30,
                             None) == jk.JKO_ERR_INVALID
     assert b"piecewise constant" in lib.jko_last_error()
+    # dL/dcoef of the generalised entropies needs the weight field
+    gen = jk.EnergySpec(kind="gen_entropy", m=1.5).to_c((8, 8))
+    assert lib.jko_backward(ctypes.byref(g), ctypes.byref(gen), ctypes.byref(prm), 2, iters, ctypes.c_void_p(1),
+                            ctypes.c_void_p(2), ctypes.c_void_p(4), None, ctypes.c_void_p(16), 1 << 30,
+                            None) == jk.JKO_ERR_INVALID
+    assert b"coef" in lib.jko_last_error()
     ent = jk.EnergySpec(kind="entropy").to_c((8, 8))
     iters = (ctypes.c_int32 * 1)(10)
     # dL/dw only for congestion

@@ -137,11 +137,13 @@ def test_gen512_one_step_full_size(precision):
     assert err <= TOL[precision]
 
 
-@pytest.mark.parametrize("shape,setup", [((48, 40), "exponents"), ((48, 40), "weights"), ((20, 24, 36), "exponents")])
+@pytest.mark.parametrize("shape,setup", [((48, 40), "exponents"), ((48, 40), "weights"), ((20, 24, 36), "exponents"),
+                                         ((20, 24, 36), "weights")])
 def test_adjoint_matches_fp64_autograd(shape, setup):
-    """dL/dp0 of L = ||p_T - target||^2 from the hand-written adjoint (its
-    prox step through the implicit derivative) against torch float64 autograd
-    through the oracle's unrolled iteration, 2 steps x 30 iterations."""
+    """dL/dp0 (and, where the weights are a field, dL/db) of
+    L = ||p_T - target||^2 from the hand-written adjoint (its prox step
+    through the implicit derivatives) against torch float64 autograd through
+    the oracle's unrolled iteration, 2 steps x 30 iterations."""
     from oracle.grad import loss_and_grads
     banner(f"gen entropy adjoint {shape} {setup}")
     wl = _case(shape, setup)
@@ -151,12 +153,14 @@ def test_adjoint_matches_fp64_autograd(shape, setup):
     target /= target.sum()
     pT, _, ck = jk.flow(dev(wl.p0), g_en, wl.gamma, wl.tau, 2, max_iters=30, checkpoints=True)
     dL = 2.0 * (pT - dev(target))
-    gw, gp = jk.backward(ck, [30, 30], dL.contiguous(), g_en, wl.gamma, wl.tau, want_w=False)
-    assert gw is None
-    loss, _, rp, _ = loss_and_grads(f32(wl.p0).astype(np.float64), np.zeros(shape), np.inf, wl.gamma, wl.tau,
+    want_b = wl.coef is not None
+    gw, gp = jk.backward(ck, [30, 30], dL.contiguous(), g_en, wl.gamma, wl.tau, want_w=want_b)
+    assert (gw is not None) == want_b
+    loss, rb, rp, _ = loss_and_grads(f32(wl.p0).astype(np.float64), np.zeros(shape), np.inf, wl.gamma, wl.tau,
                                     [30, 30], target, kind="gen_entropy", coef=o_en._coef(shape), m=o_en._m(shape),
                                     density_scale=wl.density_scale)
     ep = np.linalg.norm(host64(gp) - rp) / np.linalg.norm(rp)
-    print(f"[gpu-test] gen entropy adjoint {shape} {setup}: rel err dL/dp0 {ep:.2e}", flush=True)
-    assert ep <= 1e-3
+    eb = np.linalg.norm(host64(gw) - rb) / np.linalg.norm(rb) if want_b else 0.0
+    print(f"[gpu-test] gen entropy adjoint {shape} {setup}: rel err dL/dp0 {ep:.2e}, dL/db {eb:.2e}", flush=True)
+    assert ep <= 1e-3 and eb <= 1e-3
 

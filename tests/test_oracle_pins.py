@@ -461,8 +461,9 @@ def test_log_domain_matches_plain_where_both_finite():
 
 def test_reference_gradient_gen_entropy_matches_finite_differences():
     """The generalised-entropy flow (per-cell weights and exponents from 1 to
-    2, density units): autograd through the implicit derivative of the prox
-    == central differences of the numpy oracle's forward map in p0."""
+    2, density units): autograd through the implicit derivatives of the prox
+    == central differences of the numpy oracle's forward map in p0 and in the
+    weights b."""
     shape = (8, 8)
     rng = np.random.default_rng(8)
     gamma, tau = 2e-2, 5e-2
@@ -476,15 +477,23 @@ def test_reference_gradient_gen_entropy_matches_finite_differences():
     iters = [20, 20]
     en = O.Energy(kind="gen_entropy", coef=b, m_field=m, density_scale=D)
 
-    def fwd(p0_):
+    def fwd(p0_, b_=b):
+        e = O.Energy(kind="gen_entropy", coef=b_, m_field=m, density_scale=D)
         q = p0_
         for K in iters:
-            q, _ = O.jko_step(q, en, gamma, tau, K)
+            q, _ = O.jko_step(q, e, gamma, tau, K)
         return float(((q - target) ** 2).sum())
 
-    loss, _, gp, _ = loss_and_grads(p0, np.zeros(shape), np.inf, gamma, tau, iters, target, kind="gen_entropy",
-                                    coef=b, m=m, density_scale=D)
+    loss, gb, gp, _ = loss_and_grads(p0, np.zeros(shape), np.inf, gamma, tau, iters, target, kind="gen_entropy",
+                                     coef=b, m=m, density_scale=D)
     assert loss == pytest.approx(fwd(p0), rel=1e-13)
+    for c in [(1, 1), (4, 5), (0, 3), (7, 7)]:
+        hb = 1e-5 * b[c]
+        bp, bm = b.copy(), b.copy()
+        bp[c] += hb
+        bm[c] -= hb
+        fd = (fwd(p0, bp) - fwd(p0, bm)) / (2 * hb)
+        assert gb[c] == pytest.approx(fd, rel=1e-5, abs=1e-9 * abs(loss))
     for c in [(1, 1), (4, 5), (6, 2), (7, 7), (0, 5)]:
         hp = 1e-5 * p0[c]
         pp, pm = p0.copy(), p0.copy()
