@@ -169,3 +169,15 @@ def test_crowd256_binary_full_size(precision):
     assert differ <= 0.001
     assert st["marginal_l1"] == pytest.approx(rst["marginal_l1"], rel=0.01)
 
+
+def test_stats_of_a_binary_step():
+    """The reported mass is the sum of the returned binary density, and the
+    reported violation is the oracle's at the same count."""
+    banner("binary stats")
+    wl = _case((48, 40))
+    g_en, o_en = energies(wl)
+    p, st = jk.step(dev(wl.p0), g_en, wl.gamma, wl.tau, max_iters=40, tol=0.0)
+    _, ost = O.jko_step(f32(wl.p0).astype(np.float64), o_en, wl.gamma, wl.tau, 40)
+    assert st["mass"] == pytest.approx(float(host64(p).sum()), rel=1e-5)
+    assert st["marginal_l1"] == pytest.approx(ost["marginal_l1"], rel=1e-3)
+

@@ -164,3 +164,25 @@ def test_adjoint_matches_fp64_autograd(shape, setup):
     print(f"[gpu-test] gen entropy adjoint {shape} {setup}: rel err dL/dp0 {ep:.2e}, dL/db {eb:.2e}", flush=True)
     assert ep <= 1e-3 and eb <= 1e-3
 
+
+@pytest.mark.parametrize("resident", [True, False])
+def test_tolerance_mode_stops_like_the_oracle(resident):
+    """Tolerance mode (stop test every 10 iterations, in the resident kernel
+    or on the host-driven path): the step stops within one check interval
+    of the oracle and returns the oracle's iterate at that count."""
+    banner(f"gen entropy tolerance mode resident={resident}")
+    wl = _case((48, 40), "exponents")
+    g_en, o_en = energies(wl)
+    tol, ce = 1e-6, 10
+    p, st = jk.step(dev(wl.p0), g_en, wl.gamma, wl.tau, max_iters=3000, tol=tol, check_every=ce,
+                    resident=resident)
+    q = f32(wl.p0).astype(np.float64)
+    ref, ost = O.jko_step(q, o_en, wl.gamma, wl.tau, 3000, tol=tol, check_every=ce)
+    print(f"[gpu-test] gen entropy tolerance: device {st['iters']} iterations, oracle {ost['iters']}", flush=True)
+    assert st["stop"] == "tol" and ost["stop"] == "tol"
+    assert st["iters"] % ce == 0 and abs(st["iters"] - ost["iters"]) <= ce
+    assert st["marginal_l1"] <= tol
+    assert st["mass"] == pytest.approx(float(host64(p).sum()), rel=1e-5)
+    ref_same, _ = O.jko_step(q, o_en, wl.gamma, wl.tau, st["iters"])
+    assert rel_l1(host64(p), ref_same) <= TOL["fp32"]
+
