@@ -16,7 +16,10 @@ SIAM J. Imaging Sci. 2015):
   scaling form (Section 3.4, Proposition 3.3) with the stopping test of
   Listing 1 on the violation of the constraint pi^T 1 = q;
 * KL proximal maps of f (Section 4.2 Proposition 4.1 congestion,
-  Section 4.4 Proposition 4.2 generalised entropies).
+  Section 4.4 Proposition 4.2 generalised entropies);
+* the Wasserstein attraction with congestion of Section 5.2: the M = 2
+  scaling of Proposition 5.2 verbatim (``attraction_generic``) and reduced
+  (``attraction_step``).
 
 Three forms of the same iteration are kept so that the tests can pin each
 against the next:
@@ -433,6 +436,85 @@ def jko_step(q: np.ndarray, en: Energy, gamma: float, tau: float, max_iters: int
     t = gibbs_apply(a, gamma, mode, transpose=True)
     err = float(np.abs(b * t - q).sum())
     return p, dict(iters=max_iters, marginal_l1=err, mass=float(p.sum()), stop="cap")
+
+
+# --------------------------------------------------------------------------
+# Wasserstein attraction with congestion (Section 5.1, Section 5.2)
+# --------------------------------------------------------------------------
+
+def prox_attraction_psi1(p1, p2, tau, kappa):
+    """eq. prox-psi-attraction with h = iota_[0,kappa]: the KL_lambda prox
+    (lambda = (1, tau)) of psi_1 = iota_D + h is (p, p) with
+    p = Prox^KL_{h/(1+tau)}(p1^{1/(1+tau)} p2^{tau/(1+tau)}), and the KL prox of
+    an indicator of [0, kappa] is the clamp (eq. dfn-congestion-prox)."""
+    return np.minimum(np.power(p1, 1.0 / (1.0 + tau)) * np.power(p2, tau / (1.0 + tau)), kappa)
+
+
+def attraction_generic(q, r, kappa, gamma, tau, n_half_steps, first=1, mode="separable"):
+    """Proposition 5.2 as stated for M = 2 couplings with xi_1 = xi_2 = xi and
+    the functions of Section 5.2: psi_1 = iota_D + h on the left marginals
+    pi_m 1, psi_2 = iota_{(q, r)} on the right marginals pi_m^T 1.  All of
+    a_m, b_m, u_m, v_m start at 1.  ``first`` names the function of the odd
+    half-steps: 1 as printed ([l]_2 = 1 is psi_1), 2 for the other order (the
+    marginals first, as Proposition 3.3 orders its two functions).  Returns
+    (p, a, b, u, v), p the common left marginal of the last psi_1 half-step.
+    Conventions: 0 / 0 = 0."""
+    one = np.ones_like(q)
+    a = [one.copy(), one.copy()]
+    b = [one.copy(), one.copy()]
+    u_hist = {-1: [one, one], 0: [one, one]}
+    v_hist = {-1: [one, one], 0: [one, one]}
+    targets = (q, r)
+    p = None
+    for l in range(1, n_half_steps + 1):
+        which = first if l % 2 == 1 else 3 - first
+        at = [a[m] * u_hist[l - 2][m] for m in range(2)]       # a~ = a (l-1) * u (l-2)
+        bt = [b[m] * v_hist[l - 2][m] for m in range(2)]       # b~ = b (l-1) * v (l-2)
+        a_prev, b_prev = a, b
+        if which == 1:
+            xb = [gibbs_apply(bt[m], gamma, mode) for m in range(2)]
+            pt = [at[m] * xb[m] for m in range(2)]
+            p = prox_attraction_psi1(pt[0], pt[1], tau, kappa)
+            a = [_safe_div(p, xb[m]) for m in range(2)]
+            b = bt
+        else:
+            xa = [gibbs_apply(at[m], gamma, mode, transpose=True) for m in range(2)]
+            b = [_safe_div(targets[m], xa[m]) for m in range(2)]
+            a = at
+        u_hist[l] = [u_hist[l - 2][m] * _safe_div(a_prev[m], a[m]) for m in range(2)]
+        v_hist[l] = [v_hist[l - 2][m] * _safe_div(b_prev[m], b[m]) for m in range(2)]
+    return p, a, b, u_hist[n_half_steps], v_hist[n_half_steps]
+
+
+def attraction_step(q, r, kappa, gamma, tau, max_iters, tol=0.0, check_every=1, mode="separable"):
+    """One JKO step of f = W_gamma(r, .) + iota_[0,kappa] (Section 5.2): the
+    scaling of Proposition 5.2 with the marginals first and the corrections
+    dropped, as ``jko_step`` does for one coupling.  Iteration k:
+        t_m = xi^T a_m,  b_1 = q / t_1,  b_2 = r / t_2,  s_m = xi b_m,
+        p = min(s_1^{1/(1+tau)} s_2^{tau/(1+tau)}, kappa),  a_m = p / s_m.
+    The monitor is the violation of both couplings' right marginals,
+    ||b_1 t_1 - q||_1 + ||b_2 t_2 - r||_1, with the stop rule and the
+    statistics of ``jko_step``."""
+    a = [np.ones_like(q), np.ones_like(q)]
+    b = None
+    p = None
+    targets = (q, r)
+
+    def violation(t):
+        return float(sum(np.abs(b[m] * t[m] - targets[m]).sum() for m in range(2)))
+
+    for k in range(1, max_iters + 1):
+        t = [gibbs_apply(a[m], gamma, mode, transpose=True) for m in range(2)]
+        if k > 1 and tol > 0 and (k - 1) % check_every == 0:
+            err = violation(t)
+            if err <= tol:
+                return p, dict(iters=k - 1, marginal_l1=err, mass=float(p.sum()), stop="tol")
+        b = [_safe_div(targets[m], t[m]) for m in range(2)]
+        sv = [gibbs_apply(b[m], gamma, mode) for m in range(2)]
+        p = prox_attraction_psi1(sv[0], sv[1], tau, kappa)
+        a = [_safe_div(p, sv[m]) for m in range(2)]
+    t = [gibbs_apply(a[m], gamma, mode, transpose=True) for m in range(2)]
+    return p, dict(iters=max_iters, marginal_l1=violation(t), mass=float(p.sum()), stop="cap")
 
 
 def jko_step_log(q: np.ndarray, en: Energy, gamma: float, tau: float, max_iters: int,

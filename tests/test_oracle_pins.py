@@ -321,6 +321,109 @@ def test_converged_step_solves_the_jko_problem(kind):
         assert (ref > 0.22 - 1e-6).any(), "the capacity should be active in this case"
 
 
+# ---------------------------------------------------------- Wasserstein attraction
+
+def _attraction_case(seed=12, shape=(6, 5)):
+    rng = np.random.default_rng(seed)
+    q = rng.uniform(0.2, 1.0, size=shape)
+    q /= q.sum()
+    r = rng.uniform(0.2, 1.0, size=shape) ** 3
+    r /= r.sum()
+    return q, r
+
+
+def test_attraction_reduced_equals_proposition_5_2():
+    """Proposition 5.2 verbatim (marginals first) == the reduced iteration,
+    half-step by half-step, with u_m a_m = 1 and v_m = 1 after even
+    half-steps (the corrections that the reduction drops)."""
+    q, r = _attraction_case()
+    kappa = 1.2 * max(q.max(), r.max())
+    for L in (2, 4, 10, 30):
+        pg, a, b, u, v = O.attraction_generic(q, r, kappa, 0.05, 0.1, L, first=2, mode="dense")
+        pr, _ = O.attraction_step(q, r, kappa, 0.05, 0.1, L // 2, mode="separable")
+        np.testing.assert_allclose(pr, pg, rtol=1e-11)
+        for m in range(2):
+            np.testing.assert_allclose(u[m] * a[m], 1.0, rtol=1e-12)
+            np.testing.assert_allclose(v[m], 1.0, rtol=1e-12)
+
+
+def test_attraction_limit_does_not_depend_on_the_order():
+    """Dykstra's limit is the minimiser whatever function acts first: the
+    printed order (psi_1 first) and the marginals-first order agree once
+    converged."""
+    q, r = _attraction_case(13)
+    kappa = 1.1 * q.max()
+    p1, *_ = O.attraction_generic(q, r, kappa, 0.05, 0.1, 4001, first=1)
+    p2, *_ = O.attraction_generic(q, r, kappa, 0.05, 0.1, 4000, first=2)
+    np.testing.assert_allclose(p1, p2, rtol=1e-7, atol=1e-12)
+
+
+@pytest.mark.parametrize("p1,p2,tau,kappa", [(0.3, 0.8, 0.1, np.inf), (2.0, 0.05, 1.5, np.inf),
+                                             (0.4, 0.9, 0.7, 0.45), (1e-3, 4.0, 3.0, np.inf)])
+def test_attraction_prox_minimises(p1, p2, tau, kappa):
+    """eq. prox-psi-attraction against a direct minimisation over p of
+    KL(p|p1) + tau KL(p|p2) on [0, kappa] (the KL_lambda divergence of (p, p)
+    to (p1, p2), lambda = (1, tau))."""
+    got = float(O.prox_attraction_psi1(np.array(p1), np.array(p2), tau, kappa))
+    hi = min(kappa, 10.0 * max(p1, p2))
+    ref = _log_golden_min(lambda p: _kl(p, p1) + tau * _kl(p, p2), 1e-12 * min(p1, p2), hi)
+    assert got == pytest.approx(ref, rel=2e-6)
+
+
+def test_attraction_to_its_own_density_is_one_blur():
+    """r = q without capacity: f = W(q, .) makes the step the minimiser of
+    (1 + tau) W_gamma(q, p), the blur xi (q / xi^T 1) of the conclusion."""
+    q, _ = _attraction_case(14)
+    p, _ = O.attraction_step(q, q, np.inf, 0.05, 0.3, 3)
+    ref = O.gibbs_apply(q / O.gibbs_apply(np.ones_like(q), 0.05, transpose=True), 0.05)
+    np.testing.assert_allclose(p, ref, rtol=1e-12)
+
+
+def test_converged_attraction_step_solves_the_two_coupling_problem():
+    """The converged scaling solves the problem of Section 5.2 posed on the
+    couplings themselves: min <c, pi_1> + gamma E(pi_1) + tau (<c, pi_2> +
+    gamma E(pi_2)) s.t. pi_1^T 1 = q, pi_2^T 1 = r, pi_1 1 = pi_2 1 <= kappa,
+    found by SLSQP on the entries (1D grid)."""
+    n = 6
+    rng = np.random.default_rng(15)
+    q = rng.uniform(0.3, 1.0, n)
+    q /= q.sum()
+    r = np.linspace(0.05, 1.0, n) ** 2
+    r /= r.sum()
+    gamma, tau, kappa = 0.05, 0.4, 0.19
+    p, st = O.attraction_step(q, r, kappa, gamma, tau, max_iters=20000, tol=1e-14, check_every=1,
+                              mode="dense")
+    x = (np.arange(n) + 0.5) / n
+    c = (x[:, None] - x[None, :]) ** 2
+
+    def F(v):
+        p1, p2 = v[:n * n].reshape(n, n), v[n * n:].reshape(n, n)
+        val = (c * p1).sum() + gamma * (p1 * (np.log(p1) - 1)).sum()
+        val += tau * ((c * p2).sum() + gamma * (p2 * (np.log(p2) - 1)).sum())
+        g = np.concatenate([(c + gamma * np.log(p1)).ravel(), (tau * (c + gamma * np.log(p2))).ravel()])
+        return val, g
+
+    col = np.kron(np.ones((1, n)), np.eye(n))
+    row = np.kron(np.eye(n), np.ones((1, n)))
+    Z = np.zeros((n, n * n))
+    cons = [dict(type="eq", fun=lambda v: v[:n * n].reshape(n, n).sum(0) - q, jac=lambda v: np.hstack([col, Z])),
+            dict(type="eq", fun=lambda v: v[n * n:].reshape(n, n).sum(0) - r, jac=lambda v: np.hstack([Z, col])),
+            # equal left marginals; the last one follows from the others (both
+            # couplings carry mass one), and SLSQP needs independent constraints
+            dict(type="eq", fun=lambda v: (v[:n * n].reshape(n, n).sum(1) - v[n * n:].reshape(n, n).sum(1))[:-1],
+                 jac=lambda v: np.hstack([row, -row])[:-1]),
+            dict(type="ineq", fun=lambda v: kappa - v[:n * n].reshape(n, n).sum(1), jac=lambda v: np.hstack([-row, Z]))]
+    v0 = np.concatenate([(np.ones((n, n)) * q[None, :] / n).ravel(), (np.ones((n, n)) * r[None, :] / n).ravel()])
+    with np.errstate(all="ignore"), warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        res = minimize(F, v0, jac=True, method="SLSQP", constraints=cons, bounds=[(1e-14, None)] * (2 * n * n),
+                       options=dict(ftol=1e-16, maxiter=3000))
+    assert res.success, res.message
+    ref = res.x[:n * n].reshape(n, n).sum(1)
+    np.testing.assert_allclose(p, ref, rtol=5e-5, atol=1e-9)
+    assert p.max() <= kappa and (ref > kappa - 1e-6).any(), "the capacity should be active in this case"
+
+
 def _heat_recursion(S, gamma, tau):
     u = ((gamma + 2 * S) + math.sqrt((gamma + 2 * S) ** 2 + 8 * tau * S)) / 2
     return (u + tau) / 2
