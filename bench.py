@@ -57,7 +57,7 @@ def _energy(wl):
     import paper_1502_06216_amd as jk
     return jk.EnergySpec(kind=wl.kind, w=_dev(wl.w), kappa=_dev(wl.kappa), kappa_scalar=wl.kappa_scalar,
                          coef=_dev(wl.coef), coef_scalar=wl.coef_scalar, m=wl.m,
-                         density_scale=wl.density_scale, m_field=_dev(wl.m_field))
+                         density_scale=wl.density_scale, m_field=_dev(wl.m_field), target=_dev(wl.target))
 
 
 def run_flow(wl, precision, steps, warmup, tol=None, max_iters=None, resident=True):
@@ -382,6 +382,13 @@ def main():
             extra[f"crowd256_binary_{prec}"] = {"iters_per_s": round(itb / elb, 2),
                                                 "jko_steps_per_s": round(wlb.n_steps / elb, 3),
                                                 "iters_per_step": wlb.max_iters}
+        # Wasserstein attraction with congestion (two couplings, Section 5.2)
+        wla = make_workload("crowd256_attraction")
+        for prec in ("fp32", "split_bf16"):
+            ita, ela, sta, _ = run_flow(wla, prec, wla.n_steps, 1)
+            extra[f"crowd256_attraction_{prec}"] = {"iters_per_s": round(ita / ela, 2),
+                                                    "jko_steps_per_s": round(wla.n_steps / ela, 3),
+                                                    "iters_per_step": wla.max_iters}
         # generalised entropies with exponents varying from 1 to 2 over the grid
         wlg = make_workload("gen512")
         for prec in ("fp32", "split_bf16"):

@@ -95,14 +95,24 @@ typedef enum { JKO_FP32 = 0, JKO_SPLIT_BF16 = 1 } jko_precision;
  *                    (the m = 1 limit is psi = (D s)^{1/(1 + sigma b)}), by
  *                    newton_steps Newton steps on log psi; jko_backward
  *                    differentiates it through the implicit derivative
- *                    d log psi / d log s = 1 / (1 + sigma b m psi^{m-1}). */
+ *                    d log psi / d log s = 1 / (1 + sigma b m psi^{m-1}).
+ *  JKO_F_ATTRACTION  f = W_gamma(r, p) + iota_[0,kappa](p), the Wasserstein
+ *                    attraction towards target (r, N cells, device; a shape,
+ *                    scaled to the mass of each step's input) with
+ *                    congestion of Section 5.2, solved by the two-coupling
+ *                    scaling of Proposition 5.2 (marginals first; the proximal
+ *                    half-step is eq. prox-psi-attraction).  The workspace is
+ *                    sized by JKO_OP_ATTRACTION_STEP / _FLOW.  1D and 2D grids
+ *                    with every axis >= 3; plain domain only (absorb_threshold
+ *                    must be +inf or NaN); no resident kernel, no backward. */
 typedef enum {
     JKO_F_ZERO = 0,
     JKO_F_CONGESTION = 1,
     JKO_F_POROUS = 2,
     JKO_F_ENTROPY = 3,
     JKO_F_CONGESTION_BINARY = 4,
-    JKO_F_GEN_ENTROPY = 5
+    JKO_F_GEN_ENTROPY = 5,
+    JKO_F_ATTRACTION = 6
 } jko_energy_kind;
 
 typedef struct {
@@ -121,6 +131,7 @@ typedef struct {
     float density_scale;     /* porous / gen. entropy D, > 0 (1 = per-cell mass) */
     int32_t newton_steps;    /* porous / gen. entropy Newton steps per cell, 1..32 (0 = default 8) */
     const float* m_field;    /* gen. entropy exponents m_i >= 1, N cells, device; NULL = m */
+    const float* target;     /* attraction target density r, N cells, device */
 } jko_energy;
 
 typedef struct {
@@ -164,7 +175,14 @@ typedef struct {
 } jko_stats;
 
 /* Operation codes for jko_workspace_bytes. */
-typedef enum { JKO_OP_GIBBS = 0, JKO_OP_STEP = 1, JKO_OP_FLOW = 2, JKO_OP_BACKWARD = 3 } jko_op;
+typedef enum {
+    JKO_OP_GIBBS = 0,
+    JKO_OP_STEP = 1,
+    JKO_OP_FLOW = 2,
+    JKO_OP_BACKWARD = 3,
+    JKO_OP_ATTRACTION_STEP = 4,   /* jko_step with JKO_F_ATTRACTION */
+    JKO_OP_ATTRACTION_FLOW = 5    /* jko_flow with JKO_F_ATTRACTION */
+} jko_op;
 
 /* Bytes of device workspace `op` needs for this grid and these parameters
  * (for JKO_OP_BACKWARD, n_steps is the largest iteration count of one step).

@@ -494,7 +494,9 @@ def attraction_step(q, r, kappa, gamma, tau, max_iters, tol=0.0, check_every=1, 
         p = min(s_1^{1/(1+tau)} s_2^{tau/(1+tau)}, kappa),  a_m = p / s_m.
     The monitor is the violation of both couplings' right marginals,
     ||b_1 t_1 - q||_1 + ||b_2 t_2 - r||_1, with the stop rule and the
-    statistics of ``jko_step``."""
+    statistics of ``jko_step``.  The two couplings need marginals of one mass:
+    r is taken as a shape and scaled to the mass of q."""
+    r = r * (q.sum() / r.sum())
     a = [np.ones_like(q), np.ones_like(q)]
     b = None
     p = None

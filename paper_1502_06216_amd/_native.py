@@ -27,8 +27,9 @@ JKO_ERR_NONFINITE = -4
 JKO_ERR_INFEASIBLE = -5
 
 PRECISIONS = {"fp32": 0, "split_bf16": 1}
-ENERGY_KINDS = {"zero": 0, "congestion": 1, "porous": 2, "entropy": 3, "binary_congestion": 4, "gen_entropy": 5}
-OP_GIBBS, OP_STEP, OP_FLOW, OP_BACKWARD = 0, 1, 2, 3
+ENERGY_KINDS = {"zero": 0, "congestion": 1, "porous": 2, "entropy": 3, "binary_congestion": 4, "gen_entropy": 5,
+                "attraction": 6}
+OP_GIBBS, OP_STEP, OP_FLOW, OP_BACKWARD, OP_ATTRACTION_STEP, OP_ATTRACTION_FLOW = 0, 1, 2, 3, 4, 5
 FLAG_NO_RESIDENT = 1   # jko_flags: keep one launch per Gibbs application
 FLAG_AXIS_PASSES = 2   # jko_flags: 3D applications as three axis passes
 
@@ -48,7 +49,7 @@ class EnergyC(ctypes.Structure):
                 ("kappa_scalar", ctypes.c_float), ("coef", ctypes.c_void_p),
                 ("coef_scalar", ctypes.c_float), ("m", ctypes.c_float),
                 ("density_scale", ctypes.c_float), ("newton_steps", ctypes.c_int32),
-                ("m_field", ctypes.c_void_p)]
+                ("m_field", ctypes.c_void_p), ("target", ctypes.c_void_p)]
 
 
 class Params(ctypes.Structure):
@@ -150,7 +151,9 @@ class EnergySpec:
     kind: "zero", "congestion", "binary_congestion" (the non-convex {0, kappa}
     constraint of Section 4.5; finite kappa, no backward), "porous", "entropy",
     "gen_entropy" (the generalised entropies of Section 4.4 with per-cell
-    weights coef and exponents m_field >= 1; no backward)."""
+    weights coef and exponents m_field >= 1), "attraction" (Wasserstein
+    attraction towards the density target, with capacity kappa, Section 5.2;
+    1D/2D grids, plain domain, no backward)."""
     kind: str = "zero"
     w: Optional[torch.Tensor] = None
     kappa: Optional[torch.Tensor] = None
@@ -161,6 +164,7 @@ class EnergySpec:
     density_scale: float = 1.0
     newton_steps: int = 8
     m_field: Optional[torch.Tensor] = None
+    target: Optional[torch.Tensor] = None
 
     def to_c(self, shape) -> EnergyC:
         e = EnergyC()
@@ -174,6 +178,7 @@ class EnergySpec:
         e.density_scale = float(self.density_scale)
         e.newton_steps = int(self.newton_steps)
         e.m_field = _ptr(_field(self.m_field, shape, "m_field"))
+        e.target = _ptr(_field(self.target, shape, "target"))
         return e
 
 
@@ -228,7 +233,8 @@ def step(p: torch.Tensor, energy: EnergySpec, gamma: float, tau: float, max_iter
     g = make_grid(shape)
     prm = make_params(gamma, tau, max_iters, tol, check_every, precision, absorb_threshold, resident, planes)
     e = energy.to_c(shape)
-    nb = lib.jko_workspace_bytes(ctypes.byref(g), ctypes.byref(prm), OP_STEP, 0)
+    op = OP_ATTRACTION_STEP if energy.kind == "attraction" else OP_STEP
+    nb = lib.jko_workspace_bytes(ctypes.byref(g), ctypes.byref(prm), op, 0)
     ws = _workspace(nb, p.device)
     st = Stats()
     _check(lib.jko_step(ctypes.byref(g), ctypes.byref(e), ctypes.byref(prm), _ptr(p), _ptr(pout),
@@ -250,7 +256,8 @@ def flow(p0: torch.Tensor, energy: EnergySpec, gamma: float, tau: float, n_steps
     g = make_grid(shape)
     prm = make_params(gamma, tau, max_iters, tol, check_every, precision, absorb_threshold, resident, planes)
     e = energy.to_c(shape)
-    nb = lib.jko_workspace_bytes(ctypes.byref(g), ctypes.byref(prm), OP_FLOW, n_steps)
+    op = OP_ATTRACTION_FLOW if energy.kind == "attraction" else OP_FLOW
+    nb = lib.jko_workspace_bytes(ctypes.byref(g), ctypes.byref(prm), op, n_steps)
     ws = _workspace(nb, p0.device)
     sts = (Stats * n_steps)() if with_stats else None
     _check(lib.jko_flow(ctypes.byref(g), ctypes.byref(e), ctypes.byref(prm), int(n_steps), _ptr(p0), _ptr(pT),

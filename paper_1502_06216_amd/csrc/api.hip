@@ -95,7 +95,18 @@ Pass make_pass(const PassShape& ps) {
 
 // ---------------------------------------------------------------- workspace
 
-enum : int { OP_GIBBS = 0, OP_STEP = 1, OP_FLOW = 2, OP_BACKWARD = 3 };
+enum : int { OP_GIBBS = 0, OP_STEP = 1, OP_FLOW = 2, OP_BACKWARD = 3, OP_ATTR_STEP = 4, OP_ATTR_FLOW = 5 };
+
+// The Wasserstein attraction keeps two couplings; their scalings are stacked
+// as one field of shape (2, n...) whose first axis has the identity as factor.
+Geo stacked_of(const Geo& g) {
+    Geo s;
+    s.d = g.d + 1;
+    s.n[0] = 2;
+    for (int k = 0; k < g.d; ++k) s.n[k + 1] = g.n[k];
+    s.N = 2 * g.N;
+    return s;
+}
 
 struct Layout {
     size_t ctl = 0, sync = 0, hostout = 0, part = 0, factors = 0, fields = 0, hist = 0, stats = 0, total = 0;
@@ -389,6 +400,11 @@ jko_status check_energy(const jko_energy* en) {
         case JKO_F_ENTROPY:
             if (!en->coef && !(en->coef_scalar >= 0.f)) return fail(JKO_ERR_INVALID, "coef_scalar must be >= 0");
             return JKO_OK;
+        case JKO_F_ATTRACTION:
+            if (!en->target) return fail(JKO_ERR_INVALID, "attraction: target is NULL");
+            if (!en->kappa && (isnan(en->kappa_scalar) || en->kappa_scalar < 0.f))
+                return fail(JKO_ERR_INVALID, "kappa_scalar must be >= 0 (or +inf)");
+            return JKO_OK;
         case JKO_F_GEN_ENTROPY:
             if (!en->m_field && (!(en->m >= 1.f) || !isfinite(en->m)))
                 return fail(JKO_ERR_INVALID, "generalised entropy exponent m must be >= 1");
@@ -650,6 +666,155 @@ jko_status run_step(const Plan& P, const jko_params* pr, const ProxArgs& px, con
     return JKO_OK;
 }
 
+// Mass of a density of N cells (synchronous).
+jko_status mass_of(const Plan& P, const float* p, int64_t N, double* out) {
+    HIP_TRY(launch_input_check(p, nullptr, INFINITY, N, 0, P.part.err, 3 * 256, P.hostout, P.st));
+    HIP_TRY(hipMemcpyAsync(g_rb.host, P.hostout, sizeof(double), hipMemcpyDeviceToHost, P.st));
+    HIP_TRY(hipStreamSynchronize(P.st));
+    memcpy(out, g_rb.host, sizeof(double));
+    return JKO_OK;
+}
+
+// One JKO step of the Wasserstein attraction with congestion (Section 5.2) on
+// the stacked plan P (shape (2, n...)): the scaling of Proposition 5.2 with the
+// marginals first and the corrections dropped.  Iteration k:
+//   t_m = xi^T a_m, b_m = (q, r)_m / t_m          (b-update epilogue, stacked)
+//   s_m = xi b_m                                    (store epilogue)
+//   p = min(s_1^{1/(1+tau)} s_2^{tau/(1+tau)}, kappa), a_m = p / s_m
+// with the monitor, stop rule and statistics of run_step (the monitor is the
+// violation of both couplings' right marginals).  N cells per field; the
+// target is scaled by rscale to the mass of q (both couplings need one mass).
+jko_status run_attraction(const Plan& P, const jko_params* pr, const jko_energy* en, const float* q, float* p_out,
+                          int64_t N, double rscale, bool want_stats, jko_stats* st_out) {
+    const int K = pr->max_iters;
+    const int ce = pr->check_every;
+    const bool tolmode = pr->tol_l1 > 0.0;
+    float* a = P.F(F_A);
+    float* b = P.F(F_B);
+    float* sv = P.F(F_G);    // s_1, s_2
+    float* qs = P.F(F_KF);   // q, r
+    HIP_TRY(launch_copy(qs, q, N, P.st));
+    HIP_TRY(launch_copy_scaled(qs + N, en->target, rscale, N, P.st));   // r at the mass of q
+    HIP_TRY(launch_fill(a, 1.f, 2 * N, P.st));
+    HIP_TRY(launch_ctl_reset(P.ctl, 0, P.st));
+    EpiArgs eb{};
+    eb.kind = EpiKind::BUPDATE;
+    eb.q = qs;
+    eb.b = b;
+    eb.part = P.part;
+    eb.ctl = P.ctl;
+    EpiArgs es{};
+    es.kind = EpiKind::STORE;
+    es.y = sv;
+    es.part = P.part;
+    es.ctl = P.ctl;
+    const double alpha = 1.0 / (1.0 + pr->tau);
+    bool pending = false, stopped = false;
+    int nb = 0;
+    for (int k = 1; k <= K; ++k) {
+        eb.check = (tolmode && k > 1 && (k - 1) % ce == 0) ? 1 : 0;
+        jko_status s = apply_xi(P, a, eb, &nb);
+        if (s) return s;
+        if (eb.check) {
+            HIP_TRY(launch_ctl_check(P.ctl, P.part, nb, k, pr->tol_l1, 0, 0.0, P.st));
+            if (pending) {
+                HIP_TRY(hipEventSynchronize(g_rb.ev));
+                if (g_rb.host->done) stopped = true;
+            }
+            if (stopped) break;
+            HIP_TRY(hipMemcpyAsync(g_rb.host, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, P.st));
+            HIP_TRY(hipEventRecord(g_rb.ev, P.st));
+            pending = true;
+        }
+        if ((s = apply_xi(P, b, es, &nb))) return s;
+        HIP_TRY(launch_attraction_prox(sv, a, p_out, en->kappa, en->kappa_scalar, alpha, N, P.ctl, P.st));
+    }
+    Ctl c{};
+    if (tolmode || want_stats) {
+        HIP_TRY(hipStreamSynchronize(P.st));
+        jko_status s = read_ctl(P, &c);
+        if (s) return s;
+        if (!c.done && want_stats) {
+            EpiArgs em{};
+            em.kind = EpiKind::MONITOR;
+            em.q = qs;
+            em.b = b;
+            em.part = P.part;
+            em.ctl = P.ctl;
+            if ((s = apply_xi(P, a, em, &nb))) return s;
+            HIP_TRY(launch_ctl_check(P.ctl, P.part, nb, K + 1, -1.0, 0, 0.0, P.st));
+            if ((s = read_ctl(P, &c))) return s;
+            c.done = 0;
+        }
+    }
+    if (st_out) {
+        double mass = 0.0;
+        jko_status s = mass_of(P, p_out, N, &mass);
+        if (s) return s;
+        jko_stats& o = *st_out;
+        const bool bytol = tolmode && c.done && !c.nonfinite;
+        o.iters = bytol ? c.stop_iter : K;
+        o.absorptions = 0;
+        o.stop_reason = bytol ? JKO_STOP_TOL : JKO_STOP_CAP;
+        o.status = c.nonfinite ? JKO_ERR_NONFINITE : JKO_OK;
+        o.marginal_l1 = c.err;
+        o.mass = mass;
+        o.max_abs_log_a = 0.0;
+        o.max_abs_log_b = c.maxlogb;
+    }
+    if (c.nonfinite) return fail(JKO_ERR_NONFINITE, "non-finite value in the marginal monitor");
+    return JKO_OK;
+}
+
+// jko_step (n_steps = 1, no checkpoints) and jko_flow for the attraction.
+jko_status attraction_flow(const Geo& g, const jko_energy* en, const jko_params* pr, int n_steps, const float* p0,
+                           float* pT, float* checkpoints, jko_stats* stats, void* ws, size_t ws_bytes,
+                           hipStream_t st, bool flow) {
+    if (g.d > 2) return fail(JKO_ERR_INVALID, "attraction: 1D and 2D grids only");
+    for (int k = 0; k < g.d; ++k)
+        if (g.n[k] < 3) return fail(JKO_ERR_INVALID, "attraction: every axis needs at least 3 cells");
+    if (!(isnan(pr->absorb_threshold) || pr->absorb_threshold == INFINITY))
+        return fail(JKO_ERR_INVALID, "attraction runs in the plain domain: absorb_threshold must be +inf or NaN");
+    Plan P;
+    jko_status s = carve(&P, stacked_of(g), flow ? OP_FLOW : OP_STEP, n_steps, ws, ws_bytes, pr->precision, st);
+    if (s) return s;
+    if ((s = readback_init())) return s;
+    if ((s = build_factors(P, pr->gamma, pr->flags))) return s;
+    // the stacking axis: gamma -> 0 rounds every off-diagonal entry to zero
+    HIP_TRY(launch_build_factor(const_cast<float*>(P.K1[0]), const_cast<uint16_t*>(P.K1hi[0]),
+                                const_cast<uint16_t*>(P.K1lo[0]), 2, 1e-30, P.st));
+    // capacity of the initial density, and a target of the same mass
+    double h[3], hr[3];
+    HIP_TRY(launch_input_check(p0, en->kappa, en->kappa_scalar, g.N, 1, P.part.err, 3 * 256, P.hostout, P.st));
+    HIP_TRY(hipMemcpyAsync(g_rb.host, P.hostout, 3 * sizeof(double), hipMemcpyDeviceToHost, P.st));
+    HIP_TRY(hipStreamSynchronize(P.st));
+    memcpy(h, g_rb.host, sizeof h);
+    HIP_TRY(launch_input_check(en->target, nullptr, INFINITY, g.N, 0, P.part.err, 3 * 256, P.hostout, P.st));
+    HIP_TRY(hipMemcpyAsync(g_rb.host, P.hostout, 3 * sizeof(double), hipMemcpyDeviceToHost, P.st));
+    HIP_TRY(hipStreamSynchronize(P.st));
+    memcpy(hr, g_rb.host, sizeof hr);
+    if (h[2] > 0.0 || hr[2] > 0.0) return fail(JKO_ERR_NONFINITE, "input density, capacity or target has negative/non-finite cells");
+    if (h[1] < h[0] * (1.0 - 1e-6)) return fail(JKO_ERR_INFEASIBLE, "capacity sum %.9g < mass %.9g", h[1], h[0]);
+    if (!(hr[0] > 0.0)) return fail(JKO_ERR_INVALID, "attraction: the target has no mass");
+    const float* q = p0;
+    double mq = h[0];
+    jko_status worst = JKO_OK;
+    for (int t = 0; t < n_steps; ++t) {
+        if (checkpoints) HIP_TRY(launch_copy(checkpoints + (int64_t)t * g.N, q, g.N, P.st));
+        float* out = (t == n_steps - 1) ? pT : P.F((t % 2 == 0) ? F_P0 : F_P1);
+        if (t > 0 && (s = mass_of(P, q, g.N, &mq))) return s;
+        s = run_attraction(P, pr, en, q, out, g.N, mq / hr[0], stats != nullptr, stats ? &stats[t] : nullptr);
+        if (s == JKO_ERR_NONFINITE) {
+            worst = s;
+        } else if (s) {
+            return s;
+        }
+        q = out;
+    }
+    if (worst) return fail(worst, "non-finite value in the marginal monitor");
+    return JKO_OK;
+}
+
 jko_status common_checks(const jko_grid* grid, Geo* g) {
     if (!geo_of(grid, g)) return fail(JKO_ERR_INVALID, "grid: ndim must be 1..3 and 1 <= n[k] <= %d", kMaxN);
     return JKO_OK;
@@ -680,7 +845,11 @@ const char* jko_status_string(int32_t s) {
 size_t jko_workspace_bytes(const jko_grid* grid, const jko_params* params, int32_t op, int32_t n) {
     Geo g;
     if (!geo_of(grid, &g)) return 0;
-    if (op < OP_GIBBS || op > OP_BACKWARD) return 0;
+    if (op < OP_GIBBS || op > OP_ATTR_FLOW) return 0;
+    if (op == OP_ATTR_STEP || op == OP_ATTR_FLOW) {
+        if (g.d > 2) return 0;
+        return layout_of(stacked_of(g), op == OP_ATTR_STEP ? OP_STEP : OP_FLOW, n).total;
+    }
     int64_t extra = n;
     if (op == OP_BACKWARD && params && n <= 0) extra = params->max_iters;
     return layout_of(g, op, extra).total;
@@ -716,6 +885,9 @@ jko_status jko_step(const jko_grid* grid, const jko_energy* energy, const jko_pa
     if ((s = check_params(params)) || (s = check_energy(energy))) return s;
     if (!p_in || !p_out) return fail(JKO_ERR_INVALID, "p_in and p_out must be non-NULL");
     if (p_in == p_out) return fail(JKO_ERR_INVALID, "p_in and p_out may not alias");
+    if (energy->kind == JKO_F_ATTRACTION)
+        return attraction_flow(g, energy, params, 1, p_in, p_out, nullptr, stats, ws, ws_bytes,
+                               static_cast<hipStream_t>(stream), false);
     Plan P;
     s = carve(&P, g, OP_STEP, 0, ws, ws_bytes, params->precision, static_cast<hipStream_t>(stream));
     if (s) return s;
@@ -739,6 +911,9 @@ jko_status jko_flow(const jko_grid* grid, const jko_energy* energy, const jko_pa
     if (n_steps < 1) return fail(JKO_ERR_INVALID, "n_steps must be >= 1");
     if (!p0 || !pT) return fail(JKO_ERR_INVALID, "p0 and pT must be non-NULL");
     if (p0 == pT) return fail(JKO_ERR_INVALID, "p0 and pT may not alias");
+    if (energy->kind == JKO_F_ATTRACTION)
+        return attraction_flow(g, energy, params, n_steps, p0, pT, checkpoints, stats, ws, ws_bytes,
+                               static_cast<hipStream_t>(stream), true);
     Plan P;
     s = carve(&P, g, OP_FLOW, n_steps, ws, ws_bytes, params->precision, static_cast<hipStream_t>(stream));
     if (s) return s;
@@ -774,6 +949,7 @@ jko_status jko_time_iteration(const jko_grid* grid, const jko_energy* energy, co
     if (s) return s;
     if ((s = check_params(params)) || (s = check_energy(energy))) return s;
     if (!p_in || !ms_per_launch || reps < 1) return fail(JKO_ERR_INVALID, "bad timing arguments");
+    if (energy->kind == JKO_F_ATTRACTION) return fail(JKO_ERR_INVALID, "attraction: no iteration timing");
     Plan P;
     s = carve(&P, g, OP_STEP, 0, ws, ws_bytes, params->precision, static_cast<hipStream_t>(stream));
     if (s) return s;
@@ -908,6 +1084,7 @@ jko_status jko_backward(const jko_grid* grid, const jko_energy* energy, const jk
     if ((s = check_params(params)) || (s = check_energy(energy))) return s;
     if (energy->kind == JKO_F_CONGESTION_BINARY)
         return fail(JKO_ERR_INVALID, "binary congestion: the prox is piecewise constant, no gradient");
+    if (energy->kind == JKO_F_ATTRACTION) return fail(JKO_ERR_INVALID, "attraction: no adjoint is built");
     if (n_steps < 1) return fail(JKO_ERR_INVALID, "n_steps must be >= 1");
     if (!iters_per_step || !checkpoints || !dL_dpT) return fail(JKO_ERR_INVALID, "missing input");
     if (dL_dw && energy->kind != JKO_F_CONGESTION && energy->kind != JKO_F_GEN_ENTROPY)

@@ -218,6 +218,9 @@ hipError_t launch_build_factor(float* K1, uint16_t* hi, uint16_t* lo, int n, dou
                                hipStream_t s);
 hipError_t launch_fill(float* x, float v, int64_t n, hipStream_t s);
 hipError_t launch_copy(float* dst, const float* src, int64_t n, hipStream_t s);
+hipError_t launch_copy_scaled(float* dst, const float* src, double f, int64_t n, hipStream_t s);
+hipError_t launch_attraction_prox(const float* s, float* a, float* p, const float* kappa, float kappa_s,
+                                  double alpha, int64_t N, const Ctl* ctl, hipStream_t st);
 hipError_t launch_prepare_energy(const jko_energy* en, double sigma, int64_t N, float* g,
                                  float* kf, hipStream_t s);
 hipError_t launch_ctl_reset(Ctl* ctl, int logmode, hipStream_t s);

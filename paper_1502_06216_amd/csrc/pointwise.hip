@@ -57,6 +57,12 @@ __global__ void k_fill(float* x, float v, int64_t n) {
         x[i] = v;
 }
 
+__global__ void k_copy_scaled(float* __restrict__ d, const float* __restrict__ s, double f, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        d[i] = (float)((double)s[i] * f);
+}
+
 __global__ void k_copy(float* __restrict__ d, const float* __restrict__ s, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
@@ -83,6 +89,26 @@ __global__ void k_prepare(int kind, const float* w, const float* coef, float coe
             const double mm = (double)m;
             kf[i] = (float)log(sigma * c * mm * pow((double)D, mm - 1.0));
         }
+    }
+}
+
+// Proximal half-step of the Wasserstein attraction (eq. prox-psi-attraction,
+// h = iota_[0,kappa]) on the two stacked couplings: s = (s_1, s_2),
+// p = min(s_1^alpha s_2^{1-alpha}, kappa) with alpha = 1/(1+tau), a_m = p / s_m
+// (0/0 = 0).  Nothing is written once the step has stopped.
+__global__ void k_attraction_prox(const float* __restrict__ s, float* __restrict__ a, float* __restrict__ p,
+                                  const float* __restrict__ kappa, float kappa_s, float alpha, int64_t N,
+                                  const Ctl* ctl) {
+    if (ctl && ctl->done) return;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float s1 = s[i], s2 = s[N + i];
+        const float k = kappa ? kappa[i] : kappa_s;
+        const float g = (s1 > 0.f && s2 > 0.f) ? expf(alpha * logf(s1) + (1.f - alpha) * logf(s2)) : 0.f;
+        const float pv = fminf(g, k);
+        p[i] = pv;
+        a[i] = pv == 0.f ? 0.f : pv / s1;
+        a[N + i] = pv == 0.f ? 0.f : pv / s2;
     }
 }
 
@@ -235,6 +261,11 @@ hipError_t launch_fill(float* x, float v, int64_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_copy_scaled(float* dst, const float* src, double f, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy_scaled, dim3(blocks_for(n, 1024)), dim3(256), 0, s, dst, src, f, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_copy(float* dst, const float* src, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_copy, dim3(blocks_for(n, 1024)), dim3(256), 0, s, dst, src, n);
     return hipGetLastError();
@@ -246,6 +277,13 @@ hipError_t launch_prepare_energy(const jko_energy* en, double sigma, int64_t N, 
     const int kind = en->kind == JKO_F_CONGESTION_BINARY ? JKO_F_CONGESTION : en->kind;
     hipLaunchKernelGGL(k_prepare, dim3(blocks_for(N, 1024)), dim3(256), 0, s, kind, en->w, en->coef,
                        en->coef_scalar, en->m, en->m_field, en->density_scale, sigma, N, g, kf);
+    return hipGetLastError();
+}
+
+hipError_t launch_attraction_prox(const float* s, float* a, float* p, const float* kappa, float kappa_s,
+                                  double alpha, int64_t N, const Ctl* ctl, hipStream_t st) {
+    hipLaunchKernelGGL(k_attraction_prox, dim3(blocks_for(N, 1024)), dim3(256), 0, st, s, a, p, kappa, kappa_s,
+                       (float)alpha, N, ctl);
     return hipGetLastError();
 }
 

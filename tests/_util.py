@@ -26,7 +26,7 @@ def energies(wl):
     r = lambda a: None if a is None else f32(a).astype(np.float64)
     g = jk.EnergySpec(kind=wl.kind, w=dev(wl.w), kappa=dev(wl.kappa), kappa_scalar=float(np.float32(wl.kappa_scalar)),
                       coef=dev(wl.coef), coef_scalar=wl.coef_scalar, m=wl.m, density_scale=wl.density_scale,
-                      m_field=dev(wl.m_field))
+                      m_field=dev(wl.m_field), target=dev(wl.target))
     o = O.Energy(kind=wl.kind, w=r(wl.w), kappa=r(wl.kappa), kappa_scalar=float(np.float32(wl.kappa_scalar)),
                  coef=r(wl.coef), coef_scalar=wl.coef_scalar, m=wl.m, density_scale=wl.density_scale,
                  m_field=r(wl.m_field))

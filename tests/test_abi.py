@@ -41,7 +41,7 @@ def test_every_declared_symbol_is_exported(lib):
 def test_struct_layouts_match_header():
     # sizes implied by include/jko.h on x86-64
     assert ctypes.sizeof(nat.Grid) == 16
-    assert ctypes.sizeof(nat.EnergyC) == 64
+    assert ctypes.sizeof(nat.EnergyC) == 72
     assert ctypes.sizeof(nat.Params) == 48
     assert ctypes.sizeof(nat.Stats) == 48
 
@@ -65,6 +65,11 @@ def test_workspace_bytes(lib):
     assert bwd >= 2 * 300 * 64 * 64 * 4
     assert jk.workspace_bytes((2000,), jk.OP_STEP, 0, p) == 0       # n > 1024
     assert jk.workspace_bytes((4, 4, 4, 4)[:3], 7, 0, p) == 0       # bad op
+    # attraction: the stacked pair of couplings needs twice the fields; 1D/2D only
+    att = jk.workspace_bytes((64, 64), nat.OP_ATTRACTION_STEP, 0, p)
+    assert att > jk.workspace_bytes((64, 64), jk.OP_STEP, 0, p)
+    assert jk.workspace_bytes((64, 64), nat.OP_ATTRACTION_FLOW, 4, p) > att
+    assert jk.workspace_bytes((8, 8, 8), nat.OP_ATTRACTION_STEP, 0, p) == 0
 
 
 def _call_step(lib, grid, energy, params, p_in=1, p_out=2, ws=16, nbytes=1 << 30):
@@ -108,6 +113,16 @@ def test_argument_errors_before_any_launch(lib):
     e5 = jk.EnergySpec(kind="binary_congestion", kappa_scalar=math.inf).to_c((8, 8))
     assert _call_step(lib, g, e5, prm) == jk.JKO_ERR_INVALID
     assert b"finite" in lib.jko_last_error()
+    # attraction: a target, 1D/2D grids of at least 3 cells per axis, plain domain
+    e7 = jk.EnergySpec(kind="attraction", kappa_scalar=1.0).to_c((8, 8))
+    assert _call_step(lib, g, e7, prm) == jk.JKO_ERR_INVALID
+    assert b"target" in lib.jko_last_error()
+    e7.target = ctypes.c_void_p(8)
+    for grid_shape in ((8, 8, 8), (2, 8)):
+        assert _call_step(lib, nat.make_grid(grid_shape), e7, prm) == jk.JKO_ERR_INVALID, grid_shape
+    p_log = nat.make_params(1e-3, 1e-3, 10, absorb_threshold=50.0)
+    assert _call_step(lib, g, e7, p_log) == jk.JKO_ERR_INVALID
+    assert b"plain domain" in lib.jko_last_error()
     # generalised entropy: exponent >= 1, positive density scale
     for kw in ({"m": 0.5}, {"m": math.nan}, {"m": 1.5, "density_scale": 0.0}, {"m": 1.5, "coef_scalar": -1.0}):
         e6 = jk.EnergySpec(kind="gen_entropy", **kw).to_c((8, 8))

@@ -1,0 +1,124 @@
+"""Wasserstein attraction with congestion (Section 5.2, two couplings) on the
+HIP path against the FP64 oracle, through the C ABI.
+
+The device stacks the two couplings' scalings as one field of shape
+(2, n...) and runs the reduced scaling of Proposition 5.2 (marginals first,
+corrections dropped), which the oracle pins against the verbatim iteration.
+Tolerances (rel-L1 of the density): 1e-5 for FP32, 1e-4 for split-BF16.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_1502_06216_amd as jk
+from workloads import gaussian_bumps, make_workload, small_case
+
+from _util import banner, dev, energies, f32, host64, rel_l1
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-5, "split_bf16": 1e-4}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    jk.load()
+
+
+def _case(shape, seed=5):
+    wl = small_case(shape, "congestion", seed=seed)
+    wl.kind = "attraction"
+    wl.w = None
+    d = len(shape)
+    r = gaussian_bumps(shape, [tuple([0.25] * d), tuple([0.7] + [0.3] * (d - 1))], 0.1, [0.5, 0.5])
+    # the same mass as the float32 density the device receives
+    r32 = f32(r).astype(np.float64)
+    wl.target = r32 * (f32(wl.p0).astype(np.float64).sum() / r32.sum())
+    return wl
+
+
+def _oracle(wl, steps, iters, tol=0.0, check_every=1):
+    r = f32(wl.target).astype(np.float64)
+    kappa = f32(wl.kappa_field()).astype(np.float64)
+    q = f32(wl.p0).astype(np.float64)
+    for _ in range(steps):
+        q, st = O.attraction_step(q, r, kappa, wl.gamma, wl.tau, iters, tol=tol, check_every=check_every)
+    return q, st
+
+
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("shape", [(48, 40), (100,), (33, 29)])
+def test_flow_matches_oracle(shape, precision):
+    banner(f"attraction {shape} {precision}")
+    wl = _case(shape)
+    g_en, _ = energies(wl)
+    pT, stats, ck = jk.flow(dev(wl.p0), g_en, wl.gamma, wl.tau, 2, max_iters=30, precision=precision,
+                            checkpoints=True)
+    ref, rst = _oracle(wl, 2, 30)
+    err = rel_l1(host64(pT), ref)
+    print(f"[gpu-test] attraction {shape} {precision}: rel-L1 {err:.2e}, marginal {stats[-1]['marginal_l1']:.3e} "
+          f"vs {rst['marginal_l1']:.3e}", flush=True)
+    assert err <= TOL[precision]
+    assert (host64(pT) <= f32(wl.kappa_field()) + 0).all()
+    assert stats[-1]["marginal_l1"] == pytest.approx(rst["marginal_l1"], rel=0.05, abs=3e-6)
+    assert stats[-1]["mass"] == pytest.approx(float(host64(pT).sum()), rel=1e-5)
+
+
+def test_attraction_to_its_own_density_is_one_blur():
+    """r = q without capacity: every iteration returns the blur xi (q / xi^T 1)."""
+    banner("attraction r = q")
+    wl = _case((48, 40))
+    wl.target = f32(wl.p0).astype(np.float64)
+    wl.kappa = None
+    wl.kappa_scalar = float("inf")
+    g_en, _ = energies(wl)
+    p, _ = jk.step(dev(wl.p0), g_en, wl.gamma, wl.tau, max_iters=5, tol=0.0)
+    q = f32(wl.p0).astype(np.float64)
+    ref = O.gibbs_apply(q / O.gibbs_apply(np.ones_like(q), wl.gamma, transpose=True), wl.gamma)
+    assert rel_l1(host64(p), ref) <= 1e-6
+
+
+def test_tolerance_mode_stops_like_the_oracle():
+    banner("attraction tolerance mode")
+    wl = _case((48, 40))
+    g_en, _ = energies(wl)
+    tol, ce = 1e-6, 10
+    p, st = jk.step(dev(wl.p0), g_en, wl.gamma, wl.tau, max_iters=3000, tol=tol, check_every=ce)
+    ref, ost = _oracle(wl, 1, 3000, tol=tol, check_every=ce)
+    print(f"[gpu-test] attraction tolerance: device {st['iters']} iterations, oracle {ost['iters']}", flush=True)
+    assert st["stop"] == "tol" and ost["stop"] == "tol"
+    assert st["iters"] % ce == 0 and abs(st["iters"] - ost["iters"]) <= ce
+    assert st["marginal_l1"] <= tol
+    same, _ = _oracle(wl, 1, st["iters"])
+    assert rel_l1(host64(p), same) <= TOL["fp32"]
+
+
+def test_target_is_a_shape_and_bad_inputs_are_refused():
+    """The target is scaled to the density's mass (a target of twice the mass
+    gives the same step), and the log domain is refused."""
+    banner("attraction target scale, errors")
+    wl = _case((48, 40))
+    g_en, _ = energies(wl)
+    p1, _ = jk.step(dev(wl.p0), g_en, wl.gamma, wl.tau, max_iters=20)
+    twice = jk.EnergySpec(kind="attraction", kappa=g_en.kappa, target=g_en.target * 2.0)
+    p2, _ = jk.step(dev(wl.p0), twice, wl.gamma, wl.tau, max_iters=20)
+    assert rel_l1(host64(p2), host64(p1)) <= 1e-6
+    with pytest.raises(jk.JKOError) as e:
+        jk.step(dev(wl.p0), g_en, wl.gamma, wl.tau, max_iters=5, absorb_threshold=0.0)
+    assert e.value.status == jk.JKO_ERR_INVALID
+
+
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+def test_crowd256_attraction_one_step_full_size(precision):
+    """The benchmarked configuration (256^2, capacity with obstacles) for one
+    step of 300 iterations against the oracle."""
+    banner(f"crowd256_attraction one step {precision}")
+    wl = make_workload("crowd256_attraction")
+    g_en, _ = energies(wl)
+    p, st = jk.step(dev(wl.p0), g_en, wl.gamma, wl.tau, max_iters=wl.max_iters, tol=0.0, precision=precision)
+    ref, rst = _oracle(wl, 1, wl.max_iters)
+    err = rel_l1(host64(p), ref)
+    print(f"[gpu-test] crowd256_attraction {precision}: rel-L1 {err:.2e}", flush=True)
+    assert err <= TOL[precision]

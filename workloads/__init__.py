@@ -27,6 +27,14 @@ Workloads (synthetic stand-ins for the paper's figures, which print no data):
                    centre, as in the paper's second nonlinear-diffusion
                    example), density units, the porous512 initial density,
                    3 steps of 300 iterations.
+* ``crowd256_attraction`` -- the ``crowd256`` obstacles, capacity and bump
+                   recipe under the Wasserstein attraction of Section 5.2, at
+                   gamma = 1e-3, tau = 1e-2: the target r is p0 translated by
+                   0.1 along the first axis (26 cells, the wrapped band set to
+                   0), of the same mass; 3 steps of 300 iterations.  (The
+                   second coupling carries every cell to its target in one hop:
+                   its kernel entries stay representable in float32 while
+                   displacement^2 / gamma stays well under 87.)
 * ``crowd256_binary`` -- ``crowd256`` under the non-convex binary constraint
                    {0, kappa} (Section 4.5): potential scaled to sigma w <= 1/2
                    (above 1 the binary prox empties every cell), initial density
@@ -116,7 +124,8 @@ class Workload:
     shape: tuple
     gamma: float
     tau: float
-    kind: str                    # "congestion" | "binary_congestion" | "porous" | "entropy" | "gen_entropy" | "zero"
+    kind: str                    # "congestion" | "binary_congestion" | "porous" | "entropy" | "gen_entropy" |
+                                 # "attraction" | "zero"
     p0: np.ndarray
     w: Optional[np.ndarray] = None         # congestion potential (None = 0)
     kappa: Optional[np.ndarray] = None     # capacity field (None = kappa_scalar)
@@ -126,6 +135,7 @@ class Workload:
     m: float = 2.0
     density_scale: float = 1.0
     m_field: Optional[np.ndarray] = None   # gen_entropy exponents per cell (None = m)
+    target: Optional[np.ndarray] = None    # attraction target density r
     n_steps: int = 1
     max_iters: int = 300
     tol: float = 0.0                       # 0 = fixed iteration count
@@ -240,6 +250,14 @@ def make_workload(name: str, seed: int = 0, projected: bool = True, **over) -> W
         wl.coef = None
         wl.coef_scalar = 1.0
         wl.m_field = 1.0 + np.sin(np.pi * X[0]) * np.sin(np.pi * X[1])
+    elif name == "crowd256_attraction":
+        wl = _crowd(name, (256, 256), 1e-3, 1e-2, 8, 6, ([0.1, 0.1], [0.9, 0.9]),
+                    (0.9, 0.5), 1.2, seed, projected, 3, 300, 0.0)
+        wl.kind = "attraction"
+        wl.w = None
+        r = np.roll(wl.p0, -26, axis=0)
+        r[-26:, :] = 0.0
+        wl.target = r * (wl.p0.sum() / r.sum())
     elif name == "crowd256_binary":
         wl = _crowd(name, (256, 256), 2e-4, 2e-3, 8, 6, ([0.1, 0.1], [0.9, 0.9]),
                     (0.9, 0.5), 1.2, seed, projected, 3, 300, 0.0)
@@ -256,7 +274,8 @@ def make_workload(name: str, seed: int = 0, projected: bool = True, **over) -> W
     return wl
 
 
-WORKLOADS = ("crowd32", "crowd256", "crowd256_fixed", "crowd256_binary", "porous512", "porous512_scaled", "gen512",
+WORKLOADS = ("crowd32", "crowd256", "crowd256_fixed", "crowd256_binary", "crowd256_attraction", "porous512",
+             "porous512_scaled", "gen512",
              "crowd128c")
 
 
