@@ -10,5 +10,5 @@ from .jko_oracle import (  # noqa: F401
     log_prox_gen_entropy,
     prox_porous,
     lambertw_of_log, dykstra_coupling, dykstra_scaling, jko_step, jko_step_log, jko_flow,
-    prox_attraction_psi1, attraction_generic, attraction_step,
+    prox_attraction_psi1, attraction_generic, attraction_step, attraction_step_log,
 )

@@ -519,6 +519,40 @@ def attraction_step(q, r, kappa, gamma, tau, max_iters, tol=0.0, check_every=1, 
     return p, dict(iters=max_iters, marginal_l1=violation(t), mass=float(p.sum()), stop="cap")
 
 
+def attraction_step_log(q, r, kappa, gamma, tau, max_iters, tol=0.0, check_every=1):
+    """``attraction_step`` with log a_m, log b_m, log t_m, log s_m and the Gibbs
+    products as exact log-sum-exp (``log_gibbs_apply``); the proximal step is
+    log p = min(log s_1 / (1+tau) + tau log s_2 / (1+tau), log kappa).  Same
+    stopping rule and return values; exact zeros are -inf."""
+    r = r * (q.sum() / r.sum())
+    targets = (q, r)
+    with np.errstate(divide="ignore"):
+        logt = (np.log(q), np.log(r))
+        lk = np.log(np.broadcast_to(np.asarray(kappa, np.float64), q.shape))
+    alpha = 1.0 / (1.0 + tau)
+    La = [np.zeros_like(q), np.zeros_like(q)]
+    Lb = None
+    Lp = None
+
+    def violation(Lt):
+        return float(sum(np.abs(np.exp(Lb[m] + Lt[m]) - targets[m]).sum() for m in range(2)))
+
+    for k in range(1, max_iters + 1):
+        Lt = [log_gibbs_apply(La[m], gamma) for m in range(2)]
+        if k > 1 and tol > 0 and (k - 1) % check_every == 0:
+            err = violation(Lt)
+            if err <= tol:
+                p = np.exp(Lp)
+                return p, dict(iters=k - 1, marginal_l1=err, mass=float(p.sum()), stop="tol")
+        Lb = [logt[m] - Lt[m] for m in range(2)]
+        Ls = [log_gibbs_apply(Lb[m], gamma) for m in range(2)]
+        Lp = np.minimum(alpha * Ls[0] + (1.0 - alpha) * Ls[1], lk)
+        La = [np.where(np.isneginf(Lp), -np.inf, Lp - Ls[m]) for m in range(2)]
+    Lt = [log_gibbs_apply(La[m], gamma) for m in range(2)]
+    p = np.exp(Lp)
+    return p, dict(iters=max_iters, marginal_l1=violation(Lt), mass=float(p.sum()), stop="cap")
+
+
 def jko_step_log(q: np.ndarray, en: Energy, gamma: float, tau: float, max_iters: int,
                  tol: float = 0.0, check_every: int = 1):
     """``jko_step`` with log a, log b, log t, log s instead of a, b, t, s and the

@@ -686,6 +686,7 @@ jko_status mass_of(const Plan& P, const float* p, int64_t N, double* out) {
 // target is scaled by rscale to the mass of q (both couplings need one mass).
 jko_status run_attraction(const Plan& P, const jko_params* pr, const jko_energy* en, const float* q, float* p_out,
                           int64_t N, double rscale, bool want_stats, jko_stats* st_out) {
+    const bool logmode = pr->absorb_threshold <= 0.0;   // log domain from the first iteration
     const int K = pr->max_iters;
     const int ce = pr->check_every;
     const bool tolmode = pr->tol_l1 > 0.0;
@@ -695,8 +696,8 @@ jko_status run_attraction(const Plan& P, const jko_params* pr, const jko_energy*
     float* qs = P.F(F_KF);   // q, r
     HIP_TRY(launch_copy(qs, q, N, P.st));
     HIP_TRY(launch_copy_scaled(qs + N, en->target, rscale, N, P.st));   // r at the mass of q
-    HIP_TRY(launch_fill(a, 1.f, 2 * N, P.st));
-    HIP_TRY(launch_ctl_reset(P.ctl, 0, P.st));
+    HIP_TRY(launch_fill(a, logmode ? 0.f : 1.f, 2 * N, P.st));
+    HIP_TRY(launch_ctl_reset(P.ctl, logmode ? 1 : 0, P.st));
     EpiArgs eb{};
     eb.kind = EpiKind::BUPDATE;
     eb.q = qs;
@@ -754,7 +755,7 @@ jko_status run_attraction(const Plan& P, const jko_params* pr, const jko_energy*
         jko_stats& o = *st_out;
         const bool bytol = tolmode && c.done && !c.nonfinite;
         o.iters = bytol ? c.stop_iter : K;
-        o.absorptions = 0;
+        o.absorptions = logmode ? 1 : 0;
         o.stop_reason = bytol ? JKO_STOP_TOL : JKO_STOP_CAP;
         o.status = c.nonfinite ? JKO_ERR_NONFINITE : JKO_OK;
         o.marginal_l1 = c.err;
@@ -773,8 +774,9 @@ jko_status attraction_flow(const Geo& g, const jko_energy* en, const jko_params*
     if (g.d > 2) return fail(JKO_ERR_INVALID, "attraction: 1D and 2D grids only");
     for (int k = 0; k < g.d; ++k)
         if (g.n[k] < 3) return fail(JKO_ERR_INVALID, "attraction: every axis needs at least 3 cells");
-    if (!(isnan(pr->absorb_threshold) || pr->absorb_threshold == INFINITY))
-        return fail(JKO_ERR_INVALID, "attraction runs in the plain domain: absorb_threshold must be +inf or NaN");
+    if (!(isnan(pr->absorb_threshold) || pr->absorb_threshold == INFINITY || pr->absorb_threshold <= 0.0))
+        return fail(JKO_ERR_INVALID,
+                    "attraction: absorb_threshold must be <= 0 (log domain throughout) or +inf / NaN (plain domain)");
     Plan P;
     jko_status s = carve(&P, stacked_of(g), flow ? OP_FLOW : OP_STEP, n_steps, ws, ws_bytes, pr->precision, st);
     if (s) return s;

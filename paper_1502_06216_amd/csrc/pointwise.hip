@@ -95,15 +95,25 @@ __global__ void k_prepare(int kind, const float* w, const float* coef, float coe
 // Proximal half-step of the Wasserstein attraction (eq. prox-psi-attraction,
 // h = iota_[0,kappa]) on the two stacked couplings: s = (s_1, s_2),
 // p = min(s_1^alpha s_2^{1-alpha}, kappa) with alpha = 1/(1+tau), a_m = p / s_m
-// (0/0 = 0).  Nothing is written once the step has stopped.
+// (0/0 = 0).  Log domain (ctl->logmode): s and a hold logs,
+// log p = min(alpha log s_1 + (1-alpha) log s_2, log kappa), log a_m = log p - log s_m.
+// Nothing is written once the step has stopped.
 __global__ void k_attraction_prox(const float* __restrict__ s, float* __restrict__ a, float* __restrict__ p,
                                   const float* __restrict__ kappa, float kappa_s, float alpha, int64_t N,
                                   const Ctl* ctl) {
     if (ctl && ctl->done) return;
+    const bool logx = ctl && ctl->logmode;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
          i += (int64_t)gridDim.x * blockDim.x) {
         const float s1 = s[i], s2 = s[N + i];
         const float k = kappa ? kappa[i] : kappa_s;
+        if (logx) {
+            const float lp = fminf(alpha * s1 + (1.f - alpha) * s2, logf(k));
+            p[i] = expf(lp);
+            a[i] = lp == -INFINITY ? -INFINITY : lp - s1;
+            a[N + i] = lp == -INFINITY ? -INFINITY : lp - s2;
+            continue;
+        }
         const float g = (s1 > 0.f && s2 > 0.f) ? expf(alpha * logf(s1) + (1.f - alpha) * logf(s2)) : 0.f;
         const float pv = fminf(g, k);
         p[i] = pv;

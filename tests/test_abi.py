@@ -120,8 +120,8 @@ def test_argument_errors_before_any_launch(lib):
     e7.target = ctypes.c_void_p(8)
     for grid_shape in ((8, 8, 8), (2, 8)):
         assert _call_step(lib, nat.make_grid(grid_shape), e7, prm) == jk.JKO_ERR_INVALID, grid_shape
-    p_log = nat.make_params(1e-3, 1e-3, 10, absorb_threshold=50.0)
-    assert _call_step(lib, g, e7, p_log) == jk.JKO_ERR_INVALID
+    p_switch = nat.make_params(1e-3, 1e-3, 10, absorb_threshold=50.0)   # no switch between domains
+    assert _call_step(lib, g, e7, p_switch) == jk.JKO_ERR_INVALID
     assert b"plain domain" in lib.jko_last_error()
     # generalised entropy: exponent >= 1, positive density scale
     for kw in ({"m": 0.5}, {"m": math.nan}, {"m": 1.5, "density_scale": 0.0}, {"m": 1.5, "coef_scalar": -1.0}):

@@ -370,6 +370,17 @@ def test_attraction_prox_minimises(p1, p2, tau, kappa):
     assert got == pytest.approx(ref, rel=2e-6)
 
 
+def test_attraction_log_form_matches_plain_where_both_finite():
+    """The log form of the attraction step (exact log-sum-exp products) takes
+    the plain form's iterates where both are finite."""
+    q, r = _attraction_case(16, shape=(12, 10))
+    kappa = 1.3 * q.max()
+    p1, s1 = O.attraction_step(q, r, kappa, 0.02, 0.2, 40)
+    p2, s2 = O.attraction_step_log(q, r, kappa, 0.02, 0.2, 40)
+    np.testing.assert_allclose(p2, p1, rtol=1e-10, atol=1e-300)
+    assert s2["marginal_l1"] == pytest.approx(s1["marginal_l1"], rel=1e-8)
+
+
 def test_attraction_to_its_own_density_is_one_blur():
     """r = q without capacity: f = W(q, .) makes the step the minimiser of
     (1 + tau) W_gamma(q, p), the blur xi (q / xi^T 1) of the conclusion."""
