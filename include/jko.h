@@ -103,9 +103,9 @@ typedef enum { JKO_FP32 = 0, JKO_SPLIT_BF16 = 1 } jko_precision;
  *                    scaling of Proposition 5.2 (marginals first; the proximal
  *                    half-step is eq. prox-psi-attraction).  The workspace is
  *                    sized by JKO_OP_ATTRACTION_STEP / _FLOW.  1D and 2D grids
- *                    with every axis >= 3; absorb_threshold <= 0 runs the log
- *                    domain throughout, +inf or NaN the plain domain (no switch
- *                    in between); no resident kernel, no backward. */
+ *                    with every axis >= 3; absorption as for the other
+ *                    energies, the switch triggered by max|log b| alone; no
+ *                    resident kernel, no backward. */
 typedef enum {
     JKO_F_ZERO = 0,
     JKO_F_CONGESTION = 1,

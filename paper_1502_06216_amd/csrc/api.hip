@@ -686,10 +686,17 @@ jko_status mass_of(const Plan& P, const float* p, int64_t N, double* out) {
 // target is scaled by rscale to the mass of q (both couplings need one mass).
 jko_status run_attraction(const Plan& P, const jko_params* pr, const jko_energy* en, const float* q, float* p_out,
                           int64_t N, double rscale, bool want_stats, jko_stats* st_out) {
-    const bool logmode = pr->absorb_threshold <= 0.0;   // log domain from the first iteration
+    // Absorption as in run_step: <= 0 runs the log domain from the start, +inf
+    // (or NaN) never switches, otherwise the check that sees max|log b| above
+    // the threshold switches a and b to logs after that iteration's proximal
+    // half-step (max|log a| is not monitored here).
+    const double thr = pr->absorb_threshold;
+    const bool logmode = thr <= 0.0;
+    const double absorb = (logmode || !(thr < INFINITY)) ? 0.0 : thr;
     const int K = pr->max_iters;
     const int ce = pr->check_every;
     const bool tolmode = pr->tol_l1 > 0.0;
+    const bool checks = tolmode || absorb > 0.0;
     float* a = P.F(F_A);
     float* b = P.F(F_B);
     float* sv = P.F(F_G);    // s_1, s_2
@@ -713,11 +720,11 @@ jko_status run_attraction(const Plan& P, const jko_params* pr, const jko_energy*
     bool pending = false, stopped = false;
     int nb = 0;
     for (int k = 1; k <= K; ++k) {
-        eb.check = (tolmode && k > 1 && (k - 1) % ce == 0) ? 1 : 0;
+        eb.check = (checks && k > 1 && (k - 1) % ce == 0) ? 1 : 0;
         jko_status s = apply_xi(P, a, eb, &nb);
         if (s) return s;
-        if (eb.check) {
-            HIP_TRY(launch_ctl_check(P.ctl, P.part, nb, k, pr->tol_l1, 0, 0.0, P.st));
+        if (eb.check) HIP_TRY(launch_ctl_check(P.ctl, P.part, nb, k, pr->tol_l1, 0, absorb, P.st));
+        if (eb.check && tolmode) {
             if (pending) {
                 HIP_TRY(hipEventSynchronize(g_rb.ev));
                 if (g_rb.host->done) stopped = true;
@@ -729,6 +736,10 @@ jko_status run_attraction(const Plan& P, const jko_params* pr, const jko_energy*
         }
         if ((s = apply_xi(P, b, es, &nb))) return s;
         HIP_TRY(launch_attraction_prox(sv, a, p_out, en->kappa, en->kappa_scalar, alpha, N, P.ctl, P.st));
+        if (eb.check && absorb > 0.0) {   // a switch decided at this iteration's check takes effect now
+            HIP_TRY(launch_absorb(P.ctl, a, b, 2 * N, P.st));
+            HIP_TRY(launch_ctl_commit(P.ctl, P.st));
+        }
     }
     Ctl c{};
     if (tolmode || want_stats) {
@@ -755,7 +766,7 @@ jko_status run_attraction(const Plan& P, const jko_params* pr, const jko_energy*
         jko_stats& o = *st_out;
         const bool bytol = tolmode && c.done && !c.nonfinite;
         o.iters = bytol ? c.stop_iter : K;
-        o.absorptions = logmode ? 1 : 0;
+        o.absorptions = c.absorptions;
         o.stop_reason = bytol ? JKO_STOP_TOL : JKO_STOP_CAP;
         o.status = c.nonfinite ? JKO_ERR_NONFINITE : JKO_OK;
         o.marginal_l1 = c.err;
@@ -774,9 +785,6 @@ jko_status attraction_flow(const Geo& g, const jko_energy* en, const jko_params*
     if (g.d > 2) return fail(JKO_ERR_INVALID, "attraction: 1D and 2D grids only");
     for (int k = 0; k < g.d; ++k)
         if (g.n[k] < 3) return fail(JKO_ERR_INVALID, "attraction: every axis needs at least 3 cells");
-    if (!(isnan(pr->absorb_threshold) || pr->absorb_threshold == INFINITY || pr->absorb_threshold <= 0.0))
-        return fail(JKO_ERR_INVALID,
-                    "attraction: absorb_threshold must be <= 0 (log domain throughout) or +inf / NaN (plain domain)");
     Plan P;
     jko_status s = carve(&P, stacked_of(g), flow ? OP_FLOW : OP_STEP, n_steps, ws, ws_bytes, pr->precision, st);
     if (s) return s;

@@ -113,16 +113,13 @@ def test_argument_errors_before_any_launch(lib):
     e5 = jk.EnergySpec(kind="binary_congestion", kappa_scalar=math.inf).to_c((8, 8))
     assert _call_step(lib, g, e5, prm) == jk.JKO_ERR_INVALID
     assert b"finite" in lib.jko_last_error()
-    # attraction: a target, 1D/2D grids of at least 3 cells per axis, plain domain
+    # attraction: a target, 1D/2D grids of at least 3 cells per axis
     e7 = jk.EnergySpec(kind="attraction", kappa_scalar=1.0).to_c((8, 8))
     assert _call_step(lib, g, e7, prm) == jk.JKO_ERR_INVALID
     assert b"target" in lib.jko_last_error()
     e7.target = ctypes.c_void_p(8)
     for grid_shape in ((8, 8, 8), (2, 8)):
         assert _call_step(lib, nat.make_grid(grid_shape), e7, prm) == jk.JKO_ERR_INVALID, grid_shape
-    p_switch = nat.make_params(1e-3, 1e-3, 10, absorb_threshold=50.0)   # no switch between domains
-    assert _call_step(lib, g, e7, p_switch) == jk.JKO_ERR_INVALID
-    assert b"plain domain" in lib.jko_last_error()
     # generalised entropy: exponent >= 1, positive density scale
     for kw in ({"m": 0.5}, {"m": math.nan}, {"m": 1.5, "density_scale": 0.0}, {"m": 1.5, "coef_scalar": -1.0}):
         e6 = jk.EnergySpec(kind="gen_entropy", **kw).to_c((8, 8))
