@@ -16,7 +16,8 @@
  *     b = q / (xi^T a);  s = xi b;  p = Prox^KL_{(tau/gamma) f}(s);  a = p / s
  * with q = p_t, a cold-started at 1 at every step (Listing 1, step 2), and the
  * stopping test of Listing 1 on || b * xi^T a - q ||_1 after an even
- * half-step.  xi is applied as per-axis dense contractions with the factor
+ * half-step (JKO_F_ATTRACTION keeps two such couplings, described with the
+ * energies).  xi is applied as per-axis dense contractions with the factor
  * K1[i][j] = exp(-(x_i - x_j)^2 / gamma) (the separable Gaussian kernel of
  * Section 4.1), exactly (no truncation, no boundary condition).
  *
@@ -56,7 +57,8 @@ typedef enum {
     JKO_ERR_WORKSPACE = -2,   /* workspace missing or smaller than required */
     JKO_ERR_HIP = -3,         /* a HIP runtime call failed (see jko_last_error) */
     JKO_ERR_NONFINITE = -4,   /* NaN/inf met by the FP64 monitor; outputs are still written */
-    JKO_ERR_INFEASIBLE = -5   /* congestion (either kind) capacity sum(kappa) < sum(p_t) */
+    JKO_ERR_INFEASIBLE = -5   /* capacity sum(kappa) < sum(p_t) (congestion, binary congestion,
+                                 attraction) */
 } jko_status;
 
 /* Arithmetic of the Gibbs contractions.  Accumulation is float32 in both;
@@ -123,8 +125,9 @@ typedef struct {
 
 typedef struct {
     int32_t kind;            /* jko_energy_kind */
-    const float* w;          /* congestion potential, N cells, device; NULL = 0 */
-    const float* kappa;      /* congestion capacity, N cells, device; NULL = kappa_scalar */
+    const float* w;          /* congestion / binary congestion potential, N cells, device; NULL = 0 */
+    const float* kappa;      /* capacity (congestion, binary congestion, attraction), N cells,
+                                device; NULL = kappa_scalar */
     float kappa_scalar;      /* used when kappa == NULL; may be +inf */
     const float* coef;       /* porous / entropy / gen. entropy weight, N cells, device; NULL = coef_scalar */
     float coef_scalar;
@@ -169,9 +172,11 @@ typedef struct {
     int32_t absorptions;     /* number of log-domain absorptions performed */
     int32_t stop_reason;     /* jko_stop_reason */
     int32_t status;          /* jko_status of this step */
-    double marginal_l1;      /* ||b * xi^T a - q||_1 of the returned iterate (FP64 sum) */
+    double marginal_l1;      /* ||b * xi^T a - q||_1 of the returned iterate (FP64 sum;
+                                attraction: summed over both couplings) */
     double mass;             /* sum of the returned p (FP64 sum) */
-    double max_abs_log_a;    /* max |log a| over cells with a > 0, last check */
+    double max_abs_log_a;    /* max |log a| over cells with a > 0, last check (0 for the
+                                attraction, which does not monitor it) */
     double max_abs_log_b;    /* max |log b| over cells with b > 0, last check */
 } jko_stats;
 
@@ -226,8 +231,8 @@ jko_status jko_flow(const jko_grid* grid, const jko_energy* energy, const jko_pa
  * intermediate Gibbs products are kept in the workspace, then swept in
  * reverse.  The derivative is that of the map at the given iteration counts
  * (tol_l1 is ignored).  Energies: ZERO, CONGESTION, ENTROPY, POROUS,
- * GEN_ENTROPY (dL/dp0 only for ENTROPY and POROUS); CONGESTION_BINARY is
- * refused. */
+ * GEN_ENTROPY (dL/dp0 only for ENTROPY and POROUS); CONGESTION_BINARY and
+ * ATTRACTION are refused. */
 jko_status jko_backward(const jko_grid* grid, const jko_energy* energy, const jko_params* params,
                         int32_t n_steps, const int32_t* iters_per_step, const float* checkpoints,
                         const float* dL_dpT, float* dL_dw, float* dL_dp0,
@@ -244,7 +249,7 @@ jko_status jko_backward(const jko_grid* grid, const jko_energy* energy, const jk
  * ms_per_launch (host, room for 2*ndim doubles) receives the mean duration of
  * one launch of each, in launch order; *n_launches (host, nullable) their
  * number.  The scalings are set to 1 first; p_in is not modified.
- * Synchronous. */
+ * Synchronous.  JKO_F_ATTRACTION is refused. */
 jko_status jko_time_iteration(const jko_grid* grid, const jko_energy* energy, const jko_params* params,
                               const float* p_in, int32_t reps, double* ms_per_launch, int32_t* n_launches,
                               void* workspace, size_t workspace_bytes, void* stream);
