@@ -12,3 +12,4 @@ from .jko_oracle import (  # noqa: F401
     lambertw_of_log, dykstra_coupling, dykstra_scaling, jko_step, jko_step_log, jko_flow,
     prox_attraction_psi1, attraction_generic, attraction_step, attraction_step_log,
 )
+from .heat_oracle import HeatKernel, heat_nu, heat_system  # noqa: F401,E402

@@ -403,7 +403,7 @@ def dykstra_scaling(q: np.ndarray, en: Energy, gamma: float, tau: float,
 
 
 def jko_step(q: np.ndarray, en: Energy, gamma: float, tau: float, max_iters: int,
-             tol: float = 0.0, check_every: int = 1, mode: str = "separable"):
+             tol: float = 0.0, check_every: int = 1, mode: str = "separable", op=None):
     """One JKO step: the reduced scaling iteration (Proposition 3.3 with the
     u, v corrections dropped) and the stopping test of Listing 1.
 
@@ -417,23 +417,30 @@ def jko_step(q: np.ndarray, en: Energy, gamma: float, tau: float, max_iters: int
     Returns (p, stats) with stats = {iters, marginal_l1, mass, stop}; the
     reported marginal_l1 is the violation of the returned iterate.
     Conventions: 0 / 0 = 0 in both divisions.
+
+    ``op`` (optional) replaces the Gibbs kernel by another symmetric operator
+    called as op(x): the heat kernel of Section 4.1 (``HeatKernel``).
     """
     sigma = tau / gamma
+
+    def K(x, transpose=False):
+        return gibbs_apply(x, gamma, mode, transpose=transpose) if op is None else op(x)
+
     a = np.ones_like(q)
     b = None
     p = None
     err = math.nan
     for k in range(1, max_iters + 1):
-        t = gibbs_apply(a, gamma, mode, transpose=True)
+        t = K(a, transpose=True)
         if k > 1 and tol > 0 and (k - 1) % check_every == 0:
             err = float(np.abs(b * t - q).sum())
             if err <= tol:
                 return p, dict(iters=k - 1, marginal_l1=err, mass=float(p.sum()), stop="tol")
         b = _safe_div(q, t)
-        s = gibbs_apply(b, gamma, mode)
+        s = K(b)
         p = prox(s, sigma, en)
         a = _safe_div(p, s)
-    t = gibbs_apply(a, gamma, mode, transpose=True)
+    t = K(a, transpose=True)
     err = float(np.abs(b * t - q).sum())
     return p, dict(iters=max_iters, marginal_l1=err, mass=float(p.sum()), stop="cap")
 

@@ -35,6 +35,10 @@ Workloads (synthetic stand-ins for the paper's figures, which print no data):
                    second coupling carries every cell to its target in one hop:
                    its kernel entries stay representable in float32 while
                    displacement^2 / gamma stays well under 87.)
+* ``heat100``   -- crowd motion on a 100x100 room with a wall, a door and
+                   pillars under the heat-kernel Gibbs operator of Section 4.1
+                   (L = 10 implicit steps; ``heat_room``), capacity max p0;
+                   3 steps of 300 iterations.
 * ``crowd256_binary`` -- ``crowd256`` under the non-convex binary constraint
                    {0, kappa} (Section 4.5): potential scaled to sigma w <= 1/2
                    (above 1 the binary prox empties every cell), initial density
@@ -55,7 +59,7 @@ import numpy as np
 
 __all__ = [
     "Workload", "cell_centres", "gaussian_bumps", "box_obstacles",
-    "project_capacity", "make_workload", "WORKLOADS", "small_case",
+    "project_capacity", "make_workload", "WORKLOADS", "small_case", "heat_room",
 ]
 
 
@@ -136,6 +140,8 @@ class Workload:
     density_scale: float = 1.0
     m_field: Optional[np.ndarray] = None   # gen_entropy exponents per cell (None = m)
     target: Optional[np.ndarray] = None    # attraction target density r
+    mask: Optional[np.ndarray] = None      # heat-kernel domain (True = free cell); None = Gaussian kernel
+    heat_L: int = 10                       # implicit heat steps of the heat kernel
     n_steps: int = 1
     max_iters: int = 300
     tol: float = 0.0                       # 0 = fixed iteration count
@@ -223,6 +229,68 @@ def _porous(name, shape, gamma, tau, m, seed, density_scaled, n_steps, max_iters
     )
 
 
+def _geodesic_steps(mask: np.ndarray, goal) -> np.ndarray:
+    """Length of the shortest 4-neighbour path inside ``mask`` from every
+    cell to ``goal``, in cells (inf where unreachable)."""
+    n0, n1 = mask.shape
+    dist = np.full(mask.shape, np.inf)
+    dist[goal] = 0.0
+    frontier = [goal]
+    while frontier:
+        nxt = []
+        for (i, j) in frontier:
+            for di, dj in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+                a, b = i + di, j + dj
+                if 0 <= a < n0 and 0 <= b < n1 and mask[a, b] and dist[a, b] == np.inf:
+                    dist[a, b] = dist[i, j] + 1.0
+                    nxt.append((a, b))
+        frontier = nxt
+    return dist
+
+
+def heat_room(n0: int, n1: int, seed: int = 0, gamma=None, tau=None, L: int = 10,
+              n_steps: int = 3, max_iters: int = 300, tol: float = 0.0) -> Workload:
+    """Crowd motion on a non-convex room under the heat-kernel Gibbs operator
+    (Section 4.1 and the obstacle-domain crowd example of Section 4.3):
+    the unit square with a wall across the first axis at x0 = 0.55 pierced by
+    a door of width 0.16 around x1 = 0.5, and three square pillars in the
+    start region.  The crowd starts as 4 Gaussian bumps (std 0.05) in
+    x0 < 0.45, the potential w is the geodesic distance (4-neighbour path
+    length, in units of the longer axis) to an exit at (0.95, 0.5), and the
+    capacity is kappa = max p0 (the paper's choice).  gamma defaults to
+    L / max(n)^2 (one heat-step weight nu = 1 on the longer axis), tau to
+    20 gamma."""
+    rng = np.random.default_rng(seed)
+    shape = (n0, n1)
+    X = _mesh(shape)
+    free = np.ones(shape, bool)
+    wall = (X[0] >= 0.55) & (X[0] < 0.55 + max(0.03, 1.5 / n0))
+    door = np.abs(X[1] - 0.5) < 0.08
+    free &= ~(wall & ~door)
+    for _ in range(3):
+        c = rng.uniform([0.1, 0.1], [0.35, 0.8])
+        free &= ~box_obstacles(shape, [c], [[0.08, 0.08]])
+    centres = []
+    while len(centres) < 4:
+        c = rng.uniform([0.08, 0.1], [0.42, 0.9])
+        cell = (min(int(c[0] * n0), n0 - 1), min(int(c[1] * n1), n1 - 1))
+        if free[cell]:
+            centres.append(c)
+    p0 = gaussian_bumps(shape, centres, 0.05, rng.dirichlet(np.ones(4)))
+    p0[~free] = 0.0
+    p0 /= p0.sum()
+    exit_cell = (min(int(0.95 * n0), n0 - 1), min(int(0.5 * n1), n1 - 1))
+    w = _geodesic_steps(free, exit_cell) / max(shape)
+    w[~np.isfinite(w)] = 0.0          # cells cut off from the exit (none in this room) and obstacles
+    if gamma is None:
+        gamma = L / float(max(shape)) ** 2
+    if tau is None:
+        tau = 20.0 * gamma
+    return Workload(name=f"heat{n0}x{n1}", shape=shape, gamma=gamma, tau=tau, kind="congestion",
+                    p0=p0, w=w, kappa_scalar=float(p0.max()), n_steps=n_steps, max_iters=max_iters,
+                    tol=tol, mask=free, heat_L=L, extras=dict(centres=np.array(centres), exit=exit_cell))
+
+
 def make_workload(name: str, seed: int = 0, projected: bool = True, **over) -> Workload:
     """Build a named workload.  ``over`` overrides scalar solver parameters
     (n_steps, max_iters, tol, check_every)."""
@@ -265,6 +333,9 @@ def make_workload(name: str, seed: int = 0, projected: bool = True, **over) -> W
         wl.w = wl.w * (0.5 / ((wl.tau / wl.gamma) * float(wl.w.max())))
         kap = wl.kappa_field()
         wl.p0 = np.where((kap > 0) & (wl.p0 >= 0.5 * kap), kap, 0.0)
+    elif name == "heat100":
+        wl = heat_room(100, 100, seed)
+        wl.name = name
     else:
         raise KeyError(name)
     for k, v in over.items():
@@ -276,7 +347,7 @@ def make_workload(name: str, seed: int = 0, projected: bool = True, **over) -> W
 
 WORKLOADS = ("crowd32", "crowd256", "crowd256_fixed", "crowd256_binary", "crowd256_attraction", "porous512",
              "porous512_scaled", "gen512",
-             "crowd128c")
+             "crowd128c", "heat100")
 
 
 def small_case(shape, kind="congestion", seed=0, gamma=None, tau=None, n_boxes=None,
