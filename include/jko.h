@@ -254,6 +254,66 @@ jko_status jko_time_iteration(const jko_grid* grid, const jko_energy* energy, co
                               const float* p_in, int32_t reps, double* ms_per_launch, int32_t* n_launches,
                               void* workspace, size_t workspace_bytes, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Heat-kernel Gibbs operator on a masked 2D grid (Section 4.1, eq.
+ * heat-kernel).  On a non-convex domain M (the free cells of an n0 x n1 grid
+ * of [0,1]^2; obstacles carry no mass) xi is replaced by
+ *
+ *     xi~ = (Id - (gamma / L) Delta_M)^{-L},
+ *
+ * L implicit Euler steps of the heat equation up to time gamma, with
+ * Delta_M the five-point Laplacian of the free cells, spacing 1/n_k along
+ * axis k and no flux across the grid's edge or into an obstacle.  xi~ is
+ * symmetric, non-negative and conserves mass on each connected part of M;
+ * transport through it follows the domain's geodesics.
+ *
+ * The paper applies xi~ by L sparse back-substitutions per product.  This
+ * library builds xi~ once per (domain, gamma, L) as a dense float32 matrix
+ * in the workspace (N = n0 n1 <= 65536 cells; N^2 * 4 bytes, 400 MB at
+ * 100 x 100) by FP64 Chebyshev solves on the device, then runs every product
+ * of the scaling iteration as one matrix-vector pass.  The flow uses the
+ * iteration and stop test of jko_step with xi replaced by xi~; float32 only,
+ * no log domain, no backward.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t n0, n1;          /* grid, n0 x n1 cells (row-major, n1 fastest; n0 = 1: a 1D grid) */
+    const uint8_t* mask;     /* device, n0*n1 bytes, nonzero = free cell; NULL = no obstacle.
+                                Read by every call below: keep it alive and unchanged while the
+                                workspace's operator is in use */
+    int32_t L;               /* implicit heat steps, 1..1000 (the paper uses 10) */
+} jko_heat_domain;
+
+/* Bytes of device workspace the calls below need for this domain (the dense
+ * operator, its construction scratch, and the iteration's fields); 0 when
+ * the domain is invalid. */
+size_t jko_heat_workspace_bytes(const jko_heat_domain* domain);
+
+/* Builds xi~ for this domain and gamma into the workspace (which then holds
+ * it for jko_heat_apply and jko_heat_flow with the same domain and gamma).
+ * Each column is L solves of (Id - (gamma/L) Delta_M) x = rhs by Chebyshev
+ * iteration in FP64 to 1e-14 of the right-hand side, rounded to float32.
+ * Synchronous.  Cost: L * (about 3 sqrt(1 + 4 gamma (n0^2 + n1^2) / L) + 1)
+ * stencil sweeps over N x min(N, 1024) doubles per 1024 columns. */
+jko_status jko_heat_build(const jko_heat_domain* domain, double gamma, void* workspace,
+                          size_t workspace_bytes, void* stream);
+
+/* y = xi~ x (= xi~^T x) for an N-cell device field x (values on obstacles
+ * ignored; y is 0 there).  x and y may not alias.  Refuses a workspace
+ * whose operator was built for another domain (synchronous check). */
+jko_status jko_heat_apply(const jko_heat_domain* domain, const float* x, float* y,
+                          void* workspace, size_t workspace_bytes, void* stream);
+
+/* n_steps JKO steps from p0 with xi~ in place of xi (the crowd-motion
+ * examples of Section 4.3 on obstacle domains).  energy: every kind but
+ * JKO_F_ATTRACTION.  params: gamma must equal the gamma of jko_heat_build;
+ * precision JKO_FP32; absorb_threshold +inf or NaN; flags ignored.  p0
+ * (device, N cells) must be zero on obstacles.  stats (host, nullable): one
+ * record per step (max_abs_log_a/b are 0: not monitored).  Synchronous:
+ * the stop test and the statistics read device sums back. */
+jko_status jko_heat_flow(const jko_heat_domain* domain, const jko_energy* energy, const jko_params* params,
+                         int32_t n_steps, const float* p0, float* pT, jko_stats* stats,
+                         void* workspace, size_t workspace_bytes, void* stream);
+
 /* Static description of a status code. */
 const char* jko_status_string(int32_t status);
 

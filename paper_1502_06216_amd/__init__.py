@@ -9,9 +9,11 @@ The compute path is libjko.so (hand-written HIP kernels behind a C ABI,
 * ``flow(p0, energy, gamma, tau, n_steps, ...)``
 * ``backward(checkpoints, iters, dL_dpT, energy, gamma, tau)``
 * ``JKOFlowFn`` -- torch.autograd.Function over flow/backward
+* ``HeatOperator(shape, gamma, L, mask)`` -- the heat-kernel Gibbs operator
+  of Section 4.1 on an obstacle domain: ``apply``, ``step``, ``flow``
 """
 from ._native import (  # noqa: F401
-    EnergySpec, JKOError, JKOFlowFn, backward, time_iteration, flow, gibbs_apply, load, step, workspace_bytes,
+    EnergySpec, HeatDomain, HeatOperator, JKOError, JKOFlowFn, backward, time_iteration, flow, gibbs_apply, load, step, workspace_bytes,
     make_grid, make_params, Grid, EnergyC, Params, Stats, LIB_PATH,
     JKO_OK, JKO_ERR_INVALID, JKO_ERR_WORKSPACE, JKO_ERR_HIP, JKO_ERR_NONFINITE, JKO_ERR_INFEASIBLE,
     OP_GIBBS, OP_STEP, OP_FLOW, OP_BACKWARD,

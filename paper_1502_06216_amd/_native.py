@@ -59,6 +59,10 @@ class Params(ctypes.Structure):
                 ("absorb_threshold", ctypes.c_double)]
 
 
+class HeatDomain(ctypes.Structure):
+    _fields_ = [("n0", ctypes.c_int32), ("n1", ctypes.c_int32), ("mask", ctypes.c_void_p), ("L", ctypes.c_int32)]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("absorptions", ctypes.c_int32),
                 ("stop_reason", ctypes.c_int32), ("status", ctypes.c_int32),
@@ -97,6 +101,15 @@ def load(path: str = LIB_PATH):
     lib.jko_backward.restype = i32
     lib.jko_time_iteration.argtypes = [G, E, P, vp, i32, ctypes.POINTER(f64), ctypes.POINTER(i32), vp, sz, vp]
     lib.jko_time_iteration.restype = i32
+    H = ctypes.POINTER(HeatDomain)
+    lib.jko_heat_workspace_bytes.argtypes = [H]
+    lib.jko_heat_workspace_bytes.restype = sz
+    lib.jko_heat_build.argtypes = [H, f64, vp, sz, vp]
+    lib.jko_heat_build.restype = i32
+    lib.jko_heat_apply.argtypes = [H, vp, vp, vp, sz, vp]
+    lib.jko_heat_apply.restype = i32
+    lib.jko_heat_flow.argtypes = [H, E, P, i32, vp, vp, S, vp, sz, vp]
+    lib.jko_heat_flow.restype = i32
     lib.jko_status_string.argtypes = [i32]
     lib.jko_status_string.restype = ctypes.c_char_p
     lib.jko_last_error.argtypes = []
@@ -333,3 +346,75 @@ class JKOFlowFn(torch.autograd.Function):
         gw, gp = backward(ck, [iters] * n_steps, grad_out.contiguous(), en, gamma, tau, precision,
                           want_w=ctx.needs_input_grad[1], want_p0=ctx.needs_input_grad[0])
         return gp, gw, None, None, None, None, None, None
+
+
+class HeatOperator:
+    """The heat-kernel Gibbs operator xi~ = (Id - (gamma/L) Delta_M)^{-L} of
+    Section 4.1 on the free cells of a 2D grid (mask: CUDA bool/uint8 tensor
+    of the grid's shape, True = free; None = no obstacle).  Construction
+    builds xi~ once on the GPU into a workspace this object owns (N^2 * 4
+    bytes and more); apply() and flow() then use it.  The mask is kept (the
+    library reads it on every call)."""
+
+    def __init__(self, shape, gamma: float, L: int = 10, mask: Optional[torch.Tensor] = None, device=None):
+        lib = load()
+        shape = tuple(int(n) for n in shape)
+        if len(shape) == 1:
+            shape = (1, shape[0])
+        if len(shape) != 2:
+            raise ValueError("the heat kernel takes 1D or 2D grids")
+        self.shape = shape
+        self.gamma = float(gamma)
+        self.L = int(L)
+        if mask is not None:
+            if not isinstance(mask, torch.Tensor) or mask.device.type != "cuda":
+                raise TypeError("mask must be a CUDA (HIP) tensor")
+            if mask.numel() != shape[0] * shape[1]:
+                raise TypeError(f"mask must have {shape[0] * shape[1]} cells")
+            device = mask.device
+            self.mask = mask.reshape(shape).to(torch.uint8).contiguous()
+        else:
+            self.mask = None
+            device = torch.device("cuda") if device is None else torch.device(device)
+        self.device = device
+        self.dom = HeatDomain(shape[0], shape[1], _ptr(self.mask), self.L)
+        nb = lib.jko_heat_workspace_bytes(ctypes.byref(self.dom))
+        if nb == 0:
+            raise JKOError(JKO_ERR_INVALID, f"invalid heat domain {shape}, L={L}")
+        self.ws = _workspace(nb, device)
+        _check(lib.jko_heat_build(ctypes.byref(self.dom), self.gamma, _ptr(self.ws), self.ws.numel(),
+                                  _stream(device)))
+
+    def _grid_field(self, t, name):
+        if t is None:
+            return None
+        if t.numel() != self.shape[0] * self.shape[1]:
+            raise TypeError(f"{name} must have {self.shape[0] * self.shape[1]} cells")
+        return _field(t, tuple(t.shape), name)
+
+    def apply(self, x: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """y = xi~ x for a float32 CUDA field of the grid's cells."""
+        lib = load()
+        self._grid_field(x, "x")
+        y = torch.empty_like(x) if out is None else self._grid_field(out, "out")
+        _check(lib.jko_heat_apply(ctypes.byref(self.dom), _ptr(x), _ptr(y), _ptr(self.ws), self.ws.numel(),
+                                  _stream(x.device)))
+        return y
+
+    def flow(self, p0: torch.Tensor, energy: EnergySpec, tau: float, n_steps: int, max_iters: int = 300,
+             tol: float = 0.0, check_every: int = 10, with_stats: bool = True, out: Optional[torch.Tensor] = None):
+        """n_steps JKO steps from p0 with xi~ as the Gibbs kernel.  Returns
+        (p_T, stats list or None)."""
+        lib = load()
+        self._grid_field(p0, "p0")
+        pT = torch.empty_like(p0) if out is None else self._grid_field(out, "out")
+        prm = make_params(self.gamma, tau, max_iters, tol, check_every)
+        e = energy.to_c(tuple(p0.shape))
+        sts = (Stats * n_steps)() if with_stats else None
+        _check(lib.jko_heat_flow(ctypes.byref(self.dom), ctypes.byref(e), ctypes.byref(prm), int(n_steps), _ptr(p0),
+                                 _ptr(pT), sts, _ptr(self.ws), self.ws.numel(), _stream(p0.device)))
+        return pT, ([st.as_dict() for st in sts] if with_stats else None)
+
+    def step(self, p: torch.Tensor, energy: EnergySpec, tau: float, **kw):
+        pT, sts = self.flow(p, energy, tau, 1, **kw)
+        return pT, (sts[0] if sts else None)

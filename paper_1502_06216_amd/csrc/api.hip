@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "jko_internal.h"
+#include "heat.h"
 
 using namespace jko;
 
@@ -426,36 +427,40 @@ jko_status check_energy(const jko_energy* en) {
     }
 }
 
-ProxArgs prox_args(const Plan& P, const jko_energy* en, double sigma) {
+ProxArgs prox_args_fields(const jko_energy* en, double sigma, float* fg, float* fkf) {
     ProxArgs px{};
     px.kind = en->kind;
     px.m = en->m;
     px.newton = en->newton_steps > 0 ? en->newton_steps : 8;
     if (is_congestion(en)) {
-        px.g = en->w ? P.F(F_G) : nullptr;
+        px.g = en->w ? fg : nullptr;
         px.kappa = en->kappa;
         px.kappa_s = en->kappa_scalar;
     } else if (en->kind == JKO_F_ENTROPY) {
-        if (en->coef) px.kf = P.F(F_KF);
+        if (en->coef) px.kf = fkf;
         else px.kf_s = (float)(1.0 / (1.0 + sigma * (double)en->coef_scalar));
     } else if (en->kind == JKO_F_GEN_ENTROPY) {
         // c = sigma b m and eps = m - 1 per cell when either b or m is a field
         if (en->coef || en->m_field) {
-            px.kf = P.F(F_KF);
-            px.g = P.F(F_G);
+            px.kf = fkf;
+            px.g = fg;
         } else {
             px.kf_s = (float)(sigma * (double)en->coef_scalar * (double)en->m);
             px.eps_s = en->m - 1.f;
         }
         px.lD = (float)log((double)en->density_scale);
     } else if (en->kind == JKO_F_POROUS) {
-        if (en->coef) px.kf = P.F(F_KF);
+        if (en->coef) px.kf = fkf;
         else {
             const double m = en->m;
             px.kf_s = (float)log(sigma * (double)en->coef_scalar * m * pow((double)en->density_scale, m - 1.0));
         }
     }
     return px;
+}
+
+ProxArgs prox_args(const Plan& P, const jko_energy* en, double sigma) {
+    return prox_args_fields(en, sigma, P.F(F_G), P.F(F_KF));
 }
 
 jko_status prepare_energy(const Plan& P, const jko_energy* en, double sigma) {
@@ -1204,6 +1209,264 @@ jko_status jko_backward(const jko_grid* grid, const jko_energy* energy, const jk
     }
     if (dL_dp0) HIP_TRY(launch_copy(dL_dp0, pbar, N, P.st));
     if (dL_dw) HIP_TRY(launch_copy(dL_dw, wacc, N, P.st));
+    return JKO_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ heat kernel
+// The heat-kernel Gibbs operator of Section 4.1 on a masked 2D grid, stored
+// densely in the workspace (heat.hip), and the scaling iteration on it.
+
+namespace {
+
+constexpr int32_t kHeatMagic = 0x48454154;   // "HEAT"
+constexpr int64_t kHeatMaxCells = 65536;
+
+struct HeatHdr {
+    int32_t magic, n0, n1, L;
+    double gamma;
+    int64_t ld;
+};
+
+struct HeatLayout {
+    int64_t N = 0, ld = 0;
+    size_t hdr = 0, A = 0, scratch = 0, a = 0, b = 0, x = 0, p0 = 0, p1 = 0, g = 0, kf = 0, err = 0, out = 0;
+    size_t total = 0;
+};
+
+HeatLayout heat_layout(int n0, int n1) {
+    HeatLayout H;
+    H.N = (int64_t)n0 * n1;
+    H.ld = (H.N + 3) / 4 * 4;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { const size_t at = o; o = align_up(o + bytes); return at; };
+    H.hdr = take(sizeof(HeatHdr));
+    H.A = take((size_t)H.N * H.ld * sizeof(float));
+    H.scratch = take((size_t)heat_build_scratch(H.N) * sizeof(double));
+    H.a = take(H.ld * sizeof(float));
+    H.b = take(H.ld * sizeof(float));
+    H.x = take(H.ld * sizeof(float));
+    H.p0 = take(H.N * sizeof(float));
+    H.p1 = take(H.N * sizeof(float));
+    H.g = take(H.N * sizeof(float));
+    H.kf = take(H.N * sizeof(float));
+    H.err = take(H.N * sizeof(double));
+    H.out = take(8 * sizeof(double));
+    H.total = o;
+    return H;
+}
+
+jko_status heat_domain_check(const jko_heat_domain* d) {
+    if (!d) return fail(JKO_ERR_INVALID, "heat domain is NULL");
+    if (d->n0 < 1 || d->n1 < 1 || (int64_t)d->n0 * d->n1 > kHeatMaxCells)
+        return fail(JKO_ERR_INVALID, "heat domain: need n0, n1 >= 1 and n0 * n1 <= %lld",
+                    (long long)kHeatMaxCells);
+    if (d->L < 1 || d->L > 1000) return fail(JKO_ERR_INVALID, "heat domain: L must be in 1..1000");
+    return JKO_OK;
+}
+
+jko_status heat_ws_check(const HeatLayout& H, void* ws, size_t ws_bytes) {
+    if (!ws) return fail(JKO_ERR_WORKSPACE, "workspace is NULL (%zu bytes needed)", H.total);
+    if (ws_bytes < H.total) return fail(JKO_ERR_WORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, H.total);
+    if (((uintptr_t)ws) % 16 != 0) return fail(JKO_ERR_WORKSPACE, "workspace must be 16-byte aligned");
+    return JKO_OK;
+}
+
+// Reads the operator's record back and checks that it was built for this
+// domain (and, when gamma > 0, this gamma).  Synchronous.
+jko_status heat_hdr_check(const jko_heat_domain* d, const char* ws, double gamma, hipStream_t st) {
+    HIP_TRY(hipMemcpyAsync(g_rb.host, ws, sizeof(HeatHdr), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    HeatHdr h;
+    memcpy(&h, g_rb.host, sizeof h);
+    if (h.magic != kHeatMagic || h.n0 != d->n0 || h.n1 != d->n1 || h.L != d->L)
+        return fail(JKO_ERR_INVALID, "heat: the workspace holds no operator of this domain (call jko_heat_build)");
+    if (gamma > 0.0 && h.gamma != gamma)
+        return fail(JKO_ERR_INVALID, "heat: operator built for gamma %.17g, params ask %.17g", h.gamma, gamma);
+    return JKO_OK;
+}
+
+jko_status heat_sums(const double* err, const float* p, int64_t N, double* dev_out, hipStream_t st, double h[3]) {
+    HIP_TRY(launch_heat_sums(err, p, N, dev_out, st));
+    HIP_TRY(hipMemcpyAsync(g_rb.host, dev_out, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    memcpy(h, g_rb.host, 3 * sizeof(double));
+    return JKO_OK;
+}
+
+// One step q -> p_out by the reduced iteration (t = xi~ a; b = q / t;
+// s = xi~ b; p = Prox(s); a = p / s) with the stop test of the band path:
+// at iteration k > 1 with (k - 1) % check_every == 0 and tol > 0 the
+// violation ||b t - q||_1 of iteration k - 1 is summed, and the step returns
+// that iterate when it is at most tol.
+jko_status heat_step(const HeatLayout& H, char* base, const uint8_t* mask, const jko_params* pr,
+                     const ProxArgs& px, int kind, const float* q, float* p_out, jko_stats* st_out,
+                     hipStream_t st) {
+    const float* A = reinterpret_cast<const float*>(base + H.A);
+    float* a = reinterpret_cast<float*>(base + H.a);
+    float* b = reinterpret_cast<float*>(base + H.b);
+    double* err = reinterpret_cast<double*>(base + H.err);
+    double* dout = reinterpret_cast<double*>(base + H.out);
+    HIP_TRY(launch_heat_fill(a, 1.f, H.N, H.ld, st));
+    HIP_TRY(launch_heat_fill(b, 0.f, H.N, H.ld, st));
+    HeatGemv gt{};
+    gt.A = A;
+    gt.ld = H.ld;
+    gt.N = H.N;
+    gt.mask = mask;
+    gt.x = a;
+    gt.q = q;
+    gt.b = b;
+    gt.errrow = err;
+    HeatGemv gs = gt;
+    gs.x = b;
+    gs.a = a;
+    gs.p = p_out;
+    gs.px = px;
+    const bool tolmode = pr->tol_l1 > 0.0;
+    int iters = pr->max_iters;
+    bool bytol = false;
+    double h[3] = {0.0, 0.0, 0.0};
+    for (int k = 1; k <= pr->max_iters; ++k) {
+        gt.check = tolmode && k > 1 && (k - 1) % pr->check_every == 0;
+        HIP_TRY(launch_heat_gemv(HEAT_EK_BUPDATE, gt, st));
+        if (gt.check) {
+            jko_status s = heat_sums(err, nullptr, H.N, dout, st, h);
+            if (s) return s;
+            if (h[2] > 0.0) break;
+            if (h[0] <= pr->tol_l1) {
+                iters = k - 1;
+                bytol = true;
+                break;
+            }
+        }
+        HIP_TRY(launch_heat_gemv(HEAT_EK_PROX + kind, gs, st));
+    }
+    if (!bytol && h[2] == 0.0) HIP_TRY(launch_heat_gemv(HEAT_EK_MONITOR, gt, st));
+    jko_status s = heat_sums(err, p_out, H.N, dout, st, h);
+    if (s) return s;
+    const bool bad = h[2] > 0.0 || !isfinite(h[0]) || !isfinite(h[1]);
+    if (st_out) {
+        jko_stats& o = *st_out;
+        o.iters = iters;
+        o.absorptions = 0;
+        o.stop_reason = bytol ? JKO_STOP_TOL : JKO_STOP_CAP;
+        o.status = bad ? JKO_ERR_NONFINITE : JKO_OK;
+        o.marginal_l1 = bad ? NAN : h[0];
+        o.mass = h[1];
+        o.max_abs_log_a = 0.0;
+        o.max_abs_log_b = 0.0;
+    }
+    if (bad) return fail(JKO_ERR_NONFINITE, "non-finite value in the marginal monitor");
+    return JKO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t jko_heat_workspace_bytes(const jko_heat_domain* domain) {
+    if (!domain || domain->n0 < 1 || domain->n1 < 1 || (int64_t)domain->n0 * domain->n1 > kHeatMaxCells) return 0;
+    return heat_layout(domain->n0, domain->n1).total;
+}
+
+jko_status jko_heat_build(const jko_heat_domain* domain, double gamma, void* ws, size_t ws_bytes, void* stream) {
+    g_err.clear();
+    jko_status s = heat_domain_check(domain);
+    if (s) return s;
+    if (!(gamma > 0.0) || !isfinite(gamma)) return fail(JKO_ERR_INVALID, "gamma must be finite and > 0");
+    const HeatLayout H = heat_layout(domain->n0, domain->n1);
+    if ((s = heat_ws_check(H, ws, ws_bytes))) return s;
+    if ((s = readback_init())) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char* base = static_cast<char*>(ws);
+    HIP_TRY(heat_build_operator(domain->mask, domain->n0, domain->n1, gamma, domain->L,
+                                reinterpret_cast<float*>(base + H.A), H.ld,
+                                reinterpret_cast<double*>(base + H.scratch), st));
+    HeatHdr h{kHeatMagic, domain->n0, domain->n1, domain->L, gamma, H.ld};
+    memcpy(g_rb.host, &h, sizeof h);
+    HIP_TRY(hipMemcpyAsync(base + H.hdr, g_rb.host, sizeof h, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return JKO_OK;
+}
+
+jko_status jko_heat_apply(const jko_heat_domain* domain, const float* x, float* y, void* ws, size_t ws_bytes,
+                          void* stream) {
+    g_err.clear();
+    jko_status s = heat_domain_check(domain);
+    if (s) return s;
+    if (!x || !y) return fail(JKO_ERR_INVALID, "x and y must be non-NULL");
+    if (x == y) return fail(JKO_ERR_INVALID, "x and y may not alias");
+    const HeatLayout H = heat_layout(domain->n0, domain->n1);
+    if ((s = heat_ws_check(H, ws, ws_bytes))) return s;
+    if ((s = readback_init())) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char* base = static_cast<char*>(ws);
+    if ((s = heat_hdr_check(domain, base + H.hdr, 0.0, st))) return s;
+    float* xp = reinterpret_cast<float*>(base + H.x);
+    HIP_TRY(launch_heat_copy_pad(xp, x, H.N, H.ld, st));
+    HeatGemv g{};
+    g.A = reinterpret_cast<const float*>(base + H.A);
+    g.ld = H.ld;
+    g.N = H.N;
+    g.mask = domain->mask;
+    g.x = xp;
+    g.y = y;
+    HIP_TRY(launch_heat_gemv(HEAT_EK_STORE, g, st));
+    return JKO_OK;
+}
+
+jko_status jko_heat_flow(const jko_heat_domain* domain, const jko_energy* energy, const jko_params* params,
+                         int32_t n_steps, const float* p0, float* pT, jko_stats* stats, void* ws, size_t ws_bytes,
+                         void* stream) {
+    g_err.clear();
+    jko_status s = heat_domain_check(domain);
+    if (s) return s;
+    if ((s = check_params(params)) || (s = check_energy(energy))) return s;
+    if (energy->kind == JKO_F_ATTRACTION) return fail(JKO_ERR_INVALID, "heat: the attraction is not supported");
+    if (params->precision != JKO_FP32) return fail(JKO_ERR_INVALID, "heat: the stored operator is float32 only");
+    if (!(isnan(params->absorb_threshold) || (isinf(params->absorb_threshold) && params->absorb_threshold > 0)))
+        return fail(JKO_ERR_INVALID, "heat: no log domain (absorb_threshold must be +inf or NaN)");
+    if (n_steps < 1) return fail(JKO_ERR_INVALID, "n_steps must be >= 1");
+    if (!p0 || !pT) return fail(JKO_ERR_INVALID, "p0 and pT must be non-NULL");
+    if (p0 == pT) return fail(JKO_ERR_INVALID, "p0 and pT may not alias");
+    const HeatLayout H = heat_layout(domain->n0, domain->n1);
+    if ((s = heat_ws_check(H, ws, ws_bytes))) return s;
+    if ((s = readback_init())) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char* base = static_cast<char*>(ws);
+    if ((s = heat_hdr_check(domain, base + H.hdr, params->gamma, st))) return s;
+    const double sigma = params->tau / params->gamma;
+    float* fg = reinterpret_cast<float*>(base + H.g);
+    float* fkf = reinterpret_cast<float*>(base + H.kf);
+    const bool need = (is_congestion(energy) && energy->w) ||
+                      ((energy->kind == JKO_F_ENTROPY || energy->kind == JKO_F_POROUS) && energy->coef) ||
+                      (energy->kind == JKO_F_GEN_ENTROPY && (energy->coef || energy->m_field));
+    if (need) HIP_TRY(launch_prepare_energy(energy, sigma, H.N, fg, fkf, st));
+    double* dout = reinterpret_cast<double*>(base + H.out);
+    HIP_TRY(launch_heat_input(p0, domain->mask, is_congestion(energy) ? energy->kappa : nullptr,
+                              is_congestion(energy) ? energy->kappa_scalar : INFINITY, H.N, dout, st));
+    double h[3];
+    HIP_TRY(hipMemcpyAsync(g_rb.host, dout, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    memcpy(h, g_rb.host, sizeof h);
+    if (h[2] > 0.0)
+        return fail(JKO_ERR_NONFINITE, "heat: %g cells of p0 are negative, non-finite or on an obstacle, "
+                    "or have a negative capacity", h[2]);
+    if (is_congestion(energy) && h[1] < h[0] * (1.0 - 1e-6))
+        return fail(JKO_ERR_INFEASIBLE, "capacity sum %.9g < mass %.9g", h[1], h[0]);
+    const ProxArgs px = prox_args_fields(energy, sigma, fg, fkf);
+    const float* q = p0;
+    jko_status worst = JKO_OK;
+    for (int t = 0; t < n_steps; ++t) {
+        float* out = (t == n_steps - 1) ? pT : reinterpret_cast<float*>(base + ((t % 2 == 0) ? H.p0 : H.p1));
+        s = heat_step(H, base, domain->mask, params, px, energy->kind, q, out, stats ? &stats[t] : nullptr, st);
+        if (s == JKO_ERR_NONFINITE) worst = s;
+        else if (s) return s;
+        q = out;
+    }
+    if (worst) return fail(worst, "non-finite value in the marginal monitor");
     return JKO_OK;
 }
 

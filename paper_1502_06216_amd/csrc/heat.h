@@ -1,0 +1,70 @@
+// Heat-kernel Gibbs operator on a masked 2D grid (Section 4.1, eq. heat-kernel):
+// host-side launchers of the kernels in heat.hip.
+//
+// xi~ = (Id - (gamma/L) Delta_M)^{-L} with Delta_M the no-flux five-point
+// Laplacian of the free cells (spacing 1/n_k along axis k), i.e.
+// Id + nu_0 G_0 + nu_1 G_1 with nu_k = gamma n_k^2 / L and G_k the graph
+// Laplacian of the free axis-k neighbour pairs.  The library stores xi~ as a
+// dense N x ld float32 matrix (row i = column i, the operator is symmetric;
+// rows and columns of obstacle cells are zero, padding columns N..ld-1 zero).
+#pragma once
+
+#include "jko_internal.h"
+
+namespace jko {
+
+// One application of the stored operator, y = A x, with the result of each
+// row finished by a pointwise epilogue (EK_STORE, EK_BUPDATE, EK_MONITOR or
+// EK_PROX + energy kind, as in the band contractions).
+struct HeatGemv {
+    const float* A;          // N x ld
+    int64_t ld;              // row stride, a multiple of 4, >= N
+    int64_t N;               // cells
+    const uint8_t* mask;     // nonzero = free cell; NULL = all free (rows of obstacles are skipped)
+    const float* x;          // ld floats, padding zero
+    float* y;                // STORE: result
+    const float* q;          // BUPDATE / MONITOR: the step's input density
+    float* b;                // BUPDATE: b = q / y (0/0 = 0); MONITOR: read
+    double* errrow;          // BUPDATE (when check) / MONITOR: |b_old y - q| per row
+    int32_t check;
+    float* a;                // PROX: a = p / y (0/0 = 0)
+    float* p;                // PROX: p = Prox(y)
+    ProxArgs px;
+};
+
+// Chebyshev iterations per implicit step that bring the error of each solve
+// below 1e-14 of the right-hand side for the spectrum [1, beta].
+int heat_cheb_iters(double beta);
+
+// Scratch doubles heat_build_operator needs for an N-cell grid (4 N C).
+int64_t heat_build_scratch(int64_t N);
+
+// Writes A = xi~ (all N x ld entries).  scratch: heat_build_scratch(N)
+// doubles.  Synchronous only in the sense of stream order.
+hipError_t heat_build_operator(const uint8_t* mask, int n0, int n1, double gamma, int L, float* A, int64_t ld,
+                               double* scratch, hipStream_t st);
+
+// Epilogue codes of launch_heat_gemv: store, b-update, monitor, and the
+// proximal epilogue HEAT_EK_PROX + energy kind (the band contractions' codes).
+enum : int { HEAT_EK_STORE = 0, HEAT_EK_BUPDATE = 1, HEAT_EK_MONITOR = 2, HEAT_EK_PROX = 3 };
+
+hipError_t launch_heat_gemv(int ek, const HeatGemv& g, hipStream_t st);
+
+// x[0..n) = v, x[n..ld) = 0
+hipError_t launch_heat_fill(float* x, float v, int64_t n, int64_t ld, hipStream_t st);
+
+// x[0..n) = src, x[n..ld) = 0
+hipError_t launch_heat_copy_pad(float* x, const float* src, int64_t n, int64_t ld, hipStream_t st);
+
+// out[0] = sum errrow (when errrow != NULL), out[1] = sum p (when p != NULL),
+// out[2] = number of non-finite errrow entries.  One block, fixed order.
+hipError_t launch_heat_sums(const double* errrow, const float* p, int64_t N, double* out, hipStream_t st);
+
+// Input check of a step's density: out[0] = mass, out[1] = capacity over the
+// free cells (kappa field or kappa_s; +inf allowed), out[2] = number of
+// cells that are negative or non-finite, hold mass on an obstacle, or have a
+// negative/NaN capacity.
+hipError_t launch_heat_input(const float* p, const uint8_t* mask, const float* kappa, float kappa_s, int64_t N,
+                             double* out, hipStream_t st);
+
+}  // namespace jko

@@ -1,0 +1,341 @@
+// Heat-kernel Gibbs operator (Section 4.1, eq. heat-kernel) on a masked 2D
+// grid: construction of the dense operator and its application with the
+// scaling iteration's pointwise epilogues.
+//
+// The paper applies xi~ = (Id - (gamma/L) Delta_M)^{-L} by L sparse
+// back-substitutions per product, a sequential sweep.  On this device the
+// operator of a grid of up to 2^16 cells fits HBM as a dense float32 matrix
+// (10^4 cells: 400 MB), so it is built once per (domain, gamma, L), and every
+// product of the iteration becomes one HBM-bound matrix-vector pass whose
+// rows run in parallel.
+//
+// Construction: the columns of xi~ are L successive solves of
+// M x = rhs, M = Id + nu_0 G_0 + nu_1 G_1, from unit vectors, all columns of
+// a chunk at once (C columns, element (cell i, column c) at i*C + c, so the
+// five-point stencil reads whole rows of C consecutive doubles).  M is
+// symmetric with spectrum in [1, 1 + 4 nu_0 + 4 nu_1] (Gershgorin; G_k is
+// positive semi-definite), so each solve is a Chebyshev iteration
+// (Saad, Iterative Methods for Sparse Linear Systems, 2nd ed., Alg. 12.1)
+// with no inner products: one stencil sweep per iteration, in FP64.
+#include "heat.h"
+#include "epilogue.h"
+
+namespace jko {
+
+static_assert(HEAT_EK_STORE == EK_STORE && HEAT_EK_BUPDATE == EK_BUPDATE && HEAT_EK_MONITOR == EK_MONITOR &&
+                  HEAT_EK_PROX == EK_PROX,
+              "heat epilogue codes follow the band contractions' codes");
+
+namespace {
+
+__device__ __forceinline__ bool is_free(const uint8_t* mask, int64_t i) { return !mask || mask[i]; }
+
+// (M x)_(i, c) over a chunk: x_i + sum over free neighbours j of nu_k (x_i - x_j)
+// for a free cell; x_i (zero) for an obstacle.
+__device__ __forceinline__ double heat_mx(const double* __restrict__ x, const uint8_t* __restrict__ mask,
+                                          int64_t i, int64_t e, int C, int n0, int n1, double nu0, double nu1) {
+    const double xi = x[e];
+    if (!is_free(mask, i)) return xi;
+    const int r = (int)(i / n1), col = (int)(i - (int64_t)r * n1);
+    double acc = xi;
+    if (r > 0 && is_free(mask, i - n1)) acc += nu0 * (xi - x[e - (int64_t)n1 * C]);
+    if (r + 1 < n0 && is_free(mask, i + n1)) acc += nu0 * (xi - x[e + (int64_t)n1 * C]);
+    if (col > 0 && is_free(mask, i - 1)) acc += nu1 * (xi - x[e - C]);
+    if (col + 1 < n1 && is_free(mask, i + 1)) acc += nu1 * (xi - x[e + C]);
+    return acc;
+}
+
+// X = the unit columns j0 .. j0+C-1 (only those of free cells below N).
+__global__ void k_heat_unit(double* __restrict__ X, const uint8_t* __restrict__ mask, int64_t N, int logC,
+                            int64_t j0) {
+    const int64_t n = N << logC;
+    const int C = 1 << logC;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e >> logC;
+        const int64_t j = j0 + (e & (C - 1));
+        X[e] = (i == j && is_free(mask, i)) ? 1.0 : 0.0;
+    }
+}
+
+// Start of one solve with right-hand side and first guess X:
+// R = X - M X, D = R / theta.
+__global__ void k_heat_cheb_init(const double* __restrict__ X, double* __restrict__ R, double* __restrict__ D,
+                                 const uint8_t* __restrict__ mask, int64_t N, int logC, int n0, int n1,
+                                 double nu0, double nu1, double inv_theta) {
+    const int64_t n = N << logC;
+    const int C = 1 << logC;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e >> logC;
+        const double r = X[e] - heat_mx(X, mask, i, e, C, n0, n1, nu0, nu1);
+        R[e] = r;
+        D[e] = r * inv_theta;
+    }
+}
+
+// One Chebyshev iteration: X += D, R -= M D, Dn = c1 D + c2 R (new R).
+// D is only read (at the cell and its neighbours); X, R, Dn only at the cell.
+__global__ void k_heat_cheb_step(double* __restrict__ X, double* __restrict__ R, const double* __restrict__ D,
+                                 double* __restrict__ Dn, const uint8_t* __restrict__ mask, int64_t N, int logC,
+                                 int n0, int n1, double nu0, double nu1, double c1, double c2) {
+    const int64_t n = N << logC;
+    const int C = 1 << logC;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e >> logC;
+        const double d = D[e];
+        const double md = heat_mx(D, mask, i, e, C, n0, n1, nu0, nu1);
+        X[e] += d;
+        const double r = R[e] - md;
+        R[e] = r;
+        Dn[e] = c1 * d + c2 * r;
+    }
+}
+
+// A[i, j0 + c] = X[i, c] rounded to float32, for j0 + c < ld (columns at or
+// beyond N are zero in X).  xi~ is symmetric, so column j of the solves is
+// row j of A as well; the store writes it as column j.
+__global__ void k_heat_store(const double* __restrict__ X, float* __restrict__ A, int64_t N, int logC, int64_t ld,
+                             int64_t j0) {
+    const int64_t n = N << logC;
+    const int C = 1 << logC;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e >> logC;
+        const int64_t j = j0 + (e & (C - 1));
+        if (j < ld) A[i * ld + j] = (float)X[e];
+    }
+}
+
+// ------------------------------------------------------------------ products
+
+// Finish row i of y = A x (value v): the epilogue of the iteration's half-step.
+template <int EK>
+__device__ __forceinline__ void heat_epilogue(const HeatGemv& g, int64_t i, float v) {
+    if constexpr (EK == EK_STORE) {
+        g.y[i] = v;
+    } else if constexpr (EK == EK_BUPDATE || EK == EK_MONITOR) {
+        const float q = g.q[i];
+        if (EK == EK_MONITOR || g.check) g.errrow[i] = fabs((double)g.b[i] * (double)v - (double)q);
+        if (EK == EK_BUPDATE) g.b[i] = q == 0.f ? 0.f : q / v;
+    } else {
+        constexpr int KIND = EK - EK_PROX;
+        const ProxArgs& px = g.px;
+        float pu = 1.f, pv = 0.f;
+        if (KIND == JKO_F_CONGESTION || KIND == JKO_F_CONGESTION_BINARY) {
+            pu = px.g ? px.g[i] : 1.f;
+            pv = px.kappa ? px.kappa[i] : px.kappa_s;
+        } else if (KIND == JKO_F_ENTROPY || KIND == JKO_F_POROUS) {
+            pu = px.kf ? px.kf[i] : px.kf_s;
+        } else if (KIND == JKO_F_GEN_ENTROPY) {
+            pu = px.kf ? px.kf[i] : px.kf_s;
+            pv = px.g ? px.g[i] : px.eps_s;
+        }
+        const float p = prox_val<KIND>(px, v, pu, pv);
+        g.a[i] = p == 0.f ? 0.f : p / v;
+        g.p[i] = p;
+    }
+}
+
+constexpr int kHeatRows = 2;   // rows per wave: each load of x serves both
+
+// One wave per kHeatRows consecutive rows: every lane streams float4 runs of
+// the rows (16-byte loads, 1 KiB per wave per row and step), sums them in
+// FP32, the wave reduces by butterflies, and lane r finishes row r.  Rows of
+// obstacle cells are all zero and are not read.
+template <int EK>
+__global__ void __launch_bounds__(256) k_heat_gemv(HeatGemv g) {
+    const int lane = threadIdx.x & 63;
+    const int64_t row0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kHeatRows;
+    if (row0 >= g.N) return;
+    const int64_t n4 = g.ld >> 2;
+    const f4* __restrict__ xv = reinterpret_cast<const f4*>(g.x);
+    bool live[kHeatRows];
+    const f4* __restrict__ Ar[kHeatRows];
+    f4 s[kHeatRows];
+#pragma unroll
+    for (int r = 0; r < kHeatRows; ++r) {
+        const int64_t i = row0 + r;
+        live[r] = i < g.N && is_free(g.mask, i);
+        Ar[r] = reinterpret_cast<const f4*>(g.A + (live[r] ? i : row0) * g.ld);
+        s[r] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+    if (live[0] && live[1]) {
+#pragma unroll 4
+        for (int64_t j = lane; j < n4; j += 64) {
+            const f4 xj = xv[j];
+            s[0] += Ar[0][j] * xj;
+            s[1] += Ar[1][j] * xj;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < kHeatRows; ++r)
+            if (live[r]) {
+#pragma unroll 4
+                for (int64_t j = lane; j < n4; j += 64) s[r] += Ar[r][j] * xv[j];
+            }
+    }
+    float v[kHeatRows];
+#pragma unroll
+    for (int r = 0; r < kHeatRows; ++r) {
+        float t = (s[r].x + s[r].y) + (s[r].z + s[r].w);
+        for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+        v[r] = t;
+    }
+#pragma unroll
+    for (int r = 0; r < kHeatRows; ++r)
+        if (lane == r && row0 + r < g.N) heat_epilogue<EK>(g, row0 + r, v[r]);
+}
+
+__global__ void k_heat_fill(float* __restrict__ x, float v, int64_t n, int64_t ld) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ld; i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = i < n ? v : 0.f;
+}
+
+__global__ void k_heat_copy_pad(float* __restrict__ x, const float* __restrict__ src, int64_t n, int64_t ld) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ld; i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = i < n ? src[i] : 0.f;
+}
+
+__global__ void __launch_bounds__(256) k_heat_sums(const double* __restrict__ errrow, const float* __restrict__ p,
+                                                   int64_t N, double* __restrict__ out) {
+    __shared__ double sh[4];
+    double e = 0.0, m = 0.0, bad = 0.0;
+    for (int64_t i = threadIdx.x; i < N; i += blockDim.x) {
+        if (errrow) {
+            const double v = errrow[i];
+            if (isfinite(v)) e += v;
+            else bad += 1.0;
+        }
+        if (p) m += (double)p[i];
+    }
+    e = block_sum(e, sh);
+    if (threadIdx.x == 0) out[0] = e;
+    m = block_sum(m, sh);
+    if (threadIdx.x == 0) out[1] = m;
+    bad = block_sum(bad, sh);
+    if (threadIdx.x == 0) out[2] = bad;
+}
+
+__global__ void __launch_bounds__(256) k_heat_input(const float* __restrict__ p, const uint8_t* __restrict__ mask,
+                                                    const float* __restrict__ kappa, float kappa_s, int64_t N,
+                                                    double* __restrict__ out) {
+    __shared__ double sh[4];
+    double m = 0.0, cap = 0.0, bad = 0.0;
+    for (int64_t i = threadIdx.x; i < N; i += blockDim.x) {
+        const float v = p[i];
+        const bool fr = is_free(mask, i);
+        if (!(v >= 0.f) || !isfinite(v) || (!fr && v != 0.f)) bad += 1.0;
+        else m += (double)v;
+        const float k = kappa ? kappa[i] : kappa_s;
+        if (!(k >= 0.f)) bad += 1.0;
+        else if (fr) cap += (double)k;
+    }
+    m = block_sum(m, sh);
+    if (threadIdx.x == 0) out[0] = m;
+    cap = block_sum(cap, sh);
+    if (threadIdx.x == 0) out[1] = cap;
+    bad = block_sum(bad, sh);
+    if (threadIdx.x == 0) out[2] = bad;
+}
+
+int grid_for(int64_t n) {
+    const int64_t b = (n + 255) / 256;
+    return (int)(b < 8192 ? (b > 0 ? b : 1) : 8192);
+}
+
+int chunk_log2(int64_t N) {
+    int lg = 2;                                   // at least 4 columns (ld is a multiple of 4)
+    while (lg < 10 && ((int64_t)1 << lg) < N) ++lg;
+    return lg;                                    // at most 1024 columns per chunk
+}
+
+template <int EK>
+hipError_t gemv_as(const HeatGemv& g, hipStream_t st) {
+    const int64_t waves = (g.N + kHeatRows - 1) / kHeatRows;
+    const int blocks = (int)((waves + 3) / 4);
+    hipLaunchKernelGGL(k_heat_gemv<EK>, dim3(blocks), dim3(256), 0, st, g);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int heat_cheb_iters(double beta) {
+    if (!(beta > 1.0)) return 0;
+    const double sk = sqrt(beta);
+    const double c = (sk - 1.0) / (sk + 1.0);
+    return (int)ceil(log(0.5e-14) / log(c));
+}
+
+int64_t heat_build_scratch(int64_t N) { return 4 * N * ((int64_t)1 << chunk_log2(N)); }
+
+hipError_t heat_build_operator(const uint8_t* mask, int n0, int n1, double gamma, int L, float* A, int64_t ld,
+                               double* scratch, hipStream_t st) {
+    const int64_t N = (int64_t)n0 * n1;
+    const int logC = chunk_log2(N);
+    const int64_t C = (int64_t)1 << logC;
+    const double nu0 = n0 > 1 ? gamma * (double)n0 * n0 / L : 0.0;
+    const double nu1 = n1 > 1 ? gamma * (double)n1 * n1 / L : 0.0;
+    const double beta = 1.0 + 4.0 * (nu0 + nu1);
+    const int K = heat_cheb_iters(beta);
+    const double theta = 0.5 * (beta + 1.0), delta = 0.5 * (beta - 1.0);
+    double* X = scratch;
+    double* R = X + N * C;
+    double* D[2] = {R + N * C, R + 2 * N * C};
+    const int gb = grid_for(N * C);
+    for (int64_t j0 = 0; j0 < ld; j0 += C) {
+        hipLaunchKernelGGL(k_heat_unit, dim3(gb), dim3(256), 0, st, X, mask, N, logC, j0);
+        for (int l = 0; l < L && K > 0; ++l) {
+            // solve M x = X from the first guess X
+            hipLaunchKernelGGL(k_heat_cheb_init, dim3(gb), dim3(256), 0, st, X, R, D[0], mask, N, logC, n0, n1,
+                               nu0, nu1, 1.0 / theta);
+            const double sigma1 = theta / delta;
+            double rho = 1.0 / sigma1;
+            for (int k = 0; k < K; ++k) {
+                const double rho_n = 1.0 / (2.0 * sigma1 - rho);
+                hipLaunchKernelGGL(k_heat_cheb_step, dim3(gb), dim3(256), 0, st, X, R, D[k & 1], D[(k + 1) & 1],
+                                   mask, N, logC, n0, n1, nu0, nu1, rho_n * rho, 2.0 * rho_n / delta);
+                rho = rho_n;
+            }
+        }
+        hipLaunchKernelGGL(k_heat_store, dim3(gb), dim3(256), 0, st, X, A, N, logC, ld, j0);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_heat_gemv(int ek, const HeatGemv& g, hipStream_t st) {
+    switch (ek) {
+        case EK_STORE: return gemv_as<EK_STORE>(g, st);
+        case EK_BUPDATE: return gemv_as<EK_BUPDATE>(g, st);
+        case EK_MONITOR: return gemv_as<EK_MONITOR>(g, st);
+        case EK_PROX + JKO_F_ZERO: return gemv_as<EK_PROX + JKO_F_ZERO>(g, st);
+        case EK_PROX + JKO_F_CONGESTION: return gemv_as<EK_PROX + JKO_F_CONGESTION>(g, st);
+        case EK_PROX + JKO_F_POROUS: return gemv_as<EK_PROX + JKO_F_POROUS>(g, st);
+        case EK_PROX + JKO_F_ENTROPY: return gemv_as<EK_PROX + JKO_F_ENTROPY>(g, st);
+        case EK_PROX + JKO_F_CONGESTION_BINARY: return gemv_as<EK_PROX + JKO_F_CONGESTION_BINARY>(g, st);
+        case EK_PROX + JKO_F_GEN_ENTROPY: return gemv_as<EK_PROX + JKO_F_GEN_ENTROPY>(g, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_heat_fill(float* x, float v, int64_t n, int64_t ld, hipStream_t st) {
+    hipLaunchKernelGGL(k_heat_fill, dim3(grid_for(ld)), dim3(256), 0, st, x, v, n, ld);
+    return hipGetLastError();
+}
+
+hipError_t launch_heat_copy_pad(float* x, const float* src, int64_t n, int64_t ld, hipStream_t st) {
+    hipLaunchKernelGGL(k_heat_copy_pad, dim3(grid_for(ld)), dim3(256), 0, st, x, src, n, ld);
+    return hipGetLastError();
+}
+
+hipError_t launch_heat_sums(const double* errrow, const float* p, int64_t N, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_heat_sums, dim3(1), dim3(256), 0, st, errrow, p, N, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_heat_input(const float* p, const uint8_t* mask, const float* kappa, float kappa_s, int64_t N,
+                             double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_heat_input, dim3(1), dim3(256), 0, st, p, mask, kappa, kappa_s, N, out);
+    return hipGetLastError();
+}
+
+}  // namespace jko

@@ -181,3 +181,50 @@ def test_binding_refuses_cpu_tensors():
     x = torch.zeros(8, 8)
     with pytest.raises(TypeError):
         jk.gibbs_apply(x, 1e-3)
+
+
+def test_heat_domain_layout_and_workspace(lib):
+    """The heat-kernel entry points: struct layout, workspace sizing (the
+    dense operator dominates: N^2 * 4 bytes), and argument errors refused on
+    the host before any HIP call."""
+    assert ctypes.sizeof(nat.HeatDomain) == 24
+    d = nat.HeatDomain(100, 100, None, 10)
+    nb = lib.jko_heat_workspace_bytes(ctypes.byref(d))
+    assert nb >= 10000 * 10000 * 4
+    assert lib.jko_heat_workspace_bytes(ctypes.byref(nat.HeatDomain(1, 9, None, 10))) > 0
+    for n0, n1 in ((0, 5), (5, 0), (300, 300)):
+        assert lib.jko_heat_workspace_bytes(ctypes.byref(nat.HeatDomain(n0, n1, None, 10))) == 0
+    assert lib.jko_heat_workspace_bytes(None) == 0
+    stream = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(0x1000)
+    # build: domain, L, gamma, workspace
+    assert lib.jko_heat_build(None, 1e-3, fake, nb, stream) == jk.JKO_ERR_INVALID
+    for L in (0, 1001):
+        assert lib.jko_heat_build(ctypes.byref(nat.HeatDomain(10, 10, None, L)), 1e-3, fake, nb,
+                                  stream) == jk.JKO_ERR_INVALID
+    for gamma in (0.0, -1.0, math.inf, math.nan):
+        assert lib.jko_heat_build(ctypes.byref(d), gamma, fake, nb, stream) == jk.JKO_ERR_INVALID
+    assert lib.jko_heat_build(ctypes.byref(d), 1e-3, None, nb, stream) == jk.JKO_ERR_WORKSPACE
+    assert lib.jko_heat_build(ctypes.byref(d), 1e-3, fake, nb - 1, stream) == jk.JKO_ERR_WORKSPACE
+    assert lib.jko_heat_apply(ctypes.byref(d), fake, fake, fake, nb, stream) == jk.JKO_ERR_INVALID
+    assert b"alias" in lib.jko_last_error()
+    # flow: energy, precision, log domain, steps, pointers
+    en = jk.EnergySpec(kind="congestion", kappa_scalar=1.0).to_c((100, 100))
+    p_in, p_out = ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000)
+
+    def flow(prm, e=en, n=1, a=p_in, b=p_out):
+        return lib.jko_heat_flow(ctypes.byref(d), ctypes.byref(e), ctypes.byref(prm), n, a, b, None, fake, nb,
+                                 stream)
+    prm = nat.make_params(1e-3, 1e-2, 10)
+    att = jk.EnergySpec(kind="attraction", kappa_scalar=1.0).to_c((100, 100))
+    att.target = fake
+    assert flow(prm, e=att) == jk.JKO_ERR_INVALID and b"attraction" in lib.jko_last_error()
+    assert flow(nat.make_params(1e-3, 1e-2, 10, precision="split_bf16")) == jk.JKO_ERR_INVALID
+    for thr in (0.0, 30.0, -math.inf):
+        assert flow(nat.make_params(1e-3, 1e-2, 10, absorb_threshold=thr)) == jk.JKO_ERR_INVALID
+    assert flow(prm, n=0) == jk.JKO_ERR_INVALID
+    assert flow(prm, a=p_in, b=p_in) == jk.JKO_ERR_INVALID
+    assert flow(prm, a=None) == jk.JKO_ERR_INVALID
+    bad = nat.make_params(1e-3, 1e-2, 10)
+    bad.max_iters = 0
+    assert flow(bad) == jk.JKO_ERR_INVALID

@@ -255,7 +255,8 @@ def heat_room(n0: int, n1: int, seed: int = 0, gamma=None, tau=None, L: int = 10
     the unit square with a wall across the first axis at x0 = 0.55 pierced by
     a door of width 0.16 around x1 = 0.5, and three square pillars in the
     start region.  The crowd starts as 4 Gaussian bumps (std 0.05) in
-    x0 < 0.45, the potential w is the geodesic distance (4-neighbour path
+    x0 < 0.45, their peaks cut to a plateau at a fifth of the highest one (mass
+    kept at 1), the potential w is the geodesic distance (4-neighbour path
     length, in units of the longer axis) to an exit at (0.95, 0.5), and the
     capacity is kappa = max p0 (the paper's choice).  gamma defaults to
     L / max(n)^2 (one heat-step weight nu = 1 on the longer axis), tau to
@@ -279,6 +280,7 @@ def heat_room(n0: int, n1: int, seed: int = 0, gamma=None, tau=None, L: int = 10
     p0 = gaussian_bumps(shape, centres, 0.05, rng.dirichlet(np.ones(4)))
     p0[~free] = 0.0
     p0 /= p0.sum()
+    p0 = project_capacity(p0, 0.2 * p0.max())     # peaks flattened: the capacity max p0 binds
     exit_cell = (min(int(0.95 * n0), n0 - 1), min(int(0.5 * n1), n1 - 1))
     w = _geodesic_steps(free, exit_cell) / max(shape)
     w[~np.isfinite(w)] = 0.0          # cells cut off from the exit (none in this room) and obstacles
