@@ -42,9 +42,11 @@ def _args():
     ap.add_argument("--no-extra", action="store_true", help="skip the 3D, split and adjoint extras")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--pmc-probe", choices=["crowd256", "crowd128c"], default=None,
+    ap.add_argument("--pmc-probe", choices=["crowd256", "crowd128c", "heat100"], default=None,
                     help="profiling probe: 50 fixed iterations of one step of the workload, "
                          "then a 64 MiB device copy of known size (counter calibration)")
+    ap.add_argument("--heat-leg", action="store_true",
+                    help="run only the heat-kernel leg (heat100) and print its JSON record")
     return ap.parse_args()
 
 
@@ -303,8 +305,16 @@ def pmc_probe(name, precision):
     wl = make_workload(name)
     en = _energy(wl)
     q = _dev(wl.p0)
-    iters = wl.max_iters if len(wl.shape) == 2 else 50
-    p, st = jk.step(q, en, wl.gamma, wl.tau, max_iters=iters, tol=0.0, precision=precision)
+    if name == "heat100":
+        # the operator build, then 30 iterations (60 operator passes)
+        import numpy as np
+        mask = torch.from_numpy(np.ascontiguousarray(wl.mask.astype(np.uint8))).cuda()
+        op = jk.HeatOperator(wl.shape, wl.gamma, wl.heat_L, mask=mask)
+        iters = 30
+        p, st = op.step(q, en, wl.tau, max_iters=iters)
+    else:
+        iters = wl.max_iters if len(wl.shape) == 2 else 50
+        p, st = jk.step(q, en, wl.gamma, wl.tau, max_iters=iters, tol=0.0, precision=precision)
     torch.cuda.synchronize()
     src = torch.ones(16 * 1024 * 1024, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
@@ -315,6 +325,27 @@ def pmc_probe(name, precision):
     torch.cuda.synchronize()
     print(json.dumps({"probe": name, "iterations": iters, "precision": precision,
                       "copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4}), flush=True)
+
+
+def heat_pass_traffic():
+    """Calibrated HBM bytes of one operator pass (b-update epilogue) from the
+    committed counter summary, or None when it is missing or the heat
+    kernels' sources changed since it was taken."""
+    import hashlib
+    import re
+    path = os.path.join(PROFILES, "heat_gemv_heat100.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    h = hashlib.sha256()
+    for f in ("jko_internal.h", "epilogue.h", "heat.h", "heat.hip"):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    m_h = re.search(r"^source_sha256:\s*([0-9a-f]{64})", txt, re.M)
+    m_t = re.search(r"^traffic_bytes_per_pass:\s*([0-9]+)", txt, re.M)
+    if not m_h or not m_t or m_h.group(1) != h.hexdigest():
+        return None
+    return int(m_t.group(1))
 
 
 def heat_bench(wl):
@@ -348,7 +379,7 @@ def heat_bench(wl):
     return {"iters_per_s": round(iters / el, 2), "jko_steps_per_s": round(wl.n_steps / el, 3),
             "iters_per_step": wl.max_iters, "operator_build_s": round(build, 3),
             "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
-                         "frac": round(achieved / 8000.0, 4), "traffic": None,
+                         "frac": round(achieved / 8000.0, 4), "traffic": heat_pass_traffic(),
                          "algorithmic_bytes_per_pass": per_pass,
                          "note": "whole-step rate over the timed steps (two operator passes per iteration)"}}
 
@@ -357,6 +388,12 @@ def main():
     args = _args()
     if args.pmc_probe:
         pmc_probe(args.pmc_probe, args.precision)
+        return
+    if args.heat_leg:
+        import paper_1502_06216_amd as jk
+        from workloads import make_workload
+        jk.load()
+        print(json.dumps({"heat100_fp32": heat_bench(make_workload("heat100"))}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
