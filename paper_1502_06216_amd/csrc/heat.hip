@@ -134,17 +134,40 @@ __device__ __forceinline__ void heat_epilogue(const HeatGemv& g, int64_t i, floa
     }
 }
 
-constexpr int kHeatRows = 2;   // rows per wave: each load of x serves both
+// Launch shape of an operator pass: on the 100x100 room two rows per wave,
+// two unrolled steps and non-temporal operator loads measured fastest among
+// 1/2/4 rows, unroll 2/4/8, plain or non-temporal loads, and one wave per
+// row group or a grid-stride grid of 1024/2048 blocks.
+#ifndef JKO_HEAT_ROWS
+#define JKO_HEAT_ROWS 2
+#endif
+#ifndef JKO_HEAT_NT
+#define JKO_HEAT_NT 1
+#endif
+#ifndef JKO_HEAT_UNROLL
+#define JKO_HEAT_UNROLL 2
+#endif
+#ifndef JKO_HEAT_PERSIST
+#define JKO_HEAT_PERSIST 0        // > 0: at most that many blocks, looping over the row groups
+#endif
+constexpr int kHeatRows = JKO_HEAT_ROWS;   // rows per wave: each load of x serves all of them
+
+// One float4 of an operator row: the operator is streamed once per pass
+// (optionally with the non-temporal hint, so that it does not displace x).
+__device__ __forceinline__ f4 ld_row(const f4* p) {
+#if JKO_HEAT_NT
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
 
 // One wave per kHeatRows consecutive rows: every lane streams float4 runs of
-// the rows (16-byte loads, 1 KiB per wave per row and step), sums them in
-// FP32, the wave reduces by butterflies, and lane r finishes row r.  Rows of
-// obstacle cells are all zero and are not read.
+// the rows (16-byte loads, 1 KiB per wave per row and step) against one load
+// of x, sums them in FP32, the wave reduces by butterflies, and lane r
+// finishes row r.  Rows of obstacle cells are all zero and are not read.
 template <int EK>
-__global__ void __launch_bounds__(256) k_heat_gemv(HeatGemv g) {
-    const int lane = threadIdx.x & 63;
-    const int64_t row0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kHeatRows;
-    if (row0 >= g.N) return;
+__device__ __forceinline__ void heat_rows(const HeatGemv& g, int64_t row0, int lane) {
     const int64_t n4 = g.ld >> 2;
     const f4* __restrict__ xv = reinterpret_cast<const f4*>(g.x);
     bool live[kHeatRows];
@@ -157,19 +180,22 @@ __global__ void __launch_bounds__(256) k_heat_gemv(HeatGemv g) {
         Ar[r] = reinterpret_cast<const f4*>(g.A + (live[r] ? i : row0) * g.ld);
         s[r] = f4{0.f, 0.f, 0.f, 0.f};
     }
-    if (live[0] && live[1]) {
-#pragma unroll 4
+    bool all = true;
+#pragma unroll
+    for (int r = 0; r < kHeatRows; ++r) all = all && live[r];
+    if (all) {
+#pragma unroll JKO_HEAT_UNROLL
         for (int64_t j = lane; j < n4; j += 64) {
             const f4 xj = xv[j];
-            s[0] += Ar[0][j] * xj;
-            s[1] += Ar[1][j] * xj;
+#pragma unroll
+            for (int r = 0; r < kHeatRows; ++r) s[r] += ld_row(Ar[r] + j) * xj;
         }
     } else {
 #pragma unroll
         for (int r = 0; r < kHeatRows; ++r)
             if (live[r]) {
-#pragma unroll 4
-                for (int64_t j = lane; j < n4; j += 64) s[r] += Ar[r][j] * xv[j];
+#pragma unroll JKO_HEAT_UNROLL
+                for (int64_t j = lane; j < n4; j += 64) s[r] += ld_row(Ar[r] + j) * xv[j];
             }
     }
     float v[kHeatRows];
@@ -182,6 +208,15 @@ __global__ void __launch_bounds__(256) k_heat_gemv(HeatGemv g) {
 #pragma unroll
     for (int r = 0; r < kHeatRows; ++r)
         if (lane == r && row0 + r < g.N) heat_epilogue<EK>(g, row0 + r, v[r]);
+}
+
+template <int EK>
+__global__ void __launch_bounds__(256) k_heat_gemv(HeatGemv g) {
+    const int lane = threadIdx.x & 63;
+    const int64_t groups = (g.N + kHeatRows - 1) / kHeatRows;
+    // every wave of the grid takes row groups blockIdx*4 + wave, then strides by the grid
+    for (int64_t grp = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); grp < groups; grp += (int64_t)gridDim.x * 4)
+        heat_rows<EK>(g, grp * kHeatRows, lane);
 }
 
 __global__ void k_heat_fill(float* __restrict__ x, float v, int64_t n, int64_t ld) {
@@ -250,7 +285,8 @@ int chunk_log2(int64_t N) {
 template <int EK>
 hipError_t gemv_as(const HeatGemv& g, hipStream_t st) {
     const int64_t waves = (g.N + kHeatRows - 1) / kHeatRows;
-    const int blocks = (int)((waves + 3) / 4);
+    int blocks = (int)((waves + 3) / 4);
+    if (JKO_HEAT_PERSIST > 0 && blocks > JKO_HEAT_PERSIST) blocks = JKO_HEAT_PERSIST;
     hipLaunchKernelGGL(k_heat_gemv<EK>, dim3(blocks), dim3(256), 0, st, g);
     return hipGetLastError();
 }
