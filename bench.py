@@ -328,12 +328,13 @@ def pmc_probe(name, precision):
 
 
 def heat_pass_traffic():
-    """Calibrated HBM bytes of one operator pass (b-update epilogue) from the
+    """Calibrated HBM bytes of one operator pass (tile pass plus b-update
+    finish) from the
     committed counter summary, or None when it is missing or the heat
     kernels' sources changed since it was taken."""
     import hashlib
     import re
-    path = os.path.join(PROFILES, "heat_gemv_heat100.md")
+    path = os.path.join(PROFILES, "heat_pass_heat100.md")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
@@ -352,8 +353,9 @@ def heat_bench(wl):
     """The heat-kernel Gibbs operator on an obstacle room (Section 4.1):
     operator build time, then n_steps timed JKO steps (one warm-up step
     first).  Each iteration is two passes over the stored operator; the
-    algorithmic bytes of a pass are the free rows of the float32 operator
-    plus three N-cell float32 fields of the epilogue."""
+    algorithmic bytes of a pass are its packed upper-triangular 128 x 128
+    float32 tiles, the tile partial sums written and read back, and three
+    N-cell float32 fields of the epilogue."""
     import numpy as np
     import torch
     import paper_1502_06216_amd as jk
@@ -373,8 +375,8 @@ def heat_bench(wl):
     el = time.perf_counter() - t0
     iters = sum(s["iters"] for s in sts)
     N = int(wl.mask.size)
-    ld = (N + 3) // 4 * 4
-    per_pass = int(wl.mask.sum()) * ld * 4 + 3 * N * 4
+    nT = (N + 127) // 128
+    per_pass = nT * (nT + 1) // 2 * 128 * 128 * 4 + 2 * nT * nT * 128 * 4 + 3 * N * 4
     achieved = 2 * per_pass * iters / el / 1e9
     return {"iters_per_s": round(iters / el, 2), "jko_steps_per_s": round(wl.n_steps / el, 3),
             "iters_per_step": wl.max_iters, "operator_build_s": round(build, 3),

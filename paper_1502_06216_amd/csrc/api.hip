@@ -1231,18 +1231,19 @@ struct HeatHdr {
 
 struct HeatLayout {
     int64_t N = 0, ld = 0;
-    size_t hdr = 0, A = 0, scratch = 0, a = 0, b = 0, x = 0, p0 = 0, p1 = 0, g = 0, kf = 0, err = 0, out = 0;
+    size_t hdr = 0, A = 0, part = 0, scratch = 0, a = 0, b = 0, x = 0, p0 = 0, p1 = 0, g = 0, kf = 0, err = 0, out = 0;
     size_t total = 0;
 };
 
 HeatLayout heat_layout(int n0, int n1) {
     HeatLayout H;
     H.N = (int64_t)n0 * n1;
-    H.ld = (H.N + 3) / 4 * 4;
+    H.ld = heat_ld(H.N);
     size_t o = 0;
     auto take = [&](size_t bytes) { const size_t at = o; o = align_up(o + bytes); return at; };
     H.hdr = take(sizeof(HeatHdr));
-    H.A = take((size_t)H.N * H.ld * sizeof(float));
+    H.A = take((size_t)heat_operator_floats(H.N) * sizeof(float));
+    H.part = take((size_t)heat_partial_floats(H.N) * sizeof(float));
     H.scratch = take((size_t)heat_build_scratch(H.N) * sizeof(double));
     H.a = take(H.ld * sizeof(float));
     H.b = take(H.ld * sizeof(float));
@@ -1312,6 +1313,8 @@ jko_status heat_step(const HeatLayout& H, char* base, const uint8_t* mask, const
     HIP_TRY(launch_heat_fill(b, 0.f, H.N, H.ld, st));
     HeatGemv gt{};
     gt.A = A;
+    gt.part = reinterpret_cast<float*>(base + H.part);
+    gt.nT = (int32_t)heat_ntiles(H.N);
     gt.ld = H.ld;
     gt.N = H.N;
     gt.mask = mask;
@@ -1408,6 +1411,8 @@ jko_status jko_heat_apply(const jko_heat_domain* domain, const float* x, float* 
     HIP_TRY(launch_heat_copy_pad(xp, x, H.N, H.ld, st));
     HeatGemv g{};
     g.A = reinterpret_cast<const float*>(base + H.A);
+    g.part = reinterpret_cast<float*>(base + H.part);
+    g.nT = (int32_t)heat_ntiles(H.N);
     g.ld = H.ld;
     g.N = H.N;
     g.mask = domain->mask;

@@ -4,23 +4,42 @@
 // xi~ = (Id - (gamma/L) Delta_M)^{-L} with Delta_M the no-flux five-point
 // Laplacian of the free cells (spacing 1/n_k along axis k), i.e.
 // Id + nu_0 G_0 + nu_1 G_1 with nu_k = gamma n_k^2 / L and G_k the graph
-// Laplacian of the free axis-k neighbour pairs.  The library stores xi~ as a
-// dense N x ld float32 matrix (row i = column i, the operator is symmetric;
-// rows and columns of obstacle cells are zero, padding columns N..ld-1 zero).
+// Laplacian of the free axis-k neighbour pairs.  xi~ is symmetric; the library
+// stores its upper triangle of kHeatTile x kHeatTile float32 tiles: tile
+// (I, J), I <= J, of the ld x ld matrix (ld = N rounded up to the tile) at
+// packed index I*nT - I*(I-1)/2 + (J - I), each tile row-major.  Rows and
+// columns of obstacle cells and of the padding are zero.
 #pragma once
 
 #include "jko_internal.h"
 
 namespace jko {
 
+constexpr int kHeatTile = 128;
+
+inline int64_t heat_ld(int64_t N) { return (N + kHeatTile - 1) / kHeatTile * kHeatTile; }
+inline int64_t heat_ntiles(int64_t N) { return heat_ld(N) / kHeatTile; }
+// floats of the packed upper-triangular tiles
+inline int64_t heat_operator_floats(int64_t N) {
+    const int64_t nT = heat_ntiles(N);
+    return nT * (nT + 1) / 2 * kHeatTile * kHeatTile;
+}
+// floats of the per-pass partial sums (one row block per tile pair)
+inline int64_t heat_partial_floats(int64_t N) {
+    const int64_t nT = heat_ntiles(N);
+    return nT * nT * kHeatTile;
+}
+
 // One application of the stored operator, y = A x, with the result of each
 // row finished by a pointwise epilogue (EK_STORE, EK_BUPDATE, EK_MONITOR or
 // EK_PROX + energy kind, as in the band contractions).
 struct HeatGemv {
-    const float* A;          // N x ld
-    int64_t ld;              // row stride, a multiple of 4, >= N
+    const float* A;          // packed upper-triangular tiles
+    float* part;             // heat_partial_floats(N) scratch
+    int32_t nT;              // tiles per side
+    int64_t ld;              // nT * kHeatTile
     int64_t N;               // cells
-    const uint8_t* mask;     // nonzero = free cell; NULL = all free (rows of obstacles are skipped)
+    const uint8_t* mask;     // nonzero = free cell; NULL = all free
     const float* x;          // ld floats, padding zero
     float* y;                // STORE: result
     const float* q;          // BUPDATE / MONITOR: the step's input density
@@ -39,8 +58,8 @@ int heat_cheb_iters(double beta);
 // Scratch doubles heat_build_operator needs for an N-cell grid (4 N C).
 int64_t heat_build_scratch(int64_t N);
 
-// Writes A = xi~ (all N x ld entries).  scratch: heat_build_scratch(N)
-// doubles.  Synchronous only in the sense of stream order.
+// Writes the packed tiles of xi~ (heat_operator_floats(N) floats).
+// scratch: heat_build_scratch(N) doubles.
 hipError_t heat_build_operator(const uint8_t* mask, int n0, int n1, double gamma, int L, float* A, int64_t ld,
                                double* scratch, hipStream_t st);
 

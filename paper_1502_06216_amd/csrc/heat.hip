@@ -4,10 +4,11 @@
 //
 // The paper applies xi~ = (Id - (gamma/L) Delta_M)^{-L} by L sparse
 // back-substitutions per product, a sequential sweep.  On this device the
-// operator of a grid of up to 2^16 cells fits HBM as a dense float32 matrix
-// (10^4 cells: 400 MB), so it is built once per (domain, gamma, L), and every
-// product of the iteration becomes one HBM-bound matrix-vector pass whose
-// rows run in parallel.
+// operator of a grid of up to 2^16 cells fits HBM as a dense float32 matrix,
+// so it is built once per (domain, gamma, L), and every product of the
+// iteration becomes one memory-bound pass over it whose tiles run in
+// parallel.  Only the upper triangle is stored (xi~ is symmetric): 10^4
+// cells take 207 MB, which fits the device's 256 MB last-level cache.
 //
 // Construction: the columns of xi~ are L successive solves of
 // M x = rhs, M = Id + nu_0 G_0 + nu_1 G_1, from unit vectors, all columns of
@@ -90,17 +91,32 @@ __global__ void k_heat_cheb_step(double* __restrict__ X, double* __restrict__ R,
     }
 }
 
-// A[i, j0 + c] = X[i, c] rounded to float32, for j0 + c < ld (columns at or
-// beyond N are zero in X).  xi~ is symmetric, so column j of the solves is
-// row j of A as well; the store writes it as column j.
+__global__ void k_heat_zero(float* __restrict__ A, int64_t n) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        A[e] = 0.f;
+}
+
+// Packed index of the upper-triangular tile (I, J), I <= J, of nT x nT.
+__host__ __device__ __forceinline__ int64_t tile_index(int64_t I, int64_t J, int64_t nT) {
+    return I * nT - I * (I - 1) / 2 + (J - I);
+}
+
+// Element (i, j0 + c) of xi~ = X[i, c] rounded to float32, stored where its
+// tile lies in the upper triangle (xi~ is symmetric: the solves give every
+// column, the lower half is the transpose).  Columns at or beyond N are zero
+// in X; rows at or beyond N are not in X and stay zero.
 __global__ void k_heat_store(const double* __restrict__ X, float* __restrict__ A, int64_t N, int logC, int64_t ld,
                              int64_t j0) {
     const int64_t n = N << logC;
     const int C = 1 << logC;
+    const int64_t nT = ld / kHeatTile;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = e >> logC;
         const int64_t j = j0 + (e & (C - 1));
-        if (j < ld) A[i * ld + j] = (float)X[e];
+        const int64_t I = i / kHeatTile, J = j / kHeatTile;
+        if (j < ld && I <= J)
+            A[tile_index(I, J, nT) * kHeatTile * kHeatTile + (i - I * kHeatTile) * kHeatTile + (j - J * kHeatTile)] =
+                (float)X[e];
     }
 }
 
@@ -134,27 +150,15 @@ __device__ __forceinline__ void heat_epilogue(const HeatGemv& g, int64_t i, floa
     }
 }
 
-// Launch shape of an operator pass: on the 100x100 room two rows per wave,
-// two unrolled steps and non-temporal operator loads measured fastest among
-// 1/2/4 rows, unroll 2/4/8, plain or non-temporal loads, and one wave per
-// row group or a grid-stride grid of 1024/2048 blocks.
-#ifndef JKO_HEAT_ROWS
-#define JKO_HEAT_ROWS 2
-#endif
+// Plain loads: the packed operator of the 100 x 100 room (207 MB) stays
+// largely resident in the last-level cache between passes; with the
+// non-temporal hint the pass ran 12 % slower (11.8 K against 13.4 K
+// iterations/s of the room's flow).
 #ifndef JKO_HEAT_NT
-#define JKO_HEAT_NT 1
+#define JKO_HEAT_NT 0
 #endif
-#ifndef JKO_HEAT_UNROLL
-#define JKO_HEAT_UNROLL 2
-#endif
-#ifndef JKO_HEAT_PERSIST
-#define JKO_HEAT_PERSIST 0        // > 0: at most that many blocks, looping over the row groups
-#endif
-constexpr int kHeatRows = JKO_HEAT_ROWS;   // rows per wave: each load of x serves all of them
-
-// One float4 of an operator row: the operator is streamed once per pass
-// (optionally with the non-temporal hint, so that it does not displace x).
-__device__ __forceinline__ f4 ld_row(const f4* p) {
+// One float4 of an operator tile, with the non-temporal hint when JKO_HEAT_NT.
+__device__ __forceinline__ f4 ld_nt(const f4* p) {
 #if JKO_HEAT_NT
     return __builtin_nontemporal_load(p);
 #else
@@ -162,61 +166,83 @@ __device__ __forceinline__ f4 ld_row(const f4* p) {
 #endif
 }
 
-// One wave per kHeatRows consecutive rows: every lane streams float4 runs of
-// the rows (16-byte loads, 1 KiB per wave per row and step) against one load
-// of x, sums them in FP32, the wave reduces by butterflies, and lane r
-// finishes row r.  Rows of obstacle cells are all zero and are not read.
-template <int EK>
-__device__ __forceinline__ void heat_rows(const HeatGemv& g, int64_t row0, int lane) {
-    const int64_t n4 = g.ld >> 2;
-    const f4* __restrict__ xv = reinterpret_cast<const f4*>(g.x);
-    bool live[kHeatRows];
-    const f4* __restrict__ Ar[kHeatRows];
-    f4 s[kHeatRows];
-#pragma unroll
-    for (int r = 0; r < kHeatRows; ++r) {
-        const int64_t i = row0 + r;
-        live[r] = i < g.N && is_free(g.mask, i);
-        Ar[r] = reinterpret_cast<const f4*>(g.A + (live[r] ? i : row0) * g.ld);
-        s[r] = f4{0.f, 0.f, 0.f, 0.f};
+// Tile pass: block b takes the packed tile (I, J), I <= J, and writes
+//   part[I][J] = A_IJ x_J             (its row sums, the tile's share of y_I)
+//   part[J][I] = A_IJ^T x_I  (I < J)  (its column sums, the share of y_J
+//                                      from the transposed lower tile)
+// so that every (row block, tile) slot of part is written exactly once.  A
+// tile row is 32 float4s: thread (group g, lane c) takes float4 c of rows
+// g, g + 8, ..., g + 120 (non-temporal loads), keeps one partial row sum per
+// row and four column sums in registers; the row partials are then summed
+// through LDS (one row per thread), the column sums over the 8 groups.
+__global__ void __launch_bounds__(256) k_heat_tiles(const float* __restrict__ A, const float* __restrict__ x,
+                                                    float* __restrict__ part, int nT) {
+    constexpr int T = kHeatTile, R = T / 8;
+    const int b = blockIdx.x;
+    int I = 0, start = 0;
+    while (start + (nT - I) <= b) {    // uniform over the block; at most nT steps
+        start += nT - I;
+        ++I;
     }
-    bool all = true;
+    const int J = I + (b - start);
+    const f4* __restrict__ tile = reinterpret_cast<const f4*>(A + (int64_t)b * T * T);
+    const int t = threadIdx.x, cl = t & 31, rg = t >> 5;
+    const f4 xj = reinterpret_cast<const f4*>(x + (int64_t)J * T)[cl];
+    const float* __restrict__ xi = x + (int64_t)I * T;
+    const bool off = I != J;
+    __shared__ float red[T][33];      // row partials, padded against bank conflicts
+    __shared__ f4 cols[8][32];
+    float rp[R];
+    f4 cacc = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int r = 0; r < kHeatRows; ++r) all = all && live[r];
-    if (all) {
-#pragma unroll JKO_HEAT_UNROLL
-        for (int64_t j = lane; j < n4; j += 64) {
-            const f4 xj = xv[j];
-#pragma unroll
-            for (int r = 0; r < kHeatRows; ++r) s[r] += ld_row(Ar[r] + j) * xj;
-        }
-    } else {
-#pragma unroll
-        for (int r = 0; r < kHeatRows; ++r)
-            if (live[r]) {
-#pragma unroll JKO_HEAT_UNROLL
-                for (int64_t j = lane; j < n4; j += 64) s[r] += ld_row(Ar[r] + j) * xv[j];
-            }
-    }
-    float v[kHeatRows];
-#pragma unroll
-    for (int r = 0; r < kHeatRows; ++r) {
-        float t = (s[r].x + s[r].y) + (s[r].z + s[r].w);
-        for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
-        v[r] = t;
+    for (int k = 0; k < R; ++k) {
+        const int r = rg + 8 * k;
+        const f4 a = ld_nt(tile + r * 32 + cl);
+        rp[k] = (a.x * xj.x + a.y * xj.y) + (a.z * xj.z + a.w * xj.w);
+        if (off) cacc += a * xi[r];
     }
 #pragma unroll
-    for (int r = 0; r < kHeatRows; ++r)
-        if (lane == r && row0 + r < g.N) heat_epilogue<EK>(g, row0 + r, v[r]);
+    for (int k = 0; k < R; ++k) red[rg + 8 * k][cl] = rp[k];
+    if (off) cols[rg][cl] = cacc;
+    __syncthreads();
+    if (t < T) {
+        float y = 0.f;
+#pragma unroll
+        for (int c = 0; c < 32; ++c) y += red[t][c];
+        part[((int64_t)I * nT + J) * T + t] = y;
+    } else if (off && t < T + 32) {
+        const int c = t - T;
+        f4 v = cols[0][c];
+#pragma unroll
+        for (int g = 1; g < 8; ++g) v += cols[g][c];
+        reinterpret_cast<f4*>(part + ((int64_t)J * nT + I) * T)[c] = v;
+    }
 }
 
+// Finish pass: y_i = the sum of the nT slots of i's row block, split over 8
+// slices (slice s takes slots s, s + 8, ...) whose results are added in slice
+// order, then the pointwise epilogue of row i.  A block takes 32 consecutive
+// cells x 8 slices.
 template <int EK>
-__global__ void __launch_bounds__(256) k_heat_gemv(HeatGemv g) {
-    const int lane = threadIdx.x & 63;
-    const int64_t groups = (g.N + kHeatRows - 1) / kHeatRows;
-    // every wave of the grid takes row groups blockIdx*4 + wave, then strides by the grid
-    for (int64_t grp = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); grp < groups; grp += (int64_t)gridDim.x * 4)
-        heat_rows<EK>(g, grp * kHeatRows, lane);
+__global__ void __launch_bounds__(256) k_heat_finish(HeatGemv g) {
+    __shared__ float red[8][33];
+    const int t = threadIdx.x, c = t & 31, sl = t >> 5;
+    const int64_t i = (int64_t)blockIdx.x * 32 + c;
+    float y = 0.f;
+    if (i < g.N) {
+        const int64_t I = i / kHeatTile, il = i - I * kHeatTile;
+        const float* __restrict__ p = g.part + I * g.nT * kHeatTile + il;
+#pragma unroll 4
+        for (int K = sl; K < g.nT; K += 8) y += p[(int64_t)K * kHeatTile];
+    }
+    red[sl][c] = y;
+    __syncthreads();
+    if (sl == 0 && i < g.N) {
+        float v = red[0][c];
+#pragma unroll
+        for (int q = 1; q < 8; ++q) v += red[q][c];
+        heat_epilogue<EK>(g, i, v);
+    }
 }
 
 __global__ void k_heat_fill(float* __restrict__ x, float v, int64_t n, int64_t ld) {
@@ -284,10 +310,9 @@ int chunk_log2(int64_t N) {
 
 template <int EK>
 hipError_t gemv_as(const HeatGemv& g, hipStream_t st) {
-    const int64_t waves = (g.N + kHeatRows - 1) / kHeatRows;
-    int blocks = (int)((waves + 3) / 4);
-    if (JKO_HEAT_PERSIST > 0 && blocks > JKO_HEAT_PERSIST) blocks = JKO_HEAT_PERSIST;
-    hipLaunchKernelGGL(k_heat_gemv<EK>, dim3(blocks), dim3(256), 0, st, g);
+    const int64_t tiles = (int64_t)g.nT * (g.nT + 1) / 2;
+    hipLaunchKernelGGL(k_heat_tiles, dim3((unsigned)tiles), dim3(256), 0, st, g.A, g.x, g.part, g.nT);
+    hipLaunchKernelGGL(k_heat_finish<EK>, dim3((unsigned)((g.N + 31) / 32)), dim3(256), 0, st, g);
     return hipGetLastError();
 }
 
@@ -312,6 +337,8 @@ hipError_t heat_build_operator(const uint8_t* mask, int n0, int n1, double gamma
     const double beta = 1.0 + 4.0 * (nu0 + nu1);
     const int K = heat_cheb_iters(beta);
     const double theta = 0.5 * (beta + 1.0), delta = 0.5 * (beta - 1.0);
+    hipLaunchKernelGGL(k_heat_zero, dim3(grid_for(heat_operator_floats(N))), dim3(256), 0, st, A,
+                       heat_operator_floats(N));
     double* X = scratch;
     double* R = X + N * C;
     double* D[2] = {R + N * C, R + 2 * N * C};
