@@ -207,3 +207,26 @@ def test_heat100_one_step_full_size():
     print(f"[gpu-test] heat100: rel-L1 {err:.2e}, marginal {st['marginal_l1']:.3e} vs {rst[0]['marginal_l1']:.3e}",
           flush=True)
     assert err <= TOL_FLOW
+
+
+def test_largest_grid():
+    """The largest grid the heat path takes (2^16 cells: a 256 x 256 room,
+    512 tiles a side, an 8.6 GB operator): a product and a 10-iteration
+    step against the oracle."""
+    banner("heat largest grid 256x256")
+    wl = heat_room(256, 256, seed=5)
+    op = _op(wl)
+    H = O.HeatKernel(wl.mask, wl.gamma, wl.heat_L)
+    rng = np.random.default_rng(11)
+    x = np.where(wl.mask, rng.uniform(size=wl.shape), 0.0)
+    y = host64(op.apply(dev(x)))
+    err = rel_l1(y, H(f32(x).astype(np.float64)))
+    g_en, o_en = energies(wl)
+    p, st = op.step(dev(wl.p0), g_en, wl.tau, max_iters=10)
+    q = f32(wl.p0).astype(np.float64)
+    ref, rst = O.jko_step(q, o_en, wl.gamma, wl.tau, 10, op=H)
+    errf = rel_l1(host64(p), ref)
+    print(f"[gpu-test] heat 256x256: operator rel-L1 {err:.2e}, step rel-L1 {errf:.2e}", flush=True)
+    assert err <= TOL_OP
+    assert errf <= TOL_FLOW
+    assert st["marginal_l1"] == pytest.approx(rst["marginal_l1"], rel=0.01)
