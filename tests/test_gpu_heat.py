@@ -230,3 +230,46 @@ def test_largest_grid():
     assert err <= TOL_OP
     assert errf <= TOL_FLOW
     assert st["marginal_l1"] == pytest.approx(rst["marginal_l1"], rel=0.01)
+
+
+def test_degenerate_domains():
+    """A single free cell (xi~ is the identity there: a step keeps the
+    density), a grid without obstacles (mask NULL) with L = 1, and a domain
+    cut in two by a wall (no mass crosses it), each against the oracle."""
+    banner("heat degenerate domains")
+    # one free cell
+    mask = np.zeros((5, 7), bool)
+    mask[2, 3] = True
+    op = jk.HeatOperator(mask.shape, 1e-2, 10, mask=_mask_dev(mask))
+    x = np.where(mask, 0.7, 0.0)
+    assert np.array_equal(host64(op.apply(dev(x))), f32(x).astype(np.float64))
+    p0 = np.where(mask, 1.0, 0.0)
+    p, st = op.step(dev(p0), jk.EnergySpec(kind="congestion", kappa_scalar=2.0), 1e-2, max_iters=5)
+    assert np.array_equal(host64(p), p0) and st["marginal_l1"] == 0.0
+    # no obstacles, one implicit step
+    shape, gamma = (30, 26), 0.02
+    op = jk.HeatOperator(shape, gamma, 1)
+    H = O.HeatKernel(np.ones(shape, bool), gamma, 1)
+    rng = np.random.default_rng(4)
+    q = rng.uniform(size=shape)
+    q /= q.sum()
+    en = jk.EnergySpec(kind="entropy", coef_scalar=0.5)
+    p, _ = op.step(dev(q), en, 2.5 * gamma, max_iters=20)
+    ref, _ = O.jko_step(f32(q).astype(np.float64), O.Energy(kind="entropy", coef_scalar=0.5), gamma, 2.5 * gamma,
+                        20, op=H)
+    assert rel_l1(host64(p), ref) <= TOL_FLOW
+    # a closed wall: two rooms, mass only on the left
+    mask = np.ones((20, 24), bool)
+    mask[:, 11] = False
+    wl = heat_room(20, 24, seed=6)
+    wl.mask = mask
+    wl.w = np.zeros(mask.shape)
+    p0 = np.where(mask & (np.arange(24)[None, :] < 11), 1.0, 0.0)
+    p0 /= p0.sum()
+    wl.p0 = p0
+    g_en, o_en = energies(wl)
+    op = _op(wl)
+    p, _ = op.step(dev(p0), g_en, wl.tau, max_iters=30)
+    ref, _ = _oracle_flow(wl, o_en, 1, 30)
+    assert host64(p)[:, 12:].max() == 0.0
+    assert rel_l1(host64(p), ref) <= TOL_FLOW
