@@ -354,8 +354,8 @@ def heat_bench(wl):
     operator build time, then n_steps timed JKO steps (one warm-up step
     first).  Each iteration is two passes over the stored operator; the
     algorithmic bytes of a pass are its packed upper-triangular 128 x 128
-    float32 tiles, the tile partial sums written and read back, and three
-    N-cell float32 fields of the epilogue."""
+    float32 tiles over the free cells, the tile partial sums written and
+    read back, and three float32 fields of the epilogue per free cell."""
     import numpy as np
     import torch
     import paper_1502_06216_amd as jk
@@ -374,9 +374,9 @@ def heat_bench(wl):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     iters = sum(s["iters"] for s in sts)
-    N = int(wl.mask.size)
-    nT = (N + 127) // 128
-    per_pass = nT * (nT + 1) // 2 * 128 * 128 * 4 + 2 * nT * nT * 128 * 4 + 3 * N * 4
+    nf = int(wl.mask.sum())
+    nT = (nf + 127) // 128
+    per_pass = nT * (nT + 1) // 2 * 128 * 128 * 4 + 2 * nT * nT * 128 * 4 + 3 * nf * 4
     achieved = 2 * per_pass * iters / el / 1e9
     return {"iters_per_s": round(iters / el, 2), "jko_steps_per_s": round(wl.n_steps / el, 3),
             "iters_per_step": wl.max_iters, "operator_build_s": round(build, 3),

@@ -269,10 +269,11 @@ jko_status jko_time_iteration(const jko_grid* grid, const jko_energy* energy, co
  *
  * The paper applies xi~ by L sparse back-substitutions per product.  This
  * library builds xi~ once per (domain, gamma, L) as a dense float32 matrix
- * in the workspace (N = n0 n1 <= 65536 cells; the upper triangle of 128 x
- * 128 tiles, about N^2 * 2 bytes: 207 MB at 100 x 100) by FP64 Chebyshev
- * solves on the device, then runs every product of the scaling iteration as
- * one pass over it.  The flow uses the
+ * in the workspace (N = n0 n1 <= 65536 cells; over the Nf free cells, the
+ * upper triangle of 128 x 128 tiles, about Nf^2 * 2 bytes: 187 MB for the
+ * 9556 free cells of a 100 x 100 room) by FP64 Chebyshev solves on the
+ * device, then runs every product of the scaling iteration as one pass over
+ * it.  The flow uses the
  * iteration and stop test of jko_step with xi replaced by xi~; float32 only,
  * no log domain, no backward.
  * ------------------------------------------------------------------------ */

@@ -1226,12 +1226,13 @@ constexpr int64_t kHeatMaxCells = 65536;
 struct HeatHdr {
     int32_t magic, n0, n1, L;
     double gamma;
-    int64_t ld;
+    int64_t nf;              // free cells (the operator's order)
 };
 
 struct HeatLayout {
     int64_t N = 0, ld = 0;
-    size_t hdr = 0, A = 0, part = 0, scratch = 0, a = 0, b = 0, x = 0, p0 = 0, p1 = 0, g = 0, kf = 0, err = 0, out = 0;
+    size_t hdr = 0, A = 0, part = 0, scratch = 0, cidx = 0, gidx = 0, a = 0, b = 0, x = 0, p0 = 0, p1 = 0, g = 0,
+           kf = 0, err = 0, out = 0;
     size_t total = 0;
 };
 
@@ -1245,6 +1246,8 @@ HeatLayout heat_layout(int n0, int n1) {
     H.A = take((size_t)heat_operator_floats(H.N) * sizeof(float));
     H.part = take((size_t)heat_partial_floats(H.N) * sizeof(float));
     H.scratch = take((size_t)heat_build_scratch(H.N) * sizeof(double));
+    H.cidx = take(H.N * sizeof(int32_t));
+    H.gidx = take(H.N * sizeof(int32_t));
     H.a = take(H.ld * sizeof(float));
     H.b = take(H.ld * sizeof(float));
     H.x = take(H.ld * sizeof(float));
@@ -1276,7 +1279,7 @@ jko_status heat_ws_check(const HeatLayout& H, void* ws, size_t ws_bytes) {
 
 // Reads the operator's record back and checks that it was built for this
 // domain (and, when gamma > 0, this gamma).  Synchronous.
-jko_status heat_hdr_check(const jko_heat_domain* d, const char* ws, double gamma, hipStream_t st) {
+jko_status heat_hdr_check(const jko_heat_domain* d, const char* ws, double gamma, hipStream_t st, int64_t* nf) {
     HIP_TRY(hipMemcpyAsync(g_rb.host, ws, sizeof(HeatHdr), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     HeatHdr h;
@@ -1285,11 +1288,13 @@ jko_status heat_hdr_check(const jko_heat_domain* d, const char* ws, double gamma
         return fail(JKO_ERR_INVALID, "heat: the workspace holds no operator of this domain (call jko_heat_build)");
     if (gamma > 0.0 && h.gamma != gamma)
         return fail(JKO_ERR_INVALID, "heat: operator built for gamma %.17g, params ask %.17g", h.gamma, gamma);
+    *nf = h.nf;
     return JKO_OK;
 }
 
-jko_status heat_sums(const double* err, const float* p, int64_t N, double* dev_out, hipStream_t st, double h[3]) {
-    HIP_TRY(launch_heat_sums(err, p, N, dev_out, st));
+jko_status heat_sums(const double* err, int64_t ne, const float* p, int64_t np, double* dev_out, hipStream_t st,
+                     double h[3]) {
+    HIP_TRY(launch_heat_sums(err, ne, p, np, dev_out, st));
     HIP_TRY(hipMemcpyAsync(g_rb.host, dev_out, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     memcpy(h, g_rb.host, 3 * sizeof(double));
@@ -1301,7 +1306,7 @@ jko_status heat_sums(const double* err, const float* p, int64_t N, double* dev_o
 // at iteration k > 1 with (k - 1) % check_every == 0 and tol > 0 the
 // violation ||b t - q||_1 of iteration k - 1 is summed, and the step returns
 // that iterate when it is at most tol.
-jko_status heat_step(const HeatLayout& H, char* base, const uint8_t* mask, const jko_params* pr,
+jko_status heat_step(const HeatLayout& H, char* base, int64_t nf, const jko_params* pr,
                      const ProxArgs& px, int kind, const float* q, float* p_out, jko_stats* st_out,
                      hipStream_t st) {
     const float* A = reinterpret_cast<const float*>(base + H.A);
@@ -1309,15 +1314,17 @@ jko_status heat_step(const HeatLayout& H, char* base, const uint8_t* mask, const
     float* b = reinterpret_cast<float*>(base + H.b);
     double* err = reinterpret_cast<double*>(base + H.err);
     double* dout = reinterpret_cast<double*>(base + H.out);
-    HIP_TRY(launch_heat_fill(a, 1.f, H.N, H.ld, st));
-    HIP_TRY(launch_heat_fill(b, 0.f, H.N, H.ld, st));
+    const int64_t ldf = heat_ld(nf);
+    HIP_TRY(launch_heat_fill(a, 1.f, nf, ldf, st));
+    HIP_TRY(launch_heat_fill(b, 0.f, nf, ldf, st));
+    HIP_TRY(launch_heat_fill(p_out, 0.f, 0, H.N, st));   // obstacles: never written by the passes
     HeatGemv gt{};
     gt.A = A;
     gt.part = reinterpret_cast<float*>(base + H.part);
-    gt.nT = (int32_t)heat_ntiles(H.N);
-    gt.ld = H.ld;
-    gt.N = H.N;
-    gt.mask = mask;
+    gt.nT = (int32_t)heat_ntiles(nf);
+    gt.ld = ldf;
+    gt.N = nf;
+    gt.gidx = reinterpret_cast<const int32_t*>(base + H.gidx);
     gt.x = a;
     gt.q = q;
     gt.b = b;
@@ -1335,7 +1342,7 @@ jko_status heat_step(const HeatLayout& H, char* base, const uint8_t* mask, const
         gt.check = tolmode && k > 1 && (k - 1) % pr->check_every == 0;
         HIP_TRY(launch_heat_gemv(HEAT_EK_BUPDATE, gt, st));
         if (gt.check) {
-            jko_status s = heat_sums(err, nullptr, H.N, dout, st, h);
+            jko_status s = heat_sums(err, nf, nullptr, 0, dout, st, h);
             if (s) return s;
             if (h[2] > 0.0) break;
             if (h[0] <= pr->tol_l1) {
@@ -1347,7 +1354,7 @@ jko_status heat_step(const HeatLayout& H, char* base, const uint8_t* mask, const
         HIP_TRY(launch_heat_gemv(HEAT_EK_PROX + kind, gs, st));
     }
     if (!bytol && h[2] == 0.0) HIP_TRY(launch_heat_gemv(HEAT_EK_MONITOR, gt, st));
-    jko_status s = heat_sums(err, p_out, H.N, dout, st, h);
+    jko_status s = heat_sums(err, nf, p_out, H.N, dout, st, h);
     if (s) return s;
     const bool bad = h[2] > 0.0 || !isfinite(h[0]) || !isfinite(h[1]);
     if (st_out) {
@@ -1384,10 +1391,18 @@ jko_status jko_heat_build(const jko_heat_domain* domain, double gamma, void* ws,
     if ((s = readback_init())) return s;
     hipStream_t st = static_cast<hipStream_t>(stream);
     char* base = static_cast<char*>(ws);
-    HIP_TRY(heat_build_operator(domain->mask, domain->n0, domain->n1, gamma, domain->L,
-                                reinterpret_cast<float*>(base + H.A), H.ld,
-                                reinterpret_cast<double*>(base + H.scratch), st));
-    HeatHdr h{kHeatMagic, domain->n0, domain->n1, domain->L, gamma, H.ld};
+    int32_t* cidx = reinterpret_cast<int32_t*>(base + H.cidx);
+    int32_t* gidx = reinterpret_cast<int32_t*>(base + H.gidx);
+    int64_t* dcount = reinterpret_cast<int64_t*>(base + H.out);
+    HIP_TRY(launch_heat_compact(domain->mask, H.N, cidx, gidx, dcount, st));
+    HIP_TRY(hipMemcpyAsync(g_rb.host, dcount, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    int64_t nf = 0;
+    memcpy(&nf, g_rb.host, sizeof nf);
+    HIP_TRY(heat_build_operator(domain->mask, domain->n0, domain->n1, gamma, domain->L, cidx, gidx, nf,
+                                reinterpret_cast<float*>(base + H.A), reinterpret_cast<double*>(base + H.scratch),
+                                st));
+    HeatHdr h{kHeatMagic, domain->n0, domain->n1, domain->L, gamma, nf};
     memcpy(g_rb.host, &h, sizeof h);
     HIP_TRY(hipMemcpyAsync(base + H.hdr, g_rb.host, sizeof h, hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -1406,16 +1421,19 @@ jko_status jko_heat_apply(const jko_heat_domain* domain, const float* x, float* 
     if ((s = readback_init())) return s;
     hipStream_t st = static_cast<hipStream_t>(stream);
     char* base = static_cast<char*>(ws);
-    if ((s = heat_hdr_check(domain, base + H.hdr, 0.0, st))) return s;
+    int64_t nf = 0;
+    if ((s = heat_hdr_check(domain, base + H.hdr, 0.0, st, &nf))) return s;
+    const int32_t* gidx = reinterpret_cast<const int32_t*>(base + H.gidx);
     float* xp = reinterpret_cast<float*>(base + H.x);
-    HIP_TRY(launch_heat_copy_pad(xp, x, H.N, H.ld, st));
+    HIP_TRY(launch_heat_gather(xp, x, gidx, nf, heat_ld(nf), st));
+    HIP_TRY(launch_heat_fill(y, 0.f, 0, H.N, st));        // obstacles
     HeatGemv g{};
     g.A = reinterpret_cast<const float*>(base + H.A);
     g.part = reinterpret_cast<float*>(base + H.part);
-    g.nT = (int32_t)heat_ntiles(H.N);
-    g.ld = H.ld;
-    g.N = H.N;
-    g.mask = domain->mask;
+    g.nT = (int32_t)heat_ntiles(nf);
+    g.ld = heat_ld(nf);
+    g.N = nf;
+    g.gidx = gidx;
     g.x = xp;
     g.y = y;
     HIP_TRY(launch_heat_gemv(HEAT_EK_STORE, g, st));
@@ -1441,7 +1459,8 @@ jko_status jko_heat_flow(const jko_heat_domain* domain, const jko_energy* energy
     if ((s = readback_init())) return s;
     hipStream_t st = static_cast<hipStream_t>(stream);
     char* base = static_cast<char*>(ws);
-    if ((s = heat_hdr_check(domain, base + H.hdr, params->gamma, st))) return s;
+    int64_t nf = 0;
+    if ((s = heat_hdr_check(domain, base + H.hdr, params->gamma, st, &nf))) return s;
     const double sigma = params->tau / params->gamma;
     float* fg = reinterpret_cast<float*>(base + H.g);
     float* fkf = reinterpret_cast<float*>(base + H.kf);
@@ -1466,7 +1485,7 @@ jko_status jko_heat_flow(const jko_heat_domain* domain, const jko_energy* energy
     jko_status worst = JKO_OK;
     for (int t = 0; t < n_steps; ++t) {
         float* out = (t == n_steps - 1) ? pT : reinterpret_cast<float*>(base + ((t % 2 == 0) ? H.p0 : H.p1));
-        s = heat_step(H, base, domain->mask, params, px, energy->kind, q, out, stats ? &stats[t] : nullptr, st);
+        s = heat_step(H, base, nf, params, px, energy->kind, q, out, stats ? &stats[t] : nullptr, st);
         if (s == JKO_ERR_NONFINITE) worst = s;
         else if (s) return s;
         q = out;

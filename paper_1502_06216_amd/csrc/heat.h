@@ -4,11 +4,14 @@
 // xi~ = (Id - (gamma/L) Delta_M)^{-L} with Delta_M the no-flux five-point
 // Laplacian of the free cells (spacing 1/n_k along axis k), i.e.
 // Id + nu_0 G_0 + nu_1 G_1 with nu_k = gamma n_k^2 / L and G_k the graph
-// Laplacian of the free axis-k neighbour pairs.  xi~ is symmetric; the library
-// stores its upper triangle of kHeatTile x kHeatTile float32 tiles: tile
-// (I, J), I <= J, of the ld x ld matrix (ld = N rounded up to the tile) at
+// Laplacian of the free axis-k neighbour pairs.  The operator acts on the
+// free cells only: they are numbered in row-major order (gidx: free index ->
+// grid cell, cidx: grid cell -> free index or -1), and xi~ is stored over
+// those Nf indices.  xi~ is symmetric; the library stores its upper triangle
+// of kHeatTile x kHeatTile float32 tiles: tile (I, J), I <= J, of the ld x ld
+// matrix (ld = Nf rounded up to the tile) at
 // packed index I*nT - I*(I-1)/2 + (J - I), each tile row-major.  Rows and
-// columns of obstacle cells and of the padding are zero.
+// columns of the padding are zero.
 #pragma once
 
 #include "jko_internal.h"
@@ -33,23 +36,34 @@ inline int64_t heat_partial_floats(int64_t N) {
 // One application of the stored operator, y = A x, with the result of each
 // row finished by a pointwise epilogue (EK_STORE, EK_BUPDATE, EK_MONITOR or
 // EK_PROX + energy kind, as in the band contractions).
+// Row r of the pass is free cell gidx[r]: x, b, a and errrow are indexed by
+// r (free-cell vectors), y, q, p and the energy fields by the grid cell.
 struct HeatGemv {
     const float* A;          // packed upper-triangular tiles
     float* part;             // heat_partial_floats(N) scratch
     int32_t nT;              // tiles per side
     int64_t ld;              // nT * kHeatTile
-    int64_t N;               // cells
-    const uint8_t* mask;     // nonzero = free cell; NULL = all free
+    int64_t N;               // rows: free cells
+    const int32_t* gidx;     // free index -> grid cell
     const float* x;          // ld floats, padding zero
-    float* y;                // STORE: result
-    const float* q;          // BUPDATE / MONITOR: the step's input density
+    float* y;                // STORE: result (grid)
+    const float* q;          // BUPDATE / MONITOR: the step's input density (grid)
     float* b;                // BUPDATE: b = q / y (0/0 = 0); MONITOR: read
     double* errrow;          // BUPDATE (when check) / MONITOR: |b_old y - q| per row
     int32_t check;
     float* a;                // PROX: a = p / y (0/0 = 0)
-    float* p;                // PROX: p = Prox(y)
-    ProxArgs px;
+    float* p;                // PROX: p = Prox(y) (grid)
+    ProxArgs px;             // fields indexed by grid cell
 };
+
+// Numbers the free cells in row-major order: cidx (N), gidx (first Nf
+// entries), *count (device int64) = Nf.  One block.
+hipError_t launch_heat_compact(const uint8_t* mask, int64_t N, int32_t* cidx, int32_t* gidx, int64_t* count,
+                               hipStream_t st);
+
+// x[r] = src[gidx[r]] for r < nf, 0 up to ld.
+hipError_t launch_heat_gather(float* x, const float* src, const int32_t* gidx, int64_t nf, int64_t ld,
+                              hipStream_t st);
 
 // Chebyshev iterations per implicit step that bring the error of each solve
 // below 1e-14 of the right-hand side for the spectrum [1, beta].
@@ -58,10 +72,10 @@ int heat_cheb_iters(double beta);
 // Scratch doubles heat_build_operator needs for an N-cell grid (4 N C).
 int64_t heat_build_scratch(int64_t N);
 
-// Writes the packed tiles of xi~ (heat_operator_floats(N) floats).
-// scratch: heat_build_scratch(N) doubles.
-hipError_t heat_build_operator(const uint8_t* mask, int n0, int n1, double gamma, int L, float* A, int64_t ld,
-                               double* scratch, hipStream_t st);
+// Writes the packed tiles of xi~ over the nf free cells (heat_operator_floats(nf)
+// floats).  scratch: heat_build_scratch(N) doubles.
+hipError_t heat_build_operator(const uint8_t* mask, int n0, int n1, double gamma, int L, const int32_t* cidx,
+                               const int32_t* gidx, int64_t nf, float* A, double* scratch, hipStream_t st);
 
 // Epilogue codes of launch_heat_gemv: store, b-update, monitor, and the
 // proximal epilogue HEAT_EK_PROX + energy kind (the band contractions' codes).
@@ -75,9 +89,11 @@ hipError_t launch_heat_fill(float* x, float v, int64_t n, int64_t ld, hipStream_
 // x[0..n) = src, x[n..ld) = 0
 hipError_t launch_heat_copy_pad(float* x, const float* src, int64_t n, int64_t ld, hipStream_t st);
 
-// out[0] = sum errrow (when errrow != NULL), out[1] = sum p (when p != NULL),
-// out[2] = number of non-finite errrow entries.  One block, fixed order.
-hipError_t launch_heat_sums(const double* errrow, const float* p, int64_t N, double* out, hipStream_t st);
+// out[0] = sum of errrow[0..ne) (when errrow != NULL), out[1] = sum of
+// p[0..np) (when p != NULL), out[2] = number of non-finite errrow entries.
+// One block, fixed order.
+hipError_t launch_heat_sums(const double* errrow, int64_t ne, const float* p, int64_t np, double* out,
+                            hipStream_t st);
 
 // Input check of a step's density: out[0] = mass, out[1] = capacity over the
 // free cells (kappa field or kappa_s; +inf allowed), out[2] = number of

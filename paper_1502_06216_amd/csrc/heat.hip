@@ -46,15 +46,16 @@ __device__ __forceinline__ double heat_mx(const double* __restrict__ x, const ui
     return acc;
 }
 
-// X = the unit columns j0 .. j0+C-1 (only those of free cells below N).
-__global__ void k_heat_unit(double* __restrict__ X, const uint8_t* __restrict__ mask, int64_t N, int logC,
-                            int64_t j0) {
+// X = the unit columns of free cells j0 .. j0+C-1 (grid cell gidx[j]; none
+// at or beyond nf).
+__global__ void k_heat_unit(double* __restrict__ X, const int32_t* __restrict__ gidx, int64_t nf, int64_t N,
+                            int logC, int64_t j0) {
     const int64_t n = N << logC;
     const int C = 1 << logC;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = e >> logC;
         const int64_t j = j0 + (e & (C - 1));
-        X[e] = (i == j && is_free(mask, i)) ? 1.0 : 0.0;
+        X[e] = (j < nf && i == gidx[j]) ? 1.0 : 0.0;
     }
 }
 
@@ -101,36 +102,78 @@ __host__ __device__ __forceinline__ int64_t tile_index(int64_t I, int64_t J, int
     return I * nT - I * (I - 1) / 2 + (J - I);
 }
 
-// Element (i, j0 + c) of xi~ = X[i, c] rounded to float32, stored where its
-// tile lies in the upper triangle (xi~ is symmetric: the solves give every
-// column, the lower half is the transpose).  Columns at or beyond N are zero
-// in X; rows at or beyond N are not in X and stay zero.
-__global__ void k_heat_store(const double* __restrict__ X, float* __restrict__ A, int64_t N, int logC, int64_t ld,
-                             int64_t j0) {
+// Element (free row cidx[i], free column j0 + c) of xi~ = X[i, c] rounded to
+// float32, stored where its tile lies in the upper triangle (xi~ is
+// symmetric: the solves give every column, the lower half is the
+// transpose).  Columns at or beyond nf are zero in X; padding rows are never
+// written and stay zero.
+__global__ void k_heat_store(const double* __restrict__ X, float* __restrict__ A, const int32_t* __restrict__ cidx,
+                             int64_t N, int logC, int64_t ld, int64_t j0) {
     const int64_t n = N << logC;
     const int C = 1 << logC;
     const int64_t nT = ld / kHeatTile;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = e >> logC;
+        const int64_t r = cidx[i];
         const int64_t j = j0 + (e & (C - 1));
-        const int64_t I = i / kHeatTile, J = j / kHeatTile;
-        if (j < ld && I <= J)
-            A[tile_index(I, J, nT) * kHeatTile * kHeatTile + (i - I * kHeatTile) * kHeatTile + (j - J * kHeatTile)] =
+        const int64_t I = r / kHeatTile, J = j / kHeatTile;
+        if (r >= 0 && j < ld && I <= J)
+            A[tile_index(I, J, nT) * kHeatTile * kHeatTile + (r - I * kHeatTile) * kHeatTile + (j - J * kHeatTile)] =
                 (float)X[e];
     }
 }
 
+// Free cells in row-major order: each of the 256 threads counts a contiguous
+// run of cells, an exclusive scan of the counts gives each run's first free
+// index, and the runs are numbered in order.
+__global__ void __launch_bounds__(256) k_heat_compact(const uint8_t* __restrict__ mask, int64_t N,
+                                                      int32_t* __restrict__ cidx, int32_t* __restrict__ gidx,
+                                                      int64_t* __restrict__ count) {
+    __shared__ int64_t base[257];
+    const int t = threadIdx.x;
+    const int64_t per = (N + 255) / 256;
+    const int64_t lo = t * per < N ? t * per : N, hi = lo + per < N ? lo + per : N;
+    int64_t c = 0;
+    for (int64_t i = lo; i < hi; ++i) c += is_free(mask, i) ? 1 : 0;
+    base[t + 1] = c;
+    __syncthreads();
+    if (t == 0) {
+        base[0] = 0;
+        for (int k = 1; k <= 256; ++k) base[k] += base[k - 1];
+        *count = base[256];
+    }
+    __syncthreads();
+    int64_t r = base[t];
+    for (int64_t i = lo; i < hi; ++i) {
+        if (is_free(mask, i)) {
+            cidx[i] = (int32_t)r;
+            gidx[r] = (int32_t)i;
+            ++r;
+        } else {
+            cidx[i] = -1;
+        }
+    }
+}
+
+__global__ void k_heat_gather(float* __restrict__ x, const float* __restrict__ src, const int32_t* __restrict__ gidx,
+                              int64_t nf, int64_t ld) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < ld; r += (int64_t)gridDim.x * blockDim.x)
+        x[r] = r < nf ? src[gidx[r]] : 0.f;
+}
+
 // ------------------------------------------------------------------ products
 
-// Finish row i of y = A x (value v): the epilogue of the iteration's half-step.
+// Finish row r (free cell i = gidx[r]) of y = A x (value v): the epilogue of
+// the iteration's half-step.
 template <int EK>
-__device__ __forceinline__ void heat_epilogue(const HeatGemv& g, int64_t i, float v) {
+__device__ __forceinline__ void heat_epilogue(const HeatGemv& g, int64_t r, float v) {
+    const int64_t i = g.gidx[r];
     if constexpr (EK == EK_STORE) {
         g.y[i] = v;
     } else if constexpr (EK == EK_BUPDATE || EK == EK_MONITOR) {
         const float q = g.q[i];
-        if (EK == EK_MONITOR || g.check) g.errrow[i] = fabs((double)g.b[i] * (double)v - (double)q);
-        if (EK == EK_BUPDATE) g.b[i] = q == 0.f ? 0.f : q / v;
+        if (EK == EK_MONITOR || g.check) g.errrow[r] = fabs((double)g.b[r] * (double)v - (double)q);
+        if (EK == EK_BUPDATE) g.b[r] = q == 0.f ? 0.f : q / v;
     } else {
         constexpr int KIND = EK - EK_PROX;
         const ProxArgs& px = g.px;
@@ -145,7 +188,7 @@ __device__ __forceinline__ void heat_epilogue(const HeatGemv& g, int64_t i, floa
             pv = px.g ? px.g[i] : px.eps_s;
         }
         const float p = prox_val<KIND>(px, v, pu, pv);
-        g.a[i] = p == 0.f ? 0.f : p / v;
+        g.a[r] = p == 0.f ? 0.f : p / v;
         g.p[i] = p;
     }
 }
@@ -255,18 +298,18 @@ __global__ void k_heat_copy_pad(float* __restrict__ x, const float* __restrict__
         x[i] = i < n ? src[i] : 0.f;
 }
 
-__global__ void __launch_bounds__(256) k_heat_sums(const double* __restrict__ errrow, const float* __restrict__ p,
-                                                   int64_t N, double* __restrict__ out) {
+__global__ void __launch_bounds__(256) k_heat_sums(const double* __restrict__ errrow, int64_t ne,
+                                                   const float* __restrict__ p, int64_t np, double* __restrict__ out) {
     __shared__ double sh[4];
     double e = 0.0, m = 0.0, bad = 0.0;
-    for (int64_t i = threadIdx.x; i < N; i += blockDim.x) {
-        if (errrow) {
+    if (errrow)
+        for (int64_t i = threadIdx.x; i < ne; i += blockDim.x) {
             const double v = errrow[i];
             if (isfinite(v)) e += v;
             else bad += 1.0;
         }
-        if (p) m += (double)p[i];
-    }
+    if (p)
+        for (int64_t i = threadIdx.x; i < np; i += blockDim.x) m += (double)p[i];
     e = block_sum(e, sh);
     if (threadIdx.x == 0) out[0] = e;
     m = block_sum(m, sh);
@@ -310,6 +353,7 @@ int chunk_log2(int64_t N) {
 
 template <int EK>
 hipError_t gemv_as(const HeatGemv& g, hipStream_t st) {
+    if (g.nT == 0) return hipSuccess;   // no free cell
     const int64_t tiles = (int64_t)g.nT * (g.nT + 1) / 2;
     hipLaunchKernelGGL(k_heat_tiles, dim3((unsigned)tiles), dim3(256), 0, st, g.A, g.x, g.part, g.nT);
     hipLaunchKernelGGL(k_heat_finish<EK>, dim3((unsigned)((g.N + 31) / 32)), dim3(256), 0, st, g);
@@ -327,9 +371,10 @@ int heat_cheb_iters(double beta) {
 
 int64_t heat_build_scratch(int64_t N) { return 4 * N * ((int64_t)1 << chunk_log2(N)); }
 
-hipError_t heat_build_operator(const uint8_t* mask, int n0, int n1, double gamma, int L, float* A, int64_t ld,
-                               double* scratch, hipStream_t st) {
+hipError_t heat_build_operator(const uint8_t* mask, int n0, int n1, double gamma, int L, const int32_t* cidx,
+                               const int32_t* gidx, int64_t nf, float* A, double* scratch, hipStream_t st) {
     const int64_t N = (int64_t)n0 * n1;
+    const int64_t ld = heat_ld(nf);
     const int logC = chunk_log2(N);
     const int64_t C = (int64_t)1 << logC;
     const double nu0 = n0 > 1 ? gamma * (double)n0 * n0 / L : 0.0;
@@ -337,14 +382,14 @@ hipError_t heat_build_operator(const uint8_t* mask, int n0, int n1, double gamma
     const double beta = 1.0 + 4.0 * (nu0 + nu1);
     const int K = heat_cheb_iters(beta);
     const double theta = 0.5 * (beta + 1.0), delta = 0.5 * (beta - 1.0);
-    hipLaunchKernelGGL(k_heat_zero, dim3(grid_for(heat_operator_floats(N))), dim3(256), 0, st, A,
-                       heat_operator_floats(N));
+    hipLaunchKernelGGL(k_heat_zero, dim3(grid_for(heat_operator_floats(nf))), dim3(256), 0, st, A,
+                       heat_operator_floats(nf));
     double* X = scratch;
     double* R = X + N * C;
     double* D[2] = {R + N * C, R + 2 * N * C};
     const int gb = grid_for(N * C);
     for (int64_t j0 = 0; j0 < ld; j0 += C) {
-        hipLaunchKernelGGL(k_heat_unit, dim3(gb), dim3(256), 0, st, X, mask, N, logC, j0);
+        hipLaunchKernelGGL(k_heat_unit, dim3(gb), dim3(256), 0, st, X, gidx, nf, N, logC, j0);
         for (int l = 0; l < L && K > 0; ++l) {
             // solve M x = X from the first guess X
             hipLaunchKernelGGL(k_heat_cheb_init, dim3(gb), dim3(256), 0, st, X, R, D[0], mask, N, logC, n0, n1,
@@ -358,7 +403,7 @@ hipError_t heat_build_operator(const uint8_t* mask, int n0, int n1, double gamma
                 rho = rho_n;
             }
         }
-        hipLaunchKernelGGL(k_heat_store, dim3(gb), dim3(256), 0, st, X, A, N, logC, ld, j0);
+        hipLaunchKernelGGL(k_heat_store, dim3(gb), dim3(256), 0, st, X, A, cidx, N, logC, ld, j0);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -390,14 +435,27 @@ hipError_t launch_heat_copy_pad(float* x, const float* src, int64_t n, int64_t l
     return hipGetLastError();
 }
 
-hipError_t launch_heat_sums(const double* errrow, const float* p, int64_t N, double* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_heat_sums, dim3(1), dim3(256), 0, st, errrow, p, N, out);
+hipError_t launch_heat_sums(const double* errrow, int64_t ne, const float* p, int64_t np, double* out,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(k_heat_sums, dim3(1), dim3(256), 0, st, errrow, ne, p, np, out);
     return hipGetLastError();
 }
 
 hipError_t launch_heat_input(const float* p, const uint8_t* mask, const float* kappa, float kappa_s, int64_t N,
                              double* out, hipStream_t st) {
     hipLaunchKernelGGL(k_heat_input, dim3(1), dim3(256), 0, st, p, mask, kappa, kappa_s, N, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_heat_compact(const uint8_t* mask, int64_t N, int32_t* cidx, int32_t* gidx, int64_t* count,
+                               hipStream_t st) {
+    hipLaunchKernelGGL(k_heat_compact, dim3(1), dim3(256), 0, st, mask, N, cidx, gidx, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_heat_gather(float* x, const float* src, const int32_t* gidx, int64_t nf, int64_t ld,
+                              hipStream_t st) {
+    hipLaunchKernelGGL(k_heat_gather, dim3(grid_for(ld)), dim3(256), 0, st, x, src, gidx, nf, ld);
     return hipGetLastError();
 }
 
