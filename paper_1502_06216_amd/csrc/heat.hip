@@ -7,8 +7,9 @@
 // operator of a grid of up to 2^16 cells fits HBM as a dense float32 matrix,
 // so it is built once per (domain, gamma, L), and every product of the
 // iteration becomes one memory-bound pass over it whose tiles run in
-// parallel.  Only the upper triangle is stored (xi~ is symmetric): 10^4
-// cells take 207 MB, which fits the device's 256 MB last-level cache.
+// parallel.  The operator acts on the free cells only, and only its upper
+// triangle is stored (xi~ is symmetric): the 9556 free cells of a 100 x 100
+// room take 187 MB, which fits the device's 256 MB last-level cache.
 //
 // Construction: the columns of xi~ are L successive solves of
 // M x = rhs, M = Id + nu_0 G_0 + nu_1 G_1, from unit vectors, all columns of
@@ -193,10 +194,10 @@ __device__ __forceinline__ void heat_epilogue(const HeatGemv& g, int64_t r, floa
     }
 }
 
-// Plain loads: the packed operator of the 100 x 100 room (207 MB) stays
-// largely resident in the last-level cache between passes; with the
-// non-temporal hint the pass ran 12 % slower (11.8 K against 13.4 K
-// iterations/s of the room's flow).
+// Plain loads: the packed operator of a 100 x 100 room stays largely
+// resident in the last-level cache between passes; with the non-temporal
+// hint the room's flow ran 12 % slower (measured on the full-grid operator:
+// 11.8 K against 13.4 K iterations/s).
 #ifndef JKO_HEAT_NT
 #define JKO_HEAT_NT 0
 #endif
