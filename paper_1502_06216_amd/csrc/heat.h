@@ -86,8 +86,6 @@ hipError_t launch_heat_gemv(int ek, const HeatGemv& g, hipStream_t st);
 // x[0..n) = v, x[n..ld) = 0
 hipError_t launch_heat_fill(float* x, float v, int64_t n, int64_t ld, hipStream_t st);
 
-// x[0..n) = src, x[n..ld) = 0
-hipError_t launch_heat_copy_pad(float* x, const float* src, int64_t n, int64_t ld, hipStream_t st);
 
 // out[0] = sum of errrow[0..ne) (when errrow != NULL), out[1] = sum of
 // p[0..np) (when p != NULL), out[2] = number of non-finite errrow entries.

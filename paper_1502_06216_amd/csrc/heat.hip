@@ -294,11 +294,6 @@ __global__ void k_heat_fill(float* __restrict__ x, float v, int64_t n, int64_t l
         x[i] = i < n ? v : 0.f;
 }
 
-__global__ void k_heat_copy_pad(float* __restrict__ x, const float* __restrict__ src, int64_t n, int64_t ld) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ld; i += (int64_t)gridDim.x * blockDim.x)
-        x[i] = i < n ? src[i] : 0.f;
-}
-
 __global__ void __launch_bounds__(256) k_heat_sums(const double* __restrict__ errrow, int64_t ne,
                                                    const float* __restrict__ p, int64_t np, double* __restrict__ out) {
     __shared__ double sh[4];
@@ -347,7 +342,7 @@ int grid_for(int64_t n) {
 }
 
 int chunk_log2(int64_t N) {
-    int lg = 2;                                   // at least 4 columns (ld is a multiple of 4)
+    int lg = 2;                                   // at least 4 columns
     while (lg < 10 && ((int64_t)1 << lg) < N) ++lg;
     return lg;                                    // at most 1024 columns per chunk
 }
@@ -428,11 +423,6 @@ hipError_t launch_heat_gemv(int ek, const HeatGemv& g, hipStream_t st) {
 
 hipError_t launch_heat_fill(float* x, float v, int64_t n, int64_t ld, hipStream_t st) {
     hipLaunchKernelGGL(k_heat_fill, dim3(grid_for(ld)), dim3(256), 0, st, x, v, n, ld);
-    return hipGetLastError();
-}
-
-hipError_t launch_heat_copy_pad(float* x, const float* src, int64_t n, int64_t ld, hipStream_t st) {
-    hipLaunchKernelGGL(k_heat_copy_pad, dim3(grid_for(ld)), dim3(256), 0, st, x, src, n, ld);
     return hipGetLastError();
 }
 
