@@ -19,18 +19,23 @@
  * half-step (JKO_F_ATTRACTION keeps two such couplings, described with the
  * energies).  xi is applied as per-axis dense contractions with the factor
  * K1[i][j] = exp(-(x_i - x_j)^2 / gamma) (the separable Gaussian kernel of
- * Section 4.1), exactly (no truncation, no boundary condition).
+ * Section 4.1), exactly (no truncation, no boundary condition).  On a
+ * non-convex 2D domain (a grid with obstacles) the jko_heat_* calls replace
+ * xi by the heat kernel of Section 4.1 (eq. heat-kernel), described with
+ * them below.
  *
  * Conventions shared by every entry point:
  *  - Fields are contiguous float32 arrays in row-major order
  *    n[0] x ... x n[ndim-1] (last axis fastest), N = prod n[k] cells.
  *  - Every float / double pointer argument named as a field, and the
  *    workspace, is a DEVICE pointer on the current HIP device; pointers to
- *    jko_grid / jko_energy / jko_params / jko_stats structs, and the
+ *    jko_grid / jko_heat_domain / jko_energy / jko_params / jko_stats
+ *    structs, and the
  *    iters_per_step array of jko_backward, are HOST pointers.
  *  - The caller owns every buffer.  The library never allocates device
  *    memory: all scratch lives in the caller's workspace, whose size is given
- *    by jko_workspace_bytes().  It keeps one small pinned host buffer and one
+ *    by jko_workspace_bytes() (jko_heat_workspace_bytes() for the heat
+ *    kernel).  It keeps one small pinned host buffer and one
  *    event per process for its stop-test read-back.
  *  - All work is ordered on `stream` (a hipStream_t; NULL = default stream).
  *    A call returns before its kernels finish unless it must read a device
