@@ -8,18 +8,22 @@ iteration counts, and differentiated by torch autograd.  The JKO flow
 (Listing 1, step 2).
 
 Energies: ``zero``, ``congestion`` (Proposition 4.1; the clamp takes the
-capped branch on ties), ``entropy`` (Proposition 4.2, m = 1) and
+capped branch on ties), ``entropy`` (Proposition 4.2, m = 1),
 ``gen_entropy`` (Proposition 4.2 with per-cell weights and exponents): its
 prox is the oracle's exact Lambert-W root, differentiated through the
 implicit function theorem on eq. prox-psi,
-d log psi / d log s = 1 / (1 + sigma b m psi^{m-1}) (psi = D p).
+d log psi / d log s = 1 / (1 + sigma b m psi^{m-1}) (psi = D p), and
+``porous`` (f = sum c (D p)^m / ((m-1) D)): its prox is the exact Lambert-W
+root psi of log psi + k psi^{m-1} = log s, k = sigma c m D^{m-1} / (m-1) (the
+first-order condition of the KL prox, as in Proposition 4.2), differentiated
+the same way: d psi / d s = psi / (s (1 + (m-1) k psi^{m-1})).
 """
 from __future__ import annotations
 
 import numpy as np
 import torch
 
-from .jko_oracle import log_prox_gen_entropy
+from .jko_oracle import log_prox_gen_entropy, prox_porous
 
 
 def _centres(n):
@@ -67,6 +71,28 @@ class _GenEntropyProx(torch.autograd.Function):
         return ds, None, db, None, None
 
 
+class _PorousProx(torch.autograd.Function):
+    """p = Prox^KL_{sigma f}(s) for the porous-medium energy: the exact root
+    psi of log psi + k psi^{m-1} = log s (values from the oracle's Lambert-W
+    form), with the derivative in s from the implicit function theorem on that
+    equation, d psi / d s = psi / (s (1 + (m-1) k psi^{m-1})); 0 where s = 0."""
+
+    @staticmethod
+    def forward(ctx, s, k, m):
+        p = torch.from_numpy(prox_porous(s.detach().numpy(), k.numpy(), m))
+        ctx.save_for_backward(s, p, k)
+        ctx.m = m
+        return p
+
+    @staticmethod
+    def backward(ctx, gp):
+        s, p, k = ctx.saved_tensors
+        m = ctx.m
+        pos = s > 0
+        dpds = p / (torch.where(pos, s, torch.ones_like(s)) * (1.0 + (m - 1.0) * k * p ** (m - 1.0)))
+        return torch.where(pos, gp * dpds, torch.zeros_like(s)), None, None
+
+
 def flow_torch(p0, w, kappa, gamma, tau, iters_per_step, kind="congestion", coef=None, m=None,
                density_scale=1.0):
     """Differentiable flow output p_T (torch tensors in, torch tensor out)."""
@@ -88,6 +114,10 @@ def flow_torch(p0, w, kappa, gamma, tau, iters_per_step, kind="congestion", coef
                 p = s ** (1.0 / (1.0 + sigma * coef))
             elif kind == "gen_entropy":
                 p = _GenEntropyProx.apply(s, sigma, coef, m, density_scale)
+            elif kind == "porous":
+                # m is the scalar exponent here; k = sigma c m D^{m-1} / (m - 1)
+                k = sigma * coef * m * density_scale ** (m - 1.0) / (m - 1.0)
+                p = _PorousProx.apply(s, k.detach(), m)
             elif kind == "zero":
                 p = s
             else:
@@ -106,7 +136,10 @@ def loss_and_grads(p0, w, kappa, gamma, tau, iters_per_step, target, kind="conge
     tk = torch.tensor(np.broadcast_to(np.asarray(kappa, np.float64), p0.shape).copy())
     tc = None if coef is None else torch.tensor(np.broadcast_to(np.asarray(coef, np.float64), p0.shape).copy(),
                                                 requires_grad=(kind == "gen_entropy"))
-    tm = None if m is None else torch.tensor(np.broadcast_to(np.asarray(m, np.float64), p0.shape).copy())
+    if kind == "porous":
+        tm = float(m)   # one exponent for the whole grid
+    else:
+        tm = None if m is None else torch.tensor(np.broadcast_to(np.asarray(m, np.float64), p0.shape).copy())
     pT = flow_torch(tp0, tw, tk, gamma, tau, iters_per_step, kind, tc, tm, density_scale)
     loss = ((pT - torch.tensor(np.asarray(target, np.float64))) ** 2).sum()
     loss.backward()

@@ -403,7 +403,8 @@ def dykstra_scaling(q: np.ndarray, en: Energy, gamma: float, tau: float,
 
 
 def jko_step(q: np.ndarray, en: Energy, gamma: float, tau: float, max_iters: int,
-             tol: float = 0.0, check_every: int = 1, mode: str = "separable", op=None):
+             tol: float = 0.0, check_every: int = 1, mode: str = "separable", op=None,
+             observe=None):
     """One JKO step: the reduced scaling iteration (Proposition 3.3 with the
     u, v corrections dropped) and the stopping test of Listing 1.
 
@@ -420,6 +421,9 @@ def jko_step(q: np.ndarray, en: Energy, gamma: float, tau: float, max_iters: int
 
     ``op`` (optional) replaces the Gibbs kernel by another symmetric operator
     called as op(x): the heat kernel of Section 4.1 (``HeatKernel``).
+    ``observe`` (optional) is called as observe(k, s, p) after the proximal
+    half-step of every iteration; it only looks (the tests use it to record
+    which cells the congestion clamp caps).
     """
     sigma = tau / gamma
 
@@ -439,6 +443,8 @@ def jko_step(q: np.ndarray, en: Energy, gamma: float, tau: float, max_iters: int
         b = _safe_div(q, t)
         s = K(b)
         p = prox(s, sigma, en)
+        if observe is not None:
+            observe(k, s, p)
         a = _safe_div(p, s)
     t = K(a, transpose=True)
     err = float(np.abs(b * t - q).sum())

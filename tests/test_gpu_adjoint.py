@@ -1,0 +1,152 @@
+"""The hand-written adjoint (jko_backward) against FP64 reference gradients,
+for every energy and precision the boundary accepts.
+
+References: torch float64 autograd through the oracle's unrolled iteration
+(``oracle.grad.loss_and_grads``), and for the differentiation workload (the
+256 x 256 crowd flow of 20 JKO steps x 300 iterations and its 32 x 32
+instance) the stored FP64 gradients and central finite differences written by
+``tests/golden/make_c4_gradients.py`` from the oracle alone.  Bound: 1e-3
+relative (2-norm over the field, and per cell against the differences).
+"""
+import importlib.util
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1502_06216_amd as jk
+from oracle.grad import loss_and_grads
+from workloads import make_workload, small_case
+
+from _util import banner, dev, energies, f32, host64
+
+pytestmark = pytest.mark.gpu
+
+GRAD_TOL = 1e-3
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c4_gradients.npz")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    jk.load()
+
+
+def _golden_module():
+    path = os.path.join(os.path.dirname(GOLDEN), "make_c4_gradients.py")
+    spec = importlib.util.spec_from_file_location("make_c4_gradients", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def _rel(x, ref):
+    return float(np.linalg.norm(np.asarray(x, np.float64) - ref) / np.linalg.norm(ref))
+
+
+def _energy_case(kind, shape):
+    """A small flow of the energy `kind` with its nonlinearity active: the
+    porous energy in density units (D = N), the entropy with per-cell
+    weights."""
+    wl = small_case(shape, kind, seed=4)
+    if kind == "porous":
+        wl.density_scale = float(wl.N)
+    return wl
+
+
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("kind", ["entropy", "porous", "zero"])
+@pytest.mark.parametrize("shape,resident", [((48, 40), True), ((48, 40), False), ((20, 24, 36), True), ((70,), True)])
+def test_adjoint_energy_matches_fp64_autograd(kind, shape, resident, precision):
+    """dL/dp0 of L = ||p_T - target||^2 through 2 steps x 30 iterations for
+    the entropy (Proposition 4.2, m = 1), the porous-medium energy (its prox
+    differentiated through the implicit derivative of the root) and f = 0, on
+    the resident 2D kernel, the launch path, a ragged 3D grid and a 1D grid,
+    in both precisions."""
+    banner(f"adjoint {kind} {shape} resident={resident} {precision}")
+    wl = _energy_case(kind, shape)
+    g_en, o_en = energies(wl)
+    rng = np.random.default_rng(9)
+    target = rng.uniform(size=shape)
+    target /= target.sum()
+    iters = [30, 30]
+    pT, _, ck = jk.flow(dev(wl.p0), g_en, wl.gamma, wl.tau, len(iters), max_iters=30, checkpoints=True,
+                        precision=precision, resident=resident)
+    dL = 2.0 * (pT - dev(target))
+    gw, gp = jk.backward(ck, iters, dL.contiguous(), g_en, wl.gamma, wl.tau, precision=precision,
+                         want_w=False, resident=resident)
+    coef = None if kind == "zero" else o_en._coef(shape)
+    _, _, rp, _ = loss_and_grads(f32(wl.p0).astype(np.float64), np.zeros(shape), np.inf, wl.gamma, wl.tau,
+                                 iters, target, kind=kind, coef=coef, m=wl.m, density_scale=wl.density_scale)
+    ep = _rel(host64(gp), rp)
+    print(f"[gpu-test] adjoint {kind} {shape} {precision}: rel err dL/dp0 {ep:.2e}", flush=True)
+    assert ep <= GRAD_TOL
+
+
+@pytest.mark.parametrize("name,n_steps,iters", [("crowd32", 3, 50), ("crowd256_fixed", 2, 60)])
+def test_adjoint_split_bf16_congestion_matches_fp64_autograd(name, n_steps, iters):
+    """The congestion adjoint with split-BF16 contractions (forward
+    recomputation and reverse sweep) against float64 autograd."""
+    banner(f"adjoint split {name} {n_steps}x{iters}")
+    mod = _golden_module()
+    wl, p0, w, kappa, target = mod.instance(name)
+    g_en, _ = energies(wl)
+    pT, _, ck = jk.flow(dev(p0), g_en, wl.gamma, wl.tau, n_steps, max_iters=iters, checkpoints=True,
+                        precision="split_bf16")
+    dL = 2.0 * (pT - dev(target))
+    gw, gp = jk.backward(ck, [iters] * n_steps, dL.contiguous(), g_en, wl.gamma, wl.tau, precision="split_bf16")
+    _, rw, rp, _ = loss_and_grads(p0, w, kappa, wl.gamma, wl.tau, [iters] * n_steps, target)
+    ew, ep = _rel(host64(gw), rw), _rel(host64(gp), rp)
+    print(f"[gpu-test] adjoint split {name}: rel err dL/dw {ew:.2e}, dL/dp0 {ep:.2e}", flush=True)
+    assert ew <= GRAD_TOL and ep <= GRAD_TOL
+
+
+_GOLD = {}
+
+
+def _gold():
+    if not _GOLD:
+        with np.load(GOLDEN, allow_pickle=False) as z:
+            _GOLD.update({k: z[k] for k in z.files})
+    return _GOLD
+
+
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("name,tag", [("crowd32", "c32"), ("crowd256_fixed", "c256")])
+def test_differentiation_workload_matches_reference(name, tag, precision):
+    """The differentiation workload at its stated size and counts (20 JKO
+    steps x 300 iterations, capacity active): the adjoint's dL/dw and dL/dp0
+    against the stored FP64 autograd gradients (2-norm, 1e-3), and cell by
+    cell against the stored central differences (h = 1e-3) at the 64 seeded
+    cells, except where the capped set changed inside the difference
+    interval (a kink: the difference is no derivative there; those cells are
+    counted and printed)."""
+    banner(f"differentiation workload {name} 20x300 {precision}")
+    G = _gold()
+    mod = _golden_module()
+    wl, p0, w, kappa, target = mod.instance(name)
+    assert mod.digest(p0, w, kappa, target) == str(G[f"{tag}_digest"]), "workload changed since the golden file"
+    g_en, _ = energies(wl)
+    n_steps, iters = mod.N_STEPS, mod.ITERS
+    pT, _, ck = jk.flow(dev(p0), g_en, wl.gamma, wl.tau, n_steps, max_iters=iters, checkpoints=True,
+                        precision=precision)
+    loss = float(((host64(pT) - target) ** 2).sum())
+    dL = 2.0 * (pT - dev(target))
+    gw, gp = jk.backward(ck, [iters] * n_steps, dL.contiguous(), g_en, wl.gamma, wl.tau, precision=precision)
+    gw, gp = host64(gw).ravel(), host64(gp).ravel()
+    rw, rp = G[f"{tag}_gw"].astype(np.float64).ravel(), G[f"{tag}_gp"].astype(np.float64).ravel()
+    ew, ep = _rel(gw, rw), _rel(gp, rp)
+    out = []
+    for which, g, cells, fd, kink in (("w", gw, G[f"{tag}_cells_w"], G[f"{tag}_fd_w"], G[f"{tag}_kink_w"]),
+                                      ("p0", gp, G[f"{tag}_cells_p"], G[f"{tag}_fd_p"], G[f"{tag}_kink_p"])):
+        smooth = ~kink
+        err = np.abs(g[cells] - fd) / np.abs(fd)
+        out.append((which, float(err[smooth].max()), int(kink.sum())))
+        assert smooth.sum() >= len(cells) // 2
+        assert (err[smooth] <= GRAD_TOL).all(), (which, err[smooth].max())
+    print(f"[gpu-test] {name} 20x300 {precision}: loss {loss:.6e} (FP64 {float(G[f'{tag}_loss']):.6e}); "
+          f"rel err dL/dw {ew:.2e}, dL/dp0 {ep:.2e}; vs central differences "
+          + ", ".join(f"{k}: max {e:.2e} over smooth cells, {n} kinked" for k, e, n in out), flush=True)
+    assert loss == pytest.approx(float(G[f"{tag}_loss"]), rel=1e-4)
+    assert ew <= GRAD_TOL and ep <= GRAD_TOL

@@ -5,10 +5,12 @@ Its prox is a threshold on z = s e^{-sigma w} at kappa/e.  The device decides
 in float32 on its own float32 s, the oracle in float64, so a cell whose z
 lies within the float32 error of s from the threshold may go either way.
 The first iteration is compared cell by cell away from those near-ties
-(computed from the oracle's own z); longer runs, where a flipped decision
-feeds the next products, are compared by the fraction of cells that differ,
-and the paths of the library that share their arithmetic (resident and
-launch, plane and axis passes) must agree bit for bit.
+(computed from the oracle's own z).  In longer runs a flipped decision feeds
+the next products and moves z elsewhere by a little more than rounding, so
+there every cell decided differently must be a near-tie of the oracle's last
+prox argument within a wider band (NEAR_RUN), and few cells may differ; the
+paths of the library that share their arithmetic (resident and launch, plane
+and axis passes) must agree bit for bit.
 """
 import numpy as np
 import pytest
@@ -25,6 +27,8 @@ pytestmark = pytest.mark.gpu
 # half-width, in log z, of the band around the threshold left out of the
 # cell-by-cell comparison: a few times the relative error of the device's s
 NEAR = {"fp32": 1e-4, "split_bf16": 1e-3}
+# the same after many iterations, where earlier flips have moved z
+NEAR_RUN = 2e-2
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -37,6 +41,32 @@ def _case(shape, seed=3):
     wl = small_case(shape, "congestion", seed=seed)
     wl.kind = "binary_congestion"
     return wl
+
+
+def _oracle_run(q, o_en, wl, n_steps, iters):
+    """The oracle's flow and the log-gap of its last prox argument to the
+    threshold, log z - (log kappa - 1) with z = s e^{-sigma w}."""
+    last = {}
+
+    def observe(k, s_, p_):
+        last["s"] = s_
+
+    for _ in range(n_steps):
+        q, _ = O.jko_step(q, o_en, wl.gamma, wl.tau, iters, observe=observe)
+    sigma = wl.tau / wl.gamma
+    with np.errstate(divide="ignore", invalid="ignore"):
+        gap = np.log(last["s"]) - sigma * o_en._w(q.shape) - (np.log(o_en._kappa(q.shape)) - 1.0)
+    return q, gap
+
+
+def _check_differing_cells(p, ref, gap, label, max_frac):
+    """Cells decided differently: few, and each a near-tie of the oracle."""
+    differ = (p > 0) != (ref > 0)
+    worst = float(np.abs(gap[differ]).max()) if differ.any() else 0.0
+    print(f"[gpu-test] {label}: {differ.mean():.2e} of cells decided differently, largest oracle "
+          f"log-gap among them {worst:.2e}", flush=True)
+    assert differ.mean() <= max_frac
+    assert worst <= NEAR_RUN
 
 
 def _binary_values(p, kappa, rtol=0.0):
@@ -77,15 +107,11 @@ def test_steps_stay_binary_and_close_to_the_oracle(precision):
     g_en, o_en = energies(wl)
     pT, stats, ck = jk.flow(dev(wl.p0), g_en, wl.gamma, wl.tau, 2, max_iters=30, precision=precision,
                             checkpoints=True)
-    q = f32(wl.p0).astype(np.float64)
-    for _ in range(2):
-        q, _ = O.jko_step(q, o_en, wl.gamma, wl.tau, 30)
+    q, gap = _oracle_run(f32(wl.p0).astype(np.float64), o_en, wl, 2, 30)
     p = host64(pT)
     kappa = o_en._kappa(q.shape)
     assert _binary_values(p, kappa) and _binary_values(q, kappa)
-    differ = float(np.mean((p > 0) != (q > 0)))
-    print(f"[gpu-test] binary flow {precision}: {differ:.2e} of cells decided differently", flush=True)
-    assert differ <= 0.005
+    _check_differing_cells(p, q, gap, f"binary flow {precision}", 0.005)
     assert all(s["iters"] == 30 for s in stats)
 
 
@@ -129,9 +155,8 @@ def test_log_domain_decides_like_the_plain_domain():
         outs.append(host64(p))
     kappa = o_en._kappa(outs[0].shape)
     assert _binary_values(outs[0], kappa) and _binary_values(outs[1], kappa, rtol=1e-6)
-    differ = float(np.mean((outs[0] > 0) != (outs[1] > 0)))
-    print(f"[gpu-test] binary log vs plain: {differ:.2e} of cells decided differently", flush=True)
-    assert differ <= 0.005
+    _, gap = _oracle_run(f32(wl.p0).astype(np.float64), o_en, wl, 1, 20)
+    _check_differing_cells(outs[0], outs[1], gap, "binary log vs plain", 0.005)
 
 
 def test_collapsed_step_is_reported():
@@ -159,14 +184,15 @@ def test_crowd256_binary_full_size(precision):
     wl = make_workload("crowd256_binary")
     g_en, o_en = energies(wl)
     p, st = jk.step(dev(wl.p0), g_en, wl.gamma, wl.tau, max_iters=wl.max_iters, tol=0.0, precision=precision)
-    ref, rst = O.jko_step(f32(wl.p0).astype(np.float64), o_en, wl.gamma, wl.tau, wl.max_iters)
+    q = f32(wl.p0).astype(np.float64)
+    ref, gap = _oracle_run(q, o_en, wl, 1, wl.max_iters)
+    _, rst = O.jko_step(q, o_en, wl.gamma, wl.tau, wl.max_iters)
     p = host64(p)
     kappa = o_en._kappa(ref.shape)
     assert _binary_values(p, kappa) and _binary_values(ref, kappa)
-    differ = float(np.mean((p > 0) != (ref > 0)))
-    print(f"[gpu-test] crowd256_binary {precision}: {differ:.2e} of cells decided differently, "
-          f"marginal {st['marginal_l1']:.4e} vs {rst['marginal_l1']:.4e}", flush=True)
-    assert differ <= 0.001
+    _check_differing_cells(p, ref, gap, f"crowd256_binary {precision}", 0.001)
+    print(f"[gpu-test] crowd256_binary {precision}: marginal {st['marginal_l1']:.4e} vs "
+          f"{rst['marginal_l1']:.4e}", flush=True)
     assert st["marginal_l1"] == pytest.approx(rst["marginal_l1"], rel=0.01)
 
 

@@ -1,0 +1,109 @@
+"""The benchmarked workloads at the lengths the benchmark runs them, against
+the FP64 oracle at the same iteration counts (rel-L1 1e-5 FP32, 1e-4
+split-BF16): one full 300-iteration step of the 128^3 crowd, the 512^2
+porous-medium steps in tolerance mode (stop test every 10 iterations,
+tolerance 1e-6, cap 300), and the 256^2 crowd step at its 2000-iteration cap.
+
+The 128^3 oracle step takes a minute or two on the host; it prints its
+progress so that a long run is not mistaken for a hang.
+"""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_1502_06216_amd as jk
+from workloads import make_workload
+
+from _util import banner, dev, energies, f32, host64, rel_l1
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-5, "split_bf16": 1e-4}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    jk.load()
+
+
+_REF = {}
+
+
+def _oracle_step(name, wl, o_en, q, iters):
+    """The oracle's step at `iters` iterations, cached per workload and count."""
+    key = (name, iters, q.tobytes().__hash__())
+    if key not in _REF:
+        t0 = time.time()
+
+        def observe(k, s, p):
+            if k % 50 == 0:
+                print(f"[gpu-test]   oracle {name}: iteration {k}/{iters}, {time.time() - t0:.0f} s", flush=True)
+
+        _REF[key] = O.jko_step(q, o_en, wl.gamma, wl.tau, iters, observe=observe)
+    return _REF[key]
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+def test_crowd128c_full_step(precision):
+    """One JKO step of the 128^3 crowd as benchmarked: 300 iterations on the
+    plane and axis-0 passes."""
+    banner(f"crowd128c one step x 300 iterations {precision}")
+    wl = make_workload("crowd128c")
+    g_en, o_en = energies(wl)
+    p, st = jk.step(dev(wl.p0), g_en, wl.gamma, wl.tau, max_iters=wl.max_iters, precision=precision)
+    ref, ost = _oracle_step("crowd128c", wl, o_en, f32(wl.p0).astype(np.float64), wl.max_iters)
+    err = rel_l1(host64(p), ref)
+    print(f"[gpu-test] crowd128c 300 it {precision}: rel-L1 vs FP64 oracle {err:.3e}, marginal "
+          f"{st['marginal_l1']:.4e} (oracle {ost['marginal_l1']:.4e})", flush=True)
+    assert err <= TOL[precision]
+    assert st["marginal_l1"] == pytest.approx(ost["marginal_l1"], rel=1e-3)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("name", ["porous512_scaled", "porous512"])
+def test_porous512_steps_in_tolerance_mode(name, precision):
+    """Two steps of the 512^2 nonlinear diffusion as benchmarked (tolerance
+    1e-6 checked every 10 iterations, cap 300): each step's input and output
+    against the oracle run at the iteration count the device stopped at."""
+    banner(f"{name} 2 steps, tolerance mode, {precision}")
+    wl = make_workload(name)
+    g_en, o_en = energies(wl)
+    pT, stats, ck = jk.flow(dev(wl.p0), g_en, wl.gamma, wl.tau, 2, max_iters=wl.max_iters, tol=wl.tol,
+                            check_every=wl.check_every, precision=precision, checkpoints=True)
+    q = f32(wl.p0).astype(np.float64)
+    for t, st in enumerate(stats):
+        assert st["stop"] == "tol" and st["iters"] % wl.check_every == 0
+        if t > 0:
+            assert rel_l1(host64(ck[t]), q) <= TOL[precision]
+        q, ost = _oracle_step(name, wl, o_en, q, st["iters"])
+        # the oracle's violation at the device's stopping count is at the tolerance too
+        assert ost["marginal_l1"] <= 2.0 * wl.tol
+    err = rel_l1(host64(pT), q)
+    print(f"[gpu-test] {name} {precision}: iterations {[s['iters'] for s in stats]}, rel-L1 vs FP64 oracle "
+          f"{err:.3e}", flush=True)
+    assert err <= TOL[precision]
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+def test_crowd256_step_at_its_cap(precision):
+    """The 256^2 crowd step as benchmarked: tolerance 1e-6, which the step
+    does not reach, so it runs to its 2000-iteration cap."""
+    banner(f"crowd256 one step to the cap {precision}")
+    wl = make_workload("crowd256")
+    g_en, o_en = energies(wl)
+    p, st = jk.step(dev(wl.p0), g_en, wl.gamma, wl.tau, max_iters=wl.max_iters, tol=wl.tol,
+                    check_every=wl.check_every, precision=precision)
+    assert st["stop"] == "cap" and st["iters"] == wl.max_iters
+    ref, ost = _oracle_step("crowd256", wl, o_en, f32(wl.p0).astype(np.float64), wl.max_iters)
+    err = rel_l1(host64(p), ref)
+    print(f"[gpu-test] crowd256 2000 it {precision}: rel-L1 vs FP64 oracle {err:.3e}, marginal "
+          f"{st['marginal_l1']:.4e} (oracle {ost['marginal_l1']:.4e})", flush=True)
+    assert err <= TOL[precision]
+    assert st["marginal_l1"] == pytest.approx(ost["marginal_l1"], rel=1e-2)

@@ -42,6 +42,21 @@ def test_dense_gibbs_entries_by_loops():
                 math.exp(-((P[0] - Q[0]) ** 2 + (P[1] - Q[1]) ** 2) / gamma), rel=1e-15)
 
 
+@pytest.mark.parametrize("shape", [(9,), (7, 5), (3, 6, 5)])
+def test_gibbs_rows_equal_dense_products(shape):
+    """The single-output form used for spot checks of large grids (each
+    output as its own sum over all cells) equals rows of the dense product
+    with the N x N matrix built from pairwise distances, on ragged grids and
+    at both ends of the grid."""
+    rng = np.random.default_rng(11)
+    x = rng.uniform(0.0, 2.0, size=shape)
+    N = int(np.prod(shape))
+    idx = np.array(sorted({0, N - 1, N // 2, *rng.integers(0, N, size=5).tolist()}))
+    for gamma in (0.02, 0.5):
+        full = O.gibbs_dense(shape, gamma) @ x.ravel()
+        np.testing.assert_allclose(O.gibbs_rows(shape, gamma, idx, x), full[idx], rtol=1e-13, atol=0)
+
+
 def test_log_gibbs_matches_plain():
     rng = np.random.default_rng(2)
     x = rng.uniform(0.1, 2.0, size=(5, 6, 4))
@@ -655,4 +670,52 @@ def test_reference_gradient_matches_finite_differences():
         pp[c] += hp
         pm[c] -= hp
         fd = (fwd(pp, w) - fwd(pm, w)) / (2 * hp)
+        assert gp[c] == pytest.approx(fd, rel=1e-5, abs=1e-9 * abs(loss))
+
+
+@pytest.mark.parametrize("kind", ["porous", "entropy", "zero"])
+def test_reference_gradient_other_energies_match_finite_differences(kind):
+    """autograd through the unrolled flow == central differences of the numpy
+    oracle's forward map in p0 for the porous-medium energy (exact Lambert-W
+    prox differentiated through its implicit derivative; density units, so
+    that the nonlinearity is active), the weighted entropy (per-cell weights)
+    and f = 0."""
+    shape = (8, 7)
+    rng = np.random.default_rng(12)
+    gamma, tau = 2e-2, 5e-2
+    N = int(np.prod(shape))
+    p0 = gaussian_bumps(shape, rng.uniform(0.3, 0.7, size=(2, 2)), 0.15, [0.6, 0.4])
+    target = rng.uniform(size=shape)
+    target /= target.sum()
+    iters = [15, 15]
+    coef = m = None
+    D = 1.0
+    if kind == "porous":
+        coef, m, D = rng.uniform(0.5, 2.0, size=shape), 2.0, float(N)
+        en = O.Energy(kind="porous", coef=coef, m=m, density_scale=D)
+        # the prox is nonlinear here: (m-1) k psi^{m-1} is of order one
+        k = en.porous_k(tau / gamma, shape)
+        z = ((m - 1.0) * k * O.prox_porous(p0, k, m) ** (m - 1.0)).max()
+        assert z > 0.5
+    elif kind == "entropy":
+        coef = rng.uniform(0.2, 3.0, size=shape)
+        en = O.Energy(kind="entropy", coef=coef)
+    else:
+        en = O.Energy(kind="zero")
+
+    def fwd(p0_):
+        q = p0_
+        for K in iters:
+            q, _ = O.jko_step(q, en, gamma, tau, K)
+        return float(((q - target) ** 2).sum())
+
+    loss, _, gp, _ = loss_and_grads(p0, np.zeros(shape), np.inf, gamma, tau, iters, target, kind=kind,
+                                    coef=coef, m=m, density_scale=D)
+    assert loss == pytest.approx(fwd(p0), rel=1e-12)
+    for c in [(1, 1), (4, 5), (6, 2), (7, 6), (0, 3)]:
+        hp = 1e-5 * p0[c]
+        pp, pm = p0.copy(), p0.copy()
+        pp[c] += hp
+        pm[c] -= hp
+        fd = (fwd(pp) - fwd(pm)) / (2 * hp)
         assert gp[c] == pytest.approx(fd, rel=1e-5, abs=1e-9 * abs(loss))
