@@ -153,10 +153,14 @@ typedef struct {
     int32_t flags;           /* jko_flags bits (0 = defaults) */
     double absorb_threshold; /* log-domain absorption: at the first stop-test check where
                                 max|log a| or max|log b| exceeds it, a and b are absorbed
-                                (carried as logs) and every later contraction runs on
-                                per-fibre shifted exponentials; <= 0: log domain from the
-                                first iteration; +inf or NaN: never.  With a finite
-                                threshold the checks also run in fixed-count mode. */
+                                (carried as logs) after that iteration's proximal
+                                half-step, and every later Gibbs product is an exact
+                                log-sum-exp (each output shifted by its own largest term,
+                                no band assumed; float32 arithmetic in both precisions);
+                                <= 0: log domain from the first iteration; +inf or NaN:
+                                never.  With a finite threshold the checks also run in
+                                fixed-count mode, and the call reads each check back
+                                until the switch (one host synchronisation per check). */
 } jko_params;
 
 /* Execution flags of jko_params.flags.
@@ -167,8 +171,11 @@ typedef struct {
  * JKO_FLAG_AXIS_PASSES: on 3D grids whose axes are multiples of 32 (the
  *   second at most 128), an application of xi normally runs as a plane pass
  *   (axes 1 and 2 of each plane, the intermediate kept on chip) and an axis-0
- *   pass; this flag runs three axis passes instead.  Both give the same bits. */
-typedef enum { JKO_FLAG_NO_RESIDENT = 1, JKO_FLAG_AXIS_PASSES = 2 } jko_flags;
+ *   pass; this flag runs three axis passes instead.  Both give the same bits.
+ * JKO_FLAG_ABSORB_ON_A: the absorption switch (finite absorb_threshold)
+ *   watches max|log a| alone instead of max(max|log a|, max|log b|).  Ignored
+ *   by JKO_F_ATTRACTION, which watches max|log b|. */
+typedef enum { JKO_FLAG_NO_RESIDENT = 1, JKO_FLAG_AXIS_PASSES = 2, JKO_FLAG_ABSORB_ON_A = 4 } jko_flags;
 
 typedef enum { JKO_STOP_TOL = 0, JKO_STOP_CAP = 1 } jko_stop_reason;
 

@@ -32,6 +32,7 @@ ENERGY_KINDS = {"zero": 0, "congestion": 1, "porous": 2, "entropy": 3, "binary_c
 OP_GIBBS, OP_STEP, OP_FLOW, OP_BACKWARD, OP_ATTRACTION_STEP, OP_ATTRACTION_FLOW = 0, 1, 2, 3, 4, 5
 FLAG_NO_RESIDENT = 1   # jko_flags: keep one launch per Gibbs application
 FLAG_AXIS_PASSES = 2   # jko_flags: 3D applications as three axis passes
+FLAG_ABSORB_ON_A = 4   # jko_flags: the absorption switch watches max|log a| alone
 
 
 class JKOError(RuntimeError):
@@ -196,7 +197,7 @@ class EnergySpec:
 
 
 def make_params(gamma, tau, max_iters=300, tol=0.0, check_every=10, precision="fp32",
-                absorb_threshold=math.inf, resident=True, planes=True) -> Params:
+                absorb_threshold=math.inf, resident=True, planes=True, absorb_on_a=False) -> Params:
     p = Params()
     p.gamma = float(gamma)
     p.tau = float(tau)
@@ -204,7 +205,8 @@ def make_params(gamma, tau, max_iters=300, tol=0.0, check_every=10, precision="f
     p.max_iters = int(max_iters)
     p.check_every = int(check_every)
     p.precision = PRECISIONS[precision]
-    p.flags = (0 if resident else FLAG_NO_RESIDENT) | (0 if planes else FLAG_AXIS_PASSES)
+    p.flags = ((0 if resident else FLAG_NO_RESIDENT) | (0 if planes else FLAG_AXIS_PASSES)
+               | (FLAG_ABSORB_ON_A if absorb_on_a else 0))
     p.absorb_threshold = float(absorb_threshold)
     return p
 
@@ -233,18 +235,20 @@ def gibbs_apply(x: torch.Tensor, gamma: float, precision: str = "fp32",
 def step(p: torch.Tensor, energy: EnergySpec, gamma: float, tau: float, max_iters: int = 300,
          tol: float = 0.0, check_every: int = 10, precision: str = "fp32",
          absorb_threshold: float = math.inf, out: Optional[torch.Tensor] = None,
-         with_stats: bool = True, resident: bool = True, planes: bool = True):
+         with_stats: bool = True, resident: bool = True, planes: bool = True, absorb_on_a: bool = False):
     """One JKO step p -> argmin_p' W_gamma(p', p) + tau f(p').  Returns
     (p_next, stats dict or None).  resident=False keeps one launch per Gibbs
     application where the resident 2D kernel would run the step; planes=False
     runs 3D applications as three axis passes instead of a plane pass and an
-    axis-0 pass."""
+    axis-0 pass; absorb_on_a=True makes the absorption switch watch max|log a|
+    alone."""
     lib = load()
     shape = tuple(p.shape)
     _field(p, shape, "p")
     pout = torch.empty_like(p) if out is None else _field(out, shape, "out")
     g = make_grid(shape)
-    prm = make_params(gamma, tau, max_iters, tol, check_every, precision, absorb_threshold, resident, planes)
+    prm = make_params(gamma, tau, max_iters, tol, check_every, precision, absorb_threshold, resident, planes,
+                      absorb_on_a)
     e = energy.to_c(shape)
     op = OP_ATTRACTION_STEP if energy.kind == "attraction" else OP_STEP
     nb = lib.jko_workspace_bytes(ctypes.byref(g), ctypes.byref(prm), op, 0)
@@ -258,7 +262,8 @@ def step(p: torch.Tensor, energy: EnergySpec, gamma: float, tau: float, max_iter
 def flow(p0: torch.Tensor, energy: EnergySpec, gamma: float, tau: float, n_steps: int,
          max_iters: int = 300, tol: float = 0.0, check_every: int = 10, precision: str = "fp32",
          absorb_threshold: float = math.inf, checkpoints: bool = False, with_stats: bool = True,
-         out: Optional[torch.Tensor] = None, resident: bool = True, planes: bool = True):
+         out: Optional[torch.Tensor] = None, resident: bool = True, planes: bool = True,
+         absorb_on_a: bool = False):
     """n_steps JKO steps from p0.  Returns (p_T, stats list or None,
     checkpoints tensor (n_steps, *shape) or None)."""
     lib = load()
@@ -267,7 +272,8 @@ def flow(p0: torch.Tensor, energy: EnergySpec, gamma: float, tau: float, n_steps
     pT = torch.empty_like(p0) if out is None else _field(out, shape, "out")
     ck = torch.empty((n_steps,) + shape, dtype=torch.float32, device=p0.device) if checkpoints else None
     g = make_grid(shape)
-    prm = make_params(gamma, tau, max_iters, tol, check_every, precision, absorb_threshold, resident, planes)
+    prm = make_params(gamma, tau, max_iters, tol, check_every, precision, absorb_threshold, resident, planes,
+                      absorb_on_a)
     e = energy.to_c(shape)
     op = OP_ATTRACTION_FLOW if energy.kind == "attraction" else OP_FLOW
     nb = lib.jko_workspace_bytes(ctypes.byref(g), ctypes.byref(prm), op, n_steps)

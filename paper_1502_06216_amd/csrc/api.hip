@@ -3,7 +3,10 @@
 // One JKO step runs Listing 1 of the paper in the reduced scaling form of
 // Proposition 3.3:  per iteration  t = xi^T a -> b = q / t  and
 // s = xi b -> p = Prox(s), a = p / s, each Gibbs application being d per-axis
-// contraction passes whose last pass carries the pointwise update.  The stop
+// contraction passes whose last pass carries the pointwise update.  After an
+// absorption switch (a, b carried as logs) every application runs on the
+// exact log-sum-exp passes instead; the host always knows which domain the
+// device is in before it queues an application.  The stop
 // test of Listing 1 (|| b * xi^T a - q ||_1 <= tol after an even half-step) is
 // computed on the device every `check_every` iterations from the t of the next
 // iteration; the host queues iterations one check interval ahead of the test
@@ -19,6 +22,7 @@
 
 #include "jko_internal.h"
 #include "heat.h"
+#include "logpass.h"
 
 using namespace jko;
 
@@ -130,6 +134,12 @@ int part_cap_of(const Geo& g) {
         s.n = g.n[0];
         cap = std::max<int64_t>(cap, contract_slow_blocks(s));
     }
+    for (int k = 0; k < g.d; ++k) {   // log-domain passes
+        int64_t outer = 1, inner = 1;
+        for (int j = 0; j < k; ++j) outer *= g.n[j];
+        for (int j = k + 1; j < g.d; ++j) inner *= g.n[j];
+        cap = std::max<int64_t>(cap, log_pass_blocks(make_log_pass(outer, g.n[k], inner, 0, 1.0, nullptr)));
+    }
     return (int)cap;
 }
 
@@ -194,6 +204,8 @@ struct Plan {
     float* field[24] = {};
     hipStream_t st = nullptr;
     int prec = 0;
+    double gamma = 0.0;
+    bool ident[3] = {false, false, false};   // axis whose factor is the identity (the attraction's stacking axis)
     int W[3] = {0, 0, 0};        // float32 band half-widths of the factors
     bool fused2d = false;        // 2D applications use the fused band kernel
     bool resident = false;       // ... and a step may run in one resident launch
@@ -240,6 +252,7 @@ jko_status carve(Plan* P, const Geo& g, int op, int64_t extra, void* ws, size_t 
 }
 
 jko_status build_factors(Plan& P, double gamma, int32_t flags = 0) {
+    P.gamma = gamma;
     for (int k = 0; k < P.g.d; ++k) P.W[k] = band_halfwidth(P.g.n[k], gamma);
     P.plane3d = P.g.d == 3 && !(flags & JKO_FLAG_AXIS_PASSES) &&
                 plane3d_fits(P.g.n[0], P.g.n[1], P.g.n[2], P.W[0], P.W[1], P.W[2]);
@@ -334,6 +347,42 @@ jko_status apply_xi(const Plan& P, const float* x, EpiArgs epi, int* nblocks) {
     return JKO_OK;
 }
 
+// y = xi x in the log domain (x, y and the epilogue's scalings hold logs): one
+// exact log-sum-exp pass per axis, in the field's own layout, the last one
+// handing its values to `epi`; identity axes are skipped.  Uses z1, z2.
+jko_status apply_xi_log(const Plan& P, const float* x, EpiArgs epi, int* nblocks) {
+    int axes[3], na = 0;
+    for (int k = P.g.d - 1; k >= 0; --k)
+        if (!P.ident[k]) axes[na++] = k;
+    const float* in = x;
+    for (int i = 0; i < na; ++i) {
+        const int k = axes[i];
+        int64_t outer = 1, inner = 1;
+        for (int j = 0; j < k; ++j) outer *= P.g.n[j];
+        for (int j = k + 1; j < P.g.d; ++j) inner *= P.g.n[j];
+        const LogPass L = make_log_pass(outer, P.g.n[k], inner, P.W[k], P.gamma, in);
+        const bool last = i + 1 == na;
+        EpiArgs e = epi;
+        if (!last) {
+            e = EpiArgs{};
+            e.kind = EpiKind::STORE;
+            e.y = P.F(i % 2 == 0 ? F_Z1 : F_Z2);
+            e.ctl = epi.ctl;
+            e.part = epi.part;
+        }
+        int nb = 0;
+        HIP_TRY(launch_log_pass(L, e, &nb, P.st));
+        if (last && nblocks) *nblocks = nb;
+        in = e.y;
+    }
+    return JKO_OK;
+}
+
+// Either domain: the plain contractions, or the log-domain passes.
+jko_status apply_xi_in(bool logd, const Plan& P, const float* x, const EpiArgs& epi, int* nblocks) {
+    return logd ? apply_xi_log(P, x, epi, nblocks) : apply_xi(P, x, epi, nblocks);
+}
+
 // Pinned host mirror of the control block (one per process) and its event.
 struct Readback {
     Ctl* host = nullptr;
@@ -374,7 +423,7 @@ jko_status check_params(const jko_params* pr) {
     if (pr->precision != JKO_FP32 && pr->precision != JKO_SPLIT_BF16)
         return fail(JKO_ERR_INVALID, "unknown precision %d", pr->precision);
     if (isnan(pr->tol_l1)) return fail(JKO_ERR_INVALID, "tol_l1 is NaN");
-    if (pr->flags & ~(JKO_FLAG_NO_RESIDENT | JKO_FLAG_AXIS_PASSES))
+    if (pr->flags & ~(JKO_FLAG_NO_RESIDENT | JKO_FLAG_AXIS_PASSES | JKO_FLAG_ABSORB_ON_A))
         return fail(JKO_ERR_INVALID, "unknown flags 0x%x", pr->flags);
     return JKO_OK;
 }
@@ -498,7 +547,7 @@ bool use_resident(const Plan& P, const jko_params* pr, const ProxArgs& px) {
 // because part of the device is unavailable: the caller then runs the launch
 // path instead.
 jko_status launch_resident(const Plan& P, const float* q, float* p_out, const ProxArgs& px, int K, int ce,
-                           bool checks, double tol, double absorb, bool record_hist, bool* launched) {
+                           bool checks, double tol, double absorb, int a_only, bool record_hist, bool* launched) {
     *launched = false;
     Resident2D r{};
     r.B = Band2D{P.g.n[0], P.g.n[1], P.W[0], P.W[1], P.K1[0], P.K1[1], nullptr,
@@ -519,6 +568,7 @@ jko_status launch_resident(const Plan& P, const float* q, float* p_out, const Pr
     r.checks = checks ? 1 : 0;
     r.tol = tol;
     r.absorb = absorb;
+    r.a_only = a_only;
     r.spin_limit = kBarrierSpinLimit;
     EpiArgs al{};
     al.q = q;
@@ -574,11 +624,16 @@ jko_status run_step(const Plan& P, const jko_params* pr, const ProxArgs& px, con
     const double thr = pr->absorb_threshold;
     const bool log_from_start = thr <= 0.0;
     const double absorb = (log_from_start || !(thr < INFINITY)) ? 0.0 : thr;
+    const int a_only = (pr->flags & JKO_FLAG_ABSORB_ON_A) ? 1 : 0;
     HIP_TRY(launch_fill(a, log_from_start ? 0.f : 1.f, P.g.N, P.st));
     HIP_TRY(launch_ctl_reset(P.ctl, log_from_start ? 1 : 0, P.st));
     // Checks (monitor, absorption trigger) every `ce` iterations in tolerance
     // mode, and in fixed-count mode when absorption may trigger.
     const bool checks = tolmode || absorb > 0.0;
+    // The domain the next application runs in.  A switch is decided on the
+    // device at a check; the host reads that check back before it queues
+    // anything after it, so it always launches the right kernels.
+    bool logd = log_from_start;
 
     EpiArgs eb{};
     eb.kind = EpiKind::BUPDATE;
@@ -594,22 +649,38 @@ jko_status run_step(const Plan& P, const jko_params* pr, const ProxArgs& px, con
     ep.part = P.part;
     ep.ctl = P.ctl;
 
+    int k0 = 1;   // first iteration left to the launch path
     bool resident = false;
-    if (use_resident(P, pr, px)) {
-        jko_status s = launch_resident(P, q, p_out, px, K, ce, checks, pr->tol_l1, absorb, record_hist, &resident);
+    if (!logd && use_resident(P, pr, px)) {
+        jko_status s = launch_resident(P, q, p_out, px, K, ce, checks, pr->tol_l1, absorb, a_only, record_hist,
+                                       &resident);
         if (s) return s;
         if (resident && (s = resident_check(P))) return s;
+        if (resident && absorb > 0.0) {
+            // The kernel returns after the proximal half-step of an iteration
+            // whose check asked for the switch: convert the scalings and run
+            // the rest of the step on the log-domain passes.
+            Ctl c{};
+            if ((s = read_ctl(P, &c))) return s;
+            if (c.exit_iter > 0 && !c.done) {
+                HIP_TRY(launch_absorb(P.ctl, a, b, P.g.N, P.st));
+                HIP_TRY(launch_ctl_commit(P.ctl, P.st));
+                logd = true;
+                k0 = c.exit_iter + 1;
+                resident = false;
+            }
+        }
     }
 
     bool pending = false;   // a read-back of the control block is in flight
     bool stopped = false;
     int nb = 0;
-    for (int k = 1; k <= (resident ? 0 : K); ++k) {
+    for (int k = k0; k <= (resident ? 0 : K); ++k) {
         eb.check = (checks && k > 1 && (k - 1) % ce == 0) ? 1 : 0;
         eb.t_out = record_hist ? P.hist(2 * (int64_t)(k - 1)) : nullptr;
-        jko_status s = apply_xi(P, a, eb, &nb);
+        jko_status s = apply_xi_in(logd, P, a, eb, &nb);
         if (s) return s;
-        if (eb.check) HIP_TRY(launch_ctl_check(P.ctl, P.part, nb, k, pr->tol_l1, 1, absorb, P.st));
+        if (eb.check) HIP_TRY(launch_ctl_check(P.ctl, P.part, nb, k, pr->tol_l1, 1, absorb, a_only, P.st));
         if (eb.check && tolmode) {
             // Look at the previous stop test while this interval is queued,
             // then queue the read-back of this one.
@@ -626,12 +697,15 @@ jko_status run_step(const Plan& P, const jko_params* pr, const ProxArgs& px, con
         ep.check = cand ? 1 : 0;
         ep.write_p = cand ? 1 : 0;
         ep.s_out = record_hist ? P.hist(2 * (int64_t)(k - 1) + 1) : nullptr;
-        s = apply_xi(P, b, ep, &nb);
+        s = apply_xi_in(logd, P, b, ep, &nb);
         if (s) return s;
-        if (eb.check && absorb > 0.0) {
+        if (eb.check && absorb > 0.0 && !logd) {
             // a switch decided at this iteration's check takes effect now
             HIP_TRY(launch_absorb(P.ctl, a, b, P.g.N, P.st));
             HIP_TRY(launch_ctl_commit(P.ctl, P.st));
+            Ctl c{};
+            if ((s = read_ctl(P, &c))) return s;
+            if (c.logmode) logd = true;
         }
     }
     Ctl c{};
@@ -647,9 +721,9 @@ jko_status run_step(const Plan& P, const jko_params* pr, const ProxArgs& px, con
             em.b = b;
             em.part = P.part;
             em.ctl = P.ctl;
-            s = apply_xi(P, a, em, &nb);
+            s = apply_xi_in(logd, P, a, em, &nb);
             if (s) return s;
-            HIP_TRY(launch_ctl_check(P.ctl, P.part, nb, K + 1, -1.0, 1, 0.0, P.st));
+            HIP_TRY(launch_ctl_check(P.ctl, P.part, nb, K + 1, -1.0, 1, 0.0, 0, P.st));
             s = read_ctl(P, &c);
             if (s) return s;
             c.done = 0;
@@ -722,13 +796,14 @@ jko_status run_attraction(const Plan& P, const jko_params* pr, const jko_energy*
     es.part = P.part;
     es.ctl = P.ctl;
     const double alpha = 1.0 / (1.0 + pr->tau);
+    bool logd = logmode;   // the domain of the next application (as in run_step)
     bool pending = false, stopped = false;
     int nb = 0;
     for (int k = 1; k <= K; ++k) {
         eb.check = (checks && k > 1 && (k - 1) % ce == 0) ? 1 : 0;
-        jko_status s = apply_xi(P, a, eb, &nb);
+        jko_status s = apply_xi_in(logd, P, a, eb, &nb);
         if (s) return s;
-        if (eb.check) HIP_TRY(launch_ctl_check(P.ctl, P.part, nb, k, pr->tol_l1, 0, absorb, P.st));
+        if (eb.check) HIP_TRY(launch_ctl_check(P.ctl, P.part, nb, k, pr->tol_l1, 0, absorb, 0, P.st));
         if (eb.check && tolmode) {
             if (pending) {
                 HIP_TRY(hipEventSynchronize(g_rb.ev));
@@ -739,11 +814,14 @@ jko_status run_attraction(const Plan& P, const jko_params* pr, const jko_energy*
             HIP_TRY(hipEventRecord(g_rb.ev, P.st));
             pending = true;
         }
-        if ((s = apply_xi(P, b, es, &nb))) return s;
+        if ((s = apply_xi_in(logd, P, b, es, &nb))) return s;
         HIP_TRY(launch_attraction_prox(sv, a, p_out, en->kappa, en->kappa_scalar, alpha, N, P.ctl, P.st));
-        if (eb.check && absorb > 0.0) {   // a switch decided at this iteration's check takes effect now
+        if (eb.check && absorb > 0.0 && !logd) {   // a switch decided at this iteration's check takes effect now
             HIP_TRY(launch_absorb(P.ctl, a, b, 2 * N, P.st));
             HIP_TRY(launch_ctl_commit(P.ctl, P.st));
+            Ctl c{};
+            if ((s = read_ctl(P, &c))) return s;
+            if (c.logmode) logd = true;
         }
     }
     Ctl c{};
@@ -758,8 +836,8 @@ jko_status run_attraction(const Plan& P, const jko_params* pr, const jko_energy*
             em.b = b;
             em.part = P.part;
             em.ctl = P.ctl;
-            if ((s = apply_xi(P, a, em, &nb))) return s;
-            HIP_TRY(launch_ctl_check(P.ctl, P.part, nb, K + 1, -1.0, 0, 0.0, P.st));
+            if ((s = apply_xi_in(logd, P, a, em, &nb))) return s;
+            HIP_TRY(launch_ctl_check(P.ctl, P.part, nb, K + 1, -1.0, 0, 0.0, 0, P.st));
             if ((s = read_ctl(P, &c))) return s;
             c.done = 0;
         }
@@ -798,6 +876,7 @@ jko_status attraction_flow(const Geo& g, const jko_energy* en, const jko_params*
     // the stacking axis: gamma -> 0 rounds every off-diagonal entry to zero
     HIP_TRY(launch_build_factor(const_cast<float*>(P.K1[0]), const_cast<uint16_t*>(P.K1hi[0]),
                                 const_cast<uint16_t*>(P.K1lo[0]), 2, 1e-30, P.st));
+    P.ident[0] = true;
     // capacity of the initial density, and a target of the same mass
     double h[3], hr[3];
     HIP_TRY(launch_input_check(p0, en->kappa, en->kappa_scalar, g.N, 1, P.part.err, 3 * 256, P.hostout, P.st));
@@ -1021,7 +1100,7 @@ jko_status jko_time_iteration(const jko_grid* grid, const jko_energy* energy, co
             HIP_TRY(launch_ctl_reset(P.ctl, 0, P.st));
             HIP_TRY(hipEventRecord(e0, P.st));
             bool launched = false;
-            s = launch_resident(P, p_in, P.F(F_Z1), px, params->max_iters, 1, false, 0.0, 0.0, false, &launched);
+            s = launch_resident(P, p_in, P.F(F_Z1), px, params->max_iters, 1, false, 0.0, 0.0, 0, false, &launched);
             if (s) break;
             if (!launched) {
                 s = fail(JKO_ERR_HIP, "the cooperative grid of the resident kernel was refused");

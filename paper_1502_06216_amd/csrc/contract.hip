@@ -22,9 +22,8 @@
 // the global loads of chunk c+1 are in flight while chunk c is multiplied,
 // with one barrier per chunk.
 //
-// Log domain (after the absorption switch): X holds log values; each row is
-// shifted by its maximum over the block's band before exponentiation, and the
-// output is shift + log(sum).
+// These passes run the plain domain only: after an absorption switch every
+// product runs on the exact log-sum-exp passes of logpass.hip.
 //
 // 3D grids whose axes are multiples of 32 use two other kernels defined here,
 // which keep the layout: a plane pass (axes 2 and 1 of each plane, the
@@ -48,19 +47,6 @@ __device__ __forceinline__ int xcd_logical_block() {
     return (bid % 8) * (nb / 8) + bid / 8;
 }
 
-// exp(L - shift) for a staged log input (an all-zero row stages zeros).
-__device__ __forceinline__ float shifted_exp(float L, float shift) {
-    return (shift == shift) ? expf(L - shift) : 0.f;
-}
-
-// log of a log-domain contraction output.  A non-empty row whose sum
-// underflowed (every contribution below e^-87 of the row maximum) is held at
-// the floor shift - 104 instead of -inf, so that b = q / t stays finite.
-__device__ __forceinline__ float shifted_log(float acc, float shift) {
-    if (shift != shift) return -INFINITY;
-    return acc > 0.f ? shift + logf(acc) : shift - 104.f;
-}
-
 // BK: k per chunk.  STAGES = 2: double-buffered chunks; STAGES = 1: the whole
 // band of a tile fits in one chunk (loaded once, then multiplied).
 template <int TR, int TI, int WR, int WI, bool SPLIT, int BK, int STAGES, int EK>
@@ -78,17 +64,12 @@ contract_rot(Pass P, EpiArgs E) {
     __shared__ __attribute__((aligned(16))) float ldsf[NF];        // [stage][TR+TI][SF]
     __shared__ __attribute__((aligned(16))) uint16_t ldsh[NB];     // [stage][TR+TI][SB] hi
     __shared__ __attribute__((aligned(16))) uint16_t ldsl[NB];     //                    lo
-    __shared__ float fshift[TR];
-    __shared__ float fscr[kThreads];
     __shared__ double shd[8];
 
     // The control flags are read here but acted on only after the first chunk's
     // loads are in flight, so their latencies overlap.
-    int done = 0, lmode = 0;
-    if (E.ctl) {
-        done = E.ctl->done;
-        lmode = E.ctl->logmode;
-    }
+    int done = 0;
+    if (E.ctl) done = E.ctl->done;
 
     // Every field has at most 2^30 cells, so 32-bit element offsets suffice.
     const int n = P.n;
@@ -114,31 +95,13 @@ contract_rot(Pass P, EpiArgs E) {
         f4 k[SPLIT ? 1 : UK];
         u16x4 kh[SPLIT ? UK : 1], kl[SPLIT ? UK : 1];
     };
-    bool logx = false;
 
-    // per-row maximum of the log input over the band (log domain only)
-    auto row_shifts = [&]() {
-        constexpr int G = kThreads / TR;
-        const int f = tid / G, g = tid % G;
-        float mx = -INFINITY;
-        if (f < TR && r0 + f < R)
-            for (int k = kb0 + g; k < kb1; k += G) mx = fmaxf(mx, P.X[(r0 + f) * n + k]);
-        if (f < TR) fscr[g * TR + f] = mx;
-        __syncthreads();
-        if (tid < TR) {
-            float v = -INFINITY;
-            for (int gg = 0; gg < G; ++gg) v = fmaxf(v, fscr[gg * TR + tid]);
-            fshift[tid] = (v == -INFINITY) ? NAN : v;
-        }
-        __syncthreads();
-    };
-
-    auto load = [&](int c, float fill, Regs& g) {
+    auto load = [&](int c, Regs& g) {
         const int kc = kb0 + c * BK;
 #pragma unroll
         for (int u = 0; u < UX; ++u) {
             const int unit = tid + u * kThreads;
-            f4 v = f4{fill, fill, fill, fill};
+            f4 v = f4{0.f, 0.f, 0.f, 0.f};
             if (unit < TR * BK / 4) {
                 const int d = unit / (BK / 4), k = kc + 4 * (unit % (BK / 4));
                 const int row = r0 + d;
@@ -147,7 +110,7 @@ contract_rot(Pass P, EpiArgs E) {
                     if (vec && k + 3 < kb1) v = *reinterpret_cast<const f4*>(src);
                     else
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) v[e] = (k + e < kb1) ? src[e] : fill;
+                        for (int e = 0; e < 4; ++e) v[e] = (k + e < kb1) ? src[e] : 0.f;
                 }
             }
             g.x[u] = v;
@@ -193,12 +156,7 @@ contract_rot(Pass P, EpiArgs E) {
             const int unit = tid + u * kThreads;
             if (unit >= TR * BK / 4) continue;
             const int d = unit / (BK / 4), kq = unit % (BK / 4);
-            f4 v = g.x[u];
-            if (logx) {
-                const float m = fshift[d];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) v[e] = shifted_exp(v[e], m);
-            }
+            const f4 v = g.x[u];
             if (SPLIT) {
                 u16x4 h, l;
 #pragma unroll
@@ -308,28 +266,21 @@ contract_rot(Pass P, EpiArgs E) {
     // Pipelined form: two register sets keep the loads of chunk c+2 in flight
     // while chunk c is multiplied and chunk c+1 is written to LDS.
     Regs ra, rb;
-    load(0, 0.f, ra);
-    if (STAGES == 2 && nch > 1) load(1, 0.f, rb);
-    logx = lmode != 0;
-    if (logx) {
-        row_shifts();
-        load(0, -INFINITY, ra);   // staged logs: cells outside the band are exact zeros
-        if (STAGES == 2 && nch > 1) load(1, -INFINITY, rb);
-    }
+    load(0, ra);
+    if (STAGES == 2 && nch > 1) load(1, rb);
     store(0, ra);
     if (done) return;   // the step has stopped: nothing to compute (uniform)
     __syncthreads();
-    const float fill = logx ? -INFINITY : 0.f;
     if (STAGES == 2) {
         for (int c = 0; c < nch; c += 2) {
             // chunk c in stage 0, rb holds chunk c+1, ra is free
-            if (c + 2 < nch) load(c + 2, fill, ra);
+            if (c + 2 < nch) load(c + 2, ra);
             compute(0);
             if (c + 1 < nch) store(1, rb);
             __syncthreads();
             if (c + 1 >= nch) break;
             // chunk c+1 in stage 1, ra holds chunk c+2, rb is free
-            if (c + 3 < nch) load(c + 3, fill, rb);
+            if (c + 3 < nch) load(c + 3, rb);
             compute(1);
             if (c + 2 < nch) store(0, ra);
             __syncthreads();
@@ -337,7 +288,7 @@ contract_rot(Pass P, EpiArgs E) {
     } else {
         for (int c = 0; c < nch; ++c) {
             if (c > 0) {
-                load(c, fill, ra);
+                load(c, ra);
                 __syncthreads();
                 store(0, ra);
                 __syncthreads();
@@ -363,12 +314,8 @@ contract_rot(Pass P, EpiArgs E) {
         const int unit = tid + u * kThreads;
         const int il = unit / (TR / 4), rl = 4 * (unit % (TR / 4));
         if (ecnt[u] == 0) continue;
-        f4 v = *reinterpret_cast<const f4*>(&tile[il * TS + rl]);
-        if (logx) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) v[e] = shifted_log(v[e], fshift[rl + e]);
-        }
-        epi_apply<EK>(E, eidx[u], ecnt[u], v, logx, ein[u], ea);
+        const f4 v = *reinterpret_cast<const f4*>(&tile[il * TS + rl]);
+        epi_apply<EK>(E, eidx[u], ecnt[u], v, false, ein[u], ea);
     }
     epi_finish(E, ea, (int)blockIdx.x, shd);
 }
@@ -443,14 +390,10 @@ contract_panel(Pass P, EpiArgs E) {
     constexpr int FN = TI / WI / 16;
     static_assert(FM >= 1 && FN >= 1 && TR % 16 == 0 && TI % 16 == 0, "tile shape");
     extern __shared__ __attribute__((aligned(16))) float dyn[];
-    __shared__ float fshift[TR];
     __shared__ double shd[8];
 
-    int done = 0, lmode = 0;
-    if (E.ctl) {
-        done = E.ctl->done;
-        lmode = E.ctl->logmode;
-    }
+    int done = 0;
+    if (E.ctl) done = E.ctl->done;
     const int n = P.n;
     const int R = (int)P.R;
     const int IT = n / TI;
@@ -532,21 +475,6 @@ contract_panel(Pass P, EpiArgs E) {
         __builtin_amdgcn_s_waitcnt(0);
         return;
     }
-    const bool logx = lmode != 0;
-    if (logx) {
-        // per-row maximum of the staged logs over the band, then exponentiate
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-        if (tid < TR) {
-            float m = -INFINITY;
-            for (int pnl = 0; pnl < NP; ++pnl)
-                for (int q = 0; q < 32; ++q) m = fmaxf(m, Xs[(pnl * TR + tid) * 32 + q]);
-            fshift[tid] = (m == -INFINITY) ? NAN : m;
-        }
-        __syncthreads();
-        for (int u = tid; u < NP * TR * 32; u += kThreads) Xs[u] = shifted_exp(Xs[u], fshift[(u >> 5) % TR]);
-        __syncthreads();
-    }
 
     f4 acc[FM][FN];
 #pragma unroll
@@ -556,13 +484,12 @@ contract_panel(Pass P, EpiArgs E) {
     const int s8 = (lane >> 1) & 7;   // 128-byte row swizzle of every row this lane reads
     const int g = lane >> 4;
     for (int pnl = 0; pnl < NP; ++pnl) {
-        if (!logx) {   // this panel's copies of every wave have landed
-            // (a bare barrier: __syncthreads would first wait for every copy)
-            wait_vm((NP - 1 - pnl) * CPP);
-            __atomic_signal_fence(__ATOMIC_SEQ_CST);
-            __builtin_amdgcn_s_barrier();
-            __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        }
+        // this panel's copies of every wave have landed (a bare barrier:
+        // __syncthreads would first wait for every copy)
+        wait_vm((NP - 1 - pnl) * CPP);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_barrier();
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
         const float* xp = Xs + (pnl * TR + wr * 16 * FM + (lane & 15)) * 32;
         if (SPLIT) {
             const int s4 = (lane >> 2) & 3;
@@ -629,12 +556,8 @@ contract_panel(Pass P, EpiArgs E) {
         const int unit = tid + u * kThreads;
         const int il = unit / (TR / 4), rl = 4 * (unit % (TR / 4));
         if (ecnt[u] == 0) continue;
-        f4 v = *reinterpret_cast<const f4*>(&tile[il * TS + rl]);
-        if (logx) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) v[e] = shifted_log(v[e], fshift[rl + e]);
-        }
-        epi_apply<EK>(E, eidx[u], ecnt[u], v, logx, ein[u], ea);
+        const f4 v = *reinterpret_cast<const f4*>(&tile[il * TS + rl]);
+        epi_apply<EK>(E, eidx[u], ecnt[u], v, false, ein[u], ea);
     }
     epi_finish(E, ea, (int)blockIdx.x, shd);
 }
@@ -728,9 +651,8 @@ hipError_t launch_ek(int ek, int cfg, int64_t nb, const Pass& p, const EpiArgs& 
 // axis passes, in the same order: the plane pass's first stage is the axis-2
 // pass (rows b, outputs c' in 32-wide chunks over their 32-aligned bands), its
 // second stage the axis-1 pass on the staged intermediate (outputs b' in
-// 32-wide chunks, one per wave, each over its own band, with the same
-// log-domain shifts), and the slow-axis pass is the axis-0 pass with X staged
-// transposed.  Two launches per application instead of three, and one trip
+// 32-wide chunks, one per wave, each over its own band), and the slow-axis
+// pass is the axis-0 pass with X staged transposed.  Two launches per application instead of three, and one trip
 // of the field through memory fewer.
 
 constexpr int kPlaneMaxN1 = 128;             // one 16-row fragment of b per wave in the first stage
@@ -753,14 +675,9 @@ template <bool SPLIT>
 __global__ void __launch_bounds__(kPlaneThr)
 plane_pass(Plane3D P) {
     extern __shared__ __attribute__((aligned(16))) float dyn[];
-    __shared__ float fshift[kPlaneMaxN1];            // first stage: row shifts (log domain)
-    __shared__ float cshift[kPlaneWaves][32];        // second stage: column shifts of each wave's chunk
 
-    int done = 0, lmode = 0;
-    if (P.ctl) {
-        done = P.ctl->done;
-        lmode = P.ctl->logmode;
-    }
+    int done = 0;
+    if (P.ctl) done = P.ctl->done;
     const int n1 = P.n1, n2 = P.n2;
     const int chunks = n2 >> 5;
     const int logical = xcd_logical_block();
@@ -837,18 +754,6 @@ plane_pass(Plane3D P) {
     __builtin_amdgcn_s_waitcnt(0);
     if (done) return;   // the step has stopped: nothing to compute (uniform)
     __syncthreads();
-    const bool logx = lmode != 0;
-    if (logx) {
-        if (tid < n1) {
-            float m = -INFINITY;
-            for (int pnl = 0; pnl < NP; ++pnl)
-                for (int q = 0; q < 32; ++q) m = fmaxf(m, Xs[(pnl * n1 + tid) * 32 + q]);
-            fshift[tid] = (m == -INFINITY) ? NAN : m;
-        }
-        __syncthreads();
-        for (int u = tid; u < NP * n1 * 32; u += kPlaneThr) Xs[u] = shifted_exp(Xs[u], fshift[(u >> 5) % n1]);
-        __syncthreads();
-    }
 
     // ---- first stage: Z[b][c'] = sum_c X[b][c] K2[c'][c]; wave w owns the
     // 16-row fragment w of b and both 16-column fragments of c'
@@ -899,31 +804,13 @@ plane_pass(Plane3D P) {
     if (s1) {
         const int b = fb * 16 + 4 * g;
 #pragma unroll
-        for (int f = 0; f < 2; ++f) {
-            f4 v = acc[f];
-            if (logx)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) v[e] = shifted_log(v[e], fshift[b + e]);
-            *reinterpret_cast<f4*>(&Zt[(f * 16 + (lane & 15)) * ZS + b]) = v;
-        }
+        for (int f = 0; f < 2; ++f) *reinterpret_cast<f4*>(&Zt[(f * 16 + (lane & 15)) * ZS + b]) = acc[f];
     }
     __syncthreads();
 
     // ---- second stage: Y[b'][c'] = sum_b K1[b'][b] Z[b][c'] over the band of
     // this wave's chunk of b' (rows of the MFMA: c'; columns: b')
     if (!s2) return;
-    float csh[2] = {0.f, 0.f};
-    if (logx) {
-        const int qb1 = qb0 + 32 * NQ;
-        const int cc = lane & 31;
-        float m = -INFINITY;
-        for (int b = qb0 + (lane >> 5); b < qb1; b += 2) m = fmaxf(m, Zt[cc * ZS + b]);
-        m = fmaxf(m, __shfl_xor(m, 32, 64));
-        if (lane < 32) cshift[wave][cc] = (m == -INFINITY) ? NAN : m;
-        __builtin_amdgcn_wave_barrier();
-#pragma unroll
-        for (int f = 0; f < 2; ++f) csh[f] = cshift[wave][f * 16 + (lane & 15)];
-    }
     f4 acc2[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
     for (int q = 0; q < kPlaneQ; ++q) {
@@ -934,14 +821,8 @@ plane_pass(Plane3D P) {
 #pragma unroll
             for (int f = 0; f < 2; ++f) {
                 const float* zr = Zt + (f * 16 + (lane & 15)) * ZS + kb + 8 * g;
-                f4 v0 = *reinterpret_cast<const f4*>(zr);
-                f4 v1 = *reinterpret_cast<const f4*>(zr + 4);
-                if (logx)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        v0[e] = shifted_exp(v0[e], csh[f]);
-                        v1[e] = shifted_exp(v1[e], csh[f]);
-                    }
+                const f4 v0 = *reinterpret_cast<const f4*>(zr);
+                const f4 v1 = *reinterpret_cast<const f4*>(zr + 4);
                 split_bf16(v0, v1, ah[f], al[f]);
             }
 #pragma unroll
@@ -955,12 +836,8 @@ plane_pass(Plane3D P) {
             for (int h = 0; h < 2; ++h) {
                 f4 av[2];
 #pragma unroll
-                for (int f = 0; f < 2; ++f) {
+                for (int f = 0; f < 2; ++f)
                     av[f] = *reinterpret_cast<const f4*>(Zt + (f * 16 + (lane & 15)) * ZS + kb + 4 * (4 * h + g));
-                    if (logx)
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) av[f][e] = shifted_exp(av[f][e], csh[f]);
-                }
 #pragma unroll
                 for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -973,12 +850,8 @@ plane_pass(Plane3D P) {
 #pragma unroll
     for (int f = 0; f < 2; ++f) {
         const int cl = f * 16 + 4 * g;
-        f4 v = acc2[f];
-        if (logx)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) v[e] = shifted_log(v[e], cshift[wave][cl + e]);
         const int bp = bt + (lane & 15);
-        __builtin_nontemporal_store(v, reinterpret_cast<f4*>(P.Y + ((int64_t)a * n1 + bp) * n2 + c0 + cl));
+        __builtin_nontemporal_store(acc2[f], reinterpret_cast<f4*>(P.Y + ((int64_t)a * n1 + bp) * n2 + c0 + cl));
     }
 }
 
@@ -996,14 +869,10 @@ contract_slow(Pass P, EpiArgs E) {
     constexpr int FM = TR / WR / 16;
     constexpr int FN = TI / WI / 16;
     extern __shared__ __attribute__((aligned(16))) float dyn[];
-    __shared__ float fshift[TR];
     __shared__ double shd[8];
 
-    int done = 0, lmode = 0;
-    if (E.ctl) {
-        done = E.ctl->done;
-        lmode = E.ctl->logmode;
-    }
+    int done = 0;
+    if (E.ctl) done = E.ctl->done;
     const int n = P.n;
     const int R = (int)P.R;
     const int IT = n / TI;
@@ -1068,24 +937,9 @@ contract_slow(Pass P, EpiArgs E) {
             lds_copy16_untracked(rx, Xs + j * 256, 4 * ((kb0 + 32 * pnl + k) * R + r0 + 4 * c));
         }
     }
-    const bool logx = lmode != 0;
-    if (done || logx) __builtin_amdgcn_s_waitcnt(0);
-    if (done) return;   // the step has stopped: nothing to compute (uniform)
-    if (logx) {
-        __syncthreads();
-        // per-column (r) maximum of the staged logs over the band, then exponentiate
-        if (tid < TR) {
-            float m = -INFINITY;
-            for (int k = 0; k < NP * 32; ++k) m = fmaxf(m, Xs[k * TR + slow_pos(k, tid)]);
-            fshift[tid] = (m == -INFINITY) ? NAN : m;
-        }
-        __syncthreads();
-        for (int u = tid; u < NP * 32 * TR; u += kThreads) {
-            const int k = u / TR, p = u % TR;
-            const int r = (((p >> 2) ^ (4 * ((k >> 2) & 3))) << 2) | (p & 3);
-            Xs[u] = shifted_exp(Xs[u], fshift[r]);
-        }
-        __syncthreads();
+    if (done) {   // the step has stopped: nothing to compute (uniform)
+        __builtin_amdgcn_s_waitcnt(0);
+        return;
     }
 
     f4 acc[FM][FN];
@@ -1096,12 +950,11 @@ contract_slow(Pass P, EpiArgs E) {
     const int s8 = (lane >> 1) & 7;
     const int g = lane >> 4;
     for (int pnl = 0; pnl < NP; ++pnl) {
-        if (!logx) {   // this panel's copies of every wave have landed
-            wait_vm(2 * (NP - 1 - pnl));
-            __atomic_signal_fence(__ATOMIC_SEQ_CST);
-            __builtin_amdgcn_s_barrier();
-            __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        }
+        // this panel's copies of every wave have landed
+        wait_vm(2 * (NP - 1 - pnl));
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_barrier();
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
         const float* xp = Xs + pnl * 32 * TR;
         if (SPLIT) {
             const int s4 = (lane >> 2) & 3;
@@ -1181,12 +1034,8 @@ contract_slow(Pass P, EpiArgs E) {
         const int unit = tid + u * kThreads;
         const int il = unit / (TR / 4), rl = 4 * (unit % (TR / 4));
         if (ecnt[u] == 0) continue;
-        f4 v = *reinterpret_cast<const f4*>(&tile[il * TS + rl]);
-        if (logx) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) v[e] = shifted_log(v[e], fshift[rl + e]);
-        }
-        epi_apply<EK>(E, eidx[u], ecnt[u], v, logx, ein[u], ea);
+        const f4 v = *reinterpret_cast<const f4*>(&tile[il * TS + rl]);
+        epi_apply<EK>(E, eidx[u], ecnt[u], v, false, ein[u], ea);
     }
     epi_finish(E, ea, (int)blockIdx.x, shd);
 }

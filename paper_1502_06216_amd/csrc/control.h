@@ -14,8 +14,9 @@ namespace jko {
 // every call (the resident kernel's blocks rely on this to agree).
 //   done      when the violation is <= tol (tol > 0) or not finite; the step
 //             returns the p of iteration iter - 1;
-//   absorb_pending  set when max |log a| or max |log b| exceeds absorb: the
-//             scalings are carried as logs from the end of this iteration on.
+//   absorb_pending  set when max |log a| or max |log b| exceeds absorb (with
+//             a_only: max |log a| alone): the scalings are carried as logs from
+//             the end of this iteration on.
 // COH: the partials are read with device-scope loads (written by other
 // blocks of the same launch); at most 256 of them (one per resident block).
 template <bool COH = false>
@@ -25,7 +26,7 @@ __device__ __forceinline__ double part_ld(const double* p) {
 
 template <bool COH = false>
 __device__ __forceinline__ void ctl_update(Ctl* c, const Partials& part, int nparts, int iter, double tol,
-                                           int check_mass, double absorb) {
+                                           int check_mass, double absorb, int a_only) {
     const int lane = threadIdx.x & 63;
     double err = 0.0, mlb = 0.0, mass = 0.0, mla = 0.0;
     if (COH) {
@@ -86,7 +87,8 @@ __device__ __forceinline__ void ctl_update(Ctl* c, const Partials& part, int npa
         // the switch itself happens after this iteration's proximal
         // half-step (the scalings are converted, then logmode is set)
         c->absorb_pending = 0;
-        if (!c->done && !c->logmode && absorb > 0.0 && (mlb > absorb || (check_mass && mla > absorb))) {
+        if (!c->done && !c->logmode && absorb > 0.0 &&
+            ((!a_only && mlb > absorb) || (check_mass && mla > absorb))) {
             c->absorb_pending = 1;
             c->absorptions += 1;
         }

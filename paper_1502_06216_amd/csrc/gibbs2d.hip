@@ -12,10 +12,8 @@
 // one output tile; the tile order is XCD-aware so that neighbouring tiles,
 // which share most of their halo, share an L2.
 //
-// Log domain (after the absorption switch): X holds log values; the halo rows
-// are shifted by their maximum over the halo before the first contraction, Z
-// is carried to the second in log form and re-shifted per output column, so
-// each shift is local to the band around the outputs it serves.
+// These kernels run the plain domain only: after an absorption switch every
+// product runs on the exact log-sum-exp passes of logpass.hip.
 //
 // Resident kernel: when every tile's block fits on the chip at once, the
 // iteration of a step (3.2: t = xi^T a, b = q / t, s = xi b, a = prox(s) / s,
@@ -52,8 +50,6 @@ struct Smem {
     uint16_t Kih[kT * kS2], Kil[kT * kS2];
     float Zs[kT * kS];      // [j][ib]
     float red[8 * 4 * kRS];  // [wave][element][lane] partial sums of the second contraction
-    float sh1[kHalo];       // log domain: row shifts of the halo
-    float sh2[kT];          // log domain: column shifts of Z
     double shd[8];
 };
 
@@ -139,7 +135,7 @@ __device__ __forceinline__ void load_halo(const Band2D& B, const Tile& T, f4 (&b
     }
 }
 
-__device__ __forceinline__ void store_halo(Smem& S, const Tile& T, const f4 (&bx)[UXM], bool logx) {
+__device__ __forceinline__ void store_halo(Smem& S, const Tile& T, const f4 (&bx)[UXM]) {
     const int tid = threadIdx.x;
     const int nux = T.LIp * (T.LJp / 4);
 #pragma unroll
@@ -147,12 +143,7 @@ __device__ __forceinline__ void store_halo(Smem& S, const Tile& T, const f4 (&bx
         const int unit = tid + u * kThr;
         if (unit < nux) {
             const int r = unit / (T.LJp / 4), c = 4 * (unit % (T.LJp / 4));
-            f4 v = bx[u];
-            if (logx)   // staged logs: cells outside the halo are exact zeros
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    if (r >= T.LI || c + e >= T.LJ) v[e] = -INFINITY;
-            *reinterpret_cast<f4*>(&S.Xs[r * kS + c]) = v;
+            *reinterpret_cast<f4*>(&S.Xs[r * kS + c]) = bx[u];
         }
     }
 }
@@ -267,28 +258,12 @@ __device__ __forceinline__ void stage_bands_split(const Band2D& B, const Tile& T
 // read and multiplied with the factor bands' hi / lo, three products
 // (hi*hi + hi*lo + lo*hi) on v_mfma_f32_16x16x32_bf16, FP32 accumulation.
 template <int EK, bool COH = false, bool SPLIT = false>
-__device__ __forceinline__ void contract_tile(const EpiArgs& E, const Tile& T, const EpiIn& ein, bool logx,
-                                              Smem& S, int slot) {
+__device__ __forceinline__ void contract_tile(const EpiArgs& E, const Tile& T, const EpiIn& ein, Smem& S,
+                                              int slot) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int koff = 4 * (lane >> 4);
-    const int LI = T.LI, LJ = T.LJ, LIp = T.LIp, LJp = T.LJp;
+    const int LIp = T.LIp, LJp = T.LJp;
     __syncthreads();
-
-    if (logx) {
-        // row shifts over the halo, then exponentiate the staged logs
-        for (int r = tid; r < LIp; r += kThr) {
-            float m = -INFINITY;
-            for (int c = 0; c < LJ; ++c) m = fmaxf(m, S.Xs[r * kS + c]);
-            S.sh1[r] = (m == -INFINITY) ? NAN : m;
-        }
-        __syncthreads();
-        for (int u = tid; u < LIp * LJp; u += kThr) {
-            const int r = u / LJp, c = u % LJp;
-            const float m = S.sh1[r];
-            S.Xs[r * kS + c] = (m == m) ? expf(S.Xs[r * kS + c] - m) : 0.f;
-        }
-        __syncthreads();
-    }
 
     // ---- Z = X K1_1^T over the halo rows: wave f owns the 16-row fragment f;
     // even and odd k-chunks go to two accumulators (independent MFMA chains)
@@ -308,13 +283,6 @@ __device__ __forceinline__ void contract_tile(const EpiArgs& E, const Tile& T, c
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
-        }
-        if (logx) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const float m = S.sh1[16 * f + koff + e];
-                acc[e] = (m != m) ? -INFINITY : (acc[e] > 0.f ? m + logf(acc[e]) : m - 104.f);
-            }
         }
         *reinterpret_cast<f4*>(&S.Zs[(lane & 15) * kS + 16 * f + koff]) = acc;
     } else if (!SPLIT && wave < F) {
@@ -340,34 +308,11 @@ __device__ __forceinline__ void contract_tile(const EpiArgs& E, const Tile& T, c
 #pragma unroll
             for (int s = 0; s < 4; ++s) acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[s], b0[s], acc0, 0, 0, 0);
         }
-        f4 acc = acc0 + acc1;
+        const f4 acc = acc0 + acc1;
         // acc holds Z[ib = 16f + koff + e][j = lane & 15]
-        if (logx) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const float m = S.sh1[16 * f + koff + e];
-                acc[e] = (m != m) ? -INFINITY : (acc[e] > 0.f ? m + logf(acc[e]) : m - 104.f);
-            }
-        }
         *reinterpret_cast<f4*>(&S.Zs[(lane & 15) * kS + 16 * f + koff]) = acc;
     }
     __syncthreads();
-
-    if (logx) {
-        // column shifts of Z over the valid halo rows, then exponentiate
-        if (tid < kT) {
-            float m = -INFINITY;
-            for (int r = 0; r < LI; ++r) m = fmaxf(m, S.Zs[tid * kS + r]);
-            S.sh2[tid] = (m == -INFINITY) ? NAN : m;
-        }
-        __syncthreads();
-        for (int u = tid; u < kT * LIp; u += kThr) {
-            const int j = u / LIp, r = u % LIp;
-            const float m = S.sh2[j];
-            S.Zs[j * kS + r] = (m == m && r < LI) ? expf(S.Zs[j * kS + r] - m) : 0.f;
-        }
-        __syncthreads();
-    }
 
     // ---- Y^T = Z^T K1_0^T: one 16 x 16 fragment, its 16-wide k-chunks spread
     // over the waves (at most 8 chunks), partial sums combined in a fixed order
@@ -404,11 +349,7 @@ __device__ __forceinline__ void contract_tile(const EpiArgs& E, const Tile& T, c
         float y = S.red[e * kRS + src];
 #pragma unroll
         for (int w = 1; w < 8; ++w) y += S.red[(w * 4 + e) * kRS + src];
-        if (logx) {
-            const float m = S.sh2[jl];
-            y = (m != m) ? -INFINITY : (y > 0.f ? m + logf(y) : m - 104.f);
-        }
-        epi_apply<EK, COH, 1>(E, T.eidx, T.ecnt, f4{y, 0.f, 0.f, 0.f}, logx, ein, ea);
+        epi_apply<EK, COH, 1>(E, T.eidx, T.ecnt, f4{y, 0.f, 0.f, 0.f}, false, ein, ea);
     }
     epi_finish<COH>(E, ea, slot, S.shd);
 }
@@ -420,11 +361,8 @@ gibbs2d_kernel(Band2D B, EpiArgs E) {
 
     // The control flags are read here but acted on only after the halo loads
     // are in flight, so their latencies overlap.
-    int done = 0, lmode = 0;
-    if (E.ctl) {
-        done = E.ctl->done;
-        lmode = E.ctl->logmode;
-    }
+    int done = 0;
+    if (E.ctl) done = E.ctl->done;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const Tile T = tile_of<SPLIT>(B, xcd_block(), lane);
 
@@ -443,9 +381,9 @@ gibbs2d_kernel(Band2D B, EpiArgs E) {
         load_bands(B, T, bj, bi);
         store_bands(S, T, bj, bi);
     }
-    store_halo(S, T, bx, lmode != 0);
+    store_halo(S, T, bx);
     if (done) return;   // the step has stopped: nothing to compute (uniform)
-    contract_tile<EK, false, SPLIT>(E, T, ein, lmode != 0, S, (int)blockIdx.x);
+    contract_tile<EK, false, SPLIT>(E, T, ein, S, (int)blockIdx.x);
 }
 
 // ------------------------------------------------------------ resident kernel
@@ -608,27 +546,23 @@ resident2d(Resident2D R) {
     }
     __syncthreads();
     const int nn = n_nbr;
-    int lmode = C.logmode;
     uint32_t count = 0;   // phases this block has published
-    bool b_plain = false;  // b still plain after an absorption switch
 
     // One phase: stage the halo of X, contract, epilogue.  Specialised at
-    // compile time on the domain (plain / log) and on whether the epilogue
-    // accumulates the stop-test partials, so the common iteration runs
-    // straight-line code.
+    // compile time on whether the epilogue accumulates the stop-test
+    // partials, so the common iteration runs straight-line code.
     using yes = std::true_type;
     using no = std::false_type;
-    auto phase = [&](auto ek, auto logc, auto chkc, EpiArgs& E, const EpiIn& in, const float* X) {
+    auto phase = [&](auto ek, auto chkc, EpiArgs& E, const EpiIn& in, const float* X) {
         constexpr int EKv = decltype(ek)::value;
-        constexpr bool LOG = decltype(logc)::value;
         constexpr bool CHK = decltype(chkc)::value;
         E.check = CHK ? 1 : 0;
         if (EKv >= EK_PROX) E.write_p = CHK ? 1 : 0;
         B.X = X;
         f4 bx[UXM];
         load_halo<true>(B, T, bx);
-        store_halo(S, T, bx, LOG);
-        contract_tile<EKv, true, SPLIT>(E, T, in, LOG, S, slot);
+        store_halo(S, T, bx);
+        contract_tile<EKv, true, SPLIT>(E, T, in, S, slot);
     };
     const std::integral_constant<int, EK_BUPDATE> ekb;
     const std::integral_constant<int, PK> ekp;
@@ -638,20 +572,11 @@ resident2d(Resident2D R) {
         const bool chk = R.checks && k > 1 && (k - 1) % R.ce == 0;
         eb.t_out = R.hist ? R.hist + (2 * (int64_t)(k - 1)) * R.hist_stride : nullptr;
         EpiIn ia = inq;
-        if (chk && wave < 4) {
-            ia.v = ld4_coh(R.b, T.eidx, T.ecnt, 0.f);
-            if (b_plain) ia.v[0] = ia.v[0] > 0.f ? logf(ia.v[0]) : -INFINITY;
-        }
+        if (chk && wave < 4) ia.v = ld4_coh(R.b, T.eidx, T.ecnt, 0.f);
         if (!wait_for(R.sync, nn, nbr, count, R.spin_limit)) return;
-        if (lmode) {
-            if (chk) phase(ekb, yes(), yes(), eb, ia, R.a);
-            else phase(ekb, yes(), no(), eb, ia, R.a);
-        } else {
-            if (chk) phase(ekb, no(), yes(), eb, ia, R.a);
-            else phase(ekb, no(), no(), eb, ia, R.a);
-        }
+        if (chk) phase(ekb, yes(), eb, ia, R.a);
+        else phase(ekb, no(), eb, ia, R.a);
         publish(R.sync, slot, ++count);
-        b_plain = false;
 
         // Stop test: block 0 waits for every block's partials, takes the
         // decision and publishes it.  No block writes partials again before
@@ -666,7 +591,7 @@ resident2d(Resident2D R) {
         if (chk) {
             if (slot == 0) {
                 if (!wait_for(R.sync, nb, all, count, R.spin_limit)) return;
-                if (wave == 0) ctl_update<true>(&C, R.part, nb, k, R.tol, 1, R.absorb);
+                if (wave == 0) ctl_update<true>(&C, R.part, nb, k, R.tol, 1, R.absorb, R.a_only);
                 __syncthreads();
                 if (tid == 0) {
                     Ctl* g = R.ctl;
@@ -676,6 +601,7 @@ resident2d(Resident2D R) {
                     g->absorptions = C.absorptions;
                     g->absorb_pending = C.absorb_pending;
                     g->logmode = C.logmode;
+                    g->exit_iter = C.absorb_pending ? k : 0;
                     g->err = C.err;
                     g->mass = C.mass;
                     g->maxloga = C.maxloga;
@@ -699,13 +625,8 @@ resident2d(Resident2D R) {
         const bool cand = (R.checks && k % R.ce == 0) || k == R.K;
         ep.s_out = R.hist ? R.hist + (2 * (int64_t)(k - 1) + 1) * R.hist_stride : nullptr;
         if (!wait_for(R.sync, nn, nbr, count, R.spin_limit)) return;
-        if (lmode) {
-            if (cand) phase(ekp, yes(), yes(), ep, inp, R.b);
-            else phase(ekp, yes(), no(), ep, inp, R.b);
-        } else {
-            if (cand) phase(ekp, no(), yes(), ep, inp, R.b);
-            else phase(ekp, no(), no(), ep, inp, R.b);
-        }
+        if (cand) phase(ekp, yes(), ep, inp, R.b);
+        else phase(ekp, no(), ep, inp, R.b);
         publish(R.sync, slot, ++count);
 
         if (chk) {
@@ -717,46 +638,11 @@ resident2d(Resident2D R) {
                 decision = word;
                 if (decision & 1u) return;   // same decision in every block
             }
-            if (decision & 2u) {
-                // The switch takes effect after this proximal half-step:
-                // a <- log a on this block's own tile.  Its b is still being
-                // read by neighbours in this half-step, so it stays plain: the
-                // next b-update overwrites it, and a check there takes the log
-                // of the old b as it reads it.
-                if (tid < kT * kT) {
-                    const int i = T.i0 + tid / kT, j = T.j0 + tid % kT;
-                    if (i < B.n0 && j < B.n1) {
-                        float* pa = R.a + (int64_t)i * B.n1 + j;
-                        const float av = __hip_atomic_load(pa, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        __hip_atomic_store(pa, av > 0.f ? logf(av) : -INFINITY, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                    }
-                }
-                b_plain = true;
-                lmode = 1;
-                if (slot == 0 && tid == 0) {
-                    C.logmode = 1;
-                    C.absorb_pending = 0;
-                    R.ctl->logmode = 1;
-                    R.ctl->absorb_pending = 0;
-                }
-                publish(R.sync, slot, ++count);
-            }
-        }
-    }
-
-    // A switch after the last proximal half-step: once the neighbours have
-    // finished it (they published the switch), b <- log b on this tile, where
-    // the closing monitor of a capped step reads it.
-    if (b_plain) {
-        if (!wait_for(R.sync, nn, nbr, count, R.spin_limit)) return;
-        if (tid < kT * kT) {
-            const int i = T.i0 + tid / kT, j = T.j0 + tid % kT;
-            if (i < B.n0 && j < B.n1) {
-                float* pb = R.b + (int64_t)i * B.n1 + j;
-                const float bv = __hip_atomic_load(pb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(pb, bv > 0.f ? logf(bv) : -INFINITY, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
+            // An absorption switch takes effect after this proximal half-step:
+            // the launch returns here (every block), and the host converts
+            // the scalings to logs and runs the rest of the step on the
+            // log-domain passes (recorded in ctl->exit_iter).
+            if (decision & 2u) return;
         }
     }
 }
@@ -813,9 +699,9 @@ resident_adj(ResidentAdj R) {
             B.X = R.sbar;
             f4 bx[UXM];
             load_halo<true>(B, T, bx);
-            store_halo(S, T, bx, false);
+            store_halo(S, T, bx);
         }
-        contract_tile<EK_ADJ_B, true, SPLIT>(eb, T, ia, false, S, slot);
+        contract_tile<EK_ADJ_B, true, SPLIT>(eb, T, ia, S, slot);
         publish(R.sync, slot, ++count);
         if (k == 1) break;
         ep.hin = R.hist + (2 * (int64_t)(k - 2) + 1) * R.hist_stride;
@@ -826,9 +712,9 @@ resident_adj(ResidentAdj R) {
             B.X = R.tbar;
             f4 bx[UXM];
             load_halo<true>(B, T, bx);
-            store_halo(S, T, bx, false);
+            store_halo(S, T, bx);
         }
-        contract_tile<AK, true, SPLIT>(ep, T, ip, false, S, slot);
+        contract_tile<AK, true, SPLIT>(ep, T, ip, S, slot);
         publish(R.sync, slot, ++count);
     }
 }

@@ -24,8 +24,10 @@ struct Ctl {
     int32_t absorb_pending;  // 1 when the last check asked for the log domain: a, b are
                              //    converted after that iteration's proximal half-step
     int32_t logmode;         // 1: the scalings a, b are stored as log a, log b and every
-                             //    contraction runs log-in / log-out with per-fibre shifts
-    int32_t pad[2];
+                             //    contraction runs log-in / log-out (exact log-sum-exp passes)
+    int32_t exit_iter;       // resident 2D kernel: the iteration after whose proximal half-step
+                             //    it returned because an absorption switch is pending (0: none)
+    int32_t pad;
     double err;            // last ||b * xi^T a - q||_1
     double mass;           // last sum p
     double maxloga;        // last max |log a| over a > 0
@@ -161,7 +163,9 @@ constexpr int64_t resident_sync_words(int64_t nblocks) { return 64 + 16 * nblock
 // One JKO step's iteration on a 2D grid in one cooperative launch (one block
 // per 16 x 16 output tile, all resident).  Same arithmetic, order of
 // operations, partials and control decisions as the launch-per-application
-// path with the fused 2D kernel.
+// path with the fused 2D kernel.  Plain domain only: at a check that asks for
+// the absorption switch the launch returns after that iteration's proximal
+// half-step (ctl->exit_iter) and the host continues on the log-domain passes.
 struct Resident2D {
     Band2D B;              // geometry and factors (B.X unused)
     const float* q;        // old density
@@ -180,6 +184,7 @@ struct Resident2D {
     int32_t vec_ok;        // all field pointers 16-byte aligned
     int32_t spin_limit;    // polls before a wait gives up
     int32_t split;         // split-BF16 contractions
+    int32_t a_only;        // the absorption trigger watches max|log a| alone
     double tol;
     double absorb;
 };
@@ -225,9 +230,10 @@ hipError_t launch_prepare_energy(const jko_energy* en, double sigma, int64_t N, 
                                  float* kf, hipStream_t s);
 hipError_t launch_ctl_reset(Ctl* ctl, int logmode, hipStream_t s);
 // Sum of the per-block err partials -> ctl->err; stop / non-finite decision;
-// switch to the log domain when max|log a| or max|log b| > absorb (absorb > 0).
+// switch to the log domain when max|log a| or max|log b| > absorb (absorb > 0;
+// a_only: max|log a| alone).
 hipError_t launch_ctl_check(Ctl* ctl, Partials part, int nparts, int iter, double tol,
-                            int check_mass, double absorb, hipStream_t s);
+                            int check_mass, double absorb, int a_only, hipStream_t s);
 // a <- log a, b <- log b when the last check asked for the switch.
 hipError_t launch_absorb(Ctl* ctl, float* a, float* b, int64_t N, hipStream_t s);
 // After launch_absorb: logmode <- 1 if the switch was pending; pending <- 0.

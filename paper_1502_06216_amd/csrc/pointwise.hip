@@ -130,6 +130,7 @@ __global__ void k_ctl_reset(Ctl* c, int logmode) {
         c->absorptions = logmode ? 1 : 0;
         c->absorb_pending = 0;
         c->logmode = logmode;
+        c->exit_iter = 0;
         c->err = 0.0;
         c->mass = 0.0;
         c->maxloga = 0.0;
@@ -154,9 +155,9 @@ __device__ double fixed_sum(const double* v, int n, double* sh) {
 }
 
 __global__ void __launch_bounds__(64) k_ctl_check(Ctl* c, Partials part, int nparts, int iter,
-                                                  double tol, int check_mass, double absorb) {
+                                                  double tol, int check_mass, double absorb, int a_only) {
     if (c->done) return;
-    ctl_update(c, part, nparts, iter, tol, check_mass, absorb);
+    ctl_update(c, part, nparts, iter, tol, check_mass, absorb, a_only);
 }
 
 __global__ void k_absorb(const Ctl* c, float* __restrict__ a, float* __restrict__ b, int64_t N) {
@@ -303,8 +304,9 @@ hipError_t launch_ctl_reset(Ctl* ctl, int logmode, hipStream_t s) {
 }
 
 hipError_t launch_ctl_check(Ctl* ctl, Partials part, int nparts, int iter, double tol, int check_mass,
-                            double absorb, hipStream_t s) {
-    hipLaunchKernelGGL(k_ctl_check, dim3(1), dim3(64), 0, s, ctl, part, nparts, iter, tol, check_mass, absorb);
+                            double absorb, int a_only, hipStream_t s) {
+    hipLaunchKernelGGL(k_ctl_check, dim3(1), dim3(64), 0, s, ctl, part, nparts, iter, tol, check_mass, absorb,
+                       a_only);
     return hipGetLastError();
 }
 

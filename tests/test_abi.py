@@ -94,7 +94,7 @@ def test_argument_errors_before_any_launch(lib):
     assert _call_step(lib, empty, en, prm) == jk.JKO_ERR_INVALID
     assert b"n[k]" in lib.jko_last_error()
     for field, val in (("gamma", 0.0), ("gamma", math.nan), ("tau", -1.0), ("max_iters", 0),
-                       ("check_every", 0), ("precision", 7), ("flags", 4), ("flags", -1)):
+                       ("check_every", 0), ("precision", 7), ("flags", 8), ("flags", -1)):
         p2 = nat.make_params(1e-3, 1e-3, 10)
         setattr(p2, field, val)
         assert _call_step(lib, g, en, p2) == jk.JKO_ERR_INVALID, field

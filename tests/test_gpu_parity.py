@@ -323,27 +323,31 @@ def test_log_domain_matches_plain_oracle(threshold, precision):
     assert (ph <= np.float32(wl.kappa_scalar)).all() and ph.min() >= 0
 
 
-def test_log_domain_survives_where_plain_fp32_overflows():
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+def test_log_domain_survives_where_plain_fp32_overflows(precision):
     """Small gamma, literal bump mixture far above the capacity: the plain FP32
-    scalings overflow.  The absorbed iteration stays finite and keeps the
-    invariants; its distance to the exact log-sum-exp oracle is printed (the
-    per-fibre shift drops contributions more than e^-87 below a fibre's
-    maximum, so this case carries no tight parity claim)."""
-    banner("log domain stress")
+    scalings overflow.  The absorbed iteration stays finite, keeps the
+    invariants and matches the exact log-sum-exp oracle (each log-domain
+    product shifts every output by its own largest term and assumes no
+    band)."""
+    banner(f"log domain stress {precision}")
     wl = small_case((64, 64), "congestion", seed=1, gamma=2e-4, tau=2e-3, n_boxes=3, projected=False,
                     cap_factor=1.2)
     g_en, o_en = energies(wl)
     iters = 60
     with pytest.raises(jk.JKOError):
         jk.step(dev(wl.p0), g_en, wl.gamma, wl.tau, max_iters=iters)   # NONFINITE in plain FP32
-    p, st = jk.step(dev(wl.p0), g_en, wl.gamma, wl.tau, max_iters=iters, check_every=5, absorb_threshold=0.0)
+    p, st = jk.step(dev(wl.p0), g_en, wl.gamma, wl.tau, max_iters=iters, check_every=5, absorb_threshold=0.0,
+                    precision=precision)
     ph = host64(p)
     assert np.isfinite(ph).all() and np.isfinite(st["marginal_l1"])
     assert ph.min() >= 0 and (ph <= f32(wl.kappa_field())).all()
     ref, ost = O.jko_step_log(f32(wl.p0).astype(np.float64), o_en, wl.gamma, wl.tau, iters)
     err = rel_l1(ph, ref)
-    print(f"[gpu-test] log-domain stress: rel-L1 vs exact LSE oracle {err:.3e}, "
+    print(f"[gpu-test] log-domain stress {precision}: rel-L1 vs exact LSE oracle {err:.3e}, "
           f"marginal {st['marginal_l1']:.3e} (oracle {ost['marginal_l1']:.3e})", flush=True)
+    assert err <= TOL[precision]
+    assert st["marginal_l1"] == pytest.approx(ost["marginal_l1"], rel=1e-3)
 
 
 # ------------------------------------------------------------- adjoint
