@@ -62,7 +62,7 @@ def _energy(wl):
                          density_scale=wl.density_scale, m_field=_dev(wl.m_field), target=_dev(wl.target))
 
 
-def run_flow(wl, precision, steps, warmup, tol=None, max_iters=None, resident=True):
+def run_flow(wl, precision, steps, warmup, tol=None, max_iters=None, resident=True, **kw):
     """Run warmup + timed JKO steps of a workload; returns (iters, seconds, stats)."""
     import torch
     import paper_1502_06216_amd as jk
@@ -72,14 +72,14 @@ def run_flow(wl, precision, steps, warmup, tol=None, max_iters=None, resident=Tr
     q = _dev(wl.p0)
     for _ in range(warmup):
         q, _ = jk.step(q, en, wl.gamma, wl.tau, max_iters=max_iters, tol=tol, check_every=wl.check_every,
-                       precision=precision, resident=resident)
+                       precision=precision, resident=resident, **kw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     iters = 0
     stats = []
     for _ in range(steps):
         q, st = jk.step(q, en, wl.gamma, wl.tau, max_iters=max_iters, tol=tol, check_every=wl.check_every,
-                        precision=precision, resident=resident)
+                        precision=precision, resident=resident, **kw)
         iters += st["iters"]
         stats.append(st)
     torch.cuda.synchronize()
@@ -89,6 +89,18 @@ def run_flow(wl, precision, steps, warmup, tol=None, max_iters=None, resident=Tr
 def band_halfwidth(n, gamma):
     """Largest |i - j| at which the float32 factor exp(-((i-j)/n)^2/gamma) is non-zero."""
     return min(int(math.floor(math.sqrt(152.0 * math.log(2.0) * gamma) * n)) + 1, n - 1)
+
+
+def band32_sum(n, W):
+    """Sum over the 32-wide output chunks of an axis of 32 x the length of
+    the chunk's band of k, aligned to 32 (the k range the panel-form passes,
+    the 3D plane pass and the axis-0 pass stage and multiply)."""
+    tot = 0
+    for i0 in range(0, n, 32):
+        kb0 = max(0, i0 - W) & ~31
+        kb1 = min(n, (i0 + 32 + W + 31) & ~31)
+        tot += 32 * (kb1 - kb0)
+    return tot
 
 
 def fused2d_executed_flops(n0, n1, W0, W1):
@@ -187,14 +199,14 @@ def roofline(wl, precision, q, traffic_profile=None, resident=True):
         names = [f"resident 2D kernel, {K} iterations"]
         kfile = "gibbs2d.hip"
         W = [band_halfwidth(n, wl.gamma) for n in wl.shape]
-        executed = K * 2 * fused2d_executed_flops(wl.shape[0], wl.shape[1], W[0], W[1])
+        executed = [K * 2 * fused2d_executed_flops(wl.shape[0], wl.shape[1], W[0], W[1])]
     elif len(ms) == 2 and d == 2:
         flops = [2.0 * (wl.shape[0] + wl.shape[1]) * N] * 2
         nbytes = [12.0 * N, (8.0 + fb) * N]
         names = ["fused 2D application, b-update epilogue", "fused 2D application, prox epilogue"]
         kfile = "gibbs2d.hip"
         W = [band_halfwidth(n, wl.gamma) for n in wl.shape]
-        executed = fused2d_executed_flops(wl.shape[0], wl.shape[1], W[0], W[1])
+        executed = [fused2d_executed_flops(wl.shape[0], wl.shape[1], W[0], W[1])] * 2
     elif len(ms) == 4 and d == 3:
         # plane pass (axes 1 and 2, intermediate on chip), then the axis-0 pass with the epilogue
         fp, fs = 2.0 * (wl.shape[1] + wl.shape[2]) * N, 2.0 * wl.shape[0] * N
@@ -203,7 +215,11 @@ def roofline(wl, precision, q, traffic_profile=None, resident=True):
         names = ["plane pass (axes 1, 2)", "axis-0 pass, b-update epilogue",
                  "plane pass (axes 1, 2)", "axis-0 pass, prox epilogue"]
         kfile = "contract.hip"
-        executed = None
+        n0, n1, n2 = wl.shape
+        W = [band_halfwidth(n, wl.gamma) for n in wl.shape]
+        ep = 2 * n0 * (n1 * band32_sum(n2, W[2]) + n2 * band32_sum(n1, W[1]))
+        es = 2 * n1 * n2 * band32_sum(n0, W[0])
+        executed = [ep, es, ep, es]
     else:
         order = list(range(d - 1, -1, -1)) * 2
         flops = [2.0 * wl.shape[ax] * N for ax in order]
@@ -212,7 +228,10 @@ def roofline(wl, precision, q, traffic_profile=None, resident=True):
         names = [f"axis-{ax} pass" + (", b-update epilogue" if i == d - 1 else ", prox epilogue" if i == 2 * d - 1 else "")
                  for i, ax in enumerate(order)]
         kfile = "contract.hip"
-        executed = None
+        # panel-form passes (axes of a multiple of 32) stage 32-aligned bands
+        W = [band_halfwidth(n, wl.gamma) for n in wl.shape]
+        executed = [2 * (N // wl.shape[ax]) * band32_sum(wl.shape[ax], W[ax]) if wl.shape[ax] % 32 == 0 else None
+                    for ax in order]
     k = int(np.argmax(ms))
     sec = ms[k] * 1e-3
     peak_f = PEAK_FP32_MFMA_TFLOPS if precision == "fp32" else PEAK_BF16_MFMA_TFLOPS
@@ -229,9 +248,12 @@ def roofline(wl, precision, q, traffic_profile=None, resident=True):
            "flops_per_launch": flops[k], "algorithmic_bytes_per_launch": nbytes[k],
            "ms_per_launch": round(ms[k], 5), "ms_per_launch_all": [round(x, 5) for x in ms],
            "other_roof": hbm if bound == "mfma" else mfma}
-    if executed is not None:
-        out["executed_mfma_flops_per_launch"] = executed
-        out["executed_mfma_frac"] = round(executed / sec / 1e12 / peak_f, 4)
+    if executed is not None and executed[k] is not None:
+        # executed MFMA work: the band-limited, tile-padded products the kernel
+        # issues (split-BF16 issues three bfloat16 products per FP32 product)
+        ex = executed[k] * (1 if precision == "fp32" else 3)
+        out["executed_mfma_flops_per_launch"] = ex
+        out["executed_mfma_frac"] = round(ex / sec / 1e12 / peak_f, 4)
     if len(ms) == 1:
         out["us_per_iteration"] = round(1e3 * ms[0] / wl.max_iters, 3)
         out["launch_per_application_ms"] = [round(x, 5) for x in per_launch]
@@ -253,18 +275,74 @@ def cpu_baseline(wl, seconds):
     O.jko_step(wl.p0, en, wl.gamma, wl.tau, n_it)
     el = time.perf_counter() - t0
     cores = len(os.sched_getaffinity(0))
+    blas_desc = "unknown BLAS"
     try:   # threads the BLAS behind numpy actually runs
         from threadpoolctl import threadpool_info
-        blas = [t["num_threads"] for t in threadpool_info() if t.get("user_api") == "blas"]
+        blas = [t for t in threadpool_info() if t.get("user_api") == "blas"]
         if blas:
-            cores = min(cores, max(blas))
+            cores = min(cores, max(t["num_threads"] for t in blas))
+            b = blas[0]
+            blas_desc = f"{b.get('internal_api', '?')} {b.get('version', '?')} ({b.get('num_threads')} threads)"
     except Exception:
         pass
     return {
         "value": round(n_it / el, 3), "unit": "Sinkhorn iters/s", "cores": cores, "kind": "oracle",
+        "cpu_model": _cpu_model(), "blas": blas_desc,
         "sample": f"FP64 oracle jko_step on {wl.name} {wl.shape} (separable numpy/BLAS kernel), "
-                  f"first JKO step, {n_it} fixed iterations, {el:.1f} s; cpu={platform.processor() or 'x86_64'}",
+                  f"first JKO step, {n_it} fixed iterations, {el:.1f} s",
     }
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def equal_accuracy_128(n_steps=20, iters=300, ref_iters=3000):
+    """Split-BF16 against FP32 on the 128^3 crowd flow (20 JKO steps x 300
+    iterations, absorption on max|log a| > 50) at equal final-density
+    accuracy.  Accuracy is the rel-L1 distance of p_T to a reference flow
+    whose steps run ten times longer (3000 iterations, FP32): at 300
+    iterations each step is short of its limit by far more than either
+    precision's rounding, so both precisions reach the same accuracy at the
+    same iteration count, and the speedup at equal accuracy is the ratio of
+    the flows' wall times."""
+    import torch
+    import paper_1502_06216_amd as jk
+    from workloads import make_workload
+    wl = make_workload("crowd128c")
+    en = _energy(wl)
+    p0 = _dev(wl.p0)
+
+    def run(prec, k):
+        jk.flow(p0, en, wl.gamma, wl.tau, 1, max_iters=10, precision=prec, with_stats=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pT, _, _ = jk.flow(p0, en, wl.gamma, wl.tau, n_steps, max_iters=k, precision=prec, with_stats=False,
+                           absorb_threshold=50.0, absorb_on_a=True)
+        torch.cuda.synchronize()
+        return pT.double().cpu().numpy(), time.perf_counter() - t0
+
+    ref, _ = run("fp32", ref_iters)
+    out = {"flow": f"crowd128c {n_steps} JKO steps x {iters} iterations",
+           "reference": f"the same flow at {ref_iters} iterations per step, FP32"}
+    res = {}
+    for prec in ("fp32", "split_bf16"):
+        p, t = run(prec, iters)
+        res[prec] = (p, t)
+        out[prec] = {"rel_l1_to_reference": float(np.abs(p - ref).sum() / np.abs(ref).sum()), "flow_s": round(t, 4)}
+    f, sp = res["fp32"][0], res["split_bf16"][0]
+    out["rel_l1_split_vs_fp32"] = float(np.abs(sp - f).sum() / np.abs(f).sum())
+    acc = [out[p]["rel_l1_to_reference"] for p in ("fp32", "split_bf16")]
+    out["accuracy_ratio_split_over_fp32"] = round(acc[1] / acc[0], 4)
+    out["speedup_split_over_fp32"] = round(res["fp32"][1] / res["split_bf16"][1], 4)
+    return out
 
 
 def adjoint_ratio(precision="fp32"):
@@ -443,12 +521,19 @@ def main():
             extra["crowd256_fp32_launch_per_application"] = {
                 "iters_per_s": round(it4 / el4, 2), "jko_steps_per_s": round(args.steps / el4, 3),
                 "iters_per_step": [s["iters"] for s in st4]}
+        # the 128^3 crowd as its precision configuration states it: absorption
+        # when max|log a| exceeds 50 (JKO_FLAG_ABSORB_ON_A; max|log a| stays
+        # near 5 here, so the step stays in the plain domain), checks every 10
         wl3 = make_workload("crowd128c")
         for prec in ("fp32", "split_bf16"):
-            it3, el3, st3, q3 = run_flow(wl3, prec, 2, 1, tol=0.0, max_iters=300)
+            it3, el3, st3, q3 = run_flow(wl3, prec, 2, 1, tol=0.0, max_iters=300, absorb_threshold=50.0,
+                                         absorb_on_a=True)
             extra[f"crowd128c_{prec}"] = {"iters_per_s": round(it3 / el3, 2), "jko_steps_per_s": round(2 / el3, 3),
-                                         "iters_per_step": 300,
+                                         "iters_per_step": 300, "absorb_threshold": 50.0, "absorb_on": "max|log a|",
+                                         "absorptions": [s["absorptions"] for s in st3],
+                                         "max_abs_log_a": [round(s["max_abs_log_a"], 3) for s in st3],
                                          "roofline": roofline(wl3, prec, q3, TRAFFIC_PROFILES.get(("crowd128c", prec)))}
+        extra["crowd128c_equal_accuracy"] = equal_accuracy_128()
         # the non-convex binary constraint {0, kappa} on the same crowd
         # (300 iterations per step: the non-convex iteration has no tolerance to reach)
         wlb = make_workload("crowd256_binary")
@@ -467,16 +552,18 @@ def main():
         # generalised entropies with exponents varying from 1 to 2 over the grid
         wlg = make_workload("gen512")
         for prec in ("fp32", "split_bf16"):
-            itg, elg, stg, _ = run_flow(wlg, prec, wlg.n_steps, 1)
+            itg, elg, stg, qg = run_flow(wlg, prec, wlg.n_steps, 1)
             extra[f"gen512_{prec}"] = {"iters_per_s": round(itg / elg, 2),
                                        "jko_steps_per_s": round(wlg.n_steps / elg, 3),
-                                       "iters_per_step": wlg.max_iters}
+                                       "iters_per_step": wlg.max_iters,
+                                       "roofline": roofline(wlg, prec, qg)}
         wl5 = make_workload("porous512_scaled")
         for prec in ("fp32", "split_bf16"):
-            it5, el5, st5, _ = run_flow(wl5, prec, 3, 1)
+            it5, el5, st5, q5 = run_flow(wl5, prec, 3, 1)
             extra[f"porous512_scaled_{prec}"] = {"iters_per_s": round(it5 / el5, 2),
                                                  "jko_steps_per_s": round(3 / el5, 3),
-                                                 "iters_per_step": [s["iters"] for s in st5]}
+                                                 "iters_per_step": [s["iters"] for s in st5],
+                                                 "roofline": roofline(wl5, prec, q5)}
         # heat-kernel Gibbs operator (L = 10 implicit steps) on a 100x100 room with obstacles
         extra["heat100_fp32"] = heat_bench(make_workload("heat100"))
         extra["adjoint_fp32"] = adjoint_ratio("fp32")

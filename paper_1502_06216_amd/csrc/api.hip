@@ -17,8 +17,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
-#include <vector>
 
 #include "jko_internal.h"
 #include "heat.h"
@@ -85,9 +85,18 @@ struct PassShape {
     int axis;
 };
 
-std::vector<PassShape> passes_of(const Geo& g) {
-    std::vector<PassShape> v;
-    for (int k = g.d - 1; k >= 0; --k) v.push_back(PassShape{g.N / g.n[k], g.n[k], k});
+struct PassList {
+    PassShape p[3];
+    int count = 0;
+    const PassShape* begin() const { return p; }
+    const PassShape* end() const { return p + count; }
+    size_t size() const { return (size_t)count; }
+    const PassShape& operator[](size_t i) const { return p[i]; }
+};
+
+PassList passes_of(const Geo& g) {
+    PassList v;
+    for (int k = g.d - 1; k >= 0; --k) v.p[v.count++] = PassShape{g.N / g.n[k], g.n[k], k};
     return v;
 }
 
@@ -123,7 +132,7 @@ struct Layout {
 
 int part_cap_of(const Geo& g) {
     int64_t cap = 768;   // input check uses 3 x 256
-    if (g.d == 2) cap = std::max<int64_t>(cap, gibbs2d_blocks(g.n[0], g.n[1]));
+    if (g.d == 2) cap = std::max<int64_t>(cap, gibbs2d_blocks(g.n[0], g.n[1], 16));
     for (const PassShape& ps : passes_of(g)) {
         const int64_t b = contract_max_blocks(make_pass(ps), 0);
         if (b > cap) cap = b;
@@ -208,6 +217,7 @@ struct Plan {
     bool ident[3] = {false, false, false};   // axis whose factor is the identity (the attraction's stacking axis)
     int W[3] = {0, 0, 0};        // float32 band half-widths of the factors
     bool fused2d = false;        // 2D applications use the fused band kernel
+    int tile = 0;                // ... with output tiles of this edge (16 or 32)
     bool resident = false;       // ... and a step may run in one resident launch
     bool plane3d = false;        // 3D applications run as a plane pass and a slow-axis pass
 
@@ -257,9 +267,17 @@ jko_status build_factors(Plan& P, double gamma, int32_t flags = 0) {
     P.plane3d = P.g.d == 3 && !(flags & JKO_FLAG_AXIS_PASSES) &&
                 plane3d_fits(P.g.n[0], P.g.n[1], P.g.n[2], P.W[0], P.W[1], P.W[2]);
     // The fused kernel trades redundant halo work for one launch per
-    // application: it wins while its grid is at most one block per CU.
-    P.fused2d = P.g.d == 2 && gibbs2d_fits(P.g.n[0], P.g.n[1], P.W[0], P.W[1], P.prec) &&
-                gibbs2d_blocks(P.g.n[0], P.g.n[1]) <= kFusedMaxBlocks;
+    // application: it wins while its grid is at most one block per CU, with
+    // 16 x 16 tiles where they are few enough, else with 32 x 32 tiles.
+    P.tile = 0;
+    if (P.g.d == 2)
+        for (int tt : {16, 32})
+            if (gibbs2d_fits(P.g.n[0], P.g.n[1], P.W[0], P.W[1], P.prec, tt) &&
+                gibbs2d_blocks(P.g.n[0], P.g.n[1], tt) <= kFusedMaxBlocks) {
+                P.tile = tt;
+                break;
+            }
+    P.fused2d = P.tile != 0;
     P.resident = P.fused2d;
     for (int k = 0; k < P.g.d; ++k) {
         bool done = false;
@@ -305,7 +323,8 @@ Pass slow_of(const Plan& P) {
 jko_status apply_xi(const Plan& P, const float* x, EpiArgs epi, int* nblocks) {
     set_vec(epi);
     if (P.fused2d) {
-        Band2D b{P.g.n[0], P.g.n[1], P.W[0], P.W[1], P.K1[0], P.K1[1], x, P.K1hi[0], P.K1lo[0], P.K1hi[1], P.K1lo[1]};
+        Band2D b{P.g.n[0], P.g.n[1], P.W[0],   P.W[1],   P.K1[0], P.K1[1],
+                 x,        P.K1hi[0], P.K1lo[0], P.K1hi[1], P.K1lo[1], P.tile};
         int nb = 0;
         HIP_TRY(launch_gibbs2d(b, P.prec, epi, &nb, P.st));
         if (nblocks) *nblocks = nb;
@@ -318,7 +337,7 @@ jko_status apply_xi(const Plan& P, const float* x, EpiArgs epi, int* nblocks) {
         if (nblocks) *nblocks = nb;
         return JKO_OK;
     }
-    const std::vector<PassShape> ps = passes_of(P.g);
+    const PassList ps = passes_of(P.g);
     const float* in = x;
     for (size_t i = 0; i < ps.size(); ++i) {
         Pass pass = make_pass(ps[i]);
@@ -383,15 +402,21 @@ jko_status apply_xi_in(bool logd, const Plan& P, const float* x, const EpiArgs& 
     return logd ? apply_xi_log(P, x, epi, nblocks) : apply_xi(P, x, epi, nblocks);
 }
 
-// Pinned host mirror of the control block (one per process) and its event.
+// Host mirror of the control block for the stop-test read-back: a pinned
+// buffer and an event (made once per thread), so that the host can look at
+// one check while the next interval is queued.
 struct Readback {
     Ctl* host = nullptr;
     hipEvent_t ev = nullptr;
     int device = -1;
 };
-thread_local Readback g_rb;
+thread_local Readback g_rb;              // pinned
+thread_local Readback* g_cur = &g_rb;    // the one the current call uses
+
+Readback& rb() { return *g_cur; }
 
 jko_status readback_init() {
+    g_cur = &g_rb;
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     if (g_rb.host && g_rb.device == dev) return JKO_OK;
@@ -406,9 +431,9 @@ jko_status readback_init() {
 }
 
 jko_status read_ctl(const Plan& P, Ctl* out) {
-    HIP_TRY(hipMemcpyAsync(g_rb.host, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, P.st));
+    HIP_TRY(hipMemcpyAsync(rb().host, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, P.st));
     HIP_TRY(hipStreamSynchronize(P.st));
-    *out = *g_rb.host;
+    *out = *rb().host;
     return JKO_OK;
 }
 
@@ -526,9 +551,9 @@ jko_status input_check(const Plan& P, const jko_energy* en, const float* p) {
     HIP_TRY(launch_input_check(p, en->kappa, en->kappa_scalar, P.g.N, is_congestion(en),
                                P.part.err, 3 * 256, P.hostout, P.st));
     double h[3];
-    HIP_TRY(hipMemcpyAsync(g_rb.host, P.hostout, 3 * sizeof(double), hipMemcpyDeviceToHost, P.st));
+    HIP_TRY(hipMemcpyAsync(rb().host, P.hostout, 3 * sizeof(double), hipMemcpyDeviceToHost, P.st));
     HIP_TRY(hipStreamSynchronize(P.st));
-    memcpy(h, g_rb.host, sizeof h);
+    memcpy(h, rb().host, sizeof h);
     if (h[2] > 0.0) return fail(JKO_ERR_NONFINITE, "input density or capacity has %g negative/non-finite cells", h[2]);
     if (is_congestion(en) && h[1] < h[0] * (1.0 - 1e-6))
         return fail(JKO_ERR_INFEASIBLE, "capacity sum %.9g < mass %.9g", h[1], h[0]);
@@ -538,7 +563,8 @@ jko_status input_check(const Plan& P, const jko_energy* en, const float* p) {
 // ----------------------------------------------------------------- resident
 
 bool use_resident(const Plan& P, const jko_params* pr, const ProxArgs& px) {
-    return P.resident && !(pr->flags & JKO_FLAG_NO_RESIDENT) && resident2d_fits(P.g.n[0], P.g.n[1], P.W[0], P.W[1], px.kind, P.prec);
+    return P.resident && !(pr->flags & JKO_FLAG_NO_RESIDENT) &&
+           resident2d_fits(P.g.n[0], P.g.n[1], P.W[0], P.W[1], px.kind, P.prec, P.tile);
 }
 
 // Queue the resident kernel for K iterations of a step (scalings and control
@@ -551,7 +577,7 @@ jko_status launch_resident(const Plan& P, const float* q, float* p_out, const Pr
     *launched = false;
     Resident2D r{};
     r.B = Band2D{P.g.n[0], P.g.n[1], P.W[0], P.W[1], P.K1[0], P.K1[1], nullptr,
-                 P.K1hi[0], P.K1lo[0], P.K1hi[1], P.K1lo[1]};
+                 P.K1hi[0], P.K1lo[0], P.K1hi[1], P.K1lo[1], P.tile};
     r.split = P.prec == JKO_SPLIT_BF16 ? 1 : 0;
     r.q = q;
     r.a = P.F(F_A);
@@ -580,7 +606,7 @@ jko_status launch_resident(const Plan& P, const float* q, float* p_out, const Pr
     set_vec(al);
     r.vec_ok = al.vec_ok && (r.hist_stride % 4 == 0);
     HIP_TRY(launch_fill(reinterpret_cast<float*>(P.sync), 0.f,
-                        resident_sync_words(gibbs2d_blocks(P.g.n[0], P.g.n[1])), P.st));
+                        resident_sync_words(gibbs2d_blocks(P.g.n[0], P.g.n[1], P.tile)), P.st));
     const hipError_t e = launch_resident2d(r, P.st);
     if (e == hipErrorCooperativeLaunchTooLarge) {
         (void)hipGetLastError();
@@ -594,9 +620,9 @@ jko_status launch_resident(const Plan& P, const float* q, float* p_out, const Pr
 // Synchronous: fails if a wait of the last resident launch ran out.
 jko_status resident_check(const Plan& P) {
     uint32_t w = 0;
-    HIP_TRY(hipMemcpyAsync(g_rb.host, P.sync, sizeof w, hipMemcpyDeviceToHost, P.st));
+    HIP_TRY(hipMemcpyAsync(rb().host, P.sync, sizeof w, hipMemcpyDeviceToHost, P.st));
     HIP_TRY(hipStreamSynchronize(P.st));
-    memcpy(&w, g_rb.host, sizeof w);
+    memcpy(&w, rb().host, sizeof w);
     if (w) return fail(JKO_ERR_HIP, "resident kernel: a wait for another block timed out");
     return JKO_OK;
 }
@@ -681,17 +707,22 @@ jko_status run_step(const Plan& P, const jko_params* pr, const ProxArgs& px, con
         jko_status s = apply_xi_in(logd, P, a, eb, &nb);
         if (s) return s;
         if (eb.check) HIP_TRY(launch_ctl_check(P.ctl, P.part, nb, k, pr->tol_l1, 1, absorb, a_only, P.st));
-        if (eb.check && tolmode) {
+        if (eb.check && tolmode && rb().ev) {
             // Look at the previous stop test while this interval is queued,
             // then queue the read-back of this one.
             if (pending) {
-                HIP_TRY(hipEventSynchronize(g_rb.ev));
-                if (g_rb.host->done) stopped = true;
+                HIP_TRY(hipEventSynchronize(rb().ev));
+                if (rb().host->done) stopped = true;
             }
             if (stopped) break;
-            HIP_TRY(hipMemcpyAsync(g_rb.host, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, P.st));
-            HIP_TRY(hipEventRecord(g_rb.ev, P.st));
+            HIP_TRY(hipMemcpyAsync(rb().host, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, P.st));
+            HIP_TRY(hipEventRecord(rb().ev, P.st));
             pending = true;
+        } else if (eb.check && tolmode) {
+            // no event: read this check back before queuing more
+            Ctl c{};
+            if ((s = read_ctl(P, &c))) return s;
+            if (c.done) break;
         }
         const bool cand = (checks && k % ce == 0) || k == K;
         ep.check = cand ? 1 : 0;
@@ -748,9 +779,9 @@ jko_status run_step(const Plan& P, const jko_params* pr, const ProxArgs& px, con
 // Mass of a density of N cells (synchronous).
 jko_status mass_of(const Plan& P, const float* p, int64_t N, double* out) {
     HIP_TRY(launch_input_check(p, nullptr, INFINITY, N, 0, P.part.err, 3 * 256, P.hostout, P.st));
-    HIP_TRY(hipMemcpyAsync(g_rb.host, P.hostout, sizeof(double), hipMemcpyDeviceToHost, P.st));
+    HIP_TRY(hipMemcpyAsync(rb().host, P.hostout, sizeof(double), hipMemcpyDeviceToHost, P.st));
     HIP_TRY(hipStreamSynchronize(P.st));
-    memcpy(out, g_rb.host, sizeof(double));
+    memcpy(out, rb().host, sizeof(double));
     return JKO_OK;
 }
 
@@ -804,15 +835,19 @@ jko_status run_attraction(const Plan& P, const jko_params* pr, const jko_energy*
         jko_status s = apply_xi_in(logd, P, a, eb, &nb);
         if (s) return s;
         if (eb.check) HIP_TRY(launch_ctl_check(P.ctl, P.part, nb, k, pr->tol_l1, 0, absorb, 0, P.st));
-        if (eb.check && tolmode) {
+        if (eb.check && tolmode && rb().ev) {
             if (pending) {
-                HIP_TRY(hipEventSynchronize(g_rb.ev));
-                if (g_rb.host->done) stopped = true;
+                HIP_TRY(hipEventSynchronize(rb().ev));
+                if (rb().host->done) stopped = true;
             }
             if (stopped) break;
-            HIP_TRY(hipMemcpyAsync(g_rb.host, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, P.st));
-            HIP_TRY(hipEventRecord(g_rb.ev, P.st));
+            HIP_TRY(hipMemcpyAsync(rb().host, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, P.st));
+            HIP_TRY(hipEventRecord(rb().ev, P.st));
             pending = true;
+        } else if (eb.check && tolmode) {
+            Ctl c{};
+            if ((s = read_ctl(P, &c))) return s;
+            if (c.done) break;
         }
         if ((s = apply_xi_in(logd, P, b, es, &nb))) return s;
         HIP_TRY(launch_attraction_prox(sv, a, p_out, en->kappa, en->kappa_scalar, alpha, N, P.ctl, P.st));
@@ -880,13 +915,13 @@ jko_status attraction_flow(const Geo& g, const jko_energy* en, const jko_params*
     // capacity of the initial density, and a target of the same mass
     double h[3], hr[3];
     HIP_TRY(launch_input_check(p0, en->kappa, en->kappa_scalar, g.N, 1, P.part.err, 3 * 256, P.hostout, P.st));
-    HIP_TRY(hipMemcpyAsync(g_rb.host, P.hostout, 3 * sizeof(double), hipMemcpyDeviceToHost, P.st));
+    HIP_TRY(hipMemcpyAsync(rb().host, P.hostout, 3 * sizeof(double), hipMemcpyDeviceToHost, P.st));
     HIP_TRY(hipStreamSynchronize(P.st));
-    memcpy(h, g_rb.host, sizeof h);
+    memcpy(h, rb().host, sizeof h);
     HIP_TRY(launch_input_check(en->target, nullptr, INFINITY, g.N, 0, P.part.err, 3 * 256, P.hostout, P.st));
-    HIP_TRY(hipMemcpyAsync(g_rb.host, P.hostout, 3 * sizeof(double), hipMemcpyDeviceToHost, P.st));
+    HIP_TRY(hipMemcpyAsync(rb().host, P.hostout, 3 * sizeof(double), hipMemcpyDeviceToHost, P.st));
     HIP_TRY(hipStreamSynchronize(P.st));
-    memcpy(hr, g_rb.host, sizeof hr);
+    memcpy(hr, rb().host, sizeof hr);
     if (h[2] > 0.0 || hr[2] > 0.0) return fail(JKO_ERR_NONFINITE, "input density, capacity or target has negative/non-finite cells");
     if (h[1] < h[0] * (1.0 - 1e-6)) return fail(JKO_ERR_INFEASIBLE, "capacity sum %.9g < mass %.9g", h[1], h[0]);
     if (!(hr[0] > 0.0)) return fail(JKO_ERR_INVALID, "attraction: the target has no mass");
@@ -1134,7 +1169,7 @@ jko_status jko_time_iteration(const jko_grid* grid, const jko_energy* energy, co
             }, &ms_per_launch[slot++]);
         }
     } else {
-        const std::vector<PassShape> ps = passes_of(g);
+        const PassList ps = passes_of(g);
         for (int app = 0; app < 2 && !s; ++app) {
             for (size_t i = 0; i < ps.size() && !s; ++i) {
                 Pass pass = make_pass(ps[i]);
@@ -1229,10 +1264,10 @@ jko_status jko_backward(const jko_grid* grid, const jko_energy* energy, const jk
                                 sigma, N, P.st));
         bool resident = false;
         if (P.resident && !(params->flags & JKO_FLAG_NO_RESIDENT) &&
-            resident_adj_fits(g.n[0], g.n[1], P.W[0], P.W[1], px.kind, P.prec)) {
+            resident_adj_fits(g.n[0], g.n[1], P.W[0], P.W[1], px.kind, P.prec, P.tile)) {
             ResidentAdj r{};
             r.B = Band2D{g.n[0], g.n[1], P.W[0], P.W[1], P.K1[0], P.K1[1], nullptr,
-                         P.K1hi[0], P.K1lo[0], P.K1hi[1], P.K1lo[1]};
+                         P.K1hi[0], P.K1lo[0], P.K1hi[1], P.K1lo[1], P.tile};
             r.q = q;
             r.hist = P.hist(0);
             r.hist_stride = (int64_t)(P.hist(1) - P.hist(0));
@@ -1254,7 +1289,8 @@ jko_status jko_backward(const jko_grid* grid, const jko_energy* energy, const jk
             al.prox = px;
             set_vec(al);
             r.vec_ok = al.vec_ok && aligned16(sbar) && aligned16(wacc) && (r.hist_stride % 4 == 0);
-            HIP_TRY(launch_fill(reinterpret_cast<float*>(P.sync), 0.f, resident_sync_words(gibbs2d_blocks(g.n[0], g.n[1])),
+            HIP_TRY(launch_fill(reinterpret_cast<float*>(P.sync), 0.f,
+                                resident_sync_words(gibbs2d_blocks(g.n[0], g.n[1], P.tile)),
                                 P.st));
             const hipError_t e = launch_resident_adj(r, P.st);
             if (e == hipErrorCooperativeLaunchTooLarge) {
@@ -1359,10 +1395,10 @@ jko_status heat_ws_check(const HeatLayout& H, void* ws, size_t ws_bytes) {
 // Reads the operator's record back and checks that it was built for this
 // domain (and, when gamma > 0, this gamma).  Synchronous.
 jko_status heat_hdr_check(const jko_heat_domain* d, const char* ws, double gamma, hipStream_t st, int64_t* nf) {
-    HIP_TRY(hipMemcpyAsync(g_rb.host, ws, sizeof(HeatHdr), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(rb().host, ws, sizeof(HeatHdr), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     HeatHdr h;
-    memcpy(&h, g_rb.host, sizeof h);
+    memcpy(&h, rb().host, sizeof h);
     if (h.magic != kHeatMagic || h.n0 != d->n0 || h.n1 != d->n1 || h.L != d->L)
         return fail(JKO_ERR_INVALID, "heat: the workspace holds no operator of this domain (call jko_heat_build)");
     if (gamma > 0.0 && h.gamma != gamma)
@@ -1374,9 +1410,9 @@ jko_status heat_hdr_check(const jko_heat_domain* d, const char* ws, double gamma
 jko_status heat_sums(const double* err, int64_t ne, const float* p, int64_t np, double* dev_out, hipStream_t st,
                      double h[3]) {
     HIP_TRY(launch_heat_sums(err, ne, p, np, dev_out, st));
-    HIP_TRY(hipMemcpyAsync(g_rb.host, dev_out, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(rb().host, dev_out, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    memcpy(h, g_rb.host, 3 * sizeof(double));
+    memcpy(h, rb().host, 3 * sizeof(double));
     return JKO_OK;
 }
 
@@ -1474,16 +1510,16 @@ jko_status jko_heat_build(const jko_heat_domain* domain, double gamma, void* ws,
     int32_t* gidx = reinterpret_cast<int32_t*>(base + H.gidx);
     int64_t* dcount = reinterpret_cast<int64_t*>(base + H.out);
     HIP_TRY(launch_heat_compact(domain->mask, H.N, cidx, gidx, dcount, st));
-    HIP_TRY(hipMemcpyAsync(g_rb.host, dcount, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(rb().host, dcount, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     int64_t nf = 0;
-    memcpy(&nf, g_rb.host, sizeof nf);
+    memcpy(&nf, rb().host, sizeof nf);
     HIP_TRY(heat_build_operator(domain->mask, domain->n0, domain->n1, gamma, domain->L, cidx, gidx, nf,
                                 reinterpret_cast<float*>(base + H.A), reinterpret_cast<double*>(base + H.scratch),
                                 st));
     HeatHdr h{kHeatMagic, domain->n0, domain->n1, domain->L, gamma, nf};
-    memcpy(g_rb.host, &h, sizeof h);
-    HIP_TRY(hipMemcpyAsync(base + H.hdr, g_rb.host, sizeof h, hipMemcpyHostToDevice, st));
+    memcpy(rb().host, &h, sizeof h);
+    HIP_TRY(hipMemcpyAsync(base + H.hdr, rb().host, sizeof h, hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
     return JKO_OK;
 }
@@ -1551,9 +1587,9 @@ jko_status jko_heat_flow(const jko_heat_domain* domain, const jko_energy* energy
     HIP_TRY(launch_heat_input(p0, domain->mask, is_congestion(energy) ? energy->kappa : nullptr,
                               is_congestion(energy) ? energy->kappa_scalar : INFINITY, H.N, dout, st));
     double h[3];
-    HIP_TRY(hipMemcpyAsync(g_rb.host, dout, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(rb().host, dout, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    memcpy(h, g_rb.host, sizeof h);
+    memcpy(h, rb().host, sizeof h);
     if (h[2] > 0.0)
         return fail(JKO_ERR_NONFINITE, "heat: %g cells of p0 are negative, non-finite or on an obstacle, "
                     "or have a negative capacity", h[2]);

@@ -138,7 +138,8 @@ hipError_t launch_contract_slow(const Pass& pass, int32_t precision, const EpiAr
 int64_t contract_slow_blocks(const Pass& pass);
 
 // Fused 2D application Y = K1_0 X K1_1 restricted to the float32 band of the
-// factors (|i - j| > W => K1[i][j] == 0 exactly).
+// factors (|i - j| > W => K1[i][j] == 0 exactly), one block per output tile of
+// tile x tile cells (16 or 32).
 struct Band2D {
     int n0, n1;            // grid
     int W0, W1;            // band half-widths of K1_0, K1_1
@@ -149,9 +150,11 @@ struct Band2D {
     const uint16_t* K0lo;
     const uint16_t* K1hi;
     const uint16_t* K1lo;
+    int tile;              // output tile edge: 16 or 32
 };
-bool gibbs2d_fits(int n0, int n1, int W0, int W1, int32_t precision);
-int64_t gibbs2d_blocks(int n0, int n1);
+// The tile's halo (tile + 2 W, aligned) fits the kernel's LDS.
+bool gibbs2d_fits(int n0, int n1, int W0, int W1, int32_t precision, int tile);
+int64_t gibbs2d_blocks(int n0, int n1, int tile);
 constexpr int64_t kFusedMaxBlocks = 256;   // one block per CU of the chip
 hipError_t launch_gibbs2d(const Band2D& b, int32_t precision, const EpiArgs& epi, int* nblocks,
                           hipStream_t stream);
@@ -207,11 +210,11 @@ struct ResidentAdj {
     int32_t spin_limit;
     int32_t split;
 };
-bool resident_adj_fits(int n0, int n1, int W0, int W1, int prox_kind, int32_t precision);
+bool resident_adj_fits(int n0, int n1, int W0, int W1, int prox_kind, int32_t precision, int tile);
 hipError_t launch_resident_adj(const ResidentAdj& r, hipStream_t stream);
 
 // True when all blocks of the resident kernel fit on the device at once.
-bool resident2d_fits(int n0, int n1, int W0, int W1, int prox_kind, int32_t precision);
+bool resident2d_fits(int n0, int n1, int W0, int W1, int prox_kind, int32_t precision, int tile);
 hipError_t launch_resident2d(const Resident2D& r, hipStream_t stream);
 
 // Largest |i - j| at which the float32 factor exp(-((i-j)/n)^2/gamma) can be
