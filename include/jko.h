@@ -250,6 +250,23 @@ jko_status jko_backward(const jko_grid* grid, const jko_energy* energy, const jk
                         const float* dL_dpT, float* dL_dw, float* dL_dp0,
                         void* workspace, size_t workspace_bytes, void* stream);
 
+/* jko_step without a workspace argument, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, semantics and results as jko_step;
+ * the workspace is a static device array of JKO_STATIC_WORKSPACE_BYTES inside
+ * the library, one per GPU, held from the first call on that GPU until the
+ * process ends.  The call allocates nothing: no device or pinned host memory
+ * and no event (its stop-test and statistics read-backs are synchronous
+ * copies to pageable host memory).  Grids whose step needs more workspace
+ * than the array holds (jko_workspace_bytes with JKO_OP_STEP, or
+ * JKO_OP_ATTRACTION_STEP) are refused with JKO_ERR_WORKSPACE before any
+ * launch; 2D grids up to 512 x 512 fit.  Every call on one GPU shares that
+ * GPU's array, so calls that overlap in time on one GPU (any streams, any
+ * threads) race and must not be made. */
+#define JKO_STATIC_WORKSPACE_BYTES ((size_t)16 << 20)
+jko_status jko_step_static(const jko_grid* grid, const jko_energy* energy, const jko_params* params,
+                           const float* p_in, float* p_out, jko_stats* stats, void* stream);
+
 /* Measurement aid (not part of the method): sets up one step of p_in as
  * jko_step does, then times its kernel launches `reps` times on `stream` with
  * HIP events.  Where a step runs on the resident 2D kernel (see

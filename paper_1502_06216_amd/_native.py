@@ -96,6 +96,8 @@ def load(path: str = LIB_PATH):
     lib.jko_gibbs_apply.restype = i32
     lib.jko_step.argtypes = [G, E, P, vp, vp, S, vp, sz, vp]
     lib.jko_step.restype = i32
+    lib.jko_step_static.argtypes = [G, E, P, vp, vp, S, vp]
+    lib.jko_step_static.restype = i32
     lib.jko_flow.argtypes = [G, E, P, i32, vp, vp, vp, S, vp, sz, vp]
     lib.jko_flow.restype = i32
     lib.jko_backward.argtypes = [G, E, P, i32, ctypes.POINTER(i32), vp, vp, vp, vp, vp, sz, vp]
@@ -256,6 +258,27 @@ def step(p: torch.Tensor, energy: EnergySpec, gamma: float, tau: float, max_iter
     st = Stats()
     _check(lib.jko_step(ctypes.byref(g), ctypes.byref(e), ctypes.byref(prm), _ptr(p), _ptr(pout),
                         ctypes.byref(st) if with_stats else None, _ptr(ws), ws.numel(), _stream(p.device)))
+    return pout, (st.as_dict() if with_stats else None)
+
+
+def step_static(p: torch.Tensor, energy: EnergySpec, gamma: float, tau: float, max_iters: int = 300,
+                tol: float = 0.0, check_every: int = 10, precision: str = "fp32",
+                absorb_threshold: float = math.inf, out: Optional[torch.Tensor] = None,
+                with_stats: bool = True, resident: bool = True, planes: bool = True, absorb_on_a: bool = False):
+    """step() on the library's static device workspace (jko_step_static): no
+    workspace tensor is allocated.  `out` (optional) lets the caller supply
+    the output buffer too, so that the call allocates nothing."""
+    lib = load()
+    shape = tuple(p.shape)
+    _field(p, shape, "p")
+    pout = torch.empty_like(p) if out is None else _field(out, shape, "out")
+    g = make_grid(shape)
+    prm = make_params(gamma, tau, max_iters, tol, check_every, precision, absorb_threshold, resident, planes,
+                      absorb_on_a)
+    e = energy.to_c(shape)
+    st = Stats()
+    _check(lib.jko_step_static(ctypes.byref(g), ctypes.byref(e), ctypes.byref(prm), _ptr(p), _ptr(pout),
+                               ctypes.byref(st) if with_stats else None, _stream(p.device)))
     return pout, (st.as_dict() if with_stats else None)
 
 

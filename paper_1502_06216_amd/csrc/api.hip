@@ -18,6 +18,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 
 #include "jko_internal.h"
@@ -402,20 +403,29 @@ jko_status apply_xi_in(bool logd, const Plan& P, const float* x, const EpiArgs& 
     return logd ? apply_xi_log(P, x, epi, nblocks) : apply_xi(P, x, epi, nblocks);
 }
 
-// Host mirror of the control block for the stop-test read-back: a pinned
-// buffer and an event (made once per thread), so that the host can look at
-// one check while the next interval is queued.
+// Host mirror of the control block for the stop-test read-back.  The calls
+// use a pinned buffer and an event (made once per thread), so that the host
+// can look at one check while the next interval is queued.  The no-allocation
+// entry point uses a pageable buffer and no event instead (every read-back is
+// synchronous).
 struct Readback {
     Ctl* host = nullptr;
     hipEvent_t ev = nullptr;
     int device = -1;
 };
 thread_local Readback g_rb;              // pinned
+thread_local Ctl g_pageable[4];
+thread_local Readback g_rb_pageable{g_pageable, nullptr, -1};
 thread_local Readback* g_cur = &g_rb;    // the one the current call uses
+thread_local bool g_no_alloc = false;    // inside jko_step_static
 
 Readback& rb() { return *g_cur; }
 
 jko_status readback_init() {
+    if (g_no_alloc) {
+        g_cur = &g_rb_pageable;
+        return JKO_OK;
+    }
     g_cur = &g_rb;
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
@@ -944,6 +954,44 @@ jko_status attraction_flow(const Geo& g, const jko_energy* en, const jko_params*
     return JKO_OK;
 }
 
+// ------------------------------------------------------------ no-allocation step
+//
+// Workspace of jko_step_static: one file-scope device array, of which each
+// GPU the library runs on holds its own copy until the process ends.  Host
+// code never passes the array's name to a kernel or copy (on the host it is
+// only a stand-in for the symbol): it takes the device address once per
+// device with hipGetSymbolAddress and uses that.
+constexpr size_t kStaticWorkspaceBytes = JKO_STATIC_WORKSPACE_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticWorkspaceBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+jko_status scratch_of(void** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(JKO_ERR_HIP, "device index %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(JKO_ERR_HIP, "hipGetSymbolAddress returned NULL for the static workspace");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return JKO_OK;
+}
+
+// While alive, read-backs use the pageable buffer (no pinned allocation, no event).
+struct NoAllocScope {
+    NoAllocScope() { g_no_alloc = true; }
+    ~NoAllocScope() {
+        g_no_alloc = false;
+        g_cur = &g_rb;
+    }
+};
+
 jko_status common_checks(const jko_grid* grid, Geo* g) {
     if (!geo_of(grid, g)) return fail(JKO_ERR_INVALID, "grid: ndim must be 1..3 and 1 <= n[k] <= %d", kMaxN);
     return JKO_OK;
@@ -1027,6 +1075,25 @@ jko_status jko_step(const jko_grid* grid, const jko_energy* energy, const jko_pa
     if ((s = input_check(P, energy, p_in))) return s;
     const ProxArgs px = prox_args(P, energy, sigma);
     return run_step(P, params, px, p_in, p_out, stats != nullptr, false, stats);
+}
+
+jko_status jko_step_static(const jko_grid* grid, const jko_energy* energy, const jko_params* params,
+                           const float* p_in, float* p_out, jko_stats* stats, void* stream) {
+    g_err.clear();
+    Geo g;
+    jko_status s = common_checks(grid, &g);
+    if (s) return s;
+    if ((s = check_params(params)) || (s = check_energy(energy))) return s;
+    const bool attr = energy->kind == JKO_F_ATTRACTION;
+    if (attr && g.d > 2) return fail(JKO_ERR_INVALID, "attraction: 1D and 2D grids only");
+    const size_t need = layout_of(attr ? stacked_of(g) : g, OP_STEP, 0).total;
+    if (need > kStaticWorkspaceBytes)
+        return fail(JKO_ERR_WORKSPACE, "jko_step_static: this grid needs %zu bytes of workspace; the static one holds %zu",
+                    need, kStaticWorkspaceBytes);
+    void* ws = nullptr;
+    if ((s = scratch_of(&ws))) return s;
+    NoAllocScope scope;
+    return jko_step(grid, energy, params, p_in, p_out, stats, ws, kStaticWorkspaceBytes, stream);
 }
 
 jko_status jko_flow(const jko_grid* grid, const jko_energy* energy, const jko_params* params, int32_t n_steps,
