@@ -296,22 +296,29 @@ jko_status jko_time_iteration(const jko_grid* grid, const jko_energy* energy, co
  * symmetric, non-negative and conserves mass on each connected part of M;
  * transport through it follows the domain's geodesics.
  *
- * The paper applies xi~ by L sparse back-substitutions per product.  This
- * library builds xi~ once per (domain, gamma, L) as a dense float32 matrix
- * in the workspace (N = n0 n1 <= 65536 cells; over the Nf free cells, the
- * upper triangle of 128 x 128 tiles, about Nf^2 * 2 bytes: 187 MB for the
- * 9556 free cells of a 100 x 100 room) by FP64 Chebyshev solves on the
- * device, then runs every product of the scaling iteration as one pass over
- * it.  The flow uses the
- * iteration and stop test of jko_step with xi replaced by xi~; float32 only,
- * no log domain, no backward.
+ * The paper applies xi~ by L sparse back-substitutions per product.  Up to
+ * 65536 cells this library builds xi~ once per (domain, gamma, L) as a dense
+ * float32 matrix in the workspace (over the Nf free cells, the upper triangle
+ * of 128 x 128 tiles, about Nf^2 * 2 bytes: 187 MB for the 9556 free cells of
+ * a 100 x 100 room) by FP64 Chebyshev solves on the device, then runs every
+ * product of the scaling iteration as one pass over it.  Above 65536 cells
+ * (or with per_product = 1) it applies xi~ the paper's way instead: each
+ * product is L solves of (Id - (gamma/L) Delta_M) y = rhs on the grid, each a
+ * Chebyshev iteration in FP64 (one five-point stencil sweep per iteration,
+ * to 1e-13 of the right-hand side; linear in the grid's size), rounded to
+ * float32; no operator is stored.  The flow uses the iteration and stop test
+ * of jko_step with xi replaced by xi~; float32 only, no log domain, no
+ * backward.
  * ------------------------------------------------------------------------ */
 typedef struct {
-    int32_t n0, n1;          /* grid, n0 x n1 cells (row-major, n1 fastest; n0 = 1: a 1D grid) */
+    int32_t n0, n1;          /* grid, n0 x n1 cells (row-major, n1 fastest; n0 = 1: a 1D grid),
+                                n0 * n1 <= 2^20 */
     const uint8_t* mask;     /* device, n0*n1 bytes, nonzero = free cell; NULL = no obstacle.
                                 Read by every call below: keep it alive and unchanged while the
                                 workspace's operator is in use */
     int32_t L;               /* implicit heat steps, 1..1000 (the paper uses 10) */
+    int32_t per_product;     /* 0: the stored dense operator while n0 * n1 <= 65536, the
+                                per-product solves above; 1: the per-product solves always */
 } jko_heat_domain;
 
 /* Bytes of device workspace the calls below need for this domain (the dense

@@ -61,7 +61,8 @@ class Params(ctypes.Structure):
 
 
 class HeatDomain(ctypes.Structure):
-    _fields_ = [("n0", ctypes.c_int32), ("n1", ctypes.c_int32), ("mask", ctypes.c_void_p), ("L", ctypes.c_int32)]
+    _fields_ = [("n0", ctypes.c_int32), ("n1", ctypes.c_int32), ("mask", ctypes.c_void_p), ("L", ctypes.c_int32),
+                ("per_product", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -380,12 +381,15 @@ class JKOFlowFn(torch.autograd.Function):
 class HeatOperator:
     """The heat-kernel Gibbs operator xi~ = (Id - (gamma/L) Delta_M)^{-L} of
     Section 4.1 on the free cells of a 2D grid (mask: CUDA bool/uint8 tensor
-    of the grid's shape, True = free; None = no obstacle).  Construction
-    builds xi~ once on the GPU into a workspace this object owns (N^2 * 4
-    bytes and more); apply() and flow() then use it.  The mask is kept (the
-    library reads it on every call)."""
+    of the grid's shape, True = free; None = no obstacle).  Up to 65536 cells
+    construction builds xi~ once on the GPU into a workspace this object owns
+    (N^2 * 2 bytes and more); above (or with per_product=True) every product
+    is L solves on the grid instead and nothing is stored.  apply() and
+    flow() then use it.  The mask is kept (the library reads it on every
+    call)."""
 
-    def __init__(self, shape, gamma: float, L: int = 10, mask: Optional[torch.Tensor] = None, device=None):
+    def __init__(self, shape, gamma: float, L: int = 10, mask: Optional[torch.Tensor] = None, device=None,
+                 per_product: bool = False):
         lib = load()
         shape = tuple(int(n) for n in shape)
         if len(shape) == 1:
@@ -406,7 +410,7 @@ class HeatOperator:
             self.mask = None
             device = torch.device("cuda") if device is None else torch.device(device)
         self.device = device
-        self.dom = HeatDomain(shape[0], shape[1], _ptr(self.mask), self.L)
+        self.dom = HeatDomain(shape[0], shape[1], _ptr(self.mask), self.L, 1 if per_product else 0)
         nb = lib.jko_heat_workspace_bytes(ctypes.byref(self.dom))
         if nb == 0:
             raise JKOError(JKO_ERR_INVALID, f"invalid heat domain {shape}, L={L}")

@@ -1403,31 +1403,41 @@ jko_status jko_backward(const jko_grid* grid, const jko_energy* energy, const jk
 namespace {
 
 constexpr int32_t kHeatMagic = 0x48454154;   // "HEAT"
-constexpr int64_t kHeatMaxCells = 65536;
+constexpr int64_t kHeatMaxCells = 65536;         // the stored dense operator
+constexpr int64_t kHeatMaxCellsSolve = 1 << 20;  // the per-product solves
 
 struct HeatHdr {
     int32_t magic, n0, n1, L;
+    int32_t solve, pad;      // 1: products by L solves (no stored operator)
     double gamma;
     int64_t nf;              // free cells (the operator's order)
 };
 
 struct HeatLayout {
     int64_t N = 0, ld = 0;
+    bool solve = false;      // products by L solves on the grid, no stored operator
     size_t hdr = 0, A = 0, part = 0, scratch = 0, cidx = 0, gidx = 0, a = 0, b = 0, x = 0, p0 = 0, p1 = 0, g = 0,
            kf = 0, err = 0, out = 0;
     size_t total = 0;
 };
 
-HeatLayout heat_layout(int n0, int n1) {
+// The dense stored operator up to 2^16 cells unless the domain asks for the
+// per-product solves; the solves above.
+bool heat_solve_mode(const jko_heat_domain* d) {
+    return d->per_product != 0 || (int64_t)d->n0 * d->n1 > kHeatMaxCells;
+}
+
+HeatLayout heat_layout(int n0, int n1, bool solve) {
     HeatLayout H;
     H.N = (int64_t)n0 * n1;
     H.ld = heat_ld(H.N);
+    H.solve = solve;
     size_t o = 0;
     auto take = [&](size_t bytes) { const size_t at = o; o = align_up(o + bytes); return at; };
     H.hdr = take(sizeof(HeatHdr));
-    H.A = take((size_t)heat_operator_floats(H.N) * sizeof(float));
-    H.part = take((size_t)heat_partial_floats(H.N) * sizeof(float));
-    H.scratch = take((size_t)heat_build_scratch(H.N) * sizeof(double));
+    H.A = take(solve ? 0 : (size_t)heat_operator_floats(H.N) * sizeof(float));
+    H.part = take(solve ? 0 : (size_t)heat_partial_floats(H.N) * sizeof(float));
+    H.scratch = take((size_t)(solve ? 4 * H.N : heat_build_scratch(H.N)) * sizeof(double));
     H.cidx = take(H.N * sizeof(int32_t));
     H.gidx = take(H.N * sizeof(int32_t));
     H.a = take(H.ld * sizeof(float));
@@ -1445,9 +1455,9 @@ HeatLayout heat_layout(int n0, int n1) {
 
 jko_status heat_domain_check(const jko_heat_domain* d) {
     if (!d) return fail(JKO_ERR_INVALID, "heat domain is NULL");
-    if (d->n0 < 1 || d->n1 < 1 || (int64_t)d->n0 * d->n1 > kHeatMaxCells)
+    if (d->n0 < 1 || d->n1 < 1 || (int64_t)d->n0 * d->n1 > kHeatMaxCellsSolve)
         return fail(JKO_ERR_INVALID, "heat domain: need n0, n1 >= 1 and n0 * n1 <= %lld",
-                    (long long)kHeatMaxCells);
+                    (long long)kHeatMaxCellsSolve);
     if (d->L < 1 || d->L > 1000) return fail(JKO_ERR_INVALID, "heat domain: L must be in 1..1000");
     return JKO_OK;
 }
@@ -1466,11 +1476,21 @@ jko_status heat_hdr_check(const jko_heat_domain* d, const char* ws, double gamma
     HIP_TRY(hipStreamSynchronize(st));
     HeatHdr h;
     memcpy(&h, rb().host, sizeof h);
-    if (h.magic != kHeatMagic || h.n0 != d->n0 || h.n1 != d->n1 || h.L != d->L)
+    if (h.magic != kHeatMagic || h.n0 != d->n0 || h.n1 != d->n1 || h.L != d->L || h.solve != (heat_solve_mode(d) ? 1 : 0))
         return fail(JKO_ERR_INVALID, "heat: the workspace holds no operator of this domain (call jko_heat_build)");
     if (gamma > 0.0 && h.gamma != gamma)
         return fail(JKO_ERR_INVALID, "heat: operator built for gamma %.17g, params ask %.17g", h.gamma, gamma);
     *nf = h.nf;
+    return JKO_OK;
+}
+
+// The gamma the workspace's operator was built for (synchronous).
+jko_status heat_hdr_gamma(const char* ws, hipStream_t st, double* gamma) {
+    HIP_TRY(hipMemcpyAsync(rb().host, ws, sizeof(HeatHdr), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    HeatHdr h;
+    memcpy(&h, rb().host, sizeof h);
+    *gamma = h.gamma;
     return JKO_OK;
 }
 
@@ -1483,12 +1503,38 @@ jko_status heat_sums(const double* err, int64_t ne, const float* p, int64_t np, 
     return JKO_OK;
 }
 
+// One product of the iteration with the epilogue `ek`: a pass over the stored
+// operator, or the L solves of the per-product form (hs.X != NULL).
+jko_status heat_product(int ek, const HeatGemv& g, const HeatSolve& hs, hipStream_t st) {
+    if (hs.X) HIP_TRY(launch_heat_solve(ek, g, hs, st));
+    else HIP_TRY(launch_heat_gemv(ek, g, st));
+    return JKO_OK;
+}
+
+// The per-product solves' context of a domain (X = NULL for the stored operator).
+HeatSolve heat_solve_of(const HeatLayout& H, const jko_heat_domain* d, char* base, double gamma) {
+    HeatSolve hs{};
+    if (!H.solve) return hs;
+    double* sc = reinterpret_cast<double*>(base + H.scratch);
+    hs.mask = d->mask;
+    hs.cidx = reinterpret_cast<const int32_t*>(base + H.cidx);
+    hs.n0 = d->n0;
+    hs.n1 = d->n1;
+    hs.L = d->L;
+    hs.gamma = gamma;
+    hs.X = sc;
+    hs.R = sc + H.N;
+    hs.D0 = sc + 2 * H.N;
+    hs.D1 = sc + 3 * H.N;
+    return hs;
+}
+
 // One step q -> p_out by the reduced iteration (t = xi~ a; b = q / t;
 // s = xi~ b; p = Prox(s); a = p / s) with the stop test of the band path:
 // at iteration k > 1 with (k - 1) % check_every == 0 and tol > 0 the
 // violation ||b t - q||_1 of iteration k - 1 is summed, and the step returns
 // that iterate when it is at most tol.
-jko_status heat_step(const HeatLayout& H, char* base, int64_t nf, const jko_params* pr,
+jko_status heat_step(const HeatLayout& H, char* base, int64_t nf, const HeatSolve& hs, const jko_params* pr,
                      const ProxArgs& px, int kind, const float* q, float* p_out, jko_stats* st_out,
                      hipStream_t st) {
     const float* A = reinterpret_cast<const float*>(base + H.A);
@@ -1522,9 +1568,10 @@ jko_status heat_step(const HeatLayout& H, char* base, int64_t nf, const jko_para
     double h[3] = {0.0, 0.0, 0.0};
     for (int k = 1; k <= pr->max_iters; ++k) {
         gt.check = tolmode && k > 1 && (k - 1) % pr->check_every == 0;
-        HIP_TRY(launch_heat_gemv(HEAT_EK_BUPDATE, gt, st));
+        jko_status s = heat_product(HEAT_EK_BUPDATE, gt, hs, st);
+        if (s) return s;
         if (gt.check) {
-            jko_status s = heat_sums(err, nf, nullptr, 0, dout, st, h);
+            s = heat_sums(err, nf, nullptr, 0, dout, st, h);
             if (s) return s;
             if (h[2] > 0.0) break;
             if (h[0] <= pr->tol_l1) {
@@ -1533,9 +1580,12 @@ jko_status heat_step(const HeatLayout& H, char* base, int64_t nf, const jko_para
                 break;
             }
         }
-        HIP_TRY(launch_heat_gemv(HEAT_EK_PROX + kind, gs, st));
+        if ((s = heat_product(HEAT_EK_PROX + kind, gs, hs, st))) return s;
     }
-    if (!bytol && h[2] == 0.0) HIP_TRY(launch_heat_gemv(HEAT_EK_MONITOR, gt, st));
+    if (!bytol && h[2] == 0.0) {
+        jko_status s = heat_product(HEAT_EK_MONITOR, gt, hs, st);
+        if (s) return s;
+    }
     jko_status s = heat_sums(err, nf, p_out, H.N, dout, st, h);
     if (s) return s;
     const bool bad = h[2] > 0.0 || !isfinite(h[0]) || !isfinite(h[1]);
@@ -1559,8 +1609,9 @@ jko_status heat_step(const HeatLayout& H, char* base, int64_t nf, const jko_para
 extern "C" {
 
 size_t jko_heat_workspace_bytes(const jko_heat_domain* domain) {
-    if (!domain || domain->n0 < 1 || domain->n1 < 1 || (int64_t)domain->n0 * domain->n1 > kHeatMaxCells) return 0;
-    return heat_layout(domain->n0, domain->n1).total;
+    if (!domain || domain->n0 < 1 || domain->n1 < 1 || (int64_t)domain->n0 * domain->n1 > kHeatMaxCellsSolve)
+        return 0;
+    return heat_layout(domain->n0, domain->n1, heat_solve_mode(domain)).total;
 }
 
 jko_status jko_heat_build(const jko_heat_domain* domain, double gamma, void* ws, size_t ws_bytes, void* stream) {
@@ -1568,7 +1619,7 @@ jko_status jko_heat_build(const jko_heat_domain* domain, double gamma, void* ws,
     jko_status s = heat_domain_check(domain);
     if (s) return s;
     if (!(gamma > 0.0) || !isfinite(gamma)) return fail(JKO_ERR_INVALID, "gamma must be finite and > 0");
-    const HeatLayout H = heat_layout(domain->n0, domain->n1);
+    const HeatLayout H = heat_layout(domain->n0, domain->n1, heat_solve_mode(domain));
     if ((s = heat_ws_check(H, ws, ws_bytes))) return s;
     if ((s = readback_init())) return s;
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -1581,10 +1632,11 @@ jko_status jko_heat_build(const jko_heat_domain* domain, double gamma, void* ws,
     HIP_TRY(hipStreamSynchronize(st));
     int64_t nf = 0;
     memcpy(&nf, rb().host, sizeof nf);
-    HIP_TRY(heat_build_operator(domain->mask, domain->n0, domain->n1, gamma, domain->L, cidx, gidx, nf,
-                                reinterpret_cast<float*>(base + H.A), reinterpret_cast<double*>(base + H.scratch),
-                                st));
-    HeatHdr h{kHeatMagic, domain->n0, domain->n1, domain->L, gamma, nf};
+    if (!H.solve)
+        HIP_TRY(heat_build_operator(domain->mask, domain->n0, domain->n1, gamma, domain->L, cidx, gidx, nf,
+                                    reinterpret_cast<float*>(base + H.A), reinterpret_cast<double*>(base + H.scratch),
+                                    st));
+    HeatHdr h{kHeatMagic, domain->n0, domain->n1, domain->L, H.solve ? 1 : 0, 0, gamma, nf};
     memcpy(rb().host, &h, sizeof h);
     HIP_TRY(hipMemcpyAsync(base + H.hdr, rb().host, sizeof h, hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -1598,13 +1650,15 @@ jko_status jko_heat_apply(const jko_heat_domain* domain, const float* x, float* 
     if (s) return s;
     if (!x || !y) return fail(JKO_ERR_INVALID, "x and y must be non-NULL");
     if (x == y) return fail(JKO_ERR_INVALID, "x and y may not alias");
-    const HeatLayout H = heat_layout(domain->n0, domain->n1);
+    const HeatLayout H = heat_layout(domain->n0, domain->n1, heat_solve_mode(domain));
     if ((s = heat_ws_check(H, ws, ws_bytes))) return s;
     if ((s = readback_init())) return s;
     hipStream_t st = static_cast<hipStream_t>(stream);
     char* base = static_cast<char*>(ws);
     int64_t nf = 0;
     if ((s = heat_hdr_check(domain, base + H.hdr, 0.0, st, &nf))) return s;
+    double gamma = 0.0;   // the gamma the workspace was built for
+    if ((s = heat_hdr_gamma(base + H.hdr, st, &gamma))) return s;
     const int32_t* gidx = reinterpret_cast<const int32_t*>(base + H.gidx);
     float* xp = reinterpret_cast<float*>(base + H.x);
     HIP_TRY(launch_heat_gather(xp, x, gidx, nf, heat_ld(nf), st));
@@ -1618,8 +1672,7 @@ jko_status jko_heat_apply(const jko_heat_domain* domain, const float* x, float* 
     g.gidx = gidx;
     g.x = xp;
     g.y = y;
-    HIP_TRY(launch_heat_gemv(HEAT_EK_STORE, g, st));
-    return JKO_OK;
+    return heat_product(HEAT_EK_STORE, g, heat_solve_of(H, domain, base, gamma), st);
 }
 
 jko_status jko_heat_flow(const jko_heat_domain* domain, const jko_energy* energy, const jko_params* params,
@@ -1636,7 +1689,7 @@ jko_status jko_heat_flow(const jko_heat_domain* domain, const jko_energy* energy
     if (n_steps < 1) return fail(JKO_ERR_INVALID, "n_steps must be >= 1");
     if (!p0 || !pT) return fail(JKO_ERR_INVALID, "p0 and pT must be non-NULL");
     if (p0 == pT) return fail(JKO_ERR_INVALID, "p0 and pT may not alias");
-    const HeatLayout H = heat_layout(domain->n0, domain->n1);
+    const HeatLayout H = heat_layout(domain->n0, domain->n1, heat_solve_mode(domain));
     if ((s = heat_ws_check(H, ws, ws_bytes))) return s;
     if ((s = readback_init())) return s;
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -1667,7 +1720,8 @@ jko_status jko_heat_flow(const jko_heat_domain* domain, const jko_energy* energy
     jko_status worst = JKO_OK;
     for (int t = 0; t < n_steps; ++t) {
         float* out = (t == n_steps - 1) ? pT : reinterpret_cast<float*>(base + ((t % 2 == 0) ? H.p0 : H.p1));
-        s = heat_step(H, base, nf, params, px, energy->kind, q, out, stats ? &stats[t] : nullptr, st);
+        s = heat_step(H, base, nf, heat_solve_of(H, domain, base, params->gamma), params, px, energy->kind, q, out,
+                      stats ? &stats[t] : nullptr, st);
         if (s == JKO_ERR_NONFINITE) worst = s;
         else if (s) return s;
         q = out;

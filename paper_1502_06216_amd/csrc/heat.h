@@ -66,8 +66,30 @@ hipError_t launch_heat_gather(float* x, const float* src, const int32_t* gidx, i
                               hipStream_t st);
 
 // Chebyshev iterations per implicit step that bring the error of each solve
-// below 1e-14 of the right-hand side for the spectrum [1, beta].
-int heat_cheb_iters(double beta);
+// below tol of the right-hand side for the spectrum [1, beta].
+int heat_cheb_iters(double beta, double tol);
+
+// Per-product form: the L solves of one product stop at this error relative
+// to the right-hand side's norm.  A product's far tail lies many orders below
+// its norm, and the scaling iteration divides by it (b = q / t), so the bound
+// sits far below float32 resolution.
+constexpr double kHeatSolveTol = 1e-13;
+
+// One product y = xi~ x by L solves on the grid (the paper's form of the
+// operator): x (free-cell vector of g) is scattered to the grid vector X,
+// solved in place, and each free row finished by the epilogue `ek` of g
+// (codes of launch_heat_gemv).  R, D0, D1: grid scratch (N doubles each).
+struct HeatSolve {
+    const uint8_t* mask;     // NULL = no obstacle
+    const int32_t* cidx;     // grid cell -> free index or -1
+    int n0, n1, L;
+    double gamma;
+    double* X;
+    double* R;
+    double* D0;
+    double* D1;
+};
+hipError_t launch_heat_solve(int ek, const HeatGemv& g, const HeatSolve& h, hipStream_t st);
 
 // Scratch doubles heat_build_operator needs for an N-cell grid (4 N C).
 int64_t heat_build_scratch(int64_t N);

@@ -11,6 +11,12 @@
 // triangle is stored (xi~ is symmetric): the 9556 free cells of a 100 x 100
 // room take 187 MB, which fits the device's 256 MB last-level cache.
 //
+// Grids of more than 2^16 cells (or on request) take the paper's own form
+// instead: each product is L successive solves of (Id - (gamma/L) Delta_M) y
+// = rhs on the grid, by the same Chebyshev iteration in FP64 with one vector
+// (a stencil sweep per iteration, linear in the grid's size), and its result
+// goes through the same epilogues.  No operator is stored.
+//
 // Construction: the columns of xi~ are L successive solves of
 // M x = rhs, M = Id + nu_0 G_0 + nu_1 G_1, from unit vectors, all columns of
 // a chunk at once (C columns, element (cell i, column c) at i*C + c, so the
@@ -164,6 +170,15 @@ __global__ void k_heat_gather(float* __restrict__ x, const float* __restrict__ s
 
 // ------------------------------------------------------------------ products
 
+// X (grid, FP64) = the free-cell vector x scattered to its cells, 0 on obstacles.
+__global__ void k_heat_scatter(double* __restrict__ X, const float* __restrict__ x, const int32_t* __restrict__ cidx,
+                               int64_t N) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t r = cidx[i];
+        X[i] = r >= 0 ? (double)x[r] : 0.0;
+    }
+}
+
 // Finish row r (free cell i = gidx[r]) of y = A x (value v): the epilogue of
 // the iteration's half-step.
 template <int EK>
@@ -216,7 +231,7 @@ __device__ __forceinline__ f4 ld_nt(const f4* p) {
 //                                      from the transposed lower tile)
 // so that every (row block, tile) slot of part is written exactly once.  A
 // tile row is 32 float4s: thread (group g, lane c) takes float4 c of rows
-// g, g + 8, ..., g + 120 (non-temporal loads), keeps one partial row sum per
+// g, g + 8, ..., g + 120 (plain loads, see ld_nt), keeps one partial row sum per
 // row and four column sums in registers; the row partials are then summed
 // through LDS (one row per thread), the column sums over the 8 groups.
 __global__ void __launch_bounds__(256) k_heat_tiles(const float* __restrict__ A, const float* __restrict__ x,
@@ -289,6 +304,14 @@ __global__ void __launch_bounds__(256) k_heat_finish(HeatGemv g) {
     }
 }
 
+// Finish of a product computed by the solves: row r takes its cell's value of
+// X (rounded to float32) through the epilogue.
+template <int EK>
+__global__ void __launch_bounds__(256) k_heat_solve_finish(HeatGemv g, const double* __restrict__ X) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < g.N; r += (int64_t)gridDim.x * blockDim.x)
+        heat_epilogue<EK>(g, r, (float)X[g.gidx[r]]);
+}
+
 __global__ void k_heat_fill(float* __restrict__ x, float v, int64_t n, int64_t ld) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ld; i += (int64_t)gridDim.x * blockDim.x)
         x[i] = i < n ? v : 0.f;
@@ -347,6 +370,41 @@ int chunk_log2(int64_t N) {
     return lg;                                    // at most 1024 columns per chunk
 }
 
+// L solves of M y = X in place on the grid vector X (obstacles stay zero),
+// each a Chebyshev iteration of K steps from the first guess X.
+void heat_solves(const HeatSolve& h, int K, hipStream_t st) {
+    const int64_t N = (int64_t)h.n0 * h.n1;
+    const double nu0 = h.n0 > 1 ? h.gamma * (double)h.n0 * h.n0 / h.L : 0.0;
+    const double nu1 = h.n1 > 1 ? h.gamma * (double)h.n1 * h.n1 / h.L : 0.0;
+    const double beta = 1.0 + 4.0 * (nu0 + nu1);
+    const double theta = 0.5 * (beta + 1.0), delta = 0.5 * (beta - 1.0);
+    const int gb = grid_for(N);
+    double* D[2] = {h.D0, h.D1};
+    for (int l = 0; l < h.L && K > 0; ++l) {
+        hipLaunchKernelGGL(k_heat_cheb_init, dim3(gb), dim3(256), 0, st, h.X, h.R, D[0], h.mask, N, 0, h.n0, h.n1,
+                           nu0, nu1, 1.0 / theta);
+        const double sigma1 = theta / delta;
+        double rho = 1.0 / sigma1;
+        for (int k = 0; k < K; ++k) {
+            const double rho_n = 1.0 / (2.0 * sigma1 - rho);
+            hipLaunchKernelGGL(k_heat_cheb_step, dim3(gb), dim3(256), 0, st, h.X, h.R, D[k & 1], D[(k + 1) & 1],
+                               h.mask, N, 0, h.n0, h.n1, nu0, nu1, rho_n * rho, 2.0 * rho_n / delta);
+            rho = rho_n;
+        }
+    }
+}
+
+template <int EK>
+hipError_t solve_as(const HeatGemv& g, const HeatSolve& h, hipStream_t st) {
+    const int64_t N = (int64_t)h.n0 * h.n1;
+    hipLaunchKernelGGL(k_heat_scatter, dim3(grid_for(N)), dim3(256), 0, st, h.X, g.x, h.cidx, N);
+    const double nu0 = h.n0 > 1 ? h.gamma * (double)h.n0 * h.n0 / h.L : 0.0;
+    const double nu1 = h.n1 > 1 ? h.gamma * (double)h.n1 * h.n1 / h.L : 0.0;
+    heat_solves(h, heat_cheb_iters(1.0 + 4.0 * (nu0 + nu1), kHeatSolveTol), st);
+    if (g.N > 0) hipLaunchKernelGGL(k_heat_solve_finish<EK>, dim3(grid_for(g.N)), dim3(256), 0, st, g, h.X);
+    return hipGetLastError();
+}
+
 template <int EK>
 hipError_t gemv_as(const HeatGemv& g, hipStream_t st) {
     if (g.nT == 0) return hipSuccess;   // no free cell
@@ -358,11 +416,11 @@ hipError_t gemv_as(const HeatGemv& g, hipStream_t st) {
 
 }  // namespace
 
-int heat_cheb_iters(double beta) {
+int heat_cheb_iters(double beta, double tol) {
     if (!(beta > 1.0)) return 0;
     const double sk = sqrt(beta);
     const double c = (sk - 1.0) / (sk + 1.0);
-    return (int)ceil(log(0.5e-14) / log(c));
+    return (int)ceil(log(0.5 * tol) / log(c));
 }
 
 int64_t heat_build_scratch(int64_t N) { return 4 * N * ((int64_t)1 << chunk_log2(N)); }
@@ -376,7 +434,7 @@ hipError_t heat_build_operator(const uint8_t* mask, int n0, int n1, double gamma
     const double nu0 = n0 > 1 ? gamma * (double)n0 * n0 / L : 0.0;
     const double nu1 = n1 > 1 ? gamma * (double)n1 * n1 / L : 0.0;
     const double beta = 1.0 + 4.0 * (nu0 + nu1);
-    const int K = heat_cheb_iters(beta);
+    const int K = heat_cheb_iters(beta, 1e-14);
     const double theta = 0.5 * (beta + 1.0), delta = 0.5 * (beta - 1.0);
     hipLaunchKernelGGL(k_heat_zero, dim3(grid_for(heat_operator_floats(nf))), dim3(256), 0, st, A,
                        heat_operator_floats(nf));
@@ -417,6 +475,21 @@ hipError_t launch_heat_gemv(int ek, const HeatGemv& g, hipStream_t st) {
         case EK_PROX + JKO_F_ENTROPY: return gemv_as<EK_PROX + JKO_F_ENTROPY>(g, st);
         case EK_PROX + JKO_F_CONGESTION_BINARY: return gemv_as<EK_PROX + JKO_F_CONGESTION_BINARY>(g, st);
         case EK_PROX + JKO_F_GEN_ENTROPY: return gemv_as<EK_PROX + JKO_F_GEN_ENTROPY>(g, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_heat_solve(int ek, const HeatGemv& g, const HeatSolve& h, hipStream_t st) {
+    switch (ek) {
+        case EK_STORE: return solve_as<EK_STORE>(g, h, st);
+        case EK_BUPDATE: return solve_as<EK_BUPDATE>(g, h, st);
+        case EK_MONITOR: return solve_as<EK_MONITOR>(g, h, st);
+        case EK_PROX + JKO_F_ZERO: return solve_as<EK_PROX + JKO_F_ZERO>(g, h, st);
+        case EK_PROX + JKO_F_CONGESTION: return solve_as<EK_PROX + JKO_F_CONGESTION>(g, h, st);
+        case EK_PROX + JKO_F_POROUS: return solve_as<EK_PROX + JKO_F_POROUS>(g, h, st);
+        case EK_PROX + JKO_F_ENTROPY: return solve_as<EK_PROX + JKO_F_ENTROPY>(g, h, st);
+        case EK_PROX + JKO_F_CONGESTION_BINARY: return solve_as<EK_PROX + JKO_F_CONGESTION_BINARY>(g, h, st);
+        case EK_PROX + JKO_F_GEN_ENTROPY: return solve_as<EK_PROX + JKO_F_GEN_ENTROPY>(g, h, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -193,8 +193,13 @@ def test_heat_domain_layout_and_workspace(lib):
     nb = lib.jko_heat_workspace_bytes(ctypes.byref(d))
     assert nb >= 79 * 80 // 2 * 128 * 128 * 4
     assert lib.jko_heat_workspace_bytes(ctypes.byref(nat.HeatDomain(1, 9, None, 10))) > 0
-    for n0, n1 in ((0, 5), (5, 0), (300, 300)):
+    for n0, n1 in ((0, 5), (5, 0), (1025, 1025)):
         assert lib.jko_heat_workspace_bytes(ctypes.byref(nat.HeatDomain(n0, n1, None, 10))) == 0
+    # above 2^16 cells (or on request) the products are solves: no stored operator
+    big = lib.jko_heat_workspace_bytes(ctypes.byref(nat.HeatDomain(300, 300, None, 10)))
+    assert 0 < big < 300 * 300 * 100
+    solve = lib.jko_heat_workspace_bytes(ctypes.byref(nat.HeatDomain(100, 100, None, 10, 1)))
+    assert 0 < solve < 100 * 100 * 100 < nb
     assert lib.jko_heat_workspace_bytes(None) == 0
     stream = ctypes.c_void_p(0)
     fake = ctypes.c_void_p(0x1000)

@@ -2,11 +2,12 @@
 2D grids, on the HIP path against the FP64 oracle (sparse LU solves),
 through the C ABI.
 
-The library stores xi~ as a dense float32 matrix built on the device by
-FP64 Chebyshev solves; each product is one matrix-vector pass in float32.
-Tolerances: the operator 1e-6 (rel-L1 of a product: float32 entries and
-float32 sums), the flows 1e-5 (rel-L1 of the density, as for the Gaussian
-kernel).
+Up to 2^16 cells the library stores xi~ as a dense float32 matrix built on
+the device by FP64 Chebyshev solves; each product is one matrix-vector pass
+in float32.  Above (or on request) each product is the paper's L implicit
+solves, by FP64 Chebyshev stencil sweeps on the grid.  Tolerances: the
+operator 1e-6 (rel-L1 of a product: float32 entries and float32 sums), the
+flows 1e-5 (rel-L1 of the density, as for the Gaussian kernel).
 """
 import numpy as np
 import pytest
@@ -210,7 +211,7 @@ def test_heat100_one_step_full_size():
 
 
 def test_largest_grid():
-    """The largest grid the heat path takes (2^16 cells: a 256 x 256 room,
+    """The largest grid of the stored operator (2^16 cells: a 256 x 256 room,
     512 tiles a side, an 8.6 GB operator): a product and a 10-iteration
     step against the oracle."""
     banner("heat largest grid 256x256")
@@ -273,3 +274,53 @@ def test_degenerate_domains():
     ref, _ = _oracle_flow(wl, o_en, 1, 30)
     assert host64(p)[:, 12:].max() == 0.0
     assert rel_l1(host64(p), ref) <= TOL_FLOW
+
+
+def test_per_product_solves_match_the_stored_operator_and_oracle():
+    """The per-product form (L solves per product, no stored operator) on a
+    48 x 40 room: a product and a 2-step flow against the oracle and against
+    the stored dense operator."""
+    banner("heat per-product solves vs stored operator")
+    wl = _room((48, 40))
+    g_en, o_en = energies(wl)
+    dense = _op(wl)
+    solve = jk.HeatOperator(wl.shape, wl.gamma, wl.heat_L, mask=_mask_dev(wl.mask), per_product=True)
+    H = O.HeatKernel(wl.mask, wl.gamma, wl.heat_L)
+    rng = np.random.default_rng(8)
+    x = np.where(wl.mask, rng.uniform(size=wl.shape), 0.0)
+    ys = host64(solve.apply(dev(x)))
+    assert rel_l1(ys, H(f32(x).astype(np.float64))) <= TOL_OP
+    assert rel_l1(ys, host64(dense.apply(dev(x)))) <= TOL_OP
+    ps, sts = solve.flow(dev(wl.p0), g_en, wl.tau, 2, max_iters=30)
+    pd, _ = dense.flow(dev(wl.p0), g_en, wl.tau, 2, max_iters=30)
+    ref, rst = _oracle_flow(wl, o_en, 2, 30)
+    err = rel_l1(host64(ps), ref)
+    print(f"[gpu-test] heat per-product 48x40: rel-L1 {err:.2e} (vs stored operator "
+          f"{rel_l1(host64(ps), host64(pd)):.2e})", flush=True)
+    assert err <= TOL_FLOW
+    assert sts[-1]["marginal_l1"] == pytest.approx(rst[-1]["marginal_l1"], rel=0.05, abs=1e-6)
+
+
+@pytest.mark.timeout(600)
+def test_room_above_65536_cells():
+    """A 300 x 300 room (90 000 cells, beyond the stored operator's limit):
+    the per-product solves for a product and a 2-step x 30-iteration crowd
+    flow with the capacity active, against the oracle's sparse LU solves."""
+    banner("heat 300x300 room, per-product solves")
+    wl = _room((300, 300))
+    assert int(wl.mask.sum()) > 65536
+    op = _op(wl)
+    H = O.HeatKernel(wl.mask, wl.gamma, wl.heat_L)
+    rng = np.random.default_rng(12)
+    x = np.where(wl.mask, rng.uniform(size=wl.shape), 0.0)
+    erra = rel_l1(host64(op.apply(dev(x))), H(f32(x).astype(np.float64)))
+    g_en, o_en = energies(wl)
+    pT, stats = op.flow(dev(wl.p0), g_en, wl.tau, 2, max_iters=30)
+    ref, rst = _oracle_flow(wl, o_en, 2, 30)
+    err = rel_l1(host64(pT), ref)
+    print(f"[gpu-test] heat 300x300: operator rel-L1 {erra:.2e}, flow rel-L1 {err:.2e}, marginal "
+          f"{stats[-1]['marginal_l1']:.3e} vs {rst[-1]['marginal_l1']:.3e}", flush=True)
+    assert erra <= TOL_OP
+    assert err <= TOL_FLOW
+    assert (host64(pT) <= np.float32(wl.kappa_scalar) * (1 + 1e-6)).all()
+    assert not host64(pT)[~wl.mask].any()
