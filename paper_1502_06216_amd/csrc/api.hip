@@ -144,6 +144,8 @@ int part_cap_of(const Geo& g) {
         s.n = g.n[0];
         cap = std::max<int64_t>(cap, contract_slow_blocks(s));
     }
+    if (g.d == 3 && g.n[0] == 2)      // the attraction's two couplings on a batched 2D kernel
+        cap = std::max<int64_t>(cap, 2 * gibbs2d_blocks(g.n[1], g.n[2], 16));
     for (int k = 0; k < g.d; ++k) {   // log-domain passes
         int64_t outer = 1, inner = 1;
         for (int j = 0; j < k; ++j) outer *= g.n[j];
@@ -219,6 +221,9 @@ struct Plan {
     int W[3] = {0, 0, 0};        // float32 band half-widths of the factors
     bool fused2d = false;        // 2D applications use the fused band kernel
     int tile = 0;                // ... with output tiles of this edge (16 or 32)
+    bool batch2d = false;        // stacked (2, n0, n1) applications: the fused kernel on both fields
+    bool batch_pass = false;     // stacked (2, n0, n1) applications: per-field rotating passes, no pass over
+                                 // the identity axis
     bool resident = false;       // ... and a step may run in one resident launch
     bool plane3d = false;        // 3D applications run as a plane pass and a slow-axis pass
 
@@ -323,6 +328,14 @@ Pass slow_of(const Plan& P) {
 // intermediates; x must not alias them.  *nblocks = blocks of the last pass.
 jko_status apply_xi(const Plan& P, const float* x, EpiArgs epi, int* nblocks) {
     set_vec(epi);
+    if (P.batch2d) {
+        Band2D b{P.g.n[1], P.g.n[2], P.W[1],   P.W[2],   P.K1[1], P.K1[2],
+                 x,        P.K1hi[1], P.K1lo[1], P.K1hi[2], P.K1lo[2], P.tile, P.g.n[0]};
+        int nb = 0;
+        HIP_TRY(launch_gibbs2d(b, P.prec, epi, &nb, P.st));
+        if (nblocks) *nblocks = nb;
+        return JKO_OK;
+    }
     if (P.fused2d) {
         Band2D b{P.g.n[0], P.g.n[1], P.W[0],   P.W[1],   P.K1[0], P.K1[1],
                  x,        P.K1hi[0], P.K1lo[0], P.K1hi[1], P.K1lo[1], P.tile};
@@ -338,10 +351,12 @@ jko_status apply_xi(const Plan& P, const float* x, EpiArgs epi, int* nblocks) {
         if (nblocks) *nblocks = nb;
         return JKO_OK;
     }
-    const PassList ps = passes_of(P.g);
+    PassList ps = passes_of(P.g);
+    if (P.batch_pass) ps.count = P.g.d - 1;   // axes d-1 .. 1; axis 0 stacks the fields
     const float* in = x;
     for (size_t i = 0; i < ps.size(); ++i) {
         Pass pass = make_pass(ps[i]);
+        if (P.batch_pass) pass.B = P.g.n[0];
         pass.K1 = P.K1[ps[i].axis];
         pass.K1hi = P.K1hi[ps[i].axis];
         pass.K1lo = P.K1lo[ps[i].axis];
@@ -922,6 +937,20 @@ jko_status attraction_flow(const Geo& g, const jko_energy* en, const jko_params*
     HIP_TRY(launch_build_factor(const_cast<float*>(P.K1[0]), const_cast<uint16_t*>(P.K1hi[0]),
                                 const_cast<uint16_t*>(P.K1lo[0]), 2, 1e-30, P.st));
     P.ident[0] = true;
+    // 2D grids: both couplings in one launch of the fused 2D kernel per
+    // application (axis 0 of the stacked field is the identity)
+    if (g.d == 2)
+        for (int tt : {16, 32})
+            if (gibbs2d_fits(g.n[0], g.n[1], P.W[1], P.W[2], P.prec, tt) &&
+                gibbs2d_blocks(g.n[0], g.n[1], tt) <= kFusedMaxBlocks) {
+                P.tile = tt;
+                P.batch2d = true;
+                break;
+            }
+    // bands too wide for the fused kernel: each field rotates through its own
+    // two passes (rows of a field a multiple of 4), so no pass runs over the
+    // identity axis
+    if (g.d == 2 && !P.batch2d && g.n[0] % 4 == 0 && g.n[1] % 4 == 0) P.batch_pass = true;
     // capacity of the initial density, and a target of the same mass
     double h[3], hr[3];
     HIP_TRY(launch_input_check(p0, en->kappa, en->kappa_scalar, g.N, 1, P.part.err, 3 * 256, P.hostout, P.st));

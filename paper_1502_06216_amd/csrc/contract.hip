@@ -47,6 +47,15 @@ __device__ __forceinline__ int xcd_logical_block() {
     return (bid % 8) * (nb / 8) + bid / 8;
 }
 
+// Output offset of row r, position i of a rotating pass: the (R, n) input
+// becomes (n, R), or, with stacked fields of Rb rows, each field's (Rb, n)
+// block becomes its own (n, Rb) block.  Runs of 4 rows never straddle two
+// fields (Rb is a multiple of 4).
+__device__ __forceinline__ int out_index(int i, int r, int n, int Rb) {
+    const int f = r / Rb;
+    return f * n * Rb + i * Rb + (r - f * Rb);
+}
+
 // BK: k per chunk.  STAGES = 2: double-buffered chunks; STAGES = 1: the whole
 // band of a tile fits in one chunk (loaded once, then multiplied).
 template <int TR, int TI, int WR, int WI, bool SPLIT, int BK, int STAGES, int EK>
@@ -74,6 +83,7 @@ contract_rot(Pass P, EpiArgs E) {
     // Every field has at most 2^30 cells, so 32-bit element offsets suffice.
     const int n = P.n;
     const int R = (int)P.R;
+    const int Rb = P.B > 1 ? R / P.B : R;
     const int IT = (n + TI - 1) / TI;
     const int logical = xcd_logical_block();
     const int r0 = (logical / IT) * TR;
@@ -258,7 +268,7 @@ contract_rot(Pass P, EpiArgs E) {
         const int il = unit / (TR / 4), rl = 4 * (unit % (TR / 4));
         const int i = i0 + il, r = r0 + rl;
         ecnt[u] = (unit < TI * TR / 4 && i < n) ? max(0, min(4, R - r)) : 0;
-        eidx[u] = i * R + r;
+        eidx[u] = out_index(i, r, n, Rb);
         ein[u] = epi_prefetch<EK>(E, eidx[u], ecnt[u]);
     }
 
@@ -396,6 +406,7 @@ contract_panel(Pass P, EpiArgs E) {
     if (E.ctl) done = E.ctl->done;
     const int n = P.n;
     const int R = (int)P.R;
+    const int Rb = P.B > 1 ? R / P.B : R;
     const int IT = n / TI;
     const int logical = xcd_logical_block();
     const int r0 = (logical / IT) * TR;
@@ -420,7 +431,7 @@ contract_panel(Pass P, EpiArgs E) {
         const int il = unit / (TR / 4), rl = 4 * (unit % (TR / 4));
         const int i = i0 + il, r = r0 + rl;
         ecnt[u] = (unit < TI * TR / 4 && i < n) ? max(0, min(4, R - r)) : 0;
-        eidx[u] = i * R + r;
+        eidx[u] = out_index(i, r, n, Rb);
         ein[u] = epi_prefetch<EK>(E, eidx[u], ecnt[u]);
     }
     // Staging copies panel by panel (this wave's X rows of the panel, then its
@@ -1112,6 +1123,7 @@ hipError_t launch_contract_slow(const Pass& pass, int32_t precision, const EpiAr
 
 hipError_t launch_contract(const Pass& pass, int32_t precision, const EpiArgs& epi, int* nblocks,
                            hipStream_t stream) {
+    if (pass.B > 1 && (pass.R % pass.B != 0 || (pass.R / pass.B) % 4 != 0)) return hipErrorInvalidValue;
     const int c = pick_cfg(pass);
     const int64_t nb = tiles_of(pass, c);
     if (nblocks) *nblocks = (int)nb;

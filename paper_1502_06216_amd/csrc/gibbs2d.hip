@@ -86,6 +86,7 @@ __device__ __forceinline__ int xcd_block() {
 // multiple of 4 (the extra entries meet exact zeros of the band).
 template <int TT>
 struct Tile {
+    int fld;                                          // field of a batch (0 without one)
     int i0, j0, ib0, jb0, LI, LJ, LIp, LJp;
     int eidx[Geom<TT>::kOut], ecnt[Geom<TT>::kOut];   // outputs this thread finishes (ecnt = 0: none)
 };
@@ -96,8 +97,11 @@ __device__ __forceinline__ Tile<TT> tile_of(const Band2D& B, int logical, int la
     constexpr int RND = SPLIT ? 32 : 16;
     Tile<TT> T;
     const int tiles_j = (B.n1 + TT - 1) / TT;
-    T.i0 = (logical / tiles_j) * TT;
-    T.j0 = (logical % tiles_j) * TT;
+    const int per = ((B.n0 + TT - 1) / TT) * tiles_j;   // tiles of one field
+    T.fld = logical / per;
+    const int t = logical - T.fld * per;
+    T.i0 = (t / tiles_j) * TT;
+    T.j0 = (t % tiles_j) * TT;
     T.ib0 = max(0, T.i0 - B.W0) & ~3;
     T.jb0 = max(0, T.j0 - B.W1) & ~3;
     T.LI = min(B.n0, T.i0 + TT + B.W0) - T.ib0;
@@ -123,7 +127,7 @@ __device__ __forceinline__ Tile<TT> tile_of(const Band2D& B, int logical, int la
             mine = true;
         }
         const int ei = T.i0 + il, ej = T.j0 + jl;
-        T.eidx[u] = ei * B.n1 + ej;
+        T.eidx[u] = (T.fld * B.n0 + ei) * B.n1 + ej;
         T.ecnt[u] = (mine && ei < B.n0 && ej < B.n1) ? 1 : 0;
     }
     return T;
@@ -470,6 +474,7 @@ gibbs2d_kernel(Band2D B, EpiArgs E) {
     if (E.ctl) done = E.ctl->done;
     const int lane = threadIdx.x & 63;
     const Tile<TT> T = tile_of<TT, SPLIT>(B, xcd_block(), lane);
+    B.X += (int64_t)T.fld * B.n0 * B.n1;   // this block's field of a batch
 
     // The finishing threads' epilogue inputs are fetched now, ahead of the
     // contraction.
@@ -921,7 +926,7 @@ bool gibbs2d_fits(int n0, int n1, int W0, int W1, int32_t precision, int tile) {
 
 hipError_t launch_gibbs2d(const Band2D& b, int32_t precision, const EpiArgs& epi, int* nblocks,
                           hipStream_t stream) {
-    const int64_t nb = gibbs2d_blocks(b.n0, b.n1, b.tile);
+    const int64_t nb = gibbs2d_blocks(b.n0, b.n1, b.tile) * std::max(1, b.batch);
     if (nblocks) *nblocks = (int)nb;
     const dim3 grid((unsigned)nb), block(kThr);
     const bool split = precision == JKO_SPLIT_BF16;

@@ -74,6 +74,8 @@ struct Pass {
     const uint16_t* K1hi;  // bfloat16 split of K1 (split precision only)
     const uint16_t* K1lo;
     const float* X;        // input field
+    int32_t B;             // 0 or 1: one field; B > 1: B stacked fields of R / B rows each,
+                           // rotated separately (R / B must be a multiple of 4)
 };
 
 enum class EpiKind : int {
@@ -151,6 +153,8 @@ struct Band2D {
     const uint16_t* K1hi;
     const uint16_t* K1lo;
     int tile;              // output tile edge: 16 or 32
+    int batch;             // per-application kernel only: this many n0 x n1 fields stacked in X and in
+                           // the epilogue's fields, one block per (field, tile); 0 or 1: one field
 };
 // The tile's halo (tile + 2 W, aligned) fits the kernel's LDS.
 bool gibbs2d_fits(int n0, int n1, int W0, int W1, int32_t precision, int tile);

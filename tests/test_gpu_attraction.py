@@ -27,8 +27,8 @@ def _gpu():
     jk.load()
 
 
-def _case(shape, seed=5):
-    wl = small_case(shape, "congestion", seed=seed)
+def _case(shape, seed=5, gamma=None):
+    wl = small_case(shape, "congestion", seed=seed, gamma=gamma)
     wl.kind = "attraction"
     wl.w = None
     d = len(shape)
@@ -64,6 +64,31 @@ def test_flow_matches_oracle(shape, precision):
     assert (host64(pT) <= f32(wl.kappa_field()) + 0).all()
     assert stats[-1]["marginal_l1"] == pytest.approx(rst["marginal_l1"], rel=0.05, abs=3e-6)
     assert stats[-1]["mass"] == pytest.approx(float(host64(pT).sum()), rel=1e-5)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+@pytest.mark.parametrize("shape", [(200, 160), (201, 161)])
+def test_wide_band_matches_oracle(shape, precision):
+    """gamma = 1e-3: bands of about a third of each axis, too wide for the
+    fused 2D kernel.  (200, 160) runs the two couplings through per-field
+    rotating passes (rows a multiple of 4), (201, 161) through the stacked
+    field's three passes."""
+    banner(f"attraction wide band {shape} {precision}")
+    wl = _case(shape, gamma=1e-3)
+    wl.tau = 1e-2
+    # the density moved by 3 rows, off the obstacles (scalings within float32)
+    kappa = f32(wl.kappa_field()).astype(np.float64)
+    r = np.roll(f32(wl.p0).astype(np.float64), -3, axis=0)
+    r[-3:, :] = 0.0
+    r[kappa <= 0] = 0.0
+    wl.target = r * (f32(wl.p0).astype(np.float64).sum() / r.sum())
+    g_en, _ = energies(wl)
+    pT, stats, _ = jk.flow(dev(wl.p0), g_en, wl.gamma, wl.tau, 2, max_iters=30, precision=precision)
+    ref, rst = _oracle(wl, 2, 30)
+    err = rel_l1(host64(pT), ref)
+    print(f"[gpu-test] attraction wide band {shape} {precision}: rel-L1 {err:.2e}", flush=True)
+    assert err <= TOL[precision]
+    assert stats[-1]["marginal_l1"] == pytest.approx(rst["marginal_l1"], rel=0.05, abs=3e-6)
 
 
 def test_attraction_to_its_own_density_is_one_blur():
