@@ -42,8 +42,8 @@ def _args():
     ap.add_argument("--no-extra", action="store_true", help="skip the 3D, split and adjoint extras")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--pmc-probe", choices=["crowd256", "crowd128c", "heat100"], default=None,
-                    help="profiling probe: 50 fixed iterations of one step of the workload, "
+    ap.add_argument("--pmc-probe", choices=["crowd256", "crowd128c", "porous512_scaled", "heat100"], default=None,
+                    help="profiling probe: one fixed-count step of the workload, "
                          "then a 64 MiB device copy of known size (counter calibration)")
     ap.add_argument("--heat-leg", action="store_true",
                     help="run only the heat-kernel leg (heat100) and print its JSON record")
@@ -121,7 +121,8 @@ CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1502_0621
 PROFILES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
 # counter summaries of the dominant launch per (workload, precision)
 TRAFFIC_PROFILES = {("crowd256", "fp32"): "resident2d_congestion_crowd256_traffic.md",
-                    ("crowd128c", "fp32"): "plane_pass_crowd128c_traffic.md"}
+                    ("crowd128c", "fp32"): "plane_pass_crowd128c_traffic.md",
+                    ("porous512_scaled", "fp32"): "resident2d_porous_porous512_traffic.md"}
 
 
 def kernel_source_hash(kernel_file):
@@ -147,13 +148,15 @@ def stored_traffic(profile_name, kernel_file, launch):
         return None
     txt = open(path).read()
     m_h = re.search(r"^source_sha256:\s*([0-9a-f]{64})", txt, re.M)
-    m_b = re.search(r"^traffic_bytes_per_dispatch:\s*([0-9.eE+]+)", txt, re.M)
-    m_l = re.search(r"^launch:\s*(.+?)\s*$", txt, re.M)
-    if not m_h or not m_b or not m_l or m_l.group(1) != launch:
+    if not m_h or m_h.group(1) != kernel_source_hash(kernel_file):
         return None
-    if m_h.group(1) != kernel_source_hash(kernel_file):
-        return None
-    return float(m_b.group(1))
+    # one "launch:" line per measured launch, each followed by its figures
+    for m in re.finditer(r"^launch:\s*(.+?)\s*$", txt, re.M):
+        if m.group(1) != launch:
+            continue
+        m_b = re.compile(r"^traffic_bytes_per_dispatch:\s*([0-9.eE+]+)", re.M).search(txt, m.end())
+        return float(m_b.group(1)) if m_b else None
+    return None
 
 
 def _field_bytes(wl):
@@ -602,7 +605,8 @@ def main():
             extra[f"porous512_scaled_{prec}"] = {"iters_per_s": round(it5 / el5, 2),
                                                  "jko_steps_per_s": round(3 / el5, 3),
                                                  "iters_per_step": [s["iters"] for s in st5],
-                                                 "roofline": roofline(wl5, prec, q5)}
+                                                 "roofline": roofline(wl5, prec, q5,
+                                                                      TRAFFIC_PROFILES.get(("porous512_scaled", prec)))}
         # heat-kernel Gibbs operator (L = 10 implicit steps) on a 100x100 room with obstacles
         extra["heat100_fp32"] = heat_bench(make_workload("heat100"))
         # beyond the stored operator: a 300 x 300 room by per-product solves

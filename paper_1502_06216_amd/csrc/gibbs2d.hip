@@ -65,13 +65,18 @@ struct Smem {
     static constexpr int H = Geom<TT>::kHalo;
     static constexpr int S = H + 4;    // padded LDS row (floats)
     static constexpr int S2 = H + 8;   // padded LDS row of a bfloat16 band (16-byte aligned)
-    float Xs[H * S];                   // [ib][jb]
-    float Kj[SPLIT ? 1 : TT * S];      // [j][jb]  = K1_1[j0+j][jb0+jb]
-    float Ki[SPLIT ? 1 : TT * S];      // [i][ib]  = K1_0[i0+i][ib0+ib]
-    uint16_t Kjh[SPLIT ? TT * S2 : 1], Kjl[SPLIT ? TT * S2 : 1];   // split: bfloat16 hi / lo of the bands
-    uint16_t Kih[SPLIT ? TT * S2 : 1], Kil[SPLIT ? TT * S2 : 1];
-    float Zown[Geom<TT>::kAliasZ ? 1 : TT * S];   // [j][ib]
-    float red[8 * 4 * kRS];            // [wave][element][lane] partial sums of the second contraction
+    // every array starts on a 16-byte boundary (the unused one-element arrays
+    // of the other precision would otherwise shift the rest by 8 bytes and
+    // split the 16-byte LDS accesses)
+    alignas(16) float Xs[H * S];                   // [ib][jb]
+    alignas(16) float Kj[SPLIT ? 1 : TT * S];      // [j][jb]  = K1_1[j0+j][jb0+jb]
+    alignas(16) float Ki[SPLIT ? 1 : TT * S];      // [i][ib]  = K1_0[i0+i][ib0+ib]
+    alignas(16) uint16_t Kjh[SPLIT ? TT * S2 : 1];   // split: bfloat16 hi / lo of the bands
+    alignas(16) uint16_t Kjl[SPLIT ? TT * S2 : 1];
+    alignas(16) uint16_t Kih[SPLIT ? TT * S2 : 1];
+    alignas(16) uint16_t Kil[SPLIT ? TT * S2 : 1];
+    alignas(16) float Zown[Geom<TT>::kAliasZ ? 1 : TT * S];   // [j][ib]
+    alignas(16) float red[8 * 4 * kRS];            // [wave][element][lane] partial sums of the second contraction
     double shd[8];
     __device__ float* Z() { return Geom<TT>::kAliasZ ? Xs : Zown; }
 };
