@@ -428,7 +428,19 @@ struct Readback {
     hipEvent_t ev = nullptr;
     int device = -1;
 };
-thread_local Readback g_rb;              // pinned
+// The pinned one releases its buffer and event when its thread ends; for the
+// main thread that is at exit, before the HIP runtime's own teardown (the
+// destructors of thread-local objects run before those of static ones).
+struct PinnedReadback : Readback {
+    PinnedReadback() = default;
+    PinnedReadback(const PinnedReadback&) = delete;
+    PinnedReadback& operator=(const PinnedReadback&) = delete;
+    ~PinnedReadback() {
+        if (ev) (void)hipEventDestroy(ev);
+        if (host) (void)hipHostFree(host);
+    }
+};
+thread_local PinnedReadback g_rb;        // pinned
 thread_local Ctl g_pageable[4];
 thread_local Readback g_rb_pageable{g_pageable, nullptr, -1};
 thread_local Readback* g_cur = &g_rb;    // the one the current call uses
@@ -852,6 +864,17 @@ jko_status run_attraction(const Plan& P, const jko_params* pr, const jko_energy*
     es.part = P.part;
     es.ctl = P.ctl;
     const double alpha = 1.0 / (1.0 + pr->tau);
+    // per-field rotating passes: the last pass of s = xi b finishes the
+    // proximal step itself (it pairs both couplings' rows of its cells)
+    EpiArgs ex{};
+    ex.kind = EpiKind::ATTR_PROX;
+    ex.a = a;
+    ex.p_out = p_out;
+    ex.prox.kappa = en->kappa;
+    ex.prox.kappa_s = en->kappa_scalar;
+    ex.alpha = (float)alpha;
+    ex.part = P.part;
+    ex.ctl = P.ctl;
     bool logd = logmode;   // the domain of the next application (as in run_step)
     bool pending = false, stopped = false;
     int nb = 0;
@@ -874,8 +897,12 @@ jko_status run_attraction(const Plan& P, const jko_params* pr, const jko_energy*
             if ((s = read_ctl(P, &c))) return s;
             if (c.done) break;
         }
-        if ((s = apply_xi_in(logd, P, b, es, &nb))) return s;
-        HIP_TRY(launch_attraction_prox(sv, a, p_out, en->kappa, en->kappa_scalar, alpha, N, P.ctl, P.st));
+        if (!logd && P.batch_pass) {
+            if ((s = apply_xi(P, b, ex, &nb))) return s;
+        } else {
+            if ((s = apply_xi_in(logd, P, b, es, &nb))) return s;
+            HIP_TRY(launch_attraction_prox(sv, a, p_out, en->kappa, en->kappa_scalar, alpha, N, P.ctl, P.st));
+        }
         if (eb.check && absorb > 0.0 && !logd) {   // a switch decided at this iteration's check takes effect now
             HIP_TRY(launch_absorb(P.ctl, a, b, 2 * N, P.st));
             HIP_TRY(launch_ctl_commit(P.ctl, P.st));

@@ -80,13 +80,19 @@ contract_rot(Pass P, EpiArgs E) {
     int done = 0;
     if (E.ctl) done = E.ctl->done;
 
+    // EK_ATTR pairs the two stacked fields (B = 2): rows [0, TH) of the tile
+    // are rows r0 .. r0 + TH of field 0, rows [TH, TR) the same rows of field
+    // 1, so that the epilogue holds both couplings' values of its cells.
+    constexpr bool PAIR = EK == EK_ATTR;
+    constexpr int TH = TR / 2;
+
     // Every field has at most 2^30 cells, so 32-bit element offsets suffice.
     const int n = P.n;
     const int R = (int)P.R;
     const int Rb = P.B > 1 ? R / P.B : R;
     const int IT = (n + TI - 1) / TI;
     const int logical = xcd_logical_block();
-    const int r0 = (logical / IT) * TR;
+    const int r0 = (logical / IT) * (PAIR ? TH : TR);
     const int i0 = (logical % IT) * TI;
     // band of the output tile, start aligned down to 4 (the extra columns meet exact zeros)
     const int kb0 = max(0, i0 - P.W) & ~3;
@@ -114,8 +120,8 @@ contract_rot(Pass P, EpiArgs E) {
             f4 v = f4{0.f, 0.f, 0.f, 0.f};
             if (unit < TR * BK / 4) {
                 const int d = unit / (BK / 4), k = kc + 4 * (unit % (BK / 4));
-                const int row = r0 + d;
-                if (row < R) {
+                const int row = PAIR ? (d < TH ? r0 + d : Rb + r0 + d - TH) : r0 + d;
+                if (PAIR ? r0 + (d < TH ? d : d - TH) < Rb : row < R) {
                     const float* src = P.X + (row * n + k);
                     if (vec && k + 3 < kb1) v = *reinterpret_cast<const f4*>(src);
                     else
@@ -262,14 +268,27 @@ contract_rot(Pass P, EpiArgs E) {
     static_assert(TI * TS * 4 <= (SPLIT ? NB * 2 : NF * 4), "staged tile must fit in the staging LDS");
     EpiIn ein[UE];
     int eidx[UE], ecnt[UE];
+    f4 kap[UE];   // EK_ATTR: the capacity of the unit's cells
 #pragma unroll
     for (int u = 0; u < UE; ++u) {
         const int unit = tid + u * kThreads;
         const int il = unit / (TR / 4), rl = 4 * (unit % (TR / 4));
         const int i = i0 + il, r = r0 + rl;
-        ecnt[u] = (unit < TI * TR / 4 && i < n) ? max(0, min(4, R - r)) : 0;
-        eidx[u] = out_index(i, r, n, Rb);
-        ein[u] = epi_prefetch<EK>(E, eidx[u], ecnt[u]);
+        if (PAIR) {
+            // units of the field-0 half finish both fields' cells
+            ecnt[u] = (unit < TI * TR / 4 && rl < TH && i < n) ? max(0, min(4, Rb - r)) : 0;
+            eidx[u] = i * Rb + r;
+            kap[u] = f4{E.prox.kappa_s, E.prox.kappa_s, E.prox.kappa_s, E.prox.kappa_s};
+            if (E.prox.kappa && ecnt[u] > 0) {
+                if (ecnt[u] == 4 && E.vec_ok) kap[u] = *reinterpret_cast<const f4*>(E.prox.kappa + eidx[u]);
+                else
+                    for (int e = 0; e < ecnt[u]; ++e) kap[u][e] = E.prox.kappa[eidx[u] + e];
+            }
+        } else {
+            ecnt[u] = (unit < TI * TR / 4 && i < n) ? max(0, min(4, R - r)) : 0;
+            eidx[u] = out_index(i, r, n, Rb);
+            ein[u] = epi_prefetch<EK>(E, eidx[u], ecnt[u]);
+        }
     }
 
     // The first chunks are in flight before the control flags are looked at.
@@ -318,6 +337,40 @@ contract_rot(Pass P, EpiArgs E) {
             *reinterpret_cast<f4*>(&tile[il * TS + rl]) = acc[a][b];
         }
     __syncthreads();
+    if (PAIR) {
+        // p = min(s_1^alpha s_2^(1 - alpha), kappa), a_m = p / s_m (0/0 = 0)
+        const float al = E.alpha;
+        const int64_t N = (int64_t)n * Rb;
+#pragma unroll
+        for (int u = 0; u < UE; ++u) {
+            const int unit = tid + u * kThreads;
+            const int il = unit / (TR / 4), rl = 4 * (unit % (TR / 4));
+            if (ecnt[u] == 0) continue;
+            const f4 s1 = *reinterpret_cast<const f4*>(&tile[il * TS + rl]);
+            const f4 s2 = *reinterpret_cast<const f4*>(&tile[il * TS + TH + rl]);
+            f4 pv, a1, a2;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float g = (s1[e] > 0.f && s2[e] > 0.f) ? expf(al * logf(s1[e]) + (1.f - al) * logf(s2[e])) : 0.f;
+                pv[e] = fminf(g, kap[u][e]);
+                a1[e] = pv[e] == 0.f ? 0.f : pv[e] / s1[e];
+                a2[e] = pv[e] == 0.f ? 0.f : pv[e] / s2[e];
+            }
+            const int o = eidx[u];
+            if (ecnt[u] == 4 && E.vec_ok) {
+                *reinterpret_cast<f4*>(E.p_out + o) = pv;
+                *reinterpret_cast<f4*>(E.a + o) = a1;
+                *reinterpret_cast<f4*>(E.a + N + o) = a2;
+            } else {
+                for (int e = 0; e < ecnt[u]; ++e) {
+                    E.p_out[o + e] = pv[e];
+                    E.a[o + e] = a1[e];
+                    E.a[N + o + e] = a2[e];
+                }
+            }
+        }
+        return;
+    }
     EpiAcc ea;
 #pragma unroll
     for (int u = 0; u < UE; ++u) {
@@ -1124,6 +1177,18 @@ hipError_t launch_contract_slow(const Pass& pass, int32_t precision, const EpiAr
 hipError_t launch_contract(const Pass& pass, int32_t precision, const EpiArgs& epi, int* nblocks,
                            hipStream_t stream) {
     if (pass.B > 1 && (pass.R % pass.B != 0 || (pass.R / pass.B) % 4 != 0)) return hipErrorInvalidValue;
+    if (epi.kind == EpiKind::ATTR_PROX) {
+        // the paired 32 x 32 rotating form only
+        if (pass.B != 2) return hipErrorInvalidValue;
+        const int64_t nb = tiles_of(pass, 0);
+        if (nblocks) *nblocks = (int)nb;
+        const dim3 grid((unsigned)nb), block(kThreads);
+        if (precision == JKO_SPLIT_BF16)
+            hipLaunchKernelGGL((contract_rot<32, 32, 2, 2, true, 32, 2, EK_ATTR>), grid, block, 0, stream, pass, epi);
+        else
+            hipLaunchKernelGGL((contract_rot<32, 32, 2, 2, false, 32, 2, EK_ATTR>), grid, block, 0, stream, pass, epi);
+        return hipGetLastError();
+    }
     const int c = pick_cfg(pass);
     const int64_t nb = tiles_of(pass, c);
     if (nblocks) *nblocks = (int)nb;

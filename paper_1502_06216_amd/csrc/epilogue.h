@@ -77,11 +77,15 @@ __device__ __forceinline__ float log_prox_porous(float ls, float lk, float m, in
 // energy, fixed at compile time so that each kernel carries only its own code.
 // EK_PROX + energy kind, EK_ADJ_B, EK_ADJ_PROX + energy kind
 // (the binary congestion prox, kind 4, has no adjoint epilogue)
-enum : int { EK_STORE = 0, EK_BUPDATE = 1, EK_MONITOR = 2, EK_PROX = 3, EK_ADJ_B = 9, EK_ADJ_PROX = 10 };
+// EK_ATTR: the attraction's proximal step over two stacked couplings (only
+// the rotating pass has it).
+enum : int { EK_STORE = 0, EK_BUPDATE = 1, EK_MONITOR = 2, EK_PROX = 3, EK_ADJ_B = 9, EK_ADJ_PROX = 10,
+             EK_ATTR = 32 };
 
 __host__ __device__ constexpr EpiKind ek_kind(int ek) {
     return ek == EK_STORE ? EpiKind::STORE : ek == EK_BUPDATE ? EpiKind::BUPDATE
          : ek == EK_MONITOR ? EpiKind::MONITOR : ek == EK_ADJ_B ? EpiKind::ADJ_B
+         : ek == EK_ATTR ? EpiKind::ATTR_PROX
          : ek >= EK_ADJ_PROX ? EpiKind::ADJ_PROX : EpiKind::PROX;
 }
 
@@ -92,6 +96,7 @@ inline int ek_of(const EpiArgs& e) {
         case EpiKind::MONITOR: return EK_MONITOR;
         case EpiKind::ADJ_B: return EK_ADJ_B;
         case EpiKind::ADJ_PROX: return EK_ADJ_PROX + e.prox.kind;
+        case EpiKind::ATTR_PROX: return EK_ATTR;
         default: return EK_PROX + e.prox.kind;
     }
 }

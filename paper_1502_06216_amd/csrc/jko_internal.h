@@ -85,6 +85,8 @@ enum class EpiKind : int {
     MONITOR = 3,    // t = v; err += |b t - q| (no write)
     ADJ_B = 4,      // bbar = v; y = tbar; acc (qbar) += bbar / t         (reverse of b = q / t)
     ADJ_PROX = 5,   // abar = v; y = sbar; acc (wbar) += ...               (reverse of p = prox(s), a = p / s)
+    ATTR_PROX = 6,  // the attraction's two couplings (a pass over B = 2 stacked fields):
+                    // p = min(s_1^alpha s_2^(1 - alpha), kappa), a_m = p / s_m, p_out = p
 };
 
 struct EpiArgs {
@@ -99,6 +101,7 @@ struct EpiArgs {
     const float* hin;      // ADJ_B: t of the iteration; ADJ_PROX: s of the iteration
     float* acc;            // ADJ_B: qbar (accumulated); ADJ_PROX: wbar (accumulated) or NULL
     float sigma;           // ADJ_PROX: tau / gamma
+    float alpha;           // ATTR_PROX: 1 / (1 + tau)
     int32_t check;         // BUPDATE: accumulate err with the old b; PROX: mass + max|log a|
     int32_t write_p;
     int32_t vec_ok;        // every field pointer above is 16-byte aligned (vector access)

@@ -101,12 +101,23 @@ __global__ void k_prepare(int kind, const float* w, const float* coef, float coe
 __global__ void k_attraction_prox(const float* __restrict__ s, float* __restrict__ a, float* __restrict__ p,
                                   const float* __restrict__ kappa, float kappa_s, float alpha, int64_t N,
                                   const Ctl* ctl) {
+    // the first cell's inputs are loaded before the control block is looked
+    // at, so that the two memory latencies overlap
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float s1 = 0.f, s2 = 0.f, k = kappa_s;
+    if (i < N) {
+        s1 = s[i];
+        s2 = s[N + i];
+        if (kappa) k = kappa[i];
+    }
     if (ctl && ctl->done) return;
     const bool logx = ctl && ctl->logmode;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const float s1 = s[i], s2 = s[N + i];
-        const float k = kappa ? kappa[i] : kappa_s;
+    for (; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+        if (i != (int64_t)blockIdx.x * blockDim.x + threadIdx.x) {
+            s1 = s[i];
+            s2 = s[N + i];
+            k = kappa ? kappa[i] : kappa_s;
+        }
         if (logx) {
             const float lp = fminf(alpha * s1 + (1.f - alpha) * s2, logf(k));
             p[i] = expf(lp);
