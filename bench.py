@@ -103,17 +103,27 @@ def band32_sum(n, W):
     return tot
 
 
-def fused2d_executed_flops(n0, n1, W0, W1):
-    """MFMA flops one launch of the 2D band kernel executes (16 x 16 tiles,
-    halo rounded up to 16)."""
+def fused_tile(n0, n1):
+    """Output tile edge the library picks for a 2D grid: 16 while the grid
+    has at most 256 such tiles, else 32."""
+    return 16 if ((n0 + 15) // 16) * ((n1 + 15) // 16) <= 256 else 32
+
+
+def fused2d_executed_flops(n0, n1, W0, W1, precision="fp32"):
+    """MFMA flops one application of the 2D band kernel executes (FP32
+    equivalent): per TT x TT tile, the first contraction over the halo rows
+    and columns and the second over the halo rows, the halo extents padded
+    to whole MFMA k-steps (16 for FP32, 32 for split-BF16)."""
+    TT = fused_tile(n0, n1)
+    rnd = 16 if precision == "fp32" else 32
     tot = 0
-    for i0 in range(0, n0, 16):
+    for i0 in range(0, n0, TT):
         ib0 = max(0, i0 - W0) & ~3
-        LIp = (min(n0, i0 + 16 + W0) - ib0 + 15) & ~15
-        for j0 in range(0, n1, 16):
+        LIp = (min(n0, i0 + TT + W0) - ib0 + rnd - 1) // rnd * rnd
+        for j0 in range(0, n1, TT):
             jb0 = max(0, j0 - W1) & ~3
-            LJp = (min(n1, j0 + 16 + W1) - jb0 + 15) & ~15
-            tot += 2 * LIp * 16 * LJp + 2 * 16 * 16 * LIp
+            LJp = (min(n1, j0 + TT + W1) - jb0 + rnd - 1) // rnd * rnd
+            tot += 2 * LIp * TT * LJp + 2 * TT * TT * LIp
     return tot
 
 
@@ -202,14 +212,14 @@ def roofline(wl, precision, q, traffic_profile=None, resident=True):
         names = [f"resident 2D kernel, {K} iterations"]
         kfile = "gibbs2d.hip"
         W = [band_halfwidth(n, wl.gamma) for n in wl.shape]
-        executed = [K * 2 * fused2d_executed_flops(wl.shape[0], wl.shape[1], W[0], W[1])]
+        executed = [K * 2 * fused2d_executed_flops(wl.shape[0], wl.shape[1], W[0], W[1], precision)]
     elif len(ms) == 2 and d == 2:
         flops = [2.0 * (wl.shape[0] + wl.shape[1]) * N] * 2
         nbytes = [12.0 * N, (8.0 + fb) * N]
         names = ["fused 2D application, b-update epilogue", "fused 2D application, prox epilogue"]
         kfile = "gibbs2d.hip"
         W = [band_halfwidth(n, wl.gamma) for n in wl.shape]
-        executed = [fused2d_executed_flops(wl.shape[0], wl.shape[1], W[0], W[1])] * 2
+        executed = [fused2d_executed_flops(wl.shape[0], wl.shape[1], W[0], W[1], precision)] * 2
     elif len(ms) == 4 and d == 3:
         # plane pass (axes 1 and 2, intermediate on chip), then the axis-0 pass with the epilogue
         fp, fs = 2.0 * (wl.shape[1] + wl.shape[2]) * N, 2.0 * wl.shape[0] * N

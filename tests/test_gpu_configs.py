@@ -1,6 +1,7 @@
 """The benchmarked workloads at the lengths the benchmark runs them, against
 the FP64 oracle at the same iteration counts (rel-L1 1e-5 FP32, 1e-4
-split-BF16): one full 300-iteration step of the 128^3 crowd, the 512^2
+split-BF16): one full 300-iteration step of the 128^3 crowd and its whole
+20-step flow (against a stored oracle flow), the 512^2
 porous-medium steps in tolerance mode (stop test every 10 iterations,
 tolerance 1e-6, cap 300), and the 256^2 crowd step at its 2000-iteration cap.
 
@@ -17,7 +18,7 @@ import oracle as O
 import paper_1502_06216_amd as jk
 from workloads import make_workload
 
-from _util import banner, dev, energies, f32, host64, rel_l1
+from _util import CELL_TOL, banner, cell_err, dev, energies, f32, host64, rel_l1
 
 pytestmark = pytest.mark.gpu
 
@@ -57,11 +58,49 @@ def test_crowd128c_full_step(precision):
     g_en, o_en = energies(wl)
     p, st = jk.step(dev(wl.p0), g_en, wl.gamma, wl.tau, max_iters=wl.max_iters, precision=precision)
     ref, ost = _oracle_step("crowd128c", wl, o_en, f32(wl.p0).astype(np.float64), wl.max_iters)
-    err = rel_l1(host64(p), ref)
-    print(f"[gpu-test] crowd128c 300 it {precision}: rel-L1 vs FP64 oracle {err:.3e}, marginal "
+    err, ce = rel_l1(host64(p), ref), cell_err(host64(p), ref)
+    print(f"[gpu-test] crowd128c 300 it {precision}: rel-L1 vs FP64 oracle {err:.3e} (per cell {ce:.2e}), marginal "
           f"{st['marginal_l1']:.4e} (oracle {ost['marginal_l1']:.4e})", flush=True)
-    assert err <= TOL[precision]
+    assert err <= TOL[precision] and ce <= CELL_TOL[precision]
     assert st["marginal_l1"] == pytest.approx(ost["marginal_l1"], rel=1e-3)
+
+
+def _c5_module():
+    import importlib.util
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "make_c5_reference.py")
+    spec = importlib.util.spec_from_file_location("make_c5_reference", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+def test_crowd128c_flow_at_its_configuration(precision):
+    """The 128^3 crowd flow as its precision configuration states it: 20 JKO
+    steps x 300 iterations, absorption when max|log a| exceeds 50 (checked
+    every 10 iterations; it never does here), against the stored FP64 oracle
+    flow (tests/golden/c5_reference.npz): the final density's rel-L1 and
+    every step's mass."""
+    banner(f"crowd128c 20 steps x 300 iterations {precision}")
+    mod = _c5_module()
+    wl, p0, o_en = mod.inputs()
+    with np.load(mod.OUT, allow_pickle=False) as z:
+        G = {k: z[k] for k in z.files}
+    assert mod.digest(wl, p0, o_en) == str(G["c5_digest"]), "workload changed since the golden file"
+    g_en, _ = energies(wl)
+    pT, stats, _ = jk.flow(dev(wl.p0), g_en, wl.gamma, wl.tau, mod.N_STEPS, max_iters=mod.ITERS,
+                           precision=precision, absorb_threshold=50.0, absorb_on_a=True, check_every=10)
+    err, ce = rel_l1(host64(pT), G["c5_pT"].astype(np.float64)), cell_err(host64(pT), G["c5_pT"])
+    masses = np.array([s["mass"] for s in stats])
+    print(f"[gpu-test] crowd128c 20x300 {precision}: final rel-L1 vs FP64 oracle {err:.3e} (per cell {ce:.2e}), "
+          f"absorptions "
+          f"{sum(s['absorptions'] for s in stats)}, max|log a| {max(s['max_abs_log_a'] for s in stats):.2f}",
+          flush=True)
+    assert err <= TOL[precision] and ce <= CELL_TOL[precision]
+    assert np.allclose(masses, G["c5_mass"], rtol=1e-5)
+    assert all(s["absorptions"] == 0 for s in stats)
 
 
 @pytest.mark.timeout(600)
@@ -84,10 +123,10 @@ def test_porous512_steps_in_tolerance_mode(name, precision):
         q, ost = _oracle_step(name, wl, o_en, q, st["iters"])
         # the oracle's violation at the device's stopping count is at the tolerance too
         assert ost["marginal_l1"] <= 2.0 * wl.tol
-    err = rel_l1(host64(pT), q)
+    err, ce = rel_l1(host64(pT), q), cell_err(host64(pT), q)
     print(f"[gpu-test] {name} {precision}: iterations {[s['iters'] for s in stats]}, rel-L1 vs FP64 oracle "
-          f"{err:.3e}", flush=True)
-    assert err <= TOL[precision]
+          f"{err:.3e} (per cell {ce:.2e})", flush=True)
+    assert err <= TOL[precision] and ce <= CELL_TOL[precision]
 
 
 @pytest.mark.timeout(600)
@@ -102,8 +141,8 @@ def test_crowd256_step_at_its_cap(precision):
                     check_every=wl.check_every, precision=precision)
     assert st["stop"] == "cap" and st["iters"] == wl.max_iters
     ref, ost = _oracle_step("crowd256", wl, o_en, f32(wl.p0).astype(np.float64), wl.max_iters)
-    err = rel_l1(host64(p), ref)
-    print(f"[gpu-test] crowd256 2000 it {precision}: rel-L1 vs FP64 oracle {err:.3e}, marginal "
+    err, ce = rel_l1(host64(p), ref), cell_err(host64(p), ref)
+    print(f"[gpu-test] crowd256 2000 it {precision}: rel-L1 vs FP64 oracle {err:.3e} (per cell {ce:.2e}), marginal "
           f"{st['marginal_l1']:.4e} (oracle {ost['marginal_l1']:.4e})", flush=True)
-    assert err <= TOL[precision]
+    assert err <= TOL[precision] and ce <= CELL_TOL[precision]
     assert st["marginal_l1"] == pytest.approx(ost["marginal_l1"], rel=1e-2)

@@ -1,7 +1,10 @@
 """HIP path vs the FP64 oracle, element by element, through the C ABI.
 
 Tolerances (relative L1 on densities): 1e-5 for FP32 contractions, 1e-4 for
-split-BF16; Gibbs products alone: 1e-6 / 2e-5 (rel-L1).
+split-BF16; Gibbs products alone: 1e-6 / 2e-5 (rel-L1).  Whole flows also
+meet a per-cell bound (1e-4 / 2e-3 of each cell's value, cells under 1e-3
+of the largest measured against that floor), so that an error concentrated
+on a few cells (an obstacle's edge) cannot hide in the aggregate.
 """
 import math
 
@@ -13,7 +16,7 @@ import oracle as O
 import paper_1502_06216_amd as jk
 from workloads import make_workload, small_case, gaussian_bumps
 
-from _util import banner, dev, energies, f32, host64, rel_l1
+from _util import CELL_TOL, banner, cell_err, dev, energies, f32, host64, rel_l1
 
 pytestmark = pytest.mark.gpu
 
@@ -141,7 +144,11 @@ def test_crowd32_flow_matches_oracle(precision, projected):
     banner(f"crowd32 projected={projected} {precision}")
     wl = make_workload("crowd32", projected=projected)
     errs, stats, p, ref = _flow_parity(wl, precision, wl.n_steps, wl.max_iters)
+    ce = cell_err(p, ref)
+    print(f"[gpu-test] crowd32 projected={projected} {precision}: rel-L1 {max(errs):.2e}, per cell {ce:.2e}",
+          flush=True)
     assert max(errs) <= TOL[precision], errs
+    assert ce <= CELL_TOL[precision]
     assert (p <= np.float32(wl.kappa_scalar)).all()
 
 
@@ -151,7 +158,10 @@ def test_ragged_congestion_matches_oracle(shape, precision):
     banner(f"ragged congestion {shape} {precision}")
     wl = small_case(shape, "congestion", seed=2)
     errs, stats, p, ref = _flow_parity(wl, precision, 2, 60)
+    ce = cell_err(p, ref)
+    print(f"[gpu-test] ragged congestion {shape} {precision}: rel-L1 {max(errs):.2e}, per cell {ce:.2e}", flush=True)
     assert max(errs) <= TOL[precision], errs
+    assert ce <= CELL_TOL[precision]
     assert (p <= f32(wl.kappa_field()) + 0).all()
 
 
@@ -163,7 +173,10 @@ def test_other_energies_match_oracle(kind, precision):
     if kind == "porous":
         wl.density_scale = float(np.prod(wl.shape))   # Newton regime k s^{m-1} >> 1
     errs, stats, p, ref = _flow_parity(wl, precision, 2, 40)
+    ce = cell_err(p, ref)
+    print(f"[gpu-test] energy {kind} {precision}: rel-L1 {max(errs):.2e}, per cell {ce:.2e}", flush=True)
     assert max(errs) <= TOL[precision], errs
+    assert ce <= CELL_TOL[precision]
 
 
 def test_porous512_literal_and_scaled_one_step():
