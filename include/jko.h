@@ -305,8 +305,9 @@ jko_status jko_time_iteration(const jko_grid* grid, const jko_energy* energy, co
  * (or with per_product = 1) it applies xi~ the paper's way instead: each
  * product is L solves of (Id - (gamma/L) Delta_M) y = rhs on the grid, each a
  * Chebyshev iteration in FP64 (one five-point stencil sweep per iteration,
- * to 1e-13 of the right-hand side; linear in the grid's size), rounded to
- * float32; no operator is stored.  The flow uses the iteration and stop test
+ * eight iterations per launch on tiles with a halo of eight cells, to 1e-13
+ * of the right-hand side; linear in the grid's size), rounded to float32; no
+ * operator is stored.  The flow uses the iteration and stop test
  * of jko_step with xi replaced by xi~; float32 only, no log domain, no
  * backward.
  * ------------------------------------------------------------------------ */

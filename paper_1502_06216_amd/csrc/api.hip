@@ -1493,7 +1493,7 @@ HeatLayout heat_layout(int n0, int n1, bool solve) {
     H.hdr = take(sizeof(HeatHdr));
     H.A = take(solve ? 0 : (size_t)heat_operator_floats(H.N) * sizeof(float));
     H.part = take(solve ? 0 : (size_t)heat_partial_floats(H.N) * sizeof(float));
-    H.scratch = take((size_t)(solve ? 4 * H.N : heat_build_scratch(H.N)) * sizeof(double));
+    H.scratch = take((size_t)(solve ? 5 * H.N : heat_build_scratch(H.N)) * sizeof(double));
     H.cidx = take(H.N * sizeof(int32_t));
     H.gidx = take(H.N * sizeof(int32_t));
     H.a = take(H.ld * sizeof(float));
@@ -1580,8 +1580,9 @@ HeatSolve heat_solve_of(const HeatLayout& H, const jko_heat_domain* d, char* bas
     hs.gamma = gamma;
     hs.X = sc;
     hs.R = sc + H.N;
-    hs.D0 = sc + 2 * H.N;
-    hs.D1 = sc + 3 * H.N;
+    hs.R1 = sc + 2 * H.N;
+    hs.D0 = sc + 3 * H.N;
+    hs.D1 = sc + 4 * H.N;
     return hs;
 }
 

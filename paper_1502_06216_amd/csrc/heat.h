@@ -78,7 +78,8 @@ constexpr double kHeatSolveTol = 1e-13;
 // One product y = xi~ x by L solves on the grid (the paper's form of the
 // operator): x (free-cell vector of g) is scattered to the grid vector X,
 // solved in place, and each free row finished by the epilogue `ek` of g
-// (codes of launch_heat_gemv).  R, D0, D1: grid scratch (N doubles each).
+// (codes of launch_heat_gemv).  R, R1, D0, D1: grid scratch (N doubles
+// each; the residual and the direction alternate between their pairs).
 struct HeatSolve {
     const uint8_t* mask;     // NULL = no obstacle
     const int32_t* cidx;     // grid cell -> free index or -1
@@ -86,8 +87,15 @@ struct HeatSolve {
     double gamma;
     double* X;
     double* R;
+    double* R1;
     double* D0;
     double* D1;
+};
+
+// Coefficients of up to 8 consecutive Chebyshev iterations (one launch).
+struct HeatChebSteps {
+    double c1[8], c2[8];
+    int steps;
 };
 hipError_t launch_heat_solve(int ek, const HeatGemv& g, const HeatSolve& h, hipStream_t st);
 

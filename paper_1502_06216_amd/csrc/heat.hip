@@ -25,6 +25,8 @@
 // positive semi-definite), so each solve is a Chebyshev iteration
 // (Saad, Iterative Methods for Sparse Linear Systems, 2nd ed., Alg. 12.1)
 // with no inner products: one stencil sweep per iteration, in FP64.
+#include <algorithm>
+
 #include "heat.h"
 #include "epilogue.h"
 
@@ -96,6 +98,107 @@ __global__ void k_heat_cheb_step(double* __restrict__ X, double* __restrict__ R,
         const double r = R[e] - md;
         R[e] = r;
         Dn[e] = c1 * d + c2 * r;
+    }
+}
+
+// Several Chebyshev iterations per launch for one grid vector (the
+// per-product solves), blocked in time: a block owns a kHB x kHB tile,
+// stages R and D over the tile and a halo of kHS cells in LDS, and runs up
+// to kHS iterations there; each iteration reads D at the neighbours, so the
+// cells it can update shrink by one per iteration, and after kHS of them the
+// tile is still exact.  It then writes X, R and the new D of its tile (R and
+// D to the other buffers of a pair: other blocks still read the old ones as
+// their halos).  Per cell the arithmetic is k_heat_cheb_step's, in the same
+// order (absent neighbour terms add exact zeros).
+constexpr int kHB = 16;                  // tile edge
+constexpr int kHS = 8;                   // iterations per launch (halo width)
+constexpr int kHR = kHB + 2 * kHS;       // staged region edge
+constexpr int kHBThr = 256;
+static_assert(kHR * kHR % kHBThr == 0, "whole cells per thread");
+
+__global__ void __launch_bounds__(kHBThr)
+k_heat_cheb_block(double* __restrict__ X, const double* __restrict__ Rin, const double* __restrict__ Din,
+                  double* __restrict__ Rout, double* __restrict__ Dout, const uint8_t* __restrict__ mask, int n0,
+                  int n1, double nu0, double nu1, HeatChebSteps cf) {
+    constexpr int PER = kHR * kHR / kHBThr;
+    __shared__ double sR[kHR * kHR];
+    __shared__ double sD[2][kHR * kHR];
+    __shared__ uint8_t sM[kHR * kHR];   // 1 free cell, 0 obstacle or outside the grid
+    const int tiles_j = (n1 + kHB - 1) / kHB;
+    const int gi0 = (int)(blockIdx.x / tiles_j) * kHB - kHS;
+    const int gj0 = (int)(blockIdx.x % tiles_j) * kHB - kHS;
+    const int tid = threadIdx.x;
+    double xr[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int c = tid + q * kHBThr;
+        const int li = c / kHR, lj = c % kHR, gi = gi0 + li, gj = gj0 + lj;
+        const bool in = gi >= 0 && gi < n0 && gj >= 0 && gj < n1;
+        const int64_t g = (int64_t)gi * n1 + gj;
+        sR[c] = in ? Rin[g] : 0.0;
+        sD[0][c] = in ? Din[g] : 0.0;
+        sM[c] = (in && is_free(mask, g)) ? 1 : 0;
+        const bool own = li >= kHS && li < kHS + kHB && lj >= kHS && lj < kHS + kHB;
+        xr[q] = (in && own) ? X[g] : 0.0;
+    }
+    __syncthreads();
+    // Each cell's stencil once for the launch, branch-free: the weight of a
+    // neighbour is nu_k when both cells are free and 0 otherwise (an absent
+    // term adds an exact zero, so the sum is the same as skipping it; an
+    // obstacle's row is the identity).  Cells of the region's outer ring use
+    // themselves as neighbours: their values are never read by a cell that
+    // is still exact (the exact region shrinks by one cell per iteration).
+    int nb[PER][4];
+    double wt[PER][4];
+    double ownf[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int c = tid + q * kHBThr;
+        const int li = c / kHR, lj = c % kHR;
+        const bool ring = li == 0 || li == kHR - 1 || lj == 0 || lj == kHR - 1;
+        const bool f = sM[c] == 1 && !ring;
+        nb[q][0] = ring ? c : c - kHR;
+        nb[q][1] = ring ? c : c + kHR;
+        nb[q][2] = ring ? c : c - 1;
+        nb[q][3] = ring ? c : c + 1;
+        wt[q][0] = (f && sM[c - kHR] == 1) ? nu0 : 0.0;
+        wt[q][1] = (f && sM[c + kHR] == 1) ? nu0 : 0.0;
+        wt[q][2] = (f && sM[c - 1] == 1) ? nu1 : 0.0;
+        wt[q][3] = (f && sM[c + 1] == 1) ? nu1 : 0.0;
+        ownf[q] = (li >= kHS && li < kHS + kHB && lj >= kHS && lj < kHS + kHB) ? 1.0 : 0.0;
+    }
+    for (int st = 0; st < cf.steps; ++st) {
+        const double* D = sD[st & 1];
+        double* Dn = sD[(st + 1) & 1];
+        const double c1 = cf.c1[st], c2 = cf.c2[st];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int c = tid + q * kHBThr;
+            const double d = D[c];
+            const double du = D[nb[q][0]], dd = D[nb[q][1]], dl = D[nb[q][2]], dr = D[nb[q][3]];
+            double md = d;
+            md += wt[q][0] * (d - du);
+            md += wt[q][1] * (d - dd);
+            md += wt[q][2] * (d - dl);
+            md += wt[q][3] * (d - dr);
+            xr[q] += ownf[q] * d;
+            const double r = sR[c] - md;
+            sR[c] = r;
+            Dn[c] = c1 * d + c2 * r;
+        }
+        __syncthreads();
+    }
+    const double* Df = sD[cf.steps & 1];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int c = tid + q * kHBThr;
+        const int li = c / kHR, lj = c % kHR, gi = gi0 + li, gj = gj0 + lj;
+        const bool own = li >= kHS && li < kHS + kHB && lj >= kHS && lj < kHS + kHB;
+        if (!own || gi >= n0 || gj >= n1) continue;
+        const int64_t g = (int64_t)gi * n1 + gj;
+        X[g] = xr[q];
+        Rout[g] = sR[c];
+        Dout[g] = Df[c];
     }
 }
 
@@ -371,7 +474,8 @@ int chunk_log2(int64_t N) {
 }
 
 // L solves of M y = X in place on the grid vector X (obstacles stay zero),
-// each a Chebyshev iteration of K steps from the first guess X.
+// each a Chebyshev iteration of K steps from the first guess X, kHS steps per
+// launch (k_heat_cheb_block; R and D alternate between their two buffers).
 void heat_solves(const HeatSolve& h, int K, hipStream_t st) {
     const int64_t N = (int64_t)h.n0 * h.n1;
     const double nu0 = h.n0 > 1 ? h.gamma * (double)h.n0 * h.n0 / h.L : 0.0;
@@ -379,17 +483,27 @@ void heat_solves(const HeatSolve& h, int K, hipStream_t st) {
     const double beta = 1.0 + 4.0 * (nu0 + nu1);
     const double theta = 0.5 * (beta + 1.0), delta = 0.5 * (beta - 1.0);
     const int gb = grid_for(N);
+    const unsigned tiles = (unsigned)(((h.n0 + kHB - 1) / kHB) * ((h.n1 + kHB - 1) / kHB));
+    double* R[2] = {h.R, h.R1};
     double* D[2] = {h.D0, h.D1};
     for (int l = 0; l < h.L && K > 0; ++l) {
-        hipLaunchKernelGGL(k_heat_cheb_init, dim3(gb), dim3(256), 0, st, h.X, h.R, D[0], h.mask, N, 0, h.n0, h.n1,
+        hipLaunchKernelGGL(k_heat_cheb_init, dim3(gb), dim3(256), 0, st, h.X, R[0], D[0], h.mask, N, 0, h.n0, h.n1,
                            nu0, nu1, 1.0 / theta);
         const double sigma1 = theta / delta;
         double rho = 1.0 / sigma1;
-        for (int k = 0; k < K; ++k) {
-            const double rho_n = 1.0 / (2.0 * sigma1 - rho);
-            hipLaunchKernelGGL(k_heat_cheb_step, dim3(gb), dim3(256), 0, st, h.X, h.R, D[k & 1], D[(k + 1) & 1],
-                               h.mask, N, 0, h.n0, h.n1, nu0, nu1, rho_n * rho, 2.0 * rho_n / delta);
-            rho = rho_n;
+        int cur = 0;
+        for (int k = 0; k < K; k += kHS) {
+            HeatChebSteps cf{};
+            cf.steps = std::min(kHS, K - k);
+            for (int j = 0; j < cf.steps; ++j) {
+                const double rho_n = 1.0 / (2.0 * sigma1 - rho);
+                cf.c1[j] = rho_n * rho;
+                cf.c2[j] = 2.0 * rho_n / delta;
+                rho = rho_n;
+            }
+            hipLaunchKernelGGL(k_heat_cheb_block, dim3(tiles), dim3(kHBThr), 0, st, h.X, R[cur], D[cur], R[1 - cur],
+                               D[1 - cur], h.mask, h.n0, h.n1, nu0, nu1, cf);
+            cur = 1 - cur;
         }
     }
 }
