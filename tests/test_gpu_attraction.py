@@ -91,6 +91,44 @@ def test_wide_band_matches_oracle(shape, precision):
     assert stats[-1]["marginal_l1"] == pytest.approx(rst["marginal_l1"], rel=0.05, abs=3e-6)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+def test_wide_band_scalar_capacity(precision):
+    """The per-field rotating passes with a scalar capacity (the fused
+    proximal epilogue reads no capacity field), and without capacity."""
+    banner(f"attraction wide band, scalar capacity {precision}")
+    for kap in (1.5 / (200 * 160), float("inf")):
+        wl = _case((200, 160), gamma=1e-3)
+        wl.tau = 1e-2
+        wl.kappa = None
+        wl.kappa_scalar = kap
+        r = np.roll(f32(wl.p0).astype(np.float64), -3, axis=0)
+        r[-3:, :] = 0.0
+        wl.target = r * (f32(wl.p0).astype(np.float64).sum() / r.sum())
+        g_en, _ = energies(wl)
+        pT, stats, _ = jk.flow(dev(wl.p0), g_en, wl.gamma, wl.tau, 2, max_iters=30, precision=precision)
+        ref, _ = _oracle(wl, 2, 30)
+        err = rel_l1(host64(pT), ref)
+        print(f"[gpu-test] attraction wide band kappa={kap:.3g} {precision}: rel-L1 {err:.2e}", flush=True)
+        assert err <= TOL[precision]
+
+
+def test_wide_band_absorption_switch():
+    """A wide band (per-field rotating passes with the fused proximal step)
+    and a target beyond float32's reach: the step switches to the log domain
+    once and matches the oracle's exact log-sum-exp step."""
+    banner("attraction wide band absorption switch")
+    wl = _case((200, 160), gamma=1e-3)
+    g_en, _ = energies(wl)
+    p, st = jk.step(dev(wl.p0), g_en, wl.gamma, wl.tau, max_iters=30, check_every=1, absorb_threshold=20.0)
+    r = f32(wl.target).astype(np.float64)
+    kappa = f32(wl.kappa_field()).astype(np.float64)
+    ref, _ = O.attraction_step_log(f32(wl.p0).astype(np.float64), r, kappa, wl.gamma, wl.tau, 30)
+    err = rel_l1(host64(p), ref)
+    print(f"[gpu-test] attraction wide band switch: absorptions {st['absorptions']}, rel-L1 {err:.2e}", flush=True)
+    assert st["absorptions"] == 1
+    assert np.isfinite(host64(p)).all() and err <= TOL["fp32"]
+
+
 def test_attraction_to_its_own_density_is_one_blur():
     """r = q without capacity: every iteration returns the blur xi (q / xi^T 1)."""
     banner("attraction r = q")
