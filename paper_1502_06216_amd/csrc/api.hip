@@ -727,7 +727,7 @@ jko_status run_step(const Plan& P, const jko_params* pr, const ProxArgs& px, con
             if ((s = read_ctl(P, &c))) return s;
             if (c.exit_iter > 0 && !c.done) {
                 HIP_TRY(launch_absorb(P.ctl, a, b, P.g.N, P.st));
-                HIP_TRY(launch_ctl_commit(P.ctl, P.st));
+                HIP_TRY(launch_ctl_commit(P.ctl, c.exit_iter, P.st));
                 logd = true;
                 k0 = c.exit_iter + 1;
                 resident = false;
@@ -735,46 +735,84 @@ jko_status run_step(const Plan& P, const jko_params* pr, const ProxArgs& px, con
         }
     }
 
+    // Each check's control block is read back asynchronously after the
+    // iteration's proximal half-step (and, in the plain domain, the
+    // absorption commit), and looked at when the next check's kernels are
+    // queued, so the GPU does not idle on the read-back.  A stop makes every
+    // later kernel return at once.  A switch to the log domain makes the
+    // plain-domain kernels queued after it return at once too: when the host
+    // sees it, it resumes at the iteration after the switch in the log domain
+    // (the state is exactly the one the switch left).  Without an event
+    // (the allocation-free entry point) every check is read back at once.
+    const bool async_rb = rb().ev != nullptr;
     bool pending = false;   // a read-back of the control block is in flight
     bool stopped = false;
     int nb = 0;
-    for (int k = k0; k <= (resident ? 0 : K); ++k) {
-        eb.check = (checks && k > 1 && (k - 1) % ce == 0) ? 1 : 0;
-        eb.t_out = record_hist ? P.hist(2 * (int64_t)(k - 1)) : nullptr;
-        jko_status s = apply_xi_in(logd, P, a, eb, &nb);
-        if (s) return s;
-        if (eb.check) HIP_TRY(launch_ctl_check(P.ctl, P.part, nb, k, pr->tol_l1, 1, absorb, a_only, P.st));
-        if (eb.check && tolmode && rb().ev) {
-            // Look at the previous stop test while this interval is queued,
-            // then queue the read-back of this one.
-            if (pending) {
-                HIP_TRY(hipEventSynchronize(rb().ev));
-                if (rb().host->done) stopped = true;
+    int k = k0;
+    for (;;) {
+        for (; k <= (resident ? 0 : K); ++k) {
+            eb.check = (checks && k > 1 && (k - 1) % ce == 0) ? 1 : 0;
+            eb.t_out = record_hist ? P.hist(2 * (int64_t)(k - 1)) : nullptr;
+            jko_status s = apply_xi_in(logd, P, a, eb, &nb);
+            if (s) return s;
+            if (eb.check) {
+                HIP_TRY(launch_ctl_check(P.ctl, P.part, nb, k, pr->tol_l1, 1, absorb, a_only, logd ? 0 : 1, P.st));
+                if (pending) {
+                    HIP_TRY(hipEventSynchronize(rb().ev));
+                    pending = false;
+                    const Ctl h = *rb().host;
+                    if (h.done) {
+                        stopped = true;
+                        break;
+                    }
+                    if (h.logmode && !logd) {   // resume after the switch iteration
+                        logd = true;
+                        k = h.exit_iter;
+                        continue;
+                    }
+                }
             }
-            if (stopped) break;
-            HIP_TRY(hipMemcpyAsync(rb().host, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, P.st));
-            HIP_TRY(hipEventRecord(rb().ev, P.st));
-            pending = true;
-        } else if (eb.check && tolmode) {
-            // no event: read this check back before queuing more
-            Ctl c{};
-            if ((s = read_ctl(P, &c))) return s;
-            if (c.done) break;
+            const bool cand = (checks && k % ce == 0) || k == K;
+            ep.check = cand ? 1 : 0;
+            ep.write_p = cand ? 1 : 0;
+            ep.s_out = record_hist ? P.hist(2 * (int64_t)(k - 1) + 1) : nullptr;
+            s = apply_xi_in(logd, P, b, ep, &nb);
+            if (s) return s;
+            if (eb.check && absorb > 0.0 && !logd) {
+                // a switch decided at this iteration's check takes effect now
+                HIP_TRY(launch_absorb(P.ctl, a, b, P.g.N, P.st));
+                HIP_TRY(launch_ctl_commit(P.ctl, k, P.st));
+            }
+            if (eb.check) {
+                if (async_rb) {
+                    HIP_TRY(hipMemcpyAsync(rb().host, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, P.st));
+                    HIP_TRY(hipEventRecord(rb().ev, P.st));
+                    pending = true;
+                } else {
+                    Ctl c{};
+                    if ((s = read_ctl(P, &c))) return s;
+                    if (c.done) {
+                        stopped = true;
+                        break;
+                    }
+                    if (c.logmode) logd = true;
+                }
+            }
         }
-        const bool cand = (checks && k % ce == 0) || k == K;
-        ep.check = cand ? 1 : 0;
-        ep.write_p = cand ? 1 : 0;
-        ep.s_out = record_hist ? P.hist(2 * (int64_t)(k - 1) + 1) : nullptr;
-        s = apply_xi_in(logd, P, b, ep, &nb);
+        if (stopped || resident || logd || !(absorb > 0.0)) break;
+        // a switch after the last check that was looked at voided the
+        // iterations queued after it: resume there
+        HIP_TRY(hipStreamSynchronize(P.st));
+        pending = false;
+        Ctl c{};
+        jko_status s = read_ctl(P, &c);
         if (s) return s;
-        if (eb.check && absorb > 0.0 && !logd) {
-            // a switch decided at this iteration's check takes effect now
-            HIP_TRY(launch_absorb(P.ctl, a, b, P.g.N, P.st));
-            HIP_TRY(launch_ctl_commit(P.ctl, P.st));
-            Ctl c{};
-            if ((s = read_ctl(P, &c))) return s;
-            if (c.logmode) logd = true;
+        if (c.logmode && !logd && !c.done) {
+            logd = true;
+            k = c.exit_iter + 1;
+            continue;
         }
+        break;
     }
     Ctl c{};
     if (tolmode || want_stats) {
@@ -791,7 +829,7 @@ jko_status run_step(const Plan& P, const jko_params* pr, const ProxArgs& px, con
             em.ctl = P.ctl;
             s = apply_xi_in(logd, P, a, em, &nb);
             if (s) return s;
-            HIP_TRY(launch_ctl_check(P.ctl, P.part, nb, K + 1, -1.0, 1, 0.0, 0, P.st));
+            HIP_TRY(launch_ctl_check(P.ctl, P.part, nb, K + 1, -1.0, 1, 0.0, 0, 0, P.st));
             s = read_ctl(P, &c);
             if (s) return s;
             c.done = 0;
@@ -882,7 +920,7 @@ jko_status run_attraction(const Plan& P, const jko_params* pr, const jko_energy*
         eb.check = (checks && k > 1 && (k - 1) % ce == 0) ? 1 : 0;
         jko_status s = apply_xi_in(logd, P, a, eb, &nb);
         if (s) return s;
-        if (eb.check) HIP_TRY(launch_ctl_check(P.ctl, P.part, nb, k, pr->tol_l1, 0, absorb, 0, P.st));
+        if (eb.check) HIP_TRY(launch_ctl_check(P.ctl, P.part, nb, k, pr->tol_l1, 0, absorb, 0, 0, P.st));
         if (eb.check && tolmode && rb().ev) {
             if (pending) {
                 HIP_TRY(hipEventSynchronize(rb().ev));
@@ -905,7 +943,7 @@ jko_status run_attraction(const Plan& P, const jko_params* pr, const jko_energy*
         }
         if (eb.check && absorb > 0.0 && !logd) {   // a switch decided at this iteration's check takes effect now
             HIP_TRY(launch_absorb(P.ctl, a, b, 2 * N, P.st));
-            HIP_TRY(launch_ctl_commit(P.ctl, P.st));
+            HIP_TRY(launch_ctl_commit(P.ctl, k, P.st));
             Ctl c{};
             if ((s = read_ctl(P, &c))) return s;
             if (c.logmode) logd = true;
@@ -924,7 +962,7 @@ jko_status run_attraction(const Plan& P, const jko_params* pr, const jko_energy*
             em.part = P.part;
             em.ctl = P.ctl;
             if ((s = apply_xi_in(logd, P, a, em, &nb))) return s;
-            HIP_TRY(launch_ctl_check(P.ctl, P.part, nb, K + 1, -1.0, 0, 0.0, 0, P.st));
+            HIP_TRY(launch_ctl_check(P.ctl, P.part, nb, K + 1, -1.0, 0, 0.0, 0, 0, P.st));
             if ((s = read_ctl(P, &c))) return s;
             c.done = 0;
         }

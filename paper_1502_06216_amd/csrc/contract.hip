@@ -78,7 +78,7 @@ contract_rot(Pass P, EpiArgs E) {
     // The control flags are read here but acted on only after the first chunk's
     // loads are in flight, so their latencies overlap.
     int done = 0;
-    if (E.ctl) done = E.ctl->done;
+    if (E.ctl) done = E.ctl->done | E.ctl->logmode;
 
     // EK_ATTR pairs the two stacked fields (B = 2): rows [0, TH) of the tile
     // are rows r0 .. r0 + TH of field 0, rows [TH, TR) the same rows of field
@@ -456,7 +456,7 @@ contract_panel(Pass P, EpiArgs E) {
     __shared__ double shd[8];
 
     int done = 0;
-    if (E.ctl) done = E.ctl->done;
+    if (E.ctl) done = E.ctl->done | E.ctl->logmode;
     const int n = P.n;
     const int R = (int)P.R;
     const int Rb = P.B > 1 ? R / P.B : R;
@@ -741,7 +741,7 @@ plane_pass(Plane3D P) {
     extern __shared__ __attribute__((aligned(16))) float dyn[];
 
     int done = 0;
-    if (P.ctl) done = P.ctl->done;
+    if (P.ctl) done = P.ctl->done | P.ctl->logmode;
     const int n1 = P.n1, n2 = P.n2;
     const int chunks = n2 >> 5;
     const int logical = xcd_logical_block();
@@ -936,7 +936,7 @@ contract_slow(Pass P, EpiArgs E) {
     __shared__ double shd[8];
 
     int done = 0;
-    if (E.ctl) done = E.ctl->done;
+    if (E.ctl) done = E.ctl->done | E.ctl->logmode;
     const int n = P.n;
     const int R = (int)P.R;
     const int IT = n / TI;

@@ -476,7 +476,7 @@ gibbs2d_kernel(Band2D B, EpiArgs E) {
     // The control flags are read here but acted on only after the halo loads
     // are in flight, so their latencies overlap.
     int done = 0;
-    if (E.ctl) done = E.ctl->done;
+    if (E.ctl) done = E.ctl->done | E.ctl->logmode;
     const int lane = threadIdx.x & 63;
     const Tile<TT> T = tile_of<TT, SPLIT>(B, xcd_block(), lane);
     B.X += (int64_t)T.fld * B.n0 * B.n1;   // this block's field of a batch

@@ -107,7 +107,8 @@ struct EpiArgs {
     int32_t vec_ok;        // every field pointer above is 16-byte aligned (vector access)
     ProxArgs prox;
     Partials part;
-    const Ctl* ctl;        // kernels return early when ctl->done
+    const Ctl* ctl;        // kernels return early when ctl->done (the plain-domain
+                           // contractions also when ctl->logmode)
 };
 
 // Launch one contraction pass; returns the number of blocks (partials slots
@@ -241,13 +242,15 @@ hipError_t launch_prepare_energy(const jko_energy* en, double sigma, int64_t N, 
 hipError_t launch_ctl_reset(Ctl* ctl, int logmode, hipStream_t s);
 // Sum of the per-block err partials -> ctl->err; stop / non-finite decision;
 // switch to the log domain when max|log a| or max|log b| > absorb (absorb > 0;
-// a_only: max|log a| alone).
+// a_only: max|log a| alone).  plain: a check of plain-domain iterations, a
+// no-op once the switch has been committed.
 hipError_t launch_ctl_check(Ctl* ctl, Partials part, int nparts, int iter, double tol,
-                            int check_mass, double absorb, int a_only, hipStream_t s);
+                            int check_mass, double absorb, int a_only, int plain, hipStream_t s);
 // a <- log a, b <- log b when the last check asked for the switch.
 hipError_t launch_absorb(Ctl* ctl, float* a, float* b, int64_t N, hipStream_t s);
-// After launch_absorb: logmode <- 1 if the switch was pending; pending <- 0.
-hipError_t launch_ctl_commit(Ctl* ctl, hipStream_t s);
+// After launch_absorb: logmode <- 1 and exit_iter <- iter if the switch was
+// pending; pending <- 0.
+hipError_t launch_ctl_commit(Ctl* ctl, int iter, hipStream_t s);
 // FP64 sums of p_in, of kappa (or kappa_s * N) and non-finite / negative
 // detection of p_in; results to out[0..3] (device doubles).
 hipError_t launch_input_check(const float* p_in, const float* kappa, float kappa_s, int64_t N,

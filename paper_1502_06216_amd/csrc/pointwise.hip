@@ -165,9 +165,12 @@ __device__ double fixed_sum(const double* v, int n, double* sh) {
     return r;
 }
 
+// plain: queued as part of plain-domain iterations, which are void once a
+// switch to the log domain has been committed (their kernels returned early).
 __global__ void __launch_bounds__(64) k_ctl_check(Ctl* c, Partials part, int nparts, int iter,
-                                                  double tol, int check_mass, double absorb, int a_only) {
-    if (c->done) return;
+                                                  double tol, int check_mass, double absorb, int a_only,
+                                                  int plain) {
+    if (c->done || (plain && c->logmode)) return;
     ctl_update(c, part, nparts, iter, tol, check_mass, absorb, a_only);
 }
 
@@ -182,9 +185,12 @@ __global__ void k_absorb(const Ctl* c, float* __restrict__ a, float* __restrict_
     }
 }
 
-__global__ void k_ctl_commit(Ctl* c) {
+__global__ void k_ctl_commit(Ctl* c, int iter) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        if (c->absorb_pending && !c->done) c->logmode = 1;
+        if (c->absorb_pending && !c->done) {
+            c->logmode = 1;
+            c->exit_iter = iter;
+        }
         c->absorb_pending = 0;
     }
 }
@@ -315,9 +321,9 @@ hipError_t launch_ctl_reset(Ctl* ctl, int logmode, hipStream_t s) {
 }
 
 hipError_t launch_ctl_check(Ctl* ctl, Partials part, int nparts, int iter, double tol, int check_mass,
-                            double absorb, int a_only, hipStream_t s) {
+                            double absorb, int a_only, int plain, hipStream_t s) {
     hipLaunchKernelGGL(k_ctl_check, dim3(1), dim3(64), 0, s, ctl, part, nparts, iter, tol, check_mass, absorb,
-                       a_only);
+                       a_only, plain);
     return hipGetLastError();
 }
 
@@ -326,8 +332,8 @@ hipError_t launch_absorb(Ctl* ctl, float* a, float* b, int64_t N, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_ctl_commit(Ctl* ctl, hipStream_t s) {
-    hipLaunchKernelGGL(k_ctl_commit, dim3(1), dim3(64), 0, s, ctl);
+hipError_t launch_ctl_commit(Ctl* ctl, int iter, hipStream_t s) {
+    hipLaunchKernelGGL(k_ctl_commit, dim3(1), dim3(64), 0, s, ctl, iter);
     return hipGetLastError();
 }
 
