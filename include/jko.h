@@ -159,8 +159,11 @@ typedef struct {
                                 no band assumed; float32 arithmetic in both precisions);
                                 <= 0: log domain from the first iteration; +inf or NaN:
                                 never.  With a finite threshold the checks also run in
-                                fixed-count mode, and the call reads each check back
-                                until the switch (one host synchronisation per check). */
+                                fixed-count mode; their results are read back without
+                                stalling the queue (the plain-domain kernels queued after
+                                a switch return at once and the step resumes after the
+                                switch iteration in the log domain); the attraction
+                                reads each check back synchronously. */
 } jko_params;
 
 /* Execution flags of jko_params.flags.
