@@ -38,9 +38,14 @@
  *    kernel).  It keeps one small pinned host buffer and one
  *    event per process for its stop-test read-back.
  *  - All work is ordered on `stream` (a hipStream_t; NULL = default stream).
- *    A call returns before its kernels finish unless it must read a device
- *    result: a tolerance-mode step (it polls the stop test every
- *    check_every iterations) or a call with a non-NULL stats pointer.
+ *    jko_gibbs_apply, jko_heat_apply and jko_backward return before their
+ *    kernels finish.  The calls that run steps wait for a device result at
+ *    a few points: the check of the input density (mass, capacity,
+ *    finiteness) before the iteration is queued; the stop tests of a
+ *    tolerance-mode step (read back one check interval behind the queue);
+ *    the end of a step whose absorb_threshold is finite and positive (the
+ *    host must know which domain the step ended in); and a non-NULL host
+ *    stats pointer.
  *  - Arguments are validated before any launch; on error nothing is launched
  *    and a status < 0 is returned.  jko_last_error() describes the last
  *    failure of the calling thread.
@@ -219,13 +224,26 @@ jko_status jko_gibbs_apply(const jko_grid* grid, double gamma, int32_t precision
                            const float* x, float* y, void* workspace, size_t workspace_bytes,
                            void* stream);
 
+/* Doubles in the device statistics record of jko_step. */
+#define JKO_STATS_DEV_DOUBLES 8
+
 /* One JKO step p_out = Prox^{W_gamma}_{tau f}(p_in) (eq. def-jko-operator) by
  * the iteration of Listing 1.  p_in >= 0 (any mass); p_out may not alias
- * p_in.  stats (host, nullable) receives the step's statistics and makes the
- * call synchronous.  Returns JKO_ERR_INFEASIBLE before launching the
- * iteration when a congestion capacity cannot hold the mass of p_in. */
+ * p_in.  Returns JKO_ERR_INFEASIBLE before launching the iteration when a
+ * congestion capacity cannot hold the mass of p_in.
+ * stats (host, nullable) receives the step's statistics and makes the call
+ * wait for the step to finish.
+ * stats_dev (device, nullable, 8-byte aligned, JKO_STATS_DEV_DOUBLES doubles,
+ * aliasing neither p_in nor p_out) receives the same record, ordered on
+ * `stream` after p_out, without a read-back: the fields of jko_stats in their
+ * order (iters, absorptions, stop_reason, status, marginal_l1, mass,
+ * max_abs_log_a, max_abs_log_b), each as a double.  With stats NULL the call
+ * then does not wait for it, and a non-finite value met by the monitor
+ * appears only as status JKO_ERR_NONFINITE in the record, not as the return
+ * value.  Either pointer, when given, costs one more t = xi^T a on a step
+ * that ends at max_iters (the violation of the returned iterate). */
 jko_status jko_step(const jko_grid* grid, const jko_energy* energy, const jko_params* params,
-                    const float* p_in, float* p_out, jko_stats* stats,
+                    const float* p_in, float* p_out, jko_stats* stats, double* stats_dev,
                     void* workspace, size_t workspace_bytes, void* stream);
 
 /* n_steps JKO steps from p0 (eq. smooth-jko with fixed gamma, tau).

@@ -15,7 +15,7 @@ The compute path is libjko.so (hand-written HIP kernels behind a C ABI,
 """
 from ._native import (  # noqa: F401
     EnergySpec, HeatDomain, HeatOperator, JKOError, JKOFlowFn, backward, time_iteration, flow, gibbs_apply, load, step,
-    step_static, workspace_bytes,
+    step_static, workspace_bytes, stats_from_device, STATS_DEV_DOUBLES, ABI_VERSION,
     make_grid, make_params, Grid, EnergyC, Params, Stats, LIB_PATH,
     JKO_OK, JKO_ERR_INVALID, JKO_ERR_WORKSPACE, JKO_ERR_HIP, JKO_ERR_NONFINITE, JKO_ERR_INFEASIBLE,
     OP_GIBBS, OP_STEP, OP_FLOW, OP_BACKWARD,

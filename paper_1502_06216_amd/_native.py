@@ -65,6 +65,13 @@ class HeatDomain(ctypes.Structure):
                 ("per_product", ctypes.c_int32)]
 
 
+# Version of the C ABI this binding marshals for (jko_version()).
+ABI_VERSION = 2
+
+# Doubles in jko_step's device statistics record (JKO_STATS_DEV_DOUBLES).
+STATS_DEV_DOUBLES = 8
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("absorptions", ctypes.c_int32),
                 ("stop_reason", ctypes.c_int32), ("status", ctypes.c_int32),
@@ -95,7 +102,7 @@ def load(path: str = LIB_PATH):
     lib.jko_workspace_bytes.restype = sz
     lib.jko_gibbs_apply.argtypes = [G, f64, i32, vp, vp, vp, sz, vp]
     lib.jko_gibbs_apply.restype = i32
-    lib.jko_step.argtypes = [G, E, P, vp, vp, S, vp, sz, vp]
+    lib.jko_step.argtypes = [G, E, P, vp, vp, S, vp, vp, sz, vp]
     lib.jko_step.restype = i32
     lib.jko_step_static.argtypes = [G, E, P, vp, vp, S, vp]
     lib.jko_step_static.restype = i32
@@ -120,6 +127,9 @@ def load(path: str = LIB_PATH):
     lib.jko_last_error.restype = ctypes.c_char_p
     lib.jko_version.argtypes = []
     lib.jko_version.restype = i32
+    if lib.jko_version() != ABI_VERSION:
+        raise RuntimeError(f"{path} has ABI version {lib.jko_version()}, this binding expects {ABI_VERSION}: "
+                           "rebuild it with `python -m paper_1502_06216_amd.build`")
     _lib = lib
     return lib
 
@@ -238,16 +248,24 @@ def gibbs_apply(x: torch.Tensor, gamma: float, precision: str = "fp32",
 def step(p: torch.Tensor, energy: EnergySpec, gamma: float, tau: float, max_iters: int = 300,
          tol: float = 0.0, check_every: int = 10, precision: str = "fp32",
          absorb_threshold: float = math.inf, out: Optional[torch.Tensor] = None,
-         with_stats: bool = True, resident: bool = True, planes: bool = True, absorb_on_a: bool = False):
+         with_stats: bool = True, resident: bool = True, planes: bool = True, absorb_on_a: bool = False,
+         stats_dev: Optional[torch.Tensor] = None):
     """One JKO step p -> argmin_p' W_gamma(p', p) + tau f(p').  Returns
     (p_next, stats dict or None).  resident=False keeps one launch per Gibbs
     application where the resident 2D kernel would run the step; planes=False
     runs 3D applications as three axis passes instead of a plane pass and an
     axis-0 pass; absorb_on_a=True makes the absorption switch watch max|log a|
-    alone."""
+    alone.  stats_dev (a float64 tensor of STATS_DEV_DOUBLES elements on the
+    same device) receives the statistics on the device, ordered on the current
+    stream after p_next, with no read-back; stats_from_device() reads it."""
     lib = load()
     shape = tuple(p.shape)
     _field(p, shape, "p")
+    if stats_dev is not None and (not isinstance(stats_dev, torch.Tensor) or stats_dev.device != p.device
+                                  or stats_dev.dtype != torch.float64 or not stats_dev.is_contiguous()
+                                  or stats_dev.numel() < STATS_DEV_DOUBLES):
+        raise TypeError(f"stats_dev must be a contiguous float64 tensor of at least {STATS_DEV_DOUBLES} "
+                        f"elements on {p.device}")
     pout = torch.empty_like(p) if out is None else _field(out, shape, "out")
     g = make_grid(shape)
     prm = make_params(gamma, tau, max_iters, tol, check_every, precision, absorb_threshold, resident, planes,
@@ -258,8 +276,17 @@ def step(p: torch.Tensor, energy: EnergySpec, gamma: float, tau: float, max_iter
     ws = _workspace(nb, p.device)
     st = Stats()
     _check(lib.jko_step(ctypes.byref(g), ctypes.byref(e), ctypes.byref(prm), _ptr(p), _ptr(pout),
-                        ctypes.byref(st) if with_stats else None, _ptr(ws), ws.numel(), _stream(p.device)))
+                        ctypes.byref(st) if with_stats else None, _ptr(stats_dev), _ptr(ws), ws.numel(),
+                        _stream(p.device)))
     return pout, (st.as_dict() if with_stats else None)
+
+
+def stats_from_device(rec: torch.Tensor) -> dict:
+    """The statistics dict of a device record written by step(stats_dev=...)
+    (reads it back, after the work queued before on the current stream)."""
+    v = rec[:STATS_DEV_DOUBLES].tolist()
+    return dict(iters=int(v[0]), absorptions=int(v[1]), stop="tol" if int(v[2]) == 0 else "cap",
+                status=int(v[3]), marginal_l1=v[4], mass=v[5], max_abs_log_a=v[6], max_abs_log_b=v[7])
 
 
 def step_static(p: torch.Tensor, energy: EnergySpec, gamma: float, tau: float, max_iters: int = 300,

@@ -597,6 +597,33 @@ jko_status input_check(const Plan& P, const jko_energy* en, const float* p) {
     return JKO_OK;
 }
 
+// ------------------------------------------------------------ device stats
+
+// Writes a step's statistics, in the field order of jko_stats and all as
+// doubles, to `out` (device) from the control block the step left, so that a
+// caller can keep them on the device without a read-back.  `mass` (device,
+// nullable) replaces the control block's mass; `attr`: the attraction, which
+// does not monitor max|log a|.
+__global__ void k_stats_export(const Ctl* c, const double* mass, double* out, int32_t K, int32_t tolmode,
+                               int32_t attr) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    const bool bytol = tolmode && c->done && !c->nonfinite;
+    out[0] = bytol ? c->stop_iter : K;
+    out[1] = c->absorptions;
+    out[2] = bytol ? JKO_STOP_TOL : JKO_STOP_CAP;
+    out[3] = c->nonfinite ? JKO_ERR_NONFINITE : JKO_OK;
+    out[4] = c->err;
+    out[5] = mass ? mass[0] : c->mass;
+    out[6] = attr ? 0.0 : c->maxloga;
+    out[7] = c->maxlogb;
+}
+
+hipError_t launch_stats_export(const Ctl* c, const double* mass, double* out, int K, bool tolmode, bool attr,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(k_stats_export, dim3(1), dim3(64), 0, s, c, mass, out, K, tolmode ? 1 : 0, attr ? 1 : 0);
+    return hipGetLastError();
+}
+
 // ----------------------------------------------------------------- resident
 
 bool use_resident(const Plan& P, const jko_params* pr, const ProxArgs& px) {
@@ -671,10 +698,12 @@ struct StepOut {
 };
 
 // Runs the iteration of one step with q (device) -> p_out (device).  When
-// `t_hist`/`s_hist` are set, iteration k stores t_k and s_k into
+// `record_hist` is set, iteration k stores t_k and s_k into
 // P.hist(2(k-1)) and P.hist(2(k-1)+1) (adjoint recomputation, fixed count).
+// `st_out` (host) and `st_dev` (device, 8 doubles) receive the statistics;
+// only the host record makes the step wait for them.
 jko_status run_step(const Plan& P, const jko_params* pr, const ProxArgs& px, const float* q, float* p_out,
-                    bool want_stats, bool record_hist, jko_stats* st_out) {
+                    bool want_stats, bool record_hist, jko_stats* st_out, double* st_dev = nullptr) {
     const int K = pr->max_iters;
     const int ce = pr->check_every;
     const bool tolmode = pr->tol_l1 > 0.0;
@@ -814,27 +843,35 @@ jko_status run_step(const Plan& P, const jko_params* pr, const ProxArgs& px, con
         }
         break;
     }
+    // Cap reached: the violation of the returned iterate takes one more
+    // t = xi^T a (its kernels and check return at once on a stopped step).
+    auto monitor = [&]() -> jko_status {
+        EpiArgs em{};
+        em.kind = EpiKind::MONITOR;
+        em.q = q;
+        em.b = b;
+        em.part = P.part;
+        em.ctl = P.ctl;
+        jko_status s = apply_xi_in(logd, P, a, em, &nb);
+        if (s) return s;
+        HIP_TRY(launch_ctl_check(P.ctl, P.part, nb, K + 1, -1.0, 1, 0.0, 0, 0, P.st));
+        return JKO_OK;
+    };
     Ctl c{};
     if (tolmode || want_stats) {
         HIP_TRY(hipStreamSynchronize(P.st));
         jko_status s = read_ctl(P, &c);
         if (s) return s;
-        if (!c.done && want_stats) {
-            // Cap reached: violation of the returned iterate, one more t = xi^T a.
-            EpiArgs em{};
-            em.kind = EpiKind::MONITOR;
-            em.q = q;
-            em.b = b;
-            em.part = P.part;
-            em.ctl = P.ctl;
-            s = apply_xi_in(logd, P, a, em, &nb);
-            if (s) return s;
-            HIP_TRY(launch_ctl_check(P.ctl, P.part, nb, K + 1, -1.0, 1, 0.0, 0, 0, P.st));
-            s = read_ctl(P, &c);
-            if (s) return s;
+        if (!c.done && (want_stats || st_dev)) {
+            if ((s = monitor())) return s;
+            if ((s = read_ctl(P, &c))) return s;
             c.done = 0;
         }
+    } else if (st_dev) {
+        jko_status s = monitor();   // queued without a read-back
+        if (s) return s;
     }
+    if (st_dev) HIP_TRY(launch_stats_export(P.ctl, nullptr, st_dev, K, tolmode, false, P.st));
     if (st_out) {
         jko_stats& o = *st_out;
         const bool bytol = tolmode && c.done && !c.nonfinite;
@@ -870,7 +907,7 @@ jko_status mass_of(const Plan& P, const float* p, int64_t N, double* out) {
 // violation of both couplings' right marginals).  N cells per field; the
 // target is scaled by rscale to the mass of q (both couplings need one mass).
 jko_status run_attraction(const Plan& P, const jko_params* pr, const jko_energy* en, const float* q, float* p_out,
-                          int64_t N, double rscale, bool want_stats, jko_stats* st_out) {
+                          int64_t N, double rscale, bool want_stats, jko_stats* st_out, double* st_dev = nullptr) {
     // Absorption as in run_step: <= 0 runs the log domain from the start, +inf
     // (or NaN) never switches, otherwise the check that sees max|log b| above
     // the threshold switches a and b to logs after that iteration's proximal
@@ -949,23 +986,37 @@ jko_status run_attraction(const Plan& P, const jko_params* pr, const jko_energy*
             if (c.logmode) logd = true;
         }
     }
+    auto monitor = [&]() -> jko_status {
+        EpiArgs em{};
+        em.kind = EpiKind::MONITOR;
+        em.q = qs;
+        em.b = b;
+        em.part = P.part;
+        em.ctl = P.ctl;
+        jko_status s = apply_xi_in(logd, P, a, em, &nb);
+        if (s) return s;
+        HIP_TRY(launch_ctl_check(P.ctl, P.part, nb, K + 1, -1.0, 0, 0.0, 0, 0, P.st));
+        return JKO_OK;
+    };
     Ctl c{};
     if (tolmode || want_stats) {
         HIP_TRY(hipStreamSynchronize(P.st));
         jko_status s = read_ctl(P, &c);
         if (s) return s;
-        if (!c.done && want_stats) {
-            EpiArgs em{};
-            em.kind = EpiKind::MONITOR;
-            em.q = qs;
-            em.b = b;
-            em.part = P.part;
-            em.ctl = P.ctl;
-            if ((s = apply_xi_in(logd, P, a, em, &nb))) return s;
-            HIP_TRY(launch_ctl_check(P.ctl, P.part, nb, K + 1, -1.0, 0, 0.0, 0, 0, P.st));
+        if (!c.done && (want_stats || st_dev)) {
+            if ((s = monitor())) return s;
             if ((s = read_ctl(P, &c))) return s;
             c.done = 0;
         }
+    } else if (st_dev) {
+        jko_status s = monitor();   // queued without a read-back
+        if (s) return s;
+    }
+    if (st_dev) {
+        // the mass of the returned density (the control block holds the
+        // coupling sums), then the record
+        HIP_TRY(launch_input_check(p_out, nullptr, INFINITY, N, 0, P.part.err, 3 * 256, P.hostout, P.st));
+        HIP_TRY(launch_stats_export(P.ctl, P.hostout, st_dev, K, tolmode, true, P.st));
     }
     if (st_out) {
         double mass = 0.0;
@@ -988,8 +1039,8 @@ jko_status run_attraction(const Plan& P, const jko_params* pr, const jko_energy*
 
 // jko_step (n_steps = 1, no checkpoints) and jko_flow for the attraction.
 jko_status attraction_flow(const Geo& g, const jko_energy* en, const jko_params* pr, int n_steps, const float* p0,
-                           float* pT, float* checkpoints, jko_stats* stats, void* ws, size_t ws_bytes,
-                           hipStream_t st, bool flow) {
+                           float* pT, float* checkpoints, jko_stats* stats, double* stats_dev, void* ws,
+                           size_t ws_bytes, hipStream_t st, bool flow) {
     if (g.d > 2) return fail(JKO_ERR_INVALID, "attraction: 1D and 2D grids only");
     for (int k = 0; k < g.d; ++k)
         if (g.n[k] < 3) return fail(JKO_ERR_INVALID, "attraction: every axis needs at least 3 cells");
@@ -1036,7 +1087,8 @@ jko_status attraction_flow(const Geo& g, const jko_energy* en, const jko_params*
         if (checkpoints) HIP_TRY(launch_copy(checkpoints + (int64_t)t * g.N, q, g.N, P.st));
         float* out = (t == n_steps - 1) ? pT : P.F((t % 2 == 0) ? F_P0 : F_P1);
         if (t > 0 && (s = mass_of(P, q, g.N, &mq))) return s;
-        s = run_attraction(P, pr, en, q, out, g.N, mq / hr[0], stats != nullptr, stats ? &stats[t] : nullptr);
+        s = run_attraction(P, pr, en, q, out, g.N, mq / hr[0], stats != nullptr, stats ? &stats[t] : nullptr,
+                           t == n_steps - 1 ? stats_dev : nullptr);
         if (s == JKO_ERR_NONFINITE) {
             worst = s;
         } else if (s) {
@@ -1097,7 +1149,7 @@ jko_status common_checks(const jko_grid* grid, Geo* g) {
 
 extern "C" {
 
-int32_t jko_version(void) { return 1; }
+int32_t jko_version(void) { return 2; }
 
 const char* jko_last_error(void) { return g_err.c_str(); }
 
@@ -1148,7 +1200,7 @@ jko_status jko_gibbs_apply(const jko_grid* grid, double gamma, int32_t precision
 }
 
 jko_status jko_step(const jko_grid* grid, const jko_energy* energy, const jko_params* params, const float* p_in,
-                    float* p_out, jko_stats* stats, void* ws, size_t ws_bytes, void* stream) {
+                    float* p_out, jko_stats* stats, double* stats_dev, void* ws, size_t ws_bytes, void* stream) {
     g_err.clear();
     Geo g;
     jko_status s = common_checks(grid, &g);
@@ -1156,8 +1208,12 @@ jko_status jko_step(const jko_grid* grid, const jko_energy* energy, const jko_pa
     if ((s = check_params(params)) || (s = check_energy(energy))) return s;
     if (!p_in || !p_out) return fail(JKO_ERR_INVALID, "p_in and p_out must be non-NULL");
     if (p_in == p_out) return fail(JKO_ERR_INVALID, "p_in and p_out may not alias");
+    if (stats_dev && (reinterpret_cast<uintptr_t>(stats_dev) % alignof(double) != 0 ||
+                      static_cast<const void*>(stats_dev) == static_cast<const void*>(p_in) ||
+                      static_cast<const void*>(stats_dev) == static_cast<const void*>(p_out)))
+        return fail(JKO_ERR_INVALID, "stats_dev must be 8-byte aligned and may not alias p_in or p_out");
     if (energy->kind == JKO_F_ATTRACTION)
-        return attraction_flow(g, energy, params, 1, p_in, p_out, nullptr, stats, ws, ws_bytes,
+        return attraction_flow(g, energy, params, 1, p_in, p_out, nullptr, stats, stats_dev, ws, ws_bytes,
                                static_cast<hipStream_t>(stream), false);
     Plan P;
     s = carve(&P, g, OP_STEP, 0, ws, ws_bytes, params->precision, static_cast<hipStream_t>(stream));
@@ -1168,7 +1224,7 @@ jko_status jko_step(const jko_grid* grid, const jko_energy* energy, const jko_pa
     if ((s = prepare_energy(P, energy, sigma))) return s;
     if ((s = input_check(P, energy, p_in))) return s;
     const ProxArgs px = prox_args(P, energy, sigma);
-    return run_step(P, params, px, p_in, p_out, stats != nullptr, false, stats);
+    return run_step(P, params, px, p_in, p_out, stats != nullptr, false, stats, stats_dev);
 }
 
 jko_status jko_step_static(const jko_grid* grid, const jko_energy* energy, const jko_params* params,
@@ -1187,7 +1243,7 @@ jko_status jko_step_static(const jko_grid* grid, const jko_energy* energy, const
     void* ws = nullptr;
     if ((s = scratch_of(&ws))) return s;
     NoAllocScope scope;
-    return jko_step(grid, energy, params, p_in, p_out, stats, ws, kStaticWorkspaceBytes, stream);
+    return jko_step(grid, energy, params, p_in, p_out, stats, nullptr, ws, kStaticWorkspaceBytes, stream);
 }
 
 jko_status jko_flow(const jko_grid* grid, const jko_energy* energy, const jko_params* params, int32_t n_steps,
@@ -1202,7 +1258,7 @@ jko_status jko_flow(const jko_grid* grid, const jko_energy* energy, const jko_pa
     if (!p0 || !pT) return fail(JKO_ERR_INVALID, "p0 and pT must be non-NULL");
     if (p0 == pT) return fail(JKO_ERR_INVALID, "p0 and pT may not alias");
     if (energy->kind == JKO_F_ATTRACTION)
-        return attraction_flow(g, energy, params, n_steps, p0, pT, checkpoints, stats, ws, ws_bytes,
+        return attraction_flow(g, energy, params, n_steps, p0, pT, checkpoints, stats, nullptr, ws, ws_bytes,
                                static_cast<hipStream_t>(stream), true);
     Plan P;
     s = carve(&P, g, OP_FLOW, n_steps, ws, ws_bytes, params->precision, static_cast<hipStream_t>(stream));

@@ -47,7 +47,7 @@ def test_struct_layouts_match_header():
 
 
 def test_version_and_status_strings(lib):
-    assert lib.jko_version() >= 1
+    assert lib.jko_version() == nat.ABI_VERSION == 2
     assert lib.jko_status_string(0) == b"ok"
     assert b"capacity" in lib.jko_status_string(-5)
     assert lib.jko_status_string(123) == b"unknown status"
@@ -72,10 +72,11 @@ def test_workspace_bytes(lib):
     assert jk.workspace_bytes((8, 8, 8), nat.OP_ATTRACTION_STEP, 0, p) == 0
 
 
-def _call_step(lib, grid, energy, params, p_in=1, p_out=2, ws=16, nbytes=1 << 30):
+def _call_step(lib, grid, energy, params, p_in=1, p_out=2, ws=16, nbytes=1 << 30, stats_dev=None):
     return lib.jko_step(ctypes.byref(grid), ctypes.byref(energy) if energy else None,
                         ctypes.byref(params) if params else None, ctypes.c_void_p(p_in),
-                        ctypes.c_void_p(p_out), None, ctypes.c_void_p(ws), nbytes, None)
+                        ctypes.c_void_p(p_out), None, None if stats_dev is None else ctypes.c_void_p(stats_dev),
+                        ctypes.c_void_p(ws), nbytes, None)
 
 
 def test_argument_errors_before_any_launch(lib):
@@ -102,6 +103,11 @@ def test_argument_errors_before_any_launch(lib):
     assert _call_step(lib, g, en, None) == jk.JKO_ERR_INVALID
     assert _call_step(lib, g, en, prm, p_in=0) == jk.JKO_ERR_INVALID
     assert _call_step(lib, g, en, prm, p_in=5, p_out=5) == jk.JKO_ERR_INVALID
+    # the device statistics record: 8-byte aligned, aliasing neither density
+    assert _call_step(lib, g, en, prm, stats_dev=2) == jk.JKO_ERR_INVALID
+    assert b"stats_dev" in lib.jko_last_error()
+    assert _call_step(lib, g, en, prm, stats_dev=4100) == jk.JKO_ERR_INVALID
+    assert _call_step(lib, g, en, prm, stats_dev=4096, ws=0) == jk.JKO_ERR_WORKSPACE
     e2 = jk.EnergySpec(kind="porous", m=1.0).to_c((8, 8))
     assert _call_step(lib, g, e2, prm) == jk.JKO_ERR_INVALID
     e3 = jk.EnergySpec(kind="congestion", kappa_scalar=-1.0).to_c((8, 8))
