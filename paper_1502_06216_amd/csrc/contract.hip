@@ -56,6 +56,76 @@ __device__ __forceinline__ int out_index(int i, int r, int n, int Rb) {
     return f * n * Rb + i * Rb + (r - f * Rb);
 }
 
+// EK_ATTR tiles pair the two stacked fields (B = 2): rows [0, TH) of a TR-row
+// tile are rows r0 .. r0 + TH of field 0, rows [TH, TR) the same rows of
+// field 1, so that the epilogue holds both couplings' values of its cells.
+// X row of tile row d:
+__device__ __forceinline__ int pair_row(int d, int r0, int Rb, int TH) {
+    return d < TH ? r0 + d : Rb + r0 + d - TH;
+}
+
+// The epilogue units of a paired tile: each of the first TH / 4 units of an
+// output row i finishes 4 consecutive cells of both fields; their capacity is
+// fetched before the K loop.
+template <int TR, int TI, int UE>
+__device__ __forceinline__ void attr_units(const EpiArgs& E, int tid, int i0, int r0, int n, int Rb, int* eidx,
+                                           int* ecnt, f4* kap) {
+    constexpr int TH = TR / 2;
+#pragma unroll
+    for (int u = 0; u < UE; ++u) {
+        const int unit = tid + u * kThreads;
+        const int il = unit / (TR / 4), rl = 4 * (unit % (TR / 4));
+        const int i = i0 + il, r = r0 + rl;
+        ecnt[u] = (unit < TI * TR / 4 && rl < TH && i < n) ? max(0, min(4, Rb - r)) : 0;
+        eidx[u] = i * Rb + r;
+        kap[u] = f4{E.prox.kappa_s, E.prox.kappa_s, E.prox.kappa_s, E.prox.kappa_s};
+        if (E.prox.kappa && ecnt[u] > 0) {
+            if (ecnt[u] == 4 && E.vec_ok) kap[u] = *reinterpret_cast<const f4*>(E.prox.kappa + eidx[u]);
+            else
+                for (int e = 0; e < ecnt[u]; ++e) kap[u][e] = E.prox.kappa[eidx[u] + e];
+        }
+    }
+}
+
+// The attraction's proximal step (Section 5.2) on a paired tile staged in LDS
+// as [i][TS] rows: p = min(s_1^alpha s_2^(1 - alpha), kappa), a_m = p / s_m
+// (0/0 = 0).
+template <int TR, int TS, int UE>
+__device__ __forceinline__ void attr_finish(const EpiArgs& E, const float* tile, int tid, int n, int Rb,
+                                            const int* eidx, const int* ecnt, const f4* kap) {
+    constexpr int TH = TR / 2;
+    const float al = E.alpha;
+    const int64_t N = (int64_t)n * Rb;
+#pragma unroll
+    for (int u = 0; u < UE; ++u) {
+        const int unit = tid + u * kThreads;
+        const int il = unit / (TR / 4), rl = 4 * (unit % (TR / 4));
+        if (ecnt[u] == 0) continue;
+        const f4 s1 = *reinterpret_cast<const f4*>(&tile[il * TS + rl]);
+        const f4 s2 = *reinterpret_cast<const f4*>(&tile[il * TS + TH + rl]);
+        f4 pv, a1, a2;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const float g = (s1[e] > 0.f && s2[e] > 0.f) ? expf(al * logf(s1[e]) + (1.f - al) * logf(s2[e])) : 0.f;
+            pv[e] = fminf(g, kap[u][e]);
+            a1[e] = pv[e] == 0.f ? 0.f : pv[e] / s1[e];
+            a2[e] = pv[e] == 0.f ? 0.f : pv[e] / s2[e];
+        }
+        const int o = eidx[u];
+        if (ecnt[u] == 4 && E.vec_ok) {
+            *reinterpret_cast<f4*>(E.p_out + o) = pv;
+            *reinterpret_cast<f4*>(E.a + o) = a1;
+            *reinterpret_cast<f4*>(E.a + N + o) = a2;
+        } else {
+            for (int e = 0; e < ecnt[u]; ++e) {
+                E.p_out[o + e] = pv[e];
+                E.a[o + e] = a1[e];
+                E.a[N + o + e] = a2[e];
+            }
+        }
+    }
+}
+
 // BK: k per chunk.  STAGES = 2: double-buffered chunks; STAGES = 1: the whole
 // band of a tile fits in one chunk (loaded once, then multiplied).
 template <int TR, int TI, int WR, int WI, bool SPLIT, int BK, int STAGES, int EK>
@@ -80,9 +150,7 @@ contract_rot(Pass P, EpiArgs E) {
     int done = 0;
     if (E.ctl) done = E.ctl->done | E.ctl->logmode;
 
-    // EK_ATTR pairs the two stacked fields (B = 2): rows [0, TH) of the tile
-    // are rows r0 .. r0 + TH of field 0, rows [TH, TR) the same rows of field
-    // 1, so that the epilogue holds both couplings' values of its cells.
+    // EK_ATTR: paired tiles (pair_row)
     constexpr bool PAIR = EK == EK_ATTR;
     constexpr int TH = TR / 2;
 
@@ -120,7 +188,7 @@ contract_rot(Pass P, EpiArgs E) {
             f4 v = f4{0.f, 0.f, 0.f, 0.f};
             if (unit < TR * BK / 4) {
                 const int d = unit / (BK / 4), k = kc + 4 * (unit % (BK / 4));
-                const int row = PAIR ? (d < TH ? r0 + d : Rb + r0 + d - TH) : r0 + d;
+                const int row = PAIR ? pair_row(d, r0, Rb, TH) : r0 + d;
                 if (PAIR ? r0 + (d < TH ? d : d - TH) < Rb : row < R) {
                     const float* src = P.X + (row * n + k);
                     if (vec && k + 3 < kb1) v = *reinterpret_cast<const f4*>(src);
@@ -269,22 +337,14 @@ contract_rot(Pass P, EpiArgs E) {
     EpiIn ein[UE];
     int eidx[UE], ecnt[UE];
     f4 kap[UE];   // EK_ATTR: the capacity of the unit's cells
+    if (PAIR) {
+        attr_units<TR, TI, UE>(E, tid, i0, r0, n, Rb, eidx, ecnt, kap);
+    } else {
 #pragma unroll
-    for (int u = 0; u < UE; ++u) {
-        const int unit = tid + u * kThreads;
-        const int il = unit / (TR / 4), rl = 4 * (unit % (TR / 4));
-        const int i = i0 + il, r = r0 + rl;
-        if (PAIR) {
-            // units of the field-0 half finish both fields' cells
-            ecnt[u] = (unit < TI * TR / 4 && rl < TH && i < n) ? max(0, min(4, Rb - r)) : 0;
-            eidx[u] = i * Rb + r;
-            kap[u] = f4{E.prox.kappa_s, E.prox.kappa_s, E.prox.kappa_s, E.prox.kappa_s};
-            if (E.prox.kappa && ecnt[u] > 0) {
-                if (ecnt[u] == 4 && E.vec_ok) kap[u] = *reinterpret_cast<const f4*>(E.prox.kappa + eidx[u]);
-                else
-                    for (int e = 0; e < ecnt[u]; ++e) kap[u][e] = E.prox.kappa[eidx[u] + e];
-            }
-        } else {
+        for (int u = 0; u < UE; ++u) {
+            const int unit = tid + u * kThreads;
+            const int il = unit / (TR / 4), rl = 4 * (unit % (TR / 4));
+            const int i = i0 + il, r = r0 + rl;
             ecnt[u] = (unit < TI * TR / 4 && i < n) ? max(0, min(4, R - r)) : 0;
             eidx[u] = out_index(i, r, n, Rb);
             ein[u] = epi_prefetch<EK>(E, eidx[u], ecnt[u]);
@@ -338,37 +398,7 @@ contract_rot(Pass P, EpiArgs E) {
         }
     __syncthreads();
     if (PAIR) {
-        // p = min(s_1^alpha s_2^(1 - alpha), kappa), a_m = p / s_m (0/0 = 0)
-        const float al = E.alpha;
-        const int64_t N = (int64_t)n * Rb;
-#pragma unroll
-        for (int u = 0; u < UE; ++u) {
-            const int unit = tid + u * kThreads;
-            const int il = unit / (TR / 4), rl = 4 * (unit % (TR / 4));
-            if (ecnt[u] == 0) continue;
-            const f4 s1 = *reinterpret_cast<const f4*>(&tile[il * TS + rl]);
-            const f4 s2 = *reinterpret_cast<const f4*>(&tile[il * TS + TH + rl]);
-            f4 pv, a1, a2;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const float g = (s1[e] > 0.f && s2[e] > 0.f) ? expf(al * logf(s1[e]) + (1.f - al) * logf(s2[e])) : 0.f;
-                pv[e] = fminf(g, kap[u][e]);
-                a1[e] = pv[e] == 0.f ? 0.f : pv[e] / s1[e];
-                a2[e] = pv[e] == 0.f ? 0.f : pv[e] / s2[e];
-            }
-            const int o = eidx[u];
-            if (ecnt[u] == 4 && E.vec_ok) {
-                *reinterpret_cast<f4*>(E.p_out + o) = pv;
-                *reinterpret_cast<f4*>(E.a + o) = a1;
-                *reinterpret_cast<f4*>(E.a + N + o) = a2;
-            } else {
-                for (int e = 0; e < ecnt[u]; ++e) {
-                    E.p_out[o + e] = pv[e];
-                    E.a[o + e] = a1[e];
-                    E.a[N + o + e] = a2[e];
-                }
-            }
-        }
+        attr_finish<TR, TS, UE>(E, tile, tid, n, Rb, eidx, ecnt, kap);
         return;
     }
     EpiAcc ea;
@@ -397,7 +427,8 @@ contract_rot(Pass P, EpiArgs E) {
 //    64-byte rows: chunk c of row r is stored at c ^ ((r >> 2) & 3)
 // Split path: X is staged in FP32 and split into bfloat16 hi + lo (hardware
 // round-to-nearest-even) as each wave reads its operand.
-constexpr int kPanelMax = 5;      // panels per tile band (160 k)
+constexpr int kPanelMax = 5;      // panels per tile band (160 k): 64-row tiles, 3D passes
+constexpr int kPanelMaxRot = 7;   // panels per tile band of 32 x 32 tiles (224 k, 56 KiB of LDS)
 constexpr int kBufRsrcWord3 = 0x00020000;
 
 // Wait until at most `n` (0 .. 31) of this wave's vector memory operations are
@@ -457,12 +488,15 @@ contract_panel(Pass P, EpiArgs E) {
 
     int done = 0;
     if (E.ctl) done = E.ctl->done | E.ctl->logmode;
+    // EK_ATTR: paired tiles (pair_row)
+    constexpr bool PAIR = EK == EK_ATTR;
+    constexpr int TH = TR / 2;
     const int n = P.n;
     const int R = (int)P.R;
     const int Rb = P.B > 1 ? R / P.B : R;
     const int IT = n / TI;
     const int logical = xcd_logical_block();
-    const int r0 = (logical / IT) * TR;
+    const int r0 = (logical / IT) * (PAIR ? TH : TR);
     const int i0 = (logical % IT) * TI;
     const int kb0 = max(0, i0 - P.W) & ~31;
     const int kb1 = min(n, (i0 + TI + P.W + 31) & ~31);
@@ -478,14 +512,19 @@ contract_panel(Pass P, EpiArgs E) {
     constexpr int UE = (TI * TR / 4 + kThreads - 1) / kThreads;
     EpiIn ein[UE];
     int eidx[UE], ecnt[UE];
+    f4 kap[UE];   // EK_ATTR: the capacity of the unit's cells
+    if (PAIR) {
+        attr_units<TR, TI, UE>(E, tid, i0, r0, n, Rb, eidx, ecnt, kap);
+    } else {
 #pragma unroll
-    for (int u = 0; u < UE; ++u) {
-        const int unit = tid + u * kThreads;
-        const int il = unit / (TR / 4), rl = 4 * (unit % (TR / 4));
-        const int i = i0 + il, r = r0 + rl;
-        ecnt[u] = (unit < TI * TR / 4 && i < n) ? max(0, min(4, R - r)) : 0;
-        eidx[u] = out_index(i, r, n, Rb);
-        ein[u] = epi_prefetch<EK>(E, eidx[u], ecnt[u]);
+        for (int u = 0; u < UE; ++u) {
+            const int unit = tid + u * kThreads;
+            const int il = unit / (TR / 4), rl = 4 * (unit % (TR / 4));
+            const int i = i0 + il, r = r0 + rl;
+            ecnt[u] = (unit < TI * TR / 4 && i < n) ? max(0, min(4, R - r)) : 0;
+            eidx[u] = out_index(i, r, n, Rb);
+            ein[u] = epi_prefetch<EK>(E, eidx[u], ecnt[u]);
+        }
     }
     // Staging copies panel by panel (this wave's X rows of the panel, then its
     // K rows), CPP copies per wave and panel, so that panel p has landed once
@@ -494,7 +533,7 @@ contract_panel(Pass P, EpiArgs E) {
     constexpr int KQ = SPLIT ? 2 * (TI / 16) : TI / 8;   // K copies per panel (hi and lo rows)
     static_assert(XPP % 4 == 0 && KQ % 4 == 0, "copies spread evenly over the four waves");
     constexpr int CPP = XPP / 4 + KQ / 4;
-    static_assert((kPanelMax - 1) * CPP <= 31, "per-panel wait counts fit wait_vm");
+    static_assert((kPanelMaxRot - 1) * CPP <= 31, "per-panel wait counts fit wait_vm");
     {
         const __amdgpu_buffer_rsrc_t rx =
             __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(P.X), (short)0, R * n * 4, kBufRsrcWord3);
@@ -511,7 +550,10 @@ contract_panel(Pass P, EpiArgs E) {
             for (int q = wave; q < XPP; q += kThreads / 64) {
                 const int j = pnl * XPP + q, row = q * 8 + xrow;
                 const int col = kb0 + 32 * pnl + 4 * (xch ^ ((row >> 1) & 7));
-                lds_copy16(rx, Xs + j * 256, 4 * ((r0 + row) * n + col));
+                // rows past R read as zeros; a paired tile's field-0 rows past
+                // Rb read field-1 rows, which only reach outputs never written
+                const int grow = PAIR ? pair_row(row, r0, Rb, TH) : r0 + row;
+                lds_copy16(rx, Xs + j * 256, 4 * (grow * n + col));
             }
             if (SPLIT) {
                 // 16 rows of one bf16 panel (hi, then lo) per wave-wide copy
@@ -614,6 +656,10 @@ contract_panel(Pass P, EpiArgs E) {
             *reinterpret_cast<f4*>(&tile[il * TS + rl]) = acc[a][b];
         }
     __syncthreads();
+    if (PAIR) {
+        attr_finish<TR, TS, UE>(E, tile, tid, n, Rb, eidx, ecnt, kap);
+        return;
+    }
     EpiAcc ea;
 #pragma unroll
     for (int u = 0; u < UE; ++u) {
@@ -634,8 +680,9 @@ constexpr int panel_lds_bytes(int TR, int TI, int NP) { return NP * (TR + TI) * 
 //  0: 32 x 32, 2 x 2 waves of one fragment, chunked K loop
 //  1: 16 x 64, 1 x 4 waves (few rows: 1D grids)
 //  2: 64 x 16, 4 x 1 waves (short axes)
-//  3: 32 x 32 panel form (axes of a multiple of 32, band of at most 160 k)
-//  4: 64 x 32 panel form, when it still leaves 4 blocks per CU
+//  3: 32 x 32 panel form (axes of a multiple of 32, band of at most 224 k)
+//  4: 64 x 32 panel form, when it still leaves 4 blocks per CU (band of at
+//     most 160 k)
 // The chunked forms run K in 32-wide chunks through two LDS stages.
 constexpr int kCfgTR[5] = {32, 16, 64, 32, 64};
 constexpr int kCfgTI[5] = {32, 64, 16, 32, 32};
@@ -654,13 +701,14 @@ int panel_count(const Pass& p) {
         const int kb1 = std::min(p.n, (i0 + 32 + p.W + 31) & ~31);
         np = std::max(np, (kb1 - kb0) >> 5);
     }
-    return np <= kPanelMax ? np : 0;
+    return np <= kPanelMaxRot ? np : 0;
 }
 
 int pick_cfg(const Pass& p) {
     if (p.n <= 16) return 2;
     if (p.R <= 16) return 1;
-    if (panel_count(p) > 0) return tiles_of(p, 4) >= kPanelWideBlocks ? 4 : 3;
+    const int np = panel_count(p);
+    if (np > 0) return (np <= kPanelMax && tiles_of(p, 4) >= kPanelWideBlocks) ? 4 : 3;
     return 0;
 }
 
@@ -1178,15 +1226,24 @@ hipError_t launch_contract(const Pass& pass, int32_t precision, const EpiArgs& e
                            hipStream_t stream) {
     if (pass.B > 1 && (pass.R % pass.B != 0 || (pass.R / pass.B) % 4 != 0)) return hipErrorInvalidValue;
     if (epi.kind == EpiKind::ATTR_PROX) {
-        // the paired 32 x 32 rotating form only
+        // paired 32 x 32 tiles: the panel form where the band fits it, else
+        // the chunked form
         if (pass.B != 2) return hipErrorInvalidValue;
         const int64_t nb = tiles_of(pass, 0);
         if (nblocks) *nblocks = (int)nb;
         const dim3 grid((unsigned)nb), block(kThreads);
-        if (precision == JKO_SPLIT_BF16)
+        const int np = panel_count(pass);
+        if (np > 0) {
+            const int lds = panel_lds_bytes(32, 32, np);
+            if (precision == JKO_SPLIT_BF16)
+                hipLaunchKernelGGL((contract_panel<32, 32, 2, 2, true, EK_ATTR>), grid, block, lds, stream, pass, epi);
+            else
+                hipLaunchKernelGGL((contract_panel<32, 32, 2, 2, false, EK_ATTR>), grid, block, lds, stream, pass, epi);
+        } else if (precision == JKO_SPLIT_BF16) {
             hipLaunchKernelGGL((contract_rot<32, 32, 2, 2, true, 32, 2, EK_ATTR>), grid, block, 0, stream, pass, epi);
-        else
+        } else {
             hipLaunchKernelGGL((contract_rot<32, 32, 2, 2, false, 32, 2, EK_ATTR>), grid, block, 0, stream, pass, epi);
+        }
         return hipGetLastError();
     }
     const int c = pick_cfg(pass);
