@@ -47,6 +47,8 @@ def _args():
                          "then a 64 MiB device copy of known size (counter calibration)")
     ap.add_argument("--heat-leg", action="store_true",
                     help="run only the heat-kernel leg (heat100) and print its JSON record")
+    ap.add_argument("--attraction-leg", action="store_true",
+                    help="run only the attraction leg (crowd256_attraction, both precisions) and print its record")
     return ap.parse_args()
 
 
@@ -516,6 +518,36 @@ def heat_solve_bench(wl, steps=1, iters=100):
                                  "eight sweeps per launch on tiles with an eight-cell halo"}}
 
 
+def attraction_bench(wl, precision):
+    """The Wasserstein attraction with congestion (Section 5.2) on its two
+    stacked couplings: a 2D grid whose band is too wide for the fused kernel
+    runs four rotating passes per iteration (t = xi^T a for both couplings,
+    axis 1 then axis 0 with the b-update epilogue; s = xi b likewise, the
+    last pass with the paired proximal epilogue).  The roofline is the
+    whole-iteration rate against FP32 (or BF16) MFMA peak, on the dense
+    per-axis flops (2 couplings x N cells x n per pass, two flops each) and
+    on the flops the panel form executes (each 32-wide output chunk
+    multiplies its band of k rounded out to 32)."""
+    it, el, st, _ = run_flow(wl, precision, wl.n_steps, 1)
+    n0, n1 = wl.shape
+    N = n0 * n1
+    dense = 2 * 2 * 2 * N * (n0 + n1)            # 2 applications x (axis 1 + axis 0), 2 couplings
+    W0, W1 = band_halfwidth(n0, wl.gamma), band_halfwidth(n1, wl.gamma)
+    executed = 2 * 2 * 2 * (n0 * band32_sum(n1, W1) + n1 * band32_sum(n0, W0))
+    peak = 157.3 if precision == "fp32" else 2500.0
+    rate = it / el
+    achieved = dense * rate / 1e12
+    return {"iters_per_s": round(rate, 2), "jko_steps_per_s": round(wl.n_steps / el, 3),
+            "iters_per_step": wl.max_iters, "band": [W0, W1],
+            "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                         "frac": round(achieved / peak, 4), "traffic": None,
+                         "flops_per_iteration": dense, "executed_mfma_flops_per_iteration": executed,
+                         "executed_mfma_frac": round(executed * rate / 1e12 / peak * (3 if precision != "fp32"
+                                                                                        else 1), 4),
+                         "note": "whole-iteration rate over four latency-bound passes of 128 blocks per "
+                                 "iteration (split-BF16: three bf16 products per executed flop)"}}
+
+
 def main():
     args = _args()
     if args.pmc_probe:
@@ -526,6 +558,14 @@ def main():
         from workloads import make_workload
         jk.load()
         print(json.dumps({"heat100_fp32": heat_bench(make_workload("heat100"))}), flush=True)
+        return
+    if args.attraction_leg:
+        import paper_1502_06216_amd as jk
+        from workloads import make_workload
+        jk.load()
+        wla = make_workload("crowd256_attraction")
+        print(json.dumps({f"crowd256_attraction_{p}": attraction_bench(wla, p) for p in ("fp32", "split_bf16")}),
+              flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -597,10 +637,7 @@ def main():
         # Wasserstein attraction with congestion (two couplings, Section 5.2)
         wla = make_workload("crowd256_attraction")
         for prec in ("fp32", "split_bf16"):
-            ita, ela, sta, _ = run_flow(wla, prec, wla.n_steps, 1)
-            extra[f"crowd256_attraction_{prec}"] = {"iters_per_s": round(ita / ela, 2),
-                                                    "jko_steps_per_s": round(wla.n_steps / ela, 3),
-                                                    "iters_per_step": wla.max_iters}
+            extra[f"crowd256_attraction_{prec}"] = attraction_bench(wla, prec)
         # generalised entropies with exponents varying from 1 to 2 over the grid
         wlg = make_workload("gen512")
         for prec in ("fp32", "split_bf16"):
