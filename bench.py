@@ -134,16 +134,36 @@ PROFILES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
 # counter summaries of the dominant launch per (workload, precision)
 TRAFFIC_PROFILES = {("crowd256", "fp32"): "resident2d_congestion_crowd256_traffic.md",
                     ("crowd128c", "fp32"): "plane_pass_crowd128c_traffic.md",
-                    ("porous512_scaled", "fp32"): "resident2d_porous_porous512_traffic.md"}
+                    ("porous512_scaled", "fp32"): "resident_pass_porous512_traffic.md"}
+
+
+def resident_pass_shape(shape):
+    """True when a 2D step of this shape runs on the resident pass kernel
+    rather than the resident tile kernel (the library's rule for the bench's
+    workloads: more than 256 tiles of 16 x 16, axes of a multiple of 32)."""
+    n0, n1 = shape
+    return -(-n0 // 16) * -(-n1 // 16) > 256 and n0 % 32 == 0 and n1 % 32 == 0
 
 
 def kernel_source_hash(kernel_file):
-    """sha256 of the sources one kernel is compiled from (its file plus the
-    shared device headers); a stored counter reading is valid only for the
-    sources it was taken on."""
+    """sha256 of the sources one kernel is compiled from (its file and every
+    header of the library it includes, directly or not); a stored counter
+    reading is valid only for the sources it was taken on."""
     import hashlib
+    import re
+    files = []
+
+    def visit(f):
+        if f in files or not os.path.exists(os.path.join(CSRC, f)):
+            return
+        files.append(f)
+        with open(os.path.join(CSRC, f)) as fh:
+            for inc in re.findall(r'^#include "([^"]+)"', fh.read(), re.M):
+                visit(inc)
+
+    visit(kernel_file)
     h = hashlib.sha256()
-    for f in ("jko_internal.h", "control.h", "epilogue.h", kernel_file):
+    for f in sorted(files):
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -211,10 +231,18 @@ def roofline(wl, precision, q, traffic_profile=None, resident=True):
         K = wl.max_iters
         flops = [K * 2 * 2.0 * (wl.shape[0] + wl.shape[1]) * N]
         nbytes = [K * (12.0 + 8.0 + fb) * N]
-        names = [f"resident 2D kernel, {K} iterations"]
-        kfile = "gibbs2d.hip"
         W = [band_halfwidth(n, wl.gamma) for n in wl.shape]
-        executed = [K * 2 * fused2d_executed_flops(wl.shape[0], wl.shape[1], W[0], W[1], precision)]
+        if resident_pass_shape(wl.shape):
+            # four panel passes per iteration, each 32-wide output chunk over
+            # its band of k rounded out to 32
+            n0, n1 = wl.shape
+            names = [f"resident pass kernel, {K} iterations"]
+            kfile = "respass.hip"
+            executed = [K * 2 * 2 * (n0 * band32_sum(n1, W[1]) + n1 * band32_sum(n0, W[0]))]
+        else:
+            names = [f"resident 2D kernel, {K} iterations"]
+            kfile = "gibbs2d.hip"
+            executed = [K * 2 * fused2d_executed_flops(wl.shape[0], wl.shape[1], W[0], W[1], precision)]
     elif len(ms) == 2 and d == 2:
         flops = [2.0 * (wl.shape[0] + wl.shape[1]) * N] * 2
         nbytes = [12.0 * N, (8.0 + fb) * N]
@@ -425,19 +453,14 @@ def heat_pass_traffic():
     finish) from the
     committed counter summary, or None when it is missing or the heat
     kernels' sources changed since it was taken."""
-    import hashlib
     import re
     path = os.path.join(PROFILES, "heat_pass_heat100.md")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
-    h = hashlib.sha256()
-    for f in ("jko_internal.h", "epilogue.h", "heat.h", "heat.hip"):
-        with open(os.path.join(CSRC, f), "rb") as fh:
-            h.update(fh.read())
     m_h = re.search(r"^source_sha256:\s*([0-9a-f]{64})", txt, re.M)
     m_t = re.search(r"^traffic_bytes_per_pass:\s*([0-9]+)", txt, re.M)
-    if not m_h or not m_t or m_h.group(1) != h.hexdigest():
+    if not m_h or not m_t or m_h.group(1) != kernel_source_hash("heat.hip"):
         return None
     return int(m_t.group(1))
 

@@ -172,14 +172,24 @@ typedef struct {
 } jko_params;
 
 /* Execution flags of jko_params.flags.
- * JKO_FLAG_NO_RESIDENT: on 2D grids whose fused kernel fits the chip in one
- *   wave of blocks, a step's whole iteration normally runs in one cooperative
- *   launch (the resident kernel); this flag keeps one launch per Gibbs
- *   application instead.  Both paths give the same bits.
+ * 2D applications of xi run as the fused tile kernel (16 x 16 tiles) where at
+ * most 256 tiles cover the grid; else, on axes of a multiple of 32 with at
+ * most 256 tiles of 32 x 32 and bands of at most seven 32-cell panels, as
+ * two per-axis passes; else as the fused kernel with 32 x 32 tiles where it
+ * fits, else as the passes.  A step whose applications are fused tiles or
+ * such passes normally runs whole in one cooperative launch (the resident
+ * tile kernel, or the resident pass kernel, which runs the passes without
+ * launch boundaries); so does the attraction's pair of couplings on the
+ * passes' shapes.
+ * JKO_FLAG_NO_RESIDENT: one launch per Gibbs application (per pass) instead
+ *   of the resident kernels.  Both paths give the same bits.
  * JKO_FLAG_AXIS_PASSES: on 3D grids whose axes are multiples of 32 (the
  *   second at most 128), an application of xi normally runs as a plane pass
  *   (axes 1 and 2 of each plane, the intermediate kept on chip) and an axis-0
  *   pass; this flag runs three axis passes instead.  Both give the same bits.
+ *   On 2D grids it runs every application as per-axis passes instead of the
+ *   fused tile kernel (and a step on the resident pass kernel where its
+ *   shape allows).
  * JKO_FLAG_ABSORB_ON_A: the absorption switch (finite absorb_threshold)
  *   watches max|log a| alone instead of max(max|log a|, max|log b|).  Ignored
  *   by JKO_F_ATTRACTION, which watches max|log b|. */

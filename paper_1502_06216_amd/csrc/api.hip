@@ -225,6 +225,7 @@ struct Plan {
     bool batch_pass = false;     // stacked (2, n0, n1) applications: per-field rotating passes, no pass over
                                  // the identity axis
     bool resident = false;       // ... and a step may run in one resident launch
+    bool respass = false;        // a step may run in one launch of the resident pass kernel
     bool plane3d = false;        // 3D applications run as a plane pass and a slow-axis pass
 
     float* F(int i) const { return field[i]; }
@@ -272,19 +273,28 @@ jko_status build_factors(Plan& P, double gamma, int32_t flags = 0) {
     for (int k = 0; k < P.g.d; ++k) P.W[k] = band_halfwidth(P.g.n[k], gamma);
     P.plane3d = P.g.d == 3 && !(flags & JKO_FLAG_AXIS_PASSES) &&
                 plane3d_fits(P.g.n[0], P.g.n[1], P.g.n[2], P.W[0], P.W[1], P.W[2]);
-    // The fused kernel trades redundant halo work for one launch per
-    // application: it wins while its grid is at most one block per CU, with
-    // 16 x 16 tiles where they are few enough, else with 32 x 32 tiles.
+    // A 2D application runs as the fused tile kernel, which trades redundant
+    // halo work for one launch, with 16 x 16 tiles where at most one block
+    // per CU covers the grid.  Otherwise, for axes of a multiple of 32 whose
+    // bands span at most seven 32-k panels and at most 256 tiles of 32 x 32,
+    // as the two panel passes (and a step on the resident pass kernel, which
+    // runs them without launch boundaries); else as the fused kernel with
+    // 32 x 32 tiles where it fits, else as the passes.
     P.tile = 0;
-    if (P.g.d == 2)
-        for (int tt : {16, 32})
+    const bool passes2d =
+        P.g.d == 2 && resident_pass2d_shape_fits(P.g.n[0], P.g.n[1], P.W[0], P.W[1], 1);
+    if (P.g.d == 2 && !(flags & JKO_FLAG_AXIS_PASSES))
+        for (int tt : {16, 32}) {
+            if (tt == 32 && passes2d) break;
             if (gibbs2d_fits(P.g.n[0], P.g.n[1], P.W[0], P.W[1], P.prec, tt) &&
                 gibbs2d_blocks(P.g.n[0], P.g.n[1], tt) <= kFusedMaxBlocks) {
                 P.tile = tt;
                 break;
             }
+        }
     P.fused2d = P.tile != 0;
     P.resident = P.fused2d;
+    P.respass = !P.fused2d && passes2d;
     for (int k = 0; k < P.g.d; ++k) {
         bool done = false;
         for (int j = 0; j < k; ++j)
@@ -631,6 +641,74 @@ bool use_resident(const Plan& P, const jko_params* pr, const ProxArgs& px) {
            resident2d_fits(P.g.n[0], P.g.n[1], P.W[0], P.W[1], px.kind, P.prec, P.tile);
 }
 
+// The resident pass kernel (no history for the adjoint's recomputation).
+bool use_respass(const Plan& P, const jko_params* pr, const ProxArgs& px, bool record_hist) {
+    return P.respass && !record_hist && !(pr->flags & JKO_FLAG_NO_RESIDENT) &&
+           resident_pass2d_fits(P.g.n[0], P.g.n[1], P.W[0], P.W[1], 1, px.kind, P.prec);
+}
+
+// Queue the resident pass kernel for K iterations of a step on B stacked
+// fields (the scalings and control block initialised); q holds the B
+// marginals.  *launched as for launch_resident.
+jko_status launch_respass(const Plan& P, int B, int W0, int W1, int k0, int k1, const float* q, float* p_out,
+                          const ProxArgs& px, float alpha, int K, int ce, bool checks, double tol, double absorb,
+                          int a_only, bool* launched) {
+    *launched = false;
+    ResidentPass2D r{};
+    const int n0 = P.g.n[k0], n1 = P.g.n[k1];
+    r.n0 = n0;
+    r.n1 = n1;
+    r.W0 = W0;
+    r.W1 = W1;
+    r.K0 = P.K1[k0];
+    r.K0hi = P.K1hi[k0];
+    r.K0lo = P.K1lo[k0];
+    r.K1 = P.K1[k1];
+    r.K1hi = P.K1hi[k1];
+    r.K1lo = P.K1lo[k1];
+    r.B = B;
+    r.q = q;
+    r.a = P.F(F_A);
+    r.b = P.F(F_B);
+    r.u0 = P.F(F_Z1);
+    r.u1 = P.F(F_Z2);
+    r.p_out = p_out;
+    r.prox = px;
+    r.alpha = alpha;
+    r.part = P.part;
+    r.ctl = P.ctl;
+    r.sync = P.sync;
+    r.K = K;
+    r.ce = ce;
+    r.checks = checks ? 1 : 0;
+    r.split = P.prec == JKO_SPLIT_BF16 ? 1 : 0;
+    r.a_only = a_only;
+    r.check_mass = B == 1 ? 1 : 0;
+    r.tol = tol;
+    r.absorb = absorb;
+    r.spin_limit = kBarrierSpinLimit;
+    EpiArgs al{};
+    al.q = q;
+    al.b = r.b;
+    al.a = r.a;
+    al.y = r.u0;
+    al.acc = r.u1;
+    al.p_out = p_out;
+    al.prox = px;
+    set_vec(al);
+    r.vec_ok = al.vec_ok;
+    HIP_TRY(launch_fill(reinterpret_cast<float*>(P.sync), 0.f,
+                        resident_sync_words(resident_pass2d_blocks(n0, n1, B)), P.st));
+    const hipError_t e = launch_resident_pass2d(r, P.st);
+    if (e == hipErrorCooperativeLaunchTooLarge) {
+        (void)hipGetLastError();
+        return JKO_OK;
+    }
+    HIP_TRY(e);
+    *launched = true;
+    return JKO_OK;
+}
+
 // Queue the resident kernel for K iterations of a step (scalings and control
 // block already initialised).  *launched is false (and nothing is queued but
 // the sync-word reset) when the runtime refuses the cooperative grid, e.g.
@@ -743,9 +821,12 @@ jko_status run_step(const Plan& P, const jko_params* pr, const ProxArgs& px, con
 
     int k0 = 1;   // first iteration left to the launch path
     bool resident = false;
-    if (!logd && use_resident(P, pr, px)) {
-        jko_status s = launch_resident(P, q, p_out, px, K, ce, checks, pr->tol_l1, absorb, a_only, record_hist,
-                                       &resident);
+    const bool respass = !logd && use_respass(P, pr, px, record_hist);
+    if (!logd && (respass || use_resident(P, pr, px))) {
+        jko_status s = respass ? launch_respass(P, 1, P.W[0], P.W[1], 0, 1, q, p_out, px, 0.f, K, ce, checks,
+                                                pr->tol_l1, absorb, a_only, &resident)
+                               : launch_resident(P, q, p_out, px, K, ce, checks, pr->tol_l1, absorb, a_only,
+                                                 record_hist, &resident);
         if (s) return s;
         if (resident && (s = resident_check(P))) return s;
         if (resident && absorb > 0.0) {
@@ -953,7 +1034,31 @@ jko_status run_attraction(const Plan& P, const jko_params* pr, const jko_energy*
     bool logd = logmode;   // the domain of the next application (as in run_step)
     bool pending = false, stopped = false;
     int nb = 0;
-    for (int k = 1; k <= K; ++k) {
+    int k_first = 1;   // first iteration left to the launch path
+    if (!logd && P.respass && resident_pass2d_fits(P.g.n[1], P.g.n[2], P.W[1], P.W[2], 2, 0, P.prec)) {
+        // the whole step in one launch of the resident pass kernel (paired tiles)
+        bool launched = false;
+        jko_status s = launch_respass(P, 2, P.W[1], P.W[2], 1, 2, qs, p_out, ex.prox, ex.alpha, K, ce, checks,
+                                      pr->tol_l1, absorb, 0, &launched);
+        if (s) return s;
+        if (launched) {
+            if ((s = resident_check(P))) return s;
+            k_first = K + 1;
+            if (absorb > 0.0) {
+                // returned after the proximal half-step of the iteration whose
+                // check asked for the log domain: convert and go on there
+                Ctl c{};
+                if ((s = read_ctl(P, &c))) return s;
+                if (c.exit_iter > 0 && !c.done) {
+                    HIP_TRY(launch_absorb(P.ctl, a, b, 2 * N, P.st));
+                    HIP_TRY(launch_ctl_commit(P.ctl, c.exit_iter, P.st));
+                    logd = true;
+                    k_first = c.exit_iter + 1;
+                }
+            }
+        }
+    }
+    for (int k = k_first; k <= K; ++k) {
         eb.check = (checks && k > 1 && (k - 1) % ce == 0) ? 1 : 0;
         jko_status s = apply_xi_in(logd, P, a, eb, &nb);
         if (s) return s;
@@ -1055,7 +1160,10 @@ jko_status attraction_flow(const Geo& g, const jko_energy* en, const jko_params*
     P.ident[0] = true;
     // 2D grids: both couplings in one launch of the fused 2D kernel per
     // application (axis 0 of the stacked field is the identity)
-    if (g.d == 2)
+    // the resident pass kernel (paired tiles) where the grid and bands suit it
+    const bool respass2 = g.d == 2 && !(pr->flags & JKO_FLAG_NO_RESIDENT) &&
+                          resident_pass2d_shape_fits(g.n[0], g.n[1], P.W[1], P.W[2], 2);
+    if (g.d == 2 && !respass2 && !(pr->flags & JKO_FLAG_AXIS_PASSES))
         for (int tt : {16, 32})
             if (gibbs2d_fits(g.n[0], g.n[1], P.W[1], P.W[2], P.prec, tt) &&
                 gibbs2d_blocks(g.n[0], g.n[1], tt) <= kFusedMaxBlocks) {
@@ -1067,6 +1175,7 @@ jko_status attraction_flow(const Geo& g, const jko_energy* en, const jko_params*
     // two passes (rows of a field a multiple of 4), so no pass runs over the
     // identity axis
     if (g.d == 2 && !P.batch2d && g.n[0] % 4 == 0 && g.n[1] % 4 == 0) P.batch_pass = true;
+    P.respass = respass2;
     // capacity of the initial density, and a target of the same mass
     double h[3], hr[3];
     HIP_TRY(launch_input_check(p0, en->kappa, en->kappa_scalar, g.N, 1, P.part.err, 3 * 256, P.hostout, P.st));
@@ -1343,8 +1452,10 @@ jko_status jko_time_iteration(const jko_grid* grid, const jko_energy* energy, co
         return JKO_OK;
     };
     int slot = 0;
-    if (use_resident(P, params, px)) {
-        // one launch of the resident kernel running max_iters iterations
+    const bool respass = use_respass(P, params, px, false);
+    if (respass || use_resident(P, params, px)) {
+        // one launch of the resident kernel running max_iters iterations (the
+        // resident pass kernel writes no density here)
         if ((s = readback_init())) return s;
         double tot = 0.0;
         for (int k = 0; k <= reps && !s; ++k) {   // k = 0: warm-up
@@ -1352,7 +1463,10 @@ jko_status jko_time_iteration(const jko_grid* grid, const jko_energy* energy, co
             HIP_TRY(launch_ctl_reset(P.ctl, 0, P.st));
             HIP_TRY(hipEventRecord(e0, P.st));
             bool launched = false;
-            s = launch_resident(P, p_in, P.F(F_Z1), px, params->max_iters, 1, false, 0.0, 0.0, 0, false, &launched);
+            s = respass ? launch_respass(P, 1, P.W[0], P.W[1], 0, 1, p_in, nullptr, px, 0.f, params->max_iters, 1,
+                                         false, 0.0, 0.0, 0, &launched)
+                        : launch_resident(P, p_in, P.F(F_Z1), px, params->max_iters, 1, false, 0.0, 0.0, 0, false,
+                                          &launched);
             if (s) break;
             if (!launched) {
                 s = fail(JKO_ERR_HIP, "the cooperative grid of the resident kernel was refused");

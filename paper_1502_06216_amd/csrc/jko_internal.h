@@ -225,6 +225,51 @@ hipError_t launch_resident_adj(const ResidentAdj& r, hipStream_t stream);
 bool resident2d_fits(int n0, int n1, int W0, int W1, int prox_kind, int32_t precision, int tile);
 hipError_t launch_resident2d(const Resident2D& r, hipStream_t stream);
 
+// A whole 2D step in one cooperative launch with every application of xi
+// as the two rotating panel passes (axis 1 into the transposed intermediate
+// u, then axis 0 with the epilogue), for bands up to seven 32-k panels: block
+// t owns one 32 x 32 output tile of each pass (paired tiles, 16 rows of each
+// field, for the attraction's two couplings) and waits only for the blocks
+// whose outputs its pass reads.  Same arithmetic as the launched passes.
+struct ResidentPass2D {
+    int32_t n0, n1;        // grid, both multiples of 32
+    int32_t W0, W1;        // band half-widths
+    const float* K0;       // axis-0 factor (n0 x n0) and its bfloat16 split
+    const uint16_t* K0hi;
+    const uint16_t* K0lo;
+    const float* K1;       // axis-1 factor (n1 x n1)
+    const uint16_t* K1hi;
+    const uint16_t* K1lo;
+    int32_t B;             // stacked fields: 1, or 2 (the attraction's couplings)
+    const float* q;        // marginals, B fields
+    float* a;              // scalings, B fields each (a starts at 1)
+    float* b;
+    float* u0;             // transposed intermediates, B fields each: t half-step
+    float* u1;             //                                          s half-step
+    float* p_out;          // density written at candidate iterations
+    ProxArgs prox;
+    float alpha;           // attraction: 1 / (1 + tau)
+    Partials part;
+    Ctl* ctl;
+    uint32_t* sync;        // resident_sync_words(blocks), zeroed before the launch
+    int32_t K;             // iterations
+    int32_t ce;            // check cadence
+    int32_t checks;        // stop test / absorption checks on
+    int32_t vec_ok;        // all field pointers 16-byte aligned
+    int32_t spin_limit;    // polls before a wait gives up
+    int32_t split;         // split-BF16 contractions
+    int32_t a_only;        // the absorption trigger watches max|log a| alone
+    int32_t check_mass;    // the proximal epilogue accumulates mass and max|log a| partials
+    double tol;
+    double absorb;
+};
+int64_t resident_pass2d_blocks(int n0, int n1, int B);
+// The grid and bands suit the kernel (axes of a multiple of 32, at most 256
+// blocks, bands of at most seven panels); _fits also asks the device.
+bool resident_pass2d_shape_fits(int n0, int n1, int W0, int W1, int B);
+bool resident_pass2d_fits(int n0, int n1, int W0, int W1, int B, int prox_kind, int32_t precision);
+hipError_t launch_resident_pass2d(const ResidentPass2D& r, hipStream_t stream);
+
 // Largest |i - j| at which the float32 factor exp(-((i-j)/n)^2/gamma) can be
 // non-zero (entries below 2^-150 round to zero).
 int band_halfwidth(int n, double gamma);

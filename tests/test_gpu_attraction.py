@@ -67,14 +67,15 @@ def test_flow_matches_oracle(shape, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
-@pytest.mark.parametrize("shape", [(200, 160), (224, 100), (201, 161)])
+@pytest.mark.parametrize("shape", [(200, 160), (224, 100), (192, 160), (201, 161)])
 def test_wide_band_matches_oracle(shape, precision):
     """gamma = 1e-3: bands of about a third of each axis, too wide for the
     fused 2D kernel.  (200, 160) runs the two couplings through per-field
     rotating passes (rows a multiple of 4), the paired proximal pass in the
     chunked form (axis 0 not a multiple of 32); (224, 100) runs that pass in
     the panel form, with 100 rows per field (the last paired tile's field-0
-    half reads past its field); (201, 161) runs the stacked field's three
+    half reads past its field); (192, 160) runs the whole step on the
+    resident pass kernel; (201, 161) runs the stacked field's three
     passes."""
     banner(f"attraction wide band {shape} {precision}")
     wl = _case(shape, gamma=1e-3)

@@ -79,9 +79,10 @@ def test_flow_matches_oracle(precision):
                                      ("gen512", dict(max_iters=120, tol=0.0, check_every=10)),
                                      ("ragged", dict(max_iters=200, tol=1e-7, check_every=7))])
 def test_resident_same_bits_as_launch_path(name, kw, precision):
-    """512^2 nonlinear diffusion (tolerance mode), the generalised entropies,
-    and ragged congestion: resident and launch paths give the same bits and
-    statistics."""
+    """512^2 nonlinear diffusion (tolerance mode) and the generalised
+    entropies (both on the resident pass kernel against the launched passes:
+    512 is a multiple of 32), and ragged congestion (32 x 32 tiles): resident
+    and launch paths give the same bits and statistics."""
     banner(f"tiles32 resident vs launch {name} {precision}")
     wl = _case((300, 280)) if name == "ragged" else make_workload(name)
     _same(*_both(wl, precision=precision, **kw))
