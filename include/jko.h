@@ -116,8 +116,9 @@ typedef enum { JKO_FP32 = 0, JKO_SPLIT_BF16 = 1 } jko_precision;
  *                    half-step is eq. prox-psi-attraction).  The workspace is
  *                    sized by JKO_OP_ATTRACTION_STEP / _FLOW.  1D and 2D grids
  *                    with every axis >= 3; absorption as for the other
- *                    energies, the switch triggered by max|log b| alone; no
- *                    resident kernel, no backward. */
+ *                    energies, the switch triggered by max|log b| alone; a
+ *                    step runs on the resident pass kernel where the shape
+ *                    allows (see the execution flags); no backward. */
 typedef enum {
     JKO_F_ZERO = 0,
     JKO_F_CONGESTION = 1,
@@ -300,12 +301,12 @@ jko_status jko_step_static(const jko_grid* grid, const jko_energy* energy, const
 
 /* Measurement aid (not part of the method): sets up one step of p_in as
  * jko_step does, then times its kernel launches `reps` times on `stream` with
- * HIP events.  Where a step runs on the resident 2D kernel (see
- * JKO_FLAG_NO_RESIDENT), that is one launch running params->max_iters
- * iterations with no stop test.  Otherwise it is each launch of one
+ * HIP events.  Where a step runs on a resident kernel (the tile kernel or
+ * the pass kernel; see the execution flags), that is one launch running
+ * params->max_iters iterations with no stop test.  Otherwise it is each launch of one
  * iteration -- those of t = xi^T a ending in the b-update epilogue, then those
  * of s = xi b ending in the proximal epilogue (one launch per application for
- * 2D grids on the fused band kernel, else one per axis) -- back to back.
+ * 2D grids on the fused tile kernel, else one per axis) -- back to back.
  * ms_per_launch (host, room for 2*ndim doubles) receives the mean duration of
  * one launch of each, in launch order; *n_launches (host, nullable) their
  * number.  The scalings are set to 1 first; p_in is not modified.

@@ -252,10 +252,12 @@ def step(p: torch.Tensor, energy: EnergySpec, gamma: float, tau: float, max_iter
          stats_dev: Optional[torch.Tensor] = None):
     """One JKO step p -> argmin_p' W_gamma(p', p) + tau f(p').  Returns
     (p_next, stats dict or None).  resident=False keeps one launch per Gibbs
-    application where the resident 2D kernel would run the step; planes=False
-    runs 3D applications as three axis passes instead of a plane pass and an
-    axis-0 pass; absorb_on_a=True makes the absorption switch watch max|log a|
-    alone.  stats_dev (a float64 tensor of STATS_DEV_DOUBLES elements on the
+    application (per pass) where a resident kernel (the 2D tile kernel or the
+    pass kernel) would run the step; planes=False runs 3D applications as
+    three axis passes instead of a plane pass and an axis-0 pass, and 2D
+    applications as per-axis passes (resident: the pass kernel) instead of
+    the fused tile kernel; absorb_on_a=True makes the absorption switch watch
+    max|log a| alone.  stats_dev (a float64 tensor of STATS_DEV_DOUBLES elements on the
     same device) receives the statistics on the device, ordered on the current
     stream after p_next, with no read-back; stats_from_device() reads it."""
     lib = load()
