@@ -145,3 +145,19 @@ def test_attraction_tolerance_and_switch_same_bits():
     res, ref = _both(wl, max_iters=60, tol=0.0, check_every=10, absorb_threshold=5.0)
     _same(res, ref, ATTR_KEYS)
     assert res[1]["absorptions"] == 1
+
+
+@pytest.mark.parametrize("name,steps,kw", [
+    ("porous512_scaled", 10, dict(max_iters=300, tol=1e-6, check_every=10)),
+    ("crowd256_attraction", 3, dict(max_iters=300, tol=0.0, check_every=10)),
+])
+def test_flows_repeat_bit_for_bit(name, steps, kw):
+    """Whole flows (every step one launch of the pass kernel): two runs give
+    the same bits, and so do the launched passes."""
+    banner(f"respass flow {name} x {steps}")
+    wl = make_workload(name)
+    g_en, _ = energies(wl)
+    outs = [jk.flow(dev(wl.p0), g_en, wl.gamma, wl.tau, steps, resident=r, **kw) for r in (True, True, False)]
+    (p1, s1, _), (p2, s2, _), (p3, s3, _) = outs
+    assert torch.equal(p1, p2) and torch.equal(p1, p3)
+    assert [s["iters"] for s in s1] == [s["iters"] for s in s2] == [s["iters"] for s in s3]
