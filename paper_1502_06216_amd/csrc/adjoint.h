@@ -15,18 +15,73 @@ namespace jko {
 // convex, and both L / (1 + c) and, for L > 0, log(1 + eps L / c) / eps lie at
 // or right of the root (e^x >= 1 + x), so Newton from their minimum descends
 // monotonically onto it.  (e^x - 1) / x is taken as 1 + x/2 for |x| < 1e-4.
+//
+// Stopping rule of the Newton proxes (this one and the porous one): both
+// converge quadratically with a constant of at most 1/2 (here in Y, F''/(2F')
+// <= eps/2; the porous form in the log of its variable), so once a step's
+// update is within 2^-20 of the iterate's scale the error left is about 2^-41
+// of it, far below float32 rounding, and further steps would only move the
+// iterate by rounding.  `steps` caps the count.  The update's divisor F' only
+// sets the speed, not the root, so it takes the hardware reciprocal, and here
+// e^x comes from the residual's (e^x - 1) / x.
+constexpr float kNewtonTol = 0x1p-20f;
+
+__device__ __forceinline__ float gen_newton_step(float y, float L, float c, float eps) {
+    const float x = eps * y;
+    const float phi = fabsf(x) < 1e-4f ? 1.f + 0.5f * x : expm1f(x) / x;
+    const float f = y + c * y * phi - L;
+    return y - f * __builtin_amdgcn_rcpf(1.f + c * (1.f + x * phi));
+}
+
+__device__ __forceinline__ bool gen_newton_settled(float y, float yn) {
+    return fabsf(yn - y) <= kNewtonTol * fmaxf(fabsf(yn), 1.f);
+}
+
 __device__ __forceinline__ float log_prox_gen(float L, float c, float eps, int steps) {
     float y = L / (1.f + c);
     if (eps > 0.f && c > 0.f) {
         if (L > 0.f) y = fminf(y, log1pf(eps * L / c) / eps);
         for (int it = 0; it < steps; ++it) {
-            const float x = eps * y;
-            const float phi = fabsf(x) < 1e-4f ? 1.f + 0.5f * x : expm1f(x) / x;
-            const float f = y + c * y * phi - L;
-            y -= f / (1.f + c * expf(x));
+            const float yn = gen_newton_step(y, L, c, eps);
+            const bool done = gen_newton_settled(y, yn);
+            y = yn;
+            if (done) break;
         }
     }
     return y;
+}
+
+// Porous prox in the variable v = (m-1) k psi^{m-1}: the root equation
+// log psi + k psi^{m-1} = log s becomes v + log v = lz with
+// lz = log((m-1) k) + (m-1) log s (Lambert W of e^lz).  Newton steps on it in
+// residual form, v <- v - (log v + v - lz) v / (1 + v); the start
+// v0 = log(1 + e^lz) (lz < 1) or lz - log lz is within 2% of the root
+// everywhere, so a few steps settle it under the stopping rule of the Newton
+// proxes.
+__device__ __forceinline__ float porous_newton_step(float v, float lz) {
+    const float r = logf(v) + v - lz;
+    return v - r * v * __builtin_amdgcn_rcpf(1.f + v);
+}
+
+// The residual carries rounding noise of a few ulps of |lz|, so the relative
+// update is compared with 2^-20 max(1, |lz|) (at |lz| <= 60 the error left is
+// still below 2^-29 of v).
+__device__ __forceinline__ bool porous_newton_settled(float v, float vn, float lz) {
+    return fabsf(vn - v) <= kNewtonTol * fmaxf(fabsf(lz), 1.f) * fabsf(vn);
+}
+
+__device__ __forceinline__ float porous_start(float lz) { return (lz < 1.f) ? log1pf(expf(lz)) : lz - logf(lz); }
+
+// The root v of v + log v = lz.
+__device__ __forceinline__ float porous_root(float lz, int steps) {
+    float v = porous_start(lz);
+    for (int it = 0; it < steps; ++it) {
+        const float vn = porous_newton_step(v, lz);
+        const bool done = porous_newton_settled(v, vn, lz);
+        v = vn;
+        if (done) break;
+    }
+    return v;
 }
 
 // Reverse of p = prox(s), a = p / s at one cell:
@@ -66,11 +121,7 @@ __device__ __forceinline__ float adj_prox_cell(const ProxArgs& px, float sigma, 
             p = sv;
             dpds = 1.f;
         } else {
-            float v = (lz < 1.f) ? log1pf(expf(lz)) : lz - logf(lz);
-            for (int it = 0; it < px.newton; ++it) {
-                const float r = logf(v) + v - lz;
-                v = v - r * v / (1.f + v);
-            }
+            const float v = porous_root(lz, px.newton);
             p = expf(ls - v / (m - 1.f));
             // implicit derivative of log psi + k psi^{m-1} = log s
             dpds = (p / sv) / (1.f + v);

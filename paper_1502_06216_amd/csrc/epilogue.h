@@ -54,22 +54,83 @@ __device__ inline double block_max(double v, double* sh) {
 
 // --------------------------------------------------------- proximal maps
 
-// Porous prox in the variable v = (m-1) k psi^{m-1}: the root equation
-// log psi + k psi^{m-1} = log s becomes v + log v = lz with
-// lz = log((m-1) k) + (m-1) log s (Lambert W of e^lz).  Newton steps on it in
-// residual form; the start v0 = log(1 + e^lz) (lz < 1) or lz - log lz is within
-// 2% of the root everywhere, and 4 steps reach float32 rounding.  Returns
-// log psi.
+// log Prox(e^ls) of the porous energy: log psi = ls - v / (m - 1) with v the
+// root of v + log v = lz (porous_root).
 __device__ __forceinline__ float log_prox_porous(float ls, float lk, float m, int steps) {
     if (ls == -INFINITY) return -INFINITY;
     const float lz = lk + (m - 1.f) * ls;
     if (lz < -60.f) return ls;   // v < 1e-26: psi = s to float32 rounding (also k = 0)
-    float v = (lz < 1.f) ? log1pf(expf(lz)) : lz - logf(lz);
-    for (int it = 0; it < steps; ++it) {
-        const float r = logf(v) + v - lz;
-        v = v - r * v / (1.f + v);
+    return ls - porous_root(lz, steps) / (m - 1.f);
+}
+
+// The porous and generalised-entropy proxes of a thread's NE cells at once,
+// in the log domain (ls = log s, -inf for s = 0): log_prox_porous and
+// log_prox_gen cell by cell (a cell stops stepping once settled, as there),
+// with the loop running until every cell has settled or the cap is reached.
+// Cells that take no Newton step (s = 0, lz < -60, a zero coefficient or
+// exponent) keep their closed form.
+template <int KIND, int NE>
+__device__ __forceinline__ f4 log_prox_cells(const ProxArgs& px, f4 ls, f4 pu, f4 pv) {
+    static_assert(KIND == JKO_F_POROUS || KIND == JKO_F_GEN_ENTROPY, "Newton proxes only");
+    f4 out;
+    if constexpr (KIND == JKO_F_POROUS) {
+        const float m = px.m;
+        float lz[NE], v[NE];
+        bool go[NE];
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            const float z = pu[e] + (m - 1.f) * ls[e];
+            go[e] = !(ls[e] == -INFINITY) && !(z < -60.f);
+            lz[e] = go[e] ? z : 1.f;
+            v[e] = go[e] ? porous_start(z) : 1.f;
+        }
+        for (int it = 0; it < px.newton; ++it) {
+            bool any = false;
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                const float vn = porous_newton_step(v[e], lz[e]);
+                const bool done = porous_newton_settled(v[e], vn, lz[e]);
+                v[e] = go[e] ? vn : v[e];
+                go[e] = go[e] && !done;
+                any |= go[e];
+            }
+            if (!any) break;
+        }
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            const float z = pu[e] + (m - 1.f) * ls[e];
+            out[e] = (ls[e] == -INFINITY) ? -INFINITY : (z < -60.f) ? ls[e] : ls[e] - v[e] / (m - 1.f);
+        }
+    } else {
+        float y0[NE], y[NE], L[NE];
+        bool nw[NE], go[NE];
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            const float Le = ls[e] + px.lD, ce = pu[e], ee = pv[e];
+            y0[e] = Le / (1.f + ce);
+            nw[e] = !(ls[e] == -INFINITY) && ee > 0.f && ce > 0.f;
+            if (nw[e] && Le > 0.f) y0[e] = fminf(y0[e], log1pf(ee * Le / ce) / ee);
+            go[e] = nw[e];
+            y[e] = nw[e] ? y0[e] : 0.f;
+            L[e] = nw[e] ? Le : 0.f;
+        }
+        for (int it = 0; it < px.newton; ++it) {
+            bool any = false;
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                const float yn = gen_newton_step(y[e], L[e], go[e] ? pu[e] : 0.f, go[e] ? pv[e] : 0.f);
+                const bool done = gen_newton_settled(y[e], yn);
+                y[e] = go[e] ? yn : y[e];
+                go[e] = go[e] && !done;
+                any |= go[e];
+            }
+            if (!any) break;
+        }
+#pragma unroll
+        for (int e = 0; e < NE; ++e)
+            out[e] = (ls[e] == -INFINITY) ? -INFINITY : (nw[e] ? y[e] : y0[e]) - px.lD;
     }
-    return ls - v / (m - 1.f);
+    return out;
 }
 
 
@@ -350,16 +411,24 @@ __device__ __forceinline__ void epi_apply(const EpiArgs& E, int idx, int cnt, f4
         }
     } else {
         constexpr int KIND = EK - EK_PROX;
-        f4 an, pn;
+        constexpr bool kNewton = KIND == JKO_F_POROUS || KIND == JKO_F_GEN_ENTROPY;
+        f4 an, pn, lpn;
+        if constexpr (kNewton) {
+            f4 ls;
+#pragma unroll
+            for (int e = 0; e < NE; ++e) ls[e] = logx ? val[e] : (val[e] > 0.f ? logf(val[e]) : -INFINITY);
+            lpn = log_prox_cells<KIND, NE>(E.prox, ls, in.u, in.v);
+        }
 #pragma unroll
         for (int e = 0; e < NE; ++e) {
             if (logx) {
-                const float lp = log_prox_val<KIND>(E.prox, val[e], in.u[e], in.v[e]);
+                const float lp = kNewton ? lpn[e] : log_prox_val<KIND>(E.prox, val[e], in.u[e], in.v[e]);
                 an[e] = (lp == -INFINITY) ? -INFINITY : lp - val[e];
                 pn[e] = expf(lp);
                 if (E.check && e < cnt && an[e] > -INFINITY) acc.maxla = fmax(acc.maxla, fabs((double)an[e]));
             } else {
-                const float p = prox_val<KIND>(E.prox, val[e], in.u[e], in.v[e]);
+                const float p = kNewton ? (val[e] > 0.f ? expf(lpn[e]) : 0.f)
+                                        : prox_val<KIND>(E.prox, val[e], in.u[e], in.v[e]);
                 pn[e] = p;
                 an[e] = (p == 0.f) ? 0.f : p / val[e];
                 if (E.check && e < cnt && an[e] > 0.f) acc.maxla = fmax(acc.maxla, fabs((double)logf(an[e])));
