@@ -105,7 +105,7 @@ typedef enum { JKO_FP32 = 0, JKO_SPLIT_BF16 = 1 } jko_precision;
  *                    Prox (Proposition 4.2): psi = D p solves
  *                    log psi + sigma b m (psi^{m-1} - 1) / (m - 1) = log(D s)
  *                    (the m = 1 limit is psi = (D s)^{1/(1 + sigma b)}), by
- *                    newton_steps Newton steps on log psi; jko_backward
+ *                    Newton steps on log psi (at most newton_steps); jko_backward
  *                    differentiates it through the implicit derivative
  *                    d log psi / d log s = 1 / (1 + sigma b m psi^{m-1}).
  *  JKO_F_ATTRACTION  f = W_gamma(r, p) + iota_[0,kappa](p), the Wasserstein
@@ -144,7 +144,9 @@ typedef struct {
     float coef_scalar;
     float m;                 /* porous exponent, > 1; gen. entropy exponent when m_field == NULL, >= 1 */
     float density_scale;     /* porous / gen. entropy D, > 0 (1 = per-cell mass) */
-    int32_t newton_steps;    /* porous / gen. entropy Newton steps per cell, 1..32 (0 = default 8) */
+    int32_t newton_steps;    /* porous / gen. entropy: cap on the Newton steps per cell, 1..32
+                                (0 = default 8); a cell stops earlier, once its update is
+                                within 2^-20 of its scale (below float32 rounding after it) */
     const float* m_field;    /* gen. entropy exponents m_i >= 1, N cells, device; NULL = m */
     const float* target;     /* attraction target density r, N cells, device */
 } jko_energy;
